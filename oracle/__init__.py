@@ -1,0 +1,175 @@
+"""FP64 CPU oracle of the three-phase EHD lattice Boltzmann step.
+
+TEST INFRASTRUCTURE ONLY: the slow, plain reference the GPU path is checked
+against.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg
+of ``bench.py`` may import it.  It shares no code with the HIP library and
+never reads anything the HIP path produced.
+
+The arithmetic lives in ``lbm_ehd_oracle.c`` (plain C, double precision); this
+module only compiles it with gcc and marshals arguments through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lbm_ehd_oracle.c")
+_LIB = os.path.join(_HERE, "_lbm_ehd_oracle.so")
+
+FIELDS = ["phi1", "phi2", "phi3", "rho", "ux", "uy", "p", "psi", "Ex", "Ey",
+          "q", "mu1", "mu2", "mu3", "eps", "R"]
+FAMILIES = {"f": (0, 27), "g": (1, 9), "l": (2, 9), "h": (3, 9)}
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle shared library with gcc (OpenMP, -O2)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-std=c99", "-Wall", "-shared",
+                               "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("bc_y", ctypes.c_int32),
+        ("wall_q_mode", ctypes.c_int32), ("eps_ref_phase", ctypes.c_int32),
+        ("phase_mode", ctypes.c_int32), ("sub_min", ctypes.c_int32),
+        ("sub_max", ctypes.c_int32), ("init_sub_max", ctypes.c_int32),
+        ("pad0", ctypes.c_int32),
+        ("sub_tol", ctypes.c_double), ("init_tol", ctypes.c_double),
+        ("wall_u", ctypes.c_double * 2), ("wall_phi", ctypes.c_double * 2),
+        ("wall_q", ctypes.c_double * 2), ("E_ext", ctypes.c_double * 2),
+        ("gamma12", ctypes.c_double), ("gamma13", ctypes.c_double),
+        ("gamma23", ctypes.c_double), ("width", ctypes.c_double),
+        ("rho", ctypes.c_double * 3), ("visc", ctypes.c_double * 3),
+        ("eps", ctypes.c_double * 3), ("sigma", ctypes.c_double * 3),
+        ("tau_f", ctypes.c_double), ("tau_l", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.or_create.restype = ctypes.c_void_p
+        lib.or_create.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, dp]
+        lib.or_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+        lib.or_free.argtypes = [ctypes.c_void_p]
+        lib.or_field.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
+        lib.or_pops.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
+        lib.or_scalars.argtypes = [ctypes.c_void_p, dp]
+        lib.or_stencil.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, dp]
+        lib.or_sizeof_params.restype = ctypes.c_int
+        assert lib.or_sizeof_params() == ctypes.sizeof(_Params)
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _params(cfg: dict) -> _Params:
+    p = _Params()
+    p.nx, p.ny = int(cfg["nx"]), int(cfg["ny"])
+    p.bc_y = int(cfg.get("bc_y", 0))
+    p.wall_q_mode = int(cfg.get("wall_q_mode", 0))
+    p.eps_ref_phase = int(cfg.get("eps_ref_phase", 0))
+    p.phase_mode = int(cfg.get("phase_mode", 0))
+    p.sub_min = int(cfg.get("sub_min", 1))
+    p.sub_max = int(cfg.get("sub_max", 1))
+    p.init_sub_max = int(cfg.get("init_sub_max", 0))
+    p.sub_tol = float(cfg.get("sub_tol", 0.0))
+    p.init_tol = float(cfg.get("init_tol", 0.0))
+    for k in ("wall_u", "wall_phi", "wall_q", "E_ext"):
+        v = cfg.get(k, (0.0, 0.0))
+        getattr(p, k)[0], getattr(p, k)[1] = float(v[0]), float(v[1])
+    p.gamma12, p.gamma13, p.gamma23 = (float(cfg[k]) for k in ("gamma12", "gamma13", "gamma23"))
+    p.width = float(cfg["width"])
+    for k in ("rho", "visc", "eps", "sigma"):
+        arr = getattr(p, k)
+        for i in range(3):
+            arr[i] = float(cfg[k][i])
+    p.tau_f, p.tau_l = float(cfg["tau_f"]), float(cfg["tau_l"])
+    return p
+
+
+class Oracle:
+    """One simulation instance of the FP64 oracle.
+
+    ``cfg`` is a plain dict of physical/lattice parameters (see
+    ``paper_2608_05787_amd.inputs``); ``init`` holds the initial fields as
+    float64 arrays: ``phi0`` [3,ny,nx], optional ``u0`` [2,ny,nx], ``q0`` and
+    ``psi0`` [ny,nx].
+    """
+
+    def __init__(self, cfg: dict, init: dict):
+        lib = _load()
+        self.nx, self.ny = int(cfg["nx"]), int(cfg["ny"])
+        self._p = _params(cfg)
+        shp = (self.ny, self.nx)
+
+        def arr(name, lead):
+            v = init.get(name)
+            if v is None:
+                return None
+            v = np.ascontiguousarray(v, dtype=np.float64)
+            assert v.shape == ((lead,) + shp if lead else shp), (name, v.shape)
+            return v
+
+        self._keep = [arr("phi0", 3), arr("u0", 2), arr("q0", 0), arr("psi0", 0)]
+        h = lib.or_create(ctypes.byref(self._p), *[_ptr(a) for a in self._keep])
+        if not h:
+            raise ValueError("oracle rejected the parameters")
+        self._h = ctypes.c_void_p(h)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.or_free(h)
+            self._h = None
+
+    def step(self, n: int = 1):
+        _load().or_step(self._h, int(n))
+
+    def field(self, name: str) -> np.ndarray:
+        out = np.empty((self.ny, self.nx), np.float64)
+        rc = _load().or_field(self._h, FIELDS.index(name), _ptr(out))
+        assert rc == 0
+        return out
+
+    def fields(self, names=None) -> dict:
+        return {k: self.field(k) for k in (names or FIELDS)}
+
+    def pops(self, fam: str) -> np.ndarray:
+        idx, nq = FAMILIES[fam]
+        out = np.empty((nq, self.ny, self.nx), np.float64)
+        assert _load().or_pops(self._h, idx, _ptr(out)) == 0
+        return out
+
+    def scalars(self) -> dict:
+        out = np.zeros(9, np.float64)
+        _load().or_scalars(self._h, _ptr(out))
+        return {"steps": int(out[0]), "k_used": int(out[1]), "residual": out[2],
+                "lambda": tuple(out[3:6]), "m0": out[6], "alpha": out[7], "tau_h": out[8]}
+
+
+def stencil(cfg: dict, chi: np.ndarray):
+    """Eq. (33) gradient and Laplacian of a plain field (unit checks)."""
+    p = _params(cfg)
+    chi = np.ascontiguousarray(chi, np.float64)
+    gx, gy, lap = (np.empty_like(chi) for _ in range(3))
+    _load().or_stencil(ctypes.byref(p), _ptr(chi), _ptr(gx), _ptr(gy), _ptr(lap))
+    return gx, gy, lap

@@ -1,0 +1,679 @@
+/*
+ * FP64 CPU oracle for the three-phase leaky-dielectric EHD lattice Boltzmann
+ * step (Liu, Qian, Xiong, Wang: "Onsager-variational-principle-based lattice
+ * Boltzmann model for three-phase dielectric fluid flows", arXiv 2608.05787).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the
+ * GPU path is checked against.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load it.  It shares no code, header, table
+ * or helper with the HIP library, and it never reads anything the HIP path
+ * produced.
+ *
+ * Everything is double precision, one lattice node at a time, one stage at a
+ * time, in the order the paper's Sec. 3 describes the scheme.  OpenMP only
+ * splits node loops over rows; per-node arithmetic and every reduction order
+ * are fixed, so results are bitwise reproducible for any thread count.
+ *
+ * Where the paper is silent or garbled, the reading taken is stated at the
+ * point of use (and listed, numbered R1..R16, in the design notes):
+ *   R1  mu_i follows Eq. (20) (derivative form); Eq. (27c) is a misprint.
+ *   R2  the CH source Eq. (36) is w_j c_j . [d_t(phi_i u)/cs2 - X_i/m0].
+ *   R3  phi_i is the zeroth moment of f^i (sum of f, not of f^eq).
+ *   R4  M_ii = -sum_{k!=i} M_ik literally (zero row sums hold exactly).
+ *   R5  the -1/2 grad(alpha q^2/sigma) force of Eq. (26) is dropped (Eq. 27b).
+ *   R6  tau_g is local: tau_g = 1/2 + mu_v(phi)/(rho cs2), mu_v from Eq. (29).
+ *   R7  q = sum l + R/2 is solved for q because R depends on q.
+ *   R8  d_t(phi_i u), d_t(q u): first-order backward differences in time.
+ *   R9  step order: moments, stencils, charge (with E of the previous step),
+ *       potential sub-iterations, mu, grad mu, force/u/p, collisions, streaming.
+ *   R10 walls are half-way: bounce-back with the moving-wall term for every
+ *       family whose equilibrium carries c_j.(psi u), anti-bounce-back for a
+ *       Dirichlet potential (and a Dirichlet charge when asked for).
+ *   R11 finite-difference ghosts at walls mirror the first fluid row.
+ *   R12 grad(eps), grad(sigma), grad(rho) apply Eq. (33) to the eps, sigma
+ *       and rho fields built from phi (Eqs. 29-30) at each stencil node.
+ *   R13 potential sub-iterations stop after iteration k once k >= sub_min,
+ *       k >= 2 and the potential change of the previous iteration is below
+ *       tol; sub_min == sub_max or tol <= 0 runs a fixed count.
+ *   R14 the reference permittivity of the h equation is that of one chosen
+ *       (bulk) phase: eps_ref = eps[eps_ref_phase], tau_h = 1/2 + eps_ref/cs2.
+ *   R15 a uniform applied field E_ext is added to -grad(potential).
+ *   R16 initial populations are the equilibria of the initial fields; the
+ *       potential is first iterated with q0 (cold start).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define Q 9
+/* D2Q9 lattice, Eq. (31); c = dx/dt = 1, cs^2 = 1/3. */
+static const int CX[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int CY[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const double WT[Q] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                             1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+static const int OPP[Q] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+/* source weights of the potential equation, Eq. (43): varpi_0 = 0, 1/8 else */
+static const double VARPI[Q] = {0.0, 0.125, 0.125, 0.125, 0.125,
+                                0.125, 0.125, 0.125, 0.125};
+static const double CS2 = 1.0 / 3.0;
+
+typedef struct {
+  int32_t nx, ny;
+  int32_t bc_y;          /* 0 periodic, 1 half-way walls at y=-1/2, ny-1/2 */
+  int32_t wall_q_mode;   /* 0 charge bounce-back (no flux), 1 Dirichlet q */
+  int32_t eps_ref_phase; /* index of the phase whose eps is eps_ref (R14) */
+  int32_t phase_mode;    /* 0 evolve f^1..3, 1 order parameters frozen */
+  int32_t sub_min, sub_max;
+  int32_t init_sub_max, pad0;
+  double sub_tol, init_tol;
+  double wall_u[2];   /* tangential wall speed, [0] bottom, [1] top */
+  double wall_phi[2]; /* Dirichlet potential at the walls */
+  double wall_q[2];   /* Dirichlet charge at the walls (wall_q_mode 1) */
+  double E_ext[2];
+  double gamma12, gamma13, gamma23, width;
+  double rho[3], visc[3], eps[3], sigma[3];
+  double tau_f, tau_l;
+} or_params;
+
+typedef struct {
+  or_params p;
+  int nx, ny, N;
+  double lam[3], m0, alpha, eps_ref, tau_h;
+  double *f, *g, *l, *h;       /* populations, [family][q][y][x] */
+  double *fn, *gn, *ln, *hn;   /* streaming targets */
+  double *phi, *lsum;          /* [3][N], [N] */
+  double *rho, *sig, *eps, *visc;
+  double *gphi, *lphi;         /* [3][2][N], [3][N] */
+  double *grho, *gsig, *geps;  /* [2][N] */
+  double *q, *R, *psi, *psi_prev, *E; /* E is [2][N]: E of the last solve */
+  double *mu, *gmu;            /* [3][N], [3][2][N] */
+  double *u, *pr;              /* [2][N], [N] */
+  double *hpu, *hqu;           /* history (phi_i u)^{n-1} [3][2][N], (q u)^{n-1} [2][N] */
+  double *rowbuf;              /* per-row partial sums (deterministic reductions) */
+  int64_t nstep;
+  int k_used;
+  double res_last;
+} or_state;
+
+/* ---------------------------------------------------------------- helpers */
+
+static double *zalloc(size_t n) { return (double *)calloc(n ? n : 1, sizeof(double)); }
+
+static inline int wrapx(int x, int nx) { return (x % nx + nx) % nx; }
+
+/* Row index of a finite-difference neighbour (R11: mirror ghosts at walls). */
+static inline int fd_row(const or_state *s, int y) {
+  if (s->p.bc_y == 0) return (y % s->ny + s->ny) % s->ny;
+  if (y < 0) return 0;
+  if (y >= s->ny) return s->ny - 1;
+  return y;
+}
+
+/* Isotropic second-order gradient and Laplacian of Eq. (33) at node (x,y). */
+static void stencil(const or_state *s, const double *chi, int x, int y,
+                    double *gx, double *gy, double *lap) {
+  const int nx = s->nx;
+  const double c0 = chi[y * nx + x];
+  double sx = 0, sy = 0, sl = 0;
+  for (int j = 0; j < Q; ++j) {
+    const int xx = wrapx(x + CX[j], nx), yy = fd_row(s, y + CY[j]);
+    const double v = chi[yy * nx + xx];
+    sx += WT[j] * CX[j] * v;
+    sy += WT[j] * CY[j] * v;
+    sl += 2.0 * WT[j] * (v - c0);
+  }
+  if (gx) *gx = sx / CS2;
+  if (gy) *gy = sy / CS2;
+  if (lap) *lap = sl / CS2;
+}
+
+/* Properties of Eqs. (29)-(30). */
+static double prop_lin(const double *c, double p1, double p2, double p3) {
+  return c[0] * p1 + c[1] * p2 + c[2] * p3;
+}
+static double herm(double ph) { return ph * ph * (3.0 - 2.0 * ph); }
+static double prop_eps(const double *e, double p1, double p2, double p3) {
+  return e[0] * herm(p1) + e[1] * herm(p2) + e[2] * herm(p3);
+}
+
+/*
+ * Streaming of one 9-population family with half-way walls (R10).
+ * post: post-collision values; dst: pre-collision values of the next level.
+ * mode 0: bounce-back with moving-wall term -2 w_j psi (c_j . u_w)/cs2,
+ *         psi per node given by `carrier` (NULL means psi = 0).
+ * mode 1: anti-bounce-back for a Dirichlet value (bot, top): -post + 2 w_j v.
+ */
+static void stream_family(const or_state *s, const double *post, double *dst,
+                          int mode, const double *carrier, double bot, double top) {
+  const int nx = s->nx, ny = s->ny, N = s->N;
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      const int n = y * nx + x;
+      for (int j = 0; j < Q; ++j) {
+        const double v = post[j * N + n];
+        const int xd = wrapx(x + CX[j], nx);
+        int yd = y + CY[j];
+        if (s->p.bc_y == 0) {
+          yd = (yd % ny + ny) % ny;
+          dst[j * N + yd * nx + xd] = v;
+        } else if (yd >= 0 && yd < ny) {
+          dst[j * N + yd * nx + xd] = v;
+        } else {
+          const int side = (yd < 0) ? 0 : 1;
+          double out;
+          if (mode == 0) {
+            const double psi = carrier ? carrier[n] : 0.0;
+            out = v - 2.0 * WT[j] * psi * (CX[j] * s->p.wall_u[side]) / CS2;
+          } else {
+            out = -v + 2.0 * WT[j] * (side ? top : bot);
+          }
+          dst[OPP[j] * N + n] = out;
+        }
+      }
+    }
+}
+
+static void swap_ptr(double **a, double **b) {
+  double *t = *a;
+  *a = *b;
+  *b = t;
+}
+
+/* ------------------------------------------------------ potential (h) LB */
+
+/* Potential and its gradient from the local h moments, Eq. (45). */
+static void h_moments(const or_state *s, int n, double epshat,
+                      double *pot, double *gx, double *gy) {
+  const int N = s->N;
+  double s0 = 0, mx = 0, my = 0;
+  for (int j = 1; j < Q; ++j) s0 += s->h[j * N + n];
+  for (int j = 0; j < Q; ++j) {
+    mx += CX[j] * s->h[j * N + n];
+    my += CY[j] * s->h[j * N + n];
+  }
+  *pot = s0 / (1.0 - WT[0]);
+  const double den = epshat + CS2 * s->tau_h;
+  *gx = -mx / den;
+  *gy = -my / den;
+}
+
+static void eval_potential(or_state *s, double *dst) {
+#pragma omp parallel for schedule(static)
+  for (int n = 0; n < s->N; ++n) {
+    double gx, gy;
+    h_moments(s, n, s->eps[n] - s->eps_ref, &dst[n], &gx, &gy);
+  }
+}
+
+/* One potential sub-iteration: collision of Eq. (43) with the equilibrium of
+ * Eq. (44), then streaming with anti-bounce-back electrodes. */
+static void poisson_iteration(or_state *s) {
+  const int N = s->N;
+  const double th = s->tau_h;
+#pragma omp parallel for schedule(static)
+  for (int n = 0; n < N; ++n) {
+    const double epshat = s->eps[n] - s->eps_ref;
+    double pot, gx, gy;
+    h_moments(s, n, epshat, &pot, &gx, &gy);
+    for (int j = 0; j < Q; ++j) {
+      const double hj = s->h[j * N + n];
+      const double heq = (j == 0) ? (WT[0] - 1.0) * pot : WT[j] * pot;
+      const double cg = CX[j] * gx + CY[j] * gy;
+      s->hn[j * N + n] = hj - (hj - heq) / th - (epshat / CS2) * WT[j] * cg / th +
+                         VARPI[j] * s->q[n];
+    }
+  }
+  /* collided values are in hn; stream them back into h */
+  stream_family(s, s->hn, s->h, 1, NULL, s->p.wall_phi[0], s->p.wall_phi[1]);
+}
+
+static double rel_change(or_state *s, const double *a, const double *b) {
+  const int nx = s->nx, ny = s->ny;
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y) {
+    double d2 = 0, a2 = 0;
+    for (int x = 0; x < nx; ++x) {
+      const double d = a[y * nx + x] - b[y * nx + x];
+      d2 += d * d;
+      a2 += a[y * nx + x] * a[y * nx + x];
+    }
+    s->rowbuf[2 * y] = d2;
+    s->rowbuf[2 * y + 1] = a2;
+  }
+  double d2 = 0, a2 = 0;
+  for (int y = 0; y < ny; ++y) {
+    d2 += s->rowbuf[2 * y];
+    a2 += s->rowbuf[2 * y + 1];
+  }
+  const double na = sqrt(a2);
+  return sqrt(d2) / (na > 1e-30 ? na : 1e-30);
+}
+
+/* Sub-iteration loop with the stopping rule R13.  On return psi holds the
+ * potential of the final h, res_last the relative change of the potential over
+ * the last iteration, and E = -grad(potential) + E_ext (Eq. 45, R15). */
+static void solve_potential(or_state *s, int kmin, int kmax, double tol) {
+  const int adaptive = (tol > 0.0) && (kmax > kmin);
+  int kdone = kmax > 0 ? kmax : 0;
+  double r_prev = 0.0;
+  for (int k = 1; k <= kmax; ++k) {
+    eval_potential(s, s->psi); /* phi_{k-1}: potential of this iteration's input */
+    if (k >= 2) r_prev = rel_change(s, s->psi, s->psi_prev); /* phi_{k-2} -> phi_{k-1} */
+    swap_ptr(&s->psi, &s->psi_prev);                         /* psi_prev := phi_{k-1} */
+    poisson_iteration(s);
+    if (adaptive && k >= 2 && k >= kmin && r_prev < tol) {
+      kdone = k;
+      break;
+    }
+  }
+  s->k_used = kdone;
+  eval_potential(s, s->psi); /* phi_K */
+  s->res_last = (kdone > 0) ? rel_change(s, s->psi, s->psi_prev) : 0.0;
+  const int N = s->N;
+#pragma omp parallel for schedule(static)
+  for (int n = 0; n < N; ++n) {
+    double pot, gx, gy;
+    h_moments(s, n, s->eps[n] - s->eps_ref, &pot, &gx, &gy);
+    s->E[n] = -gx + s->p.E_ext[0];
+    s->E[N + n] = -gy + s->p.E_ext[1];
+  }
+}
+
+/* ------------------------------------------------------------ other steps */
+
+/* Order-parameter and charge moments (R3): phi_i = sum_j f^i_j. */
+static void moments(or_state *s) {
+  const int N = s->N;
+#pragma omp parallel for schedule(static)
+  for (int n = 0; n < N; ++n) {
+    for (int i = 0; i < 3; ++i) {
+      double a = 0;
+      for (int j = 0; j < Q; ++j) a += s->f[(i * Q + j) * N + n];
+      s->phi[i * N + n] = a;
+    }
+    double b = 0;
+    for (int j = 0; j < Q; ++j) b += s->l[j * N + n];
+    s->lsum[n] = b;
+  }
+}
+
+/* Properties (Eqs. 29-30) and the Eq. (33) stencils of phi_i, rho, sigma, eps. */
+static void properties_and_stencils(or_state *s) {
+  const int N = s->N, nx = s->nx, ny = s->ny;
+  const or_params *P = &s->p;
+#pragma omp parallel for schedule(static)
+  for (int n = 0; n < N; ++n) {
+    const double p1 = s->phi[n], p2 = s->phi[N + n], p3 = s->phi[2 * N + n];
+    s->rho[n] = prop_lin(P->rho, p1, p2, p3);
+    s->visc[n] = prop_lin(P->visc, p1, p2, p3);
+    s->sig[n] = prop_lin(P->sigma, p1, p2, p3);
+    s->eps[n] = prop_eps(P->eps, p1, p2, p3);
+  }
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      const int n = y * nx + x;
+      for (int i = 0; i < 3; ++i)
+        stencil(s, s->phi + i * N, x, y, &s->gphi[(2 * i) * N + n],
+                &s->gphi[(2 * i + 1) * N + n], &s->lphi[i * N + n]);
+      stencil(s, s->rho, x, y, &s->grho[n], &s->grho[N + n], NULL);
+      stencil(s, s->sig, x, y, &s->gsig[n], &s->gsig[N + n], NULL);
+      stencil(s, s->eps, x, y, &s->geps[n], &s->geps[N + n], NULL);
+    }
+}
+
+/* Charge density and the Ohmic source, Eq. (47) with R7; E of the previous
+ * step (R9). */
+static void charge(or_state *s) {
+  const int N = s->N;
+#pragma omp parallel for schedule(static)
+  for (int n = 0; n < N; ++n) {
+    const double ex = s->E[n], ey = s->E[N + n];
+    const double se = s->sig[n] / s->eps[n];
+    const double Rp = se * (s->geps[n] * ex + s->geps[N + n] * ey) -
+                      (s->gsig[n] * ex + s->gsig[N + n] * ey);
+    const double qq = (s->lsum[n] + 0.5 * Rp) / (1.0 + 0.5 * se);
+    s->q[n] = qq;
+    s->R[n] = -se * qq + Rp;
+  }
+}
+
+/* Chemical potentials, Eq. (20) with eps'(phi_i) = 6 eps_i phi_i (1-phi_i) (R1). */
+static void chem_potential(or_state *s) {
+  const int N = s->N;
+  const double D = s->p.width;
+#pragma omp parallel for schedule(static)
+  for (int n = 0; n < N; ++n) {
+    const double e2 = s->E[n] * s->E[n] + s->E[N + n] * s->E[N + n];
+    for (int i = 0; i < 3; ++i) {
+      const double ph = s->phi[i * N + n];
+      const double bulk = 24.0 / D * s->lam[i] * ph * (ph - 0.5) * (ph - 1.0);
+      const double grad = 0.75 * D * s->lam[i] * s->lphi[i * N + n];
+      const double elec = 0.5 * (6.0 * s->p.eps[i] * ph * (1.0 - ph)) * e2;
+      s->mu[i * N + n] = bulk - grad - elec;
+    }
+  }
+  const int nx = s->nx, ny = s->ny;
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      const int n = y * nx + x;
+      for (int i = 0; i < 3; ++i)
+        stencil(s, s->mu + i * N, x, y, &s->gmu[(2 * i) * N + n],
+                &s->gmu[(2 * i + 1) * N + n], NULL);
+    }
+}
+
+/* Body force of Eq. (27b) (R5) and the flow moments of Eq. (41). */
+static void force_and_flow(or_state *s, int n, double *Fx, double *Fy,
+                           double *ux, double *uy, double *pp) {
+  const int N = s->N;
+  double fx = s->q[n] * s->E[n], fy = s->q[n] * s->E[N + n];
+  for (int i = 0; i < 3; ++i) {
+    fx -= s->phi[i * N + n] * s->gmu[(2 * i) * N + n];
+    fy -= s->phi[i * N + n] * s->gmu[(2 * i + 1) * N + n];
+  }
+  double mx = 0, my = 0, s1 = 0;
+  for (int j = 0; j < Q; ++j) {
+    mx += CX[j] * s->g[j * N + n];
+    my += CY[j] * s->g[j * N + n];
+    if (j) s1 += s->g[j * N + n];
+  }
+  const double rho = s->rho[n];
+  const double vx = (mx + 0.5 * fx) / rho, vy = (my + 0.5 * fy) / rho;
+  const double udr = vx * s->grho[n] + vy * s->grho[N + n];
+  const double s0 = WT[0] * (-(vx * vx + vy * vy) / (2.0 * CS2));
+  *Fx = fx;
+  *Fy = fy;
+  *ux = vx;
+  *uy = vy;
+  *pp = CS2 / (1.0 - WT[0]) * (s1 + 0.5 * udr + rho * s0);
+}
+
+/* Collisions of Eqs. (34)-(36), (37)-(40) and (48)-(50). */
+static void collide(or_state *s) {
+  const int N = s->N;
+  const or_params *P = &s->p;
+  const double tf = P->tau_f, tl = P->tau_l, m0 = s->m0;
+#pragma omp parallel for schedule(static)
+  for (int n = 0; n < N; ++n) {
+    double Fx, Fy, ux, uy, pp;
+    force_and_flow(s, n, &Fx, &Fy, &ux, &uy, &pp);
+    s->u[n] = ux;
+    s->u[N + n] = uy;
+    s->pr[n] = pp;
+    const double rho = s->rho[n];
+    const double usq = ux * ux + uy * uy;
+
+    /* time derivatives of phi_i u and q u (R8), history update */
+    double dpu[3][2];
+    for (int i = 0; i < 3; ++i) {
+      const double ph = s->phi[i * N + n];
+      dpu[i][0] = ph * ux - s->hpu[(2 * i) * N + n];
+      dpu[i][1] = ph * uy - s->hpu[(2 * i + 1) * N + n];
+      s->hpu[(2 * i) * N + n] = ph * ux;
+      s->hpu[(2 * i + 1) * N + n] = ph * uy;
+    }
+    const double qq = s->q[n];
+    const double dqx = qq * ux - s->hqu[n], dqy = qq * uy - s->hqu[N + n];
+    s->hqu[n] = qq * ux;
+    s->hqu[N + n] = qq * uy;
+
+    /* three order-parameter families */
+    if (P->phase_mode == 0) {
+      double ph[3], Mm[3][3];
+      for (int i = 0; i < 3; ++i) ph[i] = s->phi[i * N + n];
+      /* degenerate mobility, Eq. (28), with R4 */
+      for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) Mm[i][k] = (i == k) ? 0.0 : -m0 * ph[i] * ph[k];
+      for (int i = 0; i < 3; ++i) {
+        double d = 0;
+        for (int k = 0; k < 3; ++k)
+          if (k != i) d -= Mm[i][k];
+        Mm[i][i] = d;
+      }
+      for (int i = 0; i < 3; ++i) {
+        /* variable part of the diffusion flux (split mobility) */
+        double Xx = (Mm[i][i] - m0) * s->gmu[(2 * i) * N + n];
+        double Xy = (Mm[i][i] - m0) * s->gmu[(2 * i + 1) * N + n];
+        for (int k = 0; k < 3; ++k)
+          if (k != i) {
+            Xx += Mm[i][k] * s->gmu[(2 * k) * N + n];
+            Xy += Mm[i][k] * s->gmu[(2 * k + 1) * N + n];
+          }
+        const double mu = s->mu[i * N + n];
+        for (int j = 0; j < Q; ++j) {
+          const double fj = s->f[(i * Q + j) * N + n];
+          const double cu = CX[j] * ph[i] * ux + CY[j] * ph[i] * uy;
+          const double feq = (j == 0) ? ph[i] - (1.0 - WT[0]) * mu
+                                      : WT[j] * mu + WT[j] * cu / CS2;
+          /* source of Eq. (36), reading R2 */
+          const double Fj = WT[j] * ((CX[j] * dpu[i][0] + CY[j] * dpu[i][1]) / CS2 -
+                                     (CX[j] * Xx + CY[j] * Xy) / m0);
+          s->fn[(i * Q + j) * N + n] = fj - (fj - feq) / tf + (1.0 - 0.5 / tf) * Fj;
+        }
+      }
+    }
+
+    /* flow family: local tau_g (R6), forcing of Eq. (38), equilibrium (39)-(40) */
+    const double tg = 0.5 + s->visc[n] / (rho * CS2);
+    const double gx = s->grho[n], gy = s->grho[N + n];
+    const double udr = ux * gx + uy * gy;
+    for (int j = 0; j < Q; ++j) {
+      const double gj = s->g[j * N + n];
+      const double cu = CX[j] * ux + CY[j] * uy;
+      const double sj = WT[j] * (cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - usq / (2.0 * CS2));
+      const double geq = ((j == 0) ? (WT[0] - 1.0) * pp / CS2 : WT[j] * pp / CS2) + rho * sj;
+      const double cF = CX[j] * Fx + CY[j] * Fy;
+      const double cgr = CX[j] * gx + CY[j] * gy;
+      const double Gb = WT[j] * (udr + cF / CS2 + (cu * cgr - CS2 * udr) / CS2);
+      s->gn[j * N + n] = gj - (gj - geq) / tg + (1.0 - 0.5 / tg) * Gb;
+    }
+
+    /* charge family, Eqs. (48)-(50) */
+    const double Rn = s->R[n];
+    for (int j = 0; j < Q; ++j) {
+      const double lj = s->l[j * N + n];
+      const double cu = CX[j] * ux + CY[j] * uy;
+      const double leq = WT[j] * qq * (1.0 + cu / CS2);
+      const double Sj = (1.0 - 0.5 / tl) * WT[j] * Rn;
+      const double Tj = (1.0 - 0.5 / tl) * WT[j] * (CX[j] * dqx + CY[j] * dqy) / CS2;
+      s->ln[j * N + n] = lj - (lj - leq) / tl + Sj + Tj;
+    }
+  }
+}
+
+static void stream_all(or_state *s) {
+  const int N = s->N;
+  if (s->p.phase_mode == 0) {
+    for (int i = 0; i < 3; ++i)
+      stream_family(s, s->fn + i * Q * N, s->f + i * Q * N, 0, s->phi + i * N, 0, 0);
+  }
+  stream_family(s, s->gn, s->g, 0, s->rho, 0, 0);
+  if (s->p.wall_q_mode == 1)
+    stream_family(s, s->ln, s->l, 1, NULL, s->p.wall_q[0], s->p.wall_q[1]);
+  else
+    stream_family(s, s->ln, s->l, 0, s->q, 0, 0);
+}
+
+/* ---------------------------------------------------------------- public */
+
+void or_free(or_state *s) {
+  if (!s) return;
+  double **all[] = {&s->f, &s->g, &s->l, &s->h, &s->fn, &s->gn, &s->ln, &s->hn,
+                    &s->phi, &s->lsum, &s->rho, &s->sig, &s->eps, &s->visc,
+                    &s->gphi, &s->lphi, &s->grho, &s->gsig, &s->geps, &s->q,
+                    &s->R, &s->psi, &s->psi_prev, &s->E, &s->mu, &s->gmu,
+                    &s->u, &s->pr, &s->hpu, &s->hqu, &s->rowbuf};
+  for (size_t i = 0; i < sizeof(all) / sizeof(all[0]); ++i) free(*all[i]);
+  free(s);
+}
+
+/* Create: parameter mapping, initial fields, cold-start potential, equilibria.
+ * phi0 [3][ny][nx] (required); u0 [2][ny][nx], q0 [ny][nx], psi0 [ny][nx]
+ * may be NULL (zero).  Returns NULL on invalid parameters. */
+or_state *or_create(const or_params *P, const double *phi0, const double *u0,
+                    const double *q0, const double *psi0) {
+  if (!P || !phi0 || P->nx < 1 || P->ny < 1) return NULL;
+  if (P->tau_f <= 0.5 || P->tau_l <= 0.5) return NULL;
+  if (P->eps_ref_phase < 0 || P->eps_ref_phase > 2) return NULL;
+  or_state *s = (or_state *)calloc(1, sizeof(or_state));
+  s->p = *P;
+  s->nx = P->nx;
+  s->ny = P->ny;
+  const int N = s->N = P->nx * P->ny;
+  /* spreading coefficients, Eq. (9) */
+  s->lam[0] = P->gamma12 + P->gamma13 - P->gamma23;
+  s->lam[1] = P->gamma12 + P->gamma23 - P->gamma13;
+  s->lam[2] = P->gamma13 + P->gamma23 - P->gamma12;
+  /* relaxation-time couplings: m0 (Eq. 34 text), alpha (Eq. 49 text), tau_h */
+  s->m0 = CS2 * (P->tau_f - 0.5);
+  s->alpha = CS2 * (P->tau_l - 0.5);
+  s->eps_ref = P->eps[P->eps_ref_phase];
+  s->tau_h = 0.5 + s->eps_ref / CS2;
+
+  s->f = zalloc(27 * (size_t)N); s->fn = zalloc(27 * (size_t)N);
+  s->g = zalloc(9 * (size_t)N);  s->gn = zalloc(9 * (size_t)N);
+  s->l = zalloc(9 * (size_t)N);  s->ln = zalloc(9 * (size_t)N);
+  s->h = zalloc(9 * (size_t)N);  s->hn = zalloc(9 * (size_t)N);
+  s->phi = zalloc(3 * (size_t)N); s->lsum = zalloc(N);
+  s->rho = zalloc(N); s->sig = zalloc(N); s->eps = zalloc(N); s->visc = zalloc(N);
+  s->gphi = zalloc(6 * (size_t)N); s->lphi = zalloc(3 * (size_t)N);
+  s->grho = zalloc(2 * (size_t)N); s->gsig = zalloc(2 * (size_t)N);
+  s->geps = zalloc(2 * (size_t)N);
+  s->q = zalloc(N); s->R = zalloc(N); s->psi = zalloc(N); s->psi_prev = zalloc(N);
+  s->E = zalloc(2 * (size_t)N);
+  s->mu = zalloc(3 * (size_t)N); s->gmu = zalloc(6 * (size_t)N);
+  s->u = zalloc(2 * (size_t)N); s->pr = zalloc(N);
+  s->hpu = zalloc(6 * (size_t)N); s->hqu = zalloc(2 * (size_t)N);
+  s->rowbuf = zalloc(2 * (size_t)s->ny);
+
+  memcpy(s->phi, phi0, 3 * (size_t)N * sizeof(double));
+  if (u0) memcpy(s->u, u0, 2 * (size_t)N * sizeof(double));
+  if (q0) memcpy(s->q, q0, (size_t)N * sizeof(double));
+  properties_and_stencils(s);
+
+  /* potential: equilibrium of the initial guess, then cold-start iterations
+     with the initial charge (R16) */
+  for (int n = 0; n < N; ++n) {
+    const double v = psi0 ? psi0[n] : 0.0;
+    for (int j = 0; j < Q; ++j) s->h[j * N + n] = (j == 0) ? (WT[0] - 1.0) * v : WT[j] * v;
+  }
+  solve_potential(s, 1, P->init_sub_max, P->init_tol);
+  chem_potential(s);
+
+  /* equilibria of the initial fields; p = 0 */
+  for (int n = 0; n < N; ++n) {
+    const double ux = s->u[n], uy = s->u[N + n], usq = ux * ux + uy * uy;
+    const double rho = s->rho[n];
+    for (int i = 0; i < 3; ++i) {
+      const double ph = s->phi[i * N + n], mu = s->mu[i * N + n];
+      for (int j = 0; j < Q; ++j) {
+        const double cu = CX[j] * ph * ux + CY[j] * ph * uy;
+        s->f[(i * Q + j) * N + n] = (j == 0) ? ph - (1.0 - WT[0]) * mu
+                                             : WT[j] * mu + WT[j] * cu / CS2;
+      }
+      s->hpu[(2 * i) * N + n] = ph * ux;
+      s->hpu[(2 * i + 1) * N + n] = ph * uy;
+    }
+    for (int j = 0; j < Q; ++j) {
+      const double cu = CX[j] * ux + CY[j] * uy;
+      s->g[j * N + n] = rho * WT[j] * (cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - usq / (2.0 * CS2));
+      s->l[j * N + n] = WT[j] * s->q[n] * (1.0 + cu / CS2);
+    }
+    s->hqu[n] = s->q[n] * ux;
+    s->hqu[N + n] = s->q[n] * uy;
+    s->pr[n] = 0.0;
+  }
+  s->nstep = 0;
+  return s;
+}
+
+/* n time steps, each in the order R9. */
+void or_step(or_state *s, int64_t nsteps) {
+  for (int64_t t = 0; t < nsteps; ++t) {
+    moments(s);
+    properties_and_stencils(s);
+    charge(s);
+    solve_potential(s, s->p.sub_min, s->p.sub_max, s->p.sub_tol);
+    chem_potential(s);
+    collide(s);
+    stream_all(s);
+    s->nstep++;
+  }
+}
+
+/* Field ids for or_field; fields are those computed during the last step
+ * (after create: the initial fields). */
+enum {
+  OR_PHI1 = 0, OR_PHI2, OR_PHI3, OR_RHO, OR_UX, OR_UY, OR_P, OR_PSI, OR_EX, OR_EY,
+  OR_Q, OR_MU1, OR_MU2, OR_MU3, OR_EPS, OR_R, OR_NFIELDS
+};
+
+int or_field(const or_state *s, int id, double *out) {
+  const int N = s->N;
+  const double *src = NULL;
+  switch (id) {
+    case OR_PHI1: case OR_PHI2: case OR_PHI3: src = s->phi + (id - OR_PHI1) * N; break;
+    case OR_RHO: src = s->rho; break;
+    case OR_UX: src = s->u; break;
+    case OR_UY: src = s->u + N; break;
+    case OR_P: src = s->pr; break;
+    case OR_PSI: src = s->psi; break;
+    case OR_EX: src = s->E; break;
+    case OR_EY: src = s->E + N; break;
+    case OR_Q: src = s->q; break;
+    case OR_MU1: case OR_MU2: case OR_MU3: src = s->mu + (id - OR_MU1) * N; break;
+    case OR_EPS: src = s->eps; break;
+    case OR_R: src = s->R; break;
+    default: return -1;
+  }
+  memcpy(out, src, (size_t)N * sizeof(double));
+  return 0;
+}
+
+/* Raw pre-collision populations of the current level.
+ * fam 0: f [3][9][N], 1: g [9][N], 2: l [9][N], 3: h [9][N]. */
+int or_pops(const or_state *s, int fam, double *out) {
+  const size_t N = (size_t)s->N;
+  switch (fam) {
+    case 0: memcpy(out, s->f, 27 * N * sizeof(double)); return 0;
+    case 1: memcpy(out, s->g, 9 * N * sizeof(double)); return 0;
+    case 2: memcpy(out, s->l, 9 * N * sizeof(double)); return 0;
+    case 3: memcpy(out, s->h, 9 * N * sizeof(double)); return 0;
+    default: return -1;
+  }
+}
+
+/* Scalars: [0] steps, [1] sub-iterations of the last solve, [2] residual of
+ * the last solve, [3..5] lambda_i, [6] m0, [7] alpha, [8] tau_h. */
+void or_scalars(const or_state *s, double *out) {
+  out[0] = (double)s->nstep;
+  out[1] = s->k_used;
+  out[2] = s->res_last;
+  out[3] = s->lam[0];
+  out[4] = s->lam[1];
+  out[5] = s->lam[2];
+  out[6] = s->m0;
+  out[7] = s->alpha;
+  out[8] = s->tau_h;
+}
+
+/* Eq. (33) on a plain field (for unit checks of the stencil). */
+void or_stencil(const or_params *P, const double *chi, double *gx, double *gy, double *lap) {
+  or_state tmp;
+  memset(&tmp, 0, sizeof(tmp));
+  tmp.p = *P;
+  tmp.nx = P->nx;
+  tmp.ny = P->ny;
+  tmp.N = P->nx * P->ny;
+  for (int y = 0; y < tmp.ny; ++y)
+    for (int x = 0; x < tmp.nx; ++x) {
+      const int n = y * tmp.nx + x;
+      stencil(&tmp, chi, x, y, gx + n, gy + n, lap + n);
+    }
+}
+
+int or_sizeof_params(void) { return (int)sizeof(or_params); }
