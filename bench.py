@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Throughput of the coupled three-phase EHD lattice Boltzmann step on one GPU.
+
+Workload: compound drop (core radius 60 inside shell radius 80) between
+electrodes in a 1024 x 1024 box, electric capillary number 0.2, permittivity
+ratios 2 and 0.5, conductivity ratios 3 and 0.3, charge relaxation time 0.6,
+FP32 populations, a fixed number of potential sub-iterations per step.
+One step = one coupled time step over every node (moments, stencils, charge,
+all potential sub-iterations, chemical potential, fused collide-and-stream).
+
+Prints ONE JSON line:  MLUPS (10^6 node updates per second), the dominant
+kernel's HBM roofline figure measured live with HIP events, the FP64 variant,
+the FP32-vs-FP64 field errors, and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic HBM bytes per node and launch for FP32 storage (T = 4 bytes):
+# what each kernel must read and write once, no halo re-reads.
+BYTES_PER_NODE_FP32 = {
+    "moments": (27 + 9) * 4 + (3 + 1) * 4,                 # pops in, phi + l-sum out
+    "pre": (3 + 1 + 2) * 4 + 3 * 4,                         # phi, l-sum, E in; eps, q, R out
+    "poisson": (9 + 1 + 1) * 4 + 9 * 4,                     # h, eps, q in; h out (fixed count)
+    "mu": (9 + 1 + 1 + 3) * 4 + (1 + 2 + 3) * 4,            # h, eps, psi, phi in; psi, E, mu out
+    "collide": (45 + 3 + 3 + 1 + 1 + 2 + 8) * 4 + (45 + 8) * 4,  # pops, phi, mu, q, R, E, hist
+}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in ("paper_2608_05787_amd/csrc/lbm_ehd_kernels.h", "paper_2608_05787_amd/csrc/lbm_ehd.hip"):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, launch_nodes):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, only
+    if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_field_drop_1024.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_source_hash() or kernel not in t.get("kernels", {}):
+        return None
+    k = t["kernels"][kernel]
+    return float(k["bytes_per_launch"]) if k.get("nodes") == launch_nodes else None
+
+
+def workload(n, sub, init_iters):
+    """Fixed cold-start count, so that every precision starts from the same
+    potential iterate."""
+    from paper_2608_05787_amd import inputs
+    p, init = inputs.field_compound_drop(n, sub=(sub, sub, 0.0), init_iters=init_iters, init_tol=0.0)
+    return p, init
+
+
+def run_gpu(p, init, precision, steps, warmup, profile_steps):
+    import torch
+    from paper_2608_05787_amd import binding
+    t0 = time.time()
+    sim = binding.Sim(p, init, precision=precision)
+    torch.cuda.synchronize()
+    log("%s create (cold start) %.2fs" % (precision, time.time() - t0))
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    stream = sim.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    log("%s %d steps %.3f ms/step" % (precision, steps, ms / steps))
+    prof = None
+    if profile_steps > 0:
+        sim.profile_begin()
+        sim.step(profile_steps)
+        prof = sim.profile_end()
+    d = sim.diagnostics()
+    return sim, ms, prof, d
+
+
+def cpu_baseline(p, init, budget_s):
+    from oracle import Oracle
+    q = dict(p, init_sub_max=0)  # bounded sample: no cold start
+    t0 = time.time()
+    o = Oracle(q, init)
+    log("oracle create %.1fs" % (time.time() - t0))
+    n_nodes = p["nx"] * p["ny"]
+    steps, t0 = 0, time.time()
+    while True:
+        o.step(1)
+        steps += 1
+        el = time.time() - t0
+        if el > budget_s or steps >= 200:
+            break
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    return {"value": n_nodes * steps / el / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": "%dx%d field compound drop, %d FP64 oracle steps with %d potential "
+                      "sub-iterations each (no cold start), %.1fs" % (p["nx"], p["ny"], steps, p["sub_max"], el)}
+
+
+def field_errors(p, init, steps):
+    """Relative L2 error of FP32 fields against the FP64 instance of the same
+    kernels (the FP64 instance matches the FP64 CPU oracle to ~1e-12)."""
+    import torch
+    from paper_2608_05787_amd import binding
+    a = binding.Sim(p, init, precision="fp32")
+    b = binding.Sim(p, init, precision="fp64")
+    a.step(steps)
+    b.step(steps)
+    fa, fb = a.fields(), b.fields()
+    out = {}
+    for k in ("phi1", "phi2", "phi3", "ux", "uy", "p", "psi", "Ex", "Ey", "q", "mu1", "mu2", "mu3"):
+        nb = float(torch.linalg.norm(fb[k]))
+        out[k] = float(torch.linalg.norm(fa[k] - fb[k])) / nb if nb > 0 else 0.0
+    da, db = a.diagnostics(), b.diagnostics()
+    out["D_outer_abs"] = abs(da["D_outer"] - db["D_outer"])
+    out["D_inner_abs"] = abs(da["D_inner"] - db["D_inner"])
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--sub", type=int, default=4, help="potential sub-iterations per step")
+    ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--error-steps", type=int, default=500)
+    ap.add_argument("--init-iters", type=int, default=4000, help="cold-start potential iterations")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_2608_05787_amd import binding
+    binding.load()
+
+    p, init = workload(args.n, args.sub, args.init_iters)
+    nodes = p["nx"] * p["ny"]
+    sim, ms, prof, diag = run_gpu(p, init, "fp32", args.steps, args.warmup, args.profile_steps)
+    mlups = nodes * args.steps / (ms * 1e-3) / 1e6
+    k_mean = args.sub
+
+    roofline = None
+    kernels = {}
+    if prof:
+        for k, (tot, cnt) in prof.items():
+            if cnt:
+                kernels[k] = {"avg_us": 1e3 * tot / cnt, "launches": cnt, "share": 0.0}
+        total = sum(v["avg_us"] * v["launches"] for v in kernels.values())
+        for v in kernels.values():
+            v["share"] = v["avg_us"] * v["launches"] / total
+        dom = max((k for k in kernels if k in BYTES_PER_NODE_FP32),
+                  key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
+        bpl = BYTES_PER_NODE_FP32[dom] * nodes
+        avg_s = kernels[dom]["avg_us"] * 1e-6
+        achieved = bpl / avg_s / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "bytes_per_launch": bpl, "bytes_per_node": BYTES_PER_NODE_FP32[dom],
+                    "traffic": measured_traffic(dom, nodes)}
+        for k, v in kernels.items():
+            if k in BYTES_PER_NODE_FP32:
+                v["gbs"] = round(BYTES_PER_NODE_FP32[k] * nodes / (v["avg_us"] * 1e-6) / 1e9, 1)
+    step_bytes = sum(BYTES_PER_NODE_FP32[k] * (args.sub if k == "poisson" else 1) for k in BYTES_PER_NODE_FP32)
+
+    variants = {"fp32": {"mlups": round(mlups, 1), "ms_per_step": ms / args.steps}}
+    errors = None
+    if not args.no_variants:
+        del sim
+        _, ms64, _, _ = run_gpu(p, init, "fp64", max(args.steps // 2, 1), args.warmup // 2, 0)
+        variants["fp64"] = {"mlups": round(nodes * max(args.steps // 2, 1) / (ms64 * 1e-3) / 1e6, 1),
+                            "ms_per_step": ms64 / max(args.steps // 2, 1)}
+        variants["fp16s"] = None
+        log("field errors FP32 vs FP64 after %d steps" % args.error_steps)
+        errors = field_errors(p, init, args.error_steps)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(p, init, args.cpu_seconds)
+
+    out = {
+        "metric": "coupled MLUPS (FP32 populations, fixed potential sub-iterations)",
+        "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "field compound drop %dx%d (electrodes, Ca_e 0.2, eps ratios 2/0.5, "
+                               "sigma ratios 3/0.3, radii 80/60)" % (args.n, args.n),
+                   "nodes": nodes, "potential_subiterations": k_mean, "precision": "fp32",
+                   "algorithmic_bytes_per_node_update": step_bytes},
+        "roofline": roofline,
+        "kernels": kernels,
+        "variants": variants,
+        "fp32_vs_fp64_rel_l2": errors,
+        "diagnostics": {k: diag[k] for k in ("max_sum_dev", "residual", "D_outer", "D_inner", "nonfinite")},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * lbm_ehd.h — C ABI of the MI355X (gfx950) three-phase leaky-dielectric EHD
+ * lattice Boltzmann step.
+ *
+ * Method: Liu, Qian, Xiong, Wang, "Onsager-variational-principle-based
+ * lattice Boltzmann model for three-phase dielectric fluid flows"
+ * (arXiv 2608.05787), Sec. 3: D2Q9 lattice (Eq. 31), Eq. (33) stencils,
+ * Cahn-Hilliard LB with split degenerate mobility (Eqs. 34-36, 28), flow LB
+ * (Eqs. 37-41), potential LB with permittivity decomposition (Eqs. 42-45),
+ * charge LB (Eqs. 46-50), closed system Eqs. (27a)-(27e), properties
+ * Eqs. (29)-(30), spreading coefficients Eq. (9).
+ *
+ * Conventions for every call:
+ *  - Return value: 0 on success, a negative LBM_EHD_E* code on failure.  No
+ *    call aborts, exits or throws; lbm_ehd_last_error() gives a message.
+ *  - Device memory is owned by the caller.  The library keeps non-owning
+ *    pointers into the caller's workspace and never allocates device memory.
+ *  - All device work of a handle is ordered on the HIP stream given at
+ *    create time.  Only lbm_ehd_create, lbm_ehd_populations,
+ *    lbm_ehd_diagnostics, lbm_ehd_scalars, lbm_ehd_restore and
+ *    lbm_ehd_profile_end synchronise that stream.
+ *  - One handle is used by one host thread at a time.
+ *  - Layout of every field plane: row-major [ny][nx], x fastest.
+ */
+#ifndef LBM_EHD_H
+#define LBM_EHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ehd_s *lbm_ehd_t; /* opaque; host memory owned by the library */
+
+enum {
+  LBM_EHD_OK = 0,
+  LBM_EHD_EINVAL = -1,       /* invalid argument or parameter */
+  LBM_EHD_ENOMEM = -2,       /* workspace or buffer too small / misaligned */
+  LBM_EHD_EHIP = -3,         /* a HIP runtime call failed */
+  LBM_EHD_EDIVERGED = -4,    /* non-finite populations detected */
+  LBM_EHD_ENOCONV = -5,      /* potential iteration hit its cap (state valid) */
+  LBM_EHD_ESTATE = -6,       /* call not valid in the handle's state */
+  LBM_EHD_EUNSUPPORTED = -7  /* feature not available in this build */
+};
+
+enum { LBM_BC_PERIODIC = 0, LBM_BC_WALL = 1 }; /* x is always periodic */
+enum { LBM_PREC_FP32 = 0, LBM_PREC_FP16S = 1, LBM_PREC_FP64 = 2 };
+enum { LBM_DTYPE_F32 = 0, LBM_DTYPE_F64 = 1 };
+
+/* Field bits for lbm_ehd_fields (the fields computed during the last step;
+ * after create, the initial fields). */
+enum {
+  LBM_F_PHI1 = 1u << 0, LBM_F_PHI2 = 1u << 1, LBM_F_PHI3 = 1u << 2,
+  LBM_F_RHO = 1u << 3, LBM_F_UX = 1u << 4, LBM_F_UY = 1u << 5, LBM_F_P = 1u << 6,
+  LBM_F_PSI = 1u << 7, LBM_F_EX = 1u << 8, LBM_F_EY = 1u << 9, LBM_F_Q = 1u << 10,
+  LBM_F_MU1 = 1u << 11, LBM_F_MU2 = 1u << 12, LBM_F_MU3 = 1u << 13,
+  LBM_F_EPS = 1u << 14, LBM_F_R = 1u << 15
+};
+/* Population families for lbm_ehd_populations. */
+enum { LBM_POP_F = 0, LBM_POP_G = 1, LBM_POP_L = 2, LBM_POP_H = 3 };
+
+/*
+ * Parameters of one instance.  Physical inputs in lattice units
+ * (dx = dt = 1, cs^2 = 1/3):
+ *  nx, ny        lattice nodes (>= 2 each); walls sit half-way, at y = -1/2
+ *                and y = ny - 1/2, when bc_y == LBM_BC_WALL.
+ *  wall_u        tangential wall speeds [bottom, top] (moving-wall
+ *                bounce-back of every family with an advective equilibrium).
+ *  wall_phi      Dirichlet electric potential of the walls (electrodes), by
+ *                anti-bounce-back of the potential populations.
+ *  wall_q_mode   0: charge no-flux (bounce-back); 1: Dirichlet charge wall_q.
+ *  E_ext         uniform applied field added to -grad(potential).
+ *  gamma12..23   pair surface tensions -> lambda_i of Eq. (9); each lambda_i
+ *                must be > 0.
+ *  width         interface thickness D of Eq. (7).
+ *  rho, visc, eps, sigma  per-phase density, dynamic viscosity,
+ *                permittivity, conductivity (Eqs. 29-30).
+ *  tau_f         CH relaxation time, m0 = cs^2 (tau_f - 1/2) (Eq. 34 text).
+ *  tau_l         charge relaxation time, alpha = cs^2 (tau_l - 1/2).
+ *  eps_ref_phase phase whose permittivity is the reference of Eq. (42);
+ *                tau_h = 1/2 + eps_ref / cs^2.
+ *  phase_mode    0: evolve the three order parameters; 1: keep them frozen.
+ *  sub_min, sub_max, sub_tol  potential sub-iterations per step.  Fixed
+ *                count when sub_min == sub_max or sub_tol <= 0; otherwise the
+ *                loop stops after iteration k once k >= max(sub_min, 2) and
+ *                the relative L2 change of the potential over iteration k-1
+ *                is below sub_tol.  1 <= sub_min <= sub_max <= 4096.
+ *  init_sub_max, init_tol  cold-start iterations of create (same rule with
+ *                sub_min = 1; init_tol <= 0 runs exactly init_sub_max).
+ *  precision     LBM_PREC_*: storage/arithmetic of the populations.
+ */
+typedef struct {
+  int32_t nx, ny, bc_y, wall_q_mode;
+  int32_t eps_ref_phase, phase_mode, sub_min, sub_max;
+  int32_t init_sub_max, precision, reserved0, reserved1;
+  double sub_tol, init_tol;
+  double wall_u[2], wall_phi[2], wall_q[2], E_ext[2];
+  double gamma12, gamma13, gamma23, width;
+  double rho[3], visc[3], eps[3], sigma[3];
+  double tau_f, tau_l;
+} lbm_ehd_params;
+
+/* Initial fields of one instance, HOST pointers to float64 arrays:
+ * phi0 [3][ny][nx] (required); u0 [2][ny][nx], q0 [ny][nx] and psi0 (initial
+ * guess of the potential) [ny][nx] may be NULL (zero).  Read during create
+ * only. */
+typedef struct {
+  const double *phi0, *u0, *q0, *psi0;
+} lbm_ehd_init;
+
+/* Bytes of device workspace that lbm_ehd_create needs for n_inst instances
+ * with the given parameters (array of n_inst).  The workspace must be
+ * 256-byte aligned. */
+int lbm_ehd_workspace_bytes(const lbm_ehd_params *params, int32_t n_inst, size_t *bytes);
+
+/* Create a handle for n_inst instances (params[n_inst], init[n_inst]).
+ * dev_workspace: caller-owned device memory of at least workspace_bytes.
+ * hip_stream: the hipStream_t all work is ordered on (NULL = null stream).
+ * Maps the parameters, uploads the initial fields, iterates the potential
+ * from psi0 with q0 (cold start), computes the chemical potentials and sets
+ * every population to the equilibrium of the initial fields.  Synchronises
+ * the stream.  On success *out receives the handle. */
+int lbm_ehd_create(const lbm_ehd_params *params, int32_t n_inst, const lbm_ehd_init *init,
+                   void *dev_workspace, void *hip_stream, lbm_ehd_t *out);
+
+/* Enqueue n >= 0 coupled time steps of every instance (asynchronous). */
+int lbm_ehd_step(lbm_ehd_t h, int64_t n);
+
+/* Write the selected fields of instance `inst` into caller device memory
+ * dev_dst as consecutive planes [popcount(mask)][ny][nx] in ascending bit
+ * order, converted to dtype (LBM_DTYPE_F32 or LBM_DTYPE_F64).  Async. */
+int lbm_ehd_fields(lbm_ehd_t h, int32_t inst, uint32_t mask, void *dev_dst, int32_t dtype);
+
+/* Pre-collision populations of the current level of instance `inst`,
+ * converted to dtype: family LBM_POP_F gives [3][9][ny][nx], the others
+ * [9][ny][nx].  Synchronises (the current buffer is read from the device). */
+int lbm_ehd_populations(lbm_ehd_t h, int32_t inst, int32_t family, void *dev_dst, int32_t dtype);
+
+/* Diagnostics of instance `inst` from the fields of the last step, FP64:
+ * out[0..2] sum_x phi_i, out[3] sum_x q, out[4] max |phi1+phi2+phi3-1|,
+ * out[5] relative potential change of the last sub-iteration, out[6]
+ * sub-iterations of the last step, out[7] non-finite population count,
+ * out[8] deformation of the outer drop (indicator 1 - phi1), out[9] of the
+ * inner drop (indicator phi3), both (sqrt(I_par) - sqrt(I_perp)) /
+ * (sqrt(I_par) + sqrt(I_perp)) with second moments parallel (y) and
+ * perpendicular (x) to the electrode field.  Synchronises.  Returns
+ * LBM_EHD_EDIVERGED if out[7] > 0. */
+int lbm_ehd_diagnostics(lbm_ehd_t h, int32_t inst, double out[10]);
+
+/* Host-side counters: out[0] steps taken, out[1] total potential
+ * sub-iterations run in those steps (summed over instances), out[2]
+ * instances.  Synchronises. */
+int lbm_ehd_scalars(lbm_ehd_t h, double out[3]);
+
+/* Save / restore the complete evolving state (populations of the current
+ * level, history planes, last fields, control words) to / from caller
+ * device memory of lbm_ehd_checkpoint_bytes.  Checkpoint is async; restore
+ * synchronises (it reads back the restored step count).  N+N steps with a
+ * save/restore in between equal 2N steps bitwise. */
+int lbm_ehd_checkpoint_bytes(lbm_ehd_t h, size_t *bytes);
+int lbm_ehd_checkpoint(lbm_ehd_t h, void *dev_buf);
+int lbm_ehd_restore(lbm_ehd_t h, const void *dev_buf);
+
+/* Gradient of a final-state objective with respect to (eps2/eps1,
+ * eps3/eps1, sigma2/sigma1, sigma3/sigma1, E0) by a hand-written reverse
+ * step.  Not available in this build: returns LBM_EHD_EUNSUPPORTED. */
+int lbm_ehd_adjoint(lbm_ehd_t h, int64_t n_steps, int32_t ckpt_every, const void *dev_seed,
+                    uint32_t seed_mask, double grad_theta[5]);
+
+/* Kernel timing.  Between lbm_ehd_profile_begin and lbm_ehd_profile_end
+ * every kernel launch of the handle is bracketed by HIP events on its stream
+ * (kernel durations are unchanged; launches are not otherwise altered).
+ * lbm_ehd_profile_end synchronises and returns, per kernel kind, the summed
+ * event time in ms and the launch count: index 0 moments, 1 charge/stencil
+ * (pre), 2 potential sub-iteration, 3 field + chemical potential, 4 fused
+ * collide-and-stream, 5 diagnostics; 6..7 unused. */
+int lbm_ehd_profile_begin(lbm_ehd_t h);
+int lbm_ehd_profile_end(lbm_ehd_t h, double ms[8], int64_t launches[8]);
+
+/* Release the handle (not the caller's device memory).  NULL is ignored. */
+void lbm_ehd_destroy(lbm_ehd_t h);
+
+const char *lbm_ehd_strerror(int code);
+/* Message of the last failing call on h (h may be NULL: last create error). */
+const char *lbm_ehd_last_error(lbm_ehd_t h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_EHD_H */

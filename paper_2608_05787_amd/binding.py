@@ -1,0 +1,239 @@
+"""ctypes binding of the C ABI in include/lbm_ehd.h (argument marshalling only).
+
+Every step of the method runs in the HIP library ``liblbm_ehd.so``; PyTorch
+only provides the device workspace, the output buffers and the stream.
+Loading fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm_ehd.so")
+
+FIELDS = ["phi1", "phi2", "phi3", "rho", "ux", "uy", "p", "psi", "Ex", "Ey",
+          "q", "mu1", "mu2", "mu3", "eps", "R"]
+PRECISION = {"fp32": 0, "fp16s": 1, "fp64": 2}
+FAMILY = {"f": (0, 27), "g": (1, 9), "l": (2, 9), "h": (3, 9)}
+DIAG_KEYS = ["mass1", "mass2", "mass3", "charge", "max_sum_dev", "residual", "k_sub",
+             "nonfinite", "D_outer", "D_inner"]
+
+
+class LbmEhdError(RuntimeError):
+    pass
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("bc_y", ctypes.c_int32),
+        ("wall_q_mode", ctypes.c_int32), ("eps_ref_phase", ctypes.c_int32),
+        ("phase_mode", ctypes.c_int32), ("sub_min", ctypes.c_int32), ("sub_max", ctypes.c_int32),
+        ("init_sub_max", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+        ("sub_tol", ctypes.c_double), ("init_tol", ctypes.c_double),
+        ("wall_u", ctypes.c_double * 2), ("wall_phi", ctypes.c_double * 2),
+        ("wall_q", ctypes.c_double * 2), ("E_ext", ctypes.c_double * 2),
+        ("gamma12", ctypes.c_double), ("gamma13", ctypes.c_double),
+        ("gamma23", ctypes.c_double), ("width", ctypes.c_double),
+        ("rho", ctypes.c_double * 3), ("visc", ctypes.c_double * 3),
+        ("eps", ctypes.c_double * 3), ("sigma", ctypes.c_double * 3),
+        ("tau_f", ctypes.c_double), ("tau_l", ctypes.c_double),
+    ]
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class Init(ctypes.Structure):
+    _fields_ = [("phi0", _dp), ("u0", _dp), ("q0", _dp), ("psi0", _dp)]
+
+
+EXPORTS = ["lbm_ehd_workspace_bytes", "lbm_ehd_create", "lbm_ehd_step", "lbm_ehd_fields",
+           "lbm_ehd_populations", "lbm_ehd_diagnostics", "lbm_ehd_scalars",
+           "lbm_ehd_checkpoint_bytes", "lbm_ehd_checkpoint", "lbm_ehd_restore",
+           "lbm_ehd_adjoint", "lbm_ehd_profile_begin", "lbm_ehd_profile_end",
+           "lbm_ehd_destroy", "lbm_ehd_strerror", "lbm_ehd_last_error"]
+KERNELS = ["moments", "pre", "poisson", "mu", "collide", "diag"]
+
+_lib = None
+
+
+def load():
+    """Load liblbm_ehd.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LbmEhdError("HIP library %s is not built; run __graft_entry__.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    lib.lbm_ehd_workspace_bytes.argtypes = [ctypes.POINTER(Params), ctypes.c_int32, ctypes.POINTER(sz)]
+    lib.lbm_ehd_create.argtypes = [ctypes.POINTER(Params), ctypes.c_int32, ctypes.POINTER(Init), vp, vp,
+                                   ctypes.POINTER(vp)]
+    lib.lbm_ehd_step.argtypes = [vp, ctypes.c_int64]
+    lib.lbm_ehd_fields.argtypes = [vp, ctypes.c_int32, ctypes.c_uint32, vp, ctypes.c_int32]
+    lib.lbm_ehd_populations.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int32]
+    lib.lbm_ehd_diagnostics.argtypes = [vp, ctypes.c_int32, _dp]
+    lib.lbm_ehd_scalars.argtypes = [vp, _dp]
+    lib.lbm_ehd_checkpoint_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.lbm_ehd_checkpoint.argtypes = [vp, vp]
+    lib.lbm_ehd_restore.argtypes = [vp, vp]
+    lib.lbm_ehd_adjoint.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_uint32, _dp]
+    lib.lbm_ehd_profile_begin.argtypes = [vp]
+    lib.lbm_ehd_profile_end.argtypes = [vp, _dp, ctypes.POINTER(ctypes.c_int64)]
+    lib.lbm_ehd_destroy.argtypes = [vp]
+    lib.lbm_ehd_destroy.restype = None
+    lib.lbm_ehd_strerror.argtypes = [ctypes.c_int]
+    lib.lbm_ehd_strerror.restype = ctypes.c_char_p
+    lib.lbm_ehd_last_error.argtypes = [vp]
+    lib.lbm_ehd_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def make_params(cfg: dict, precision: str = "fp32") -> Params:
+    p = Params()
+    p.nx, p.ny = int(cfg["nx"]), int(cfg["ny"])
+    p.bc_y = int(cfg.get("bc_y", 0))
+    p.wall_q_mode = int(cfg.get("wall_q_mode", 0))
+    p.eps_ref_phase = int(cfg.get("eps_ref_phase", 0))
+    p.phase_mode = int(cfg.get("phase_mode", 0))
+    p.sub_min = int(cfg.get("sub_min", 1))
+    p.sub_max = int(cfg.get("sub_max", 1))
+    p.init_sub_max = int(cfg.get("init_sub_max", 0))
+    p.precision = PRECISION[precision]
+    p.sub_tol = float(cfg.get("sub_tol", 0.0))
+    p.init_tol = float(cfg.get("init_tol", 0.0))
+    for k in ("wall_u", "wall_phi", "wall_q", "E_ext"):
+        v = cfg.get(k, (0.0, 0.0))
+        getattr(p, k)[0], getattr(p, k)[1] = float(v[0]), float(v[1])
+    p.gamma12, p.gamma13, p.gamma23 = (float(cfg[k]) for k in ("gamma12", "gamma13", "gamma23"))
+    p.width = float(cfg["width"])
+    for k in ("rho", "visc", "eps", "sigma"):
+        for i in range(3):
+            getattr(p, k)[i] = float(cfg[k][i])
+    p.tau_f, p.tau_l = float(cfg["tau_f"]), float(cfg["tau_l"])
+    return p
+
+
+class Sim:
+    """A handle over one or more instances (a batch when several are given).
+
+    cfgs: parameter dict or list of dicts; inits: dict or list of dicts of
+    float64 host arrays (phi0 [3,ny,nx], optional u0, q0, psi0).
+    """
+
+    def __init__(self, cfgs, inits, precision: str = "fp32", device="cuda", stream=None):
+        import torch
+        lib = load()
+        if isinstance(cfgs, dict):
+            cfgs, inits = [cfgs], [inits]
+        self.n_inst = len(cfgs)
+        self.shapes = [(int(c["ny"]), int(c["nx"])) for c in cfgs]
+        self.precision = precision
+        self.device = torch.device(device)
+        n = self.n_inst
+        self._params = (Params * n)(*[make_params(c, precision) for c in cfgs])
+        nbytes = ctypes.c_size_t()
+        rc = lib.lbm_ehd_workspace_bytes(self._params, n, ctypes.byref(nbytes))
+        self._check(rc, None)
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self._keep = []
+        init_arr = (Init * n)()
+        for i, ini in enumerate(inits):
+            for k in ("phi0", "u0", "q0", "psi0"):
+                v = ini.get(k)
+                if v is not None:
+                    v = np.ascontiguousarray(v, dtype=np.float64)
+                    self._keep.append(v)
+                    setattr(init_arr[i], k, v.ctypes.data_as(_dp))
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = lib.lbm_ehd_create(self._params, n, init_arr, ctypes.c_void_p(self.workspace.data_ptr()),
+                                    ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        self._check(rc, None)
+        self._h = h
+        self._keep = []
+
+    # -- helpers
+    def _check(self, rc, h):
+        if rc != 0:
+            lib = load()
+            msg = lib.lbm_ehd_last_error(h if h is not None else None)
+            raise LbmEhdError("%s: %s" % (lib.lbm_ehd_strerror(rc).decode(), (msg or b"").decode()))
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.lbm_ehd_destroy(h)
+            self._h = None
+
+    __del__ = close
+
+    # -- API
+    def step(self, n: int = 1):
+        self._check(load().lbm_ehd_step(self._h, int(n)), self._h)
+
+    def fields(self, names=None, inst: int = 0, dtype=None):
+        import torch
+        names = list(names or FIELDS)
+        mask = 0
+        for k in names:
+            mask |= 1 << FIELDS.index(k)
+        order = [k for k in FIELDS if mask & (1 << FIELDS.index(k))]
+        ny, nx = self.shapes[inst]
+        dtype = dtype or torch.float64
+        out = torch.empty((len(order), ny, nx), dtype=dtype, device=self.device)
+        dt = 1 if dtype == torch.float64 else 0
+        self._check(load().lbm_ehd_fields(self._h, inst, mask, ctypes.c_void_p(out.data_ptr()), dt), self._h)
+        return {k: out[i] for i, k in enumerate(order)}
+
+    def populations(self, fam: str, inst: int = 0, dtype=None):
+        import torch
+        idx, nq = FAMILY[fam]
+        ny, nx = self.shapes[inst]
+        dtype = dtype or torch.float64
+        out = torch.empty((nq, ny, nx), dtype=dtype, device=self.device)
+        dt = 1 if dtype == torch.float64 else 0
+        self._check(load().lbm_ehd_populations(self._h, inst, idx, ctypes.c_void_p(out.data_ptr()), dt), self._h)
+        return out
+
+    def diagnostics(self, inst: int = 0) -> dict:
+        out = (ctypes.c_double * 10)()
+        rc = load().lbm_ehd_diagnostics(self._h, inst, out)
+        d = dict(zip(DIAG_KEYS, list(out)))
+        if rc not in (0, -4):
+            self._check(rc, self._h)
+        d["status"] = rc
+        return d
+
+    def scalars(self) -> dict:
+        out = (ctypes.c_double * 3)()
+        self._check(load().lbm_ehd_scalars(self._h, out), self._h)
+        return {"steps": int(out[0]), "k_total": int(out[1]), "n_inst": int(out[2])}
+
+    def profile_begin(self):
+        self._check(load().lbm_ehd_profile_begin(self._h), self._h)
+
+    def profile_end(self) -> dict:
+        ms = (ctypes.c_double * 8)()
+        cnt = (ctypes.c_int64 * 8)()
+        self._check(load().lbm_ehd_profile_end(self._h, ms, cnt), self._h)
+        return {k: (ms[i], int(cnt[i])) for i, k in enumerate(KERNELS)}
+
+    def checkpoint(self):
+        import torch
+        nb = ctypes.c_size_t()
+        self._check(load().lbm_ehd_checkpoint_bytes(self._h, ctypes.byref(nb)), self._h)
+        buf = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        self._check(load().lbm_ehd_checkpoint(self._h, ctypes.c_void_p(buf.data_ptr())), self._h)
+        return buf
+
+    def restore(self, buf):
+        self._check(load().lbm_ehd_restore(self._h, ctypes.c_void_p(buf.data_ptr())), self._h)

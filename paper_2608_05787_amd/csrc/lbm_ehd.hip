@@ -1,0 +1,619 @@
+// Host runtime and C ABI of the three-phase EHD lattice Boltzmann step
+// (declared in include/lbm_ehd.h).  The caller owns all device memory; this
+// file carves the caller's workspace into planes, uploads the initial fields,
+// and enqueues the kernels of lbm_ehd_kernels.h on the caller's stream.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm_ehd.h"
+#include "lbm_ehd_kernels.h"
+
+using namespace lbm;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+thread_local std::string g_create_error;
+
+// Byte offsets of one instance inside the workspace.
+struct Layout {
+  size_t ctl, part_p, part_mu, part_d, planes, f[2], g[2], l[2], h[2], end;
+  int nblk;
+};
+// Macroscopic plane groups, each [k][ny][nx] contiguous with plane stride N:
+// phi(3) lsum eps q R psi E(2) mu(3) u(2) p rho hpu(6) hqu(2)
+constexpr int N_GROUPS = 13;
+constexpr int GROUP_PLANES[N_GROUPS] = {3, 1, 1, 1, 1, 1, 2, 3, 2, 1, 1, 6, 2};
+
+size_t elem_size(int prec) { return prec == LBM_PREC_FP64 ? 8 : 4; }
+size_t pop_size(int prec) { return prec == LBM_PREC_FP64 ? 8 : (prec == LBM_PREC_FP16S ? 2 : 4); }
+
+Layout layout_one(const lbm_ehd_params &p, size_t off) {
+  Layout L;
+  const size_t N = (size_t)p.nx * p.ny;
+  const size_t te = elem_size(p.precision), se = pop_size(p.precision);
+  L.nblk = (int)((N + NT - 1) / NT);
+  L.ctl = off;
+  off = align_up(off + sizeof(Ctl));
+  L.part_p = off;
+  off = align_up(off + (size_t)L.nblk * 2 * sizeof(double));
+  L.part_mu = off;
+  off = align_up(off + (size_t)L.nblk * 2 * sizeof(double));
+  L.part_d = off;
+  off = align_up(off + (size_t)L.nblk * 16 * sizeof(double));
+  L.planes = off;
+  for (int g = 0; g < N_GROUPS; ++g) off += align_up(GROUP_PLANES[g] * N * te);
+  for (int b = 0; b < 2; ++b) {
+    L.f[b] = off;
+    off = align_up(off + 27 * N * se);
+    L.g[b] = off;
+    off = align_up(off + 9 * N * se);
+    L.l[b] = off;
+    off = align_up(off + 9 * N * se);
+    L.h[b] = off;
+    off = align_up(off + 9 * N * te);
+  }
+  L.end = off;
+  return L;
+}
+
+struct Plan {
+  size_t desc_off, b2i_off, state_off, total;
+  int total_blocks;
+  std::vector<Layout> lay;
+};
+
+Plan make_plan(const lbm_ehd_params *p, int n) {
+  Plan P;
+  P.desc_off = 0;
+  size_t off = align_up((size_t)n * sizeof(Inst));
+  P.total_blocks = 0;
+  for (int i = 0; i < n; ++i) P.total_blocks += (int)(((size_t)p[i].nx * p[i].ny + NT - 1) / NT);
+  P.b2i_off = off;
+  off = align_up(off + (size_t)P.total_blocks * sizeof(int2));
+  P.state_off = off;
+  for (int i = 0; i < n; ++i) {
+    P.lay.push_back(layout_one(p[i], off));
+    off = P.lay.back().end;
+  }
+  P.total = off;
+  return P;
+}
+
+template <typename T> void fill_phys(Phys<T> &P, const lbm_ehd_params &p) {
+  const double cs2 = 1.0 / 3.0;
+  // spreading coefficients, Eq. (9)
+  P.lam[0] = (T)(p.gamma12 + p.gamma13 - p.gamma23);
+  P.lam[1] = (T)(p.gamma12 + p.gamma23 - p.gamma13);
+  P.lam[2] = (T)(p.gamma13 + p.gamma23 - p.gamma12);
+  P.m0 = (T)(cs2 * (p.tau_f - 0.5));
+  P.tau_f = (T)p.tau_f;
+  P.tau_l = (T)p.tau_l;
+  P.eps_ref = (T)p.eps[p.eps_ref_phase];
+  P.tau_h = (T)(0.5 + p.eps[p.eps_ref_phase] / cs2);
+  P.D = (T)p.width;
+  for (int i = 0; i < 3; ++i) {
+    P.rho[i] = (T)p.rho[i];
+    P.visc[i] = (T)p.visc[i];
+    P.eps[i] = (T)p.eps[i];
+    P.sig[i] = (T)p.sigma[i];
+  }
+  for (int s = 0; s < 2; ++s) {
+    P.Eext[s] = (T)p.E_ext[s];
+    P.wall_u[s] = (T)p.wall_u[s];
+    P.wall_phi[s] = (T)p.wall_phi[s];
+    P.wall_q[s] = (T)p.wall_q[s];
+  }
+}
+
+const char *validate(const lbm_ehd_params &p, const lbm_ehd_params &p0) {
+  if (p.nx < 2 || p.ny < 2) return "nx and ny must be >= 2";
+  if ((long long)p.nx * p.ny > (1ll << 30)) return "too many nodes in one instance";
+  if (p.bc_y != LBM_BC_PERIODIC && p.bc_y != LBM_BC_WALL) return "bc_y must be LBM_BC_PERIODIC or LBM_BC_WALL";
+  if (p.wall_q_mode != 0 && p.wall_q_mode != 1) return "wall_q_mode must be 0 or 1";
+  if (p.eps_ref_phase < 0 || p.eps_ref_phase > 2) return "eps_ref_phase must be 0, 1 or 2";
+  if (p.phase_mode != 0 && p.phase_mode != 1) return "phase_mode must be 0 or 1";
+  if (!(p.tau_f > 0.5) || !(p.tau_l > 0.5)) return "tau_f and tau_l must exceed 1/2";
+  if (!(p.width > 0)) return "width must be > 0";
+  const double l1 = p.gamma12 + p.gamma13 - p.gamma23, l2 = p.gamma12 + p.gamma23 - p.gamma13,
+               l3 = p.gamma13 + p.gamma23 - p.gamma12;
+  if (!(l1 > 0) || !(l2 > 0) || !(l3 > 0)) return "spreading coefficients lambda_i (Eq. 9) must be > 0";
+  for (int i = 0; i < 3; ++i) {
+    if (!(p.rho[i] > 0)) return "densities must be > 0";
+    if (!(p.visc[i] > 0)) return "viscosities must be > 0";
+    if (!(p.eps[i] > 0)) return "permittivities must be > 0";
+    if (!(p.sigma[i] >= 0)) return "conductivities must be >= 0";
+  }
+  if (p.sub_min < 1 || p.sub_max < p.sub_min || p.sub_max > 4096) return "need 1 <= sub_min <= sub_max <= 4096";
+  if (p.init_sub_max < 0) return "init_sub_max must be >= 0";
+  if (p.precision != LBM_PREC_FP32 && p.precision != LBM_PREC_FP64 && p.precision != LBM_PREC_FP16S)
+    return "unknown precision";
+  if (p.precision == LBM_PREC_FP16S) return "FP16S storage is not available in this build";
+  if (p.precision != p0.precision || p.sub_min != p0.sub_min || p.sub_max != p0.sub_max ||
+      p.sub_tol != p0.sub_tol || p.init_sub_max != p0.init_sub_max || p.init_tol != p0.init_tol)
+    return "all instances of a handle must share precision and sub-iteration settings";
+  return nullptr;
+}
+
+}  // namespace
+
+struct lbm_ehd_s {
+  int n_inst = 0, prec = 0;
+  hipStream_t stream = nullptr;
+  char *ws = nullptr;
+  Plan plan;
+  std::vector<lbm_ehd_params> params;
+  std::vector<Inst> hinst;
+  Inst *d_insts = nullptr;
+  int2 *d_b2i = nullptr;
+  int sub_min = 1, sub_max = 1, adaptive = 0;
+  double sub_tol = 0;
+  long long steps = 0;
+  std::string err;
+  // kernel timing (lbm_ehd_profile_begin/end)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_kind;  // kind of each recorded pair
+  size_t ev_used = 0;
+
+  // Bracket one launch with events when profiling; returns the stop event.
+  hipEvent_t prof_start(int kind) {
+    if (!prof) return nullptr;
+    if (ev_used + 2 > ev_pool.size()) {
+      for (int i = 0; i < 256; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        ev_pool.push_back(e);
+      }
+    }
+    hipEvent_t a = ev_pool[ev_used], b = ev_pool[ev_used + 1];
+    ev_used += 2;
+    ev_kind.push_back(kind);
+    (void)hipEventRecord(a, stream);
+    return b;
+  }
+  void prof_stop(hipEvent_t b) {
+    if (b) (void)hipEventRecord(b, stream);
+  }
+  ~lbm_ehd_s() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  }
+
+  int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    err = buf;
+    return code;
+  }
+};
+
+#define HIPC(h, call)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess) return (h)->fail(LBM_EHD_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+namespace {
+
+template <typename T, typename S>
+int do_create(lbm_ehd_s *H, const lbm_ehd_init *init) {
+  const dim3 grid(H->plan.total_blocks), block(NT);
+  const size_t te = sizeof(T);
+  // upload initial fields (converted to T on the host)
+  for (int i = 0; i < H->n_inst; ++i) {
+    const Inst &I = H->hinst[i];
+    const size_t N = (size_t)I.N;
+    std::vector<T> buf(3 * N);
+    auto up = [&](const double *src, void *dst, size_t count) -> int {
+      for (size_t k = 0; k < count; ++k) buf[k] = src ? (T)src[k] : T(0);
+      HIPC(H, hipMemcpyAsync(dst, buf.data(), count * te, hipMemcpyHostToDevice, H->stream));
+      HIPC(H, hipStreamSynchronize(H->stream));
+      return LBM_EHD_OK;
+    };
+    int rc;
+    if ((rc = up(init[i].phi0, I.phi, 3 * N))) return rc;
+    if ((rc = up(init[i].u0, I.u, 2 * N))) return rc;
+    if ((rc = up(init[i].q0, I.q, N))) return rc;
+    if ((rc = up(init[i].psi0, I.psi, N))) return rc;
+  }
+  k_init_potential<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i);
+  HIPC(H, hipGetLastError());
+  // cold start of the potential with the initial charge
+  const lbm_ehd_params &p0 = H->params[0];
+  const int kmax = p0.init_sub_max;
+  const bool adaptive = p0.init_tol > 0 && kmax > 1;
+  const int chunk = 256;
+  for (int k0 = 1; k0 <= kmax; k0 += chunk) {
+    const int k1 = std::min(kmax, k0 + chunk - 1);
+    for (int k = k0; k <= k1; ++k) {
+      k_poisson<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, k, kmax, adaptive ? 1 : 0);
+      if (adaptive) k_reduce_poisson<<<H->n_inst, block, 0, H->stream>>>(H->d_insts, k, 1, p0.init_tol);
+    }
+    HIPC(H, hipGetLastError());
+    if (adaptive) {
+      // stop launching once every instance has converged
+      HIPC(H, hipStreamSynchronize(H->stream));
+      bool all = true;
+      for (int i = 0; i < H->n_inst && all; ++i) {
+        int done = 0;
+        HIPC(H, hipMemcpy(&done, &H->hinst[i].ctl->done, sizeof(int), hipMemcpyDeviceToHost));
+        all = done != 0;
+      }
+      if (all) break;
+    }
+  }
+  const int hofs = adaptive ? 0 : (kmax & 1);
+  k_mu<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, hofs);
+  k_init_pops<T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, hofs);
+  HIPC(H, hipGetLastError());
+  HIPC(H, hipStreamSynchronize(H->stream));
+  return LBM_EHD_OK;
+}
+
+template <typename T, typename S>
+int do_step(lbm_ehd_s *H, int64_t n) {
+  const dim3 grid(H->plan.total_blocks), block(NT);
+  const int K = H->sub_max, ad = H->adaptive;
+  for (int64_t s = 0; s < n; ++s) {
+    const int pc = (int)((H->steps + s) & 1);
+    hipEvent_t e = H->prof_start(0);
+    k_moments<T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, pc);
+    H->prof_stop(e);
+    e = H->prof_start(1);
+    k_pre<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i);
+    H->prof_stop(e);
+    for (int k = 1; k <= K; ++k) {
+      e = H->prof_start(2);
+      k_poisson<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, k, K, ad);
+      H->prof_stop(e);
+      if (ad) k_reduce_poisson<<<H->n_inst, block, 0, H->stream>>>(H->d_insts, k, H->sub_min, H->sub_tol);
+    }
+    e = H->prof_start(3);
+    k_mu<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, ad ? 0 : (K & 1));
+    H->prof_stop(e);
+    e = H->prof_start(4);
+    k_collide<T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, pc, s == n - 1 ? 1 : 0, ad ? 0 : K);
+    H->prof_stop(e);
+    HIPC(H, hipGetLastError());
+  }
+  H->steps += n;
+  return LBM_EHD_OK;
+}
+
+template <typename T, typename S>
+int do_diag(lbm_ehd_s *H) {
+  const dim3 grid(H->plan.total_blocks), block(NT);
+  hipEvent_t e = H->prof_start(5);
+  k_diag<T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, (int)(H->steps & 1));
+  k_reduce_diag<<<H->n_inst, block, 0, H->stream>>>(H->d_insts);
+  H->prof_stop(e);
+  HIPC(H, hipGetLastError());
+  return LBM_EHD_OK;
+}
+
+template <typename Tin>
+int convert(lbm_ehd_s *H, const void *src, void *dst, size_t count, int dtype) {
+  const dim3 grid((unsigned)((count + NT - 1) / NT)), block(NT);
+  if (count == 0) return LBM_EHD_OK;
+  if (dtype == LBM_DTYPE_F32)
+    k_convert<Tin, float><<<grid, block, 0, H->stream>>>((const Tin *)src, (float *)dst, count);
+  else
+    k_convert<Tin, double><<<grid, block, 0, H->stream>>>((const Tin *)src, (double *)dst, count);
+  HIPC(H, hipGetLastError());
+  return LBM_EHD_OK;
+}
+
+int convert_any(lbm_ehd_s *H, int elem, const void *src, void *dst, size_t count, int dtype) {
+  if (elem == 8) return convert<double>(H, src, dst, count, dtype);
+  if (elem == 4) return convert<float>(H, src, dst, count, dtype);
+  return convert<__half>(H, src, dst, count, dtype);
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_ehd_workspace_bytes(const lbm_ehd_params *params, int32_t n_inst, size_t *bytes) {
+  if (!params || n_inst < 1 || !bytes) return LBM_EHD_EINVAL;
+  for (int i = 0; i < n_inst; ++i)
+    if (const char *m = validate(params[i], params[0])) {
+      g_create_error = m;
+      return LBM_EHD_EINVAL;
+    }
+  *bytes = make_plan(params, n_inst).total;
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_create(const lbm_ehd_params *params, int32_t n_inst, const lbm_ehd_init *init,
+                   void *dev_workspace, void *hip_stream, lbm_ehd_t *out) {
+  g_create_error.clear();
+  if (!out) return LBM_EHD_EINVAL;
+  *out = nullptr;
+  if (!params || !init || n_inst < 1) {
+    g_create_error = "params, init and n_inst >= 1 are required";
+    return LBM_EHD_EINVAL;
+  }
+  for (int i = 0; i < n_inst; ++i) {
+    if (const char *m = validate(params[i], params[0])) {
+      char buf[256];
+      snprintf(buf, sizeof buf, "instance %d: %s", i, m);
+      g_create_error = buf;
+      return LBM_EHD_EINVAL;
+    }
+    if (!init[i].phi0) {
+      g_create_error = "init.phi0 is required";
+      return LBM_EHD_EINVAL;
+    }
+  }
+  if (!dev_workspace || ((uintptr_t)dev_workspace % ALIGN) != 0) {
+    g_create_error = "workspace must be non-NULL and 256-byte aligned";
+    return LBM_EHD_ENOMEM;
+  }
+  lbm_ehd_s *H = new lbm_ehd_s();
+  H->n_inst = n_inst;
+  H->prec = params[0].precision;
+  H->stream = (hipStream_t)hip_stream;
+  H->ws = (char *)dev_workspace;
+  H->params.assign(params, params + n_inst);
+  H->plan = make_plan(params, n_inst);
+  H->sub_min = params[0].sub_min;
+  H->sub_max = params[0].sub_max;
+  H->sub_tol = params[0].sub_tol;
+  H->adaptive = (H->sub_tol > 0 && H->sub_max > H->sub_min) ? 1 : 0;
+  H->d_insts = (Inst *)(H->ws + H->plan.desc_off);
+  H->d_b2i = (int2 *)(H->ws + H->plan.b2i_off);
+
+  const size_t te = elem_size(H->prec);
+  // logical block order: instances one after another, blocks in row order
+  std::vector<int2> logical;
+  for (int i = 0; i < n_inst; ++i) {
+    const lbm_ehd_params &p = params[i];
+    const Layout &L = H->plan.lay[i];
+    Inst I;
+    memset(&I, 0, sizeof I);
+    I.nx = p.nx;
+    I.ny = p.ny;
+    I.N = p.nx * p.ny;
+    I.bc_y = p.bc_y;
+    I.wall_q_mode = p.wall_q_mode;
+    I.phase_mode = p.phase_mode;
+    I.nblk = L.nblk;
+    for (int b = 0; b < 2; ++b) {
+      I.f[b] = H->ws + L.f[b];
+      I.g[b] = H->ws + L.g[b];
+      I.l[b] = H->ws + L.l[b];
+      I.h[b] = H->ws + L.h[b];
+    }
+    char *base = H->ws + L.planes;
+    void **group[N_GROUPS] = {&I.phi, &I.lsum, &I.eps, &I.q, &I.R, &I.psi, &I.E,
+                              &I.mu, &I.u, &I.p, &I.rho, &I.hpu, &I.hqu};
+    for (int g = 0; g < N_GROUPS; ++g) {
+      *group[g] = base;
+      base += align_up(GROUP_PLANES[g] * (size_t)I.N * te);
+    }
+    I.part_p = (double *)(H->ws + L.part_p);
+    I.part_mu = (double *)(H->ws + L.part_mu);
+    I.part_d = (double *)(H->ws + L.part_d);
+    I.ctl = (Ctl *)(H->ws + L.ctl);
+    fill_phys(I.pf, p);
+    fill_phys(I.pd, p);
+    H->hinst.push_back(I);
+    for (int b = 0; b < L.nblk; ++b) logical.push_back(make_int2(i, b));
+  }
+  // XCD-aware order: launched block b runs on XCD b % 8; give XCD x the
+  // contiguous logical range [off(x), off(x) + count(x)).
+  const int B = (int)logical.size(), nx8 = 8, q8 = B / nx8, r8 = B % nx8;
+  std::vector<int2> b2i(B);
+  for (int b = 0; b < B; ++b) {
+    const int x = b % nx8, i = b / nx8;
+    b2i[b] = logical[x * q8 + std::min(x, r8) + i];
+  }
+  int rc = LBM_EHD_OK;
+  auto bad = [&](int code) {
+    g_create_error = H->err;
+    delete H;
+    return code;
+  };
+  hipError_t e;
+  if ((e = hipMemsetAsync(H->ws + H->plan.state_off, 0, H->plan.total - H->plan.state_off, H->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(H->d_insts, H->hinst.data(), sizeof(Inst) * n_inst, hipMemcpyHostToDevice, H->stream)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(H->d_b2i, b2i.data(), sizeof(int2) * b2i.size(), hipMemcpyHostToDevice, H->stream)) !=
+          hipSuccess ||
+      (e = hipStreamSynchronize(H->stream)) != hipSuccess) {
+    H->err = std::string("workspace setup: ") + hipGetErrorString(e);
+    return bad(LBM_EHD_EHIP);
+  }
+  if (H->prec == LBM_PREC_FP64)
+    rc = do_create<double, double>(H, init);
+  else
+    rc = do_create<float, float>(H, init);
+  if (rc) return bad(rc);
+  *out = H;
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_step(lbm_ehd_t H, int64_t n) {
+  if (!H || n < 0) return LBM_EHD_EINVAL;
+  if (n == 0) return LBM_EHD_OK;
+  if (H->prec == LBM_PREC_FP64) return do_step<double, double>(H, n);
+  return do_step<float, float>(H, n);
+}
+
+static void *field_src(const Inst &I, int bit) {
+  switch (bit) {
+    case 0: case 1: case 2: return I.phi;  // offset applied by caller
+    case 3: return I.rho;
+    case 4: case 5: return I.u;
+    case 6: return I.p;
+    case 7: return I.psi;
+    case 8: case 9: return I.E;
+    case 10: return I.q;
+    case 11: case 12: case 13: return I.mu;
+    case 14: return I.eps;
+    case 15: return I.R;
+    default: return nullptr;
+  }
+}
+static int field_sub(int bit) {
+  switch (bit) {
+    case 1: case 5: case 9: case 12: return 1;
+    case 2: case 13: return 2;
+    default: return 0;
+  }
+}
+
+int lbm_ehd_fields(lbm_ehd_t H, int32_t inst, uint32_t mask, void *dev_dst, int32_t dtype) {
+  if (!H || inst < 0 || inst >= H->n_inst || !dev_dst || (mask >> 16) != 0)
+    return H ? H->fail(LBM_EHD_EINVAL, "fields: bad argument") : LBM_EHD_EINVAL;
+  if (dtype != LBM_DTYPE_F32 && dtype != LBM_DTYPE_F64) return H->fail(LBM_EHD_EINVAL, "fields: bad dtype");
+  const Inst &I = H->hinst[inst];
+  const size_t N = (size_t)I.N, te = elem_size(H->prec), de = dtype == LBM_DTYPE_F64 ? 8 : 4;
+  char *dst = (char *)dev_dst;
+  for (int bit = 0; bit < 16; ++bit) {
+    if (!(mask & (1u << bit))) continue;
+    const char *src = (const char *)field_src(I, bit) + field_sub(bit) * N * te;
+    int rc = convert_any(H, (int)te, src, dst, N, dtype);
+    if (rc) return rc;
+    dst += N * de;
+  }
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_populations(lbm_ehd_t H, int32_t inst, int32_t family, void *dev_dst, int32_t dtype) {
+  if (!H || inst < 0 || inst >= H->n_inst || !dev_dst || family < 0 || family > 3)
+    return H ? H->fail(LBM_EHD_EINVAL, "populations: bad argument") : LBM_EHD_EINVAL;
+  if (dtype != LBM_DTYPE_F32 && dtype != LBM_DTYPE_F64) return H->fail(LBM_EHD_EINVAL, "populations: bad dtype");
+  const Inst &I = H->hinst[inst];
+  Ctl c;
+  HIPC(H, hipStreamSynchronize(H->stream));
+  HIPC(H, hipMemcpy(&c, I.ctl, sizeof c, hipMemcpyDeviceToHost));
+  const size_t N = (size_t)I.N;
+  const int te = (int)elem_size(H->prec), se = (int)pop_size(H->prec);
+  const int pc = (int)(H->steps & 1);
+  switch (family) {
+    case LBM_POP_F: return convert_any(H, se, I.f[I.phase_mode ? 0 : pc], dev_dst, 27 * N, dtype);
+    case LBM_POP_G: return convert_any(H, se, I.g[pc], dev_dst, 9 * N, dtype);
+    case LBM_POP_L: return convert_any(H, se, I.l[pc], dev_dst, 9 * N, dtype);
+    default: return convert_any(H, te, I.h[c.hcur], dev_dst, 9 * N, dtype);
+  }
+}
+
+int lbm_ehd_diagnostics(lbm_ehd_t H, int32_t inst, double out[10]) {
+  if (!H || inst < 0 || inst >= H->n_inst || !out) return LBM_EHD_EINVAL;
+  int rc = H->prec == LBM_PREC_FP64 ? do_diag<double, double>(H) : do_diag<float, float>(H);
+  if (rc) return rc;
+  Ctl c;
+  HIPC(H, hipStreamSynchronize(H->stream));
+  HIPC(H, hipMemcpy(&c, H->hinst[inst].ctl, sizeof c, hipMemcpyDeviceToHost));
+  for (int k = 0; k < 10; ++k) out[k] = c.diag[k];
+  if (out[7] > 0) return H->fail(LBM_EHD_EDIVERGED, "non-finite populations in instance %d", inst);
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_scalars(lbm_ehd_t H, double out[3]) {
+  if (!H || !out) return LBM_EHD_EINVAL;
+  HIPC(H, hipStreamSynchronize(H->stream));
+  double ktot = 0;
+  for (int i = 0; i < H->n_inst; ++i) {
+    Ctl c;
+    HIPC(H, hipMemcpy(&c, H->hinst[i].ctl, sizeof c, hipMemcpyDeviceToHost));
+    ktot += (double)c.k_total;
+  }
+  out[0] = (double)H->steps;
+  out[1] = ktot;
+  out[2] = H->n_inst;
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_checkpoint_bytes(lbm_ehd_t H, size_t *bytes) {
+  if (!H || !bytes) return LBM_EHD_EINVAL;
+  *bytes = H->plan.total - H->plan.state_off;
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_checkpoint(lbm_ehd_t H, void *dev_buf) {
+  if (!H || !dev_buf) return LBM_EHD_EINVAL;
+  HIPC(H, hipMemcpyAsync(dev_buf, H->ws + H->plan.state_off, H->plan.total - H->plan.state_off,
+                         hipMemcpyDeviceToDevice, H->stream));
+  H->err.clear();
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_restore(lbm_ehd_t H, const void *dev_buf) {
+  if (!H || !dev_buf) return LBM_EHD_EINVAL;
+  HIPC(H, hipMemcpyAsync(H->ws + H->plan.state_off, dev_buf, H->plan.total - H->plan.state_off,
+                         hipMemcpyDeviceToDevice, H->stream));
+  // the population buffer parity follows the restored step count
+  Ctl c;
+  HIPC(H, hipStreamSynchronize(H->stream));
+  HIPC(H, hipMemcpy(&c, H->hinst[0].ctl, sizeof c, hipMemcpyDeviceToHost));
+  H->steps = c.steps;
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_adjoint(lbm_ehd_t H, int64_t, int32_t, const void *, uint32_t, double grad_theta[5]) {
+  (void)grad_theta;
+  if (!H) return LBM_EHD_EINVAL;
+  return H->fail(LBM_EHD_EUNSUPPORTED, "adjoint is not available in this build");
+}
+
+int lbm_ehd_profile_begin(lbm_ehd_t H) {
+  if (!H) return LBM_EHD_EINVAL;
+  H->prof = true;
+  H->ev_used = 0;
+  H->ev_kind.clear();
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_profile_end(lbm_ehd_t H, double ms[8], int64_t launches[8]) {
+  if (!H || !ms || !launches) return LBM_EHD_EINVAL;
+  if (!H->prof) return H->fail(LBM_EHD_ESTATE, "profile_end without profile_begin");
+  H->prof = false;
+  for (int k = 0; k < 8; ++k) {
+    ms[k] = 0;
+    launches[k] = 0;
+  }
+  HIPC(H, hipStreamSynchronize(H->stream));
+  for (size_t i = 0; i < H->ev_kind.size(); ++i) {
+    float t = 0;
+    HIPC(H, hipEventElapsedTime(&t, H->ev_pool[2 * i], H->ev_pool[2 * i + 1]));
+    ms[H->ev_kind[i]] += t;
+    launches[H->ev_kind[i]] += 1;
+  }
+  H->ev_used = 0;
+  H->ev_kind.clear();
+  return LBM_EHD_OK;
+}
+
+void lbm_ehd_destroy(lbm_ehd_t H) { delete H; }
+
+const char *lbm_ehd_strerror(int code) {
+  switch (code) {
+    case LBM_EHD_OK: return "ok";
+    case LBM_EHD_EINVAL: return "invalid argument";
+    case LBM_EHD_ENOMEM: return "workspace too small or misaligned";
+    case LBM_EHD_EHIP: return "HIP runtime error";
+    case LBM_EHD_EDIVERGED: return "simulation diverged (non-finite populations)";
+    case LBM_EHD_ENOCONV: return "potential iteration reached its cap";
+    case LBM_EHD_ESTATE: return "call not valid in this state";
+    case LBM_EHD_EUNSUPPORTED: return "not supported by this build";
+    default: return "unknown error";
+  }
+}
+
+const char *lbm_ehd_last_error(lbm_ehd_t H) { return H ? H->err.c_str() : g_create_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,761 @@
+// Device-side data structures and kernels of the three-phase EHD LB step for
+// gfx950.  Included once, by lbm_ehd.hip.
+//
+// Layout: every plane is [ny][nx] with x fastest (structure of arrays), so a
+// wave of 64 lanes reads 64 consecutive nodes of one row.  Populations are
+// double-buffered; which buffer is current lives in a per-instance control
+// block in device memory, so the host launch sequence (and a captured graph)
+// does not depend on the step parity or on how many potential sub-iterations
+// ran.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int NT = 256;  // threads per block (4 waves of 64)
+constexpr int Q = 9;
+
+// D2Q9 velocities and weights, Eq. (31).
+__host__ __device__ constexpr int cx(int j) { return j == 1 || j == 5 || j == 8 ? 1 : (j == 3 || j == 6 || j == 7 ? -1 : 0); }
+__host__ __device__ constexpr int cy(int j) { return j == 2 || j == 5 || j == 6 ? 1 : (j == 4 || j == 7 || j == 8 ? -1 : 0); }
+__host__ __device__ constexpr int opp(int j) { return j == 0 ? 0 : (j <= 4 ? ((j + 1) & 3) + 1 : ((j - 3) & 3) + 5); }
+template <typename T> __host__ __device__ constexpr T wgt(int j) {
+  return j == 0 ? T(4) / T(9) : (j <= 4 ? T(1) / T(9) : T(1) / T(36));
+}
+
+// Per-instance control words (device memory).  The f/g/l buffer parity is
+// known to the host (one flip per step) and passed to the kernels; the
+// potential buffer parity depends on how many sub-iterations ran, so it lives
+// here.  Hot kernels never use atomics: reductions go through per-block
+// partials and a separate one-block-per-instance pass (fixed order).
+struct Ctl {
+  int hcur;          // current potential buffer at the start of a step
+  int done;          // potential loop converged in this step (adaptive mode)
+  int k_used;        // sub-iterations run in this step
+  int pad;
+  double res_prev;   // relative potential change of the previous sub-iteration
+  double res_last;   // relative potential change of the last sub-iteration
+  long long k_total; // sub-iterations summed over steps
+  long long steps;
+  double diag[16];
+};
+
+template <typename T> struct Phys {
+  T lam[3];
+  T m0, tau_f, tau_l, tau_h, eps_ref, D;
+  T rho[3], visc[3], eps[3], sig[3];
+  T Eext[2], wall_u[2], wall_phi[2], wall_q[2];
+};
+
+// Instance descriptor (device memory, read with uniform loads).
+struct Inst {
+  int nx, ny, N, bc_y;
+  int wall_q_mode, phase_mode, nblk, pad;
+  void *f[2], *g[2], *l[2], *h[2];
+  void *phi, *lsum, *eps, *q, *R, *psi, *E, *mu, *u, *p, *rho, *hpu, *hqu;
+  double *part_p;   // potential residual partials, nblk x 2
+  double *part_mu;  // last-iteration residual partials, nblk x 2
+  double *part_d;   // diagnostics partials, nblk x 16
+  Ctl *ctl;
+  Phys<float> pf;
+  Phys<double> pd;
+};
+
+template <typename T> __device__ __forceinline__ const Phys<T> &phys(const Inst &I);
+template <> __device__ __forceinline__ const Phys<float> &phys<float>(const Inst &I) { return I.pf; }
+template <> __device__ __forceinline__ const Phys<double> &phys<double>(const Inst &I) { return I.pd; }
+
+// ------------------------------------------------------------ helpers
+
+// Order-parameter populations are not evolved when the phases are frozen,
+// so they stay in buffer 0 instead of alternating with the other families.
+__device__ __forceinline__ int fbuf(const Inst &I, int pc) { return I.phase_mode ? 0 : pc; }
+
+struct Node {
+  int inst, n, x, y;
+  bool valid;
+};
+
+// The block table maps each launched block to (instance, block within the
+// instance).  The host orders it so that the blocks one XCD receives
+// (consecutive block ids go round-robin over the 8 XCDs) cover a contiguous
+// range of rows: stencil neighbours then hit that XCD's own L2.
+__device__ __forceinline__ Node locate(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
+                                       const Inst *&Ip, int &lblk) {
+  Node nd;
+  const int2 t = b2i[blockIdx.x];
+  nd.inst = t.x;
+  lblk = t.y;
+  Ip = insts + nd.inst;
+  const int local = t.y * NT + (int)threadIdx.x;
+  nd.valid = local < Ip->N;
+  nd.n = nd.valid ? local : 0;
+  nd.y = nd.n / Ip->nx;
+  nd.x = nd.n - nd.y * Ip->nx;
+  return nd;
+}
+
+__device__ __forceinline__ int wrapx(int x, int nx) { return x < 0 ? x + nx : (x >= nx ? x - nx : x); }
+// finite-difference neighbour row: wrap (periodic) or mirror ghost (walls)
+__device__ __forceinline__ int fdrow(int y, int ny, int walls) {
+  if (walls) return y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+  return y < 0 ? y + ny : (y >= ny ? y - ny : y);
+}
+
+// Eq. (33) gradient (gx, gy) and Laplacian from the 9 stencil values v[j]
+// (v[j] = chi(x + c_j)).
+template <typename T>
+__device__ __forceinline__ void fd9(const T *v, T &gx, T &gy, T &lap) {
+  T sx = 0, sy = 0, sl = 0;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    sx += wgt<T>(j) * T(cx(j)) * v[j];
+    sy += wgt<T>(j) * T(cy(j)) * v[j];
+    sl += T(2) * wgt<T>(j) * (v[j] - v[0]);
+  }
+  gx = sx * T(3);
+  gy = sy * T(3);
+  lap = sl * T(3);
+}
+
+template <typename T> __device__ __forceinline__ T herm(T p) { return p * p * (T(3) - T(2) * p); }
+
+// Block-wide sum of K doubles; result valid in thread 0.
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K]) {
+  __shared__ double red[NT / 64][K];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_down(v[k], o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[w][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = 0;
+      for (int i = 0; i < NT / 64; ++i) s += red[i][k];
+      v[k] = s;
+    }
+}
+
+// Second pass of a reduction, run by one block per instance: sums the K
+// partials of nblk blocks in a fixed order (strided per thread, then the
+// block tree), so results are bitwise reproducible.  Valid in thread 0.
+template <int K>
+__device__ __forceinline__ void reduce_partials(const double *__restrict__ part, int nblk, double (&v)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += NT)
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += part[(size_t)b * K + k];
+  block_sum<K>(v);
+}
+
+// Push-stream one family from node (x, y) with half-way walls.
+// mode 0: bounce-back with moving-wall term -2 w_j psi (c_j . u_w) / cs2;
+// mode 1: anti-bounce-back toward Dirichlet values (vb bottom, vt top).
+template <typename T, typename S>
+__device__ __forceinline__ void push(S *__restrict__ dst, const T (&v)[Q], const Inst &I, int x, int y,
+                                     int n, int mode, T psi, T ub, T ut, T vb, T vt) {
+  const int nx = I.nx, ny = I.ny, N = I.N;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const int xd = wrapx(x + cx(j), nx);
+    int yd = y + cy(j);
+    if (!I.bc_y) {
+      yd = yd < 0 ? yd + ny : (yd >= ny ? yd - ny : yd);
+      dst[(size_t)j * N + yd * nx + xd] = (S)v[j];
+    } else if (yd >= 0 && yd < ny) {
+      dst[(size_t)j * N + yd * nx + xd] = (S)v[j];
+    } else {
+      const bool top = yd >= ny;
+      T out;
+      if (mode == 0)
+        out = v[j] - T(2) * wgt<T>(j) * psi * (T(cx(j)) * (top ? ut : ub)) * T(3);
+      else
+        out = -v[j] + T(2) * wgt<T>(j) * (top ? vt : vb);
+      dst[(size_t)opp(j) * N + n] = (S)out;
+    }
+  }
+}
+
+// ------------------------------------------------------------ kernels
+
+// a1: order-parameter moments phi_i = sum_j f^i_j and the charge-population
+// sum; resets the per-step potential control words.
+template <typename T, typename S>
+__global__ __launch_bounds__(NT) void k_moments(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
+                                                int pc) {
+  const Inst *Ip;
+  int lblk;
+  const Node nd = locate(insts, b2i, Ip, lblk);
+  const Inst &I = *Ip;
+  if (lblk == 0 && threadIdx.x == 0) {
+    I.ctl->done = 0;
+    I.ctl->k_used = 0;
+  }
+  if (!nd.valid) return;
+  const int N = I.N, n = nd.n;
+  const S *f = (const S *)I.f[fbuf(I, pc)];
+  const S *l = (const S *)I.l[pc];
+  T *phi = (T *)I.phi;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T a = 0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) a += (T)f[(size_t)(i * Q + j) * N + n];
+    phi[(size_t)i * N + n] = a;
+  }
+  T b = 0;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) b += (T)l[(size_t)j * N + n];
+  ((T *)I.lsum)[n] = b;
+}
+
+// a2 + a3: permittivity/conductivity stencils (Eq. 33 on the eps and sigma
+// fields of Eqs. 29-30), charge recovery q = (sum l + R'/2)/(1 + sigma/(2 eps))
+// and the Ohmic source R of Eq. (47) with the previous step's field.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, const int2 *__restrict__ b2i) {
+  const Inst *Ip;
+  int lblk;
+  const Node nd = locate(insts, b2i, Ip, lblk);
+  if (!nd.valid) return;
+  const Inst &I = *Ip;
+  const Phys<T> &P = phys<T>(I);
+  const int N = I.N, nx = I.nx, n = nd.n;
+  const T *phi = (const T *)I.phi;
+  T ev[Q], sv[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const int m = fdrow(nd.y + cy(j), I.ny, I.bc_y) * nx + wrapx(nd.x + cx(j), nx);
+    const T p1 = phi[m], p2 = phi[(size_t)N + m], p3 = phi[(size_t)2 * N + m];
+    ev[j] = P.eps[0] * herm(p1) + P.eps[1] * herm(p2) + P.eps[2] * herm(p3);
+    sv[j] = P.sig[0] * p1 + P.sig[1] * p2 + P.sig[2] * p3;
+  }
+  T gex, gey, gsx, gsy, dummy;
+  fd9(ev, gex, gey, dummy);
+  fd9(sv, gsx, gsy, dummy);
+  const T *E = (const T *)I.E;
+  const T ex = E[n], ey = E[(size_t)N + n];
+  const T se = sv[0] / ev[0];
+  const T Rp = se * (gex * ex + gey * ey) - (gsx * ex + gsy * ey);
+  const T q = (((const T *)I.lsum)[n] + T(0.5) * Rp) / (T(1) + T(0.5) * se);
+  ((T *)I.q)[n] = q;
+  ((T *)I.R)[n] = -se * q + Rp;
+  ((T *)I.eps)[n] = ev[0];
+}
+
+// a4: one potential sub-iteration (Eqs. 43-45): local potential and gradient
+// from the pre-collision h, collision with the eps_hat first-moment source
+// and the charge source, push with anti-bounce-back electrodes.
+//   k: 1-based iteration index; K: iterations launched this step.
+//   Fixed count (adaptive == 0): the buffer parity follows k; the last
+//   iteration stores the potential of its input for the final residual.
+//   Adaptive: skipped once the loop has converged; stores the potential of
+//   its input and, from k = 2 on, the residual partials of the previous
+//   iteration for k_reduce_poisson.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
+                                                int k, int K, int adaptive) {
+  const Inst *Ip;
+  int lblk;
+  const Node nd = locate(insts, b2i, Ip, lblk);
+  const Inst &I = *Ip;
+  const Ctl *ctl = I.ctl;
+  if (adaptive && ctl->done) return;  // uniform over the instance
+  const Phys<T> &P = phys<T>(I);
+  const int hc = adaptive ? ctl->hcur : (ctl->hcur ^ ((k - 1) & 1));
+  const bool write_psi = adaptive || k == K;
+  const bool resid = adaptive && k >= 2;
+  double red[2] = {0.0, 0.0};
+  if (nd.valid) {
+    const int N = I.N, n = nd.n;
+    const T *src = (const T *)I.h[hc];
+    T *dst = (T *)I.h[hc ^ 1];
+    T h[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) h[j] = src[(size_t)j * N + n];
+    const T epshat = ((const T *)I.eps)[n] - P.eps_ref;
+    T s1 = 0, mx = 0, my = 0;
+#pragma unroll
+    for (int j = 1; j < Q; ++j) s1 += h[j];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      mx += T(cx(j)) * h[j];
+      my += T(cy(j)) * h[j];
+    }
+    const T pot = s1 / (T(1) - wgt<T>(0));
+    const T den = epshat + P.tau_h / T(3);
+    const T gx = -mx / den, gy = -my / den;  // grad(potential), Eq. (45)
+    if (write_psi) {
+      T *psi = (T *)I.psi;
+      if (resid) {
+        const double d = (double)pot - (double)psi[n];
+        red[0] = d * d;
+        red[1] = (double)pot * (double)pot;
+      }
+      psi[n] = pot;
+    }
+    const T q = ((const T *)I.q)[n];
+    const T ith = T(1) / P.tau_h;
+    T v[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const T heq = j == 0 ? (wgt<T>(0) - T(1)) * pot : wgt<T>(j) * pot;
+      const T cg = T(cx(j)) * gx + T(cy(j)) * gy;
+      v[j] = h[j] - (h[j] - heq) * ith - epshat * T(3) * wgt<T>(j) * cg * ith + (j ? T(0.125) : T(0)) * q;
+    }
+    push<T, T>(dst, v, I, nd.x, nd.y, n, 1, T(0), T(0), T(0), P.wall_phi[0], P.wall_phi[1]);
+  }
+  if (resid) {
+    block_sum<2>(red);
+    if (threadIdx.x == 0) {
+      I.part_p[(size_t)lblk * 2] = red[0];
+      I.part_p[(size_t)lblk * 2 + 1] = red[1];
+    }
+  }
+}
+
+// Adaptive potential loop control, one block per instance, after iteration
+// k: residual of iteration k-1, stopping test, buffer flip.
+__global__ __launch_bounds__(NT) void k_reduce_poisson(const Inst *__restrict__ insts, int k, int kmin,
+                                                       double tol) {
+  const Inst &I = insts[blockIdx.x];
+  Ctl *ctl = I.ctl;
+  if (ctl->done) return;  // iteration k did not run
+  double v[2];
+  if (k >= 2) reduce_partials<2>(I.part_p, I.nblk, v);
+  if (threadIdx.x == 0) {
+    if (k >= 2) {
+      const double na = sqrt(v[1]);
+      const double r = sqrt(v[0]) / (na > 1e-30 ? na : 1e-30);
+      ctl->res_prev = r;
+      if (k >= (kmin > 2 ? kmin : 2) && r < tol) ctl->done = 1;
+    }
+    ctl->k_used = k;
+    ctl->hcur ^= 1;
+  }
+}
+
+// a5: field E = -grad(potential) + E_ext from the converged h (Eq. 45), the
+// potential plane and last-iteration residual, and the chemical potentials
+// of Eq. (20) with eps'(phi_i) = 6 eps_i phi_i (1 - phi_i).
+//   hofs: buffer offset of the final h relative to ctl->hcur (fixed count:
+//   K & 1; adaptive: 0, the control pass already flipped it).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
+                                           int hofs) {
+  const Inst *Ip;
+  int lblk;
+  const Node nd = locate(insts, b2i, Ip, lblk);
+  const Inst &I = *Ip;
+  const Ctl *ctl = I.ctl;
+  const Phys<T> &P = phys<T>(I);
+  double red[2] = {0.0, 0.0};
+  if (nd.valid) {
+    const int N = I.N, nx = I.nx, n = nd.n;
+    const T *h = (const T *)I.h[ctl->hcur ^ hofs];
+    T s1 = 0, mx = 0, my = 0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const T v = h[(size_t)j * N + n];
+      if (j) s1 += v;
+      mx += T(cx(j)) * v;
+      my += T(cy(j)) * v;
+    }
+    const T eps = ((const T *)I.eps)[n];
+    const T pot = s1 / (T(1) - wgt<T>(0));
+    const T den = (eps - P.eps_ref) + P.tau_h / T(3);
+    const T ex = mx / den + P.Eext[0], ey = my / den + P.Eext[1];
+    T *psi = (T *)I.psi;
+    const double d = (double)pot - (double)psi[n];
+    red[0] = d * d;
+    red[1] = (double)pot * (double)pot;
+    psi[n] = pot;
+    T *E = (T *)I.E;
+    E[n] = ex;
+    E[(size_t)N + n] = ey;
+    const T e2 = ex * ex + ey * ey;
+    const T *phi = (const T *)I.phi;
+    T *mu = (T *)I.mu;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      T v[Q];
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        const int m = fdrow(nd.y + cy(j), I.ny, I.bc_y) * nx + wrapx(nd.x + cx(j), nx);
+        v[j] = phi[(size_t)i * N + m];
+      }
+      T gx, gy, lap;
+      fd9(v, gx, gy, lap);
+      const T ph = v[0];
+      const T bulk = T(24) / P.D * P.lam[i] * ph * (ph - T(0.5)) * (ph - T(1));
+      const T grad = T(0.75) * P.D * P.lam[i] * lap;
+      const T elec = T(0.5) * (T(6) * P.eps[i] * ph * (T(1) - ph)) * e2;
+      mu[(size_t)i * N + n] = bulk - grad - elec;
+    }
+  }
+  block_sum<2>(red);
+  if (threadIdx.x == 0) {
+    I.part_mu[(size_t)lblk * 2] = red[0];
+    I.part_mu[(size_t)lblk * 2 + 1] = red[1];
+  }
+}
+
+// a6-a11: grad(mu_i) (Eq. 33), force -sum phi_i grad mu_i + q E (Eq. 27b),
+// flow moments (Eq. 41), degenerate mobility (Eq. 28), the three CH
+// collisions (Eqs. 34-36), the flow collision (Eqs. 37-40) and the charge
+// collision (Eqs. 48-50), each pushed to its neighbours with wall rules.
+//   pc: current f/g/l buffer; write_macro: store u, p, rho for output;
+//   fixedK: sub-iterations of a fixed-count step (0 in adaptive mode), whose
+//   buffer parity block 0 folds into ctl->hcur (no other kernel of the step
+//   reads it any more).
+template <typename T, typename S>
+__global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
+                                                int pc, int write_macro, int fixedK) {
+  const Inst *Ip;
+  int lblk;
+  const Node nd = locate(insts, b2i, Ip, lblk);
+  const Inst &I = *Ip;
+  if (lblk == 0 && threadIdx.x == 0) {
+    Ctl *ctl = I.ctl;
+    if (fixedK > 0) {
+      ctl->hcur ^= (fixedK & 1);
+      ctl->k_used = fixedK;
+    }
+    ctl->k_total += ctl->k_used;
+    ctl->steps += 1;
+  }
+  if (nd.valid) {
+    const Phys<T> &P = phys<T>(I);
+    const int N = I.N, nx = I.nx, n = nd.n, x = nd.x, y = nd.y;
+    const T *phi = (const T *)I.phi;
+    const T *mu = (const T *)I.mu;
+    int m[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) m[j] = fdrow(y + cy(j), I.ny, I.bc_y) * nx + wrapx(x + cx(j), nx);
+
+    // density stencil (Eq. 33 on rho of Eq. 29) and mu gradients
+    T ph[3], rv[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const T p1 = phi[m[j]], p2 = phi[(size_t)N + m[j]], p3 = phi[(size_t)2 * N + m[j]];
+      rv[j] = P.rho[0] * p1 + P.rho[1] * p2 + P.rho[2] * p3;
+      if (j == 0) {
+        ph[0] = p1;
+        ph[1] = p2;
+        ph[2] = p3;
+      }
+    }
+    T grx, gry, dummy;
+    fd9(rv, grx, gry, dummy);
+    T gmx[3], gmy[3], muc[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      T v[Q];
+#pragma unroll
+      for (int j = 0; j < Q; ++j) v[j] = mu[(size_t)i * N + m[j]];
+      fd9(v, gmx[i], gmy[i], dummy);
+      muc[i] = v[0];
+    }
+    const T rho = rv[0];
+    const T q = ((const T *)I.q)[n];
+    const T *E = (const T *)I.E;
+    const T ex = E[n], ey = E[(size_t)N + n];
+
+    // force and flow moments
+    T Fx = q * ex, Fy = q * ey;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      Fx -= ph[i] * gmx[i];
+      Fy -= ph[i] * gmy[i];
+    }
+    const S *gs = (const S *)I.g[pc];
+    T g[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) g[j] = (T)gs[(size_t)j * N + n];
+    T mxg = 0, myg = 0, s1 = 0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      mxg += T(cx(j)) * g[j];
+      myg += T(cy(j)) * g[j];
+      if (j) s1 += g[j];
+    }
+    const T ux = (mxg + T(0.5) * Fx) / rho, uy = (myg + T(0.5) * Fy) / rho;
+    const T udr = ux * grx + uy * gry;
+    const T usq = ux * ux + uy * uy;
+    const T s0 = wgt<T>(0) * (-usq * T(1.5));
+    const T pp = (s1 + T(0.5) * udr + rho * s0) / (T(3) * (T(1) - wgt<T>(0)));
+    if (write_macro) {
+      ((T *)I.u)[n] = ux;
+      ((T *)I.u)[(size_t)N + n] = uy;
+      ((T *)I.p)[n] = pp;
+      ((T *)I.rho)[n] = rho;
+    }
+
+    // history of phi_i u and q u (first-order time derivatives)
+    T *hpu = (T *)I.hpu;
+    T *hqu = (T *)I.hqu;
+    T dpx[3], dpy[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const T ax = ph[i] * ux, ay = ph[i] * uy;
+      dpx[i] = ax - hpu[(size_t)(2 * i) * N + n];
+      dpy[i] = ay - hpu[(size_t)(2 * i + 1) * N + n];
+      hpu[(size_t)(2 * i) * N + n] = ax;
+      hpu[(size_t)(2 * i + 1) * N + n] = ay;
+    }
+    const T qx = q * ux, qy = q * uy;
+    const T dqx = qx - hqu[n], dqy = qy - hqu[(size_t)N + n];
+    hqu[n] = qx;
+    hqu[(size_t)N + n] = qy;
+
+    const int nc = pc ^ 1;
+    // three CH families
+    if (I.phase_mode == 0) {
+      const T m0 = P.m0, itf = T(1) / P.tau_f, cf = T(1) - T(0.5) * itf;
+      const S *fs = (const S *)I.f[fbuf(I, pc)];
+      S *fd = (S *)I.f[fbuf(I, nc)];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        // degenerate mobility row i: M_ik = -m0 phi_i phi_k, M_ii = -sum_k M_ik
+        T Xx = 0, Xy = 0, mii = 0;
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk)
+          if (kk != i) {
+            const T mik = -m0 * ph[i] * ph[kk];
+            mii -= mik;
+            Xx += mik * gmx[kk];
+            Xy += mik * gmy[kk];
+          }
+        Xx += (mii - m0) * gmx[i];
+        Xy += (mii - m0) * gmy[i];
+        const T dtx = dpx[i] * T(3) - Xx / m0, dty = dpy[i] * T(3) - Xy / m0;
+        const T pux = ph[i] * ux, puy = ph[i] * uy;
+        T v[Q];
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+          const T fj = (T)fs[(size_t)(i * Q + j) * N + n];
+          const T cu = T(cx(j)) * pux + T(cy(j)) * puy;
+          const T feq = j == 0 ? ph[i] - (T(1) - wgt<T>(0)) * muc[i] : wgt<T>(j) * muc[i] + wgt<T>(j) * cu * T(3);
+          const T Fj = wgt<T>(j) * (T(cx(j)) * dtx + T(cy(j)) * dty);
+          v[j] = fj - (fj - feq) * itf + cf * Fj;
+        }
+        push<T, S>(fd + (size_t)i * Q * N, v, I, x, y, n, 0, ph[i], P.wall_u[0], P.wall_u[1], T(0), T(0));
+      }
+    }
+
+    // flow family
+    {
+      const T tg = T(0.5) + (P.visc[0] * ph[0] + P.visc[1] * ph[1] + P.visc[2] * ph[2]) * T(3) / rho;
+      const T itg = T(1) / tg, cg = T(1) - T(0.5) * itg;
+      T v[Q];
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        const T cu = T(cx(j)) * ux + T(cy(j)) * uy;
+        const T sj = wgt<T>(j) * (cu * T(3) + cu * cu * T(4.5) - usq * T(1.5));
+        const T geq = (j == 0 ? (wgt<T>(0) - T(1)) * pp * T(3) : wgt<T>(j) * pp * T(3)) + rho * sj;
+        const T cF = T(cx(j)) * Fx + T(cy(j)) * Fy;
+        const T cgr = T(cx(j)) * grx + T(cy(j)) * gry;
+        const T Gb = wgt<T>(j) * (udr + cF * T(3) + (cu * cgr - udr / T(3)) * T(3));
+        v[j] = g[j] - (g[j] - geq) * itg + cg * Gb;
+      }
+      push<T, S>((S *)I.g[nc], v, I, x, y, n, 0, rho, P.wall_u[0], P.wall_u[1], T(0), T(0));
+    }
+
+    // charge family
+    {
+      const S *ls = (const S *)I.l[pc];
+      const T itl = T(1) / P.tau_l, cl = T(1) - T(0.5) * itl;
+      const T R = ((const T *)I.R)[n];
+      T v[Q];
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        const T lj = (T)ls[(size_t)j * N + n];
+        const T cu = T(cx(j)) * ux + T(cy(j)) * uy;
+        const T leq = wgt<T>(j) * q * (T(1) + cu * T(3));
+        const T Sj = cl * wgt<T>(j) * R;
+        const T Tj = cl * wgt<T>(j) * (T(cx(j)) * dqx + T(cy(j)) * dqy) * T(3);
+        v[j] = lj - (lj - leq) * itl + Sj + Tj;
+      }
+      const int mode = I.wall_q_mode == 1 ? 1 : 0;
+      push<T, S>((S *)I.l[nc], v, I, x, y, n, mode, q, P.wall_u[0], P.wall_u[1], P.wall_q[0], P.wall_q[1]);
+    }
+  }
+}
+
+// ------------------------------------------------------------ create-time
+
+// Permittivity of the initial order parameters and the potential
+// populations at the equilibrium of the initial guess (Eq. 44).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_init_potential(const Inst *__restrict__ insts, const int2 *__restrict__ b2i) {
+  const Inst *Ip;
+  int lblk;
+  const Node nd = locate(insts, b2i, Ip, lblk);
+  if (!nd.valid) return;
+  const Inst &I = *Ip;
+  const Phys<T> &P = phys<T>(I);
+  const int N = I.N, n = nd.n;
+  const T *phi = (const T *)I.phi;
+  ((T *)I.eps)[n] = P.eps[0] * herm(phi[n]) + P.eps[1] * herm(phi[(size_t)N + n]) + P.eps[2] * herm(phi[(size_t)2 * N + n]);
+  const T v = ((const T *)I.psi)[n];
+  T *h = (T *)I.h[I.ctl->hcur];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) h[(size_t)j * N + n] = j == 0 ? (wgt<T>(0) - T(1)) * v : wgt<T>(j) * v;
+}
+
+// Equilibria of the initial fields (p = 0) into buffer 0 and the history
+// planes; block 0 folds the cold start's buffer parity hofs into ctl->hcur.
+template <typename T, typename S>
+__global__ __launch_bounds__(NT) void k_init_pops(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
+                                                  int hofs) {
+  const Inst *Ip;
+  int lblk;
+  const Node nd = locate(insts, b2i, Ip, lblk);
+  const Inst &I = *Ip;
+  if (lblk == 0 && threadIdx.x == 0) I.ctl->hcur ^= hofs;
+  if (!nd.valid) return;
+  const Phys<T> &P = phys<T>(I);
+  const int N = I.N, n = nd.n, pc = 0;
+  const T *phi = (const T *)I.phi;
+  const T *mu = (const T *)I.mu;
+  const T ux = ((const T *)I.u)[n], uy = ((const T *)I.u)[(size_t)N + n];
+  const T usq = ux * ux + uy * uy;
+  const T q = ((const T *)I.q)[n];
+  T rho = 0;
+  S *f = (S *)I.f[pc];
+  T *hpu = (T *)I.hpu;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const T ph = phi[(size_t)i * N + n], m = mu[(size_t)i * N + n];
+    rho += P.rho[i] * ph;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const T cu = T(cx(j)) * ph * ux + T(cy(j)) * ph * uy;
+      f[(size_t)(i * Q + j) * N + n] = (S)(j == 0 ? ph - (T(1) - wgt<T>(0)) * m : wgt<T>(j) * m + wgt<T>(j) * cu * T(3));
+    }
+    hpu[(size_t)(2 * i) * N + n] = ph * ux;
+    hpu[(size_t)(2 * i + 1) * N + n] = ph * uy;
+  }
+  S *g = (S *)I.g[pc];
+  S *l = (S *)I.l[pc];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const T cu = T(cx(j)) * ux + T(cy(j)) * uy;
+    g[(size_t)j * N + n] = (S)(rho * wgt<T>(j) * (cu * T(3) + cu * cu * T(4.5) - usq * T(1.5)));
+    l[(size_t)j * N + n] = (S)(wgt<T>(j) * q * (T(1) + cu * T(3)));
+  }
+  ((T *)I.hqu)[n] = q * ux;
+  ((T *)I.hqu)[(size_t)N + n] = q * uy;
+  ((T *)I.p)[n] = T(0);
+  ((T *)I.rho)[n] = rho;
+  ((T *)I.R)[n] = T(0);
+}
+
+// ------------------------------------------------------------ output / diag
+
+// Copy (and convert) `nplanes` planes of element type Tin to Tout.
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(NT) void k_convert(const Tin *__restrict__ src, Tout *__restrict__ dst, size_t count) {
+  const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
+  if (i < count) dst[i] = (Tout)src[i];
+}
+
+// Diagnostics, first pass: masses, charge, max |sum phi - 1|, non-finite
+// populations and the raw second moments of the outer (1 - phi1) and inner
+// (phi3) indicators, per block.
+template <typename T, typename S>
+__global__ __launch_bounds__(NT) void k_diag(const Inst *__restrict__ insts, const int2 *__restrict__ b2i, int pc) {
+  const Inst *Ip;
+  int lblk;
+  const Node nd = locate(insts, b2i, Ip, lblk);
+  const Inst &I = *Ip;
+  double v[15];
+#pragma unroll
+  for (int k = 0; k < 15; ++k) v[k] = 0.0;
+  double mx = 0.0;
+  if (nd.valid) {
+    const int N = I.N, n = nd.n;
+    const T *phi = (const T *)I.phi;
+    const double p1 = phi[n], p2 = phi[(size_t)N + n], p3 = phi[(size_t)2 * N + n];
+    v[0] = p1;
+    v[1] = p2;
+    v[2] = p3;
+    v[3] = ((const T *)I.q)[n];
+    mx = fabs(p1 + p2 + p3 - 1.0);
+    int bad = 0;
+    const S *f = (const S *)I.f[fbuf(I, pc)];
+    for (int j = 0; j < 27; ++j) bad += !isfinite((double)(T)f[(size_t)j * N + n]);
+    const S *g = (const S *)I.g[pc];
+    const S *l = (const S *)I.l[pc];
+    const T *h = (const T *)I.h[I.ctl->hcur];
+    for (int j = 0; j < Q; ++j) {
+      bad += !isfinite((double)(T)g[(size_t)j * N + n]);
+      bad += !isfinite((double)(T)l[(size_t)j * N + n]);
+      bad += !isfinite((double)h[(size_t)j * N + n]);
+    }
+    v[4] = bad;
+    const double xx = nd.x, yy = nd.y;
+    const double wo = 1.0 - p1, wi = p3;
+    v[5] = wo; v[6] = wo * xx; v[7] = wo * yy; v[8] = wo * xx * xx; v[9] = wo * yy * yy;
+    v[10] = wi; v[11] = wi * xx; v[12] = wi * yy; v[13] = wi * xx * xx; v[14] = wi * yy * yy;
+  }
+  block_sum<15>(v);
+  __shared__ double mred[NT / 64];
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_down(mx, o, 64));
+  if ((threadIdx.x & 63) == 0) mred[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = mred[0];
+    for (int i = 1; i < NT / 64; ++i) m = fmax(m, mred[i]);
+    double *dst = I.part_d + (size_t)lblk * 16;
+    for (int k = 0; k < 15; ++k) dst[k] = v[k];
+    dst[15] = m;
+  }
+}
+
+// Diagnostics, second pass (one block per instance, fixed order): the
+// outputs of lbm_ehd_diagnostics, including the residual of the last
+// potential sub-iteration from k_mu's partials.
+__global__ __launch_bounds__(NT) void k_reduce_diag(const Inst *__restrict__ insts) {
+  const Inst &I = insts[blockIdx.x];
+  Ctl *ctl = I.ctl;
+  double s[16];
+  reduce_partials<16>(I.part_d, I.nblk, s);
+  double r[2];
+  reduce_partials<2>(I.part_mu, I.nblk, r);
+  // max over blocks of |sum phi - 1|
+  double m = 0.0;
+  for (int b = threadIdx.x; b < I.nblk; b += NT) m = fmax(m, I.part_d[(size_t)b * 16 + 15]);
+  __shared__ double mred[NT / 64];
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o, 64));
+  if ((threadIdx.x & 63) == 0) mred[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int i = 1; i < NT / 64; ++i) mred[0] = fmax(mred[0], mred[i]);
+  double *out = ctl->diag;
+  const double na = sqrt(r[1]);
+  ctl->res_last = sqrt(r[0]) / (na > 1e-30 ? na : 1e-30);
+  out[0] = s[0]; out[1] = s[1]; out[2] = s[2]; out[3] = s[3]; out[4] = mred[0];
+  out[5] = ctl->res_last; out[6] = ctl->k_used; out[7] = s[4];
+  for (int d = 0; d < 2; ++d) {
+    const double w = s[5 + 5 * d], sx = s[6 + 5 * d], sy = s[7 + 5 * d];
+    const double sxx = s[8 + 5 * d], syy = s[9 + 5 * d];
+    double val = 0.0;
+    if (w > 0) {
+      const double ipar = syy / w - (sy / w) * (sy / w);  // along the field (y)
+      const double iper = sxx / w - (sx / w) * (sx / w);  // across it (x)
+      const double a = sqrt(ipar > 0 ? ipar : 0), b = sqrt(iper > 0 ? iper : 0);
+      val = (a + b) > 0 ? (a - b) / (a + b) : 0.0;
+    }
+    out[8 + d] = val;
+  }
+}
+
+}  // namespace lbm
