@@ -118,24 +118,35 @@ def cpu_baseline(p, init, budget_s):
                       "sub-iterations each (no cold start), %.1fs" % (p["nx"], p["ny"], steps, p["sub_max"], el)}
 
 
-def field_errors(p, init, steps):
-    """Relative L2 error of FP32 fields against the FP64 instance of the same
-    kernels (the FP64 instance matches the FP64 CPU oracle to ~1e-12)."""
+def field_errors(p, init, steps, precisions=("fp32", "fp16s")):
+    """Relative L2 error of each precision's fields against the FP64 instance
+    of the same kernels (the FP64 instance matches the FP64 CPU oracle to
+    ~1e-12), after the same fixed cold start and `steps` steps."""
     import torch
     from paper_2608_05787_amd import binding
-    a = binding.Sim(p, init, precision="fp32")
     b = binding.Sim(p, init, precision="fp64")
-    a.step(steps)
     b.step(steps)
-    fa, fb = a.fields(), b.fields()
-    out = {}
-    for k in ("phi1", "phi2", "phi3", "ux", "uy", "p", "psi", "Ex", "Ey", "q", "mu1", "mu2", "mu3"):
-        nb = float(torch.linalg.norm(fb[k]))
-        out[k] = float(torch.linalg.norm(fa[k] - fb[k])) / nb if nb > 0 else 0.0
-    da, db = a.diagnostics(), b.diagnostics()
-    out["D_outer_abs"] = abs(da["D_outer"] - db["D_outer"])
-    out["D_inner_abs"] = abs(da["D_inner"] - db["D_inner"])
-    return out
+    fb = b.fields()
+    db = b.diagnostics()
+    del b
+    res = {}
+    for prec in precisions:
+        a = binding.Sim(p, init, precision=prec)
+        a.step(steps)
+        fa = a.fields()
+        out = {}
+        for k in ("phi1", "phi2", "phi3", "ux", "uy", "p", "psi", "Ex", "Ey", "q", "mu1", "mu2", "mu3"):
+            nb = float(torch.linalg.norm(fb[k]))
+            out[k] = float(torch.linalg.norm(fa[k] - fb[k])) / nb if nb > 0 else 0.0
+        da = a.diagnostics()
+        out["D_outer_abs"] = abs(da["D_outer"] - db["D_outer"])
+        out["D_inner_abs"] = abs(da["D_inner"] - db["D_inner"])
+        out["mass_rel"] = max(abs(da["mass%d" % i] - db["mass%d" % i]) / abs(db["mass%d" % i]) for i in (1, 2, 3))
+        res[prec] = out
+        del a
+    res["D_outer_fp64"] = db["D_outer"]
+    res["D_inner_fp64"] = db["D_inner"]
+    return res
 
 
 def main():
@@ -151,6 +162,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--error-steps", type=int, default=500)
     ap.add_argument("--init-iters", type=int, default=4000, help="cold-start potential iterations")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
@@ -162,6 +175,14 @@ def main():
     from paper_2608_05787_amd import binding
     binding.load()
 
+    if args.calib_copy_mib > 0:
+        a = torch.ones(args.calib_copy_mib * 262144, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy of %d MiB done" % args.calib_copy_mib)
+        del a, b
     p, init = workload(args.n, args.sub, args.init_iters)
     nodes = p["nx"] * p["ny"]
     sim, ms, prof, diag = run_gpu(p, init, "fp32", args.steps, args.warmup, args.profile_steps)
@@ -198,8 +219,10 @@ def main():
         _, ms64, _, _ = run_gpu(p, init, "fp64", max(args.steps // 2, 1), args.warmup // 2, 0)
         variants["fp64"] = {"mlups": round(nodes * max(args.steps // 2, 1) / (ms64 * 1e-3) / 1e6, 1),
                             "ms_per_step": ms64 / max(args.steps // 2, 1)}
-        variants["fp16s"] = None
-        log("field errors FP32 vs FP64 after %d steps" % args.error_steps)
+        _, ms16, _, _ = run_gpu(p, init, "fp16s", args.steps, args.warmup, 0)
+        variants["fp16s"] = {"mlups": round(nodes * args.steps / (ms16 * 1e-3) / 1e6, 1),
+                             "ms_per_step": ms16 / args.steps}
+        log("field errors FP32 / FP16S vs FP64 after %d steps" % args.error_steps)
         errors = field_errors(p, init, args.error_steps)
 
     cpu = None
@@ -219,7 +242,7 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "variants": variants,
-        "fp32_vs_fp64_rel_l2": errors,
+        "rel_l2_vs_fp64": errors,
         "diagnostics": {k: diag[k] for k in ("max_sum_dev", "residual", "D_outer", "D_inner", "nonfinite")},
         "cpu_baseline": cpu,
     }

@@ -16,8 +16,7 @@
  *  - Device memory is owned by the caller.  The library keeps non-owning
  *    pointers into the caller's workspace and never allocates device memory.
  *  - All device work of a handle is ordered on the HIP stream given at
- *    create time.  Only lbm_ehd_create, lbm_ehd_populations,
- *    lbm_ehd_diagnostics, lbm_ehd_scalars, lbm_ehd_restore and
+ *    create time.  Only lbm_ehd_create, lbm_ehd_diagnostics, lbm_ehd_scalars, lbm_ehd_restore and
  *    lbm_ehd_profile_end synchronise that stream.
  *  - One handle is used by one host thread at a time.
  *  - Layout of every field plane: row-major [ny][nx], x fastest.
@@ -89,7 +88,13 @@ enum { LBM_POP_F = 0, LBM_POP_G = 1, LBM_POP_L = 2, LBM_POP_H = 3 };
  *                is below sub_tol.  1 <= sub_min <= sub_max <= 4096.
  *  init_sub_max, init_tol  cold-start iterations of create (same rule with
  *                sub_min = 1; init_tol <= 0 runs exactly init_sub_max).
- *  precision     LBM_PREC_*: storage/arithmetic of the populations.
+ *  precision     LBM_PREC_FP32: FP32 populations and arithmetic;
+ *                LBM_PREC_FP64: the same kernels in double precision;
+ *                LBM_PREC_FP16S: FP32 arithmetic, populations stored as
+ *                half-precision values scaled by 2^14 (f, j >= 1), 2^16 (g)
+ *                and 2^16 (l), rest populations f^i_0 and the potential
+ *                populations in FP32; magnitudes must stay below 4, 1 and 1
+ *                (overflow shows up as non-finite populations).
  */
 typedef struct {
   int32_t nx, ny, bc_y, wall_q_mode;
@@ -135,7 +140,8 @@ int lbm_ehd_fields(lbm_ehd_t h, int32_t inst, uint32_t mask, void *dev_dst, int3
 
 /* Pre-collision populations of the current level of instance `inst`,
  * converted to dtype: family LBM_POP_F gives [3][9][ny][nx], the others
- * [9][ny][nx].  Synchronises (the current buffer is read from the device). */
+ * [9][ny][nx].  FP16S values are unscaled (the stored half value divided by
+ * its family's power-of-two scale; f^i_0 from its FP32 plane).  Async. */
 int lbm_ehd_populations(lbm_ehd_t h, int32_t inst, int32_t family, void *dev_dst, int32_t dtype);
 
 /* Diagnostics of instance `inst` from the fields of the last step, FP64:

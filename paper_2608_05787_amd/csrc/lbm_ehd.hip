@@ -26,7 +26,7 @@ thread_local std::string g_create_error;
 
 // Byte offsets of one instance inside the workspace.
 struct Layout {
-  size_t ctl, part_p, part_mu, part_d, planes, f[2], g[2], l[2], h[2], end;
+  size_t ctl, part_p, part_mu, part_d, planes, f[2], f0[2], g[2], l[2], h[2], end;
   int nblk;
 };
 // Macroscopic plane groups, each [k][ny][nx] contiguous with plane stride N:
@@ -55,6 +55,8 @@ Layout layout_one(const lbm_ehd_params &p, size_t off) {
   for (int b = 0; b < 2; ++b) {
     L.f[b] = off;
     off = align_up(off + 27 * N * se);
+    L.f0[b] = off;
+    if (p.precision == LBM_PREC_FP16S) off = align_up(off + 3 * N * sizeof(float));
     L.g[b] = off;
     off = align_up(off + 9 * N * se);
     L.l[b] = off;
@@ -137,7 +139,6 @@ const char *validate(const lbm_ehd_params &p, const lbm_ehd_params &p0) {
   if (p.init_sub_max < 0) return "init_sub_max must be >= 0";
   if (p.precision != LBM_PREC_FP32 && p.precision != LBM_PREC_FP64 && p.precision != LBM_PREC_FP16S)
     return "unknown precision";
-  if (p.precision == LBM_PREC_FP16S) return "FP16S storage is not available in this build";
   if (p.precision != p0.precision || p.sub_min != p0.sub_min || p.sub_max != p0.sub_max ||
       p.sub_tol != p0.sub_tol || p.init_sub_max != p0.init_sub_max || p.init_tol != p0.init_tol)
     return "all instances of a handle must share precision and sub-iteration settings";
@@ -392,6 +393,7 @@ int lbm_ehd_create(const lbm_ehd_params *params, int32_t n_inst, const lbm_ehd_i
     I.nblk = L.nblk;
     for (int b = 0; b < 2; ++b) {
       I.f[b] = H->ws + L.f[b];
+      I.f0[b] = p.precision == LBM_PREC_FP16S ? (float *)(H->ws + L.f0[b]) : nullptr;
       I.g[b] = H->ws + L.g[b];
       I.l[b] = H->ws + L.l[b];
       I.h[b] = H->ws + L.h[b];
@@ -438,6 +440,8 @@ int lbm_ehd_create(const lbm_ehd_params *params, int32_t n_inst, const lbm_ehd_i
   }
   if (H->prec == LBM_PREC_FP64)
     rc = do_create<double, double>(H, init);
+  else if (H->prec == LBM_PREC_FP16S)
+    rc = do_create<float, __half>(H, init);
   else
     rc = do_create<float, float>(H, init);
   if (rc) return bad(rc);
@@ -449,6 +453,7 @@ int lbm_ehd_step(lbm_ehd_t H, int64_t n) {
   if (!H || n < 0) return LBM_EHD_EINVAL;
   if (n == 0) return LBM_EHD_OK;
   if (H->prec == LBM_PREC_FP64) return do_step<double, double>(H, n);
+  if (H->prec == LBM_PREC_FP16S) return do_step<float, __half>(H, n);
   return do_step<float, float>(H, n);
 }
 
@@ -497,23 +502,31 @@ int lbm_ehd_populations(lbm_ehd_t H, int32_t inst, int32_t family, void *dev_dst
     return H ? H->fail(LBM_EHD_EINVAL, "populations: bad argument") : LBM_EHD_EINVAL;
   if (dtype != LBM_DTYPE_F32 && dtype != LBM_DTYPE_F64) return H->fail(LBM_EHD_EINVAL, "populations: bad dtype");
   const Inst &I = H->hinst[inst];
-  Ctl c;
-  HIPC(H, hipStreamSynchronize(H->stream));
-  HIPC(H, hipMemcpy(&c, I.ctl, sizeof c, hipMemcpyDeviceToHost));
-  const size_t N = (size_t)I.N;
-  const int te = (int)elem_size(H->prec), se = (int)pop_size(H->prec);
+  const dim3 grid((unsigned)((I.N + NT - 1) / NT)), block(NT);
   const int pc = (int)(H->steps & 1);
-  switch (family) {
-    case LBM_POP_F: return convert_any(H, se, I.f[I.phase_mode ? 0 : pc], dev_dst, 27 * N, dtype);
-    case LBM_POP_G: return convert_any(H, se, I.g[pc], dev_dst, 9 * N, dtype);
-    case LBM_POP_L: return convert_any(H, se, I.l[pc], dev_dst, 9 * N, dtype);
-    default: return convert_any(H, te, I.h[c.hcur], dev_dst, 9 * N, dtype);
-  }
+#define EXPORT(T, S)                                                                                      \
+  do {                                                                                                    \
+    if (dtype == LBM_DTYPE_F64)                                                                           \
+      k_export_pops<T, S, double><<<grid, block, 0, H->stream>>>(H->d_insts, inst, family, pc, (double *)dev_dst); \
+    else                                                                                                  \
+      k_export_pops<T, S, float><<<grid, block, 0, H->stream>>>(H->d_insts, inst, family, pc, (float *)dev_dst);   \
+  } while (0)
+  if (H->prec == LBM_PREC_FP64)
+    EXPORT(double, double);
+  else if (H->prec == LBM_PREC_FP16S)
+    EXPORT(float, __half);
+  else
+    EXPORT(float, float);
+#undef EXPORT
+  HIPC(H, hipGetLastError());
+  return LBM_EHD_OK;
 }
 
 int lbm_ehd_diagnostics(lbm_ehd_t H, int32_t inst, double out[10]) {
   if (!H || inst < 0 || inst >= H->n_inst || !out) return LBM_EHD_EINVAL;
-  int rc = H->prec == LBM_PREC_FP64 ? do_diag<double, double>(H) : do_diag<float, float>(H);
+  int rc = H->prec == LBM_PREC_FP64   ? do_diag<double, double>(H)
+           : H->prec == LBM_PREC_FP16S ? do_diag<float, __half>(H)
+                                       : do_diag<float, float>(H);
   if (rc) return rc;
   Ctl c;
   HIPC(H, hipStreamSynchronize(H->stream));

@@ -8,6 +8,7 @@
 // does not depend on the step parity or on how many potential sub-iterations
 // ran.
 #pragma once
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -53,6 +54,7 @@ struct Inst {
   int nx, ny, N, bc_y;
   int wall_q_mode, phase_mode, nblk, pad;
   void *f[2], *g[2], *l[2], *h[2];
+  float *f0[2];  // FP16S only: FP32 rest populations f^i_0, [3][N]
   void *phi, *lsum, *eps, *q, *R, *psi, *E, *mu, *u, *p, *rho, *hpu, *hqu;
   double *part_p;   // potential residual partials, nblk x 2
   double *part_mu;  // last-iteration residual partials, nblk x 2
@@ -67,6 +69,30 @@ template <> __device__ __forceinline__ const Phys<float> &phys<float>(const Inst
 template <> __device__ __forceinline__ const Phys<double> &phys<double>(const Inst &I) { return I.pd; }
 
 // ------------------------------------------------------------ helpers
+
+// Population storage.  FP32 and FP64 store the populations as they are.
+// FP16S stores each population as a half-precision value scaled by a power
+// of two per family (its deviation from the rest state, where g, l and the
+// moving f populations vanish), and keeps the three rest populations f^i_0 in
+// FP32: the colliding node writes f^i_0 = (its post-collision total) - (sum of
+// the rounded moving populations it sends), so sum_x phi_i stays exact to
+// FP32 rounding.  Arithmetic is FP32 in both FP32 and FP16S.
+constexpr float SC_F = 16384.f;  // |f^i_j| < 4 for j >= 1
+constexpr float SC_G = 65536.f;  // |g_j| < 1
+constexpr float SC_L = 65536.f;  // |l_j| < 1
+
+template <typename S, typename T> struct PopIO {
+  static constexpr bool split = false;
+  __device__ static __forceinline__ T ld(const S *p, size_t i, T) { return (T)p[i]; }
+  __device__ static __forceinline__ S cv(T v, T) { return (S)v; }
+  __device__ static __forceinline__ T back(S s, T) { return (T)s; }
+};
+template <> struct PopIO<__half, float> {
+  static constexpr bool split = true;
+  __device__ static __forceinline__ float ld(const __half *p, size_t i, float sc) { return __half2float(p[i]) / sc; }
+  __device__ static __forceinline__ __half cv(float v, float sc) { return __float2half_rn(v * sc); }
+  __device__ static __forceinline__ float back(__half s, float sc) { return __half2float(s) / sc; }
+};
 
 // Order-parameter populations are not evolved when the phases are frozen,
 // so they stay in buffer 0 instead of alternating with the other families.
@@ -158,29 +184,39 @@ __device__ __forceinline__ void reduce_partials(const double *__restrict__ part,
 // Push-stream one family from node (x, y) with half-way walls.
 // mode 0: bounce-back with moving-wall term -2 w_j psi (c_j . u_w) / cs2;
 // mode 1: anti-bounce-back toward Dirichlet values (vb bottom, vt top).
+// sc: storage scale (FP16S); skip0: do not store the rest population.
+// Returns the sum of the moving populations as stored (after rounding).
 template <typename T, typename S>
-__device__ __forceinline__ void push(S *__restrict__ dst, const T (&v)[Q], const Inst &I, int x, int y,
-                                     int n, int mode, T psi, T ub, T ut, T vb, T vt) {
+__device__ __forceinline__ T push(S *__restrict__ dst, const T (&v)[Q], const Inst &I, int x, int y, int n,
+                                  int mode, T psi, T ub, T ut, T vb, T vt, T sc, bool skip0) {
+  using IO = PopIO<S, T>;
   const int nx = I.nx, ny = I.ny, N = I.N;
+  T moved = 0;
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
     const int xd = wrapx(x + cx(j), nx);
     int yd = y + cy(j);
+    T out = v[j];
+    size_t idx;
     if (!I.bc_y) {
       yd = yd < 0 ? yd + ny : (yd >= ny ? yd - ny : yd);
-      dst[(size_t)j * N + yd * nx + xd] = (S)v[j];
+      idx = (size_t)j * N + yd * nx + xd;
     } else if (yd >= 0 && yd < ny) {
-      dst[(size_t)j * N + yd * nx + xd] = (S)v[j];
+      idx = (size_t)j * N + yd * nx + xd;
     } else {
       const bool top = yd >= ny;
-      T out;
       if (mode == 0)
         out = v[j] - T(2) * wgt<T>(j) * psi * (T(cx(j)) * (top ? ut : ub)) * T(3);
       else
         out = -v[j] + T(2) * wgt<T>(j) * (top ? vt : vb);
-      dst[(size_t)opp(j) * N + n] = (S)out;
+      idx = (size_t)opp(j) * N + n;
     }
+    if (j == 0 && skip0) continue;
+    const S st = IO::cv(out, sc);
+    dst[idx] = st;
+    if (j) moved += IO::back(st, sc);
   }
+  return moved;
 }
 
 // ------------------------------------------------------------ kernels
@@ -200,19 +236,21 @@ __global__ __launch_bounds__(NT) void k_moments(const Inst *__restrict__ insts, 
   }
   if (!nd.valid) return;
   const int N = I.N, n = nd.n;
-  const S *f = (const S *)I.f[fbuf(I, pc)];
+  using IO = PopIO<S, T>;
+  const int fb = fbuf(I, pc);
+  const S *f = (const S *)I.f[fb];
   const S *l = (const S *)I.l[pc];
   T *phi = (T *)I.phi;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    T a = 0;
+    T a = IO::split ? (T)I.f0[fb][(size_t)i * N + n] : T(0);
 #pragma unroll
-    for (int j = 0; j < Q; ++j) a += (T)f[(size_t)(i * Q + j) * N + n];
+    for (int j = IO::split ? 1 : 0; j < Q; ++j) a += IO::ld(f, (size_t)(i * Q + j) * N + n, T(SC_F));
     phi[(size_t)i * N + n] = a;
   }
   T b = 0;
 #pragma unroll
-  for (int j = 0; j < Q; ++j) b += (T)l[(size_t)j * N + n];
+  for (int j = 0; j < Q; ++j) b += IO::ld(l, (size_t)j * N + n, T(SC_L));
   ((T *)I.lsum)[n] = b;
 }
 
@@ -310,7 +348,7 @@ __global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, 
       const T cg = T(cx(j)) * gx + T(cy(j)) * gy;
       v[j] = h[j] - (h[j] - heq) * ith - epshat * T(3) * wgt<T>(j) * cg * ith + (j ? T(0.125) : T(0)) * q;
     }
-    push<T, T>(dst, v, I, nd.x, nd.y, n, 1, T(0), T(0), T(0), P.wall_phi[0], P.wall_phi[1]);
+    push<T, T>(dst, v, I, nd.x, nd.y, n, 1, T(0), T(0), T(0), P.wall_phi[0], P.wall_phi[1], T(1), false);
   }
   if (resid) {
     block_sum<2>(red);
@@ -475,10 +513,11 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
       Fx -= ph[i] * gmx[i];
       Fy -= ph[i] * gmy[i];
     }
+    using IO = PopIO<S, T>;
     const S *gs = (const S *)I.g[pc];
     T g[Q];
 #pragma unroll
-    for (int j = 0; j < Q; ++j) g[j] = (T)gs[(size_t)j * N + n];
+    for (int j = 0; j < Q; ++j) g[j] = IO::ld(gs, (size_t)j * N + n, T(SC_G));
     T mxg = 0, myg = 0, s1 = 0;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
@@ -519,8 +558,9 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
     // three CH families
     if (I.phase_mode == 0) {
       const T m0 = P.m0, itf = T(1) / P.tau_f, cf = T(1) - T(0.5) * itf;
-      const S *fs = (const S *)I.f[fbuf(I, pc)];
-      S *fd = (S *)I.f[fbuf(I, nc)];
+      const int fbs = fbuf(I, pc), fbd = fbuf(I, nc);
+      const S *fs = (const S *)I.f[fbs];
+      S *fd = (S *)I.f[fbd];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         // degenerate mobility row i: M_ik = -m0 phi_i phi_k, M_ii = -sum_k M_ik
@@ -540,13 +580,21 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
         T v[Q];
 #pragma unroll
         for (int j = 0; j < Q; ++j) {
-          const T fj = (T)fs[(size_t)(i * Q + j) * N + n];
+          const T fj = (IO::split && j == 0) ? (T)I.f0[fbs][(size_t)i * N + n]
+                                             : IO::ld(fs, (size_t)(i * Q + j) * N + n, T(SC_F));
           const T cu = T(cx(j)) * pux + T(cy(j)) * puy;
           const T feq = j == 0 ? ph[i] - (T(1) - wgt<T>(0)) * muc[i] : wgt<T>(j) * muc[i] + wgt<T>(j) * cu * T(3);
           const T Fj = wgt<T>(j) * (T(cx(j)) * dtx + T(cy(j)) * dty);
           v[j] = fj - (fj - feq) * itf + cf * Fj;
         }
-        push<T, S>(fd + (size_t)i * Q * N, v, I, x, y, n, 0, ph[i], P.wall_u[0], P.wall_u[1], T(0), T(0));
+        const T moved = push<T, S>(fd + (size_t)i * Q * N, v, I, x, y, n, 0, ph[i], P.wall_u[0], P.wall_u[1],
+                                   T(0), T(0), T(SC_F), IO::split);
+        if (IO::split) {
+          T tot = 0;
+#pragma unroll
+          for (int j = 0; j < Q; ++j) tot += v[j];
+          I.f0[fbd][(size_t)i * N + n] = (float)(tot - moved);
+        }
       }
     }
 
@@ -565,7 +613,7 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
         const T Gb = wgt<T>(j) * (udr + cF * T(3) + (cu * cgr - udr / T(3)) * T(3));
         v[j] = g[j] - (g[j] - geq) * itg + cg * Gb;
       }
-      push<T, S>((S *)I.g[nc], v, I, x, y, n, 0, rho, P.wall_u[0], P.wall_u[1], T(0), T(0));
+      push<T, S>((S *)I.g[nc], v, I, x, y, n, 0, rho, P.wall_u[0], P.wall_u[1], T(0), T(0), T(SC_G), false);
     }
 
     // charge family
@@ -576,7 +624,7 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
       T v[Q];
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
-        const T lj = (T)ls[(size_t)j * N + n];
+        const T lj = IO::ld(ls, (size_t)j * N + n, T(SC_L));
         const T cu = T(cx(j)) * ux + T(cy(j)) * uy;
         const T leq = wgt<T>(j) * q * (T(1) + cu * T(3));
         const T Sj = cl * wgt<T>(j) * R;
@@ -584,7 +632,8 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
         v[j] = lj - (lj - leq) * itl + Sj + Tj;
       }
       const int mode = I.wall_q_mode == 1 ? 1 : 0;
-      push<T, S>((S *)I.l[nc], v, I, x, y, n, mode, q, P.wall_u[0], P.wall_u[1], P.wall_q[0], P.wall_q[1]);
+      push<T, S>((S *)I.l[nc], v, I, x, y, n, mode, q, P.wall_u[0], P.wall_u[1], P.wall_q[0], P.wall_q[1],
+                 T(SC_L), false);
     }
   }
 }
@@ -629,17 +678,24 @@ __global__ __launch_bounds__(NT) void k_init_pops(const Inst *__restrict__ insts
   const T usq = ux * ux + uy * uy;
   const T q = ((const T *)I.q)[n];
   T rho = 0;
+  using IO = PopIO<S, T>;
   S *f = (S *)I.f[pc];
   T *hpu = (T *)I.hpu;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const T ph = phi[(size_t)i * N + n], m = mu[(size_t)i * N + n];
     rho += P.rho[i] * ph;
+    T moved = 0;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
       const T cu = T(cx(j)) * ph * ux + T(cy(j)) * ph * uy;
-      f[(size_t)(i * Q + j) * N + n] = (S)(j == 0 ? ph - (T(1) - wgt<T>(0)) * m : wgt<T>(j) * m + wgt<T>(j) * cu * T(3));
+      const T feq = j == 0 ? ph - (T(1) - wgt<T>(0)) * m : wgt<T>(j) * m + wgt<T>(j) * cu * T(3);
+      if (IO::split && j == 0) continue;
+      const S st = IO::cv(feq, T(SC_F));
+      f[(size_t)(i * Q + j) * N + n] = st;
+      moved += IO::back(st, T(SC_F));
     }
+    if (IO::split) I.f0[pc][(size_t)i * N + n] = (float)(ph - moved);
     hpu[(size_t)(2 * i) * N + n] = ph * ux;
     hpu[(size_t)(2 * i + 1) * N + n] = ph * uy;
   }
@@ -648,8 +704,8 @@ __global__ __launch_bounds__(NT) void k_init_pops(const Inst *__restrict__ insts
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
     const T cu = T(cx(j)) * ux + T(cy(j)) * uy;
-    g[(size_t)j * N + n] = (S)(rho * wgt<T>(j) * (cu * T(3) + cu * cu * T(4.5) - usq * T(1.5)));
-    l[(size_t)j * N + n] = (S)(wgt<T>(j) * q * (T(1) + cu * T(3)));
+    g[(size_t)j * N + n] = IO::cv(rho * wgt<T>(j) * (cu * T(3) + cu * cu * T(4.5) - usq * T(1.5)), T(SC_G));
+    l[(size_t)j * N + n] = IO::cv(wgt<T>(j) * q * (T(1) + cu * T(3)), T(SC_L));
   }
   ((T *)I.hqu)[n] = q * ux;
   ((T *)I.hqu)[(size_t)N + n] = q * uy;
@@ -665,6 +721,33 @@ template <typename Tin, typename Tout>
 __global__ __launch_bounds__(NT) void k_convert(const Tin *__restrict__ src, Tout *__restrict__ dst, size_t count) {
   const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
   if (i < count) dst[i] = (Tout)src[i];
+}
+
+// Populations of the current level of instance `inst`, family fam (0 f,
+// 1 g, 2 l, 3 h), as plain numbers [planes][N] of type Tout.
+template <typename T, typename S, typename Tout>
+__global__ __launch_bounds__(NT) void k_export_pops(const Inst *__restrict__ insts, int inst, int fam, int pc,
+                                                    Tout *__restrict__ dst) {
+  using IO = PopIO<S, T>;
+  const Inst &I = insts[inst];
+  const int n = blockIdx.x * NT + threadIdx.x;
+  if (n >= I.N) return;
+  const size_t N = I.N;
+  if (fam == 0) {
+    const int fb = fbuf(I, pc);
+    const S *f = (const S *)I.f[fb];
+    for (int j = 0; j < 27; ++j) {
+      const T v = (IO::split && j % Q == 0) ? (T)I.f0[fb][(j / Q) * N + n] : IO::ld(f, j * N + n, T(SC_F));
+      dst[j * N + n] = (Tout)v;
+    }
+  } else if (fam == 3) {
+    const T *h = (const T *)I.h[I.ctl->hcur];
+    for (int j = 0; j < Q; ++j) dst[j * N + n] = (Tout)h[j * N + n];
+  } else {
+    const S *p = (const S *)(fam == 1 ? I.g[pc] : I.l[pc]);
+    const T sc = fam == 1 ? T(SC_G) : T(SC_L);
+    for (int j = 0; j < Q; ++j) dst[j * N + n] = (Tout)IO::ld(p, j * N + n, sc);
+  }
 }
 
 // Diagnostics, first pass: masses, charge, max |sum phi - 1|, non-finite
@@ -689,15 +772,21 @@ __global__ __launch_bounds__(NT) void k_diag(const Inst *__restrict__ insts, con
     v[2] = p3;
     v[3] = ((const T *)I.q)[n];
     mx = fabs(p1 + p2 + p3 - 1.0);
+    using IO = PopIO<S, T>;
     int bad = 0;
-    const S *f = (const S *)I.f[fbuf(I, pc)];
-    for (int j = 0; j < 27; ++j) bad += !isfinite((double)(T)f[(size_t)j * N + n]);
+    const int fb = fbuf(I, pc);
+    const S *f = (const S *)I.f[fb];
+    for (int j = 0; j < 27; ++j) {
+      const T v = (IO::split && j % Q == 0) ? (T)I.f0[fb][(size_t)(j / Q) * N + n]
+                                             : IO::ld(f, (size_t)j * N + n, T(SC_F));
+      bad += !isfinite((double)v);
+    }
     const S *g = (const S *)I.g[pc];
     const S *l = (const S *)I.l[pc];
     const T *h = (const T *)I.h[I.ctl->hcur];
     for (int j = 0; j < Q; ++j) {
-      bad += !isfinite((double)(T)g[(size_t)j * N + n]);
-      bad += !isfinite((double)(T)l[(size_t)j * N + n]);
+      bad += !isfinite((double)IO::ld(g, (size_t)j * N + n, T(SC_G)));
+      bad += !isfinite((double)IO::ld(l, (size_t)j * N + n, T(SC_L)));
       bad += !isfinite((double)h[(size_t)j * N + n]);
     }
     v[4] = bad;

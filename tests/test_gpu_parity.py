@@ -53,6 +53,15 @@ def compare(sim, ref, tol, fields=FIELDS, pops=True):
     return errs
 
 
+# FP16S (half-precision populations scaled per family, FP32 rest populations
+# f^i_0, FP32 arithmetic and FP32 potential populations): phi carried by the
+# FP32 f^i_0 plus 8 half values of size ~w_j mu keeps ~1e-6; charge, flow and
+# potential inherit the 2^-11 relative step of the half values of l and g.
+FP16_TOL = {"phi1": 5e-5, "phi2": 5e-5, "phi3": 5e-5, "rho": 5e-5, "eps": 5e-5,
+            "psi": 1e-2, "q": 1e-2, "R": 1e-2, "ux": 1e-2, "uy": 1e-2,
+            "p": 2e-2, "Ex": 2e-2, "Ey": 2e-2, "mu1": 2e-2, "mu2": 2e-2, "mu3": 2e-2,
+            "pop_f": 5e-5, "pop_l": 1e-2, "pop_h": 1e-2, "pop_g": 2e-2}
+
 CASES = [(8, 8, True), (9, 7, False), (33, 17, True), (130, 70, True), (64, 48, False)]
 
 
@@ -77,6 +86,50 @@ def test_fp32_matches_oracle(nx, ny, walls):
     ref.step(12)
     sim.step(12)
     compare(sim, ref, FP32_TOL)
+
+
+@pytest.mark.parametrize("nx,ny,walls", CASES[1:4])
+def test_fp16s_matches_oracle(nx, ny, walls):
+    print("case fp16s", nx, ny, walls, flush=True)
+    p, init = inputs.parity_case(nx, ny, seed=nx + ny, walls=walls)
+    ref = Oracle(p, init)
+    sim = binding.Sim(p, init, precision="fp16s")
+    m0 = [ref.field("phi%d" % i).sum() for i in (1, 2, 3)]
+    ref.step(12)
+    sim.step(12)
+    compare(sim, ref, FP16_TOL)
+    f = sim.fields(["phi1", "phi2", "phi3"])
+    for i in (1, 2, 3):
+        assert abs(float(f["phi%d" % i].sum()) - m0[i - 1]) <= 1e-6 * abs(m0[i - 1])
+
+
+def test_fp16s_deformation_within_target():
+    """Field-driven compound drop: FP16S storage keeps the deformation
+    parameters within 1e-3 of the FP64 instance (itself checked element by
+    element against the oracle above).  Phase masses: the FP64 instance keeps
+    them to ~1e-13; FP32 arithmetic (FP32 and FP16S) drifts by accumulated
+    rounding of the collision, well under 3000 steps x 2^-24 per step."""
+    print("case fp16s deformation", flush=True)
+    p, init = inputs.field_compound_drop(160, r_shell=30, r_core=20, ca_e=0.4, init_iters=3000, init_tol=0.0)
+    b = binding.Sim(p, init, precision="fp64")
+    d0 = b.diagnostics()
+    b.step(3000)
+    db = b.diagnostics()
+    assert db["status"] == 0
+    assert abs(db["D_outer"]) > 1e-4  # the drop really deforms
+    for i in (1, 2, 3):
+        k = "mass%d" % i
+        assert abs(db[k] - d0[k]) <= 1e-12 * abs(d0[k])
+    for prec in ("fp16s", "fp32"):
+        a = binding.Sim(p, init, precision=prec)
+        a.step(3000)
+        da = a.diagnostics()
+        assert da["status"] == 0
+        assert abs(da["D_outer"] - db["D_outer"]) < 1e-3, prec
+        assert abs(da["D_inner"] - db["D_inner"]) < 1e-3, prec
+        for i in (1, 2, 3):
+            k = "mass%d" % i
+            assert abs(da[k] - d0[k]) <= 5e-5 * abs(d0[k]), (prec, k, da[k], d0[k])
 
 
 def test_adaptive_subiterations_match_oracle():
