@@ -25,15 +25,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic HBM bytes per node and launch for FP32 storage (T = 4 bytes):
-# what each kernel must read and write once, no halo re-reads.
-BYTES_PER_NODE_FP32 = {
-    "moments": (27 + 9) * 4 + (3 + 1) * 4,                 # pops in, phi + l-sum out
-    "pre": (3 + 1 + 2) * 4 + 3 * 4,                         # phi, l-sum, E in; eps, q, R out
-    "poisson": (9 + 1 + 1) * 4 + 9 * 4,                     # h, eps, q in; h out (fixed count)
-    "mu": (9 + 1 + 1 + 3) * 4 + (1 + 2 + 3) * 4,            # h, eps, psi, phi in; psi, E, mu out
-    "collide": (45 + 3 + 3 + 1 + 1 + 2 + 8) * 4 + (45 + 8) * 4,  # pops, phi, mu, q, R, E, hist
-}
+
+
+def bytes_per_node(kernel, prec="fp32"):
+    """Algorithmic HBM bytes per node and launch: what a kernel must read and
+    write once (stencil neighbours and recomputed tile rings come from L2).
+    T = macroscopic element size; populations f (27), g (9), l (9) are T
+    wide, except FP16S: f^i_0 FP32 and the other 42 populations 2 bytes."""
+    t = 8 if prec == "fp64" else 4
+    s = {"fp64": 8, "fp32": 4, "fp16s": 2}[prec]             # moving/flow/charge population size
+    fpops = 3 * (t if prec != "fp16s" else 4) + 24 * s      # f: rest populations + 24 others
+    pops = fpops + 18 * s                                    # + g (9) + l (9)
+    return {
+        "moments": fpops + 9 * s + 4 * t,            # f, l in; phi, l-sum out
+        "pre": (3 + 1 + 2) * t + 3 * t,              # phi, l-sum, E in; eps, q, R out
+        "poisson": (9 + 1 + 1) * t + 9 * t,          # h, eps, q in; h out (one sub-iteration)
+        "poisson2": (9 + 1 + 1) * t + 9 * t,         # the same for two sub-iterations per launch
+        "mu": (9 + 1 + 1 + 3) * t + (1 + 2 + 3) * t,  # h, eps, psi, phi in; psi, E, mu out
+        # pops in and out; phi, mu, q, R, E, history in; history out
+        "collide": 2 * pops + (3 + 3 + 1 + 1 + 2 + 8) * t + 8 * t,
+    }[kernel]
+
+
+BYTES_PER_NODE_FP32 = {k: bytes_per_node(k) for k in ("moments", "pre", "poisson", "poisson2", "mu", "collide")}
 
 
 def log(*a):
@@ -210,18 +224,23 @@ def main():
         for k, v in kernels.items():
             if k in BYTES_PER_NODE_FP32:
                 v["gbs"] = round(BYTES_PER_NODE_FP32[k] * nodes / (v["avg_us"] * 1e-6) / 1e9, 1)
-    step_bytes = sum(BYTES_PER_NODE_FP32[k] * (args.sub if k == "poisson" else 1) for k in BYTES_PER_NODE_FP32)
+    n2, n1 = args.sub // 2, args.sub % 2
+    step_bytes = {prec: sum(bytes_per_node(k, prec) * {"poisson": n1, "poisson2": n2}.get(k, 1)
+                            for k in BYTES_PER_NODE_FP32) for prec in ("fp32", "fp16s", "fp64")}
 
-    variants = {"fp32": {"mlups": round(mlups, 1), "ms_per_step": ms / args.steps}}
+    variants = {"fp32": {"mlups": round(mlups, 1), "ms_per_step": ms / args.steps,
+                         "bytes_per_node_update": step_bytes["fp32"]}}
     errors = None
     if not args.no_variants:
         del sim
         _, ms64, _, _ = run_gpu(p, init, "fp64", max(args.steps // 2, 1), args.warmup // 2, 0)
         variants["fp64"] = {"mlups": round(nodes * max(args.steps // 2, 1) / (ms64 * 1e-3) / 1e6, 1),
-                            "ms_per_step": ms64 / max(args.steps // 2, 1)}
+                            "ms_per_step": ms64 / max(args.steps // 2, 1),
+                            "bytes_per_node_update": step_bytes["fp64"]}
         _, ms16, _, _ = run_gpu(p, init, "fp16s", args.steps, args.warmup, 0)
         variants["fp16s"] = {"mlups": round(nodes * args.steps / (ms16 * 1e-3) / 1e6, 1),
-                             "ms_per_step": ms16 / args.steps}
+                             "ms_per_step": ms16 / args.steps,
+                             "bytes_per_node_update": step_bytes["fp16s"]}
         log("field errors FP32 / FP16S vs FP64 after %d steps" % args.error_steps)
         errors = field_errors(p, init, args.error_steps)
 
@@ -238,7 +257,7 @@ def main():
         "config": {"workload": "field compound drop %dx%d (electrodes, Ca_e 0.2, eps ratios 2/0.5, "
                                "sigma ratios 3/0.3, radii 80/60)" % (args.n, args.n),
                    "nodes": nodes, "potential_subiterations": k_mean, "precision": "fp32",
-                   "algorithmic_bytes_per_node_update": step_bytes},
+                   "algorithmic_bytes_per_node_update": step_bytes["fp32"]},
         "roofline": roofline,
         "kernels": kernels,
         "variants": variants,

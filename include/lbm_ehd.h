@@ -180,8 +180,9 @@ int lbm_ehd_adjoint(lbm_ehd_t h, int64_t n_steps, int32_t ckpt_every, const void
  * (kernel durations are unchanged; launches are not otherwise altered).
  * lbm_ehd_profile_end synchronises and returns, per kernel kind, the summed
  * event time in ms and the launch count: index 0 moments, 1 charge/stencil
- * (pre), 2 potential sub-iteration, 3 field + chemical potential, 4 fused
- * collide-and-stream, 5 diagnostics; 6..7 unused. */
+ * (pre), 2 single potential sub-iteration, 3 field + chemical potential,
+ * 4 fused collide-and-stream, 5 diagnostics, 6 two potential sub-iterations
+ * in one launch; 7 unused. */
 int lbm_ehd_profile_begin(lbm_ehd_t h);
 int lbm_ehd_profile_end(lbm_ehd_t h, double ms[8], int64_t launches[8]);
 

@@ -56,7 +56,7 @@ EXPORTS = ["lbm_ehd_workspace_bytes", "lbm_ehd_create", "lbm_ehd_step", "lbm_ehd
            "lbm_ehd_checkpoint_bytes", "lbm_ehd_checkpoint", "lbm_ehd_restore",
            "lbm_ehd_adjoint", "lbm_ehd_profile_begin", "lbm_ehd_profile_end",
            "lbm_ehd_destroy", "lbm_ehd_strerror", "lbm_ehd_last_error"]
-KERNELS = ["moments", "pre", "poisson", "mu", "collide", "diag"]
+KERNELS = ["moments", "pre", "poisson", "mu", "collide", "diag", "poisson2"]
 
 _lib = None
 

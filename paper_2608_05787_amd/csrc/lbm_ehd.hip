@@ -69,8 +69,8 @@ Layout layout_one(const lbm_ehd_params &p, size_t off) {
 }
 
 struct Plan {
-  size_t desc_off, b2i_off, state_off, total;
-  int total_blocks;
+  size_t desc_off, b2i_off, t2_off, state_off, total;
+  int total_blocks, total_tiles2;
   std::vector<Layout> lay;
 };
 
@@ -82,6 +82,10 @@ Plan make_plan(const lbm_ehd_params *p, int n) {
   for (int i = 0; i < n; ++i) P.total_blocks += (int)(((size_t)p[i].nx * p[i].ny + NT - 1) / NT);
   P.b2i_off = off;
   off = align_up(off + (size_t)P.total_blocks * sizeof(int2));
+  P.total_tiles2 = 0;
+  for (int i = 0; i < n; ++i) P.total_tiles2 += ((p[i].nx + P2W - 1) / P2W) * ((p[i].ny + P2H - 1) / P2H);
+  P.t2_off = off;
+  off = align_up(off + (size_t)P.total_tiles2 * sizeof(int4));
   P.state_off = off;
   for (int i = 0; i < n; ++i) {
     P.lay.push_back(layout_one(p[i], off));
@@ -156,6 +160,7 @@ struct lbm_ehd_s {
   std::vector<Inst> hinst;
   Inst *d_insts = nullptr;
   int2 *d_b2i = nullptr;
+  int4 *d_t2 = nullptr;
   int sub_min = 1, sub_max = 1, adaptive = 0;
   double sub_tol = 0;
   long long steps = 0;
@@ -208,6 +213,28 @@ struct lbm_ehd_s {
 
 namespace {
 
+// Fixed-count potential iterations 1..K: one single-iteration launch first
+// when K is odd, then two-iteration launches.  Returns the launch count (its
+// parity is the buffer flip of the whole loop).
+template <typename T>
+int enqueue_fixed_potential(lbm_ehd_s *H, int K) {
+  const dim3 grid(H->plan.total_blocks), grid2(H->plan.total_tiles2), block(NT), block2(P2NT);
+  int L = 0, k = 1;
+  if (K & 1) {
+    hipEvent_t e = H->prof_start(2);
+    k_poisson<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, 1, K, 0, 0);
+    H->prof_stop(e);
+    L = 1;
+    k = 2;
+  }
+  for (; k + 1 <= K; k += 2, ++L) {
+    hipEvent_t e = H->prof_start(6);
+    k_poisson2<T><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, k + 1 == K ? 1 : 0);
+    H->prof_stop(e);
+  }
+  return L;
+}
+
 template <typename T, typename S>
 int do_create(lbm_ehd_s *H, const lbm_ehd_init *init) {
   const dim3 grid(H->plan.total_blocks), block(NT);
@@ -236,26 +263,29 @@ int do_create(lbm_ehd_s *H, const lbm_ehd_init *init) {
   const int kmax = p0.init_sub_max;
   const bool adaptive = p0.init_tol > 0 && kmax > 1;
   const int chunk = 256;
-  for (int k0 = 1; k0 <= kmax; k0 += chunk) {
+  int nlaunch = 0;
+  if (!adaptive) {
+    nlaunch = enqueue_fixed_potential<T>(H, kmax);
+    HIPC(H, hipGetLastError());
+  }
+  for (int k0 = 1; adaptive && k0 <= kmax; k0 += chunk) {
     const int k1 = std::min(kmax, k0 + chunk - 1);
     for (int k = k0; k <= k1; ++k) {
-      k_poisson<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, k, kmax, adaptive ? 1 : 0);
-      if (adaptive) k_reduce_poisson<<<H->n_inst, block, 0, H->stream>>>(H->d_insts, k, 1, p0.init_tol);
+      k_poisson<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, k, kmax, 1, 0);
+      k_reduce_poisson<<<H->n_inst, block, 0, H->stream>>>(H->d_insts, k, 1, p0.init_tol);
     }
     HIPC(H, hipGetLastError());
-    if (adaptive) {
-      // stop launching once every instance has converged
-      HIPC(H, hipStreamSynchronize(H->stream));
-      bool all = true;
-      for (int i = 0; i < H->n_inst && all; ++i) {
-        int done = 0;
-        HIPC(H, hipMemcpy(&done, &H->hinst[i].ctl->done, sizeof(int), hipMemcpyDeviceToHost));
-        all = done != 0;
-      }
-      if (all) break;
+    // stop launching once every instance has converged
+    HIPC(H, hipStreamSynchronize(H->stream));
+    bool all = true;
+    for (int i = 0; i < H->n_inst && all; ++i) {
+      int done = 0;
+      HIPC(H, hipMemcpy(&done, &H->hinst[i].ctl->done, sizeof(int), hipMemcpyDeviceToHost));
+      all = done != 0;
     }
+    if (all) break;
   }
-  const int hofs = adaptive ? 0 : (kmax & 1);
+  const int hofs = adaptive ? 0 : (nlaunch & 1);
   k_mu<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, hofs);
   k_init_pops<T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, hofs);
   HIPC(H, hipGetLastError());
@@ -275,17 +305,23 @@ int do_step(lbm_ehd_s *H, int64_t n) {
     e = H->prof_start(1);
     k_pre<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i);
     H->prof_stop(e);
-    for (int k = 1; k <= K; ++k) {
-      e = H->prof_start(2);
-      k_poisson<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, k, K, ad);
-      H->prof_stop(e);
-      if (ad) k_reduce_poisson<<<H->n_inst, block, 0, H->stream>>>(H->d_insts, k, H->sub_min, H->sub_tol);
+    int hflip = 0;
+    if (ad) {
+      for (int k = 1; k <= K; ++k) {
+        e = H->prof_start(2);
+        k_poisson<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, k, K, 1, 0);
+        H->prof_stop(e);
+        k_reduce_poisson<<<H->n_inst, block, 0, H->stream>>>(H->d_insts, k, H->sub_min, H->sub_tol);
+      }
+    } else {
+      hflip = enqueue_fixed_potential<T>(H, K) & 1;
     }
     e = H->prof_start(3);
-    k_mu<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, ad ? 0 : (K & 1));
+    k_mu<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, hflip);
     H->prof_stop(e);
     e = H->prof_start(4);
-    k_collide<T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, pc, s == n - 1 ? 1 : 0, ad ? 0 : K);
+    k_collide<T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, pc, s == n - 1 ? 1 : 0, ad ? 0 : K,
+                                                   hflip);
     H->prof_stop(e);
     HIPC(H, hipGetLastError());
   }
@@ -375,6 +411,7 @@ int lbm_ehd_create(const lbm_ehd_params *params, int32_t n_inst, const lbm_ehd_i
   H->adaptive = (H->sub_tol > 0 && H->sub_max > H->sub_min) ? 1 : 0;
   H->d_insts = (Inst *)(H->ws + H->plan.desc_off);
   H->d_b2i = (int2 *)(H->ws + H->plan.b2i_off);
+  H->d_t2 = (int4 *)(H->ws + H->plan.t2_off);
 
   const size_t te = elem_size(H->prec);
   // logical block order: instances one after another, blocks in row order
@@ -416,12 +453,20 @@ int lbm_ehd_create(const lbm_ehd_params *params, int32_t n_inst, const lbm_ehd_i
   }
   // XCD-aware order: launched block b runs on XCD b % 8; give XCD x the
   // contiguous logical range [off(x), off(x) + count(x)).
-  const int B = (int)logical.size(), nx8 = 8, q8 = B / nx8, r8 = B % nx8;
+  auto xcd_order = [](int B, int b) {
+    const int q8 = B / 8, r8 = B % 8, x = b % 8, i = b / 8;
+    return x * q8 + std::min(x, r8) + i;
+  };
+  const int B = (int)logical.size();
   std::vector<int2> b2i(B);
-  for (int b = 0; b < B; ++b) {
-    const int x = b % nx8, i = b / nx8;
-    b2i[b] = logical[x * q8 + std::min(x, r8) + i];
-  }
+  for (int b = 0; b < B; ++b) b2i[b] = logical[xcd_order(B, b)];
+  // tiles of the two-iteration potential kernel, rows of tiles in order
+  std::vector<int4> tl;
+  for (int i = 0; i < n_inst; ++i)
+    for (int y0 = 0; y0 < params[i].ny; y0 += P2H)
+      for (int x0 = 0; x0 < params[i].nx; x0 += P2W) tl.push_back(make_int4(i, x0, y0, 0));
+  std::vector<int4> t2(tl.size());
+  for (int b = 0; b < (int)tl.size(); ++b) t2[b] = tl[xcd_order((int)tl.size(), b)];
   int rc = LBM_EHD_OK;
   auto bad = [&](int code) {
     g_create_error = H->err;
@@ -433,6 +478,8 @@ int lbm_ehd_create(const lbm_ehd_params *params, int32_t n_inst, const lbm_ehd_i
       (e = hipMemcpyAsync(H->d_insts, H->hinst.data(), sizeof(Inst) * n_inst, hipMemcpyHostToDevice, H->stream)) !=
           hipSuccess ||
       (e = hipMemcpyAsync(H->d_b2i, b2i.data(), sizeof(int2) * b2i.size(), hipMemcpyHostToDevice, H->stream)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(H->d_t2, t2.data(), sizeof(int4) * t2.size(), hipMemcpyHostToDevice, H->stream)) !=
           hipSuccess ||
       (e = hipStreamSynchronize(H->stream)) != hipSuccess) {
     H->err = std::string("workspace setup: ") + hipGetErrorString(e);

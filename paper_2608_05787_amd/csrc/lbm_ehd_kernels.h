@@ -288,18 +288,45 @@ __global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, cons
   ((T *)I.eps)[n] = ev[0];
 }
 
+// Potential LB at one node (Eqs. 43-45): potential and gradient from the
+// pre-collision h, then the collision with the eps_hat first-moment source
+// and the charge source.  Returns the potential of the input h.
+template <typename T>
+__device__ __forceinline__ T poisson_collide(const T (&h)[Q], T epshat, T q, const Phys<T> &P, T (&v)[Q]) {
+  T s1 = 0, mx = 0, my = 0;
+#pragma unroll
+  for (int j = 1; j < Q; ++j) s1 += h[j];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    mx += T(cx(j)) * h[j];
+    my += T(cy(j)) * h[j];
+  }
+  const T pot = s1 / (T(1) - wgt<T>(0));
+  const T den = epshat + P.tau_h / T(3);
+  const T gx = -mx / den, gy = -my / den;  // grad(potential), Eq. (45)
+  const T ith = T(1) / P.tau_h;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const T heq = j == 0 ? (wgt<T>(0) - T(1)) * pot : wgt<T>(j) * pot;
+    const T cg = T(cx(j)) * gx + T(cy(j)) * gy;
+    v[j] = h[j] - (h[j] - heq) * ith - epshat * T(3) * wgt<T>(j) * cg * ith + (j ? T(0.125) : T(0)) * q;
+  }
+  return pot;
+}
+
 // a4: one potential sub-iteration (Eqs. 43-45): local potential and gradient
 // from the pre-collision h, collision with the eps_hat first-moment source
 // and the charge source, push with anti-bounce-back electrodes.
-//   k: 1-based iteration index; K: iterations launched this step.
-//   Fixed count (adaptive == 0): the buffer parity follows k; the last
-//   iteration stores the potential of its input for the final residual.
+//   k: 1-based iteration index; K: iterations this step; hpar: parity of the
+//   input buffer relative to ctl->hcur (fixed count: the launch index).
+//   Fixed count (adaptive == 0): the last iteration stores the potential of
+//   its input for the final residual.
 //   Adaptive: skipped once the loop has converged; stores the potential of
 //   its input and, from k = 2 on, the residual partials of the previous
 //   iteration for k_reduce_poisson.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
-                                                int k, int K, int adaptive) {
+                                                int k, int K, int adaptive, int hpar) {
   const Inst *Ip;
   int lblk;
   const Node nd = locate(insts, b2i, Ip, lblk);
@@ -307,7 +334,7 @@ __global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, 
   const Ctl *ctl = I.ctl;
   if (adaptive && ctl->done) return;  // uniform over the instance
   const Phys<T> &P = phys<T>(I);
-  const int hc = adaptive ? ctl->hcur : (ctl->hcur ^ ((k - 1) & 1));
+  const int hc = adaptive ? ctl->hcur : (ctl->hcur ^ hpar);
   const bool write_psi = adaptive || k == K;
   const bool resid = adaptive && k >= 2;
   double red[2] = {0.0, 0.0};
@@ -319,17 +346,9 @@ __global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, 
 #pragma unroll
     for (int j = 0; j < Q; ++j) h[j] = src[(size_t)j * N + n];
     const T epshat = ((const T *)I.eps)[n] - P.eps_ref;
-    T s1 = 0, mx = 0, my = 0;
-#pragma unroll
-    for (int j = 1; j < Q; ++j) s1 += h[j];
-#pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      mx += T(cx(j)) * h[j];
-      my += T(cy(j)) * h[j];
-    }
-    const T pot = s1 / (T(1) - wgt<T>(0));
-    const T den = epshat + P.tau_h / T(3);
-    const T gx = -mx / den, gy = -my / den;  // grad(potential), Eq. (45)
+    const T q = ((const T *)I.q)[n];
+    T v[Q];
+    const T pot = poisson_collide(h, epshat, q, P, v);
     if (write_psi) {
       T *psi = (T *)I.psi;
       if (resid) {
@@ -339,15 +358,6 @@ __global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, 
       }
       psi[n] = pot;
     }
-    const T q = ((const T *)I.q)[n];
-    const T ith = T(1) / P.tau_h;
-    T v[Q];
-#pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      const T heq = j == 0 ? (wgt<T>(0) - T(1)) * pot : wgt<T>(j) * pot;
-      const T cg = T(cx(j)) * gx + T(cy(j)) * gy;
-      v[j] = h[j] - (h[j] - heq) * ith - epshat * T(3) * wgt<T>(j) * cg * ith + (j ? T(0.125) : T(0)) * q;
-    }
     push<T, T>(dst, v, I, nd.x, nd.y, n, 1, T(0), T(0), T(0), P.wall_phi[0], P.wall_phi[1], T(1), false);
   }
   if (resid) {
@@ -356,6 +366,103 @@ __global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, 
       I.part_p[(size_t)lblk * 2] = red[0];
       I.part_p[(size_t)lblk * 2 + 1] = red[1];
     }
+  }
+}
+
+// Two potential sub-iterations in one launch (fixed count).  A block owns a
+// P2W x P2H tile and recomputes a ring of width 2 around it: it loads h,
+// eps_hat and q of the (P2W + 4) x (P2H + 4) extended tile (neighbour rows
+// come from L2), collides every extended node, streams inside LDS (pull, with
+// anti-bounce-back where the source lies beyond an electrode), collides
+// again where both neighbours were valid, streams again, and writes the
+// interior's pre-collision values to the other buffer: 80 B/node of HBM
+// traffic for two iterations instead of 160.
+//   tiles: (instance, x0, y0, -) per block; hpar: input parity relative to
+//   ctl->hcur; write_psi: store the potential of the second iteration's input
+//   (the last iteration of the step).
+constexpr int P2NT = 1024;  // threads per block of the two-iteration kernel (one node each)
+constexpr int P2EW = 64, P2ER = 16, P2W = P2EW - 4, P2H = P2ER - 4, P2RPT = P2ER / (P2NT / 64);
+
+template <typename T>
+__global__ __launch_bounds__(P2NT) void k_poisson2(const Inst *__restrict__ insts, const int4 *__restrict__ tiles,
+                                                 int hpar, int write_psi) {
+  __shared__ T buf[Q * P2EW * P2ER];
+  const int4 t = tiles[blockIdx.x];
+  const Inst &I = insts[t.x];
+  const Phys<T> &P = phys<T>(I);
+  const int nx = I.nx, ny = I.ny, N = I.N, walls = I.bc_y;
+  const int hc = I.ctl->hcur ^ hpar;
+  const T *src = (const T *)I.h[hc];
+  T *dst = (T *)I.h[hc ^ 1];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int gx = wrapx(((t.y - 2 + tx) % nx + nx) % nx, nx);
+  T h[P2RPT][Q], eh[P2RPT], qq[P2RPT];
+  int gy[P2RPT];
+  bool inside[P2RPT];
+#pragma unroll
+  for (int k = 0; k < P2RPT; ++k) {
+    const int r = ty + (P2NT / 64) * k;  // extended row of this thread's k-th node
+    int y = t.z - 2 + r;
+    bool in = true;
+    if (walls) in = (y >= 0 && y < ny);
+    else y = ((y % ny) + ny) % ny;
+    gy[k] = y;
+    inside[k] = in;
+    if (in) {
+      const int n = y * nx + gx;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) h[k][j] = src[(size_t)j * N + n];
+      eh[k] = ((const T *)I.eps)[n] - P.eps_ref;
+      qq[k] = ((const T *)I.q)[n];
+    } else {
+#pragma unroll
+      for (int j = 0; j < Q; ++j) h[k][j] = T(0);
+      eh[k] = T(0);
+      qq[k] = T(0);
+    }
+  }
+  for (int it = 0; it < 2; ++it) {
+    // collide every node this iteration can still use, post values to LDS
+#pragma unroll
+    for (int k = 0; k < P2RPT; ++k) {
+      const int r = ty + (P2NT / 64) * k, e = r * P2EW + tx;
+      T v[Q];
+      const T pot = poisson_collide(h[k], eh[k], qq[k], P, v);
+      if (it == 1 && write_psi && inside[k] && r >= 2 && r < 2 + P2H && tx >= 2 && tx < 2 + P2W) {
+        const int ux = t.y + tx - 2, uy = t.z + r - 2;
+        if (ux < nx && uy < ny) ((T *)I.psi)[gy[k] * nx + gx] = pot;
+      }
+#pragma unroll
+      for (int j = 0; j < Q; ++j) buf[j * (P2EW * P2ER) + e] = v[j];
+    }
+    __syncthreads();
+    // pull streaming inside the tile; sources beyond an electrode reflect
+    const int lo = it + 1;  // ring still valid after this streaming
+#pragma unroll
+    for (int k = 0; k < P2RPT; ++k) {
+      const int r = ty + (P2NT / 64) * k, e = r * P2EW + tx;
+      if (r < lo || r >= P2ER - lo || tx < lo || tx >= P2EW - lo || !inside[k]) continue;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        const int sy = gy[k] - cy(j);
+        if (walls && (sy < 0 || sy >= ny))
+          h[k][j] = -buf[opp(j) * (P2EW * P2ER) + e] + T(2) * wgt<T>(j) * (sy < 0 ? P.wall_phi[0] : P.wall_phi[1]);
+        else
+          h[k][j] = buf[j * (P2EW * P2ER) + e - cy(j) * P2EW - cx(j)];
+      }
+    }
+    __syncthreads();
+  }
+  // interior pre-collision values of the next level
+#pragma unroll
+  for (int k = 0; k < P2RPT; ++k) {
+    const int r = ty + (P2NT / 64) * k;
+    if (r < 2 || r >= 2 + P2H || tx < 2 || tx >= 2 + P2W || !inside[k]) continue;
+    const int ux = t.y + tx - 2, uy = t.z + r - 2;
+    if (ux >= nx || uy >= ny) continue;
+    const int n = gy[k] * nx + gx;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) dst[(size_t)j * N + n] = h[k][j];
   }
 }
 
@@ -384,7 +491,8 @@ __global__ __launch_bounds__(NT) void k_reduce_poisson(const Inst *__restrict__ 
 // potential plane and last-iteration residual, and the chemical potentials
 // of Eq. (20) with eps'(phi_i) = 6 eps_i phi_i (1 - phi_i).
 //   hofs: buffer offset of the final h relative to ctl->hcur (fixed count:
-//   K & 1; adaptive: 0, the control pass already flipped it).
+//   parity of the potential launches; adaptive: 0, the control pass already
+//   flipped it).
 template <typename T>
 __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
                                            int hofs) {
@@ -450,12 +558,12 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
 // collisions (Eqs. 34-36), the flow collision (Eqs. 37-40) and the charge
 // collision (Eqs. 48-50), each pushed to its neighbours with wall rules.
 //   pc: current f/g/l buffer; write_macro: store u, p, rho for output;
-//   fixedK: sub-iterations of a fixed-count step (0 in adaptive mode), whose
-//   buffer parity block 0 folds into ctl->hcur (no other kernel of the step
-//   reads it any more).
+//   fixedK: sub-iterations of a fixed-count step (0 in adaptive mode) and
+//   hflip the buffer parity of its launches, which block 0 folds into
+//   ctl->hcur (no other kernel of the step reads it any more).
 template <typename T, typename S>
 __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
-                                                int pc, int write_macro, int fixedK) {
+                                                int pc, int write_macro, int fixedK, int hflip) {
   const Inst *Ip;
   int lblk;
   const Node nd = locate(insts, b2i, Ip, lblk);
@@ -463,7 +571,7 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
   if (lblk == 0 && threadIdx.x == 0) {
     Ctl *ctl = I.ctl;
     if (fixedK > 0) {
-      ctl->hcur ^= (fixedK & 1);
+      ctl->hcur ^= hflip;
       ctl->k_used = fixedK;
     }
     ctl->k_total += ctl->k_used;

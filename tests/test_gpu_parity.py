@@ -77,6 +77,22 @@ def test_fp64_matches_oracle(nx, ny, walls):
     compare(sim, ref, FP64_TOL)
 
 
+@pytest.mark.parametrize("K,walls", [(1, True), (3, True), (4, False), (5, True)])
+def test_fp64_potential_iteration_counts(K, walls):
+    """Fixed counts run as one single-iteration launch (odd K) plus
+    two-iteration LDS-tiled launches; every count matches the oracle, on a
+    box narrower and wider than one tile in both directions."""
+    print("case fp64 K", K, walls, flush=True)
+    p, init = inputs.parity_case(70, 45, seed=K, walls=walls, sub=(K, K, 0.0))
+    p["init_sub_max"] = 2 * K + 1
+    ref = Oracle(p, init)
+    sim = binding.Sim(p, init, precision="fp64")
+    compare(sim, ref, FP64_TOL)
+    ref.step(5)
+    sim.step(5)
+    compare(sim, ref, FP64_TOL)
+
+
 @pytest.mark.parametrize("nx,ny,walls", CASES)
 def test_fp32_matches_oracle(nx, ny, walls):
     print("case fp32", nx, ny, walls, flush=True)
