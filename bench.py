@@ -163,6 +163,53 @@ def field_errors(p, init, steps, precisions=("fp32", "fp16s")):
     return res
 
 
+def batch_bench(n_inst, steps, sub, init_iters, graph_len=10):
+    """Parameter sweep (seeded sizes 128..512, field strengths, permittivity
+    and conductivity ratios, half sheared): aggregate MLUPS of one batched
+    handle replaying a captured graph of `graph_len` steps, of the same handle
+    launched kernel by kernel, and of one handle per instance stepped in turn
+    (sequential per-instance launches), all FP32 on one side stream."""
+    import torch
+    from paper_2608_05787_amd import binding, inputs
+    cases = inputs.batch_sweep(n_inst=n_inst, sub=(sub, sub, 0.0), init_iters=init_iters)
+    cfgs = [c[0] for c in cases]
+    inits = [c[1] for c in cases]
+    nodes = sum(c["nx"] * c["ny"] for c in cfgs)
+    stream = torch.cuda.Stream()
+
+    def timed(fn, reps):
+        fn(graph_len)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn(reps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    t0 = time.time()
+    batch = binding.Sim(cfgs, inits, precision="fp32", stream=stream)
+    torch.cuda.synchronize()
+    log("batch create %.1fs, %d instances, %d nodes" % (time.time() - t0, n_inst, nodes))
+    ms_eager = timed(batch.step, steps)
+    batch.graph(graph_len)
+    ms_graph = timed(batch.step, steps)
+    del batch
+    sims = [binding.Sim(c, i, precision="fp32", stream=stream) for c, i in zip(cfgs, inits)]
+
+    def seq(n):
+        for _ in range(n):
+            for sm in sims:
+                sm.step(1)
+    ms_seq = timed(seq, steps)
+    del sims
+    mlups = lambda ms: round(nodes * steps / (ms * 1e-3) / 1e6, 1)
+    return {"instances": n_inst, "nodes": nodes, "steps": steps, "potential_subiterations": sub,
+            "graph_steps": graph_len, "mlups_graph": mlups(ms_graph), "mlups_batched_eager": mlups(ms_eager),
+            "mlups_sequential": mlups(ms_seq), "speedup_graph_vs_sequential": round(ms_seq / ms_graph, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,6 +223,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--error-steps", type=int, default=500)
     ap.add_argument("--init-iters", type=int, default=4000, help="cold-start potential iterations")
+    ap.add_argument("--batch-instances", type=int, default=64, help="0 skips the parameter-sweep leg")
+    ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -244,6 +293,11 @@ def main():
         log("field errors FP32 / FP16S vs FP64 after %d steps" % args.error_steps)
         errors = field_errors(p, init, args.error_steps)
 
+    batch = None
+    if args.batch_instances > 0 and not args.no_variants:
+        log("batched parameter sweep")
+        batch = batch_bench(args.batch_instances, args.batch_steps, args.sub, 1000)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -262,6 +316,7 @@ def main():
         "kernels": kernels,
         "variants": variants,
         "rel_l2_vs_fp64": errors,
+        "batch_sweep": batch,
         "diagnostics": {k: diag[k] for k in ("max_sum_dev", "residual", "D_outer", "D_inner", "nonfinite")},
         "cpu_baseline": cpu,
     }

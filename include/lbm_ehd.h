@@ -130,8 +130,17 @@ int lbm_ehd_workspace_bytes(const lbm_ehd_params *params, int32_t n_inst, size_t
 int lbm_ehd_create(const lbm_ehd_params *params, int32_t n_inst, const lbm_ehd_init *init,
                    void *dev_workspace, void *hip_stream, lbm_ehd_t *out);
 
-/* Enqueue n >= 0 coupled time steps of every instance (asynchronous). */
+/* Enqueue n >= 0 coupled time steps of every instance (asynchronous).
+ * With a captured graph (lbm_ehd_graph) whole blocks of steps are replayed
+ * with one hipGraphLaunch each; remaining steps are launched kernel by
+ * kernel.  Results are identical either way. */
 int lbm_ehd_step(lbm_ehd_t h, int64_t n);
+
+/* Capture steps_per_graph (even, >= 2) coupled steps of every instance into
+ * a HIP graph that lbm_ehd_step replays (one launch for the whole block, all
+ * instances and all kernels).  0 releases the graph.  Needs a non-default
+ * stream; enqueues nothing. */
+int lbm_ehd_graph(lbm_ehd_t h, int32_t steps_per_graph);
 
 /* Write the selected fields of instance `inst` into caller device memory
  * dev_dst as consecutive planes [popcount(mask)][ny][nx] in ascending bit

@@ -54,7 +54,7 @@ class Init(ctypes.Structure):
 EXPORTS = ["lbm_ehd_workspace_bytes", "lbm_ehd_create", "lbm_ehd_step", "lbm_ehd_fields",
            "lbm_ehd_populations", "lbm_ehd_diagnostics", "lbm_ehd_scalars",
            "lbm_ehd_checkpoint_bytes", "lbm_ehd_checkpoint", "lbm_ehd_restore",
-           "lbm_ehd_adjoint", "lbm_ehd_profile_begin", "lbm_ehd_profile_end",
+           "lbm_ehd_adjoint", "lbm_ehd_profile_begin", "lbm_ehd_profile_end", "lbm_ehd_graph",
            "lbm_ehd_destroy", "lbm_ehd_strerror", "lbm_ehd_last_error"]
 KERNELS = ["moments", "pre", "poisson", "mu", "collide", "diag", "poisson2"]
 
@@ -84,6 +84,7 @@ def load():
     lib.lbm_ehd_adjoint.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_uint32, _dp]
     lib.lbm_ehd_profile_begin.argtypes = [vp]
     lib.lbm_ehd_profile_end.argtypes = [vp, _dp, ctypes.POINTER(ctypes.c_int64)]
+    lib.lbm_ehd_graph.argtypes = [vp, ctypes.c_int32]
     lib.lbm_ehd_destroy.argtypes = [vp]
     lib.lbm_ehd_destroy.restype = None
     lib.lbm_ehd_strerror.argtypes = [ctypes.c_int]
@@ -162,6 +163,16 @@ class Sim:
         self._keep = []
 
     # -- helpers
+    def _handoff(self, out):
+        """Outputs are written on the handle's stream: make the caller's
+        current stream wait for it and keep the allocation alive there."""
+        import torch
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            out.record_stream(self.stream)
+            cur.wait_stream(self.stream)
+        return out
+
     def _check(self, rc, h):
         if rc != 0:
             lib = load()
@@ -191,7 +202,9 @@ class Sim:
         dtype = dtype or torch.float64
         out = torch.empty((len(order), ny, nx), dtype=dtype, device=self.device)
         dt = 1 if dtype == torch.float64 else 0
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         self._check(load().lbm_ehd_fields(self._h, inst, mask, ctypes.c_void_p(out.data_ptr()), dt), self._h)
+        self._handoff(out)
         return {k: out[i] for i, k in enumerate(order)}
 
     def populations(self, fam: str, inst: int = 0, dtype=None):
@@ -201,8 +214,9 @@ class Sim:
         dtype = dtype or torch.float64
         out = torch.empty((nq, ny, nx), dtype=dtype, device=self.device)
         dt = 1 if dtype == torch.float64 else 0
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         self._check(load().lbm_ehd_populations(self._h, inst, idx, ctypes.c_void_p(out.data_ptr()), dt), self._h)
-        return out
+        return self._handoff(out)
 
     def diagnostics(self, inst: int = 0) -> dict:
         out = (ctypes.c_double * 10)()
@@ -218,6 +232,10 @@ class Sim:
         self._check(load().lbm_ehd_scalars(self._h, out), self._h)
         return {"steps": int(out[0]), "k_total": int(out[1]), "n_inst": int(out[2])}
 
+    def graph(self, steps_per_graph: int):
+        """Capture a block of steps into a HIP graph replayed by step()."""
+        self._check(load().lbm_ehd_graph(self._h, int(steps_per_graph)), self._h)
+
     def profile_begin(self):
         self._check(load().lbm_ehd_profile_begin(self._h), self._h)
 
@@ -232,8 +250,11 @@ class Sim:
         nb = ctypes.c_size_t()
         self._check(load().lbm_ehd_checkpoint_bytes(self._h, ctypes.byref(nb)), self._h)
         buf = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         self._check(load().lbm_ehd_checkpoint(self._h, ctypes.c_void_p(buf.data_ptr())), self._h)
-        return buf
+        return self._handoff(buf)
 
     def restore(self, buf):
+        import torch
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         self._check(load().lbm_ehd_restore(self._h, ctypes.c_void_p(buf.data_ptr())), self._h)

@@ -190,7 +190,19 @@ struct lbm_ehd_s {
   void prof_stop(hipEvent_t b) {
     if (b) (void)hipEventRecord(b, stream);
   }
+  // captured block of steps (lbm_ehd_graph)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int glen = 0, gpar = 0;
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    glen = 0;
+  }
   ~lbm_ehd_s() {
+    drop_graph();
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   }
 
@@ -496,12 +508,57 @@ int lbm_ehd_create(const lbm_ehd_params *params, int32_t n_inst, const lbm_ehd_i
   return LBM_EHD_OK;
 }
 
-int lbm_ehd_step(lbm_ehd_t H, int64_t n) {
-  if (!H || n < 0) return LBM_EHD_EINVAL;
-  if (n == 0) return LBM_EHD_OK;
+static int step_eager(lbm_ehd_t H, int64_t n) {
   if (H->prec == LBM_PREC_FP64) return do_step<double, double>(H, n);
   if (H->prec == LBM_PREC_FP16S) return do_step<float, __half>(H, n);
   return do_step<float, float>(H, n);
+}
+
+int lbm_ehd_step(lbm_ehd_t H, int64_t n) {
+  if (!H || n < 0) return LBM_EHD_EINVAL;
+  while (n > 0) {
+    if (H->gexec && !H->prof && n >= H->glen && (H->steps & 1) == H->gpar) {
+      HIPC(H, hipGraphLaunch(H->gexec, H->stream));
+      H->steps += H->glen;
+      n -= H->glen;
+      continue;
+    }
+    // without a graph, or to restore the graph's step parity, or a tail
+    const int64_t k = (H->gexec && !H->prof) ? (n >= H->glen ? 1 : n) : n;
+    const int rc = step_eager(H, k);
+    if (rc) return rc;
+    n -= k;
+  }
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_graph(lbm_ehd_t H, int32_t steps_per_graph) {
+  if (!H) return LBM_EHD_EINVAL;
+  H->drop_graph();
+  if (steps_per_graph == 0) return LBM_EHD_OK;
+  if (steps_per_graph < 2 || (steps_per_graph & 1))
+    return H->fail(LBM_EHD_EINVAL, "steps_per_graph must be an even number >= 2 (or 0 to release)");
+  if (!H->stream) return H->fail(LBM_EHD_EINVAL, "graph capture needs a non-default stream");
+  if (H->prof) return H->fail(LBM_EHD_ESTATE, "cannot capture while profiling");
+  const long long saved = H->steps;
+  HIPC(H, hipStreamBeginCapture(H->stream, hipStreamCaptureModeThreadLocal));
+  const int rc = step_eager(H, steps_per_graph);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(H->stream, &g);
+  H->steps = saved;  // captured work has not run
+  if (rc || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc ? rc : H->fail(LBM_EHD_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  }
+  H->graph = g;
+  hipError_t ei = hipGraphInstantiate(&H->gexec, g, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    H->drop_graph();
+    return H->fail(LBM_EHD_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+  }
+  H->glen = steps_per_graph;
+  H->gpar = (int)(saved & 1);
+  return LBM_EHD_OK;
 }
 
 static void *field_src(const Inst &I, int bit) {

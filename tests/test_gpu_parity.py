@@ -217,6 +217,30 @@ def test_batch_equals_separate_runs_bitwise():
             assert torch.equal(batch.populations(fam, inst=i), alone.populations(fam)), (i, fam)
 
 
+def test_graph_replay_matches_eager():
+    """A captured block of steps replayed with one graph launch gives the
+    same populations, bitwise, as kernel-by-kernel launches: a batch of three
+    instances (fixed count, odd K) and a residual-controlled single instance,
+    with an eager step in between to exercise the step-parity fix-up."""
+    print("case graph", flush=True)
+    cases = [inputs.parity_case(n, m, seed=n, sub=(3, 3, 0.0)) for n, m in ((24, 20), (41, 33), (17, 9))]
+    single = inputs.parity_case(40, 36, seed=11, sub=(1, 30, 1e-6))
+    for cfgs, inits in (([c[0] for c in cases], [c[1] for c in cases]), (single[0], single[1])):
+        s1 = torch.cuda.Stream()
+        s2 = torch.cuda.Stream()
+        a = binding.Sim(cfgs, inits, precision="fp32", stream=s1)
+        b = binding.Sim(cfgs, inits, precision="fp32", stream=s2)
+        b.graph(4)
+        a.step(14)
+        b.step(8)   # two replays
+        b.step(1)   # eager: parity flips
+        b.step(5)   # one eager step restores the parity, then one replay
+        for inst in range(a.n_inst):
+            for fam in "fglh":
+                assert torch.equal(a.populations(fam, inst=inst), b.populations(fam, inst=inst)), (inst, fam)
+        assert a.scalars()["k_total"] == b.scalars()["k_total"]
+
+
 def test_checkpoint_restore_and_determinism():
     print("case checkpoint", flush=True)
     p, init = inputs.parity_case(37, 29, seed=2)
