@@ -160,7 +160,9 @@ int lbm_ehd_populations(lbm_ehd_t h, int32_t inst, int32_t family, void *dev_dst
  * out[8] deformation of the outer drop (indicator 1 - phi1), out[9] of the
  * inner drop (indicator phi3), both (sqrt(I_par) - sqrt(I_perp)) /
  * (sqrt(I_par) + sqrt(I_perp)) with second moments parallel (y) and
- * perpendicular (x) to the electrode field.  Synchronises.  Returns
+ * perpendicular (x) to the electrode field; the indicator w enters as
+ * w * s(w), s = 0 below 0.005, 1 above 0.02, cubic smoothstep between (the
+ * far-field tail is dropped).  Synchronises.  Returns
  * LBM_EHD_EDIVERGED if out[7] > 0. */
 int lbm_ehd_diagnostics(lbm_ehd_t h, int32_t inst, double out[10]);
 

@@ -858,6 +858,18 @@ __global__ __launch_bounds__(NT) void k_export_pops(const Inst *__restrict__ ins
   }
 }
 
+// Indicator of a drop for the deformation moments: the order parameter with
+// its far-field tail removed (weight 0 below 0.005, full weight from 0.02,
+// cubic blend between).  Whole-box moments would weigh a 1e-5 background by
+// (y - y_c)^2 ~ 1e5 and drown the drop's own shape.
+__device__ __forceinline__ double drop_indicator(double w) {
+  const double a = 0.005, b = 0.02;
+  if (w <= a) return 0.0;
+  if (w >= b) return w;
+  const double s = (w - a) / (b - a);
+  return w * s * s * (3.0 - 2.0 * s);
+}
+
 // Diagnostics, first pass: masses, charge, max |sum phi - 1|, non-finite
 // populations and the raw second moments of the outer (1 - phi1) and inner
 // (phi3) indicators, per block.
@@ -899,7 +911,7 @@ __global__ __launch_bounds__(NT) void k_diag(const Inst *__restrict__ insts, con
     }
     v[4] = bad;
     const double xx = nd.x, yy = nd.y;
-    const double wo = 1.0 - p1, wi = p3;
+    const double wo = drop_indicator(1.0 - p1), wi = drop_indicator(p3);
     v[5] = wo; v[6] = wo * xx; v[7] = wo * yy; v[8] = wo * xx * xx; v[9] = wo * yy * yy;
     v[10] = wi; v[11] = wi * xx; v[12] = wi * yy; v[13] = wi * xx * xx; v[14] = wi * yy * yy;
   }

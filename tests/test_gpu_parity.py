@@ -273,7 +273,10 @@ def test_diagnostics_and_mass_conservation():
     np.testing.assert_allclose(d1["max_sum_dev"], np.abs(s - 1).max(), rtol=1e-6, atol=1e-12)
     ny, nx = s.shape
     y, x = np.mgrid[0:ny, 0:nx].astype(float)
-    for key, w in (("D_outer", 1 - f["phi1"]), ("D_inner", f["phi3"])):
+    def indicator(w):
+        sm = np.clip((w - 0.005) / 0.015, 0.0, 1.0)
+        return np.where(w <= 0.005, 0.0, w * sm * sm * (3 - 2 * sm))
+    for key, w in (("D_outer", indicator(1 - f["phi1"])), ("D_inner", indicator(f["phi3"]))):
         W = w.sum()
         xb, yb = (w * x).sum() / W, (w * y).sum() / W
         a = np.sqrt((w * (y - yb) ** 2).sum() / W)
