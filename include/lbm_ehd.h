@@ -45,8 +45,10 @@ enum {
 };
 
 enum { LBM_BC_PERIODIC = 0, LBM_BC_WALL = 1 }; /* x is always periodic */
-enum { LBM_PREC_FP32 = 0, LBM_PREC_FP16S = 1, LBM_PREC_FP64 = 2 };
-enum { LBM_DTYPE_F32 = 0, LBM_DTYPE_F64 = 1 };
+enum { LBM_PREC_FP32 = 0, LBM_PREC_FP16S = 1, LBM_PREC_FP64 = 2, LBM_PREC_TANGENT = 3 };
+/* LBM_DTYPE_TANGENT_F64: the derivative part of a tangent-mode handle's
+ * fields, as float64. */
+enum { LBM_DTYPE_F32 = 0, LBM_DTYPE_F64 = 1, LBM_DTYPE_TANGENT_F64 = 2 };
 
 /* Field bits for lbm_ehd_fields (the fields computed during the last step;
  * after create, the initial fields). */
@@ -94,7 +96,18 @@ enum { LBM_POP_F = 0, LBM_POP_G = 1, LBM_POP_L = 2, LBM_POP_H = 3 };
  *                half-precision values scaled by 2^14 (f, j >= 1), 2^16 (g)
  *                and 2^16 (l), rest populations f^i_0 and the potential
  *                populations in FP32; magnitudes must stay below 4, 1 and 1
- *                (overflow shows up as non-finite populations).
+ *                (overflow shows up as non-finite populations);
+ *                LBM_PREC_TANGENT: FP64 values carrying their derivative
+ *                along the parameter direction dtheta (forward-mode
+ *                differentiation of the same kernels, 16 bytes per value).
+ *  dtheta        tangent mode only: direction in the parameter space
+ *                theta = (eps2/eps1, eps3/eps1, sigma2/sigma1, sigma3/sigma1,
+ *                E0).  The first four scale eps2, eps3, sigma2, sigma3 with
+ *                eps1, sigma1 fixed.  E0 is the magnitude of the applied
+ *                field |E_ext + (0, (wall_phi[0] - wall_phi[1]) / ny)|; its
+ *                direction scales E_ext, the electrode potentials about
+ *                their mean and the initial potential guess about the same
+ *                mean, proportionally.
  */
 typedef struct {
   int32_t nx, ny, bc_y, wall_q_mode;
@@ -105,6 +118,7 @@ typedef struct {
   double gamma12, gamma13, gamma23, width;
   double rho[3], visc[3], eps[3], sigma[3];
   double tau_f, tau_l;
+  double dtheta[5];
 } lbm_ehd_params;
 
 /* Initial fields of one instance, HOST pointers to float64 arrays:
@@ -144,7 +158,8 @@ int lbm_ehd_graph(lbm_ehd_t h, int32_t steps_per_graph);
 
 /* Write the selected fields of instance `inst` into caller device memory
  * dev_dst as consecutive planes [popcount(mask)][ny][nx] in ascending bit
- * order, converted to dtype (LBM_DTYPE_F32 or LBM_DTYPE_F64).  Async. */
+ * order, converted to dtype (LBM_DTYPE_F32 or LBM_DTYPE_F64; for a tangent
+ * handle LBM_DTYPE_TANGENT_F64 gives the derivatives).  Async. */
 int lbm_ehd_fields(lbm_ehd_t h, int32_t inst, uint32_t mask, void *dev_dst, int32_t dtype);
 
 /* Pre-collision populations of the current level of instance `inst`,
@@ -180,11 +195,25 @@ int lbm_ehd_checkpoint_bytes(lbm_ehd_t h, size_t *bytes);
 int lbm_ehd_checkpoint(lbm_ehd_t h, void *dev_buf);
 int lbm_ehd_restore(lbm_ehd_t h, const void *dev_buf);
 
-/* Gradient of a final-state objective with respect to (eps2/eps1,
- * eps3/eps1, sigma2/sigma1, sigma3/sigma1, E0) by a hand-written reverse
- * step.  Not available in this build: returns LBM_EHD_EUNSUPPORTED. */
+/* Gradient of a linear functional of the final fields,
+ *   J = sum over selected fields F and nodes x of seed_F(x) * F(x),
+ * with respect to theta = (eps2/eps1, eps3/eps1, sigma2/sigma1,
+ * sigma3/sigma1, E0) (see dtheta above), for the run of n_steps steps that
+ * starts from this handle's creation state (create's cold start included).
+ * A nonlinear objective of the fields (a deformation parameter, say) passes
+ * its derivative with respect to the fields as the seed.
+ * Method: forward mode.  Each of the 5 components is one tangent run of the
+ * same kernels in FP64 (LBM_PREC_TANGENT) inside dev_work; the tangent
+ * fields are contracted with the seed by an FP64 reduction.  Cost: 5 FP64
+ * tangent runs of n_steps (no checkpoints; ckpt_every is accepted and
+ * ignored).  Single-instance handles only.
+ * dev_seed: device float64 planes [popcount(seed_mask)][ny][nx] in
+ * ascending bit order of seed_mask (LBM_F_* bits).  dev_work: caller device
+ * memory of lbm_ehd_adjoint_workspace_bytes, 256-byte aligned.
+ * Synchronises.  grad_theta receives dJ/dtheta. */
+int lbm_ehd_adjoint_workspace_bytes(lbm_ehd_t h, size_t *bytes);
 int lbm_ehd_adjoint(lbm_ehd_t h, int64_t n_steps, int32_t ckpt_every, const void *dev_seed,
-                    uint32_t seed_mask, double grad_theta[5]);
+                    uint32_t seed_mask, void *dev_work, size_t work_bytes, double grad_theta[5]);
 
 /* Kernel timing.  Between lbm_ehd_profile_begin and lbm_ehd_profile_end
  * every kernel launch of the handle is bracketed by HIP events on its stream

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm_ehd.so")
 
 FIELDS = ["phi1", "phi2", "phi3", "rho", "ux", "uy", "p", "psi", "Ex", "Ey",
           "q", "mu1", "mu2", "mu3", "eps", "R"]
-PRECISION = {"fp32": 0, "fp16s": 1, "fp64": 2}
+PRECISION = {"fp32": 0, "fp16s": 1, "fp64": 2, "tangent": 3}
 FAMILY = {"f": (0, 27), "g": (1, 9), "l": (2, 9), "h": (3, 9)}
 DIAG_KEYS = ["mass1", "mass2", "mass3", "charge", "max_sum_dev", "residual", "k_sub",
              "nonfinite", "D_outer", "D_inner"]
@@ -41,6 +41,7 @@ class Params(ctypes.Structure):
         ("rho", ctypes.c_double * 3), ("visc", ctypes.c_double * 3),
         ("eps", ctypes.c_double * 3), ("sigma", ctypes.c_double * 3),
         ("tau_f", ctypes.c_double), ("tau_l", ctypes.c_double),
+        ("dtheta", ctypes.c_double * 5),
     ]
 
 
@@ -51,7 +52,7 @@ class Init(ctypes.Structure):
     _fields_ = [("phi0", _dp), ("u0", _dp), ("q0", _dp), ("psi0", _dp)]
 
 
-EXPORTS = ["lbm_ehd_workspace_bytes", "lbm_ehd_create", "lbm_ehd_step", "lbm_ehd_fields",
+EXPORTS = ["lbm_ehd_adjoint_workspace_bytes", "lbm_ehd_workspace_bytes", "lbm_ehd_create", "lbm_ehd_step", "lbm_ehd_fields",
            "lbm_ehd_populations", "lbm_ehd_diagnostics", "lbm_ehd_scalars",
            "lbm_ehd_checkpoint_bytes", "lbm_ehd_checkpoint", "lbm_ehd_restore",
            "lbm_ehd_adjoint", "lbm_ehd_profile_begin", "lbm_ehd_profile_end", "lbm_ehd_graph",
@@ -81,7 +82,8 @@ def load():
     lib.lbm_ehd_checkpoint_bytes.argtypes = [vp, ctypes.POINTER(sz)]
     lib.lbm_ehd_checkpoint.argtypes = [vp, vp]
     lib.lbm_ehd_restore.argtypes = [vp, vp]
-    lib.lbm_ehd_adjoint.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_uint32, _dp]
+    lib.lbm_ehd_adjoint.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_uint32, vp, sz, _dp]
+    lib.lbm_ehd_adjoint_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
     lib.lbm_ehd_profile_begin.argtypes = [vp]
     lib.lbm_ehd_profile_end.argtypes = [vp, _dp, ctypes.POINTER(ctypes.c_int64)]
     lib.lbm_ehd_graph.argtypes = [vp, ctypes.c_int32]
@@ -117,6 +119,8 @@ def make_params(cfg: dict, precision: str = "fp32") -> Params:
         for i in range(3):
             getattr(p, k)[i] = float(cfg[k][i])
     p.tau_f, p.tau_l = float(cfg["tau_f"]), float(cfg["tau_l"])
+    for i, v in enumerate(cfg.get("dtheta", (0.0,) * 5)):
+        p.dtheta[i] = float(v)
     return p
 
 
@@ -191,7 +195,9 @@ class Sim:
     def step(self, n: int = 1):
         self._check(load().lbm_ehd_step(self._h, int(n)), self._h)
 
-    def fields(self, names=None, inst: int = 0, dtype=None):
+    def fields(self, names=None, inst: int = 0, dtype=None, tangent: bool = False):
+        """Fields of the last step as [ny, nx] tensors; tangent=True gives the
+        derivative parts of a tangent-mode handle (float64)."""
         import torch
         names = list(names or FIELDS)
         mask = 0
@@ -199,9 +205,9 @@ class Sim:
             mask |= 1 << FIELDS.index(k)
         order = [k for k in FIELDS if mask & (1 << FIELDS.index(k))]
         ny, nx = self.shapes[inst]
-        dtype = dtype or torch.float64
+        dtype = torch.float64 if tangent else (dtype or torch.float64)
         out = torch.empty((len(order), ny, nx), dtype=dtype, device=self.device)
-        dt = 1 if dtype == torch.float64 else 0
+        dt = 2 if tangent else (1 if dtype == torch.float64 else 0)
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
         self._check(load().lbm_ehd_fields(self._h, inst, mask, ctypes.c_void_p(out.data_ptr()), dt), self._h)
         self._handoff(out)
@@ -231,6 +237,28 @@ class Sim:
         out = (ctypes.c_double * 3)()
         self._check(load().lbm_ehd_scalars(self._h, out), self._h)
         return {"steps": int(out[0]), "k_total": int(out[1]), "n_inst": int(out[2])}
+
+    def adjoint(self, n_steps: int, seed: dict):
+        """dJ/dtheta for J = sum over the seed's fields of seed * field after
+        n_steps from this handle's creation state; theta = (eps2/eps1,
+        eps3/eps1, sigma2/sigma1, sigma3/sigma1, E0).  seed: {field name:
+        [ny, nx] tensor}.  Runs forward-mode tangent passes in the library."""
+        import torch
+        lib = load()
+        mask = 0
+        for k in seed:
+            mask |= 1 << FIELDS.index(k)
+        order = [k for k in FIELDS if mask & (1 << FIELDS.index(k))]
+        planes = torch.stack([seed[k].to(self.device, torch.float64) for k in order]).contiguous()
+        nb = ctypes.c_size_t()
+        self._check(lib.lbm_ehd_adjoint_workspace_bytes(self._h, ctypes.byref(nb)), self._h)
+        work = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.device)
+        base = (work.data_ptr() + 255) // 256 * 256
+        grad = (ctypes.c_double * 5)()
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        self._check(lib.lbm_ehd_adjoint(self._h, int(n_steps), 0, ctypes.c_void_p(planes.data_ptr()), mask,
+                                        ctypes.c_void_p(base), int(nb.value), grad), self._h)
+        return list(grad)
 
     def graph(self, steps_per_graph: int):
         """Capture a block of steps into a HIP graph replayed by step()."""

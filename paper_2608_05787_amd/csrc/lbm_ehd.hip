@@ -7,6 +7,7 @@
 
 #include <cmath>
 #include <cstdarg>
+#include <type_traits>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -34,8 +35,10 @@ struct Layout {
 constexpr int N_GROUPS = 13;
 constexpr int GROUP_PLANES[N_GROUPS] = {3, 1, 1, 1, 1, 1, 2, 3, 2, 1, 1, 6, 2};
 
-size_t elem_size(int prec) { return prec == LBM_PREC_FP64 ? 8 : 4; }
-size_t pop_size(int prec) { return prec == LBM_PREC_FP64 ? 8 : (prec == LBM_PREC_FP16S ? 2 : 4); }
+size_t elem_size(int prec) { return prec == LBM_PREC_TANGENT ? 16 : (prec == LBM_PREC_FP64 ? 8 : 4); }
+size_t pop_size(int prec) {
+  return prec == LBM_PREC_TANGENT ? 16 : prec == LBM_PREC_FP64 ? 8 : (prec == LBM_PREC_FP16S ? 2 : 4);
+}
 
 Layout layout_one(const lbm_ehd_params &p, size_t off) {
   Layout L;
@@ -121,6 +124,45 @@ template <typename T> void fill_phys(Phys<T> &P, const lbm_ehd_params &p) {
   }
 }
 
+// Applied-field magnitude E0 and the mean electrode potential about which
+// the E0 direction scales the electric boundary data (see dtheta).
+void applied_field(const lbm_ehd_params &p, double &E0, double &mean) {
+  const bool walls = p.bc_y == LBM_BC_WALL;
+  const double ey = walls ? (p.wall_phi[0] - p.wall_phi[1]) / p.ny : 0.0;
+  E0 = sqrt(p.E_ext[0] * p.E_ext[0] + (p.E_ext[1] + ey) * (p.E_ext[1] + ey));
+  mean = walls ? 0.5 * (p.wall_phi[0] + p.wall_phi[1]) : 0.0;
+}
+
+// Tangent-mode parameters: values of fill_phys<double> plus derivatives
+// along dtheta (eps2/eps1, eps3/eps1, sigma2/sigma1, sigma3/sigma1, E0).
+void fill_tangent(Phys<DualD> &T, const lbm_ehd_params &p) {
+  Phys<double> v;
+  fill_phys(v, p);
+  auto cp = [](DualD *d, const double *s, int n) {
+    for (int i = 0; i < n; ++i) d[i] = DualD(s[i], 0.0);
+  };
+  cp(T.lam, v.lam, 3);
+  T.m0 = v.m0; T.tau_f = v.tau_f; T.tau_l = v.tau_l; T.tau_h = v.tau_h; T.eps_ref = v.eps_ref; T.D = v.D;
+  cp(T.rho, v.rho, 3); cp(T.visc, v.visc, 3); cp(T.eps, v.eps, 3); cp(T.sig, v.sig, 3);
+  cp(T.Eext, v.Eext, 2); cp(T.wall_u, v.wall_u, 2); cp(T.wall_phi, v.wall_phi, 2); cp(T.wall_q, v.wall_q, 2);
+  T.eps[1].d = p.eps[0] * p.dtheta[0];
+  T.eps[2].d = p.eps[0] * p.dtheta[1];
+  T.sig[1].d = p.sigma[0] * p.dtheta[2];
+  T.sig[2].d = p.sigma[0] * p.dtheta[3];
+  double E0, mean;
+  applied_field(p, E0, mean);
+  if (E0 > 0) {
+    const double s = p.dtheta[4] / E0;
+    for (int k = 0; k < 2; ++k) {
+      T.Eext[k].d = p.E_ext[k] * s;
+      if (p.bc_y == LBM_BC_WALL) T.wall_phi[k].d = (p.wall_phi[k] - mean) * s;
+    }
+  }
+  // the reference permittivity (and tau_h) belongs to one phase: if that
+  // phase's eps moves along dtheta, so does eps_ref
+  T.eps_ref = T.eps[p.eps_ref_phase];
+}
+
 const char *validate(const lbm_ehd_params &p, const lbm_ehd_params &p0) {
   if (p.nx < 2 || p.ny < 2) return "nx and ny must be >= 2";
   if ((long long)p.nx * p.ny > (1ll << 30)) return "too many nodes in one instance";
@@ -141,8 +183,11 @@ const char *validate(const lbm_ehd_params &p, const lbm_ehd_params &p0) {
   }
   if (p.sub_min < 1 || p.sub_max < p.sub_min || p.sub_max > 4096) return "need 1 <= sub_min <= sub_max <= 4096";
   if (p.init_sub_max < 0) return "init_sub_max must be >= 0";
-  if (p.precision != LBM_PREC_FP32 && p.precision != LBM_PREC_FP64 && p.precision != LBM_PREC_FP16S)
+  if (p.precision != LBM_PREC_FP32 && p.precision != LBM_PREC_FP64 && p.precision != LBM_PREC_FP16S &&
+      p.precision != LBM_PREC_TANGENT)
     return "unknown precision";
+  if (p.precision == LBM_PREC_TANGENT && p.eps_ref_phase != 0 && (p.dtheta[0] != 0 || p.dtheta[1] != 0))
+    return "tangent mode along permittivity ratios needs eps_ref_phase 0 (tau_h must stay fixed)";
   if (p.precision != p0.precision || p.sub_min != p0.sub_min || p.sub_max != p0.sub_max ||
       p.sub_tol != p0.sub_tol || p.init_sub_max != p0.init_sub_max || p.init_tol != p0.init_tol)
     return "all instances of a handle must share precision and sub-iteration settings";
@@ -165,6 +210,8 @@ struct lbm_ehd_s {
   double sub_tol = 0;
   long long steps = 0;
   std::string err;
+  // host copies of the initial fields (tangent runs restart from them)
+  std::vector<std::vector<double>> init_phi, init_u, init_q, init_psi;
   // kernel timing (lbm_ehd_profile_begin/end)
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -239,10 +286,20 @@ int enqueue_fixed_potential(lbm_ehd_s *H, int K) {
     L = 1;
     k = 2;
   }
-  for (; k + 1 <= K; k += 2, ++L) {
-    hipEvent_t e = H->prof_start(6);
-    k_poisson2<T><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, k + 1 == K ? 1 : 0);
-    H->prof_stop(e);
+  if constexpr (sizeof(T) <= 8) {
+    for (; k + 1 <= K; k += 2, ++L) {
+      hipEvent_t e = H->prof_start(6);
+      k_poisson2<T><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, k + 1 == K ? 1 : 0);
+      H->prof_stop(e);
+    }
+  } else {
+    // tangent mode: 16-byte values leave no room for the two-iteration
+    // kernel's LDS tile; one launch per iteration
+    for (; k <= K; ++k, ++L) {
+      hipEvent_t e = H->prof_start(2);
+      k_poisson<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, k, K, 0, L & 1);
+      H->prof_stop(e);
+    }
   }
   return L;
 }
@@ -266,7 +323,22 @@ int do_create(lbm_ehd_s *H, const lbm_ehd_init *init) {
     if ((rc = up(init[i].phi0, I.phi, 3 * N))) return rc;
     if ((rc = up(init[i].u0, I.u, 2 * N))) return rc;
     if ((rc = up(init[i].q0, I.q, N))) return rc;
-    if ((rc = up(init[i].psi0, I.psi, N))) return rc;
+    if constexpr (std::is_same<T, DualD>::value) {
+      // the initial potential guess scales with the applied field about the
+      // electrodes' mean potential, like the electrode data
+      const lbm_ehd_params &p = H->params[i];
+      double E0, mean;
+      applied_field(p, E0, mean);
+      const double sc = E0 > 0 ? p.dtheta[4] / E0 : 0.0;
+      for (size_t k = 0; k < N; ++k) {
+        const double v = init[i].psi0 ? init[i].psi0[k] : 0.0;
+        buf[k] = DualD(v, (v - mean) * sc);
+      }
+      HIPC(H, hipMemcpyAsync(I.psi, buf.data(), N * te, hipMemcpyHostToDevice, H->stream));
+      HIPC(H, hipStreamSynchronize(H->stream));
+    } else {
+      if ((rc = up(init[i].psi0, I.psi, N))) return rc;
+    }
   }
   k_init_potential<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i);
   HIPC(H, hipGetLastError());
@@ -365,6 +437,15 @@ int convert(lbm_ehd_s *H, const void *src, void *dst, size_t count, int dtype) {
 }
 
 int convert_any(lbm_ehd_s *H, int elem, const void *src, void *dst, size_t count, int dtype) {
+  if (dtype == LBM_DTYPE_TANGENT_F64) {
+    if (elem != 16) return H->fail(LBM_EHD_EINVAL, "tangent fields exist only in tangent mode");
+    if (count == 0) return LBM_EHD_OK;
+    k_tangent<double><<<dim3((unsigned)((count + NT - 1) / NT)), dim3(NT), 0, H->stream>>>((const DualD *)src,
+                                                                                      (double *)dst, count);
+    HIPC(H, hipGetLastError());
+    return LBM_EHD_OK;
+  }
+  if (elem == 16) return convert<DualD>(H, src, dst, count, dtype);
   if (elem == 8) return convert<double>(H, src, dst, count, dtype);
   if (elem == 4) return convert<float>(H, src, dst, count, dtype);
   return convert<__half>(H, src, dst, count, dtype);
@@ -431,8 +512,7 @@ int lbm_ehd_create(const lbm_ehd_params *params, int32_t n_inst, const lbm_ehd_i
   for (int i = 0; i < n_inst; ++i) {
     const lbm_ehd_params &p = params[i];
     const Layout &L = H->plan.lay[i];
-    Inst I;
-    memset(&I, 0, sizeof I);
+    Inst I{};
     I.nx = p.nx;
     I.ny = p.ny;
     I.N = p.nx * p.ny;
@@ -460,6 +540,7 @@ int lbm_ehd_create(const lbm_ehd_params *params, int32_t n_inst, const lbm_ehd_i
     I.ctl = (Ctl *)(H->ws + L.ctl);
     fill_phys(I.pf, p);
     fill_phys(I.pd, p);
+    fill_tangent(I.pt, p);
     H->hinst.push_back(I);
     for (int b = 0; b < L.nblk; ++b) logical.push_back(make_int2(i, b));
   }
@@ -497,8 +578,20 @@ int lbm_ehd_create(const lbm_ehd_params *params, int32_t n_inst, const lbm_ehd_i
     H->err = std::string("workspace setup: ") + hipGetErrorString(e);
     return bad(LBM_EHD_EHIP);
   }
+  for (int i = 0; i < n_inst; ++i) {
+    const size_t N = (size_t)params[i].nx * params[i].ny;
+    auto keep = [&](std::vector<std::vector<double>> &dst, const double *src, size_t cnt) {
+      dst.emplace_back(src ? std::vector<double>(src, src + cnt) : std::vector<double>());
+    };
+    keep(H->init_phi, init[i].phi0, 3 * N);
+    keep(H->init_u, init[i].u0, 2 * N);
+    keep(H->init_q, init[i].q0, N);
+    keep(H->init_psi, init[i].psi0, N);
+  }
   if (H->prec == LBM_PREC_FP64)
     rc = do_create<double, double>(H, init);
+  else if (H->prec == LBM_PREC_TANGENT)
+    rc = do_create<DualD, DualD>(H, init);
   else if (H->prec == LBM_PREC_FP16S)
     rc = do_create<float, __half>(H, init);
   else
@@ -510,6 +603,7 @@ int lbm_ehd_create(const lbm_ehd_params *params, int32_t n_inst, const lbm_ehd_i
 
 static int step_eager(lbm_ehd_t H, int64_t n) {
   if (H->prec == LBM_PREC_FP64) return do_step<double, double>(H, n);
+  if (H->prec == LBM_PREC_TANGENT) return do_step<DualD, DualD>(H, n);
   if (H->prec == LBM_PREC_FP16S) return do_step<float, __half>(H, n);
   return do_step<float, float>(H, n);
 }
@@ -587,9 +681,10 @@ static int field_sub(int bit) {
 int lbm_ehd_fields(lbm_ehd_t H, int32_t inst, uint32_t mask, void *dev_dst, int32_t dtype) {
   if (!H || inst < 0 || inst >= H->n_inst || !dev_dst || (mask >> 16) != 0)
     return H ? H->fail(LBM_EHD_EINVAL, "fields: bad argument") : LBM_EHD_EINVAL;
-  if (dtype != LBM_DTYPE_F32 && dtype != LBM_DTYPE_F64) return H->fail(LBM_EHD_EINVAL, "fields: bad dtype");
+  if (dtype != LBM_DTYPE_F32 && dtype != LBM_DTYPE_F64 && dtype != LBM_DTYPE_TANGENT_F64)
+    return H->fail(LBM_EHD_EINVAL, "fields: bad dtype");
   const Inst &I = H->hinst[inst];
-  const size_t N = (size_t)I.N, te = elem_size(H->prec), de = dtype == LBM_DTYPE_F64 ? 8 : 4;
+  const size_t N = (size_t)I.N, te = elem_size(H->prec), de = dtype == LBM_DTYPE_F32 ? 4 : 8;
   char *dst = (char *)dev_dst;
   for (int bit = 0; bit < 16; ++bit) {
     if (!(mask & (1u << bit))) continue;
@@ -617,6 +712,8 @@ int lbm_ehd_populations(lbm_ehd_t H, int32_t inst, int32_t family, void *dev_dst
   } while (0)
   if (H->prec == LBM_PREC_FP64)
     EXPORT(double, double);
+  else if (H->prec == LBM_PREC_TANGENT)
+    EXPORT(DualD, DualD);
   else if (H->prec == LBM_PREC_FP16S)
     EXPORT(float, __half);
   else
@@ -628,9 +725,10 @@ int lbm_ehd_populations(lbm_ehd_t H, int32_t inst, int32_t family, void *dev_dst
 
 int lbm_ehd_diagnostics(lbm_ehd_t H, int32_t inst, double out[10]) {
   if (!H || inst < 0 || inst >= H->n_inst || !out) return LBM_EHD_EINVAL;
-  int rc = H->prec == LBM_PREC_FP64   ? do_diag<double, double>(H)
-           : H->prec == LBM_PREC_FP16S ? do_diag<float, __half>(H)
-                                       : do_diag<float, float>(H);
+  int rc = H->prec == LBM_PREC_FP64      ? do_diag<double, double>(H)
+           : H->prec == LBM_PREC_TANGENT ? do_diag<DualD, DualD>(H)
+           : H->prec == LBM_PREC_FP16S   ? do_diag<float, __half>(H)
+                                         : do_diag<float, float>(H);
   if (rc) return rc;
   Ctl c;
   HIPC(H, hipStreamSynchronize(H->stream));
@@ -681,10 +779,64 @@ int lbm_ehd_restore(lbm_ehd_t H, const void *dev_buf) {
   return LBM_EHD_OK;
 }
 
-int lbm_ehd_adjoint(lbm_ehd_t H, int64_t, int32_t, const void *, uint32_t, double grad_theta[5]) {
-  (void)grad_theta;
-  if (!H) return LBM_EHD_EINVAL;
-  return H->fail(LBM_EHD_EUNSUPPORTED, "adjoint is not available in this build");
+static lbm_ehd_params tangent_params(const lbm_ehd_params &p, int dir) {
+  lbm_ehd_params t = p;
+  t.precision = LBM_PREC_TANGENT;
+  for (int k = 0; k < 5; ++k) t.dtheta[k] = (k == dir) ? 1.0 : 0.0;
+  return t;
+}
+
+int lbm_ehd_adjoint_workspace_bytes(lbm_ehd_t H, size_t *bytes) {
+  if (!H || !bytes) return LBM_EHD_EINVAL;
+  if (H->n_inst != 1) return H->fail(LBM_EHD_EUNSUPPORTED, "gradients need a single-instance handle");
+  const lbm_ehd_params t = tangent_params(H->params[0], 0);
+  *bytes = make_plan(&t, 1).total;
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_adjoint(lbm_ehd_t H, int64_t n_steps, int32_t, const void *dev_seed, uint32_t seed_mask,
+                    void *dev_work, size_t work_bytes, double grad_theta[5]) {
+  if (!H || !grad_theta || !dev_seed || n_steps < 0) return LBM_EHD_EINVAL;
+  if (H->n_inst != 1) return H->fail(LBM_EHD_EUNSUPPORTED, "gradients need a single-instance handle");
+  if (seed_mask == 0 || (seed_mask >> 16) != 0) return H->fail(LBM_EHD_EINVAL, "adjoint: bad seed mask");
+  size_t need = 0;
+  lbm_ehd_adjoint_workspace_bytes(H, &need);
+  if (!dev_work || work_bytes < need || ((uintptr_t)dev_work % ALIGN) != 0)
+    return H->fail(LBM_EHD_ENOMEM, "adjoint: work buffer must be >= %zu bytes and 256-byte aligned", need);
+  lbm_ehd_init ini;
+  ini.phi0 = H->init_phi[0].data();
+  ini.u0 = H->init_u[0].empty() ? nullptr : H->init_u[0].data();
+  ini.q0 = H->init_q[0].empty() ? nullptr : H->init_q[0].data();
+  ini.psi0 = H->init_psi[0].empty() ? nullptr : H->init_psi[0].data();
+  for (int dir = 0; dir < 5; ++dir) {
+    const lbm_ehd_params t = tangent_params(H->params[0], dir);
+    lbm_ehd_t T = nullptr;
+    int rc = lbm_ehd_create(&t, 1, &ini, dev_work, (void *)H->stream, &T);
+    if (rc) return H->fail(rc, "adjoint: tangent run: %s", g_create_error.c_str());
+    rc = lbm_ehd_step(T, n_steps);
+    if (rc) {
+      H->err = T->err;
+      lbm_ehd_destroy(T);
+      return rc;
+    }
+    // contract the tangent fields of the last step with the seed
+    const Inst &I = T->hinst[0];
+    SeedPlanes sp;
+    sp.count = 0;
+    for (int bit = 0; bit < 16; ++bit)
+      if (seed_mask & (1u << bit))
+        sp.plane[sp.count++] = (const DualD *)field_src(I, bit) + (size_t)field_sub(bit) * I.N;
+    k_seed_dot<<<dim3(I.nblk), dim3(NT), 0, T->stream>>>(T->d_insts, sp, (const double *)dev_seed);
+    k_reduce_seed_dot<<<1, NT, 0, T->stream>>>(T->d_insts);
+    Ctl c;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(T->stream);
+    if (e == hipSuccess) e = hipMemcpy(&c, I.ctl, sizeof c, hipMemcpyDeviceToHost);
+    lbm_ehd_destroy(T);
+    if (e != hipSuccess) return H->fail(LBM_EHD_EHIP, "adjoint: %s", hipGetErrorString(e));
+    grad_theta[dir] = c.diag[10];
+  }
+  return LBM_EHD_OK;
 }
 
 int lbm_ehd_profile_begin(lbm_ehd_t H) {

@@ -14,6 +14,30 @@
 
 namespace lbm {
 
+// Forward-mode (tangent) arithmetic: a value and its derivative along one
+// parameter direction.  Instantiating the kernels with Dual<double> runs the
+// exact tangent-linear step next to the FP64 step.
+template <typename R> struct Dual {
+  R v, d;
+  __host__ __device__ constexpr Dual() : v(0), d(0) {}
+  __host__ __device__ constexpr Dual(R a) : v(a), d(0) {}
+  __host__ __device__ constexpr Dual(int a) : v(R(a)), d(0) {}
+  __host__ __device__ constexpr Dual(R a, R b) : v(a), d(b) {}
+  __host__ __device__ constexpr explicit operator double() const { return (double)v; }
+  __host__ __device__ constexpr explicit operator float() const { return (float)v; }
+  friend __host__ __device__ constexpr Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+  friend __host__ __device__ constexpr Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+  friend __host__ __device__ constexpr Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+  friend __host__ __device__ constexpr Dual operator/(Dual a, Dual b) {
+    return Dual(a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v));
+  }
+  __host__ __device__ constexpr Dual operator-() const { return Dual(-v, -d); }
+  __host__ __device__ Dual &operator+=(Dual b) { v += b.v; d += b.d; return *this; }
+  __host__ __device__ Dual &operator-=(Dual b) { v -= b.v; d -= b.d; return *this; }
+  __host__ __device__ Dual &operator*=(Dual b) { *this = *this * b; return *this; }
+};
+using DualD = Dual<double>;
+
 constexpr int NT = 256;  // threads per block (4 waves of 64)
 constexpr int Q = 9;
 
@@ -62,11 +86,13 @@ struct Inst {
   Ctl *ctl;
   Phys<float> pf;
   Phys<double> pd;
+  Phys<DualD> pt;  // tangent mode: parameters with their derivatives along one direction
 };
 
 template <typename T> __device__ __forceinline__ const Phys<T> &phys(const Inst &I);
 template <> __device__ __forceinline__ const Phys<float> &phys<float>(const Inst &I) { return I.pf; }
 template <> __device__ __forceinline__ const Phys<double> &phys<double>(const Inst &I) { return I.pd; }
+template <> __device__ __forceinline__ const Phys<DualD> &phys<DualD>(const Inst &I) { return I.pt; }
 
 // ------------------------------------------------------------ helpers
 
@@ -870,6 +896,38 @@ __device__ __forceinline__ double drop_indicator(double w) {
   return w * s * s * (3.0 - 2.0 * s);
 }
 
+// Tangent parts of `count` dual values.
+template <typename Tout>
+__global__ __launch_bounds__(NT) void k_tangent(const DualD *__restrict__ src, Tout *__restrict__ dst, size_t count) {
+  const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
+  if (i < count) dst[i] = (Tout)src[i].d;
+}
+
+// Seeded directional derivative, first pass: per block, sum over the
+// selected planes of seed * tangent (planes: pointers to [N] dual planes).
+struct SeedPlanes {
+  const DualD *plane[16];
+  int count;
+};
+__global__ __launch_bounds__(NT) void k_seed_dot(const Inst *__restrict__ insts, SeedPlanes sp,
+                                                 const double *__restrict__ seed) {
+  const Inst &I = insts[0];
+  const int n = blockIdx.x * NT + threadIdx.x;
+  double v[1] = {0.0};
+  if (n < I.N)
+    for (int k = 0; k < sp.count; ++k) v[0] += seed[(size_t)k * I.N + n] * sp.plane[k][n].d;
+  block_sum<1>(v);
+  if (threadIdx.x == 0) I.part_p[(size_t)blockIdx.x * 2] = v[0];
+}
+__global__ __launch_bounds__(NT) void k_reduce_seed_dot(const Inst *__restrict__ insts) {
+  const Inst &I = insts[0];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < I.nblk; b += NT) s += I.part_p[(size_t)b * 2];
+  double v[1] = {s};
+  block_sum<1>(v);
+  if (threadIdx.x == 0) I.ctl->diag[10] = v[0];
+}
+
 // Diagnostics, first pass: masses, charge, max |sum phi - 1|, non-finite
 // populations and the raw second moments of the outer (1 - phi1) and inner
 // (phi3) indicators, per block.
@@ -886,11 +944,11 @@ __global__ __launch_bounds__(NT) void k_diag(const Inst *__restrict__ insts, con
   if (nd.valid) {
     const int N = I.N, n = nd.n;
     const T *phi = (const T *)I.phi;
-    const double p1 = phi[n], p2 = phi[(size_t)N + n], p3 = phi[(size_t)2 * N + n];
+    const double p1 = (double)phi[n], p2 = (double)phi[(size_t)N + n], p3 = (double)phi[(size_t)2 * N + n];
     v[0] = p1;
     v[1] = p2;
     v[2] = p3;
-    v[3] = ((const T *)I.q)[n];
+    v[3] = (double)((const T *)I.q)[n];
     mx = fabs(p1 + p2 + p3 - 1.0);
     using IO = PopIO<S, T>;
     int bad = 0;

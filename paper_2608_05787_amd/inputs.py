@@ -25,7 +25,7 @@ import numpy as np
 __all__ = [
     "base_params", "tanh_drop", "compound_drop", "doublet", "flat_layers",
     "eof_channel", "static_doublet", "field_compound_drop", "batch_sweep",
-    "adjoint_case", "parity_case",
+    "adjoint_case", "parity_case", "applied_field", "theta_of", "with_theta",
 ]
 
 
@@ -210,3 +210,45 @@ def parity_case(nx, ny, seed=0, walls=True, field=True, shear=True, sub=(2, 2, 0
         p.update(E_ext=(2e-3, -1e-3))
     psi0 = 0.4 * (y + 0.5) / ny if (walls and field) else np.zeros((ny, nx))
     return p, {"phi0": phi0, "u0": u0, "q0": q0, "psi0": psi0}
+
+
+# ---------------------------------------------- gradient parameterisation
+# theta = (eps2/eps1, eps3/eps1, sigma2/sigma1, sigma3/sigma1, E0).  Phases
+# 2 and 3 scale against phase 1; E0 is the applied field magnitude, and
+# changing it scales E_ext, the electrode potentials and the initial
+# potential guess about the electrodes' mean potential.
+
+def applied_field(cfg: dict):
+    """(E0, mean electrode potential) with the conventions of dtheta."""
+    walls = int(cfg.get("bc_y", 0)) == 1
+    wp = cfg.get("wall_phi", (0.0, 0.0))
+    ex, ey = cfg.get("E_ext", (0.0, 0.0))
+    ey = ey + ((wp[0] - wp[1]) / cfg["ny"] if walls else 0.0)
+    mean = 0.5 * (wp[0] + wp[1]) if walls else 0.0
+    return math.hypot(ex, ey), mean
+
+
+def theta_of(cfg: dict):
+    e, s = cfg["eps"], cfg["sigma"]
+    return [e[1] / e[0], e[2] / e[0], s[1] / s[0], s[2] / s[0], applied_field(cfg)[0]]
+
+
+def with_theta(cfg: dict, init: dict, theta):
+    """Copy of (cfg, init) with the five parameters set to theta."""
+    t = [float(v) for v in theta]
+    c = dict(cfg)
+    e, s = list(cfg["eps"]), list(cfg["sigma"])
+    c["eps"] = (e[0], e[0] * t[0], e[0] * t[1])
+    c["sigma"] = (s[0], s[0] * t[2], s[0] * t[3])
+    E0, mean = applied_field(cfg)
+    new = dict(init)
+    if E0 > 0:
+        r = t[4] / E0
+        c["E_ext"] = tuple(v * r for v in cfg.get("E_ext", (0.0, 0.0)))
+        if int(cfg.get("bc_y", 0)) == 1:
+            c["wall_phi"] = tuple(mean + (v - mean) * r for v in cfg["wall_phi"])
+        if init.get("psi0") is not None:
+            new["psi0"] = mean + (np.asarray(init["psi0"]) - mean) * r
+    return c, new
+
+

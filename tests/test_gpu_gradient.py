@@ -1,0 +1,107 @@
+"""Gradients with respect to theta = (eps2/eps1, eps3/eps1, sigma2/sigma1,
+sigma3/sigma1, E0) from lbm_ehd_adjoint (forward-mode tangent runs of the
+same kernels in FP64), checked against central finite differences of the FP64
+GPU run and of the FP64 CPU oracle (relative step 1e-3), and through the
+torch.autograd.Function on a deformation objective."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+from oracle import Oracle  # noqa: E402
+from paper_2608_05787_amd import autograd, binding, inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 60
+REL = 1e-3
+
+
+def small_case():
+    return inputs.field_compound_drop(48, r_shell=12.0, r_core=7.0, ca_e=0.4, init_iters=100,
+                                      init_tol=0.0, sub=(2, 2, 0.0))
+
+
+def seeds(shape, names, seed=0):
+    rng = np.random.default_rng(seed)
+    return {k: rng.standard_normal(shape) for k in names}
+
+
+def J_gpu(cfg, init, seed):
+    sim = binding.Sim(cfg, init, precision="fp64")
+    sim.step(STEPS)
+    f = sim.fields(list(seed))
+    return sum(float((f[k].cpu().numpy() * s).sum()) for k, s in seed.items())
+
+
+def J_oracle(cfg, init, seed):
+    o = Oracle(cfg, init)
+    o.step(STEPS)
+    return sum(float((o.field(k) * s).sum()) for k, s in seed.items())
+
+
+def fd(Jfn, cfg, init, seed):
+    th = inputs.theta_of(cfg)
+    out = []
+    for k in range(5):
+        h = REL * th[k]
+        tp, tm = list(th), list(th)
+        tp[k] += h
+        tm[k] -= h
+        Jp = Jfn(*inputs.with_theta(cfg, init, tp), seed)
+        Jm = Jfn(*inputs.with_theta(cfg, init, tm), seed)
+        out.append((Jp - Jm) / (2 * h))
+    return np.array(out)
+
+
+def check(g, ref, rel=1e-4):
+    g, ref = np.asarray(g), np.asarray(ref)
+    tol = rel * np.abs(ref) + 1e-7 * np.abs(ref).max()
+    assert np.all(np.abs(g - ref) <= tol), (g, ref, np.abs(g - ref) / np.abs(ref))
+
+
+def tangent_grad(cfg, init, seed):
+    sim = binding.Sim(cfg, init, precision="fp64")
+    return sim.adjoint(STEPS, {k: torch.from_numpy(v) for k, v in seed.items()})
+
+
+def test_tangent_gradient_matches_fd_of_gpu_fp64():
+    print("case gradient vs gpu fd", flush=True)
+    cfg, init = small_case()
+    seed = seeds((cfg["ny"], cfg["nx"]), ["phi1", "phi3", "psi", "ux", "q"])
+    g = tangent_grad(cfg, init, seed)
+    assert all(abs(v) > 0 for v in g)
+    check(g, fd(J_gpu, cfg, init, seed))
+
+
+def test_tangent_gradient_matches_fd_of_oracle():
+    """The FP64 oracle's finite-difference gradient (the reference gradient
+    the method defines) against the tangent gradient of the GPU kernels."""
+    print("case gradient vs oracle fd", flush=True)
+    cfg, init = small_case()
+    seed = seeds((cfg["ny"], cfg["nx"]), ["phi2", "Ey", "uy"], seed=1)
+    check(tangent_grad(cfg, init, seed), fd(J_oracle, cfg, init, seed))
+
+
+def test_autograd_deformation_gradient():
+    """dD/dtheta of the outer drop's deformation through the autograd
+    Function (forward in FP64 here) against finite differences of D."""
+    print("case autograd deformation", flush=True)
+    cfg, init = small_case()
+
+    def D_of(theta):
+        phi = autograd.LbmEhdFn.apply(theta, cfg, init, STEPS, "fp64")
+        return autograd.deformation(autograd.drop_indicator(1.0 - phi[0]))
+
+    th0 = torch.tensor(inputs.theta_of(cfg), dtype=torch.float64, device="cuda", requires_grad=True)
+    D = D_of(th0)
+    D.backward()
+    g = th0.grad.cpu().numpy()
+    ref = []
+    with torch.no_grad():
+        for k in range(5):
+            h = REL * float(th0[k])
+            tp, tm = th0.detach().clone(), th0.detach().clone()
+            tp[k] += h
+            tm[k] -= h
+            ref.append((float(D_of(tp)) - float(D_of(tm))) / (2 * h))
+    check(g, ref, rel=2e-4)
