@@ -210,6 +210,52 @@ def batch_bench(n_inst, steps, sub, init_iters, graph_len=10):
             "mlups_sequential": mlups(ms_seq), "speedup_graph_vs_sequential": round(ms_seq / ms_graph, 2)}
 
 
+def gradient_bench(n, steps, sub, init_iters):
+    """Gradient of the outer deformation after `steps` steps with respect to
+    the five parameters (lbm_ehd_adjoint: five FP64 tangent runs) against the
+    FP32 forward run of the same length, both from create (cold start
+    included), on the adjoint workload (n x n, radii 40/30)."""
+    import torch
+    from paper_2608_05787_amd import autograd, binding, inputs
+    p, init = inputs.field_compound_drop(n, r_shell=40.0, r_core=30.0, sub=(sub, sub, 0.0),
+                                         init_iters=init_iters, init_tol=0.0)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    fwd = binding.Sim(p, init, precision="fp32")
+    fwd.step(steps)
+    phi = fwd.fields(["phi1"])["phi1"]
+    torch.cuda.synchronize()
+    t_fwd = time.time() - t0
+    w = (1.0 - phi).clone().requires_grad_(True)
+    D = autograd.deformation(autograd.drop_indicator(w))
+    D.backward()
+    seed = {"phi1": -w.grad.detach()}
+    ref = binding.Sim(p, init, precision="fp64")
+    torch.cuda.synchronize()
+    t0 = time.time()
+    g = ref.adjoint(steps, seed)
+    torch.cuda.synchronize()
+    t_grad = time.time() - t0
+    # per-step cost of one tangent run
+    tan = binding.Sim(dict(p, dtheta=(1.0, 0.0, 0.0, 0.0, 0.0)), init, precision="tangent")
+    torch.cuda.synchronize()
+    t0 = time.time()
+    tan.step(steps)
+    torch.cuda.synchronize()
+    t_tan = (time.time() - t0) / steps
+    t0 = time.time()
+    fwd.step(steps)
+    torch.cuda.synchronize()
+    t_step = (time.time() - t0) / steps
+    return {"workload": "field compound drop %dx%d, radii 40/30, %d steps, %d potential sub-iterations"
+                        % (n, n, steps, sub),
+            "method": "forward mode: 5 FP64 tangent runs", "D_outer": float(D), "dD_dtheta": g,
+            "forward_s": round(t_fwd, 4), "gradient_s": round(t_grad, 4),
+            "gradient_over_forward": round(t_grad / t_fwd, 2),
+            "per_step_tangent_over_fp32": round(t_tan / t_step, 2),
+            "per_step_gradient_over_fp32": round(5 * t_tan / t_step, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,6 +271,7 @@ def main():
     ap.add_argument("--init-iters", type=int, default=4000, help="cold-start potential iterations")
     ap.add_argument("--batch-instances", type=int, default=64, help="0 skips the parameter-sweep leg")
     ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--grad-steps", type=int, default=250, help="0 skips the gradient leg")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -298,6 +345,11 @@ def main():
         log("batched parameter sweep")
         batch = batch_bench(args.batch_instances, args.batch_steps, args.sub, 1000)
 
+    grad = None
+    if args.grad_steps > 0 and not args.no_variants:
+        log("gradient (adjoint workload)")
+        grad = gradient_bench(512, args.grad_steps, args.sub, 2000)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -317,6 +369,7 @@ def main():
         "variants": variants,
         "rel_l2_vs_fp64": errors,
         "batch_sweep": batch,
+        "gradient": grad,
         "diagnostics": {k: diag[k] for k in ("max_sum_dev", "residual", "D_outer", "D_inner", "nonfinite")},
         "cpu_baseline": cpu,
     }
