@@ -25,7 +25,7 @@ import numpy as np
 __all__ = [
     "base_params", "tanh_drop", "compound_drop", "doublet", "flat_layers",
     "eof_channel", "static_doublet", "field_compound_drop", "batch_sweep",
-    "adjoint_case", "parity_case", "applied_field", "theta_of", "with_theta",
+    "adjoint_case", "parity_case", "applied_field", "theta_of", "with_theta", "liquid_lens",
 ]
 
 
@@ -173,6 +173,26 @@ def batch_sweep(n_inst=64, seed=5787, lo=128, hi=512, sub=(4, 4, 0.0), init_iter
                                       wall_u=0.01 if i in sheared else 0.0)
         out.append((p, init))
     return out
+
+
+def liquid_lens(n=200, radius=30.0, ratio=(1.0, 1.0, 1.0), gamma=2e-3, rho=(10.0, 1.0, 5.0), width=4.0,
+                tau=0.8):
+    """Liquid lens (Eq. 56): a drop of phase 1 centred on the flat interface
+    between phase 2 (above) and phase 3 (below); walls at top and bottom,
+    periodic in x.  Surface tensions gamma * ratio (gamma12 : gamma13 :
+    gamma23); densities rho; dynamic viscosities 0.1 rho_i so that the flow
+    relaxation time is tau = 0.8 in every phase.  No field."""
+    xc = yc = 0.5 * (n - 1)
+    phi1 = tanh_drop(n, n, xc, yc, radius, width)
+    _, y = _grid(n, n)
+    phi2 = np.maximum(0.5 + 0.5 * np.tanh(2.0 * (y - yc) / width) - phi1, 0.0)
+    phi0 = np.stack([phi1, phi2, 1.0 - phi1 - phi2])
+    g12, g13, g23 = (gamma * r for r in ratio)
+    cs2 = 1.0 / 3.0
+    visc = tuple(cs2 * (tau - 0.5) * r for r in rho)
+    p = base_params(n, n, bc_y=1, gamma12=g12, gamma13=g13, gamma23=g23, width=width,
+                    rho=tuple(rho), visc=visc, sigma=(0.0, 0.0, 0.0), tau_f=tau)
+    return p, {"phi0": phi0}
 
 
 def adjoint_case(n=512):
