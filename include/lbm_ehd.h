@@ -195,25 +195,49 @@ int lbm_ehd_checkpoint_bytes(lbm_ehd_t h, size_t *bytes);
 int lbm_ehd_checkpoint(lbm_ehd_t h, void *dev_buf);
 int lbm_ehd_restore(lbm_ehd_t h, const void *dev_buf);
 
-/* Gradient of a linear functional of the final fields,
+/* Gradients of a linear functional of the final fields,
  *   J = sum over selected fields F and nodes x of seed_F(x) * F(x),
  * with respect to theta = (eps2/eps1, eps3/eps1, sigma2/sigma1,
  * sigma3/sigma1, E0) (see dtheta above), for the run of n_steps steps that
  * starts from this handle's creation state (create's cold start included).
  * A nonlinear objective of the fields (a deformation parameter, say) passes
- * its derivative with respect to the fields as the seed.
- * Method: forward mode.  Each of the 5 components is one tangent run of the
- * same kernels in FP64 (LBM_PREC_TANGENT) inside dev_work; the tangent
- * fields are contracted with the seed by an FP64 reduction.  Cost: 5 FP64
- * tangent runs of n_steps (no checkpoints; ckpt_every is accepted and
- * ignored).  Single-instance handles only.
- * dev_seed: device float64 planes [popcount(seed_mask)][ny][nx] in
- * ascending bit order of seed_mask (LBM_F_* bits).  dev_work: caller device
- * memory of lbm_ehd_adjoint_workspace_bytes, 256-byte aligned.
- * Synchronises.  grad_theta receives dJ/dtheta. */
-int lbm_ehd_adjoint_workspace_bytes(lbm_ehd_t h, size_t *bytes);
+ * its derivative with respect to the fields as the seed.  Fields are the
+ * planes lbm_ehd_fields returns after the run.  dev_seed: device float64
+ * planes [popcount(seed_mask)][ny][nx] in ascending bit order of seed_mask
+ * (LBM_F_* bits).  grad_theta receives dJ/dtheta.  All calls synchronise;
+ * single-instance handles only.
+ *
+ * Reverse mode (the discrete adjoint of the step and of create):
+ * lbm_ehd_record steps the handle n_steps from its creation state exactly
+ * like lbm_ehd_step (bitwise the same states) and saves a checkpoint of the
+ * state every ckpt_every steps into dev_work.  lbm_ehd_adjoint then runs
+ * the adjoint sweep: segments of ckpt_every steps, last first, are
+ * recomputed from their checkpoint in a private handle inside dev_work,
+ * storing each step's forward values, and the step adjoints run backwards
+ * through them; finally the adjoint of create (equilibrium populations,
+ * field, the cold-start potential iterations recomputed in chunks, the
+ * initial potential guess).  If dev_work does not hold a recording of this
+ * handle for the same n_steps and ckpt_every, lbm_ehd_adjoint first makes
+ * one inside it from the handle's initial fields (the handle itself is not
+ * touched).  Needs: FP32 or FP64 precision, fixed sub-iteration counts
+ * (step and cold start), eps_ref_phase 0, seeds on LBM_F_PHI1..3 only.
+ * Arithmetic in the handle's precision, parameter sums in FP64.
+ * Returns LBM_EHD_EUNSUPPORTED otherwise.  dev_work: caller device memory
+ * of lbm_ehd_adjoint_workspace_bytes(n_steps, ckpt_every), 256-byte
+ * aligned: a workspace, one checkpoint per segment, ckpt_every step
+ * records of (22 + 9 K) planes and 178 adjoint planes.
+ *
+ * Forward mode: lbm_ehd_tangent_gradient runs one tangent run of the same
+ * kernels in FP64 (LBM_PREC_TANGENT) per component of theta inside dev_work
+ * (lbm_ehd_tangent_workspace_bytes) and contracts the tangent fields with
+ * the seed; any fields may be seeded.  Cost: 5 FP64 tangent runs. */
+int lbm_ehd_adjoint_workspace_bytes(lbm_ehd_t h, int64_t n_steps, int32_t ckpt_every, size_t *bytes);
+int lbm_ehd_record(lbm_ehd_t h, int64_t n_steps, int32_t ckpt_every, void *dev_work, size_t work_bytes);
 int lbm_ehd_adjoint(lbm_ehd_t h, int64_t n_steps, int32_t ckpt_every, const void *dev_seed,
                     uint32_t seed_mask, void *dev_work, size_t work_bytes, double grad_theta[5]);
+int lbm_ehd_tangent_workspace_bytes(lbm_ehd_t h, size_t *bytes);
+int lbm_ehd_tangent_gradient(lbm_ehd_t h, int64_t n_steps, const void *dev_seed, uint32_t seed_mask,
+                             void *dev_work, size_t work_bytes, double grad_theta[5]);
 
 /* Kernel timing.  Between lbm_ehd_profile_begin and lbm_ehd_profile_end
  * every kernel launch of the handle is bracketed by HIP events on its stream

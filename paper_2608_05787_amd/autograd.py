@@ -4,9 +4,11 @@ theta = (eps2/eps1, eps3/eps1, sigma2/sigma1, sigma3/sigma1, E0): the
 forward builds the instance's parameters from theta (phases 2 and 3 scaled
 against phase 1; the applied field scaled about the electrodes' mean
 potential, initial potential guess included), runs the steps in the chosen
-precision and returns the order parameters of the last step.  The backward
-passes the incoming gradient as the seed of lbm_ehd_adjoint, which returns
-dJ/dtheta from tangent runs of the same kernels in FP64.
+precision (FP32 or FP64) while checkpointing every ckpt_every steps
+(lbm_ehd_record), and returns the order parameters of the last step.  The
+backward passes the incoming gradient as the seed of lbm_ehd_adjoint, whose
+reverse sweep recomputes the segments from those checkpoints and returns
+dJ/dtheta in the forward's precision.
 """
 from __future__ import annotations
 
@@ -17,24 +19,24 @@ from .inputs import applied_field, theta_of, with_theta  # noqa: F401  (re-expor
 
 
 class LbmEhdFn(torch.autograd.Function):
-    """phi = LbmEhdFn.apply(theta, cfg, init, n_steps, precision):
+    """phi = LbmEhdFn.apply(theta, cfg, init, n_steps, precision, ckpt_every):
     order parameters [3, ny, nx] after n_steps."""
 
     @staticmethod
-    def forward(ctx, theta, cfg, init, n_steps, precision="fp32"):
+    def forward(ctx, theta, cfg, init, n_steps, precision="fp32", ckpt_every=250):
         c, ini = with_theta(cfg, init, theta.detach().cpu().tolist())
         sim = binding.Sim(c, ini, precision=precision)
-        sim.step(int(n_steps))
+        sim.record(int(n_steps), int(ckpt_every))
         f = sim.fields(["phi1", "phi2", "phi3"])
-        ctx.cfg, ctx.init, ctx.n = c, ini, int(n_steps)
+        ctx.sim, ctx.n, ctx.every = sim, int(n_steps), int(ckpt_every)
         ctx.dtype, ctx.device = theta.dtype, theta.device
         return torch.stack([f["phi1"], f["phi2"], f["phi3"]])
 
     @staticmethod
     def backward(ctx, grad_phi):
-        sim = binding.Sim(ctx.cfg, ctx.init, precision="fp64")
-        g = sim.adjoint(ctx.n, {"phi1": grad_phi[0], "phi2": grad_phi[1], "phi3": grad_phi[2]})
-        return torch.tensor(g, dtype=ctx.dtype, device=ctx.device), None, None, None, None
+        g = ctx.sim.adjoint(ctx.n, {"phi1": grad_phi[0], "phi2": grad_phi[1], "phi3": grad_phi[2]}, ctx.every)
+        ctx.sim = None
+        return torch.tensor(g, dtype=ctx.dtype, device=ctx.device), None, None, None, None, None
 
 
 def drop_indicator(w):

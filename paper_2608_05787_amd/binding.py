@@ -55,7 +55,8 @@ class Init(ctypes.Structure):
 EXPORTS = ["lbm_ehd_adjoint_workspace_bytes", "lbm_ehd_workspace_bytes", "lbm_ehd_create", "lbm_ehd_step", "lbm_ehd_fields",
            "lbm_ehd_populations", "lbm_ehd_diagnostics", "lbm_ehd_scalars",
            "lbm_ehd_checkpoint_bytes", "lbm_ehd_checkpoint", "lbm_ehd_restore",
-           "lbm_ehd_adjoint", "lbm_ehd_profile_begin", "lbm_ehd_profile_end", "lbm_ehd_graph",
+           "lbm_ehd_adjoint", "lbm_ehd_record", "lbm_ehd_tangent_workspace_bytes", "lbm_ehd_tangent_gradient",
+           "lbm_ehd_profile_begin", "lbm_ehd_profile_end", "lbm_ehd_graph",
            "lbm_ehd_destroy", "lbm_ehd_strerror", "lbm_ehd_last_error"]
 KERNELS = ["moments", "pre", "poisson", "mu", "collide", "diag", "poisson2"]
 
@@ -83,7 +84,10 @@ def load():
     lib.lbm_ehd_checkpoint.argtypes = [vp, vp]
     lib.lbm_ehd_restore.argtypes = [vp, vp]
     lib.lbm_ehd_adjoint.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_uint32, vp, sz, _dp]
-    lib.lbm_ehd_adjoint_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.lbm_ehd_adjoint_workspace_bytes.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(sz)]
+    lib.lbm_ehd_record.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp, sz]
+    lib.lbm_ehd_tangent_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.lbm_ehd_tangent_gradient.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_uint32, vp, sz, _dp]
     lib.lbm_ehd_profile_begin.argtypes = [vp]
     lib.lbm_ehd_profile_end.argtypes = [vp, _dp, ctypes.POINTER(ctypes.c_int64)]
     lib.lbm_ehd_graph.argtypes = [vp, ctypes.c_int32]
@@ -238,26 +242,66 @@ class Sim:
         self._check(load().lbm_ehd_scalars(self._h, out), self._h)
         return {"steps": int(out[0]), "k_total": int(out[1]), "n_inst": int(out[2])}
 
-    def adjoint(self, n_steps: int, seed: dict):
-        """dJ/dtheta for J = sum over the seed's fields of seed * field after
-        n_steps from this handle's creation state; theta = (eps2/eps1,
-        eps3/eps1, sigma2/sigma1, sigma3/sigma1, E0).  seed: {field name:
-        [ny, nx] tensor}.  Runs forward-mode tangent passes in the library."""
+    def _seed_planes(self, seed: dict):
         import torch
-        lib = load()
         mask = 0
         for k in seed:
             mask |= 1 << FIELDS.index(k)
         order = [k for k in FIELDS if mask & (1 << FIELDS.index(k))]
         planes = torch.stack([seed[k].to(self.device, torch.float64) for k in order]).contiguous()
+        return mask, planes
+
+    def _adjoint_work(self, n_steps: int, ckpt_every: int):
+        import torch
         nb = ctypes.c_size_t()
-        self._check(lib.lbm_ehd_adjoint_workspace_bytes(self._h, ctypes.byref(nb)), self._h)
+        self._check(load().lbm_ehd_adjoint_workspace_bytes(self._h, int(n_steps), int(ckpt_every), ctypes.byref(nb)),
+                    self._h)
+        work = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.device)
+        base = (work.data_ptr() + 255) // 256 * 256
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        work.record_stream(self.stream)
+        return work, base, int(nb.value)
+
+    def record(self, n_steps: int, ckpt_every: int = 250):
+        """Step n_steps from the creation state (the same states as step())
+        while checkpointing every ckpt_every steps for adjoint()."""
+        work, base, nb = self._adjoint_work(n_steps, ckpt_every)
+        self._check(load().lbm_ehd_record(self._h, int(n_steps), int(ckpt_every), ctypes.c_void_p(base), nb),
+                    self._h)
+        self._rec = (work, base, nb, int(n_steps), int(ckpt_every))
+
+    def adjoint(self, n_steps: int, seed: dict, ckpt_every: int = 250):
+        """dJ/dtheta by the reverse (adjoint) sweep, for J = sum over the seed's
+        fields (phi1..phi3) of seed * field after n_steps from this handle's
+        creation state; theta = (eps2/eps1, eps3/eps1, sigma2/sigma1,
+        sigma3/sigma1, E0).  seed: {field name: [ny, nx] tensor}.  Uses the
+        checkpoints of record() when it ran with the same n_steps and
+        ckpt_every, else records its own run first."""
+        mask, planes = self._seed_planes(seed)
+        rec = getattr(self, "_rec", None)
+        if rec is not None and rec[3] == int(n_steps) and rec[4] == int(ckpt_every):
+            work, base, nb = rec[0], rec[1], rec[2]
+        else:
+            work, base, nb = self._adjoint_work(n_steps, ckpt_every)
+        grad = (ctypes.c_double * 5)()
+        self._check(load().lbm_ehd_adjoint(self._h, int(n_steps), int(ckpt_every), ctypes.c_void_p(planes.data_ptr()),
+                                           mask, ctypes.c_void_p(base), nb, grad), self._h)
+        return list(grad)
+
+    def tangent_gradient(self, n_steps: int, seed: dict):
+        """The same gradient as adjoint() by forward mode: five FP64 tangent
+        runs inside the library; any fields may be seeded."""
+        import torch
+        lib = load()
+        mask, planes = self._seed_planes(seed)
+        nb = ctypes.c_size_t()
+        self._check(lib.lbm_ehd_tangent_workspace_bytes(self._h, ctypes.byref(nb)), self._h)
         work = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.device)
         base = (work.data_ptr() + 255) // 256 * 256
         grad = (ctypes.c_double * 5)()
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
-        self._check(lib.lbm_ehd_adjoint(self._h, int(n_steps), 0, ctypes.c_void_p(planes.data_ptr()), mask,
-                                        ctypes.c_void_p(base), int(nb.value), grad), self._h)
+        self._check(lib.lbm_ehd_tangent_gradient(self._h, int(n_steps), ctypes.c_void_p(planes.data_ptr()), mask,
+                                                 ctypes.c_void_p(base), int(nb.value), grad), self._h)
         return list(grad)
 
     def graph(self, steps_per_graph: int):

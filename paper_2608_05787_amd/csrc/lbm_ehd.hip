@@ -15,6 +15,7 @@
 
 #include "lbm_ehd.h"
 #include "lbm_ehd_kernels.h"
+#include "lbm_ehd_adjoint.h"
 
 using namespace lbm;
 
@@ -210,8 +211,12 @@ struct lbm_ehd_s {
   double sub_tol = 0;
   long long steps = 0;
   std::string err;
-  // host copies of the initial fields (tangent runs restart from them)
+  // host copies of the initial fields (gradient runs restart from them)
   std::vector<std::vector<double>> init_phi, init_u, init_q, init_psi;
+  // recording made by lbm_ehd_record (checkpoints in the caller's buffer)
+  void *rec_work = nullptr;
+  int64_t rec_n = -1;
+  int rec_every = 0;
   // kernel timing (lbm_ehd_profile_begin/end)
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -453,25 +458,15 @@ int convert_any(lbm_ehd_s *H, int elem, const void *src, void *dst, size_t count
 
 }  // namespace
 
-extern "C" {
-
-int lbm_ehd_workspace_bytes(const lbm_ehd_params *params, int32_t n_inst, size_t *bytes) {
-  if (!params || n_inst < 1 || !bytes) return LBM_EHD_EINVAL;
-  for (int i = 0; i < n_inst; ++i)
-    if (const char *m = validate(params[i], params[0])) {
-      g_create_error = m;
-      return LBM_EHD_EINVAL;
-    }
-  *bytes = make_plan(params, n_inst).total;
-  return LBM_EHD_OK;
-}
-
-int lbm_ehd_create(const lbm_ehd_params *params, int32_t n_inst, const lbm_ehd_init *init,
-                   void *dev_workspace, void *hip_stream, lbm_ehd_t *out) {
+// Creates a handle over the caller's workspace.  run_init: upload the
+// initial fields and run the cold start; otherwise the state is left zeroed
+// (a shell whose state a later restore provides).
+static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_ehd_init *init,
+                       void *dev_workspace, void *hip_stream, lbm_ehd_t *out, bool run_init) {
   g_create_error.clear();
   if (!out) return LBM_EHD_EINVAL;
   *out = nullptr;
-  if (!params || !init || n_inst < 1) {
+  if (!params || (run_init && !init) || n_inst < 1) {
     g_create_error = "params, init and n_inst >= 1 are required";
     return LBM_EHD_EINVAL;
   }
@@ -482,7 +477,7 @@ int lbm_ehd_create(const lbm_ehd_params *params, int32_t n_inst, const lbm_ehd_i
       g_create_error = buf;
       return LBM_EHD_EINVAL;
     }
-    if (!init[i].phi0) {
+    if (run_init && !init[i].phi0) {
       g_create_error = "init.phi0 is required";
       return LBM_EHD_EINVAL;
     }
@@ -578,6 +573,10 @@ int lbm_ehd_create(const lbm_ehd_params *params, int32_t n_inst, const lbm_ehd_i
     H->err = std::string("workspace setup: ") + hipGetErrorString(e);
     return bad(LBM_EHD_EHIP);
   }
+  if (!run_init) {
+    *out = H;
+    return LBM_EHD_OK;
+  }
   for (int i = 0; i < n_inst; ++i) {
     const size_t N = (size_t)params[i].nx * params[i].ny;
     auto keep = [&](std::vector<std::vector<double>> &dst, const double *src, size_t cnt) {
@@ -598,6 +597,313 @@ int lbm_ehd_create(const lbm_ehd_params *params, int32_t n_inst, const lbm_ehd_i
     rc = do_create<float, float>(H, init);
   if (rc) return bad(rc);
   *out = H;
+  return LBM_EHD_OK;
+}
+
+
+// ------------------------------------------------------------ reverse mode
+
+namespace {
+
+constexpr int REC_FIXED = 22;    // planes of a step record before the potential levels
+constexpr int ADJ_AREA = 178;    // planes of the adjoint buffers (see rev_bufs)
+
+// Layout of the buffer shared by lbm_ehd_record and lbm_ehd_adjoint (byte
+// offsets from its start, 256-byte aligned): a private handle's workspace,
+// the checkpoints (one per segment of `every` steps), the step records of
+// one segment (reused for the cold start's potential levels), the adjoint
+// buffers, the per-block parameter partials and the cold start's chunk
+// checkpoints.
+struct AdjLayout {
+  size_t shell, ckpt, ckpt_stride, seg, slot_stride, adj, tb, out, cold_ck, total;
+  int64_t rev;     // steps whose adjoint runs in full (the last step's is its seed)
+  int nseg, nck, slots, rec_planes, cold_len, cold_chunks, tb_slots;
+};
+
+AdjLayout adj_layout(const lbm_ehd_s *H, int64_t n_steps, int every) {
+  AdjLayout L{};
+  const lbm_ehd_params &p = H->params[0];
+  const size_t N = (size_t)p.nx * p.ny, te = elem_size(H->prec);
+  L.rev = n_steps > 1 ? n_steps - 1 : 0;
+  L.nseg = (int)((L.rev + every - 1) / every);
+  L.nck = L.nseg > 0 ? L.nseg : 1;
+  L.slots = (int)std::min<int64_t>(every, L.rev > 0 ? L.rev : 1);
+  L.rec_planes = REC_FIXED + 9 * H->sub_max;
+  size_t off = 0;
+  L.shell = off;
+  off = align_up(off + H->plan.total);
+  L.ckpt = off;
+  L.ckpt_stride = align_up(H->plan.total - H->plan.state_off);
+  off = align_up(off + (size_t)L.nck * L.ckpt_stride);
+  L.seg = off;
+  L.slot_stride = align_up((size_t)L.rec_planes * N * te);
+  off = align_up(off + (size_t)L.slots * L.slot_stride);
+  L.adj = off;
+  off = align_up(off + (size_t)ADJ_AREA * N * te);
+  L.tb = off;
+  L.tb_slots = std::max(H->hinst[0].nblk, H->plan.total_tiles2);
+  off = align_up(off + (size_t)L.tb_slots * TB_SLOTS * sizeof(double));
+  L.out = off;
+  off = align_up(off + TB_SLOTS * sizeof(double));
+  L.cold_len = std::max(1, (int)(((size_t)L.slots * L.slot_stride) / (9 * N * te)));
+  L.cold_chunks = p.init_sub_max > 0 ? (p.init_sub_max + L.cold_len - 1) / L.cold_len : 0;
+  L.cold_ck = off;
+  off = align_up(off + (size_t)L.cold_chunks * 9 * N * te);
+  L.total = off;
+  return L;
+}
+
+const char *adjoint_unsupported(const lbm_ehd_s *H) {
+  if (H->n_inst != 1) return "gradients need a single-instance handle";
+  if (H->prec != LBM_PREC_FP32 && H->prec != LBM_PREC_FP64) return "reverse mode needs FP32 or FP64 precision";
+  if (H->adaptive) return "reverse mode needs a fixed number of potential sub-iterations";
+  const lbm_ehd_params &p = H->params[0];
+  if (p.init_tol > 0 && p.init_sub_max > 1) return "reverse mode needs a fixed-count cold start (init_tol <= 0)";
+  if (p.eps_ref_phase != 0) return "gradients along permittivity ratios need eps_ref_phase 0";
+  return nullptr;
+}
+
+// Pointers of one step record: phi 3, q, R, eps, E_prev 2, mu 3, E 2, g 9,
+// then the input level of each potential sub-iteration (9 planes each).
+template <typename T> Rec<T> rec_slot(char *slot, size_t N) {
+  T *b = (T *)slot;
+  Rec<T> r;
+  r.phi = b;
+  r.q = b + 3 * N;
+  r.R = b + 4 * N;
+  r.eps = b + 5 * N;
+  r.Eo = b + 6 * N;
+  r.mu = b + 8 * N;
+  r.En = b + 11 * N;
+  r.g = b + 13 * N;
+  return r;
+}
+template <typename T> T *rec_level(char *slot, size_t N, int k) { return (T *)slot + (REC_FIXED + 9 * (size_t)k) * N; }
+
+// One forward step that also writes its record: the launches of an
+// ordinary fixed-count step, the potential kernels storing the input level
+// of every sub-iteration.
+template <typename T>
+void step_record(lbm_ehd_s *W, char *slot) {
+  const dim3 grid(W->plan.total_blocks), block(NT), grid2(W->plan.total_tiles2), block2(P2NT);
+  const size_t N = (size_t)W->hinst[0].N;
+  const int K = W->sub_max, pc = (int)(W->steps & 1);
+  const Rec<T> rc = rec_slot<T>(slot, N);
+  k_moments<T, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, pc, rc);
+  k_pre<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, rc);
+  int L = 0, k = 1;
+  if (K & 1) {
+    k_poisson<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, 1, K, 0, 0, rec_level<T>(slot, N, 0));
+    L = 1;
+    k = 2;
+  }
+  for (; k + 1 <= K; k += 2, ++L)
+    k_poisson2<T><<<grid2, block2, 0, W->stream>>>(W->d_insts, W->d_t2, L & 1, k + 1 == K ? 1 : 0,
+                                                   rec_level<T>(slot, N, k - 1), rec_level<T>(slot, N, k));
+  const int hflip = L & 1;
+  k_mu<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, hflip, rc);
+  k_collide<T, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, pc, 0, K, hflip, rc);
+  W->steps += 1;
+}
+
+// Adjoint of one recorded step: a[cur], pb[cur], hb[hs] hold the adjoint of
+// the next level on entry; on return cur and hs name this level's.
+template <typename T>
+void step_adjoint(lbm_ehd_s *W, char *slot, const AdjBufs<T> &ab, int &cur, int &hs) {
+  const dim3 grid(W->plan.total_blocks), block(NT);
+  const size_t N = (size_t)W->hinst[0].N;
+  const int K = W->sub_max;
+  const Rec<T> rc = rec_slot<T>(slot, N);
+  k_adj_collide<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, rc, ab, cur);
+  k_adj_mu<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, rc, ab, cur, hs, 1);
+  // sub-iterations K, K-1, ... in pairs on LDS tiles, a single one last when K is odd
+  int k = K;
+  for (; k >= 2; k -= 2) {
+    k_adj_poisson2<T><<<dim3(W->plan.total_tiles2), dim3(P2NT), 0, W->stream>>>(
+        W->d_insts, W->d_t2, rec_level<T>(slot, N, k - 1), rec_level<T>(slot, N, k - 2), rc.eps, ab, hs, ab.qb);
+    hs ^= 1;
+  }
+  if (k == 1) {
+    k_adj_poisson<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, rec_level<T>(slot, N, 0), rc.eps, ab, hs,
+                                                    ab.qb);
+    hs ^= 1;
+  }
+  k_adj_pre<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, rc, ab, cur);
+  k_adj_phi<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, rc, ab, cur);
+  cur ^= 1;
+}
+
+// Steps handle R from its create state through n_steps, writing a
+// checkpoint at the start of every segment of `every` steps.
+int record_run(lbm_ehd_s *R, char *work, const AdjLayout &L, int64_t n_steps, int every) {
+  int64_t t = 0;
+  int ck = 0;
+  for (;;) {
+    if (ck < L.nck && t == (int64_t)ck * every) {
+      const int rc = lbm_ehd_checkpoint(R, work + L.ckpt + (size_t)ck * L.ckpt_stride);
+      if (rc) return rc;
+      ++ck;
+    }
+    if (t >= n_steps) break;
+    const int64_t next = std::min<int64_t>(n_steps, (t / every + 1) * every);
+    const int rc = lbm_ehd_step(R, next - t);
+    if (rc) return rc;
+    t = next;
+  }
+  return LBM_EHD_OK;
+}
+
+// The reverse sweep over a recording: segments last to first (restore the
+// segment's checkpoint into W, re-run it writing step records, then the
+// step adjoints last to first), then the adjoint of create (equilibrium
+// populations, field and chemical potential, the cold-start potential
+// iterations in recomputed chunks, the initial potential guess).
+template <typename T>
+int reverse_sweep(lbm_ehd_s *H, lbm_ehd_s *W, char *work, const AdjLayout &L, int64_t n_steps, int every,
+                  const double *seed, uint32_t mask, double grad[5]) {
+  const dim3 grid(W->plan.total_blocks), block(NT);
+  const Inst &I = W->hinst[0];
+  const size_t N = (size_t)I.N;
+  const lbm_ehd_params &p = W->params[0];
+  T *base = (T *)(work + L.adj);
+  AdjBufs<T> ab;
+  ab.a[0] = base;
+  ab.a[1] = base + 55 * N;
+  ab.hb[0] = base + 110 * N;
+  ab.hb[1] = base + 119 * N;
+  ab.pb[0] = base + 128 * N;
+  ab.pb[1] = base + 132 * N;
+  ab.muL = base + 136 * N;
+  ab.gm = base + 139 * N;
+  ab.gr = base + 145 * N;
+  ab.qb = base + 147 * N;
+  ab.rb = base + 148 * N;
+  ab.en = base + 149 * N;
+  ab.eb = base + 151 * N;
+  ab.lb = base + 152 * N;
+  ab.ge = base + 155 * N;
+  ab.gs = base + 157 * N;
+  T *psi0 = base + 159 * N;
+  T *cold[2] = {base + 160 * N, base + 169 * N};
+  ab.tb = (double *)(work + L.tb);
+  double E0, mean;
+  applied_field(p, E0, mean);
+  const double inv_e0 = E0 > 0 ? 1.0 / E0 : 0.0;
+  const bool walls = p.bc_y == LBM_BC_WALL;
+  for (int k = 0; k < 2; ++k) {
+    ab.dEext[k] = p.E_ext[k] * inv_e0;
+    ab.dwall[k] = walls ? (p.wall_phi[k] - mean) * inv_e0 : 0.0;
+  }
+  HIPC(H, hipMemsetAsync(base, 0, (size_t)ADJ_AREA * N * sizeof(T), W->stream));
+  HIPC(H, hipMemsetAsync(ab.tb, 0, (size_t)L.tb_slots * TB_SLOTS * sizeof(double), W->stream));
+  int cur = 0, hs = 0;
+  if (n_steps >= 1) {
+    int sel[3] = {0, 0, 0}, count = 0;
+    for (int b = 0; b < 3; ++b)
+      if (mask & (1u << b)) sel[count++] = b;
+    k_adj_seed<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, seed, make_int3(sel[0], sel[1], sel[2]), count,
+                                                 ab.pb[0]);
+    HIPC(H, hipGetLastError());
+    for (int sg = L.nseg - 1; sg >= 0; --sg) {
+      const int64_t s0 = (int64_t)sg * every, s1 = std::min<int64_t>(s0 + every, L.rev);
+      int rc = lbm_ehd_restore(W, work + L.ckpt + (size_t)sg * L.ckpt_stride);
+      if (rc) return H->fail(rc, "adjoint: restore: %s", W->err.c_str());
+      for (int64_t t = s0; t < s1; ++t) step_record<T>(W, work + L.seg + (size_t)(t - s0) * L.slot_stride);
+      for (int64_t t = s1 - 1; t >= s0; --t)
+        step_adjoint<T>(W, work + L.seg + (size_t)(t - s0) * L.slot_stride, ab, cur, hs);
+      HIPC(H, hipGetLastError());
+    }
+    // create: populations and field of the initial state
+    int rc = lbm_ehd_restore(W, work + L.ckpt);
+    if (rc) return H->fail(rc, "adjoint: restore: %s", W->err.c_str());
+    k_adj_init_pops<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, ab, cur);
+    Rec<T> rc0{};
+    rc0.phi = (T *)I.phi;
+    rc0.eps = (T *)I.eps;
+    rc0.En = (T *)I.E;
+    k_adj_mu<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, rc0, ab, cur, hs, 0);
+    HIPC(H, hipGetLastError());
+  }
+  // initial potential guess
+  {
+    std::vector<T> buf(N);
+    const std::vector<double> &ps = H->init_psi[0];
+    for (size_t k = 0; k < N; ++k) buf[k] = ps.empty() ? T(0) : (T)ps[k];
+    HIPC(H, hipMemcpyAsync(psi0, buf.data(), N * sizeof(T), hipMemcpyHostToDevice, W->stream));
+    HIPC(H, hipStreamSynchronize(W->stream));
+  }
+  const int K0 = p.init_sub_max;
+  if (n_steps >= 1 && K0 > 0) {
+    // cold start: chunk checkpoints, then each chunk recomputed with its
+    // levels recorded and reversed
+    const size_t lv = 9 * N;
+    T *ck = (T *)(work + L.cold_ck);
+    T *lev = (T *)(work + L.seg);
+    k_h_equilibrium<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, psi0, cold[0]);
+    int cp = 0;
+    // checkpoints are needed up to the start of the last chunk
+    const int kck = (L.cold_chunks - 1) * L.cold_len + 1;
+    for (int k = 0; k < kck; ++k) {
+      if (k % L.cold_len == 0)
+        HIPC(H, hipMemcpyAsync(ck + (size_t)(k / L.cold_len) * lv, cold[cp], lv * sizeof(T), hipMemcpyDeviceToDevice,
+                               W->stream));
+      if (k + 1 < kck)
+        k_poisson_buf<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, cold[cp], cold[cp ^ 1],
+                                                        (const T *)I.eps, (const T *)I.q, nullptr);
+      cp ^= 1;
+    }
+    for (int c = L.cold_chunks - 1; c >= 0; --c) {
+      const int ka = c * L.cold_len, kb = std::min(K0, ka + L.cold_len);
+      HIPC(H, hipMemcpyAsync(cold[0], ck + (size_t)c * lv, lv * sizeof(T), hipMemcpyDeviceToDevice, W->stream));
+      cp = 0;
+      for (int k = ka; k < kb; ++k) {
+        k_poisson_buf<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, cold[cp], cold[cp ^ 1],
+                                                        (const T *)I.eps, (const T *)I.q, lev + (size_t)(k - ka) * lv);
+        cp ^= 1;
+      }
+      for (int k = kb - 1; k >= ka; --k) {
+        k_adj_poisson<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, lev + (size_t)(k - ka) * lv,
+                                                        (const T *)I.eps, ab, hs, ab.rb);
+        hs ^= 1;
+      }
+      HIPC(H, hipGetLastError());
+    }
+  }
+  if (n_steps >= 1)
+    k_adj_create_tail<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, ab, hs, (const T *)I.phi, psi0, mean,
+                                                        inv_e0);
+  double *out = (double *)(work + L.out);
+  k_adj_reduce<<<1, block, 0, W->stream>>>(ab.tb, L.tb_slots, out);
+  HIPC(H, hipGetLastError());
+  double o[TB_SLOTS];
+  HIPC(H, hipMemcpyAsync(o, out, sizeof o, hipMemcpyDeviceToHost, W->stream));
+  HIPC(H, hipStreamSynchronize(W->stream));
+  // theta = (eps2/eps1, eps3/eps1, sigma2/sigma1, sigma3/sigma1, E0)
+  grad[0] = p.eps[0] * o[1];
+  grad[1] = p.eps[0] * o[2];
+  grad[2] = p.sigma[0] * o[4];
+  grad[3] = p.sigma[0] * o[5];
+  grad[4] = o[6];
+  return LBM_EHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_ehd_create(const lbm_ehd_params *params, int32_t n_inst, const lbm_ehd_init *init,
+                   void *dev_workspace, void *hip_stream, lbm_ehd_t *out) {
+  return create_impl(params, n_inst, init, dev_workspace, hip_stream, out, true);
+}
+
+int lbm_ehd_workspace_bytes(const lbm_ehd_params *params, int32_t n_inst, size_t *bytes) {
+  if (!params || n_inst < 1 || !bytes) return LBM_EHD_EINVAL;
+  for (int i = 0; i < n_inst; ++i)
+    if (const char *m = validate(params[i], params[0])) {
+      g_create_error = m;
+      return LBM_EHD_EINVAL;
+    }
+  *bytes = make_plan(params, n_inst).total;
   return LBM_EHD_OK;
 }
 
@@ -786,7 +1092,7 @@ static lbm_ehd_params tangent_params(const lbm_ehd_params &p, int dir) {
   return t;
 }
 
-int lbm_ehd_adjoint_workspace_bytes(lbm_ehd_t H, size_t *bytes) {
+int lbm_ehd_tangent_workspace_bytes(lbm_ehd_t H, size_t *bytes) {
   if (!H || !bytes) return LBM_EHD_EINVAL;
   if (H->n_inst != 1) return H->fail(LBM_EHD_EUNSUPPORTED, "gradients need a single-instance handle");
   const lbm_ehd_params t = tangent_params(H->params[0], 0);
@@ -794,15 +1100,15 @@ int lbm_ehd_adjoint_workspace_bytes(lbm_ehd_t H, size_t *bytes) {
   return LBM_EHD_OK;
 }
 
-int lbm_ehd_adjoint(lbm_ehd_t H, int64_t n_steps, int32_t, const void *dev_seed, uint32_t seed_mask,
-                    void *dev_work, size_t work_bytes, double grad_theta[5]) {
+int lbm_ehd_tangent_gradient(lbm_ehd_t H, int64_t n_steps, const void *dev_seed, uint32_t seed_mask,
+                             void *dev_work, size_t work_bytes, double grad_theta[5]) {
   if (!H || !grad_theta || !dev_seed || n_steps < 0) return LBM_EHD_EINVAL;
   if (H->n_inst != 1) return H->fail(LBM_EHD_EUNSUPPORTED, "gradients need a single-instance handle");
-  if (seed_mask == 0 || (seed_mask >> 16) != 0) return H->fail(LBM_EHD_EINVAL, "adjoint: bad seed mask");
+  if (seed_mask == 0 || (seed_mask >> 16) != 0) return H->fail(LBM_EHD_EINVAL, "tangent gradient: bad seed mask");
   size_t need = 0;
-  lbm_ehd_adjoint_workspace_bytes(H, &need);
+  lbm_ehd_tangent_workspace_bytes(H, &need);
   if (!dev_work || work_bytes < need || ((uintptr_t)dev_work % ALIGN) != 0)
-    return H->fail(LBM_EHD_ENOMEM, "adjoint: work buffer must be >= %zu bytes and 256-byte aligned", need);
+    return H->fail(LBM_EHD_ENOMEM, "tangent gradient: work buffer must be >= %zu bytes and 256-byte aligned", need);
   lbm_ehd_init ini;
   ini.phi0 = H->init_phi[0].data();
   ini.u0 = H->init_u[0].empty() ? nullptr : H->init_u[0].data();
@@ -812,7 +1118,7 @@ int lbm_ehd_adjoint(lbm_ehd_t H, int64_t n_steps, int32_t, const void *dev_seed,
     const lbm_ehd_params t = tangent_params(H->params[0], dir);
     lbm_ehd_t T = nullptr;
     int rc = lbm_ehd_create(&t, 1, &ini, dev_work, (void *)H->stream, &T);
-    if (rc) return H->fail(rc, "adjoint: tangent run: %s", g_create_error.c_str());
+    if (rc) return H->fail(rc, "tangent gradient: tangent run: %s", g_create_error.c_str());
     rc = lbm_ehd_step(T, n_steps);
     if (rc) {
       H->err = T->err;
@@ -833,10 +1139,73 @@ int lbm_ehd_adjoint(lbm_ehd_t H, int64_t n_steps, int32_t, const void *dev_seed,
     if (e == hipSuccess) e = hipStreamSynchronize(T->stream);
     if (e == hipSuccess) e = hipMemcpy(&c, I.ctl, sizeof c, hipMemcpyDeviceToHost);
     lbm_ehd_destroy(T);
-    if (e != hipSuccess) return H->fail(LBM_EHD_EHIP, "adjoint: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return H->fail(LBM_EHD_EHIP, "tangent gradient: %s", hipGetErrorString(e));
     grad_theta[dir] = c.diag[10];
   }
   return LBM_EHD_OK;
+}
+
+int lbm_ehd_adjoint_workspace_bytes(lbm_ehd_t H, int64_t n_steps, int32_t ckpt_every, size_t *bytes) {
+  if (!H || !bytes || n_steps < 0 || ckpt_every < 1) return LBM_EHD_EINVAL;
+  if (const char *m = adjoint_unsupported(H)) return H->fail(LBM_EHD_EUNSUPPORTED, "%s", m);
+  *bytes = adj_layout(H, n_steps, ckpt_every).total;
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_record(lbm_ehd_t H, int64_t n_steps, int32_t ckpt_every, void *dev_work, size_t work_bytes) {
+  if (!H || n_steps < 0 || ckpt_every < 1) return LBM_EHD_EINVAL;
+  if (const char *m = adjoint_unsupported(H)) return H->fail(LBM_EHD_EUNSUPPORTED, "%s", m);
+  if (H->steps != 0) return H->fail(LBM_EHD_ESTATE, "record: the handle must be at its create state");
+  const AdjLayout L = adj_layout(H, n_steps, ckpt_every);
+  if (!dev_work || work_bytes < L.total || ((uintptr_t)dev_work % ALIGN) != 0)
+    return H->fail(LBM_EHD_ENOMEM, "record: work buffer must be >= %zu bytes and 256-byte aligned", L.total);
+  H->rec_work = nullptr;
+  const int rc = record_run(H, (char *)dev_work, L, n_steps, ckpt_every);
+  if (rc) return rc;
+  H->rec_work = dev_work;
+  H->rec_n = n_steps;
+  H->rec_every = ckpt_every;
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_adjoint(lbm_ehd_t H, int64_t n_steps, int32_t ckpt_every, const void *dev_seed, uint32_t seed_mask,
+                    void *dev_work, size_t work_bytes, double grad_theta[5]) {
+  if (!H || !grad_theta || !dev_seed || n_steps < 0 || ckpt_every < 1) return LBM_EHD_EINVAL;
+  if (const char *m = adjoint_unsupported(H)) return H->fail(LBM_EHD_EUNSUPPORTED, "%s", m);
+  if (seed_mask == 0 || (seed_mask & ~7u) != 0)
+    return H->fail(LBM_EHD_EUNSUPPORTED, "adjoint: seeds on phi1..phi3 only (lbm_ehd_tangent_gradient takes any field)");
+  const AdjLayout L = adj_layout(H, n_steps, ckpt_every);
+  if (!dev_work || work_bytes < L.total || ((uintptr_t)dev_work % ALIGN) != 0)
+    return H->fail(LBM_EHD_ENOMEM, "adjoint: work buffer must be >= %zu bytes and 256-byte aligned", L.total);
+  char *work = (char *)dev_work;
+  const bool recorded = H->rec_work == dev_work && H->rec_n == n_steps && H->rec_every == ckpt_every;
+  lbm_ehd_t W = nullptr;
+  int rc;
+  if (recorded) {
+    rc = create_impl(&H->params[0], 1, nullptr, work + L.shell, (void *)H->stream, &W, false);
+  } else {
+    lbm_ehd_init ini;
+    ini.phi0 = H->init_phi[0].data();
+    ini.u0 = H->init_u[0].empty() ? nullptr : H->init_u[0].data();
+    ini.q0 = H->init_q[0].empty() ? nullptr : H->init_q[0].data();
+    ini.psi0 = H->init_psi[0].empty() ? nullptr : H->init_psi[0].data();
+    rc = create_impl(&H->params[0], 1, &ini, work + L.shell, (void *)H->stream, &W, true);
+    if (!rc) {
+      rc = record_run(W, work, L, n_steps, ckpt_every);
+      if (rc) H->err = W->err;
+    }
+  }
+  if (rc) {
+    if (W) lbm_ehd_destroy(W);
+    else H->err = g_create_error;
+    return rc;
+  }
+  if (H->prec == LBM_PREC_FP64)
+    rc = reverse_sweep<double>(H, W, work, L, n_steps, ckpt_every, (const double *)dev_seed, seed_mask, grad_theta);
+  else
+    rc = reverse_sweep<float>(H, W, work, L, n_steps, ckpt_every, (const double *)dev_seed, seed_mask, grad_theta);
+  lbm_ehd_destroy(W);
+  return rc;
 }
 
 int lbm_ehd_profile_begin(lbm_ehd_t H) {

@@ -1,0 +1,810 @@
+// Reverse-mode (discrete adjoint) kernels of the three-phase EHD LB step for
+// gfx950.  Included once, by lbm_ehd.hip, after lbm_ehd_kernels.h.
+//
+// The adjoint of one time step runs the step's kernels backwards: the
+// collide-and-push kernel (flow, charge and order-parameter families), the
+// chemical-potential kernel, the potential sub-iterations (last first), the
+// charge-recovery kernel and the order-parameter moments.  Each adjoint
+// kernel is a gather: the transpose of a push is a pull from the slots the
+// node pushed to, and the transpose of an Eq. (33) stencil is a sum over the
+// nodes whose stencil reaches this node (mirror ghosts included).  So every
+// thread writes only its own node and no atomics are needed.  Forward values
+// come from the step's record (Rec, written by the forward kernels during a
+// recording run) and are recomputed locally where cheaper.
+//
+// Adjoint state between steps (planes of N values, type T):
+//   a[2]   f 27, g 9, l 9 (adjoint of the populations a step reads, without
+//          the moment part), hpu 6, hqu 2, E 2 (previous-step field)
+//   hb[2]  potential populations 9 (ping-pong over the sub-iterations)
+//   pb[2]  phi 3 and sum-of-l 1: the adjoint of the step's moments, which
+//          the next (earlier) step's pull adds to every f^i_j and l_j.
+// Parameter adjoints (d/d eps_i, d/d sigma_i, d/d E0) accumulate in per-block
+// FP64 slots, block b owning slot b: the sweep's kernels run in stream order,
+// so += needs no atomics, and the final sum has a fixed order.
+#pragma once
+
+namespace lbm {
+
+constexpr int ADJ_PLANES = 55;  // f 27, g 9, l 9, hpu 6, hqu 2, E 2
+constexpr int AO_G = 27, AO_L = 36, AO_HPU = 45, AO_HQU = 51, AO_E = 53;
+constexpr int TB_SLOTS = 8;     // eps 3, sigma 3, E0 1, spare
+
+template <typename T> struct AdjBufs {
+  T *a[2], *hb[2], *pb[2];
+  // per-step intermediates: mu-bar (local part) 3, grad(mu)-bar 6,
+  // grad(rho)-bar 2, q-bar, R-bar, E-bar of the step's field 2, eps-bar,
+  // Laplacian-bar 3, grad(eps)-bar 2, grad(sigma)-bar 2
+  T *muL, *gm, *gr, *qb, *rb, *en, *eb, *lb, *ge, *gs;
+  double *tb;      // nblk x TB_SLOTS
+  double dEext[2]; // d E_ext / d E0
+  double dwall[2]; // d wall_phi / d E0
+};
+
+// Destination slot of the population (x, y, j) pushed by the forward step:
+// returns false at a wall, where the slot is (opp(j), this node).
+__device__ __forceinline__ bool push_slot(const Inst &I, int x, int y, int n, int j, size_t &slot, int &dn,
+                                          bool &top) {
+  const int nx = I.nx, ny = I.ny, N = I.N;
+  const int xd = wrapx(x + cx(j), nx);
+  int yd = y + cy(j);
+  top = yd >= ny;
+  if (!I.bc_y) {
+    yd = yd < 0 ? yd + ny : (yd >= ny ? yd - ny : yd);
+  } else if (yd < 0 || yd >= ny) {
+    dn = n;
+    slot = (size_t)opp(j) * N + n;
+    return false;
+  }
+  dn = yd * nx + xd;
+  slot = (size_t)j * N + dn;
+  return true;
+}
+
+// Transpose of an Eq. (33) stencil: calls f(j, m) for every node m and
+// direction j whose stencil point m + c_j is the node (x, y), through the
+// periodic wrap or the mirror ghost rows at walls.
+template <typename F>
+__device__ __forceinline__ void for_sources(const Inst &I, int x, int y, F &&f) {
+  const int nx = I.nx, ny = I.ny;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const int sx = wrapx(x - cx(j), nx);
+    int sy = y - cy(j);
+    if (!I.bc_y) {
+      sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
+      f(j, sy * nx + sx);
+    } else {
+      if (sy >= 0 && sy < ny) f(j, sy * nx + sx);
+      // a stencil point beyond a wall reads the first fluid row
+      if ((y == 0 && cy(j) == -1) || (y == ny - 1 && cy(j) == 1)) f(j, y * nx + sx);
+    }
+  }
+}
+
+// Adds the block's parameter adjoints to its slot.
+__device__ __forceinline__ void add_theta(const Inst &I, double *tb, int lblk, double (&v)[TB_SLOTS]) {
+  block_sum<TB_SLOTS>(v);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < TB_SLOTS; ++k) tb[(size_t)lblk * TB_SLOTS + k] += v[k];
+}
+
+// Adjoint of the collide-and-push kernel of one step.  Reads the adjoint of
+// the next level (a[cur], pb[cur]); writes the adjoint of this level's
+// populations and history (a[cur ^ 1]), the local phi-bar (pb[cur ^ 1]) and
+// the intermediates consumed by the following adjoint kernels.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
+                                                    Rec<T> rc, AdjBufs<T> ab, int cur) {
+  const Inst *Ip;
+  int lblk;
+  const Node nd = locate(insts, b2i, Ip, lblk);
+  if (!nd.valid) return;
+  const Inst &I = *Ip;
+  const Phys<T> &P = phys<T>(I);
+  const int N = I.N, nx = I.nx, n = nd.n, x = nd.x, y = nd.y;
+  const T *A = ab.a[cur];
+  T *An = ab.a[cur ^ 1];
+  const T *PBc = ab.pb[cur];
+  T *PBn = ab.pb[cur ^ 1];
+
+  // ---- forward values
+  int m[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) m[j] = fdrow(y + cy(j), I.ny, I.bc_y) * nx + wrapx(x + cx(j), nx);
+  T ph[3], rv[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const T p1 = rc.phi[m[j]], p2 = rc.phi[(size_t)N + m[j]], p3 = rc.phi[(size_t)2 * N + m[j]];
+    rv[j] = P.rho[0] * p1 + P.rho[1] * p2 + P.rho[2] * p3;
+    if (j == 0) {
+      ph[0] = p1;
+      ph[1] = p2;
+      ph[2] = p3;
+    }
+  }
+  T grx, gry, dummy;
+  fd9(rv, grx, gry, dummy);
+  T gmx[3], gmy[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T v[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) v[j] = rc.mu[(size_t)i * N + m[j]];
+    fd9(v, gmx[i], gmy[i], dummy);
+  }
+  const T rho = rv[0];
+  const T q = rc.q[n];
+  const T ex = rc.En[n], ey = rc.En[(size_t)N + n];
+  T Fx = q * ex, Fy = q * ey;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    Fx -= ph[i] * gmx[i];
+    Fy -= ph[i] * gmy[i];
+  }
+  T g[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) g[j] = rc.g[(size_t)j * N + n];
+  T mxg = 0, myg = 0, s1 = 0;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    mxg += T(cx(j)) * g[j];
+    myg += T(cy(j)) * g[j];
+    if (j) s1 += g[j];
+  }
+  const T ux = (mxg + T(0.5) * Fx) / rho, uy = (myg + T(0.5) * Fy) / rho;
+  const T udr = ux * grx + uy * gry;
+  const T usq = ux * ux + uy * uy;
+  const T s0 = wgt<T>(0) * (-usq * T(1.5));
+  const T pp = (s1 + T(0.5) * udr + rho * s0) / (T(3) * (T(1) - wgt<T>(0)));
+  const T mv = P.visc[0] * ph[0] + P.visc[1] * ph[1] + P.visc[2] * ph[2];
+  const T tg = T(0.5) + mv * T(3) / rho;
+  const T itg = T(1) / tg, cg = T(1) - T(0.5) * itg;
+
+  // ---- where each population was pushed: slot offset (plane j or, at a
+  // wall, plane opp(j) of this node), node of that slot, wall speed factor
+  int so[Q], dnode[Q];
+  T wu[Q];  // -6 w_j c_jx u_wall at a wall, 0 inside
+  bool wal[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    size_t slot;
+    bool top;
+    wal[j] = !push_slot(I, x, y, n, j, slot, dnode[j], top);
+    so[j] = wal[j] ? opp(j) : j;
+    wu[j] = wal[j] ? -T(6) * wgt<T>(j) * T(cx(j)) * (top ? P.wall_u[1] : P.wall_u[0]) : T(0);
+  }
+  auto at = [&](const T *plane0, int j) { return plane0[(size_t)so[j] * N + dnode[j]]; };
+
+  // ---- adjoint accumulators
+  T ph_b[3] = {T(0), T(0), T(0)}, mu_b[3] = {T(0), T(0), T(0)};
+  T gmx_b[3] = {T(0), T(0), T(0)}, gmy_b[3] = {T(0), T(0), T(0)};
+  T ux_b = 0, uy_b = 0, rho_b = 0, pp_b = 0, Fx_b = 0, Fy_b = 0, grx_b = 0, gry_b = 0;
+  T q_b = 0, R_b = 0, itg_b = 0;
+
+  // ---- charge family (Eqs. 48-50)
+  {
+    const T itl = T(1) / P.tau_l, cl = T(1) - T(0.5) * itl;
+    const bool dir = I.wall_q_mode == 1;
+    T dqx_b = 0, dqy_b = 0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const T a = at(A + (size_t)AO_L * N, j) + PBc[(size_t)3 * N + dnode[j]];
+      T vb = a;
+      if (wal[j]) {
+        if (dir)
+          vb = -a;
+        else
+          q_b += a * wu[j];
+      }
+      An[(size_t)AO_L * N + (size_t)j * N + n] = vb * (T(1) - itl);
+      const T cu = T(cx(j)) * ux + T(cy(j)) * uy;
+      const T wv = vb * itl * wgt<T>(j);
+      q_b += wv * (T(1) + T(3) * cu);
+      ux_b += wv * q * T(3) * T(cx(j));
+      uy_b += wv * q * T(3) * T(cy(j));
+      R_b += vb * cl * wgt<T>(j);
+      dqx_b += vb * cl * wgt<T>(j) * T(3) * T(cx(j));
+      dqy_b += vb * cl * wgt<T>(j) * T(3) * T(cy(j));
+    }
+    // dq = q u - (q u)_prev; (q u) is also this step's history output
+    const T hx = A[(size_t)AO_HQU * N + n], hy = A[(size_t)(AO_HQU + 1) * N + n];
+    q_b += (dqx_b + hx) * ux + (dqy_b + hy) * uy;
+    ux_b += q * (dqx_b + hx);
+    uy_b += q * (dqy_b + hy);
+    An[(size_t)AO_HQU * N + n] = -dqx_b;
+    An[(size_t)(AO_HQU + 1) * N + n] = -dqy_b;
+  }
+
+  // ---- flow family (Eqs. 37-40), local tau_g
+  T g_b[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const T vb = at(A + (size_t)AO_G * N, j);
+    rho_b += vb * wu[j];
+    const T cu = T(cx(j)) * ux + T(cy(j)) * uy;
+    const T sj = wgt<T>(j) * (cu * T(3) + cu * cu * T(4.5) - usq * T(1.5));
+    const T geq = (j == 0 ? (wgt<T>(0) - T(1)) * pp * T(3) : wgt<T>(j) * pp * T(3)) + rho * sj;
+    const T cF = T(cx(j)) * Fx + T(cy(j)) * Fy;
+    const T cgr = T(cx(j)) * grx + T(cy(j)) * gry;
+    const T Gb = wgt<T>(j) * (udr + cF * T(3) + (cu * cgr - udr / T(3)) * T(3));
+    g_b[j] = vb * (T(1) - itg);
+    itg_b += vb * (-(g[j] - geq) - T(0.5) * Gb);
+    pp_b += vb * itg * (j == 0 ? T(3) * (wgt<T>(0) - T(1)) : T(3) * wgt<T>(j));
+    rho_b += vb * itg * sj;
+    const T ws = vb * itg * rho * wgt<T>(j);
+    ux_b += ws * (T(3) * T(cx(j)) + T(9) * cu * T(cx(j)) - T(3) * ux);
+    uy_b += ws * (T(3) * T(cy(j)) + T(9) * cu * T(cy(j)) - T(3) * uy);
+    const T Gb_b = vb * cg * T(3) * wgt<T>(j);
+    Fx_b += Gb_b * T(cx(j));
+    Fy_b += Gb_b * T(cy(j));
+    ux_b += Gb_b * cgr * T(cx(j));
+    uy_b += Gb_b * cgr * T(cy(j));
+    grx_b += Gb_b * cu * T(cx(j));
+    gry_b += Gb_b * cu * T(cy(j));
+  }
+  {
+    const T tg_b = -itg_b * itg * itg;
+    const T mv_b = tg_b * T(3) / rho;
+    rho_b -= tg_b * T(3) * mv / (rho * rho);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) ph_b[i] += P.visc[i] * mv_b;
+  }
+
+  // ---- order-parameter families (Eqs. 34-36) and their history
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const T hx = A[(size_t)(AO_HPU + 2 * i) * N + n], hy = A[(size_t)(AO_HPU + 2 * i + 1) * N + n];
+    T dpx_b = 0, dpy_b = 0;
+    if (I.phase_mode == 0) {
+      const T m0 = P.m0, itf = T(1) / P.tau_f, cf = T(1) - T(0.5) * itf;
+      T dtx_b = 0, dty_b = 0;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        const T vb = at(A + (size_t)(i * Q) * N, j) + PBc[(size_t)i * N + dnode[j]];
+        ph_b[i] += vb * wu[j];
+        An[(size_t)(i * Q + j) * N + n] = vb * (T(1) - itf);
+        if (j == 0) {
+          ph_b[i] += vb * itf;
+          mu_b[i] -= vb * itf * (T(1) - wgt<T>(0));
+        } else {
+          const T wv = vb * itf * wgt<T>(j);
+          ph_b[i] += wv * T(3) * (T(cx(j)) * ux + T(cy(j)) * uy);
+          ux_b += wv * T(3) * ph[i] * T(cx(j));
+          uy_b += wv * T(3) * ph[i] * T(cy(j));
+          mu_b[i] += wv;
+        }
+        dtx_b += cf * vb * wgt<T>(j) * T(cx(j));
+        dty_b += cf * vb * wgt<T>(j) * T(cy(j));
+      }
+      dpx_b = T(3) * dtx_b;
+      dpy_b = T(3) * dty_b;
+      // X_i = sum_{k != i} M_ik grad mu_k + (M_ii - m0) grad mu_i (Eq. 28)
+      const T Xx_b = -dtx_b / m0, Xy_b = -dty_b / m0;
+      T mii = 0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if (k != i) mii += m0 * ph[i] * ph[k];
+      const T si = Xx_b * gmx[i] + Xy_b * gmy[i];
+      gmx_b[i] += (mii - m0) * Xx_b;
+      gmy_b[i] += (mii - m0) * Xy_b;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if (k != i) {
+          const T sk = Xx_b * gmx[k] + Xy_b * gmy[k];
+          gmx_b[k] -= m0 * ph[i] * ph[k] * Xx_b;
+          gmy_b[k] -= m0 * ph[i] * ph[k] * Xy_b;
+          ph_b[i] += m0 * ph[k] * (si - sk);
+          ph_b[k] += m0 * ph[i] * (si - sk);
+        }
+    } else {
+#pragma unroll
+      for (int j = 0; j < Q; ++j) An[(size_t)(i * Q + j) * N + n] = T(0);
+    }
+    // dp = phi_i u - (phi_i u)_prev; (phi_i u) is also the history output
+    ph_b[i] += (dpx_b + hx) * ux + (dpy_b + hy) * uy;
+    ux_b += ph[i] * (dpx_b + hx);
+    uy_b += ph[i] * (dpy_b + hy);
+    An[(size_t)(AO_HPU + 2 * i) * N + n] = -dpx_b;
+    An[(size_t)(AO_HPU + 2 * i + 1) * N + n] = -dpy_b;
+  }
+
+  // ---- flow moments (Eq. 41)
+  {
+    const T c3 = T(1) / (T(3) * (T(1) - wgt<T>(0)));
+    const T s1_b = pp_b * c3, udr_b = T(0.5) * pp_b * c3;
+    rho_b += s0 * pp_b * c3;
+    const T usq_b = rho * pp_b * c3 * wgt<T>(0) * T(-1.5);
+    ux_b += T(2) * ux * usq_b + udr_b * grx;
+    uy_b += T(2) * uy * usq_b + udr_b * gry;
+    grx_b += udr_b * ux;
+    gry_b += udr_b * uy;
+    const T mx_b = ux_b / rho, my_b = uy_b / rho;
+    Fx_b += T(0.5) * mx_b;
+    Fy_b += T(0.5) * my_b;
+    rho_b -= (ux_b * ux + uy_b * uy) / rho;
+#pragma unroll
+    for (int j = 0; j < Q; ++j)
+      An[(size_t)(AO_G + j) * N + n] = g_b[j] + T(cx(j)) * mx_b + T(cy(j)) * my_b + (j ? s1_b : T(0));
+  }
+
+  // ---- force -sum phi_i grad mu_i + q E (Eq. 27b) and rho of Eq. (29)
+  q_b += Fx_b * ex + Fy_b * ey;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    ph_b[i] -= Fx_b * gmx[i] + Fy_b * gmy[i] - P.rho[i] * rho_b;
+    gmx_b[i] -= ph[i] * Fx_b;
+    gmy_b[i] -= ph[i] * Fy_b;
+    PBn[(size_t)i * N + n] = ph_b[i];
+    ab.muL[(size_t)i * N + n] = mu_b[i];
+    ab.gm[(size_t)(2 * i) * N + n] = gmx_b[i];
+    ab.gm[(size_t)(2 * i + 1) * N + n] = gmy_b[i];
+  }
+  ab.gr[n] = grx_b;
+  ab.gr[(size_t)N + n] = gry_b;
+  ab.qb[n] = q_b;
+  ab.rb[n] = R_b;
+  ab.en[n] = q * Fx_b;
+  ab.en[(size_t)N + n] = q * Fy_b;
+}
+
+// Adjoint of the chemical-potential kernel (Eq. 20 and the field of
+// Eq. 45).  with_step: the collide adjoint ran (its grad-mu-bar,
+// grad-rho-bar and field-bar are added); at create only the local mu-bar
+// and the state's field-bar are there.  Adds grad(h)-terms to hb[hsel] in
+// place and starts eps-bar.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_adj_mu(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
+                                               Rec<T> rc, AdjBufs<T> ab, int cur, int hsel, int with_step) {
+  const Inst *Ip;
+  int lblk;
+  const Node nd = locate(insts, b2i, Ip, lblk);
+  const Inst &I = *Ip;
+  double th[TB_SLOTS] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (nd.valid) {
+    const Phys<T> &P = phys<T>(I);
+    const int N = I.N, n = nd.n;
+    T mu_b[3], ph_b[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) mu_b[i] = ab.muL[(size_t)i * N + n];
+    T ex_b = ab.a[cur][(size_t)AO_E * N + n], ey_b = ab.a[cur][(size_t)(AO_E + 1) * N + n];
+    if (with_step) {
+      T gr_t = 0;
+      for_sources(I, nd.x, nd.y, [&](int j, int s) {
+        const T w3 = T(3) * wgt<T>(j);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          mu_b[i] += w3 * (T(cx(j)) * ab.gm[(size_t)(2 * i) * N + s] + T(cy(j)) * ab.gm[(size_t)(2 * i + 1) * N + s]);
+        gr_t += w3 * (T(cx(j)) * ab.gr[s] + T(cy(j)) * ab.gr[(size_t)N + s]);
+      });
+#pragma unroll
+      for (int i = 0; i < 3; ++i) ph_b[i] += P.rho[i] * gr_t;
+      ex_b += ab.en[n];
+      ey_b += ab.en[(size_t)N + n];
+    }
+    const T Ex = rc.En[n], Ey = rc.En[(size_t)N + n];
+    const T e2 = Ex * Ex + Ey * Ey;
+    T e2_b = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const T ph = rc.phi[(size_t)i * N + n];
+      ph_b[i] += mu_b[i] * T(24) / P.D * P.lam[i] * (T(3) * ph * ph - T(3) * ph + T(0.5));
+      ab.lb[(size_t)i * N + n] = -mu_b[i] * T(0.75) * P.D * P.lam[i];
+      ph_b[i] -= mu_b[i] * T(3) * P.eps[i] * (T(1) - T(2) * ph) * e2;
+      e2_b -= mu_b[i] * T(3) * P.eps[i] * ph * (T(1) - ph);
+      th[i] -= (double)(mu_b[i] * T(3) * ph * (T(1) - ph) * e2);
+    }
+    ex_b += T(2) * Ex * e2_b;
+    ey_b += T(2) * Ey * e2_b;
+    th[6] += (double)ex_b * ab.dEext[0] + (double)ey_b * ab.dEext[1];
+    // E = m / den + E_ext with m the first moment of the final h
+    const T den = (rc.eps[n] - P.eps_ref) + P.tau_h / T(3);
+    const T mx = (Ex - P.Eext[0]) * den, my = (Ey - P.Eext[1]) * den;
+    const T mx_b = ex_b / den, my_b = ey_b / den;
+    ab.eb[n] = -(ex_b * mx + ey_b * my) / (den * den);
+    T *hb = ab.hb[hsel];
+#pragma unroll
+    for (int j = 1; j < Q; ++j) hb[(size_t)j * N + n] += T(cx(j)) * mx_b + T(cy(j)) * my_b;
+    T *PBn = ab.pb[cur ^ 1];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) PBn[(size_t)i * N + n] += ph_b[i];
+  }
+  add_theta(I, ab.tb, lblk, th);
+}
+
+// Local part of the adjoint of one potential sub-iteration at a node: vb
+// is the adjoint of the node's post-collision populations (already pulled
+// through the push), h its forward input; returns the adjoint of h and adds
+// to eps_hat-bar and q-bar.
+template <typename T>
+__device__ __forceinline__ void adj_poisson_local(const T (&vb)[Q], const T (&h)[Q], T eh, const Phys<T> &P,
+                                                  T (&hb)[Q], T &eh_b, T &q_b) {
+  T mx = 0, my = 0;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    mx += T(cx(j)) * h[j];
+    my += T(cy(j)) * h[j];
+  }
+  const T den = eh + P.tau_h / T(3);
+  const T gx = -mx / den, gy = -my / den;
+  const T ith = T(1) / P.tau_h;
+  T pot_b = 0, gx_b = 0, gy_b = 0;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    pot_b += vb[j] * ith * (j == 0 ? wgt<T>(0) - T(1) : wgt<T>(j));
+    const T c3 = vb[j] * T(3) * wgt<T>(j) * ith;
+    gx_b -= c3 * eh * T(cx(j));
+    gy_b -= c3 * eh * T(cy(j));
+    eh_b -= c3 * (T(cx(j)) * gx + T(cy(j)) * gy);
+    if (j) q_b += T(0.125) * vb[j];
+  }
+  const T mx_b = -gx_b / den, my_b = -gy_b / den;
+  eh_b += (gx_b * mx + gy_b * my) / (den * den);
+  const T ps_b = pot_b / (T(1) - wgt<T>(0));
+#pragma unroll
+  for (int j = 0; j < Q; ++j) hb[j] = vb[j] * (T(1) - ith) + T(cx(j)) * mx_b + T(cy(j)) * my_b + (j ? ps_b : T(0));
+}
+
+// Adjoint of one potential sub-iteration (Eqs. 43-45 with anti-bounce-back
+// electrodes): hb[src] holds the adjoint of the output level, h_in the
+// forward input level; writes the adjoint of the input level to hb[src ^ 1]
+// and adds to eps-bar and q-bar (qb may alias a scratch plane).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_adj_poisson(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
+                                                    const T *__restrict__ h_in, const T *__restrict__ eps,
+                                                    AdjBufs<T> ab, int src, T *qb) {
+  const Inst *Ip;
+  int lblk;
+  const Node nd = locate(insts, b2i, Ip, lblk);
+  const Inst &I = *Ip;
+  double th[TB_SLOTS] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (nd.valid) {
+    const Phys<T> &P = phys<T>(I);
+    const int N = I.N, n = nd.n;
+    const T *Hs = ab.hb[src];
+    T vb[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      size_t slot;
+      int dn;
+      bool top;
+      const bool in = push_slot(I, nd.x, nd.y, n, j, slot, dn, top);
+      const T a = Hs[slot];
+      if (in) {
+        vb[j] = a;
+      } else {
+        vb[j] = -a;
+        th[6] += 2.0 * (double)(wgt<T>(j) * a) * ab.dwall[top ? 1 : 0];
+      }
+    }
+    T h[Q], hb[Q], eh_b = 0, q_b = 0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) h[j] = h_in[(size_t)j * N + n];
+    adj_poisson_local(vb, h, eps[n] - P.eps_ref, P, hb, eh_b, q_b);
+    T *Hd = ab.hb[src ^ 1];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) Hd[(size_t)j * N + n] = hb[j];
+    ab.eb[n] += eh_b;
+    qb[n] += q_b;
+  }
+  // only blocks holding a wall row carry a d/d E0 term (uniform per block)
+  if (I.bc_y && (lblk * NT < I.nx || (lblk + 1) * NT > (I.ny - 1) * I.nx)) add_theta(I, ab.tb, lblk, th);
+}
+
+// Adjoints of two potential sub-iterations in one launch, the transpose of
+// k_poisson2: a block owns the same tiles, loads the adjoint of the output
+// level for the extended tile into LDS, pulls and transforms it on the ring
+// of width 1 (forward input level h1 there), writes that level back to LDS,
+// pulls and transforms it on the interior (input level h0) and writes the
+// adjoint of h0 to hb[src ^ 1].  eps-bar and q-bar of both iterations are
+// added on the interior; wall tiles add their d/d E0 terms to slot
+// blockIdx.x of tb.
+template <typename T>
+__global__ __launch_bounds__(P2NT) void k_adj_poisson2(const Inst *__restrict__ insts, const int4 *__restrict__ tiles,
+                                                      const T *__restrict__ h1, const T *__restrict__ h0,
+                                                      const T *__restrict__ eps, AdjBufs<T> ab, int src, T *qb) {
+  __shared__ T buf[Q * P2EW * P2ER];
+  __shared__ double red[P2NT / 64];
+  const int4 t = tiles[blockIdx.x];
+  const Inst &I = insts[t.x];
+  const Phys<T> &P = phys<T>(I);
+  const int nx = I.nx, ny = I.ny, N = I.N, walls = I.bc_y;
+  const int tx = threadIdx.x & 63, r = threadIdx.x >> 6;  // one extended node per thread (P2RPT == 1)
+  const int gx = wrapx(((t.y - 2 + tx) % nx + nx) % nx, nx);
+  int gy = t.z - 2 + r;
+  bool inside = true;
+  if (walls) inside = gy >= 0 && gy < ny;
+  else gy = ((gy % ny) + ny) % ny;
+  const int n = gy * nx + gx;
+  const int e = r * P2EW + tx;
+  const T *Hs = ab.hb[src];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) buf[j * (P2EW * P2ER) + e] = inside ? Hs[(size_t)j * N + n] : T(0);
+  __syncthreads();
+  const bool ring1 = inside && r >= 1 && r < P2ER - 1 && tx >= 1 && tx < P2EW - 1;
+  const bool interior = inside && r >= 2 && r < 2 + P2H && tx >= 2 && tx < 2 + P2W && t.y + tx - 2 < nx &&
+                        t.z + r - 2 < ny;
+  double th = 0.0;
+  T eh_b = 0, q_b = 0;
+  const T eh = ring1 ? eps[n] - P.eps_ref : T(0);
+  // pull of the adjoint through the push of node (r, tx); wall slots at the node itself
+  auto pull = [&](T (&vb)[Q]) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const int yd = gy + cy(j);
+      if (walls && (yd < 0 || yd >= ny)) {
+        const T a = buf[opp(j) * (P2EW * P2ER) + e];
+        vb[j] = -a;
+        if (interior) th += 2.0 * (double)(wgt<T>(j) * a) * ab.dwall[yd >= ny ? 1 : 0];
+      } else {
+        vb[j] = buf[j * (P2EW * P2ER) + e + cy(j) * P2EW + cx(j)];
+      }
+    }
+  };
+  T hb[Q];
+  if (ring1) {
+    T vb[Q], h[Q];
+    pull(vb);
+#pragma unroll
+    for (int j = 0; j < Q; ++j) h[j] = h1[(size_t)j * N + n];
+    T eb1 = 0, qb1 = 0;
+    adj_poisson_local(vb, h, eh, P, hb, eb1, qb1);
+    if (interior) {
+      eh_b += eb1;
+      q_b += qb1;
+    }
+  }
+  __syncthreads();
+  if (ring1)
+#pragma unroll
+    for (int j = 0; j < Q; ++j) buf[j * (P2EW * P2ER) + e] = hb[j];
+  __syncthreads();
+  if (interior) {
+    T vb[Q], h[Q];
+    pull(vb);
+#pragma unroll
+    for (int j = 0; j < Q; ++j) h[j] = h0[(size_t)j * N + n];
+    adj_poisson_local(vb, h, eh, P, hb, eh_b, q_b);
+    T *Hd = ab.hb[src ^ 1];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) Hd[(size_t)j * N + n] = hb[j];
+    ab.eb[n] += eh_b;
+    qb[n] += q_b;
+  }
+  if (walls && (t.z == 0 || t.z + P2H >= ny)) {
+    for (int o = 32; o > 0; o >>= 1) th += __shfl_down(th, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = th;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0;
+      for (int w = 0; w < P2NT / 64; ++w) s += red[w];
+      ab.tb[(size_t)blockIdx.x * TB_SLOTS + 6] += s;
+    }
+  }
+}
+
+// Adjoint of charge recovery (Eq. 47 with the previous step's field) and of
+// the permittivity field; gathers the Laplacian-bar of the mu adjoint.
+// Writes the lsum-bar, the previous field's adjoint (state), and the
+// gradient-bars of eps and sigma for the last kernel.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_adj_pre(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
+                                                Rec<T> rc, AdjBufs<T> ab, int cur) {
+  const Inst *Ip;
+  int lblk;
+  const Node nd = locate(insts, b2i, Ip, lblk);
+  const Inst &I = *Ip;
+  double th[TB_SLOTS] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (nd.valid) {
+    const Phys<T> &P = phys<T>(I);
+    const int N = I.N, nx = I.nx, n = nd.n;
+    T ph_b[3] = {T(0), T(0), T(0)};
+    // transpose of the Laplacian in mu: 6 sum_j w_j v(m + c_j) - 6 v(m)
+    for_sources(I, nd.x, nd.y, [&](int j, int s) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) ph_b[i] += T(6) * wgt<T>(j) * ab.lb[(size_t)i * N + s];
+    });
+#pragma unroll
+    for (int i = 0; i < 3; ++i) ph_b[i] -= T(6) * ab.lb[(size_t)i * N + n];
+    // forward values
+    T ev[Q], sv[Q], ph[3];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const int m = fdrow(nd.y + cy(j), I.ny, I.bc_y) * nx + wrapx(nd.x + cx(j), nx);
+      const T p1 = rc.phi[m], p2 = rc.phi[(size_t)N + m], p3 = rc.phi[(size_t)2 * N + m];
+      ev[j] = P.eps[0] * herm(p1) + P.eps[1] * herm(p2) + P.eps[2] * herm(p3);
+      sv[j] = P.sig[0] * p1 + P.sig[1] * p2 + P.sig[2] * p3;
+      if (j == 0) {
+        ph[0] = p1;
+        ph[1] = p2;
+        ph[2] = p3;
+      }
+    }
+    T gex, gey, gsx, gsy, dummy;
+    fd9(ev, gex, gey, dummy);
+    fd9(sv, gsx, gsy, dummy);
+    const T ex = rc.Eo[n], ey = rc.Eo[(size_t)N + n];
+    const T se = sv[0] / ev[0];
+    const T B = T(1) + T(0.5) * se;
+    const T q = rc.q[n];
+    // adjoints
+    const T R_b = ab.rb[n];
+    T q_b = ab.qb[n] - se * R_b;
+    T se_b = -q * R_b;
+    T Rp_b = R_b;
+    const T A_b = q_b / B, B_b = -q_b * q / B;
+    const T Ls_b = A_b;
+    Rp_b += T(0.5) * A_b;
+    se_b += T(0.5) * B_b;
+    se_b += Rp_b * (gex * ex + gey * ey);
+    const T gex_b = Rp_b * se * ex, gey_b = Rp_b * se * ey;
+    const T gsx_b = -Rp_b * ex, gsy_b = -Rp_b * ey;
+    const T ex_b = Rp_b * (se * gex - gsx), ey_b = Rp_b * (se * gey - gsy);
+    const T sv_b = se_b / ev[0];
+    const T ev_b = -se_b * se / ev[0] + ab.eb[n];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      ph_b[i] += ev_b * P.eps[i] * T(6) * ph[i] * (T(1) - ph[i]) + sv_b * P.sig[i];
+      th[i] += (double)(ev_b * herm(ph[i]));
+      th[3 + i] += (double)(sv_b * ph[i]);
+    }
+    T *PBn = ab.pb[cur ^ 1];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) PBn[(size_t)i * N + n] += ph_b[i];
+    PBn[(size_t)3 * N + n] = Ls_b;
+    T *An = ab.a[cur ^ 1];
+    An[(size_t)AO_E * N + n] = ex_b;
+    An[(size_t)(AO_E + 1) * N + n] = ey_b;
+    ab.ge[n] = gex_b;
+    ab.ge[(size_t)N + n] = gey_b;
+    ab.gs[n] = gsx_b;
+    ab.gs[(size_t)N + n] = gsy_b;
+  }
+  add_theta(I, ab.tb, lblk, th);
+}
+
+// Last kernel of a step's adjoint: transposes the eps and sigma gradient
+// stencils of the charge-recovery kernel onto phi-bar.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_adj_phi(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
+                                                Rec<T> rc, AdjBufs<T> ab, int cur) {
+  const Inst *Ip;
+  int lblk;
+  const Node nd = locate(insts, b2i, Ip, lblk);
+  const Inst &I = *Ip;
+  double th[TB_SLOTS] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (nd.valid) {
+    const Phys<T> &P = phys<T>(I);
+    const int N = I.N, n = nd.n;
+    T te = 0, ts = 0;
+    for_sources(I, nd.x, nd.y, [&](int j, int s) {
+      const T w3 = T(3) * wgt<T>(j);
+      te += w3 * (T(cx(j)) * ab.ge[s] + T(cy(j)) * ab.ge[(size_t)N + s]);
+      ts += w3 * (T(cx(j)) * ab.gs[s] + T(cy(j)) * ab.gs[(size_t)N + s]);
+    });
+    T *PBn = ab.pb[cur ^ 1];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const T ph = rc.phi[(size_t)i * N + n];
+      PBn[(size_t)i * N + n] += te * P.eps[i] * T(6) * ph * (T(1) - ph) + ts * P.sig[i];
+      th[i] += (double)(te * herm(ph));
+      th[3 + i] += (double)(ts * ph);
+    }
+  }
+  add_theta(I, ab.tb, lblk, th);
+}
+
+// Seed of the sweep: phi-bar of the last step's moments from the FP64
+// seed planes (plane k belongs to phase sel[k]).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_adj_seed(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
+                                                 const double *__restrict__ seed, int3 sel, int count, T *pb) {
+  const Inst *Ip;
+  int lblk;
+  const Node nd = locate(insts, b2i, Ip, lblk);
+  if (!nd.valid) return;
+  const int N = Ip->N, n = nd.n;
+  const int s[3] = {sel.x, sel.y, sel.z};
+  for (int k = 0; k < count; ++k) pb[(size_t)s[k] * N + n] += (T)seed[(size_t)k * N + n];
+}
+
+// Create-time populations are the equilibria of the initial fields (Eq. 35):
+// their adjoint reaches mu only.  The state's f-bar is the stored part plus
+// the moments part phi-bar.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_adj_init_pops(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
+                                                      AdjBufs<T> ab, int cur) {
+  const Inst *Ip;
+  int lblk;
+  const Node nd = locate(insts, b2i, Ip, lblk);
+  if (!nd.valid) return;
+  const int N = Ip->N, n = nd.n;
+  const T *A = ab.a[cur];
+  const T *PB = ab.pb[cur];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const T pb = PB[(size_t)i * N + n];
+    T mb = -(T(1) - wgt<T>(0)) * (A[(size_t)(i * Q) * N + n] + pb);
+#pragma unroll
+    for (int j = 1; j < Q; ++j) mb += wgt<T>(j) * (A[(size_t)(i * Q + j) * N + n] + pb);
+    ab.muL[(size_t)i * N + n] = Ip->phase_mode == 0 ? mb : T(0);
+  }
+}
+
+// One potential sub-iteration on explicit buffers (the cold start of
+// create, recomputed during the sweep): same collision and push as the
+// forward potential kernels.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_poisson_buf(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
+                                                    const T *__restrict__ src, T *__restrict__ dst,
+                                                    const T *__restrict__ eps, const T *__restrict__ q,
+                                                    T *rec_in) {
+  const Inst *Ip;
+  int lblk;
+  const Node nd = locate(insts, b2i, Ip, lblk);
+  if (!nd.valid) return;
+  const Inst &I = *Ip;
+  const Phys<T> &P = phys<T>(I);
+  const int N = I.N, n = nd.n;
+  T h[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) h[j] = src[(size_t)j * N + n];
+  if (rec_in)
+#pragma unroll
+    for (int j = 0; j < Q; ++j) rec_in[(size_t)j * N + n] = h[j];
+  T v[Q];
+  poisson_collide(h, eps[n] - P.eps_ref, q[n], P, v);
+  push<T, T>(dst, v, I, nd.x, nd.y, n, 1, T(0), T(0), T(0), P.wall_phi[0], P.wall_phi[1], T(1), false);
+}
+
+// Equilibrium potential populations of a potential plane (Eq. 44), the
+// cold start's first level.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_h_equilibrium(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
+                                                      const T *__restrict__ psi, T *__restrict__ h) {
+  const Inst *Ip;
+  int lblk;
+  const Node nd = locate(insts, b2i, Ip, lblk);
+  if (!nd.valid) return;
+  const int N = Ip->N, n = nd.n;
+  const T v = psi[n];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) h[(size_t)j * N + n] = j == 0 ? (wgt<T>(0) - T(1)) * v : wgt<T>(j) * v;
+}
+
+// End of the sweep: the initial potential guess and the create-time
+// permittivity.  psi0_b = adjoint of the equilibrium h of psi0 (d/d E0 via
+// (psi0 - mean) / E0); eps-bar of create reaches eps_i through Eq. (30).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_adj_create_tail(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
+                                                        AdjBufs<T> ab, int hsel, const T *__restrict__ phi0,
+                                                        const T *__restrict__ psi0, double mean, double inv_e0) {
+  const Inst *Ip;
+  int lblk;
+  const Node nd = locate(insts, b2i, Ip, lblk);
+  const Inst &I = *Ip;
+  double th[TB_SLOTS] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (nd.valid) {
+    const int N = I.N, n = nd.n;
+    const T *hb = ab.hb[hsel];
+    T pb = (wgt<T>(0) - T(1)) * hb[n];
+#pragma unroll
+    for (int j = 1; j < Q; ++j) pb += wgt<T>(j) * hb[(size_t)j * N + n];
+    th[6] += (double)pb * ((double)psi0[n] - mean) * inv_e0;
+    const T eb = ab.eb[n];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) th[i] += (double)(eb * herm(phi0[(size_t)i * N + n]));
+  }
+  add_theta(I, ab.tb, lblk, th);
+}
+
+// Sum of the per-block parameter adjoints (one block, fixed order).
+__global__ __launch_bounds__(NT) void k_adj_reduce(const double *__restrict__ tb, int nblk, double *__restrict__ out) {
+  double v[TB_SLOTS];
+  reduce_partials<TB_SLOTS>(tb, nblk, v);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < TB_SLOTS; ++k) out[k] = v[k];
+}
+
+}  // namespace lbm

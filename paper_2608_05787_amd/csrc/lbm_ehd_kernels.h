@@ -129,6 +129,16 @@ struct Node {
   bool valid;
 };
 
+// Forward values that the reverse (adjoint) sweep needs from one step, as
+// written by the step's own kernels when the pointers are set (recording
+// runs); null in ordinary steps.  Planes of N values each: phi 3, q, R, eps,
+// E of the previous step 2, mu 3, E of this step 2, the pre-collision flow
+// populations 9; the potential populations of each sub-iteration's input
+// level go to the separate pointers of the potential kernels.
+template <typename T> struct Rec {
+  T *phi, *q, *R, *eps, *Eo, *mu, *En, *g;
+};
+
 // The block table maps each launched block to (instance, block within the
 // instance).  The host orders it so that the blocks one XCD receives
 // (consecutive block ids go round-robin over the 8 XCDs) cover a contiguous
@@ -251,7 +261,7 @@ __device__ __forceinline__ T push(S *__restrict__ dst, const T (&v)[Q], const In
 // sum; resets the per-step potential control words.
 template <typename T, typename S>
 __global__ __launch_bounds__(NT) void k_moments(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
-                                                int pc) {
+                                                int pc, Rec<T> rc = Rec<T>{}) {
   const Inst *Ip;
   int lblk;
   const Node nd = locate(insts, b2i, Ip, lblk);
@@ -273,6 +283,7 @@ __global__ __launch_bounds__(NT) void k_moments(const Inst *__restrict__ insts, 
 #pragma unroll
     for (int j = IO::split ? 1 : 0; j < Q; ++j) a += IO::ld(f, (size_t)(i * Q + j) * N + n, T(SC_F));
     phi[(size_t)i * N + n] = a;
+    if (rc.phi) rc.phi[(size_t)i * N + n] = a;
   }
   T b = 0;
 #pragma unroll
@@ -284,7 +295,8 @@ __global__ __launch_bounds__(NT) void k_moments(const Inst *__restrict__ insts, 
 // fields of Eqs. 29-30), charge recovery q = (sum l + R'/2)/(1 + sigma/(2 eps))
 // and the Ohmic source R of Eq. (47) with the previous step's field.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, const int2 *__restrict__ b2i) {
+__global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
+                                            Rec<T> rc = Rec<T>{}) {
   const Inst *Ip;
   int lblk;
   const Node nd = locate(insts, b2i, Ip, lblk);
@@ -312,6 +324,13 @@ __global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, cons
   ((T *)I.q)[n] = q;
   ((T *)I.R)[n] = -se * q + Rp;
   ((T *)I.eps)[n] = ev[0];
+  if (rc.q) {
+    rc.q[n] = q;
+    rc.R[n] = -se * q + Rp;
+    rc.eps[n] = ev[0];
+    rc.Eo[n] = ex;
+    rc.Eo[(size_t)N + n] = ey;
+  }
 }
 
 // Potential LB at one node (Eqs. 43-45): potential and gradient from the
@@ -350,9 +369,10 @@ __device__ __forceinline__ T poisson_collide(const T (&h)[Q], T epshat, T q, con
 //   Adaptive: skipped once the loop has converged; stores the potential of
 //   its input and, from k = 2 on, the residual partials of the previous
 //   iteration for k_reduce_poisson.
+//   rec_in: when set, receives the input level (recording runs).
 template <typename T>
 __global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
-                                                int k, int K, int adaptive, int hpar) {
+                                                int k, int K, int adaptive, int hpar, T *rec_in = nullptr) {
   const Inst *Ip;
   int lblk;
   const Node nd = locate(insts, b2i, Ip, lblk);
@@ -371,6 +391,9 @@ __global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, 
     T h[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) h[j] = src[(size_t)j * N + n];
+    if (rec_in)
+#pragma unroll
+      for (int j = 0; j < Q; ++j) rec_in[(size_t)j * N + n] = h[j];
     const T epshat = ((const T *)I.eps)[n] - P.eps_ref;
     const T q = ((const T *)I.q)[n];
     T v[Q];
@@ -409,9 +432,12 @@ __global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, 
 constexpr int P2NT = 1024;  // threads per block of the two-iteration kernel (one node each)
 constexpr int P2EW = 64, P2ER = 16, P2W = P2EW - 4, P2H = P2ER - 4, P2RPT = P2ER / (P2NT / 64);
 
+//   rec_in, rec_mid: when set, receive the input level and the level after
+//   the first sub-iteration (recording runs).
 template <typename T>
 __global__ __launch_bounds__(P2NT) void k_poisson2(const Inst *__restrict__ insts, const int4 *__restrict__ tiles,
-                                                 int hpar, int write_psi) {
+                                                 int hpar, int write_psi, T *rec_in = nullptr,
+                                                 T *rec_mid = nullptr) {
   __shared__ T buf[Q * P2EW * P2ER];
   const int4 t = tiles[blockIdx.x];
   const Inst &I = insts[t.x];
@@ -447,6 +473,22 @@ __global__ __launch_bounds__(P2NT) void k_poisson2(const Inst *__restrict__ inst
       qq[k] = T(0);
     }
   }
+  // interior node of this tile (the nodes the launch writes)
+  auto interior = [&](int k, int &n) {
+    const int r = ty + (P2NT / 64) * k;
+    if (r < 2 || r >= 2 + P2H || tx < 2 || tx >= 2 + P2W || !inside[k]) return false;
+    if (t.y + tx - 2 >= nx || t.z + r - 2 >= ny) return false;
+    n = gy[k] * nx + gx;
+    return true;
+  };
+  if (rec_in)
+#pragma unroll
+    for (int k = 0; k < P2RPT; ++k) {
+      int n;
+      if (interior(k, n))
+#pragma unroll
+        for (int j = 0; j < Q; ++j) rec_in[(size_t)j * N + n] = h[k][j];
+    }
   for (int it = 0; it < 2; ++it) {
     // collide every node this iteration can still use, post values to LDS
 #pragma unroll
@@ -478,6 +520,14 @@ __global__ __launch_bounds__(P2NT) void k_poisson2(const Inst *__restrict__ inst
       }
     }
     __syncthreads();
+    if (it == 0 && rec_mid)
+#pragma unroll
+      for (int k = 0; k < P2RPT; ++k) {
+        int n;
+        if (interior(k, n))
+#pragma unroll
+          for (int j = 0; j < Q; ++j) rec_mid[(size_t)j * N + n] = h[k][j];
+      }
   }
   // interior pre-collision values of the next level
 #pragma unroll
@@ -521,7 +571,7 @@ __global__ __launch_bounds__(NT) void k_reduce_poisson(const Inst *__restrict__ 
 //   flipped it).
 template <typename T>
 __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
-                                           int hofs) {
+                                           int hofs, Rec<T> rc = Rec<T>{}) {
   const Inst *Ip;
   int lblk;
   const Node nd = locate(insts, b2i, Ip, lblk);
@@ -552,6 +602,10 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
     T *E = (T *)I.E;
     E[n] = ex;
     E[(size_t)N + n] = ey;
+    if (rc.En) {
+      rc.En[n] = ex;
+      rc.En[(size_t)N + n] = ey;
+    }
     const T e2 = ex * ex + ey * ey;
     const T *phi = (const T *)I.phi;
     T *mu = (T *)I.mu;
@@ -570,6 +624,7 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
       const T grad = T(0.75) * P.D * P.lam[i] * lap;
       const T elec = T(0.5) * (T(6) * P.eps[i] * ph * (T(1) - ph)) * e2;
       mu[(size_t)i * N + n] = bulk - grad - elec;
+      if (rc.mu) rc.mu[(size_t)i * N + n] = bulk - grad - elec;
     }
   }
   block_sum<2>(red);
@@ -589,7 +644,8 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
 //   ctl->hcur (no other kernel of the step reads it any more).
 template <typename T, typename S>
 __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
-                                                int pc, int write_macro, int fixedK, int hflip) {
+                                                int pc, int write_macro, int fixedK, int hflip,
+                                                Rec<T> rc = Rec<T>{}) {
   const Inst *Ip;
   int lblk;
   const Node nd = locate(insts, b2i, Ip, lblk);
@@ -652,6 +708,9 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
     T g[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) g[j] = IO::ld(gs, (size_t)j * N + n, T(SC_G));
+    if (rc.g)
+#pragma unroll
+      for (int j = 0; j < Q; ++j) rc.g[(size_t)j * N + n] = g[j];
     T mxg = 0, myg = 0, s1 = 0;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {

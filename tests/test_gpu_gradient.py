@@ -1,7 +1,10 @@
 """Gradients with respect to theta = (eps2/eps1, eps3/eps1, sigma2/sigma1,
-sigma3/sigma1, E0) from lbm_ehd_adjoint (forward-mode tangent runs of the
-same kernels in FP64), checked against central finite differences of the FP64
-GPU run and of the FP64 CPU oracle (relative step 1e-3), and through the
+sigma3/sigma1, E0).  Forward mode (lbm_ehd_tangent_gradient: tangent runs of
+the same kernels in FP64) is checked against central finite differences of
+the FP64 GPU run and of the FP64 CPU oracle (relative step 1e-3).  Reverse
+mode (lbm_ehd_record + lbm_ehd_adjoint: the discrete adjoint of the step and
+of create) is checked against forward mode to rounding in FP64, against the
+oracle's finite differences, in FP32 against FP64, and through the
 torch.autograd.Function on a deformation objective."""
 import numpy as np
 import pytest
@@ -59,9 +62,14 @@ def check(g, ref, rel=1e-4):
     assert np.all(np.abs(g - ref) <= tol), (g, ref, np.abs(g - ref) / np.abs(ref))
 
 
-def tangent_grad(cfg, init, seed):
+def tangent_grad(cfg, init, seed, steps=STEPS):
     sim = binding.Sim(cfg, init, precision="fp64")
-    return sim.adjoint(STEPS, {k: torch.from_numpy(v) for k, v in seed.items()})
+    return sim.tangent_gradient(steps, {k: torch.from_numpy(v) for k, v in seed.items()})
+
+
+def reverse_grad(cfg, init, seed, steps=STEPS, every=16, precision="fp64"):
+    sim = binding.Sim(cfg, init, precision=precision)
+    return sim.adjoint(steps, {k: torch.from_numpy(v) for k, v in seed.items()}, every)
 
 
 def test_tangent_gradient_matches_fd_of_gpu_fp64():
@@ -80,6 +88,73 @@ def test_tangent_gradient_matches_fd_of_oracle():
     cfg, init = small_case()
     seed = seeds((cfg["ny"], cfg["nx"]), ["phi2", "Ey", "uy"], seed=1)
     check(tangent_grad(cfg, init, seed), fd(J_oracle, cfg, init, seed))
+
+
+def reverse_cases():
+    drop = inputs.field_compound_drop(48, r_shell=12.0, r_core=7.0, ca_e=0.4, init_iters=9,
+                                      init_tol=0.0, sub=(2, 2, 0.0))
+    shear = inputs.field_compound_drop(40, r_shell=12.0, r_core=7.0, ca_e=0.4, init_iters=5,
+                                       init_tol=0.0, sub=(3, 3, 0.0), wall_u=0.01)
+    periodic = inputs.parity_case(37, 29, seed=4, walls=False, sub=(1, 1, 0.0))
+    return {"drop": (drop, 23, 5), "shear": (shear, 9, 4), "periodic": (periodic, 7, 3)}
+
+
+@pytest.mark.parametrize("name", ["drop", "shear", "periodic"])
+def test_reverse_matches_tangent_fp64(name):
+    """The discrete adjoint equals forward mode to rounding: walls with
+    electrodes and a shear start, a periodic box with an applied field,
+    1-3 sub-iterations, a cold start, several checkpoint segments."""
+    print("case reverse vs tangent", name, flush=True)
+    (cfg, init), steps, every = reverse_cases()[name]
+    seed = seeds((cfg["ny"], cfg["nx"]), ["phi1", "phi2", "phi3"], seed=3)
+    gt = np.array(tangent_grad(cfg, init, seed, steps))
+    gr = np.array(reverse_grad(cfg, init, seed, steps, every))
+    assert np.all(np.abs(gr - gt) <= 1e-10 * np.abs(gt) + 1e-12 * np.abs(gt).max()), (gr, gt)
+
+
+def test_reverse_matches_fd_of_oracle():
+    print("case reverse vs oracle fd", flush=True)
+    cfg, init = small_case()
+    seed = seeds((cfg["ny"], cfg["nx"]), ["phi1", "phi3"], seed=2)
+    check(reverse_grad(cfg, init, seed), fd(J_oracle, cfg, init, seed))
+
+
+def test_reverse_fp32_against_fp64():
+    """The FP32 sweep over an FP32 run against the FP64 gradient."""
+    print("case reverse fp32", flush=True)
+    cfg, init = small_case()
+    seed = seeds((cfg["ny"], cfg["nx"]), ["phi1", "phi2", "phi3"], seed=5)
+    g64 = np.array(reverse_grad(cfg, init, seed))
+    g32 = np.array(reverse_grad(cfg, init, seed, precision="fp32"))
+    assert np.all(np.abs(g32 - g64) <= 1e-3 * np.abs(g64) + 1e-5 * np.abs(g64).max()), (g32, g64)
+
+
+def test_record_matches_step_and_is_reused():
+    """record() advances the handle exactly like step(); the adjoint over
+    that recording equals the adjoint that records its own run."""
+    print("case record", flush=True)
+    cfg, init = small_case()
+    seed = {k: torch.from_numpy(v) for k, v in seeds((cfg["ny"], cfg["nx"]), ["phi2"], seed=6).items()}
+    a = binding.Sim(cfg, init, precision="fp32")
+    a.record(STEPS, 16)
+    b = binding.Sim(cfg, init, precision="fp32")
+    b.step(STEPS)
+    for fam in "fglh":
+        assert torch.equal(a.populations(fam), b.populations(fam)), fam
+    assert a.adjoint(STEPS, seed, 16) == b.adjoint(STEPS, seed, 16)
+
+
+def test_reverse_mode_limits():
+    """Seeds outside phi, adaptive sub-iterations and FP16 storage are
+    refused with EUNSUPPORTED (forward mode covers them)."""
+    print("case reverse limits", flush=True)
+    cfg, init = small_case()
+    seed = {"q": torch.zeros(cfg["ny"], cfg["nx"], dtype=torch.float64)}
+    with pytest.raises(binding.LbmEhdError):
+        binding.Sim(cfg, init, precision="fp64").adjoint(4, seed, 2)
+    for c, prec in ((dict(cfg, sub_min=1, sub_max=8, sub_tol=1e-6), "fp32"), (cfg, "fp16s")):
+        with pytest.raises(binding.LbmEhdError):
+            binding.Sim(c, init, precision=prec).record(4, 2)
 
 
 def test_autograd_deformation_gradient():
