@@ -861,9 +861,17 @@ int reverse_sweep(lbm_ehd_s *H, lbm_ehd_s *W, char *work, const AdjLayout &L, in
                                                         (const T *)I.eps, (const T *)I.q, lev + (size_t)(k - ka) * lv);
         cp ^= 1;
       }
-      for (int k = kb - 1; k >= ka; --k) {
-        k_adj_poisson<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, lev + (size_t)(k - ka) * lv,
-                                                        (const T *)I.eps, ab, hs, ab.rb);
+      for (int k = kb - 1; k >= ka;) {
+        if (k - 1 >= ka) {
+          k_adj_poisson2<T><<<dim3(W->plan.total_tiles2), dim3(P2NT), 0, W->stream>>>(
+              W->d_insts, W->d_t2, lev + (size_t)(k - ka) * lv, lev + (size_t)(k - 1 - ka) * lv, (const T *)I.eps,
+              ab, hs, ab.rb);
+          k -= 2;
+        } else {
+          k_adj_poisson<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, lev + (size_t)(k - ka) * lv,
+                                                          (const T *)I.eps, ab, hs, ab.rb);
+          k -= 1;
+        }
         hs ^= 1;
       }
       HIPC(H, hipGetLastError());

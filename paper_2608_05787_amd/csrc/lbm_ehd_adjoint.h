@@ -152,29 +152,46 @@ __global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ ins
     myg += T(cy(j)) * g[j];
     if (j) s1 += g[j];
   }
-  const T ux = (mxg + T(0.5) * Fx) / rho, uy = (myg + T(0.5) * Fy) / rho;
+  // the sweep multiplies by reciprocals (its values need not match the
+  // forward's rounding, only its arithmetic)
+  const T irho = T(1) / rho;
+  const T ux = (mxg + T(0.5) * Fx) * irho, uy = (myg + T(0.5) * Fy) * irho;
   const T udr = ux * grx + uy * gry;
   const T usq = ux * ux + uy * uy;
   const T s0 = wgt<T>(0) * (-usq * T(1.5));
   const T pp = (s1 + T(0.5) * udr + rho * s0) / (T(3) * (T(1) - wgt<T>(0)));
   const T mv = P.visc[0] * ph[0] + P.visc[1] * ph[1] + P.visc[2] * ph[2];
-  const T tg = T(0.5) + mv * T(3) / rho;
+  const T tg = T(0.5) + mv * T(3) * irho;
   const T itg = T(1) / tg, cg = T(1) - T(0.5) * itg;
 
-  // ---- where each population was pushed: slot offset (plane j or, at a
-  // wall, plane opp(j) of this node), node of that slot, wall speed factor
-  int so[Q], dnode[Q];
-  T wu[Q];  // -6 w_j c_jx u_wall at a wall, 0 inside
-  bool wal[Q];
-#pragma unroll
-  for (int j = 0; j < Q; ++j) {
-    size_t slot;
-    bool top;
-    wal[j] = !push_slot(I, x, y, n, j, slot, dnode[j], top);
-    so[j] = wal[j] ? opp(j) : j;
-    wu[j] = wal[j] ? -T(6) * wgt<T>(j) * T(cx(j)) * (top ? P.wall_u[1] : P.wall_u[0]) : T(0);
+  // ---- where each population was pushed: neighbour rows and columns once;
+  // at a wall the slot is plane opp(j) of this node and the moving-wall
+  // term -6 w_j c_jx u_wall multiplies the carrier
+  const int xm = wrapx(x - 1, nx), xp = wrapx(x + 1, nx);
+  int ym = y - 1, yp = y + 1;
+  bool wb = false, wt = false;
+  if (I.bc_y) {
+    wb = ym < 0;
+    wt = yp >= I.ny;
+  } else {
+    ym = ym < 0 ? ym + I.ny : ym;
+    yp = yp >= I.ny ? yp - I.ny : yp;
   }
-  auto at = [&](const T *plane0, int j) { return plane0[(size_t)so[j] * N + dnode[j]]; };
+  auto wall = [&](int j) { return (cy(j) < 0 && wb) || (cy(j) > 0 && wt); };
+  auto at = [&](const T *plane0, int j) {
+    const int xx = cx(j) < 0 ? xm : (cx(j) > 0 ? xp : x);
+    const int yy = cy(j) < 0 ? ym : (cy(j) > 0 ? yp : y);
+    const bool w = wall(j);
+    return plane0[(size_t)(w ? opp(j) : j) * N + (w ? n : yy * nx + xx)];
+  };
+  auto dnode = [&](int j) {
+    const int xx = cx(j) < 0 ? xm : (cx(j) > 0 ? xp : x);
+    const int yy = cy(j) < 0 ? ym : (cy(j) > 0 ? yp : y);
+    return wall(j) ? n : yy * nx + xx;
+  };
+  auto wu = [&](int j) {
+    return wall(j) ? -T(6) * wgt<T>(j) * T(cx(j)) * (cy(j) > 0 ? P.wall_u[1] : P.wall_u[0]) : T(0);
+  };
 
   // ---- adjoint accumulators
   T ph_b[3] = {T(0), T(0), T(0)}, mu_b[3] = {T(0), T(0), T(0)};
@@ -189,14 +206,9 @@ __global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ ins
     T dqx_b = 0, dqy_b = 0;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-      const T a = at(A + (size_t)AO_L * N, j) + PBc[(size_t)3 * N + dnode[j]];
-      T vb = a;
-      if (wal[j]) {
-        if (dir)
-          vb = -a;
-        else
-          q_b += a * wu[j];
-      }
+      const T a = at(A + (size_t)AO_L * N, j) + PBc[(size_t)3 * N + dnode(j)];
+      const T vb = (dir && wall(j)) ? -a : a;
+      if (!dir) q_b += a * wu(j);
       An[(size_t)AO_L * N + (size_t)j * N + n] = vb * (T(1) - itl);
       const T cu = T(cx(j)) * ux + T(cy(j)) * uy;
       const T wv = vb * itl * wgt<T>(j);
@@ -221,7 +233,7 @@ __global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ ins
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
     const T vb = at(A + (size_t)AO_G * N, j);
-    rho_b += vb * wu[j];
+    rho_b += vb * wu(j);
     const T cu = T(cx(j)) * ux + T(cy(j)) * uy;
     const T sj = wgt<T>(j) * (cu * T(3) + cu * cu * T(4.5) - usq * T(1.5));
     const T geq = (j == 0 ? (wgt<T>(0) - T(1)) * pp * T(3) : wgt<T>(j) * pp * T(3)) + rho * sj;
@@ -245,8 +257,8 @@ __global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ ins
   }
   {
     const T tg_b = -itg_b * itg * itg;
-    const T mv_b = tg_b * T(3) / rho;
-    rho_b -= tg_b * T(3) * mv / (rho * rho);
+    const T mv_b = tg_b * T(3) * irho;
+    rho_b -= tg_b * T(3) * mv * irho * irho;
 #pragma unroll
     for (int i = 0; i < 3; ++i) ph_b[i] += P.visc[i] * mv_b;
   }
@@ -257,12 +269,12 @@ __global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ ins
     const T hx = A[(size_t)(AO_HPU + 2 * i) * N + n], hy = A[(size_t)(AO_HPU + 2 * i + 1) * N + n];
     T dpx_b = 0, dpy_b = 0;
     if (I.phase_mode == 0) {
-      const T m0 = P.m0, itf = T(1) / P.tau_f, cf = T(1) - T(0.5) * itf;
+      const T m0 = P.m0, itf = T(1) / P.tau_f, cf = T(1) - T(0.5) * itf, im0 = T(1) / P.m0;
       T dtx_b = 0, dty_b = 0;
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
-        const T vb = at(A + (size_t)(i * Q) * N, j) + PBc[(size_t)i * N + dnode[j]];
-        ph_b[i] += vb * wu[j];
+        const T vb = at(A + (size_t)(i * Q) * N, j) + PBc[(size_t)i * N + dnode(j)];
+        ph_b[i] += vb * wu(j);
         An[(size_t)(i * Q + j) * N + n] = vb * (T(1) - itf);
         if (j == 0) {
           ph_b[i] += vb * itf;
@@ -280,7 +292,7 @@ __global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ ins
       dpx_b = T(3) * dtx_b;
       dpy_b = T(3) * dty_b;
       // X_i = sum_{k != i} M_ik grad mu_k + (M_ii - m0) grad mu_i (Eq. 28)
-      const T Xx_b = -dtx_b / m0, Xy_b = -dty_b / m0;
+      const T Xx_b = -dtx_b * im0, Xy_b = -dty_b * im0;
       T mii = 0;
 #pragma unroll
       for (int k = 0; k < 3; ++k)
@@ -319,10 +331,10 @@ __global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ ins
     uy_b += T(2) * uy * usq_b + udr_b * gry;
     grx_b += udr_b * ux;
     gry_b += udr_b * uy;
-    const T mx_b = ux_b / rho, my_b = uy_b / rho;
+    const T mx_b = ux_b * irho, my_b = uy_b * irho;
     Fx_b += T(0.5) * mx_b;
     Fy_b += T(0.5) * my_b;
-    rho_b -= (ux_b * ux + uy_b * uy) / rho;
+    rho_b -= (ux_b * ux + uy_b * uy) * irho;
 #pragma unroll
     for (int j = 0; j < Q; ++j)
       An[(size_t)(AO_G + j) * N + n] = g_b[j] + T(cx(j)) * mx_b + T(cy(j)) * my_b + (j ? s1_b : T(0));
