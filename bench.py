@@ -222,7 +222,10 @@ def gradient_bench(n, steps, sub, init_iters, every):
     from paper_2608_05787_amd import autograd, binding, inputs
     p, init = inputs.field_compound_drop(n, r_shell=40.0, r_core=30.0, sub=(sub, sub, 0.0),
                                          init_iters=init_iters, init_tol=0.0)
+    warm = binding.Sim(p, init, precision="fp32")  # first-use costs stay out of the timings
+    warm.step(10)
     torch.cuda.synchronize()
+    del warm
     t0 = time.time()
     fwd = binding.Sim(p, init, precision="fp32")
     fwd.step(steps)
@@ -254,7 +257,7 @@ def gradient_bench(n, steps, sub, init_iters, every):
     return {"workload": "field compound drop %dx%d, radii 40/30, %d steps, %d potential sub-iterations, "
                         "cold start %d iterations" % (n, n, steps, sub, init_iters),
             "method": "reverse sweep, FP32, checkpoint every %d steps" % every,
-            "D_outer": float(D), "dD_dtheta": g, "dD_dtheta_fp64_sweep": g64,
+            "D_outer": float(D.detach()), "dD_dtheta": g, "dD_dtheta_fp64_sweep": g64,
             "rel_diff_fp32_vs_fp64": rel,
             "forward_s": round(t_fwd, 4), "record_s": round(t_rec, 4), "adjoint_s": round(t_adj, 4),
             "adjoint_over_forward": round(t_adj / t_fwd, 2),
@@ -278,6 +281,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--grad-steps", type=int, default=5000, help="0 skips the gradient leg")
     ap.add_argument("--grad-every", type=int, default=250, help="checkpoint interval of the reverse sweep")
+    ap.add_argument("--gradient-only", action="store_true",
+                    help="run only the gradient leg (for profiling) and print its JSON object")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -290,6 +295,11 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     from paper_2608_05787_amd import binding
     binding.load()
+
+    if args.gradient_only:
+        print(json.dumps({"gradient": gradient_bench(512, args.grad_steps, args.sub, 2000, args.grad_every)}),
+              flush=True)
+        return
 
     if args.calib_copy_mib > 0:
         a = torch.ones(args.calib_copy_mib * 262144, dtype=torch.float32, device="cuda")
