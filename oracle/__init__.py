@@ -21,8 +21,8 @@ _SRC = os.path.join(_HERE, "lbm_ehd_oracle.c")
 _LIB = os.path.join(_HERE, "_lbm_ehd_oracle.so")
 
 FIELDS = ["phi1", "phi2", "phi3", "rho", "ux", "uy", "p", "psi", "Ex", "Ey",
-          "q", "mu1", "mu2", "mu3", "eps", "R"]
-FAMILIES = {"f": (0, 27), "g": (1, 9), "l": (2, 9), "h": (3, 9)}
+          "q", "mu1", "mu2", "mu3", "eps", "R", "uz", "Ez"]
+FAMILIES = {"f": (0, 3), "g": (1, 1), "l": (2, 1), "h": (3, 1)}  # id, planes per lattice direction
 
 
 def build(force: bool = False) -> str:
@@ -50,6 +50,7 @@ class _Params(ctypes.Structure):
         ("rho", ctypes.c_double * 3), ("visc", ctypes.c_double * 3),
         ("eps", ctypes.c_double * 3), ("sigma", ctypes.c_double * 3),
         ("tau_f", ctypes.c_double), ("tau_l", ctypes.c_double),
+        ("nz", ctypes.c_int32), ("lattice", ctypes.c_int32), ("E_ext_z", ctypes.c_double),
     ]
 
 
@@ -68,7 +69,7 @@ def _load():
         lib.or_field.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
         lib.or_pops.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
         lib.or_scalars.argtypes = [ctypes.c_void_p, dp]
-        lib.or_stencil.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, dp]
+        lib.or_stencil.argtypes = [ctypes.POINTER(_Params), dp, dp, dp]
         lib.or_sizeof_params.restype = ctypes.c_int
         assert lib.or_sizeof_params() == ctypes.sizeof(_Params)
         _lib = lib
@@ -103,7 +104,19 @@ def _params(cfg: dict) -> _Params:
         for i in range(3):
             arr[i] = float(cfg[k][i])
     p.tau_f, p.tau_l = float(cfg["tau_f"]), float(cfg["tau_l"])
+    p.nz = int(cfg.get("nz", 1))
+    p.lattice = int(cfg.get("lattice", 0))
+    p.E_ext_z = float(cfg.get("E_ext_z", 0.0))
     return p
+
+
+def _geometry(cfg: dict):
+    """(plane shape, spatial dimension, velocities): D2Q9 planes are
+    [ny, nx]; D3Q15 boxes [nz, ny, nx]."""
+    nx, ny = int(cfg["nx"]), int(cfg["ny"])
+    if int(cfg.get("lattice", 0)) == 1:
+        return (int(cfg.get("nz", 1)), ny, nx), 3, 15
+    return (ny, nx), 2, 9
 
 
 class Oracle:
@@ -111,15 +124,17 @@ class Oracle:
 
     ``cfg`` is a plain dict of physical/lattice parameters (see
     ``paper_2608_05787_amd.inputs``); ``init`` holds the initial fields as
-    float64 arrays: ``phi0`` [3,ny,nx], optional ``u0`` [2,ny,nx], ``q0`` and
-    ``psi0`` [ny,nx].
+    float64 arrays on the lattice's grid G ([ny, nx] for D2Q9, [nz, ny, nx]
+    for D3Q15): ``phi0`` [3, *G], optional ``u0`` [D, *G], ``q0`` and
+    ``psi0`` G.
     """
 
     def __init__(self, cfg: dict, init: dict):
         lib = _load()
         self.nx, self.ny = int(cfg["nx"]), int(cfg["ny"])
         self._p = _params(cfg)
-        shp = (self.ny, self.nx)
+        shp, self.dim, self.q = _geometry(cfg)
+        self.shape = shp
 
         def arr(name, lead):
             v = init.get(name)
@@ -129,7 +144,7 @@ class Oracle:
             assert v.shape == ((lead,) + shp if lead else shp), (name, v.shape)
             return v
 
-        self._keep = [arr("phi0", 3), arr("u0", 2), arr("q0", 0), arr("psi0", 0)]
+        self._keep = [arr("phi0", 3), arr("u0", self.dim), arr("q0", 0), arr("psi0", 0)]
         h = lib.or_create(ctypes.byref(self._p), *[_ptr(a) for a in self._keep])
         if not h:
             raise ValueError("oracle rejected the parameters")
@@ -145,17 +160,17 @@ class Oracle:
         _load().or_step(self._h, int(n))
 
     def field(self, name: str) -> np.ndarray:
-        out = np.empty((self.ny, self.nx), np.float64)
+        out = np.empty(self.shape, np.float64)
         rc = _load().or_field(self._h, FIELDS.index(name), _ptr(out))
         assert rc == 0
         return out
 
     def fields(self, names=None) -> dict:
-        return {k: self.field(k) for k in (names or FIELDS)}
+        return {k: self.field(k) for k in (names or FIELDS[:16])}
 
     def pops(self, fam: str) -> np.ndarray:
-        idx, nq = FAMILIES[fam]
-        out = np.empty((nq, self.ny, self.nx), np.float64)
+        idx, mult = FAMILIES[fam]
+        out = np.empty((mult * self.q,) + self.shape, np.float64)
         assert _load().or_pops(self._h, idx, _ptr(out)) == 0
         return out
 
@@ -167,9 +182,12 @@ class Oracle:
 
 
 def stencil(cfg: dict, chi: np.ndarray):
-    """Eq. (33) gradient and Laplacian of a plain field (unit checks)."""
+    """Eq. (33) gradient components and Laplacian of a plain field (unit
+    checks): (gx, gy, lap) on D2Q9, (gx, gy, gz, lap) on D3Q15."""
     p = _params(cfg)
+    _, dim, _ = _geometry(cfg)
     chi = np.ascontiguousarray(chi, np.float64)
-    gx, gy, lap = (np.empty_like(chi) for _ in range(3))
-    _load().or_stencil(ctypes.byref(p), _ptr(chi), _ptr(gx), _ptr(gy), _ptr(lap))
-    return gx, gy, lap
+    g = np.empty((dim,) + chi.shape, np.float64)
+    lap = np.empty_like(chi)
+    _load().or_stencil(ctypes.byref(p), _ptr(chi), _ptr(g), _ptr(lap))
+    return tuple(g) + (lap,)

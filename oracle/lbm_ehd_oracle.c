@@ -14,8 +14,13 @@
  * splits node loops over rows; per-node arithmetic and every reduction order
  * are fixed, so results are bitwise reproducible for any thread count.
  *
+ * Two lattices (Sec. 3.1): D2Q9 (Eq. 31) on an nx x ny plane, and D3Q15
+ * (Eq. 32) on an nx x ny x nz box.  x (and z) are periodic; y is periodic or
+ * bounded by half-way walls.  Node n = (z ny + y) nx + x; vector fields are
+ * stored as D planes (x, y[, z]).
+ *
  * Where the paper is silent or garbled, the reading taken is stated at the
- * point of use (and listed, numbered R1..R16, in the design notes):
+ * point of use (and listed, numbered R1..R22, in the design notes):
  *   R1  mu_i follows Eq. (20) (derivative form); Eq. (27c) is a misprint.
  *   R2  the CH source Eq. (36) is w_j c_j . [d_t(phi_i u)/cs2 - X_i/m0].
  *   R3  phi_i is the zeroth moment of f^i (sum of f, not of f^eq).
@@ -40,23 +45,44 @@
  *   R15 a uniform applied field E_ext is added to -grad(potential).
  *   R16 initial populations are the equilibria of the initial fields; the
  *       potential is first iterated with q0 (cold start).
+ *   R22 D3Q15: the potential source weights are varpi_0 = 0 and 1/14 for
+ *       the 14 moving directions (Eq. 43 gives 1/8 for D2Q9: the same rule,
+ *       weights summing to one with zero first moment); every other formula
+ *       is written for a general lattice and dimension.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
-#define Q 9
-/* D2Q9 lattice, Eq. (31); c = dx/dt = 1, cs^2 = 1/3. */
-static const int CX[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-static const int CY[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-static const double WT[Q] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
-                             1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-static const int OPP[Q] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-/* source weights of the potential equation, Eq. (43): varpi_0 = 0, 1/8 else */
-static const double VARPI[Q] = {0.0, 0.125, 0.125, 0.125, 0.125,
-                                0.125, 0.125, 0.125, 0.125};
+#define QMAX 15
 static const double CS2 = 1.0 / 3.0;
+
+/* Lattices of Eqs. (31)-(32), c = dx/dt = 1, cs^2 = 1/3. */
+typedef struct {
+  int Q, D;
+  int c[QMAX][3];
+  double w[QMAX];
+  int opp[QMAX];
+  double varpi[QMAX]; /* potential source weights, Eq. (43) (R22) */
+} lattice;
+
+static const lattice D2Q9 = {
+    9, 2,
+    {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0}, {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}},
+    {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36},
+    {0, 3, 4, 1, 2, 7, 8, 5, 6},
+    {0.0, 0.125, 0.125, 0.125, 0.125, 0.125, 0.125, 0.125, 0.125}};
+
+static const lattice D3Q15 = {
+    15, 3,
+    {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}, {1, 1, 1},
+     {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1}, {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}},
+    {2.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 72, 1.0 / 72, 1.0 / 72, 1.0 / 72,
+     1.0 / 72, 1.0 / 72, 1.0 / 72, 1.0 / 72},
+    {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13},
+    {0.0, 1.0 / 14, 1.0 / 14, 1.0 / 14, 1.0 / 14, 1.0 / 14, 1.0 / 14, 1.0 / 14, 1.0 / 14, 1.0 / 14, 1.0 / 14,
+     1.0 / 14, 1.0 / 14, 1.0 / 14, 1.0 / 14}};
 
 typedef struct {
   int32_t nx, ny;
@@ -67,29 +93,33 @@ typedef struct {
   int32_t sub_min, sub_max;
   int32_t init_sub_max, pad0;
   double sub_tol, init_tol;
-  double wall_u[2];   /* tangential wall speed, [0] bottom, [1] top */
+  double wall_u[2];   /* tangential (x) wall speed, [0] bottom, [1] top */
   double wall_phi[2]; /* Dirichlet potential at the walls */
   double wall_q[2];   /* Dirichlet charge at the walls (wall_q_mode 1) */
   double E_ext[2];
   double gamma12, gamma13, gamma23, width;
   double rho[3], visc[3], eps[3], sigma[3];
   double tau_f, tau_l;
+  int32_t nz;         /* layers in z (1 for D2Q9) */
+  int32_t lattice;    /* 0 D2Q9, 1 D3Q15 */
+  double E_ext_z;     /* z component of the applied field (D3Q15) */
 } or_params;
 
 typedef struct {
   or_params p;
-  int nx, ny, N;
-  double lam[3], m0, alpha, eps_ref, tau_h;
-  double *f, *g, *l, *h;       /* populations, [family][q][y][x] */
+  const lattice *L;
+  int nx, ny, nz, N, Q, D;
+  double lam[3], m0, alpha, eps_ref, tau_h, Eext[3];
+  double *f, *g, *l, *h;       /* populations, [family][q][N] */
   double *fn, *gn, *ln, *hn;   /* streaming targets */
   double *phi, *lsum;          /* [3][N], [N] */
   double *rho, *sig, *eps, *visc;
-  double *gphi, *lphi;         /* [3][2][N], [3][N] */
-  double *grho, *gsig, *geps;  /* [2][N] */
-  double *q, *R, *psi, *psi_prev, *E; /* E is [2][N]: E of the last solve */
-  double *mu, *gmu;            /* [3][N], [3][2][N] */
-  double *u, *pr;              /* [2][N], [N] */
-  double *hpu, *hqu;           /* history (phi_i u)^{n-1} [3][2][N], (q u)^{n-1} [2][N] */
+  double *gphi, *lphi;         /* [3][D][N], [3][N] */
+  double *grho, *gsig, *geps;  /* [D][N] */
+  double *q, *R, *psi, *psi_prev, *E; /* E is [D][N]: E of the last solve */
+  double *mu, *gmu;            /* [3][N], [3][D][N] */
+  double *u, *pr;              /* [D][N], [N] */
+  double *hpu, *hqu;           /* history (phi_i u)^{n-1} [3][D][N], (q u)^{n-1} [D][N] */
   double *rowbuf;              /* per-row partial sums (deterministic reductions) */
   int64_t nstep;
   int k_used;
@@ -100,32 +130,56 @@ typedef struct {
 
 static double *zalloc(size_t n) { return (double *)calloc(n ? n : 1, sizeof(double)); }
 
-static inline int wrapx(int x, int nx) { return (x % nx + nx) % nx; }
+static inline int wrap(int v, int n) { return (v % n + n) % n; }
 
 /* Row index of a finite-difference neighbour (R11: mirror ghosts at walls). */
 static inline int fd_row(const or_state *s, int y) {
-  if (s->p.bc_y == 0) return (y % s->ny + s->ny) % s->ny;
+  if (s->p.bc_y == 0) return wrap(y, s->ny);
   if (y < 0) return 0;
   if (y >= s->ny) return s->ny - 1;
   return y;
 }
 
-/* Isotropic second-order gradient and Laplacian of Eq. (33) at node (x,y). */
-static void stencil(const or_state *s, const double *chi, int x, int y,
-                    double *gx, double *gy, double *lap) {
-  const int nx = s->nx;
-  const double c0 = chi[y * nx + x];
-  double sx = 0, sy = 0, sl = 0;
-  for (int j = 0; j < Q; ++j) {
-    const int xx = wrapx(x + CX[j], nx), yy = fd_row(s, y + CY[j]);
-    const double v = chi[yy * nx + xx];
-    sx += WT[j] * CX[j] * v;
-    sy += WT[j] * CY[j] * v;
-    sl += 2.0 * WT[j] * (v - c0);
+static inline int node(const or_state *s, int x, int y, int z) { return (z * s->ny + y) * s->nx + x; }
+
+/* Isotropic second-order gradient and Laplacian of Eq. (33) at node
+ * (x, y, z); g receives D components (may be NULL). */
+static void stencil(const or_state *s, const double *chi, int x, int y, int z, double *g, double *lap) {
+  const lattice *L = s->L;
+  const double c0 = chi[node(s, x, y, z)];
+  double sg[3] = {0, 0, 0}, sl = 0;
+  for (int j = 0; j < L->Q; ++j) {
+    const int xx = wrap(x + L->c[j][0], s->nx), yy = fd_row(s, y + L->c[j][1]);
+    const int zz = wrap(z + L->c[j][2], s->nz);
+    const double v = chi[node(s, xx, yy, zz)];
+    for (int d = 0; d < L->D; ++d) sg[d] += L->w[j] * L->c[j][d] * v;
+    sl += 2.0 * L->w[j] * (v - c0);
   }
-  if (gx) *gx = sx / CS2;
-  if (gy) *gy = sy / CS2;
+  if (g)
+    for (int d = 0; d < L->D; ++d) g[d] = sg[d] / CS2;
   if (lap) *lap = sl / CS2;
+}
+
+/* Eq. (33) on a plane field, writing gradient planes [D][N] and the Laplacian. */
+static void stencil_field(or_state *s, const double *chi, double *g, double *lap) {
+  const int N = s->N, D = s->D;
+#pragma omp parallel for schedule(static)
+  for (int r = 0; r < s->ny * s->nz; ++r) {
+    const int y = r % s->ny, z = r / s->ny;
+    for (int x = 0; x < s->nx; ++x) {
+      const int n = node(s, x, y, z);
+      double gg[3];
+      stencil(s, chi, x, y, z, g ? gg : NULL, lap ? lap + n : NULL);
+      if (g)
+        for (int d = 0; d < D; ++d) g[d * N + n] = gg[d];
+    }
+  }
+}
+
+static double dotc(const lattice *L, int j, const double *v) {
+  double a = 0;
+  for (int d = 0; d < L->D; ++d) a += L->c[j][d] * v[d];
+  return a;
 }
 
 /* Properties of Eqs. (29)-(30). */
@@ -138,7 +192,7 @@ static double prop_eps(const double *e, double p1, double p2, double p3) {
 }
 
 /*
- * Streaming of one 9-population family with half-way walls (R10).
+ * Streaming of one family with half-way walls (R10).
  * post: post-collision values; dst: pre-collision values of the next level.
  * mode 0: bounce-back with moving-wall term -2 w_j psi (c_j . u_w)/cs2,
  *         psi per node given by `carrier` (NULL means psi = 0).
@@ -146,33 +200,35 @@ static double prop_eps(const double *e, double p1, double p2, double p3) {
  */
 static void stream_family(const or_state *s, const double *post, double *dst,
                           int mode, const double *carrier, double bot, double top) {
+  const lattice *L = s->L;
   const int nx = s->nx, ny = s->ny, N = s->N;
 #pragma omp parallel for schedule(static)
-  for (int y = 0; y < ny; ++y)
+  for (int r = 0; r < ny * s->nz; ++r) {
+    const int y = r % ny, z = r / ny;
     for (int x = 0; x < nx; ++x) {
-      const int n = y * nx + x;
-      for (int j = 0; j < Q; ++j) {
+      const int n = node(s, x, y, z);
+      for (int j = 0; j < L->Q; ++j) {
         const double v = post[j * N + n];
-        const int xd = wrapx(x + CX[j], nx);
-        int yd = y + CY[j];
+        const int xd = wrap(x + L->c[j][0], nx), zd = wrap(z + L->c[j][2], s->nz);
+        int yd = y + L->c[j][1];
         if (s->p.bc_y == 0) {
-          yd = (yd % ny + ny) % ny;
-          dst[j * N + yd * nx + xd] = v;
+          dst[j * N + node(s, xd, wrap(yd, ny), zd)] = v;
         } else if (yd >= 0 && yd < ny) {
-          dst[j * N + yd * nx + xd] = v;
+          dst[j * N + node(s, xd, yd, zd)] = v;
         } else {
           const int side = (yd < 0) ? 0 : 1;
           double out;
           if (mode == 0) {
             const double psi = carrier ? carrier[n] : 0.0;
-            out = v - 2.0 * WT[j] * psi * (CX[j] * s->p.wall_u[side]) / CS2;
+            out = v - 2.0 * L->w[j] * psi * (L->c[j][0] * s->p.wall_u[side]) / CS2;
           } else {
-            out = -v + 2.0 * WT[j] * (side ? top : bot);
+            out = -v + 2.0 * L->w[j] * (side ? top : bot);
           }
-          dst[OPP[j] * N + n] = out;
+          dst[L->opp[j] * N + n] = out;
         }
       }
     }
+  }
 }
 
 static void swap_ptr(double **a, double **b) {
@@ -184,45 +240,42 @@ static void swap_ptr(double **a, double **b) {
 /* ------------------------------------------------------ potential (h) LB */
 
 /* Potential and its gradient from the local h moments, Eq. (45). */
-static void h_moments(const or_state *s, int n, double epshat,
-                      double *pot, double *gx, double *gy) {
+static void h_moments(const or_state *s, int n, double epshat, double *pot, double *g) {
+  const lattice *L = s->L;
   const int N = s->N;
-  double s0 = 0, mx = 0, my = 0;
-  for (int j = 1; j < Q; ++j) s0 += s->h[j * N + n];
-  for (int j = 0; j < Q; ++j) {
-    mx += CX[j] * s->h[j * N + n];
-    my += CY[j] * s->h[j * N + n];
-  }
-  *pot = s0 / (1.0 - WT[0]);
+  double s0 = 0, m[3] = {0, 0, 0};
+  for (int j = 1; j < L->Q; ++j) s0 += s->h[j * N + n];
+  for (int j = 0; j < L->Q; ++j)
+    for (int d = 0; d < L->D; ++d) m[d] += L->c[j][d] * s->h[j * N + n];
+  *pot = s0 / (1.0 - L->w[0]);
   const double den = epshat + CS2 * s->tau_h;
-  *gx = -mx / den;
-  *gy = -my / den;
+  for (int d = 0; d < L->D; ++d) g[d] = -m[d] / den;
 }
 
 static void eval_potential(or_state *s, double *dst) {
 #pragma omp parallel for schedule(static)
   for (int n = 0; n < s->N; ++n) {
-    double gx, gy;
-    h_moments(s, n, s->eps[n] - s->eps_ref, &dst[n], &gx, &gy);
+    double g[3];
+    h_moments(s, n, s->eps[n] - s->eps_ref, &dst[n], g);
   }
 }
 
 /* One potential sub-iteration: collision of Eq. (43) with the equilibrium of
  * Eq. (44), then streaming with anti-bounce-back electrodes. */
 static void poisson_iteration(or_state *s) {
+  const lattice *L = s->L;
   const int N = s->N;
   const double th = s->tau_h;
 #pragma omp parallel for schedule(static)
   for (int n = 0; n < N; ++n) {
     const double epshat = s->eps[n] - s->eps_ref;
-    double pot, gx, gy;
-    h_moments(s, n, epshat, &pot, &gx, &gy);
-    for (int j = 0; j < Q; ++j) {
+    double pot, g[3];
+    h_moments(s, n, epshat, &pot, g);
+    for (int j = 0; j < L->Q; ++j) {
       const double hj = s->h[j * N + n];
-      const double heq = (j == 0) ? (WT[0] - 1.0) * pot : WT[j] * pot;
-      const double cg = CX[j] * gx + CY[j] * gy;
-      s->hn[j * N + n] = hj - (hj - heq) / th - (epshat / CS2) * WT[j] * cg / th +
-                         VARPI[j] * s->q[n];
+      const double heq = (j == 0) ? (L->w[0] - 1.0) * pot : L->w[j] * pot;
+      const double cg = dotc(L, j, g);
+      s->hn[j * N + n] = hj - (hj - heq) / th - (epshat / CS2) * L->w[j] * cg / th + L->varpi[j] * s->q[n];
     }
   }
   /* collided values are in hn; stream them back into h */
@@ -230,22 +283,22 @@ static void poisson_iteration(or_state *s) {
 }
 
 static double rel_change(or_state *s, const double *a, const double *b) {
-  const int nx = s->nx, ny = s->ny;
+  const int nx = s->nx, R = s->ny * s->nz;
 #pragma omp parallel for schedule(static)
-  for (int y = 0; y < ny; ++y) {
+  for (int r = 0; r < R; ++r) {
     double d2 = 0, a2 = 0;
     for (int x = 0; x < nx; ++x) {
-      const double d = a[y * nx + x] - b[y * nx + x];
+      const double d = a[r * nx + x] - b[r * nx + x];
       d2 += d * d;
-      a2 += a[y * nx + x] * a[y * nx + x];
+      a2 += a[r * nx + x] * a[r * nx + x];
     }
-    s->rowbuf[2 * y] = d2;
-    s->rowbuf[2 * y + 1] = a2;
+    s->rowbuf[2 * r] = d2;
+    s->rowbuf[2 * r + 1] = a2;
   }
   double d2 = 0, a2 = 0;
-  for (int y = 0; y < ny; ++y) {
-    d2 += s->rowbuf[2 * y];
-    a2 += s->rowbuf[2 * y + 1];
+  for (int r = 0; r < R; ++r) {
+    d2 += s->rowbuf[2 * r];
+    a2 += s->rowbuf[2 * r + 1];
   }
   const double na = sqrt(a2);
   return sqrt(d2) / (na > 1e-30 ? na : 1e-30);
@@ -271,13 +324,12 @@ static void solve_potential(or_state *s, int kmin, int kmax, double tol) {
   s->k_used = kdone;
   eval_potential(s, s->psi); /* phi_K */
   s->res_last = (kdone > 0) ? rel_change(s, s->psi, s->psi_prev) : 0.0;
-  const int N = s->N;
+  const int N = s->N, D = s->D;
 #pragma omp parallel for schedule(static)
   for (int n = 0; n < N; ++n) {
-    double pot, gx, gy;
-    h_moments(s, n, s->eps[n] - s->eps_ref, &pot, &gx, &gy);
-    s->E[n] = -gx + s->p.E_ext[0];
-    s->E[N + n] = -gy + s->p.E_ext[1];
+    double pot, g[3];
+    h_moments(s, n, s->eps[n] - s->eps_ref, &pot, g);
+    for (int d = 0; d < D; ++d) s->E[d * N + n] = -g[d] + s->Eext[d];
   }
 }
 
@@ -285,7 +337,7 @@ static void solve_potential(or_state *s, int kmin, int kmax, double tol) {
 
 /* Order-parameter and charge moments (R3): phi_i = sum_j f^i_j. */
 static void moments(or_state *s) {
-  const int N = s->N;
+  const int N = s->N, Q = s->Q;
 #pragma omp parallel for schedule(static)
   for (int n = 0; n < N; ++n) {
     for (int i = 0; i < 3; ++i) {
@@ -301,7 +353,7 @@ static void moments(or_state *s) {
 
 /* Properties (Eqs. 29-30) and the Eq. (33) stencils of phi_i, rho, sigma, eps. */
 static void properties_and_stencils(or_state *s) {
-  const int N = s->N, nx = s->nx, ny = s->ny;
+  const int N = s->N, D = s->D;
   const or_params *P = &s->p;
 #pragma omp parallel for schedule(static)
   for (int n = 0; n < N; ++n) {
@@ -311,29 +363,25 @@ static void properties_and_stencils(or_state *s) {
     s->sig[n] = prop_lin(P->sigma, p1, p2, p3);
     s->eps[n] = prop_eps(P->eps, p1, p2, p3);
   }
-#pragma omp parallel for schedule(static)
-  for (int y = 0; y < ny; ++y)
-    for (int x = 0; x < nx; ++x) {
-      const int n = y * nx + x;
-      for (int i = 0; i < 3; ++i)
-        stencil(s, s->phi + i * N, x, y, &s->gphi[(2 * i) * N + n],
-                &s->gphi[(2 * i + 1) * N + n], &s->lphi[i * N + n]);
-      stencil(s, s->rho, x, y, &s->grho[n], &s->grho[N + n], NULL);
-      stencil(s, s->sig, x, y, &s->gsig[n], &s->gsig[N + n], NULL);
-      stencil(s, s->eps, x, y, &s->geps[n], &s->geps[N + n], NULL);
-    }
+  for (int i = 0; i < 3; ++i) stencil_field(s, s->phi + i * N, s->gphi + i * D * N, s->lphi + i * N);
+  stencil_field(s, s->rho, s->grho, NULL);
+  stencil_field(s, s->sig, s->gsig, NULL);
+  stencil_field(s, s->eps, s->geps, NULL);
 }
 
 /* Charge density and the Ohmic source, Eq. (47) with R7; E of the previous
  * step (R9). */
 static void charge(or_state *s) {
-  const int N = s->N;
+  const int N = s->N, D = s->D;
 #pragma omp parallel for schedule(static)
   for (int n = 0; n < N; ++n) {
-    const double ex = s->E[n], ey = s->E[N + n];
     const double se = s->sig[n] / s->eps[n];
-    const double Rp = se * (s->geps[n] * ex + s->geps[N + n] * ey) -
-                      (s->gsig[n] * ex + s->gsig[N + n] * ey);
+    double ge = 0, gs = 0;
+    for (int d = 0; d < D; ++d) {
+      ge += s->geps[d * N + n] * s->E[d * N + n];
+      gs += s->gsig[d * N + n] * s->E[d * N + n];
+    }
+    const double Rp = se * ge - gs;
     const double qq = (s->lsum[n] + 0.5 * Rp) / (1.0 + 0.5 * se);
     s->q[n] = qq;
     s->R[n] = -se * qq + Rp;
@@ -342,84 +390,77 @@ static void charge(or_state *s) {
 
 /* Chemical potentials, Eq. (20) with eps'(phi_i) = 6 eps_i phi_i (1-phi_i) (R1). */
 static void chem_potential(or_state *s) {
-  const int N = s->N;
-  const double D = s->p.width;
+  const int N = s->N, D = s->D;
+  const double Dw = s->p.width;
 #pragma omp parallel for schedule(static)
   for (int n = 0; n < N; ++n) {
-    const double e2 = s->E[n] * s->E[n] + s->E[N + n] * s->E[N + n];
+    double e2 = 0;
+    for (int d = 0; d < D; ++d) e2 += s->E[d * N + n] * s->E[d * N + n];
     for (int i = 0; i < 3; ++i) {
       const double ph = s->phi[i * N + n];
-      const double bulk = 24.0 / D * s->lam[i] * ph * (ph - 0.5) * (ph - 1.0);
-      const double grad = 0.75 * D * s->lam[i] * s->lphi[i * N + n];
+      const double bulk = 24.0 / Dw * s->lam[i] * ph * (ph - 0.5) * (ph - 1.0);
+      const double grad = 0.75 * Dw * s->lam[i] * s->lphi[i * N + n];
       const double elec = 0.5 * (6.0 * s->p.eps[i] * ph * (1.0 - ph)) * e2;
       s->mu[i * N + n] = bulk - grad - elec;
     }
   }
-  const int nx = s->nx, ny = s->ny;
-#pragma omp parallel for schedule(static)
-  for (int y = 0; y < ny; ++y)
-    for (int x = 0; x < nx; ++x) {
-      const int n = y * nx + x;
-      for (int i = 0; i < 3; ++i)
-        stencil(s, s->mu + i * N, x, y, &s->gmu[(2 * i) * N + n],
-                &s->gmu[(2 * i + 1) * N + n], NULL);
-    }
+  for (int i = 0; i < 3; ++i) stencil_field(s, s->mu + i * N, s->gmu + i * D * N, NULL);
 }
 
 /* Body force of Eq. (27b) (R5) and the flow moments of Eq. (41). */
-static void force_and_flow(or_state *s, int n, double *Fx, double *Fy,
-                           double *ux, double *uy, double *pp) {
-  const int N = s->N;
-  double fx = s->q[n] * s->E[n], fy = s->q[n] * s->E[N + n];
-  for (int i = 0; i < 3; ++i) {
-    fx -= s->phi[i * N + n] * s->gmu[(2 * i) * N + n];
-    fy -= s->phi[i * N + n] * s->gmu[(2 * i + 1) * N + n];
+static void force_and_flow(or_state *s, int n, double *F, double *u, double *pp) {
+  const lattice *L = s->L;
+  const int N = s->N, D = s->D;
+  double m[3] = {0, 0, 0}, s1 = 0;
+  for (int d = 0; d < D; ++d) {
+    F[d] = s->q[n] * s->E[d * N + n];
+    for (int i = 0; i < 3; ++i) F[d] -= s->phi[i * N + n] * s->gmu[(i * D + d) * N + n];
   }
-  double mx = 0, my = 0, s1 = 0;
-  for (int j = 0; j < Q; ++j) {
-    mx += CX[j] * s->g[j * N + n];
-    my += CY[j] * s->g[j * N + n];
+  for (int j = 0; j < L->Q; ++j) {
+    for (int d = 0; d < D; ++d) m[d] += L->c[j][d] * s->g[j * N + n];
     if (j) s1 += s->g[j * N + n];
   }
   const double rho = s->rho[n];
-  const double vx = (mx + 0.5 * fx) / rho, vy = (my + 0.5 * fy) / rho;
-  const double udr = vx * s->grho[n] + vy * s->grho[N + n];
-  const double s0 = WT[0] * (-(vx * vx + vy * vy) / (2.0 * CS2));
-  *Fx = fx;
-  *Fy = fy;
-  *ux = vx;
-  *uy = vy;
-  *pp = CS2 / (1.0 - WT[0]) * (s1 + 0.5 * udr + rho * s0);
+  double udr = 0, usq = 0;
+  for (int d = 0; d < D; ++d) {
+    u[d] = (m[d] + 0.5 * F[d]) / rho;
+    udr += u[d] * s->grho[d * N + n];
+    usq += u[d] * u[d];
+  }
+  const double s0 = L->w[0] * (-usq / (2.0 * CS2));
+  *pp = CS2 / (1.0 - L->w[0]) * (s1 + 0.5 * udr + rho * s0);
 }
 
 /* Collisions of Eqs. (34)-(36), (37)-(40) and (48)-(50). */
 static void collide(or_state *s) {
-  const int N = s->N;
+  const lattice *L = s->L;
+  const int N = s->N, D = s->D, Q = s->Q;
   const or_params *P = &s->p;
   const double tf = P->tau_f, tl = P->tau_l, m0 = s->m0;
 #pragma omp parallel for schedule(static)
   for (int n = 0; n < N; ++n) {
-    double Fx, Fy, ux, uy, pp;
-    force_and_flow(s, n, &Fx, &Fy, &ux, &uy, &pp);
-    s->u[n] = ux;
-    s->u[N + n] = uy;
+    double F[3], u[3], pp;
+    force_and_flow(s, n, F, u, &pp);
+    for (int d = 0; d < D; ++d) s->u[d * N + n] = u[d];
     s->pr[n] = pp;
     const double rho = s->rho[n];
-    const double usq = ux * ux + uy * uy;
+    double usq = 0;
+    for (int d = 0; d < D; ++d) usq += u[d] * u[d];
 
     /* time derivatives of phi_i u and q u (R8), history update */
-    double dpu[3][2];
+    double dpu[3][3], dq[3];
     for (int i = 0; i < 3; ++i) {
       const double ph = s->phi[i * N + n];
-      dpu[i][0] = ph * ux - s->hpu[(2 * i) * N + n];
-      dpu[i][1] = ph * uy - s->hpu[(2 * i + 1) * N + n];
-      s->hpu[(2 * i) * N + n] = ph * ux;
-      s->hpu[(2 * i + 1) * N + n] = ph * uy;
+      for (int d = 0; d < D; ++d) {
+        dpu[i][d] = ph * u[d] - s->hpu[(i * D + d) * N + n];
+        s->hpu[(i * D + d) * N + n] = ph * u[d];
+      }
     }
     const double qq = s->q[n];
-    const double dqx = qq * ux - s->hqu[n], dqy = qq * uy - s->hqu[N + n];
-    s->hqu[n] = qq * ux;
-    s->hqu[N + n] = qq * uy;
+    for (int d = 0; d < D; ++d) {
+      dq[d] = qq * u[d] - s->hqu[d * N + n];
+      s->hqu[d * N + n] = qq * u[d];
+    }
 
     /* three order-parameter families */
     if (P->phase_mode == 0) {
@@ -436,22 +477,19 @@ static void collide(or_state *s) {
       }
       for (int i = 0; i < 3; ++i) {
         /* variable part of the diffusion flux (split mobility) */
-        double Xx = (Mm[i][i] - m0) * s->gmu[(2 * i) * N + n];
-        double Xy = (Mm[i][i] - m0) * s->gmu[(2 * i + 1) * N + n];
-        for (int k = 0; k < 3; ++k)
-          if (k != i) {
-            Xx += Mm[i][k] * s->gmu[(2 * k) * N + n];
-            Xy += Mm[i][k] * s->gmu[(2 * k + 1) * N + n];
-          }
+        double X[3];
+        for (int d = 0; d < D; ++d) {
+          X[d] = (Mm[i][i] - m0) * s->gmu[(i * D + d) * N + n];
+          for (int k = 0; k < 3; ++k)
+            if (k != i) X[d] += Mm[i][k] * s->gmu[(k * D + d) * N + n];
+        }
         const double mu = s->mu[i * N + n];
         for (int j = 0; j < Q; ++j) {
           const double fj = s->f[(i * Q + j) * N + n];
-          const double cu = CX[j] * ph[i] * ux + CY[j] * ph[i] * uy;
-          const double feq = (j == 0) ? ph[i] - (1.0 - WT[0]) * mu
-                                      : WT[j] * mu + WT[j] * cu / CS2;
+          const double cu = ph[i] * dotc(L, j, u);
+          const double feq = (j == 0) ? ph[i] - (1.0 - L->w[0]) * mu : L->w[j] * mu + L->w[j] * cu / CS2;
           /* source of Eq. (36), reading R2 */
-          const double Fj = WT[j] * ((CX[j] * dpu[i][0] + CY[j] * dpu[i][1]) / CS2 -
-                                     (CX[j] * Xx + CY[j] * Xy) / m0);
+          const double Fj = L->w[j] * (dotc(L, j, dpu[i]) / CS2 - dotc(L, j, X) / m0);
           s->fn[(i * Q + j) * N + n] = fj - (fj - feq) / tf + (1.0 - 0.5 / tf) * Fj;
         }
       }
@@ -459,16 +497,19 @@ static void collide(or_state *s) {
 
     /* flow family: local tau_g (R6), forcing of Eq. (38), equilibrium (39)-(40) */
     const double tg = 0.5 + s->visc[n] / (rho * CS2);
-    const double gx = s->grho[n], gy = s->grho[N + n];
-    const double udr = ux * gx + uy * gy;
+    double gr[3], udr = 0;
+    for (int d = 0; d < D; ++d) {
+      gr[d] = s->grho[d * N + n];
+      udr += u[d] * gr[d];
+    }
     for (int j = 0; j < Q; ++j) {
       const double gj = s->g[j * N + n];
-      const double cu = CX[j] * ux + CY[j] * uy;
-      const double sj = WT[j] * (cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - usq / (2.0 * CS2));
-      const double geq = ((j == 0) ? (WT[0] - 1.0) * pp / CS2 : WT[j] * pp / CS2) + rho * sj;
-      const double cF = CX[j] * Fx + CY[j] * Fy;
-      const double cgr = CX[j] * gx + CY[j] * gy;
-      const double Gb = WT[j] * (udr + cF / CS2 + (cu * cgr - CS2 * udr) / CS2);
+      const double cu = dotc(L, j, u);
+      const double sj = L->w[j] * (cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - usq / (2.0 * CS2));
+      const double geq = ((j == 0) ? (L->w[0] - 1.0) * pp / CS2 : L->w[j] * pp / CS2) + rho * sj;
+      const double cF = dotc(L, j, F);
+      const double cgr = dotc(L, j, gr);
+      const double Gb = L->w[j] * (udr + cF / CS2 + (cu * cgr - CS2 * udr) / CS2);
       s->gn[j * N + n] = gj - (gj - geq) / tg + (1.0 - 0.5 / tg) * Gb;
     }
 
@@ -476,17 +517,17 @@ static void collide(or_state *s) {
     const double Rn = s->R[n];
     for (int j = 0; j < Q; ++j) {
       const double lj = s->l[j * N + n];
-      const double cu = CX[j] * ux + CY[j] * uy;
-      const double leq = WT[j] * qq * (1.0 + cu / CS2);
-      const double Sj = (1.0 - 0.5 / tl) * WT[j] * Rn;
-      const double Tj = (1.0 - 0.5 / tl) * WT[j] * (CX[j] * dqx + CY[j] * dqy) / CS2;
+      const double cu = dotc(L, j, u);
+      const double leq = L->w[j] * qq * (1.0 + cu / CS2);
+      const double Sj = (1.0 - 0.5 / tl) * L->w[j] * Rn;
+      const double Tj = (1.0 - 0.5 / tl) * L->w[j] * dotc(L, j, dq) / CS2;
       s->ln[j * N + n] = lj - (lj - leq) / tl + Sj + Tj;
     }
   }
 }
 
 static void stream_all(or_state *s) {
-  const int N = s->N;
+  const int N = s->N, Q = s->Q;
   if (s->p.phase_mode == 0) {
     for (int i = 0; i < 3; ++i)
       stream_family(s, s->fn + i * Q * N, s->f + i * Q * N, 0, s->phi + i * N, 0, 0);
@@ -512,18 +553,26 @@ void or_free(or_state *s) {
 }
 
 /* Create: parameter mapping, initial fields, cold-start potential, equilibria.
- * phi0 [3][ny][nx] (required); u0 [2][ny][nx], q0 [ny][nx], psi0 [ny][nx]
- * may be NULL (zero).  Returns NULL on invalid parameters. */
+ * phi0 [3][N] (required); u0 [D][N], q0 [N], psi0 [N] may be NULL (zero).
+ * Returns NULL on invalid parameters. */
 or_state *or_create(const or_params *P, const double *phi0, const double *u0,
                     const double *q0, const double *psi0) {
   if (!P || !phi0 || P->nx < 1 || P->ny < 1) return NULL;
   if (P->tau_f <= 0.5 || P->tau_l <= 0.5) return NULL;
   if (P->eps_ref_phase < 0 || P->eps_ref_phase > 2) return NULL;
+  if (P->lattice != 0 && P->lattice != 1) return NULL;
+  if (P->lattice == 0 && P->nz != 1) return NULL;
+  if (P->nz < 1) return NULL;
   or_state *s = (or_state *)calloc(1, sizeof(or_state));
   s->p = *P;
+  s->L = P->lattice == 1 ? &D3Q15 : &D2Q9;
+  s->Q = s->L->Q;
+  s->D = s->L->D;
   s->nx = P->nx;
   s->ny = P->ny;
-  const int N = s->N = P->nx * P->ny;
+  s->nz = P->nz;
+  const int N = s->N = P->nx * P->ny * P->nz;
+  const int Q = s->Q, D = s->D;
   /* spreading coefficients, Eq. (9) */
   s->lam[0] = P->gamma12 + P->gamma13 - P->gamma23;
   s->lam[1] = P->gamma12 + P->gamma23 - P->gamma13;
@@ -533,25 +582,28 @@ or_state *or_create(const or_params *P, const double *phi0, const double *u0,
   s->alpha = CS2 * (P->tau_l - 0.5);
   s->eps_ref = P->eps[P->eps_ref_phase];
   s->tau_h = 0.5 + s->eps_ref / CS2;
+  s->Eext[0] = P->E_ext[0];
+  s->Eext[1] = P->E_ext[1];
+  s->Eext[2] = P->E_ext_z;
 
-  s->f = zalloc(27 * (size_t)N); s->fn = zalloc(27 * (size_t)N);
-  s->g = zalloc(9 * (size_t)N);  s->gn = zalloc(9 * (size_t)N);
-  s->l = zalloc(9 * (size_t)N);  s->ln = zalloc(9 * (size_t)N);
-  s->h = zalloc(9 * (size_t)N);  s->hn = zalloc(9 * (size_t)N);
+  s->f = zalloc(3 * Q * (size_t)N); s->fn = zalloc(3 * Q * (size_t)N);
+  s->g = zalloc(Q * (size_t)N);  s->gn = zalloc(Q * (size_t)N);
+  s->l = zalloc(Q * (size_t)N);  s->ln = zalloc(Q * (size_t)N);
+  s->h = zalloc(Q * (size_t)N);  s->hn = zalloc(Q * (size_t)N);
   s->phi = zalloc(3 * (size_t)N); s->lsum = zalloc(N);
   s->rho = zalloc(N); s->sig = zalloc(N); s->eps = zalloc(N); s->visc = zalloc(N);
-  s->gphi = zalloc(6 * (size_t)N); s->lphi = zalloc(3 * (size_t)N);
-  s->grho = zalloc(2 * (size_t)N); s->gsig = zalloc(2 * (size_t)N);
-  s->geps = zalloc(2 * (size_t)N);
+  s->gphi = zalloc(3 * D * (size_t)N); s->lphi = zalloc(3 * (size_t)N);
+  s->grho = zalloc(D * (size_t)N); s->gsig = zalloc(D * (size_t)N);
+  s->geps = zalloc(D * (size_t)N);
   s->q = zalloc(N); s->R = zalloc(N); s->psi = zalloc(N); s->psi_prev = zalloc(N);
-  s->E = zalloc(2 * (size_t)N);
-  s->mu = zalloc(3 * (size_t)N); s->gmu = zalloc(6 * (size_t)N);
-  s->u = zalloc(2 * (size_t)N); s->pr = zalloc(N);
-  s->hpu = zalloc(6 * (size_t)N); s->hqu = zalloc(2 * (size_t)N);
-  s->rowbuf = zalloc(2 * (size_t)s->ny);
+  s->E = zalloc(D * (size_t)N);
+  s->mu = zalloc(3 * (size_t)N); s->gmu = zalloc(3 * D * (size_t)N);
+  s->u = zalloc(D * (size_t)N); s->pr = zalloc(N);
+  s->hpu = zalloc(3 * D * (size_t)N); s->hqu = zalloc(D * (size_t)N);
+  s->rowbuf = zalloc(2 * (size_t)s->ny * s->nz);
 
   memcpy(s->phi, phi0, 3 * (size_t)N * sizeof(double));
-  if (u0) memcpy(s->u, u0, 2 * (size_t)N * sizeof(double));
+  if (u0) memcpy(s->u, u0, D * (size_t)N * sizeof(double));
   if (q0) memcpy(s->q, q0, (size_t)N * sizeof(double));
   properties_and_stencils(s);
 
@@ -559,32 +611,34 @@ or_state *or_create(const or_params *P, const double *phi0, const double *u0,
      with the initial charge (R16) */
   for (int n = 0; n < N; ++n) {
     const double v = psi0 ? psi0[n] : 0.0;
-    for (int j = 0; j < Q; ++j) s->h[j * N + n] = (j == 0) ? (WT[0] - 1.0) * v : WT[j] * v;
+    for (int j = 0; j < Q; ++j) s->h[j * N + n] = (j == 0) ? (s->L->w[0] - 1.0) * v : s->L->w[j] * v;
   }
   solve_potential(s, 1, P->init_sub_max, P->init_tol);
   chem_potential(s);
 
   /* equilibria of the initial fields; p = 0 */
+  const lattice *L = s->L;
   for (int n = 0; n < N; ++n) {
-    const double ux = s->u[n], uy = s->u[N + n], usq = ux * ux + uy * uy;
+    double u[3] = {0, 0, 0}, usq = 0;
+    for (int d = 0; d < D; ++d) {
+      u[d] = s->u[d * N + n];
+      usq += u[d] * u[d];
+    }
     const double rho = s->rho[n];
     for (int i = 0; i < 3; ++i) {
       const double ph = s->phi[i * N + n], mu = s->mu[i * N + n];
       for (int j = 0; j < Q; ++j) {
-        const double cu = CX[j] * ph * ux + CY[j] * ph * uy;
-        s->f[(i * Q + j) * N + n] = (j == 0) ? ph - (1.0 - WT[0]) * mu
-                                             : WT[j] * mu + WT[j] * cu / CS2;
+        const double cu = ph * dotc(L, j, u);
+        s->f[(i * Q + j) * N + n] = (j == 0) ? ph - (1.0 - L->w[0]) * mu : L->w[j] * mu + L->w[j] * cu / CS2;
       }
-      s->hpu[(2 * i) * N + n] = ph * ux;
-      s->hpu[(2 * i + 1) * N + n] = ph * uy;
+      for (int d = 0; d < D; ++d) s->hpu[(i * D + d) * N + n] = ph * u[d];
     }
     for (int j = 0; j < Q; ++j) {
-      const double cu = CX[j] * ux + CY[j] * uy;
-      s->g[j * N + n] = rho * WT[j] * (cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - usq / (2.0 * CS2));
-      s->l[j * N + n] = WT[j] * s->q[n] * (1.0 + cu / CS2);
+      const double cu = dotc(L, j, u);
+      s->g[j * N + n] = rho * L->w[j] * (cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - usq / (2.0 * CS2));
+      s->l[j * N + n] = L->w[j] * s->q[n] * (1.0 + cu / CS2);
     }
-    s->hqu[n] = s->q[n] * ux;
-    s->hqu[N + n] = s->q[n] * uy;
+    for (int d = 0; d < D; ++d) s->hqu[d * N + n] = s->q[n] * u[d];
     s->pr[n] = 0.0;
   }
   s->nstep = 0;
@@ -606,10 +660,10 @@ void or_step(or_state *s, int64_t nsteps) {
 }
 
 /* Field ids for or_field; fields are those computed during the last step
- * (after create: the initial fields). */
+ * (after create: the initial fields).  UZ and EZ are zero on D2Q9. */
 enum {
   OR_PHI1 = 0, OR_PHI2, OR_PHI3, OR_RHO, OR_UX, OR_UY, OR_P, OR_PSI, OR_EX, OR_EY,
-  OR_Q, OR_MU1, OR_MU2, OR_MU3, OR_EPS, OR_R, OR_NFIELDS
+  OR_Q, OR_MU1, OR_MU2, OR_MU3, OR_EPS, OR_R, OR_UZ, OR_EZ, OR_NFIELDS
 };
 
 int or_field(const or_state *s, int id, double *out) {
@@ -620,29 +674,34 @@ int or_field(const or_state *s, int id, double *out) {
     case OR_RHO: src = s->rho; break;
     case OR_UX: src = s->u; break;
     case OR_UY: src = s->u + N; break;
+    case OR_UZ: src = s->D == 3 ? s->u + 2 * N : NULL; break;
     case OR_P: src = s->pr; break;
     case OR_PSI: src = s->psi; break;
     case OR_EX: src = s->E; break;
     case OR_EY: src = s->E + N; break;
+    case OR_EZ: src = s->D == 3 ? s->E + 2 * N : NULL; break;
     case OR_Q: src = s->q; break;
     case OR_MU1: case OR_MU2: case OR_MU3: src = s->mu + (id - OR_MU1) * N; break;
     case OR_EPS: src = s->eps; break;
     case OR_R: src = s->R; break;
     default: return -1;
   }
-  memcpy(out, src, (size_t)N * sizeof(double));
+  if (src)
+    memcpy(out, src, (size_t)N * sizeof(double));
+  else
+    memset(out, 0, (size_t)N * sizeof(double));
   return 0;
 }
 
 /* Raw pre-collision populations of the current level.
- * fam 0: f [3][9][N], 1: g [9][N], 2: l [9][N], 3: h [9][N]. */
+ * fam 0: f [3][Q][N], 1: g [Q][N], 2: l [Q][N], 3: h [Q][N]. */
 int or_pops(const or_state *s, int fam, double *out) {
-  const size_t N = (size_t)s->N;
+  const size_t N = (size_t)s->N, Q = (size_t)s->Q;
   switch (fam) {
-    case 0: memcpy(out, s->f, 27 * N * sizeof(double)); return 0;
-    case 1: memcpy(out, s->g, 9 * N * sizeof(double)); return 0;
-    case 2: memcpy(out, s->l, 9 * N * sizeof(double)); return 0;
-    case 3: memcpy(out, s->h, 9 * N * sizeof(double)); return 0;
+    case 0: memcpy(out, s->f, 3 * Q * N * sizeof(double)); return 0;
+    case 1: memcpy(out, s->g, Q * N * sizeof(double)); return 0;
+    case 2: memcpy(out, s->l, Q * N * sizeof(double)); return 0;
+    case 3: memcpy(out, s->h, Q * N * sizeof(double)); return 0;
     default: return -1;
   }
 }
@@ -661,19 +720,26 @@ void or_scalars(const or_state *s, double *out) {
   out[8] = s->tau_h;
 }
 
-/* Eq. (33) on a plain field (for unit checks of the stencil). */
-void or_stencil(const or_params *P, const double *chi, double *gx, double *gy, double *lap) {
+/* Eq. (33) on a plain field (unit checks of the stencil): g [D][N], lap [N]. */
+void or_stencil(const or_params *P, const double *chi, double *g, double *lap) {
   or_state tmp;
   memset(&tmp, 0, sizeof(tmp));
   tmp.p = *P;
+  tmp.L = P->lattice == 1 ? &D3Q15 : &D2Q9;
+  tmp.Q = tmp.L->Q;
+  tmp.D = tmp.L->D;
   tmp.nx = P->nx;
   tmp.ny = P->ny;
-  tmp.N = P->nx * P->ny;
-  for (int y = 0; y < tmp.ny; ++y)
-    for (int x = 0; x < tmp.nx; ++x) {
-      const int n = y * tmp.nx + x;
-      stencil(&tmp, chi, x, y, gx + n, gy + n, lap + n);
-    }
+  tmp.nz = P->nz > 0 ? P->nz : 1;
+  tmp.N = P->nx * P->ny * tmp.nz;
+  for (int z = 0; z < tmp.nz; ++z)
+    for (int y = 0; y < tmp.ny; ++y)
+      for (int x = 0; x < tmp.nx; ++x) {
+        const int n = node(&tmp, x, y, z);
+        double gg[3];
+        stencil(&tmp, chi, x, y, z, gg, lap + n);
+        for (int d = 0; d < tmp.D; ++d) g[d * tmp.N + n] = gg[d];
+      }
 }
 
 int or_sizeof_params(void) { return (int)sizeof(or_params); }

@@ -14,7 +14,7 @@ A parameter dict carries:
   nx, ny, bc_y (0 periodic, 1 walls), wall_u, wall_phi, wall_q_mode, wall_q,
   E_ext, gamma12, gamma13, gamma23, width, rho[3], visc[3], eps[3], sigma[3],
   tau_f, tau_l, eps_ref_phase, phase_mode, sub_min, sub_max, sub_tol,
-  init_sub_max, init_tol.
+  init_sub_max, init_tol, nz, lattice (0 D2Q9, 1 D3Q15), E_ext_z.
 """
 from __future__ import annotations
 
@@ -26,6 +26,7 @@ __all__ = [
     "base_params", "tanh_drop", "compound_drop", "doublet", "flat_layers",
     "eof_channel", "static_doublet", "field_compound_drop", "batch_sweep",
     "adjoint_case", "parity_case", "applied_field", "theta_of", "with_theta", "liquid_lens",
+    "base_params3d", "sphere_drop", "compound_drop3d", "parity_case3d", "field_compound_drop3d",
 ]
 
 
@@ -39,14 +40,39 @@ def base_params(nx: int, ny: int, **kw) -> dict:
              rho=(1.0, 1.0, 1.0), visc=(0.1, 0.1, 0.1), eps=(0.1, 0.1, 0.1),
              sigma=(1e-3, 1e-3, 1e-3), tau_f=0.8, tau_l=0.8, eps_ref_phase=0,
              phase_mode=0, sub_min=1, sub_max=1, sub_tol=0.0,
-             init_sub_max=0, init_tol=0.0)
+             init_sub_max=0, init_tol=0.0, nz=1, lattice=0, E_ext_z=0.0)
     p.update(kw)
     return p
+
+
+def base_params3d(nx: int, ny: int, nz: int, **kw) -> dict:
+    """base_params on the D3Q15 lattice (Eq. 32): an nx x ny x nz box,
+    periodic in x and z, y periodic or walled."""
+    return base_params(nx, ny, nz=int(nz), lattice=1, **kw)
 
 
 def _grid(nx, ny):
     y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
     return x, y
+
+
+def _grid3(nx, ny, nz):
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx].astype(np.float64)
+    return x, y, z
+
+
+def sphere_drop(nx, ny, nz, c, r, width):
+    """The profile of Eq. (54) around a sphere: [nz, ny, nx]."""
+    x, y, z = _grid3(nx, ny, nz)
+    d = np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2)
+    return 0.5 + 0.5 * np.tanh(2.0 * (r - d) / width)
+
+
+def compound_drop3d(nx, ny, nz, c, r_shell, r_core, width):
+    """Concentric spherical compound drop: phi0 [3, nz, ny, nx]."""
+    core = sphere_drop(nx, ny, nz, c, r_core, width)
+    shell = (1.0 - core) * sphere_drop(nx, ny, nz, c, r_shell, width)
+    return np.stack([1.0 - core - shell, shell, core])
 
 
 def tanh_drop(nx, ny, cx, cy, r, width):
@@ -230,6 +256,60 @@ def parity_case(nx, ny, seed=0, walls=True, field=True, shear=True, sub=(2, 2, 0
         p.update(E_ext=(2e-3, -1e-3))
     psi0 = 0.4 * (y + 0.5) / ny if (walls and field) else np.zeros((ny, nx))
     return p, {"phi0": phi0, "u0": u0, "q0": q0, "psi0": psi0}
+
+
+def parity_case3d(nx, ny, nz, seed=0, walls=True, field=True, shear=True, sub=(2, 2, 0.0)):
+    """parity_case on the D3Q15 lattice: a spherical compound drop with every
+    term of the step on (three phases with unequal properties, electrodes,
+    an applied field with a z component, moving walls, a non-zero initial
+    3-D velocity and charge)."""
+    rng = np.random.default_rng(seed)
+    m = min(nx, ny, nz)
+    r2 = 0.30 * m + rng.uniform(-0.3, 0.3)
+    r3 = 0.18 * m + rng.uniform(-0.3, 0.3)
+    c = tuple(0.5 * (k - 1) + rng.uniform(-0.7, 0.7) for k in (nx, ny, nz))
+    width = 2.5
+    phi0 = compound_drop3d(nx, ny, nz, c, r2, r3, width)
+    x, y, z = _grid3(nx, ny, nz)
+    noise = lambda: 2e-4 * rng.standard_normal((nz, ny, nx))  # noqa: E731
+    u0 = np.stack([1e-3 * np.sin(2 * np.pi * (y + 0.5) / ny) + noise(),
+                   1e-3 * np.cos(2 * np.pi * x / nx) + noise(),
+                   8e-4 * np.sin(2 * np.pi * (x + z) / max(nx, nz)) + noise()])
+    q0 = 1e-3 * rng.standard_normal((nz, ny, nx))
+    q0 -= q0.mean()
+    p = base_params3d(nx, ny, nz, bc_y=1 if walls else 0,
+                      gamma12=1.0e-2, gamma13=1.3e-2, gamma23=0.8e-2, width=width,
+                      rho=(1.0, 1.3, 0.8), visc=(0.1, 0.15, 0.07),
+                      eps=(0.1, 0.25, 0.05), sigma=(2e-3, 5e-3, 4e-4), tau_f=0.9, tau_l=0.7,
+                      sub_min=int(sub[0]), sub_max=int(sub[1]), sub_tol=float(sub[2]),
+                      init_sub_max=6, init_tol=0.0)
+    if walls:
+        p.update(wall_u=(-3e-3, 5e-3) if shear else (0.0, 0.0),
+                 wall_phi=(0.0, 0.4) if field else (0.0, 0.0))
+    if field:
+        p.update(E_ext=(2e-3, -1e-3), E_ext_z=1.5e-3)
+    psi0 = 0.4 * (y + 0.5) / ny if (walls and field) else np.zeros((nz, ny, nx))
+    return p, {"phi0": phi0, "u0": u0, "q0": q0, "psi0": psi0}
+
+
+def field_compound_drop3d(n=128, r_shell=40.0, r_core=30.0, ca_e=0.2,
+                          eps_ratio=(2.0, 0.5), sigma_ratio=(3.0, 0.3), tau_l=0.6,
+                          sub=(4, 4, 0.0), init_iters=2000, init_tol=0.0):
+    """The field-driven compound drop in 3-D (Sec. 4.4): a spherical core
+    inside a spherical shell centred in an n^3 box between electrodes (walls
+    at y = -1/2, n - 1/2), periodic in x and z; parameters of workload 3."""
+    eps1, sig1, gamma = 0.1, 1e-3, 1e-3
+    E0 = math.sqrt(ca_e * gamma / (eps1 * r_shell))
+    dV = E0 * n
+    eps = (eps1, eps1 * eps_ratio[0], eps1 * eps_ratio[1])
+    sig = (sig1, sig1 * sigma_ratio[0], sig1 * sigma_ratio[1])
+    p = base_params3d(n, n, n, bc_y=1, wall_phi=(0.0, dV), eps=eps, sigma=sig, tau_l=tau_l,
+                      sub_min=int(sub[0]), sub_max=int(sub[1]), sub_tol=float(sub[2]),
+                      init_sub_max=int(init_iters), init_tol=float(init_tol))
+    c = (0.5 * (n - 1),) * 3
+    phi0 = compound_drop3d(n, n, n, c, r_shell, r_core, 4.0)
+    _, y, _ = _grid3(n, n, n)
+    return p, {"phi0": phi0, "psi0": dV * (y + 0.5) / n}
 
 
 # ---------------------------------------------- gradient parameterisation
