@@ -44,7 +44,8 @@ enum {
   LBM_EHD_EUNSUPPORTED = -7  /* feature not available in this build */
 };
 
-enum { LBM_BC_PERIODIC = 0, LBM_BC_WALL = 1 }; /* x is always periodic */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_WALL = 1 }; /* x (and z) are always periodic */
+enum { LBM_LATTICE_D2Q9 = 0, LBM_LATTICE_D3Q15 = 1 };
 enum { LBM_PREC_FP32 = 0, LBM_PREC_FP16S = 1, LBM_PREC_FP64 = 2, LBM_PREC_TANGENT = 3 };
 /* LBM_DTYPE_TANGENT_F64: the derivative part of a tangent-mode handle's
  * fields, as float64. */
@@ -57,7 +58,8 @@ enum {
   LBM_F_RHO = 1u << 3, LBM_F_UX = 1u << 4, LBM_F_UY = 1u << 5, LBM_F_P = 1u << 6,
   LBM_F_PSI = 1u << 7, LBM_F_EX = 1u << 8, LBM_F_EY = 1u << 9, LBM_F_Q = 1u << 10,
   LBM_F_MU1 = 1u << 11, LBM_F_MU2 = 1u << 12, LBM_F_MU3 = 1u << 13,
-  LBM_F_EPS = 1u << 14, LBM_F_R = 1u << 15
+  LBM_F_EPS = 1u << 14, LBM_F_R = 1u << 15,
+  LBM_F_UZ = 1u << 16, LBM_F_EZ = 1u << 17 /* D3Q15 only */
 };
 /* Population families for lbm_ehd_populations. */
 enum { LBM_POP_F = 0, LBM_POP_G = 1, LBM_POP_L = 2, LBM_POP_H = 3 };
@@ -100,6 +102,17 @@ enum { LBM_POP_F = 0, LBM_POP_G = 1, LBM_POP_L = 2, LBM_POP_H = 3 };
  *                LBM_PREC_TANGENT: FP64 values carrying their derivative
  *                along the parameter direction dtheta (forward-mode
  *                differentiation of the same kernels, 16 bytes per value).
+ *  lattice       LBM_LATTICE_D2Q9 (Eq. 31: an nx x ny plane, nz must be 0 or
+ *                1) or LBM_LATTICE_D3Q15 (Eq. 32: an nx x ny x nz box,
+ *                periodic in z as in x; y as set by bc_y).  All instances
+ *                of a handle share the lattice.  Fields and populations are
+ *                then [nz][ny][nx]; vector fields have 3 components (u, E:
+ *                the z parts are the LBM_F_UZ, LBM_F_EZ fields) and the
+ *                families 15 populations (f 45).  The potential source
+ *                weights are 1/14 on the moving D3Q15 directions (1/8 on
+ *                D2Q9).  Reverse-mode gradients are D2Q9 only.
+ *  nz            layers in z (D3Q15); 0 is read as 1.
+ *  E_ext_z       z component of the applied field (D3Q15).
  *  dtheta        tangent mode only: direction in the parameter space
  *                theta = (eps2/eps1, eps3/eps1, sigma2/sigma1, sigma3/sigma1,
  *                E0).  The first four scale eps2, eps3, sigma2, sigma3 with
@@ -112,13 +125,14 @@ enum { LBM_POP_F = 0, LBM_POP_G = 1, LBM_POP_L = 2, LBM_POP_H = 3 };
 typedef struct {
   int32_t nx, ny, bc_y, wall_q_mode;
   int32_t eps_ref_phase, phase_mode, sub_min, sub_max;
-  int32_t init_sub_max, precision, reserved0, reserved1;
+  int32_t init_sub_max, precision, nz, lattice;
   double sub_tol, init_tol;
   double wall_u[2], wall_phi[2], wall_q[2], E_ext[2];
   double gamma12, gamma13, gamma23, width;
   double rho[3], visc[3], eps[3], sigma[3];
   double tau_f, tau_l;
   double dtheta[5];
+  double E_ext_z;
 } lbm_ehd_params;
 
 /* Initial fields of one instance, HOST pointers to float64 arrays:

@@ -15,9 +15,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm_ehd.so")
 
 FIELDS = ["phi1", "phi2", "phi3", "rho", "ux", "uy", "p", "psi", "Ex", "Ey",
-          "q", "mu1", "mu2", "mu3", "eps", "R"]
+          "q", "mu1", "mu2", "mu3", "eps", "R", "uz", "Ez"]  # uz, Ez: D3Q15 only
 PRECISION = {"fp32": 0, "fp16s": 1, "fp64": 2, "tangent": 3}
-FAMILY = {"f": (0, 27), "g": (1, 9), "l": (2, 9), "h": (3, 9)}
+FAMILY = {"f": (0, 3), "g": (1, 1), "l": (2, 1), "h": (3, 1)}  # id, planes per lattice velocity
 DIAG_KEYS = ["mass1", "mass2", "mass3", "charge", "max_sum_dev", "residual", "k_sub",
              "nonfinite", "D_outer", "D_inner"]
 
@@ -32,7 +32,7 @@ class Params(ctypes.Structure):
         ("wall_q_mode", ctypes.c_int32), ("eps_ref_phase", ctypes.c_int32),
         ("phase_mode", ctypes.c_int32), ("sub_min", ctypes.c_int32), ("sub_max", ctypes.c_int32),
         ("init_sub_max", ctypes.c_int32), ("precision", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+        ("nz", ctypes.c_int32), ("lattice", ctypes.c_int32),
         ("sub_tol", ctypes.c_double), ("init_tol", ctypes.c_double),
         ("wall_u", ctypes.c_double * 2), ("wall_phi", ctypes.c_double * 2),
         ("wall_q", ctypes.c_double * 2), ("E_ext", ctypes.c_double * 2),
@@ -42,6 +42,7 @@ class Params(ctypes.Structure):
         ("eps", ctypes.c_double * 3), ("sigma", ctypes.c_double * 3),
         ("tau_f", ctypes.c_double), ("tau_l", ctypes.c_double),
         ("dtheta", ctypes.c_double * 5),
+        ("E_ext_z", ctypes.c_double),
     ]
 
 
@@ -125,14 +126,25 @@ def make_params(cfg: dict, precision: str = "fp32") -> Params:
     p.tau_f, p.tau_l = float(cfg["tau_f"]), float(cfg["tau_l"])
     for i, v in enumerate(cfg.get("dtheta", (0.0,) * 5)):
         p.dtheta[i] = float(v)
+    p.nz = int(cfg.get("nz", 1))
+    p.lattice = int(cfg.get("lattice", 0))
+    p.E_ext_z = float(cfg.get("E_ext_z", 0.0))
     return p
+
+
+def grid_shape(cfg: dict):
+    """Shape of a field: [ny, nx] on D2Q9, [nz, ny, nx] on D3Q15."""
+    if int(cfg.get("lattice", 0)) == 1:
+        return (int(cfg.get("nz", 1)), int(cfg["ny"]), int(cfg["nx"]))
+    return (int(cfg["ny"]), int(cfg["nx"]))
 
 
 class Sim:
     """A handle over one or more instances (a batch when several are given).
 
     cfgs: parameter dict or list of dicts; inits: dict or list of dicts of
-    float64 host arrays (phi0 [3,ny,nx], optional u0, q0, psi0).
+    float64 host arrays on the lattice's grid G ([ny, nx] for D2Q9,
+    [nz, ny, nx] for D3Q15): phi0 [3, *G], optional u0 [D, *G], q0, psi0 G.
     """
 
     def __init__(self, cfgs, inits, precision: str = "fp32", device="cuda", stream=None):
@@ -141,7 +153,8 @@ class Sim:
         if isinstance(cfgs, dict):
             cfgs, inits = [cfgs], [inits]
         self.n_inst = len(cfgs)
-        self.shapes = [(int(c["ny"]), int(c["nx"])) for c in cfgs]
+        self.shapes = [grid_shape(c) for c in cfgs]
+        self.q = 15 if int(cfgs[0].get("lattice", 0)) == 1 else 9
         self.precision = precision
         self.device = torch.device(device)
         n = self.n_inst
@@ -203,14 +216,13 @@ class Sim:
         """Fields of the last step as [ny, nx] tensors; tangent=True gives the
         derivative parts of a tangent-mode handle (float64)."""
         import torch
-        names = list(names or FIELDS)
+        names = list(names or (FIELDS if self.q == 15 else FIELDS[:16]))
         mask = 0
         for k in names:
             mask |= 1 << FIELDS.index(k)
         order = [k for k in FIELDS if mask & (1 << FIELDS.index(k))]
-        ny, nx = self.shapes[inst]
         dtype = torch.float64 if tangent else (dtype or torch.float64)
-        out = torch.empty((len(order), ny, nx), dtype=dtype, device=self.device)
+        out = torch.empty((len(order),) + self.shapes[inst], dtype=dtype, device=self.device)
         dt = 2 if tangent else (1 if dtype == torch.float64 else 0)
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
         self._check(load().lbm_ehd_fields(self._h, inst, mask, ctypes.c_void_p(out.data_ptr()), dt), self._h)
@@ -219,10 +231,9 @@ class Sim:
 
     def populations(self, fam: str, inst: int = 0, dtype=None):
         import torch
-        idx, nq = FAMILY[fam]
-        ny, nx = self.shapes[inst]
+        idx, mult = FAMILY[fam]
         dtype = dtype or torch.float64
-        out = torch.empty((nq, ny, nx), dtype=dtype, device=self.device)
+        out = torch.empty((mult * self.q,) + self.shapes[inst], dtype=dtype, device=self.device)
         dt = 1 if dtype == torch.float64 else 0
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
         self._check(load().lbm_ehd_populations(self._h, inst, idx, ctypes.c_void_p(out.data_ptr()), dt), self._h)

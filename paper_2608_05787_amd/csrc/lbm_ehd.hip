@@ -31,10 +31,16 @@ struct Layout {
   size_t ctl, part_p, part_mu, part_d, planes, f[2], f0[2], g[2], l[2], h[2], end;
   int nblk;
 };
-// Macroscopic plane groups, each [k][ny][nx] contiguous with plane stride N:
-// phi(3) lsum eps q R psi E(2) mu(3) u(2) p rho hpu(6) hqu(2)
+// Macroscopic plane groups, each [k][nz][ny][nx] contiguous with plane
+// stride N: phi(3) lsum eps q R psi E(D) mu(3) u(D) p rho hpu(3D) hqu(D)
 constexpr int N_GROUPS = 13;
-constexpr int GROUP_PLANES[N_GROUPS] = {3, 1, 1, 1, 1, 1, 2, 3, 2, 1, 1, 6, 2};
+int group_planes(int g, int D) {
+  const int k[N_GROUPS] = {3, 1, 1, 1, 1, 1, D, 3, D, 1, 1, 3 * D, D};
+  return k[g];
+}
+int lat_q(const lbm_ehd_params &p) { return p.lattice == LBM_LATTICE_D3Q15 ? 15 : 9; }
+int lat_d(const lbm_ehd_params &p) { return p.lattice == LBM_LATTICE_D3Q15 ? 3 : 2; }
+int lat_nz(const lbm_ehd_params &p) { return p.nz > 1 ? p.nz : 1; }
 
 size_t elem_size(int prec) { return prec == LBM_PREC_TANGENT ? 16 : (prec == LBM_PREC_FP64 ? 8 : 4); }
 size_t pop_size(int prec) {
@@ -43,7 +49,9 @@ size_t pop_size(int prec) {
 
 Layout layout_one(const lbm_ehd_params &p, size_t off) {
   Layout L;
-  const size_t N = (size_t)p.nx * p.ny;
+  const size_t N = (size_t)p.nx * p.ny * lat_nz(p);
+  const size_t Q = lat_q(p);
+  const int D = lat_d(p);
   const size_t te = elem_size(p.precision), se = pop_size(p.precision);
   L.nblk = (int)((N + NT - 1) / NT);
   L.ctl = off;
@@ -55,18 +63,18 @@ Layout layout_one(const lbm_ehd_params &p, size_t off) {
   L.part_d = off;
   off = align_up(off + (size_t)L.nblk * 16 * sizeof(double));
   L.planes = off;
-  for (int g = 0; g < N_GROUPS; ++g) off += align_up(GROUP_PLANES[g] * N * te);
+  for (int g = 0; g < N_GROUPS; ++g) off += align_up(group_planes(g, D) * N * te);
   for (int b = 0; b < 2; ++b) {
     L.f[b] = off;
-    off = align_up(off + 27 * N * se);
+    off = align_up(off + 3 * Q * N * se);
     L.f0[b] = off;
     if (p.precision == LBM_PREC_FP16S) off = align_up(off + 3 * N * sizeof(float));
     L.g[b] = off;
-    off = align_up(off + 9 * N * se);
+    off = align_up(off + Q * N * se);
     L.l[b] = off;
-    off = align_up(off + 9 * N * se);
+    off = align_up(off + Q * N * se);
     L.h[b] = off;
-    off = align_up(off + 9 * N * te);
+    off = align_up(off + Q * N * te);
   }
   L.end = off;
   return L;
@@ -83,11 +91,13 @@ Plan make_plan(const lbm_ehd_params *p, int n) {
   P.desc_off = 0;
   size_t off = align_up((size_t)n * sizeof(Inst));
   P.total_blocks = 0;
-  for (int i = 0; i < n; ++i) P.total_blocks += (int)(((size_t)p[i].nx * p[i].ny + NT - 1) / NT);
+  for (int i = 0; i < n; ++i) P.total_blocks += (int)(((size_t)p[i].nx * p[i].ny * lat_nz(p[i]) + NT - 1) / NT);
   P.b2i_off = off;
   off = align_up(off + (size_t)P.total_blocks * sizeof(int2));
   P.total_tiles2 = 0;
-  for (int i = 0; i < n; ++i) P.total_tiles2 += ((p[i].nx + P2W - 1) / P2W) * ((p[i].ny + P2H - 1) / P2H);
+  // two-iteration potential tiles (D2Q9 planes only)
+  for (int i = 0; i < n; ++i)
+    if (p[i].lattice == LBM_LATTICE_D2Q9) P.total_tiles2 += ((p[i].nx + P2W - 1) / P2W) * ((p[i].ny + P2H - 1) / P2H);
   P.t2_off = off;
   off = align_up(off + (size_t)P.total_tiles2 * sizeof(int4));
   P.state_off = off;
@@ -123,6 +133,7 @@ template <typename T> void fill_phys(Phys<T> &P, const lbm_ehd_params &p) {
     P.wall_phi[s] = (T)p.wall_phi[s];
     P.wall_q[s] = (T)p.wall_q[s];
   }
+  P.Eext[2] = (T)(p.lattice == LBM_LATTICE_D3Q15 ? p.E_ext_z : 0.0);
 }
 
 // Applied-field magnitude E0 and the mean electrode potential about which
@@ -130,7 +141,8 @@ template <typename T> void fill_phys(Phys<T> &P, const lbm_ehd_params &p) {
 void applied_field(const lbm_ehd_params &p, double &E0, double &mean) {
   const bool walls = p.bc_y == LBM_BC_WALL;
   const double ey = walls ? (p.wall_phi[0] - p.wall_phi[1]) / p.ny : 0.0;
-  E0 = sqrt(p.E_ext[0] * p.E_ext[0] + (p.E_ext[1] + ey) * (p.E_ext[1] + ey));
+  const double ez = p.lattice == LBM_LATTICE_D3Q15 ? p.E_ext_z : 0.0;
+  E0 = sqrt(p.E_ext[0] * p.E_ext[0] + (p.E_ext[1] + ey) * (p.E_ext[1] + ey) + ez * ez);
   mean = walls ? 0.5 * (p.wall_phi[0] + p.wall_phi[1]) : 0.0;
 }
 
@@ -145,7 +157,7 @@ void fill_tangent(Phys<DualD> &T, const lbm_ehd_params &p) {
   cp(T.lam, v.lam, 3);
   T.m0 = v.m0; T.tau_f = v.tau_f; T.tau_l = v.tau_l; T.tau_h = v.tau_h; T.eps_ref = v.eps_ref; T.D = v.D;
   cp(T.rho, v.rho, 3); cp(T.visc, v.visc, 3); cp(T.eps, v.eps, 3); cp(T.sig, v.sig, 3);
-  cp(T.Eext, v.Eext, 2); cp(T.wall_u, v.wall_u, 2); cp(T.wall_phi, v.wall_phi, 2); cp(T.wall_q, v.wall_q, 2);
+  cp(T.Eext, v.Eext, 3); cp(T.wall_u, v.wall_u, 2); cp(T.wall_phi, v.wall_phi, 2); cp(T.wall_q, v.wall_q, 2);
   T.eps[1].d = p.eps[0] * p.dtheta[0];
   T.eps[2].d = p.eps[0] * p.dtheta[1];
   T.sig[1].d = p.sigma[0] * p.dtheta[2];
@@ -158,6 +170,7 @@ void fill_tangent(Phys<DualD> &T, const lbm_ehd_params &p) {
       T.Eext[k].d = p.E_ext[k] * s;
       if (p.bc_y == LBM_BC_WALL) T.wall_phi[k].d = (p.wall_phi[k] - mean) * s;
     }
+    T.Eext[2].d = v.Eext[2] * s;
   }
   // the reference permittivity (and tau_h) belongs to one phase: if that
   // phase's eps moves along dtheta, so does eps_ref
@@ -166,7 +179,10 @@ void fill_tangent(Phys<DualD> &T, const lbm_ehd_params &p) {
 
 const char *validate(const lbm_ehd_params &p, const lbm_ehd_params &p0) {
   if (p.nx < 2 || p.ny < 2) return "nx and ny must be >= 2";
-  if ((long long)p.nx * p.ny > (1ll << 30)) return "too many nodes in one instance";
+  if (p.lattice != LBM_LATTICE_D2Q9 && p.lattice != LBM_LATTICE_D3Q15) return "unknown lattice";
+  if (p.nz < 0 || (p.lattice == LBM_LATTICE_D2Q9 && p.nz > 1)) return "nz must be 0 or 1 on D2Q9 (>= 1 on D3Q15)";
+  if (p.lattice != p0.lattice) return "all instances of a handle must share the lattice";
+  if ((long long)p.nx * p.ny * lat_nz(p) > (1ll << 30)) return "too many nodes in one instance";
   if (p.bc_y != LBM_BC_PERIODIC && p.bc_y != LBM_BC_WALL) return "bc_y must be LBM_BC_PERIODIC or LBM_BC_WALL";
   if (p.wall_q_mode != 0 && p.wall_q_mode != 1) return "wall_q_mode must be 0 or 1";
   if (p.eps_ref_phase < 0 || p.eps_ref_phase > 2) return "eps_ref_phase must be 0, 1 or 2";
@@ -198,7 +214,7 @@ const char *validate(const lbm_ehd_params &p, const lbm_ehd_params &p0) {
 }  // namespace
 
 struct lbm_ehd_s {
-  int n_inst = 0, prec = 0;
+  int n_inst = 0, prec = 0, lattice = 0;
   hipStream_t stream = nullptr;
   char *ws = nullptr;
   Plan plan;
@@ -277,39 +293,39 @@ struct lbm_ehd_s {
 
 namespace {
 
-// Fixed-count potential iterations 1..K: one single-iteration launch first
-// when K is odd, then two-iteration launches.  Returns the launch count (its
-// parity is the buffer flip of the whole loop).
-template <typename T>
+// Fixed-count potential iterations 1..K: on D2Q9 planes one
+// single-iteration launch first when K is odd, then two-iteration LDS-tiled
+// launches; elsewhere (D3Q15 boxes, 16-byte tangent values that leave no
+// room for the tile) one launch per iteration.  Returns the launch count
+// (its parity is the buffer flip of the whole loop).
+template <class Lat, typename T>
 int enqueue_fixed_potential(lbm_ehd_s *H, int K) {
   const dim3 grid(H->plan.total_blocks), grid2(H->plan.total_tiles2), block(NT), block2(P2NT);
   int L = 0, k = 1;
-  if (K & 1) {
-    hipEvent_t e = H->prof_start(2);
-    k_poisson<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, 1, K, 0, 0);
-    H->prof_stop(e);
-    L = 1;
-    k = 2;
-  }
-  if constexpr (sizeof(T) <= 8) {
+  if constexpr (sizeof(T) <= 8 && std::is_same<Lat, D2Q9>::value) {
+    if (K & 1) {
+      hipEvent_t e = H->prof_start(2);
+      k_poisson<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, 1, K, 0, 0);
+      H->prof_stop(e);
+      L = 1;
+      k = 2;
+    }
     for (; k + 1 <= K; k += 2, ++L) {
       hipEvent_t e = H->prof_start(6);
       k_poisson2<T><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, k + 1 == K ? 1 : 0);
       H->prof_stop(e);
     }
   } else {
-    // tangent mode: 16-byte values leave no room for the two-iteration
-    // kernel's LDS tile; one launch per iteration
     for (; k <= K; ++k, ++L) {
       hipEvent_t e = H->prof_start(2);
-      k_poisson<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, k, K, 0, L & 1);
+      k_poisson<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, k, K, 0, L & 1);
       H->prof_stop(e);
     }
   }
   return L;
 }
 
-template <typename T, typename S>
+template <class Lat, typename T, typename S>
 int do_create(lbm_ehd_s *H, const lbm_ehd_init *init) {
   const dim3 grid(H->plan.total_blocks), block(NT);
   const size_t te = sizeof(T);
@@ -326,7 +342,7 @@ int do_create(lbm_ehd_s *H, const lbm_ehd_init *init) {
     };
     int rc;
     if ((rc = up(init[i].phi0, I.phi, 3 * N))) return rc;
-    if ((rc = up(init[i].u0, I.u, 2 * N))) return rc;
+    if ((rc = up(init[i].u0, I.u, (size_t)Lat::D * N))) return rc;
     if ((rc = up(init[i].q0, I.q, N))) return rc;
     if constexpr (std::is_same<T, DualD>::value) {
       // the initial potential guess scales with the applied field about the
@@ -345,7 +361,7 @@ int do_create(lbm_ehd_s *H, const lbm_ehd_init *init) {
       if ((rc = up(init[i].psi0, I.psi, N))) return rc;
     }
   }
-  k_init_potential<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i);
+  k_init_potential<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i);
   HIPC(H, hipGetLastError());
   // cold start of the potential with the initial charge
   const lbm_ehd_params &p0 = H->params[0];
@@ -354,13 +370,13 @@ int do_create(lbm_ehd_s *H, const lbm_ehd_init *init) {
   const int chunk = 256;
   int nlaunch = 0;
   if (!adaptive) {
-    nlaunch = enqueue_fixed_potential<T>(H, kmax);
+    nlaunch = enqueue_fixed_potential<Lat, T>(H, kmax);
     HIPC(H, hipGetLastError());
   }
   for (int k0 = 1; adaptive && k0 <= kmax; k0 += chunk) {
     const int k1 = std::min(kmax, k0 + chunk - 1);
     for (int k = k0; k <= k1; ++k) {
-      k_poisson<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, k, kmax, 1, 0);
+      k_poisson<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, k, kmax, 1, 0);
       k_reduce_poisson<<<H->n_inst, block, 0, H->stream>>>(H->d_insts, k, 1, p0.init_tol);
     }
     HIPC(H, hipGetLastError());
@@ -375,42 +391,42 @@ int do_create(lbm_ehd_s *H, const lbm_ehd_init *init) {
     if (all) break;
   }
   const int hofs = adaptive ? 0 : (nlaunch & 1);
-  k_mu<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, hofs);
-  k_init_pops<T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, hofs);
+  k_mu<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, hofs);
+  k_init_pops<Lat, T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, hofs);
   HIPC(H, hipGetLastError());
   HIPC(H, hipStreamSynchronize(H->stream));
   return LBM_EHD_OK;
 }
 
-template <typename T, typename S>
+template <class Lat, typename T, typename S>
 int do_step(lbm_ehd_s *H, int64_t n) {
   const dim3 grid(H->plan.total_blocks), block(NT);
   const int K = H->sub_max, ad = H->adaptive;
   for (int64_t s = 0; s < n; ++s) {
     const int pc = (int)((H->steps + s) & 1);
     hipEvent_t e = H->prof_start(0);
-    k_moments<T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, pc);
+    k_moments<Lat, T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, pc);
     H->prof_stop(e);
     e = H->prof_start(1);
-    k_pre<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i);
+    k_pre<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i);
     H->prof_stop(e);
     int hflip = 0;
     if (ad) {
       for (int k = 1; k <= K; ++k) {
         e = H->prof_start(2);
-        k_poisson<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, k, K, 1, 0);
+        k_poisson<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, k, K, 1, 0);
         H->prof_stop(e);
         k_reduce_poisson<<<H->n_inst, block, 0, H->stream>>>(H->d_insts, k, H->sub_min, H->sub_tol);
       }
     } else {
-      hflip = enqueue_fixed_potential<T>(H, K) & 1;
+      hflip = enqueue_fixed_potential<Lat, T>(H, K) & 1;
     }
     e = H->prof_start(3);
-    k_mu<T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, hflip);
+    k_mu<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, hflip);
     H->prof_stop(e);
     e = H->prof_start(4);
-    k_collide<T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, pc, s == n - 1 ? 1 : 0, ad ? 0 : K,
-                                                   hflip);
+    k_collide<Lat, T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, pc, s == n - 1 ? 1 : 0,
+                                                        ad ? 0 : K, hflip);
     H->prof_stop(e);
     HIPC(H, hipGetLastError());
   }
@@ -418,11 +434,11 @@ int do_step(lbm_ehd_s *H, int64_t n) {
   return LBM_EHD_OK;
 }
 
-template <typename T, typename S>
+template <class Lat, typename T, typename S>
 int do_diag(lbm_ehd_s *H) {
   const dim3 grid(H->plan.total_blocks), block(NT);
   hipEvent_t e = H->prof_start(5);
-  k_diag<T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, (int)(H->steps & 1));
+  k_diag<Lat, T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, (int)(H->steps & 1));
   k_reduce_diag<<<H->n_inst, block, 0, H->stream>>>(H->d_insts);
   H->prof_stop(e);
   HIPC(H, hipGetLastError());
@@ -455,6 +471,42 @@ int convert_any(lbm_ehd_s *H, int elem, const void *src, void *dst, size_t count
   if (elem == 4) return convert<float>(H, src, dst, count, dtype);
   return convert<__half>(H, src, dst, count, dtype);
 }
+
+// Runs F::template run<Lattice, T, S>(args...) for the handle's lattice and
+// precision.
+template <class F, class... A> int dispatch(const lbm_ehd_s *H, A &&...a) {
+  if (H->lattice == LBM_LATTICE_D3Q15) {
+    if (H->prec == LBM_PREC_FP64) return F::template run<D3Q15, double, double>(a...);
+    if (H->prec == LBM_PREC_TANGENT) return F::template run<D3Q15, DualD, DualD>(a...);
+    if (H->prec == LBM_PREC_FP16S) return F::template run<D3Q15, float, __half>(a...);
+    return F::template run<D3Q15, float, float>(a...);
+  }
+  if (H->prec == LBM_PREC_FP64) return F::template run<D2Q9, double, double>(a...);
+  if (H->prec == LBM_PREC_TANGENT) return F::template run<D2Q9, DualD, DualD>(a...);
+  if (H->prec == LBM_PREC_FP16S) return F::template run<D2Q9, float, __half>(a...);
+  return F::template run<D2Q9, float, float>(a...);
+}
+struct CreateF {
+  template <class L, typename T, typename S> static int run(lbm_ehd_s *H, const lbm_ehd_init *i) {
+    return do_create<L, T, S>(H, i);
+  }
+};
+struct StepF {
+  template <class L, typename T, typename S> static int run(lbm_ehd_s *H, int64_t n) { return do_step<L, T, S>(H, n); }
+};
+struct DiagF {
+  template <class L, typename T, typename S> static int run(lbm_ehd_s *H) { return do_diag<L, T, S>(H); }
+};
+struct ExportF {
+  template <class L, typename T, typename S>
+  static int run(lbm_ehd_s *H, dim3 grid, dim3 block, int inst, int family, int pc, void *dst, int dtype) {
+    if (dtype == LBM_DTYPE_F64)
+      k_export_pops<L, T, S, double><<<grid, block, 0, H->stream>>>(H->d_insts, inst, family, pc, (double *)dst);
+    else
+      k_export_pops<L, T, S, float><<<grid, block, 0, H->stream>>>(H->d_insts, inst, family, pc, (float *)dst);
+    return 0;
+  }
+};
 
 }  // namespace
 
@@ -489,6 +541,7 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
   lbm_ehd_s *H = new lbm_ehd_s();
   H->n_inst = n_inst;
   H->prec = params[0].precision;
+  H->lattice = params[0].lattice;
   H->stream = (hipStream_t)hip_stream;
   H->ws = (char *)dev_workspace;
   H->params.assign(params, params + n_inst);
@@ -510,7 +563,8 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
     Inst I{};
     I.nx = p.nx;
     I.ny = p.ny;
-    I.N = p.nx * p.ny;
+    I.nz = lat_nz(p);
+    I.N = p.nx * p.ny * I.nz;
     I.bc_y = p.bc_y;
     I.wall_q_mode = p.wall_q_mode;
     I.phase_mode = p.phase_mode;
@@ -527,7 +581,7 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
                               &I.mu, &I.u, &I.p, &I.rho, &I.hpu, &I.hqu};
     for (int g = 0; g < N_GROUPS; ++g) {
       *group[g] = base;
-      base += align_up(GROUP_PLANES[g] * (size_t)I.N * te);
+      base += align_up(group_planes(g, lat_d(p)) * (size_t)I.N * te);
     }
     I.part_p = (double *)(H->ws + L.part_p);
     I.part_mu = (double *)(H->ws + L.part_mu);
@@ -551,8 +605,9 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
   // tiles of the two-iteration potential kernel, rows of tiles in order
   std::vector<int4> tl;
   for (int i = 0; i < n_inst; ++i)
-    for (int y0 = 0; y0 < params[i].ny; y0 += P2H)
-      for (int x0 = 0; x0 < params[i].nx; x0 += P2W) tl.push_back(make_int4(i, x0, y0, 0));
+    if (params[i].lattice == LBM_LATTICE_D2Q9)
+      for (int y0 = 0; y0 < params[i].ny; y0 += P2H)
+        for (int x0 = 0; x0 < params[i].nx; x0 += P2W) tl.push_back(make_int4(i, x0, y0, 0));
   std::vector<int4> t2(tl.size());
   for (int b = 0; b < (int)tl.size(); ++b) t2[b] = tl[xcd_order((int)tl.size(), b)];
   int rc = LBM_EHD_OK;
@@ -578,23 +633,16 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
     return LBM_EHD_OK;
   }
   for (int i = 0; i < n_inst; ++i) {
-    const size_t N = (size_t)params[i].nx * params[i].ny;
+    const size_t N = (size_t)params[i].nx * params[i].ny * lat_nz(params[i]);
     auto keep = [&](std::vector<std::vector<double>> &dst, const double *src, size_t cnt) {
       dst.emplace_back(src ? std::vector<double>(src, src + cnt) : std::vector<double>());
     };
     keep(H->init_phi, init[i].phi0, 3 * N);
-    keep(H->init_u, init[i].u0, 2 * N);
+    keep(H->init_u, init[i].u0, (size_t)lat_d(params[i]) * N);
     keep(H->init_q, init[i].q0, N);
     keep(H->init_psi, init[i].psi0, N);
   }
-  if (H->prec == LBM_PREC_FP64)
-    rc = do_create<double, double>(H, init);
-  else if (H->prec == LBM_PREC_TANGENT)
-    rc = do_create<DualD, DualD>(H, init);
-  else if (H->prec == LBM_PREC_FP16S)
-    rc = do_create<float, __half>(H, init);
-  else
-    rc = do_create<float, float>(H, init);
+  rc = dispatch<CreateF>(H, H, init);
   if (rc) return bad(rc);
   *out = H;
   return LBM_EHD_OK;
@@ -655,6 +703,7 @@ AdjLayout adj_layout(const lbm_ehd_s *H, int64_t n_steps, int every) {
 
 const char *adjoint_unsupported(const lbm_ehd_s *H) {
   if (H->n_inst != 1) return "gradients need a single-instance handle";
+  if (H->lattice != LBM_LATTICE_D2Q9) return "reverse mode is built for D2Q9 (forward mode covers D3Q15)";
   if (H->prec != LBM_PREC_FP32 && H->prec != LBM_PREC_FP64) return "reverse mode needs FP32 or FP64 precision";
   if (H->adaptive) return "reverse mode needs a fixed number of potential sub-iterations";
   const lbm_ehd_params &p = H->params[0];
@@ -689,11 +738,11 @@ void step_record(lbm_ehd_s *W, char *slot) {
   const size_t N = (size_t)W->hinst[0].N;
   const int K = W->sub_max, pc = (int)(W->steps & 1);
   const Rec<T> rc = rec_slot<T>(slot, N);
-  k_moments<T, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, pc, rc);
-  k_pre<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, rc);
+  k_moments<D2Q9, T, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, pc, rc);
+  k_pre<D2Q9, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, rc);
   int L = 0, k = 1;
   if (K & 1) {
-    k_poisson<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, 1, K, 0, 0, rec_level<T>(slot, N, 0));
+    k_poisson<D2Q9, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, 1, K, 0, 0, rec_level<T>(slot, N, 0));
     L = 1;
     k = 2;
   }
@@ -701,8 +750,8 @@ void step_record(lbm_ehd_s *W, char *slot) {
     k_poisson2<T><<<grid2, block2, 0, W->stream>>>(W->d_insts, W->d_t2, L & 1, k + 1 == K ? 1 : 0,
                                                    rec_level<T>(slot, N, k - 1), rec_level<T>(slot, N, k));
   const int hflip = L & 1;
-  k_mu<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, hflip, rc);
-  k_collide<T, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, pc, 0, K, hflip, rc);
+  k_mu<D2Q9, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, hflip, rc);
+  k_collide<D2Q9, T, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, pc, 0, K, hflip, rc);
   W->steps += 1;
 }
 
@@ -915,12 +964,7 @@ int lbm_ehd_workspace_bytes(const lbm_ehd_params *params, int32_t n_inst, size_t
   return LBM_EHD_OK;
 }
 
-static int step_eager(lbm_ehd_t H, int64_t n) {
-  if (H->prec == LBM_PREC_FP64) return do_step<double, double>(H, n);
-  if (H->prec == LBM_PREC_TANGENT) return do_step<DualD, DualD>(H, n);
-  if (H->prec == LBM_PREC_FP16S) return do_step<float, __half>(H, n);
-  return do_step<float, float>(H, n);
-}
+static int step_eager(lbm_ehd_t H, int64_t n) { return dispatch<StepF>(H, H, n); }
 
 int lbm_ehd_step(lbm_ehd_t H, int64_t n) {
   if (!H || n < 0) return LBM_EHD_EINVAL;
@@ -981,26 +1025,30 @@ static void *field_src(const Inst &I, int bit) {
     case 11: case 12: case 13: return I.mu;
     case 14: return I.eps;
     case 15: return I.R;
+    case 16: return I.u;
+    case 17: return I.E;
     default: return nullptr;
   }
 }
 static int field_sub(int bit) {
   switch (bit) {
     case 1: case 5: case 9: case 12: return 1;
-    case 2: case 13: return 2;
+    case 2: case 13: case 16: case 17: return 2;
     default: return 0;
   }
 }
 
 int lbm_ehd_fields(lbm_ehd_t H, int32_t inst, uint32_t mask, void *dev_dst, int32_t dtype) {
-  if (!H || inst < 0 || inst >= H->n_inst || !dev_dst || (mask >> 16) != 0)
+  if (!H || inst < 0 || inst >= H->n_inst || !dev_dst || (mask >> 18) != 0)
     return H ? H->fail(LBM_EHD_EINVAL, "fields: bad argument") : LBM_EHD_EINVAL;
+  if ((mask >> 16) != 0 && H->lattice != LBM_LATTICE_D3Q15)
+    return H->fail(LBM_EHD_EINVAL, "fields: z components exist on D3Q15 only");
   if (dtype != LBM_DTYPE_F32 && dtype != LBM_DTYPE_F64 && dtype != LBM_DTYPE_TANGENT_F64)
     return H->fail(LBM_EHD_EINVAL, "fields: bad dtype");
   const Inst &I = H->hinst[inst];
   const size_t N = (size_t)I.N, te = elem_size(H->prec), de = dtype == LBM_DTYPE_F32 ? 4 : 8;
   char *dst = (char *)dev_dst;
-  for (int bit = 0; bit < 16; ++bit) {
+  for (int bit = 0; bit < 18; ++bit) {
     if (!(mask & (1u << bit))) continue;
     const char *src = (const char *)field_src(I, bit) + field_sub(bit) * N * te;
     int rc = convert_any(H, (int)te, src, dst, N, dtype);
@@ -1017,32 +1065,14 @@ int lbm_ehd_populations(lbm_ehd_t H, int32_t inst, int32_t family, void *dev_dst
   const Inst &I = H->hinst[inst];
   const dim3 grid((unsigned)((I.N + NT - 1) / NT)), block(NT);
   const int pc = (int)(H->steps & 1);
-#define EXPORT(T, S)                                                                                      \
-  do {                                                                                                    \
-    if (dtype == LBM_DTYPE_F64)                                                                           \
-      k_export_pops<T, S, double><<<grid, block, 0, H->stream>>>(H->d_insts, inst, family, pc, (double *)dev_dst); \
-    else                                                                                                  \
-      k_export_pops<T, S, float><<<grid, block, 0, H->stream>>>(H->d_insts, inst, family, pc, (float *)dev_dst);   \
-  } while (0)
-  if (H->prec == LBM_PREC_FP64)
-    EXPORT(double, double);
-  else if (H->prec == LBM_PREC_TANGENT)
-    EXPORT(DualD, DualD);
-  else if (H->prec == LBM_PREC_FP16S)
-    EXPORT(float, __half);
-  else
-    EXPORT(float, float);
-#undef EXPORT
+  dispatch<ExportF>(H, H, grid, block, inst, family, pc, dev_dst, dtype);
   HIPC(H, hipGetLastError());
   return LBM_EHD_OK;
 }
 
 int lbm_ehd_diagnostics(lbm_ehd_t H, int32_t inst, double out[10]) {
   if (!H || inst < 0 || inst >= H->n_inst || !out) return LBM_EHD_EINVAL;
-  int rc = H->prec == LBM_PREC_FP64      ? do_diag<double, double>(H)
-           : H->prec == LBM_PREC_TANGENT ? do_diag<DualD, DualD>(H)
-           : H->prec == LBM_PREC_FP16S   ? do_diag<float, __half>(H)
-                                         : do_diag<float, float>(H);
+  int rc = dispatch<DiagF>(H, H);
   if (rc) return rc;
   Ctl c;
   HIPC(H, hipStreamSynchronize(H->stream));
@@ -1112,7 +1142,8 @@ int lbm_ehd_tangent_gradient(lbm_ehd_t H, int64_t n_steps, const void *dev_seed,
                              void *dev_work, size_t work_bytes, double grad_theta[5]) {
   if (!H || !grad_theta || !dev_seed || n_steps < 0) return LBM_EHD_EINVAL;
   if (H->n_inst != 1) return H->fail(LBM_EHD_EUNSUPPORTED, "gradients need a single-instance handle");
-  if (seed_mask == 0 || (seed_mask >> 16) != 0) return H->fail(LBM_EHD_EINVAL, "tangent gradient: bad seed mask");
+  if (seed_mask == 0 || (seed_mask >> 18) != 0 || ((seed_mask >> 16) != 0 && H->lattice != LBM_LATTICE_D3Q15))
+    return H->fail(LBM_EHD_EINVAL, "tangent gradient: bad seed mask");
   size_t need = 0;
   lbm_ehd_tangent_workspace_bytes(H, &need);
   if (!dev_work || work_bytes < need || ((uintptr_t)dev_work % ALIGN) != 0)
@@ -1137,7 +1168,7 @@ int lbm_ehd_tangent_gradient(lbm_ehd_t H, int64_t n_steps, const void *dev_seed,
     const Inst &I = T->hinst[0];
     SeedPlanes sp;
     sp.count = 0;
-    for (int bit = 0; bit < 16; ++bit)
+    for (int bit = 0; bit < 18; ++bit)
       if (seed_mask & (1u << bit))
         sp.plane[sp.count++] = (const DualD *)field_src(I, bit) + (size_t)field_sub(bit) * I.N;
     k_seed_dot<<<dim3(I.nblk), dim3(NT), 0, T->stream>>>(T->d_insts, sp, (const double *)dev_seed);

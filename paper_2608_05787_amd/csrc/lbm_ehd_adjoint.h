@@ -1,5 +1,6 @@
 // Reverse-mode (discrete adjoint) kernels of the three-phase EHD LB step for
-// gfx950.  Included once, by lbm_ehd.hip, after lbm_ehd_kernels.h.
+// gfx950, on the D2Q9 lattice.  Included once, by lbm_ehd.hip, after
+// lbm_ehd_kernels.h.
 //
 // The adjoint of one time step runs the step's kernels backwards: the
 // collide-and-push kernel (flow, charge and order-parameter families), the
@@ -765,8 +766,8 @@ __global__ __launch_bounds__(NT) void k_poisson_buf(const Inst *__restrict__ ins
 #pragma unroll
     for (int j = 0; j < Q; ++j) rec_in[(size_t)j * N + n] = h[j];
   T v[Q];
-  poisson_collide(h, eps[n] - P.eps_ref, q[n], P, v);
-  push<T, T>(dst, v, I, nd.x, nd.y, n, 1, T(0), T(0), T(0), P.wall_phi[0], P.wall_phi[1], T(1), false);
+  poisson_collide<D2Q9>(h, eps[n] - P.eps_ref, q[n], P, v);
+  push<D2Q9, T, T>(dst, v, I, nd, 1, T(0), T(0), T(0), P.wall_phi[0], P.wall_phi[1], T(1), false);
 }
 
 // Equilibrium potential populations of a potential plane (Eq. 44), the

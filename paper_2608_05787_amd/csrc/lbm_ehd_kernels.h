@@ -1,8 +1,12 @@
 // Device-side data structures and kernels of the three-phase EHD LB step for
 // gfx950.  Included once, by lbm_ehd.hip.
 //
-// Layout: every plane is [ny][nx] with x fastest (structure of arrays), so a
-// wave of 64 lanes reads 64 consecutive nodes of one row.  Populations are
+// The step kernels are templates on the lattice: D2Q9 (Eq. 31) on an
+// nx x ny plane or D3Q15 (Eq. 32) on an nx x ny x nz box, periodic in x (and
+// z), y periodic or bounded by half-way walls.  Vector fields carry D planes.
+//
+// Layout: every plane is [nz][ny][nx] with x fastest (structure of arrays), so
+// a wave of 64 lanes reads 64 consecutive nodes of one row.  Populations are
 // double-buffered; which buffer is current lives in a per-instance control
 // block in device memory, so the host launch sequence (and a captured graph)
 // does not depend on the step parity or on how many potential sub-iterations
@@ -49,6 +53,33 @@ template <typename T> __host__ __device__ constexpr T wgt(int j) {
   return j == 0 ? T(4) / T(9) : (j <= 4 ? T(1) / T(9) : T(1) / T(36));
 }
 
+// Velocity sets as compile-time traits: c(j, d), weights w, opposite
+// direction, and the source weights of the potential scheme (Eq. 43:
+// 0 at rest, equal on the moving directions, summing to one).
+struct D2Q9 {
+  static constexpr int Q = 9, D = 2;
+  __host__ __device__ static constexpr int c(int j, int d) { return d == 0 ? cx(j) : (d == 1 ? cy(j) : 0); }
+  __host__ __device__ static constexpr int op(int j) { return opp(j); }
+  template <typename T> __host__ __device__ static constexpr T w(int j) { return wgt<T>(j); }
+  template <typename T> __host__ __device__ static constexpr T varpi(int j) { return j ? T(1) / T(8) : T(0); }
+};
+struct D3Q15 {
+  static constexpr int Q = 15, D = 3;
+  __host__ __device__ static constexpr int c(int j, int d) {
+    constexpr int X[15] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, -1, 1};
+    constexpr int Y[15] = {0, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, -1, 1, 1, -1};
+    constexpr int Z[15] = {0, 0, 0, 0, 0, 1, -1, 1, -1, -1, 1, 1, -1, 1, -1};
+    return d == 0 ? X[j] : (d == 1 ? Y[j] : Z[j]);
+  }
+  __host__ __device__ static constexpr int op(int j) { return j == 0 ? 0 : (j & 1 ? j + 1 : j - 1); }
+  template <typename T> __host__ __device__ static constexpr T w(int j) {
+    return j == 0 ? T(2) / T(9) : (j <= 6 ? T(1) / T(9) : T(1) / T(72));
+  }
+  template <typename T> __host__ __device__ static constexpr T varpi(int j) { return j ? T(1) / T(14) : T(0); }
+};
+template <class L, typename T> __host__ __device__ constexpr T lw(int j) { return L::template w<T>(j); }
+template <class L, typename T> __host__ __device__ constexpr T lc(int j, int d) { return T(L::c(j, d)); }
+
 // Per-instance control words (device memory).  The f/g/l buffer parity is
 // known to the host (one flip per step) and passed to the kernels; the
 // potential buffer parity depends on how many sub-iterations ran, so it lives
@@ -70,15 +101,16 @@ template <typename T> struct Phys {
   T lam[3];
   T m0, tau_f, tau_l, tau_h, eps_ref, D;
   T rho[3], visc[3], eps[3], sig[3];
-  T Eext[2], wall_u[2], wall_phi[2], wall_q[2];
+  T Eext[3], wall_u[2], wall_phi[2], wall_q[2];
 };
 
 // Instance descriptor (device memory, read with uniform loads).
 struct Inst {
   int nx, ny, N, bc_y;
-  int wall_q_mode, phase_mode, nblk, pad;
+  int wall_q_mode, phase_mode, nblk, nz;
   void *f[2], *g[2], *l[2], *h[2];
   float *f0[2];  // FP16S only: FP32 rest populations f^i_0, [3][N]
+  // planes: phi 3, lsum, eps, q, R, psi, E D, mu 3, u D, p, rho, hpu 3D, hqu D
   void *phi, *lsum, *eps, *q, *R, *psi, *E, *mu, *u, *p, *rho, *hpu, *hqu;
   double *part_p;   // potential residual partials, nblk x 2
   double *part_mu;  // last-iteration residual partials, nblk x 2
@@ -125,7 +157,7 @@ template <> struct PopIO<__half, float> {
 __device__ __forceinline__ int fbuf(const Inst &I, int pc) { return I.phase_mode ? 0 : pc; }
 
 struct Node {
-  int inst, n, x, y;
+  int inst, n, x, y, z;
   bool valid;
 };
 
@@ -143,6 +175,7 @@ template <typename T> struct Rec {
 // instance).  The host orders it so that the blocks one XCD receives
 // (consecutive block ids go round-robin over the 8 XCDs) cover a contiguous
 // range of rows: stencil neighbours then hit that XCD's own L2.
+template <class L = D2Q9>
 __device__ __forceinline__ Node locate(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
                                        const Inst *&Ip, int &lblk) {
   Node nd;
@@ -153,8 +186,15 @@ __device__ __forceinline__ Node locate(const Inst *__restrict__ insts, const int
   const int local = t.y * NT + (int)threadIdx.x;
   nd.valid = local < Ip->N;
   nd.n = nd.valid ? local : 0;
-  nd.y = nd.n / Ip->nx;
-  nd.x = nd.n - nd.y * Ip->nx;
+  int r = nd.n;
+  nd.z = 0;
+  if (L::D == 3) {
+    const int plane = Ip->nx * Ip->ny;
+    nd.z = r / plane;
+    r -= nd.z * plane;
+  }
+  nd.y = r / Ip->nx;
+  nd.x = r - nd.y * Ip->nx;
   return nd;
 }
 
@@ -165,20 +205,50 @@ __device__ __forceinline__ int fdrow(int y, int ny, int walls) {
   return y < 0 ? y + ny : (y >= ny ? y - ny : y);
 }
 
-// Eq. (33) gradient (gx, gy) and Laplacian from the 9 stencil values v[j]
+// Node index of the Eq. (33) stencil point x + c_j (periodic wrap in x and
+// z; mirror ghost rows at walls in y).
+template <class L>
+__device__ __forceinline__ int nbr(const Inst &I, const Node &nd, int j) {
+  const int row = fdrow(nd.y + L::c(j, 1), I.ny, I.bc_y);
+  const int col = wrapx(nd.x + L::c(j, 0), I.nx);
+  if (L::D == 2) return row * I.nx + col;
+  return (wrapx(nd.z + L::c(j, 2), I.nz) * I.ny + row) * I.nx + col;
+}
+
+// Eq. (33) gradient g[D] and Laplacian from the Q stencil values v[j]
 // (v[j] = chi(x + c_j)).
+template <class L, typename T>
+__device__ __forceinline__ void fdq(const T *v, T (&g)[L::D], T &lap) {
+  T sg[L::D], sl = 0;
+#pragma unroll
+  for (int d = 0; d < L::D; ++d) sg[d] = 0;
+#pragma unroll
+  for (int j = 0; j < L::Q; ++j) {
+#pragma unroll
+    for (int d = 0; d < L::D; ++d) sg[d] += lw<L, T>(j) * lc<L, T>(j, d) * v[j];
+    sl += T(2) * lw<L, T>(j) * (v[j] - v[0]);
+  }
+#pragma unroll
+  for (int d = 0; d < L::D; ++d) g[d] = sg[d] * T(3);
+  lap = sl * T(3);
+}
+
+// D2Q9 form of fdq with named components (used by the reverse-mode kernels).
 template <typename T>
 __device__ __forceinline__ void fd9(const T *v, T &gx, T &gy, T &lap) {
-  T sx = 0, sy = 0, sl = 0;
+  T g[2];
+  fdq<D2Q9, T>(v, g, lap);
+  gx = g[0];
+  gy = g[1];
+}
+
+// c_j . a for a D-vector a.
+template <class L, typename T>
+__device__ __forceinline__ T cdot(int j, const T (&a)[L::D]) {
+  T r = lc<L, T>(j, 0) * a[0];
 #pragma unroll
-  for (int j = 0; j < Q; ++j) {
-    sx += wgt<T>(j) * T(cx(j)) * v[j];
-    sy += wgt<T>(j) * T(cy(j)) * v[j];
-    sl += T(2) * wgt<T>(j) * (v[j] - v[0]);
-  }
-  gx = sx * T(3);
-  gy = sy * T(3);
-  lap = sl * T(3);
+  for (int d = 1; d < L::D; ++d) r += lc<L, T>(j, d) * a[d];
+  return r;
 }
 
 template <typename T> __device__ __forceinline__ T herm(T p) { return p * p * (T(3) - T(2) * p); }
@@ -217,35 +287,37 @@ __device__ __forceinline__ void reduce_partials(const double *__restrict__ part,
   block_sum<K>(v);
 }
 
-// Push-stream one family from node (x, y) with half-way walls.
-// mode 0: bounce-back with moving-wall term -2 w_j psi (c_j . u_w) / cs2;
+// Push-stream one family from node nd with half-way walls (y).
+// mode 0: bounce-back with moving-wall term -2 w_j psi (c_j . u_w) / cs2
+//         (walls move along x);
 // mode 1: anti-bounce-back toward Dirichlet values (vb bottom, vt top).
 // sc: storage scale (FP16S); skip0: do not store the rest population.
 // Returns the sum of the moving populations as stored (after rounding).
-template <typename T, typename S>
-__device__ __forceinline__ T push(S *__restrict__ dst, const T (&v)[Q], const Inst &I, int x, int y, int n,
+template <class L, typename T, typename S>
+__device__ __forceinline__ T push(S *__restrict__ dst, const T (&v)[L::Q], const Inst &I, const Node &nd,
                                   int mode, T psi, T ub, T ut, T vb, T vt, T sc, bool skip0) {
   using IO = PopIO<S, T>;
-  const int nx = I.nx, ny = I.ny, N = I.N;
+  const int nx = I.nx, ny = I.ny, N = I.N, n = nd.n;
   T moved = 0;
 #pragma unroll
-  for (int j = 0; j < Q; ++j) {
-    const int xd = wrapx(x + cx(j), nx);
-    int yd = y + cy(j);
+  for (int j = 0; j < L::Q; ++j) {
+    const int xd = wrapx(nd.x + L::c(j, 0), nx);
+    int yd = nd.y + L::c(j, 1);
+    const int zoff = L::D == 3 ? wrapx(nd.z + L::c(j, 2), I.nz) * ny : 0;
     T out = v[j];
     size_t idx;
     if (!I.bc_y) {
       yd = yd < 0 ? yd + ny : (yd >= ny ? yd - ny : yd);
-      idx = (size_t)j * N + yd * nx + xd;
+      idx = (size_t)j * N + (zoff + yd) * nx + xd;
     } else if (yd >= 0 && yd < ny) {
-      idx = (size_t)j * N + yd * nx + xd;
+      idx = (size_t)j * N + (zoff + yd) * nx + xd;
     } else {
       const bool top = yd >= ny;
       if (mode == 0)
-        out = v[j] - T(2) * wgt<T>(j) * psi * (T(cx(j)) * (top ? ut : ub)) * T(3);
+        out = v[j] - T(2) * lw<L, T>(j) * psi * (lc<L, T>(j, 0) * (top ? ut : ub)) * T(3);
       else
-        out = -v[j] + T(2) * wgt<T>(j) * (top ? vt : vb);
-      idx = (size_t)opp(j) * N + n;
+        out = -v[j] + T(2) * lw<L, T>(j) * (top ? vt : vb);
+      idx = (size_t)L::op(j) * N + n;
     }
     if (j == 0 && skip0) continue;
     const S st = IO::cv(out, sc);
@@ -259,12 +331,13 @@ __device__ __forceinline__ T push(S *__restrict__ dst, const T (&v)[Q], const In
 
 // a1: order-parameter moments phi_i = sum_j f^i_j and the charge-population
 // sum; resets the per-step potential control words.
-template <typename T, typename S>
+template <class L, typename T, typename S>
 __global__ __launch_bounds__(NT) void k_moments(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
                                                 int pc, Rec<T> rc = Rec<T>{}) {
+  constexpr int Q = L::Q;
   const Inst *Ip;
   int lblk;
-  const Node nd = locate(insts, b2i, Ip, lblk);
+  const Node nd = locate<L>(insts, b2i, Ip, lblk);
   const Inst &I = *Ip;
   if (lblk == 0 && threadIdx.x == 0) {
     I.ctl->done = 0;
@@ -294,32 +367,41 @@ __global__ __launch_bounds__(NT) void k_moments(const Inst *__restrict__ insts, 
 // a2 + a3: permittivity/conductivity stencils (Eq. 33 on the eps and sigma
 // fields of Eqs. 29-30), charge recovery q = (sum l + R'/2)/(1 + sigma/(2 eps))
 // and the Ohmic source R of Eq. (47) with the previous step's field.
-template <typename T>
+template <class L, typename T>
 __global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
                                             Rec<T> rc = Rec<T>{}) {
+  constexpr int Q = L::Q, D = L::D;
   const Inst *Ip;
   int lblk;
-  const Node nd = locate(insts, b2i, Ip, lblk);
+  const Node nd = locate<L>(insts, b2i, Ip, lblk);
   if (!nd.valid) return;
   const Inst &I = *Ip;
   const Phys<T> &P = phys<T>(I);
-  const int N = I.N, nx = I.nx, n = nd.n;
+  const int N = I.N, n = nd.n;
   const T *phi = (const T *)I.phi;
   T ev[Q], sv[Q];
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
-    const int m = fdrow(nd.y + cy(j), I.ny, I.bc_y) * nx + wrapx(nd.x + cx(j), nx);
+    const int m = nbr<L>(I, nd, j);
     const T p1 = phi[m], p2 = phi[(size_t)N + m], p3 = phi[(size_t)2 * N + m];
     ev[j] = P.eps[0] * herm(p1) + P.eps[1] * herm(p2) + P.eps[2] * herm(p3);
     sv[j] = P.sig[0] * p1 + P.sig[1] * p2 + P.sig[2] * p3;
   }
-  T gex, gey, gsx, gsy, dummy;
-  fd9(ev, gex, gey, dummy);
-  fd9(sv, gsx, gsy, dummy);
+  T ge[D], gs[D], dummy;
+  fdq<L>(ev, ge, dummy);
+  fdq<L>(sv, gs, dummy);
   const T *E = (const T *)I.E;
-  const T ex = E[n], ey = E[(size_t)N + n];
+  T e[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) e[d] = E[(size_t)d * N + n];
   const T se = sv[0] / ev[0];
-  const T Rp = se * (gex * ex + gey * ey) - (gsx * ex + gsy * ey);
+  T gee = ge[0] * e[0], gse = gs[0] * e[0];
+#pragma unroll
+  for (int d = 1; d < D; ++d) {
+    gee += ge[d] * e[d];
+    gse += gs[d] * e[d];
+  }
+  const T Rp = se * gee - gse;
   const T q = (((const T *)I.lsum)[n] + T(0.5) * Rp) / (T(1) + T(0.5) * se);
   ((T *)I.q)[n] = q;
   ((T *)I.R)[n] = -se * q + Rp;
@@ -328,33 +410,37 @@ __global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, cons
     rc.q[n] = q;
     rc.R[n] = -se * q + Rp;
     rc.eps[n] = ev[0];
-    rc.Eo[n] = ex;
-    rc.Eo[(size_t)N + n] = ey;
+#pragma unroll
+    for (int d = 0; d < D; ++d) rc.Eo[(size_t)d * N + n] = e[d];
   }
 }
 
 // Potential LB at one node (Eqs. 43-45): potential and gradient from the
 // pre-collision h, then the collision with the eps_hat first-moment source
 // and the charge source.  Returns the potential of the input h.
-template <typename T>
-__device__ __forceinline__ T poisson_collide(const T (&h)[Q], T epshat, T q, const Phys<T> &P, T (&v)[Q]) {
-  T s1 = 0, mx = 0, my = 0;
+template <class L, typename T>
+__device__ __forceinline__ T poisson_collide(const T (&h)[L::Q], T epshat, T q, const Phys<T> &P, T (&v)[L::Q]) {
+  constexpr int Q = L::Q, D = L::D;
+  T s1 = 0, m[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) m[d] = 0;
 #pragma unroll
   for (int j = 1; j < Q; ++j) s1 += h[j];
 #pragma unroll
-  for (int j = 0; j < Q; ++j) {
-    mx += T(cx(j)) * h[j];
-    my += T(cy(j)) * h[j];
-  }
-  const T pot = s1 / (T(1) - wgt<T>(0));
+  for (int j = 0; j < Q; ++j)
+#pragma unroll
+    for (int d = 0; d < D; ++d) m[d] += lc<L, T>(j, d) * h[j];
+  const T pot = s1 / (T(1) - lw<L, T>(0));
   const T den = epshat + P.tau_h / T(3);
-  const T gx = -mx / den, gy = -my / den;  // grad(potential), Eq. (45)
+  T g[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) g[d] = -m[d] / den;  // grad(potential), Eq. (45)
   const T ith = T(1) / P.tau_h;
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
-    const T heq = j == 0 ? (wgt<T>(0) - T(1)) * pot : wgt<T>(j) * pot;
-    const T cg = T(cx(j)) * gx + T(cy(j)) * gy;
-    v[j] = h[j] - (h[j] - heq) * ith - epshat * T(3) * wgt<T>(j) * cg * ith + (j ? T(0.125) : T(0)) * q;
+    const T heq = j == 0 ? (lw<L, T>(0) - T(1)) * pot : lw<L, T>(j) * pot;
+    const T cg = cdot<L>(j, g);
+    v[j] = h[j] - (h[j] - heq) * ith - epshat * T(3) * lw<L, T>(j) * cg * ith + L::template varpi<T>(j) * q;
   }
   return pot;
 }
@@ -370,12 +456,13 @@ __device__ __forceinline__ T poisson_collide(const T (&h)[Q], T epshat, T q, con
 //   its input and, from k = 2 on, the residual partials of the previous
 //   iteration for k_reduce_poisson.
 //   rec_in: when set, receives the input level (recording runs).
-template <typename T>
+template <class L, typename T>
 __global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
                                                 int k, int K, int adaptive, int hpar, T *rec_in = nullptr) {
+  constexpr int Q = L::Q;
   const Inst *Ip;
   int lblk;
-  const Node nd = locate(insts, b2i, Ip, lblk);
+  const Node nd = locate<L>(insts, b2i, Ip, lblk);
   const Inst &I = *Ip;
   const Ctl *ctl = I.ctl;
   if (adaptive && ctl->done) return;  // uniform over the instance
@@ -397,7 +484,7 @@ __global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, 
     const T epshat = ((const T *)I.eps)[n] - P.eps_ref;
     const T q = ((const T *)I.q)[n];
     T v[Q];
-    const T pot = poisson_collide(h, epshat, q, P, v);
+    const T pot = poisson_collide<L>(h, epshat, q, P, v);
     if (write_psi) {
       T *psi = (T *)I.psi;
       if (resid) {
@@ -407,7 +494,7 @@ __global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, 
       }
       psi[n] = pot;
     }
-    push<T, T>(dst, v, I, nd.x, nd.y, n, 1, T(0), T(0), T(0), P.wall_phi[0], P.wall_phi[1], T(1), false);
+    push<L, T, T>(dst, v, I, nd, 1, T(0), T(0), T(0), P.wall_phi[0], P.wall_phi[1], T(1), false);
   }
   if (resid) {
     block_sum<2>(red);
@@ -418,7 +505,7 @@ __global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, 
   }
 }
 
-// Two potential sub-iterations in one launch (fixed count).  A block owns a
+// Two potential sub-iterations in one launch (fixed count, D2Q9).  A block owns a
 // P2W x P2H tile and recomputes a ring of width 2 around it: it loads h,
 // eps_hat and q of the (P2W + 4) x (P2H + 4) extended tile (neighbour rows
 // come from L2), collides every extended node, streams inside LDS (pull, with
@@ -495,7 +582,7 @@ __global__ __launch_bounds__(P2NT) void k_poisson2(const Inst *__restrict__ inst
     for (int k = 0; k < P2RPT; ++k) {
       const int r = ty + (P2NT / 64) * k, e = r * P2EW + tx;
       T v[Q];
-      const T pot = poisson_collide(h[k], eh[k], qq[k], P, v);
+      const T pot = poisson_collide<D2Q9>(h[k], eh[k], qq[k], P, v);
       if (it == 1 && write_psi && inside[k] && r >= 2 && r < 2 + P2H && tx >= 2 && tx < 2 + P2W) {
         const int ux = t.y + tx - 2, uy = t.z + r - 2;
         if (ux < nx && uy < ny) ((T *)I.psi)[gy[k] * nx + gx] = pot;
@@ -569,56 +656,58 @@ __global__ __launch_bounds__(NT) void k_reduce_poisson(const Inst *__restrict__ 
 //   hofs: buffer offset of the final h relative to ctl->hcur (fixed count:
 //   parity of the potential launches; adaptive: 0, the control pass already
 //   flipped it).
-template <typename T>
+template <class L, typename T>
 __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
                                            int hofs, Rec<T> rc = Rec<T>{}) {
+  constexpr int Q = L::Q, D = L::D;
   const Inst *Ip;
   int lblk;
-  const Node nd = locate(insts, b2i, Ip, lblk);
+  const Node nd = locate<L>(insts, b2i, Ip, lblk);
   const Inst &I = *Ip;
   const Ctl *ctl = I.ctl;
   const Phys<T> &P = phys<T>(I);
   double red[2] = {0.0, 0.0};
   if (nd.valid) {
-    const int N = I.N, nx = I.nx, n = nd.n;
+    const int N = I.N, n = nd.n;
     const T *h = (const T *)I.h[ctl->hcur ^ hofs];
-    T s1 = 0, mx = 0, my = 0;
+    T s1 = 0, m[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) m[d] = 0;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
       const T v = h[(size_t)j * N + n];
       if (j) s1 += v;
-      mx += T(cx(j)) * v;
-      my += T(cy(j)) * v;
+#pragma unroll
+      for (int d = 0; d < D; ++d) m[d] += lc<L, T>(j, d) * v;
     }
     const T eps = ((const T *)I.eps)[n];
-    const T pot = s1 / (T(1) - wgt<T>(0));
+    const T pot = s1 / (T(1) - lw<L, T>(0));
     const T den = (eps - P.eps_ref) + P.tau_h / T(3);
-    const T ex = mx / den + P.Eext[0], ey = my / den + P.Eext[1];
+    T e[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) e[d] = m[d] / den + P.Eext[d];
     T *psi = (T *)I.psi;
-    const double d = (double)pot - (double)psi[n];
-    red[0] = d * d;
+    const double dd = (double)pot - (double)psi[n];
+    red[0] = dd * dd;
     red[1] = (double)pot * (double)pot;
     psi[n] = pot;
     T *E = (T *)I.E;
-    E[n] = ex;
-    E[(size_t)N + n] = ey;
-    if (rc.En) {
-      rc.En[n] = ex;
-      rc.En[(size_t)N + n] = ey;
+    T e2 = e[0] * e[0];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      E[(size_t)d * N + n] = e[d];
+      if (rc.En) rc.En[(size_t)d * N + n] = e[d];
+      if (d) e2 += e[d] * e[d];
     }
-    const T e2 = ex * ex + ey * ey;
     const T *phi = (const T *)I.phi;
     T *mu = (T *)I.mu;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       T v[Q];
 #pragma unroll
-      for (int j = 0; j < Q; ++j) {
-        const int m = fdrow(nd.y + cy(j), I.ny, I.bc_y) * nx + wrapx(nd.x + cx(j), nx);
-        v[j] = phi[(size_t)i * N + m];
-      }
-      T gx, gy, lap;
-      fd9(v, gx, gy, lap);
+      for (int j = 0; j < Q; ++j) v[j] = phi[(size_t)i * N + nbr<L>(I, nd, j)];
+      T gg[D], lap;
+      fdq<L>(v, gg, lap);
       const T ph = v[0];
       const T bulk = T(24) / P.D * P.lam[i] * ph * (ph - T(0.5)) * (ph - T(1));
       const T grad = T(0.75) * P.D * P.lam[i] * lap;
@@ -642,13 +731,14 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
 //   fixedK: sub-iterations of a fixed-count step (0 in adaptive mode) and
 //   hflip the buffer parity of its launches, which block 0 folds into
 //   ctl->hcur (no other kernel of the step reads it any more).
-template <typename T, typename S>
+template <class L, typename T, typename S>
 __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
                                                 int pc, int write_macro, int fixedK, int hflip,
                                                 Rec<T> rc = Rec<T>{}) {
+  constexpr int Q = L::Q, D = L::D;
   const Inst *Ip;
   int lblk;
-  const Node nd = locate(insts, b2i, Ip, lblk);
+  const Node nd = locate<L>(insts, b2i, Ip, lblk);
   const Inst &I = *Ip;
   if (lblk == 0 && threadIdx.x == 0) {
     Ctl *ctl = I.ctl;
@@ -661,12 +751,12 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
   }
   if (nd.valid) {
     const Phys<T> &P = phys<T>(I);
-    const int N = I.N, nx = I.nx, n = nd.n, x = nd.x, y = nd.y;
+    const int N = I.N, n = nd.n;
     const T *phi = (const T *)I.phi;
     const T *mu = (const T *)I.mu;
     int m[Q];
 #pragma unroll
-    for (int j = 0; j < Q; ++j) m[j] = fdrow(y + cy(j), I.ny, I.bc_y) * nx + wrapx(x + cx(j), nx);
+    for (int j = 0; j < Q; ++j) m[j] = nbr<L>(I, nd, j);
 
     // density stencil (Eq. 33 on rho of Eq. 29) and mu gradients
     T ph[3], rv[Q];
@@ -680,28 +770,28 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
         ph[2] = p3;
       }
     }
-    T grx, gry, dummy;
-    fd9(rv, grx, gry, dummy);
-    T gmx[3], gmy[3], muc[3];
+    T gr[D], dummy;
+    fdq<L>(rv, gr, dummy);
+    T gm[3][D], muc[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       T v[Q];
 #pragma unroll
       for (int j = 0; j < Q; ++j) v[j] = mu[(size_t)i * N + m[j]];
-      fd9(v, gmx[i], gmy[i], dummy);
+      fdq<L>(v, gm[i], dummy);
       muc[i] = v[0];
     }
     const T rho = rv[0];
     const T q = ((const T *)I.q)[n];
     const T *E = (const T *)I.E;
-    const T ex = E[n], ey = E[(size_t)N + n];
 
     // force and flow moments
-    T Fx = q * ex, Fy = q * ey;
+    T F[D];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      Fx -= ph[i] * gmx[i];
-      Fy -= ph[i] * gmy[i];
+    for (int d = 0; d < D; ++d) {
+      F[d] = q * E[(size_t)d * N + n];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) F[d] -= ph[i] * gm[i][d];
     }
     using IO = PopIO<S, T>;
     const S *gs = (const S *)I.g[pc];
@@ -711,21 +801,29 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
     if (rc.g)
 #pragma unroll
       for (int j = 0; j < Q; ++j) rc.g[(size_t)j * N + n] = g[j];
-    T mxg = 0, myg = 0, s1 = 0;
+    T mg[D], s1 = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) mg[d] = 0;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-      mxg += T(cx(j)) * g[j];
-      myg += T(cy(j)) * g[j];
+#pragma unroll
+      for (int d = 0; d < D; ++d) mg[d] += lc<L, T>(j, d) * g[j];
       if (j) s1 += g[j];
     }
-    const T ux = (mxg + T(0.5) * Fx) / rho, uy = (myg + T(0.5) * Fy) / rho;
-    const T udr = ux * grx + uy * gry;
-    const T usq = ux * ux + uy * uy;
-    const T s0 = wgt<T>(0) * (-usq * T(1.5));
-    const T pp = (s1 + T(0.5) * udr + rho * s0) / (T(3) * (T(1) - wgt<T>(0)));
+    T u[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) u[d] = (mg[d] + T(0.5) * F[d]) / rho;
+    T udr = u[0] * gr[0], usq = u[0] * u[0];
+#pragma unroll
+    for (int d = 1; d < D; ++d) {
+      udr += u[d] * gr[d];
+      usq += u[d] * u[d];
+    }
+    const T s0 = lw<L, T>(0) * (-usq * T(1.5));
+    const T pp = (s1 + T(0.5) * udr + rho * s0) / (T(3) * (T(1) - lw<L, T>(0)));
     if (write_macro) {
-      ((T *)I.u)[n] = ux;
-      ((T *)I.u)[(size_t)N + n] = uy;
+#pragma unroll
+      for (int d = 0; d < D; ++d) ((T *)I.u)[(size_t)d * N + n] = u[d];
       ((T *)I.p)[n] = pp;
       ((T *)I.rho)[n] = rho;
     }
@@ -733,19 +831,21 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
     // history of phi_i u and q u (first-order time derivatives)
     T *hpu = (T *)I.hpu;
     T *hqu = (T *)I.hqu;
-    T dpx[3], dpy[3];
+    T dp[3][D], dq[D];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const T ax = ph[i] * ux, ay = ph[i] * uy;
-      dpx[i] = ax - hpu[(size_t)(2 * i) * N + n];
-      dpy[i] = ay - hpu[(size_t)(2 * i + 1) * N + n];
-      hpu[(size_t)(2 * i) * N + n] = ax;
-      hpu[(size_t)(2 * i + 1) * N + n] = ay;
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const T a = ph[i] * u[d];
+        dp[i][d] = a - hpu[(size_t)(i * D + d) * N + n];
+        hpu[(size_t)(i * D + d) * N + n] = a;
+      }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const T a = q * u[d];
+      dq[d] = a - hqu[(size_t)d * N + n];
+      hqu[(size_t)d * N + n] = a;
     }
-    const T qx = q * ux, qy = q * uy;
-    const T dqx = qx - hqu[n], dqy = qy - hqu[(size_t)N + n];
-    hqu[n] = qx;
-    hqu[(size_t)N + n] = qy;
 
     const int nc = pc ^ 1;
     // three CH families
@@ -757,31 +857,36 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         // degenerate mobility row i: M_ik = -m0 phi_i phi_k, M_ii = -sum_k M_ik
-        T Xx = 0, Xy = 0, mii = 0;
+        T X[D], mii = 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) X[d] = 0;
 #pragma unroll
         for (int kk = 0; kk < 3; ++kk)
           if (kk != i) {
             const T mik = -m0 * ph[i] * ph[kk];
             mii -= mik;
-            Xx += mik * gmx[kk];
-            Xy += mik * gmy[kk];
+#pragma unroll
+            for (int d = 0; d < D; ++d) X[d] += mik * gm[kk][d];
           }
-        Xx += (mii - m0) * gmx[i];
-        Xy += (mii - m0) * gmy[i];
-        const T dtx = dpx[i] * T(3) - Xx / m0, dty = dpy[i] * T(3) - Xy / m0;
-        const T pux = ph[i] * ux, puy = ph[i] * uy;
+        T dt[D], pu[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          X[d] += (mii - m0) * gm[i][d];
+          dt[d] = dp[i][d] * T(3) - X[d] / m0;
+          pu[d] = ph[i] * u[d];
+        }
         T v[Q];
 #pragma unroll
         for (int j = 0; j < Q; ++j) {
           const T fj = (IO::split && j == 0) ? (T)I.f0[fbs][(size_t)i * N + n]
                                              : IO::ld(fs, (size_t)(i * Q + j) * N + n, T(SC_F));
-          const T cu = T(cx(j)) * pux + T(cy(j)) * puy;
-          const T feq = j == 0 ? ph[i] - (T(1) - wgt<T>(0)) * muc[i] : wgt<T>(j) * muc[i] + wgt<T>(j) * cu * T(3);
-          const T Fj = wgt<T>(j) * (T(cx(j)) * dtx + T(cy(j)) * dty);
+          const T cu = cdot<L>(j, pu);
+          const T feq = j == 0 ? ph[i] - (T(1) - lw<L, T>(0)) * muc[i] : lw<L, T>(j) * muc[i] + lw<L, T>(j) * cu * T(3);
+          const T Fj = lw<L, T>(j) * cdot<L>(j, dt);
           v[j] = fj - (fj - feq) * itf + cf * Fj;
         }
-        const T moved = push<T, S>(fd + (size_t)i * Q * N, v, I, x, y, n, 0, ph[i], P.wall_u[0], P.wall_u[1],
-                                   T(0), T(0), T(SC_F), IO::split);
+        const T moved = push<L, T, S>(fd + (size_t)i * Q * N, v, I, nd, 0, ph[i], P.wall_u[0], P.wall_u[1], T(0),
+                                      T(0), T(SC_F), IO::split);
         if (IO::split) {
           T tot = 0;
 #pragma unroll
@@ -798,15 +903,15 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
       T v[Q];
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
-        const T cu = T(cx(j)) * ux + T(cy(j)) * uy;
-        const T sj = wgt<T>(j) * (cu * T(3) + cu * cu * T(4.5) - usq * T(1.5));
-        const T geq = (j == 0 ? (wgt<T>(0) - T(1)) * pp * T(3) : wgt<T>(j) * pp * T(3)) + rho * sj;
-        const T cF = T(cx(j)) * Fx + T(cy(j)) * Fy;
-        const T cgr = T(cx(j)) * grx + T(cy(j)) * gry;
-        const T Gb = wgt<T>(j) * (udr + cF * T(3) + (cu * cgr - udr / T(3)) * T(3));
+        const T cu = cdot<L>(j, u);
+        const T sj = lw<L, T>(j) * (cu * T(3) + cu * cu * T(4.5) - usq * T(1.5));
+        const T geq = (j == 0 ? (lw<L, T>(0) - T(1)) * pp * T(3) : lw<L, T>(j) * pp * T(3)) + rho * sj;
+        const T cF = cdot<L>(j, F);
+        const T cgr = cdot<L>(j, gr);
+        const T Gb = lw<L, T>(j) * (udr + cF * T(3) + (cu * cgr - udr / T(3)) * T(3));
         v[j] = g[j] - (g[j] - geq) * itg + cg * Gb;
       }
-      push<T, S>((S *)I.g[nc], v, I, x, y, n, 0, rho, P.wall_u[0], P.wall_u[1], T(0), T(0), T(SC_G), false);
+      push<L, T, S>((S *)I.g[nc], v, I, nd, 0, rho, P.wall_u[0], P.wall_u[1], T(0), T(0), T(SC_G), false);
     }
 
     // charge family
@@ -818,15 +923,15 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
         const T lj = IO::ld(ls, (size_t)j * N + n, T(SC_L));
-        const T cu = T(cx(j)) * ux + T(cy(j)) * uy;
-        const T leq = wgt<T>(j) * q * (T(1) + cu * T(3));
-        const T Sj = cl * wgt<T>(j) * R;
-        const T Tj = cl * wgt<T>(j) * (T(cx(j)) * dqx + T(cy(j)) * dqy) * T(3);
+        const T cu = cdot<L>(j, u);
+        const T leq = lw<L, T>(j) * q * (T(1) + cu * T(3));
+        const T Sj = cl * lw<L, T>(j) * R;
+        const T Tj = cl * lw<L, T>(j) * cdot<L>(j, dq) * T(3);
         v[j] = lj - (lj - leq) * itl + Sj + Tj;
       }
       const int mode = I.wall_q_mode == 1 ? 1 : 0;
-      push<T, S>((S *)I.l[nc], v, I, x, y, n, mode, q, P.wall_u[0], P.wall_u[1], P.wall_q[0], P.wall_q[1],
-                 T(SC_L), false);
+      push<L, T, S>((S *)I.l[nc], v, I, nd, mode, q, P.wall_u[0], P.wall_u[1], P.wall_q[0], P.wall_q[1],
+                    T(SC_L), false);
     }
   }
 }
@@ -835,11 +940,12 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
 
 // Permittivity of the initial order parameters and the potential
 // populations at the equilibrium of the initial guess (Eq. 44).
-template <typename T>
+template <class L, typename T>
 __global__ __launch_bounds__(NT) void k_init_potential(const Inst *__restrict__ insts, const int2 *__restrict__ b2i) {
+  constexpr int Q = L::Q;
   const Inst *Ip;
   int lblk;
-  const Node nd = locate(insts, b2i, Ip, lblk);
+  const Node nd = locate<L>(insts, b2i, Ip, lblk);
   if (!nd.valid) return;
   const Inst &I = *Ip;
   const Phys<T> &P = phys<T>(I);
@@ -849,17 +955,18 @@ __global__ __launch_bounds__(NT) void k_init_potential(const Inst *__restrict__ 
   const T v = ((const T *)I.psi)[n];
   T *h = (T *)I.h[I.ctl->hcur];
 #pragma unroll
-  for (int j = 0; j < Q; ++j) h[(size_t)j * N + n] = j == 0 ? (wgt<T>(0) - T(1)) * v : wgt<T>(j) * v;
+  for (int j = 0; j < Q; ++j) h[(size_t)j * N + n] = j == 0 ? (lw<L, T>(0) - T(1)) * v : lw<L, T>(j) * v;
 }
 
 // Equilibria of the initial fields (p = 0) into buffer 0 and the history
 // planes; block 0 folds the cold start's buffer parity hofs into ctl->hcur.
-template <typename T, typename S>
+template <class L, typename T, typename S>
 __global__ __launch_bounds__(NT) void k_init_pops(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
                                                   int hofs) {
+  constexpr int Q = L::Q, D = L::D;
   const Inst *Ip;
   int lblk;
-  const Node nd = locate(insts, b2i, Ip, lblk);
+  const Node nd = locate<L>(insts, b2i, Ip, lblk);
   const Inst &I = *Ip;
   if (lblk == 0 && threadIdx.x == 0) I.ctl->hcur ^= hofs;
   if (!nd.valid) return;
@@ -867,8 +974,12 @@ __global__ __launch_bounds__(NT) void k_init_pops(const Inst *__restrict__ insts
   const int N = I.N, n = nd.n, pc = 0;
   const T *phi = (const T *)I.phi;
   const T *mu = (const T *)I.mu;
-  const T ux = ((const T *)I.u)[n], uy = ((const T *)I.u)[(size_t)N + n];
-  const T usq = ux * ux + uy * uy;
+  T u[D], usq = 0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    u[d] = ((const T *)I.u)[(size_t)d * N + n];
+    usq += u[d] * u[d];
+  }
   const T q = ((const T *)I.q)[n];
   T rho = 0;
   using IO = PopIO<S, T>;
@@ -881,27 +992,27 @@ __global__ __launch_bounds__(NT) void k_init_pops(const Inst *__restrict__ insts
     T moved = 0;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-      const T cu = T(cx(j)) * ph * ux + T(cy(j)) * ph * uy;
-      const T feq = j == 0 ? ph - (T(1) - wgt<T>(0)) * m : wgt<T>(j) * m + wgt<T>(j) * cu * T(3);
+      const T cu = ph * cdot<L>(j, u);
+      const T feq = j == 0 ? ph - (T(1) - lw<L, T>(0)) * m : lw<L, T>(j) * m + lw<L, T>(j) * cu * T(3);
       if (IO::split && j == 0) continue;
       const S st = IO::cv(feq, T(SC_F));
       f[(size_t)(i * Q + j) * N + n] = st;
       moved += IO::back(st, T(SC_F));
     }
     if (IO::split) I.f0[pc][(size_t)i * N + n] = (float)(ph - moved);
-    hpu[(size_t)(2 * i) * N + n] = ph * ux;
-    hpu[(size_t)(2 * i + 1) * N + n] = ph * uy;
+#pragma unroll
+    for (int d = 0; d < D; ++d) hpu[(size_t)(i * D + d) * N + n] = ph * u[d];
   }
   S *g = (S *)I.g[pc];
   S *l = (S *)I.l[pc];
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
-    const T cu = T(cx(j)) * ux + T(cy(j)) * uy;
-    g[(size_t)j * N + n] = IO::cv(rho * wgt<T>(j) * (cu * T(3) + cu * cu * T(4.5) - usq * T(1.5)), T(SC_G));
-    l[(size_t)j * N + n] = IO::cv(wgt<T>(j) * q * (T(1) + cu * T(3)), T(SC_L));
+    const T cu = cdot<L>(j, u);
+    g[(size_t)j * N + n] = IO::cv(rho * lw<L, T>(j) * (cu * T(3) + cu * cu * T(4.5) - usq * T(1.5)), T(SC_G));
+    l[(size_t)j * N + n] = IO::cv(lw<L, T>(j) * q * (T(1) + cu * T(3)), T(SC_L));
   }
-  ((T *)I.hqu)[n] = q * ux;
-  ((T *)I.hqu)[(size_t)N + n] = q * uy;
+#pragma unroll
+  for (int d = 0; d < D; ++d) ((T *)I.hqu)[(size_t)d * N + n] = q * u[d];
   ((T *)I.p)[n] = T(0);
   ((T *)I.rho)[n] = rho;
   ((T *)I.R)[n] = T(0);
@@ -918,9 +1029,10 @@ __global__ __launch_bounds__(NT) void k_convert(const Tin *__restrict__ src, Tou
 
 // Populations of the current level of instance `inst`, family fam (0 f,
 // 1 g, 2 l, 3 h), as plain numbers [planes][N] of type Tout.
-template <typename T, typename S, typename Tout>
+template <class L, typename T, typename S, typename Tout>
 __global__ __launch_bounds__(NT) void k_export_pops(const Inst *__restrict__ insts, int inst, int fam, int pc,
                                                     Tout *__restrict__ dst) {
+  constexpr int Q = L::Q;
   using IO = PopIO<S, T>;
   const Inst &I = insts[inst];
   const int n = blockIdx.x * NT + threadIdx.x;
@@ -929,7 +1041,7 @@ __global__ __launch_bounds__(NT) void k_export_pops(const Inst *__restrict__ ins
   if (fam == 0) {
     const int fb = fbuf(I, pc);
     const S *f = (const S *)I.f[fb];
-    for (int j = 0; j < 27; ++j) {
+    for (int j = 0; j < 3 * Q; ++j) {
       const T v = (IO::split && j % Q == 0) ? (T)I.f0[fb][(j / Q) * N + n] : IO::ld(f, j * N + n, T(SC_F));
       dst[j * N + n] = (Tout)v;
     }
@@ -965,7 +1077,7 @@ __global__ __launch_bounds__(NT) void k_tangent(const DualD *__restrict__ src, T
 // Seeded directional derivative, first pass: per block, sum over the
 // selected planes of seed * tangent (planes: pointers to [N] dual planes).
 struct SeedPlanes {
-  const DualD *plane[16];
+  const DualD *plane[18];
   int count;
 };
 __global__ __launch_bounds__(NT) void k_seed_dot(const Inst *__restrict__ insts, SeedPlanes sp,
@@ -990,11 +1102,12 @@ __global__ __launch_bounds__(NT) void k_reduce_seed_dot(const Inst *__restrict__
 // Diagnostics, first pass: masses, charge, max |sum phi - 1|, non-finite
 // populations and the raw second moments of the outer (1 - phi1) and inner
 // (phi3) indicators, per block.
-template <typename T, typename S>
+template <class L, typename T, typename S>
 __global__ __launch_bounds__(NT) void k_diag(const Inst *__restrict__ insts, const int2 *__restrict__ b2i, int pc) {
+  constexpr int Q = L::Q;
   const Inst *Ip;
   int lblk;
-  const Node nd = locate(insts, b2i, Ip, lblk);
+  const Node nd = locate<L>(insts, b2i, Ip, lblk);
   const Inst &I = *Ip;
   double v[15];
 #pragma unroll
@@ -1013,7 +1126,7 @@ __global__ __launch_bounds__(NT) void k_diag(const Inst *__restrict__ insts, con
     int bad = 0;
     const int fb = fbuf(I, pc);
     const S *f = (const S *)I.f[fb];
-    for (int j = 0; j < 27; ++j) {
+    for (int j = 0; j < 3 * Q; ++j) {
       const T v = (IO::split && j % Q == 0) ? (T)I.f0[fb][(size_t)(j / Q) * N + n]
                                              : IO::ld(f, (size_t)j * N + n, T(SC_F));
       bad += !isfinite((double)v);

@@ -323,9 +323,10 @@ def applied_field(cfg: dict):
     walls = int(cfg.get("bc_y", 0)) == 1
     wp = cfg.get("wall_phi", (0.0, 0.0))
     ex, ey = cfg.get("E_ext", (0.0, 0.0))
+    ez = float(cfg.get("E_ext_z", 0.0)) if int(cfg.get("lattice", 0)) == 1 else 0.0
     ey = ey + ((wp[0] - wp[1]) / cfg["ny"] if walls else 0.0)
     mean = 0.5 * (wp[0] + wp[1]) if walls else 0.0
-    return math.hypot(ex, ey), mean
+    return math.sqrt(ex * ex + ey * ey + ez * ez), mean
 
 
 def theta_of(cfg: dict):
@@ -345,6 +346,7 @@ def with_theta(cfg: dict, init: dict, theta):
     if E0 > 0:
         r = t[4] / E0
         c["E_ext"] = tuple(v * r for v in cfg.get("E_ext", (0.0, 0.0)))
+        c["E_ext_z"] = float(cfg.get("E_ext_z", 0.0)) * r
         if int(cfg.get("bc_y", 0)) == 1:
             c["wall_phi"] = tuple(mean + (v - mean) * r for v in cfg["wall_phi"])
         if init.get("psi0") is not None:

@@ -1,0 +1,166 @@
+"""Parity of the D3Q15 kernels (through the C ABI) with the FP64 oracle on
+3-D boxes: FP64 to rounding, FP32 and FP16-shifted storage within the
+per-field bounds of the D2Q9 tests (the same arithmetic per node, 15
+velocities instead of 9).  Boxes span several 256-node blocks with ragged
+tails, walls and periodic y, fixed and residual-controlled potential
+sub-iterations; batches, graph replay, diagnostics and forward-mode
+gradients run on 3-D handles too."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+from oracle import Oracle  # noqa: E402
+from paper_2608_05787_amd import binding, inputs  # noqa: E402
+
+from test_gpu_parity import FP16_TOL, FP32_TOL, FP64_TOL, rel_err, rel_l2  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+FIELDS3 = ["phi1", "phi2", "phi3", "rho", "ux", "uy", "uz", "p", "psi", "Ex", "Ey", "Ez", "q",
+           "mu1", "mu2", "mu3", "eps", "R"]
+
+
+def _tol3(t):
+    if not isinstance(t, dict):
+        return t
+    t = dict(t)
+    t["uz"], t["Ez"] = t["ux"], t["Ex"]
+    return t
+
+
+def compare3(sim, ref, tol, pops=True):
+    metric = rel_err if not isinstance(tol, dict) else rel_l2
+    tol = _tol3(tol)
+    got = {k: v.cpu().numpy() for k, v in sim.fields(FIELDS3).items()}
+    errs = {k: metric(got[k], ref.field(k)) for k in FIELDS3}
+    if pops:
+        for fam in "fglh":
+            errs["pop_" + fam] = metric(sim.populations(fam).cpu().numpy(), ref.pops(fam))
+    lim = (lambda k: tol[k]) if isinstance(tol, dict) else (lambda k: tol)
+    bad = {k: v for k, v in errs.items() if not v <= lim(k)}
+    assert not bad, (bad, errs)
+    return errs
+
+
+CASES3 = [(11, 10, 9, True), (8, 8, 8, False), (20, 12, 6, True)]
+
+
+@pytest.mark.parametrize("nx,ny,nz,walls", CASES3)
+def test_d3q15_fp64_matches_oracle(nx, ny, nz, walls):
+    print("case d3q15 fp64", nx, ny, nz, walls, flush=True)
+    p, init = inputs.parity_case3d(nx, ny, nz, seed=nx + ny + nz, walls=walls)
+    ref = Oracle(p, init)
+    sim = binding.Sim(p, init, precision="fp64")
+    compare3(sim, ref, FP64_TOL)
+    ref.step(8)
+    sim.step(8)
+    compare3(sim, ref, FP64_TOL)
+
+
+@pytest.mark.parametrize("K", [1, 3])
+def test_d3q15_fp64_potential_counts_and_adaptive(K):
+    print("case d3q15 K", K, flush=True)
+    p, init = inputs.parity_case3d(13, 11, 7, seed=K, sub=(K, K, 0.0))
+    ref = Oracle(p, init)
+    sim = binding.Sim(p, init, precision="fp64")
+    ref.step(5)
+    sim.step(5)
+    compare3(sim, ref, FP64_TOL)
+    p, init = inputs.parity_case3d(13, 11, 7, seed=10 + K, sub=(1, 25, 1e-6))
+    ref = Oracle(p, init)
+    sim = binding.Sim(p, init, precision="fp64")
+    ref.step(4)
+    sim.step(4)
+    compare3(sim, ref, FP64_TOL)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16s"])
+def test_d3q15_reduced_precision_matches_oracle(prec):
+    print("case d3q15", prec, flush=True)
+    p, init = inputs.parity_case3d(20, 12, 6, seed=4)
+    ref = Oracle(p, init)
+    sim = binding.Sim(p, init, precision=prec)
+    m0 = [ref.field("phi%d" % i).sum() for i in (1, 2, 3)]
+    ref.step(10)
+    sim.step(10)
+    compare3(sim, ref, FP32_TOL if prec == "fp32" else FP16_TOL)
+    f = sim.fields(["phi1", "phi2", "phi3"])
+    for i in (1, 2, 3):
+        assert abs(float(f["phi%d" % i].sum()) - m0[i - 1]) <= 1e-6 * abs(m0[i - 1])
+
+
+def test_d3q15_batch_and_graph_bitwise():
+    """A batch of 3-D boxes equals separate runs, and graph replays equal
+    kernel-by-kernel launches, bitwise."""
+    print("case d3q15 batch/graph", flush=True)
+    cases = [inputs.parity_case3d(n, m, k, seed=n) for n, m, k in ((12, 10, 8), (9, 7, 5), (16, 8, 4))]
+    cfgs = [c[0] for c in cases]
+    inits = [c[1] for c in cases]
+    batch = binding.Sim(cfgs, inits, precision="fp32")
+    batch.step(6)
+    for i, (c, ini) in enumerate(cases):
+        alone = binding.Sim(c, ini, precision="fp32")
+        alone.step(6)
+        for fam in "fglh":
+            assert torch.equal(batch.populations(fam, inst=i), alone.populations(fam)), (i, fam)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    a = binding.Sim(cfgs, inits, precision="fp32", stream=s1)
+    b = binding.Sim(cfgs, inits, precision="fp32", stream=s2)
+    b.graph(4)
+    a.step(9)
+    b.step(9)
+    for inst in range(3):
+        for fam in "fglh":
+            assert torch.equal(a.populations(fam, inst=inst), b.populations(fam, inst=inst)), (inst, fam)
+
+
+def test_d3q15_diagnostics_and_mass():
+    print("case d3q15 diagnostics", flush=True)
+    p, init = inputs.field_compound_drop3d(32, r_shell=10.0, r_core=6.0, init_iters=100)
+    sim = binding.Sim(p, init, precision="fp32")
+    d0 = sim.diagnostics()
+    sim.step(40)
+    d1 = sim.diagnostics()
+    f = {k: v.cpu().numpy().astype(np.float64) for k, v in sim.fields(["phi1", "phi2", "phi3"]).items()}
+    for i in range(3):
+        np.testing.assert_allclose(d1["mass%d" % (i + 1)], f["phi%d" % (i + 1)].sum(), rtol=1e-9)
+        np.testing.assert_allclose(d1["mass%d" % (i + 1)], d0["mass%d" % (i + 1)], rtol=2e-6)
+    s = f["phi1"] + f["phi2"] + f["phi3"]
+    np.testing.assert_allclose(d1["max_sum_dev"], np.abs(s - 1).max(), rtol=1e-6, atol=1e-12)
+    assert d1["nonfinite"] == 0 and d1["status"] == 0
+
+
+def test_d3q15_tangent_gradient_matches_fd():
+    """Forward-mode gradients run on D3Q15 handles: the tangent of a 3-D run
+    matches central differences of FP64 3-D runs."""
+    print("case d3q15 tangent", flush=True)
+    p, init = inputs.parity_case3d(12, 10, 6, seed=21, sub=(2, 2, 0.0))
+    steps = 12
+    rng = np.random.default_rng(0)
+    seed = {k: rng.standard_normal((6, 10, 12)) for k in ("phi1", "q", "uz")}
+    sim = binding.Sim(p, init, precision="fp64")
+    g = np.array(sim.tangent_gradient(steps, {k: torch.from_numpy(v) for k, v in seed.items()}))
+
+    def J(cfg, ini):
+        s = binding.Sim(cfg, ini, precision="fp64")
+        s.step(steps)
+        f = s.fields(list(seed))
+        return sum(float((f[k].cpu().numpy() * v).sum()) for k, v in seed.items())
+
+    th = inputs.theta_of(p)
+    fd = []
+    for k in range(5):
+        h = 1e-3 * th[k]
+        tp, tm = list(th), list(th)
+        tp[k] += h
+        tm[k] -= h
+        fd.append((J(*inputs.with_theta(p, init, tp)) - J(*inputs.with_theta(p, init, tm))) / (2 * h))
+    fd = np.array(fd)
+    assert np.all(np.abs(g - fd) <= 1e-4 * np.abs(fd) + 1e-7 * np.abs(fd).max()), (g, fd)
+
+
+def test_d3q15_reverse_mode_refused():
+    p, init = inputs.parity_case3d(8, 8, 8, seed=1)
+    sim = binding.Sim(p, init, precision="fp64")
+    with pytest.raises(binding.LbmEhdError):
+        sim.record(4, 2)
