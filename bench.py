@@ -27,23 +27,24 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def bytes_per_node(kernel, prec="fp32"):
+def bytes_per_node(kernel, prec="fp32", Q=9, D=2):
     """Algorithmic HBM bytes per node and launch: what a kernel must read and
     write once (stencil neighbours and recomputed tile rings come from L2).
-    T = macroscopic element size; populations f (27), g (9), l (9) are T
-    wide, except FP16S: f^i_0 FP32 and the other 42 populations 2 bytes."""
+    T = macroscopic element size; populations f (3Q), g (Q), l (Q) are T
+    wide, except FP16S: f^i_0 FP32 and the other populations 2 bytes.
+    Q, D: the velocity set (9, 2 for D2Q9; 15, 3 for D3Q15)."""
     t = 8 if prec == "fp64" else 4
-    s = {"fp64": 8, "fp32": 4, "fp16s": 2}[prec]             # moving/flow/charge population size
-    fpops = 3 * (t if prec != "fp16s" else 4) + 24 * s      # f: rest populations + 24 others
-    pops = fpops + 18 * s                                    # + g (9) + l (9)
+    s = {"fp64": 8, "fp32": 4, "fp16s": 2}[prec]                  # moving/flow/charge population size
+    fpops = 3 * (t if prec != "fp16s" else 4) + 3 * (Q - 1) * s  # f: rest populations + moving ones
+    pops = fpops + 2 * Q * s                                      # + g (Q) + l (Q)
     return {
-        "moments": fpops + 9 * s + 4 * t,            # f, l in; phi, l-sum out
-        "pre": (3 + 1 + 2) * t + 3 * t,              # phi, l-sum, E in; eps, q, R out
-        "poisson": (9 + 1 + 1) * t + 9 * t,          # h, eps, q in; h out (one sub-iteration)
-        "poisson2": (9 + 1 + 1) * t + 9 * t,         # the same for two sub-iterations per launch
-        "mu": (9 + 1 + 1 + 3) * t + (1 + 2 + 3) * t,  # h, eps, psi, phi in; psi, E, mu out
-        # pops in and out; phi, mu, q, R, E, history in; history out
-        "collide": 2 * pops + (3 + 3 + 1 + 1 + 2 + 8) * t + 8 * t,
+        "moments": fpops + Q * s + 4 * t,                  # f, l in; phi, l-sum out
+        "pre": (3 + 1 + D) * t + 3 * t,                    # phi, l-sum, E in; eps, q, R out
+        "poisson": (Q + 1 + 1) * t + Q * t,                # h, eps, q in; h out (one sub-iteration)
+        "poisson2": (Q + 1 + 1) * t + Q * t,               # the same for two sub-iterations per launch
+        "mu": (Q + 1 + 1 + 3) * t + (1 + D + 3) * t,        # h, eps, psi, phi in; psi, E, mu out
+        # pops in and out; phi, mu, q, R, E, history (phi_i u, q u) in; history out
+        "collide": 2 * pops + (3 + 3 + 1 + 1 + D + 4 * D) * t + 4 * D * t,
     }[kernel]
 
 
@@ -210,6 +211,41 @@ def batch_bench(n_inst, steps, sub, init_iters, graph_len=10):
             "mlups_sequential": mlups(ms_seq), "speedup_graph_vs_sequential": round(ms_seq / ms_graph, 2)}
 
 
+def d3q15_bench(n, steps, warmup, sub, init_iters, profile_steps):
+    """The field-driven compound drop on the D3Q15 lattice (n^3 box, radii
+    0.3125 n and 0.234 n): FP32 MLUPS, per-kernel average launch times and
+    their algorithmic GB/s, and the FP16S and FP64 rates."""
+    import torch
+    from paper_2608_05787_amd import inputs
+    p, init = inputs.field_compound_drop3d(n, r_shell=0.3125 * n, r_core=0.234375 * n, sub=(sub, sub, 0.0),
+                                           init_iters=init_iters)
+    nodes = n ** 3
+    out = {"workload": "field compound drop %d^3 on D3Q15 (electrodes, Ca_e 0.2, eps ratios 2/0.5, "
+                       "sigma ratios 3/0.3, radii %.0f/%.0f)" % (n, 0.3125 * n, 0.234375 * n),
+           "nodes": nodes, "potential_subiterations": sub}
+    for prec in ("fp32", "fp16s", "fp64"):
+        k = steps if prec != "fp64" else max(steps // 2, 1)
+        sim, ms, prof, diag = run_gpu(p, init, prec, k, warmup, profile_steps if prec == "fp32" else 0)
+        step_bytes = sum(bytes_per_node(kk, prec, 15, 3) * (sub if kk == "poisson" else 1)
+                         for kk in ("moments", "pre", "poisson", "mu", "collide"))
+        out[prec] = {"mlups": round(nodes * k / (ms * 1e-3) / 1e6, 1), "ms_per_step": ms / k,
+                     "bytes_per_node_update": step_bytes,
+                     "effective_gbs": round(step_bytes * nodes * k / (ms * 1e-3) / 1e9, 1)}
+        if prof:
+            kern = {}
+            for name, (tot, cnt) in prof.items():
+                if cnt:
+                    avg = 1e3 * tot / cnt
+                    kern[name] = {"avg_us": round(avg, 2), "launches": cnt}
+                    if name in ("moments", "pre", "poisson", "mu", "collide"):
+                        kern[name]["gbs"] = round(bytes_per_node(name, prec, 15, 3) * nodes / (avg * 1e-6) / 1e9, 1)
+            out[prec]["kernels"] = kern
+            out[prec]["diagnostics"] = {kk: diag[kk] for kk in ("max_sum_dev", "D_outer", "D_inner", "nonfinite")}
+        del sim
+        torch.cuda.empty_cache()
+    return out
+
+
 def gradient_bench(n, steps, sub, init_iters, every):
     """Gradient of the outer deformation after `steps` steps with respect to
     the five parameters on the adjoint workload (n x n, radii 40/30) by the
@@ -281,6 +317,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--grad-steps", type=int, default=5000, help="0 skips the gradient leg")
     ap.add_argument("--grad-every", type=int, default=250, help="checkpoint interval of the reverse sweep")
+    ap.add_argument("--n3", type=int, default=128, help="edge of the D3Q15 box (0 skips the 3-D leg)")
     ap.add_argument("--gradient-only", action="store_true",
                     help="run only the gradient leg (for profiling) and print its JSON object")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -366,6 +403,12 @@ def main():
         log("gradient (adjoint workload)")
         grad = gradient_bench(512, args.grad_steps, args.sub, 2000, args.grad_every)
 
+    d3 = None
+    if args.n3 > 0 and not args.no_variants:
+        log("D3Q15 leg")
+        d3 = d3q15_bench(args.n3, max(args.steps // 4, 10), max(args.warmup // 4, 5), args.sub, 1000,
+                         args.profile_steps)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -386,6 +429,7 @@ def main():
         "rel_l2_vs_fp64": errors,
         "batch_sweep": batch,
         "gradient": grad,
+        "d3q15": d3,
         "diagnostics": {k: diag[k] for k in ("max_sum_dev", "residual", "D_outer", "D_inner", "nonfinite")},
         "cpu_baseline": cpu,
     }
