@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lbm {
 
 // Forward-mode (tangent) arithmetic: a value and its derivative along one
@@ -121,6 +123,26 @@ struct Inst {
   Phys<DualD> pt;  // tangent mode: parameters with their derivatives along one direction
 };
 
+// Global-memory view of a state pointer.  The pointers live in the instance
+// descriptor, so the compiler cannot tell their address space and would emit
+// flat loads and stores, whose completion it can only wait for all at once;
+// global instructions complete in order and let loads stay in flight.
+// Arithmetic element types only: the tangent type keeps generic pointers
+// (its copy constructor cannot bind a global-memory reference), and FP16
+// storage is viewed as raw 16-bit words (PopIO converts).
+template <typename T>
+using gptr = typename std::conditional<std::is_arithmetic<typename std::remove_cv<T>::type>::value,
+                                       __attribute__((address_space(1))) T *, T *>::type;
+template <typename T> __device__ __forceinline__ gptr<T> gbl(T *p) { return (gptr<T>)p; }
+using gwords = __attribute__((address_space(1))) unsigned short *;
+using gcwords = const __attribute__((address_space(1))) unsigned short *;
+__device__ __forceinline__ gwords gbl(__half *p) { return (gwords)p; }
+__device__ __forceinline__ gcwords gbl(const __half *p) { return (gcwords)p; }
+__device__ __forceinline__ __half ld_half(const __half *p, size_t i) { return p[i]; }
+__device__ __forceinline__ __half ld_half(gcwords p, size_t i) { return __ushort_as_half(p[i]); }
+__device__ __forceinline__ __half ld_half(gwords p, size_t i) { return __ushort_as_half(p[i]); }
+__device__ __forceinline__ void st_half(__half *p, size_t i, __half v) { p[i] = v; }
+__device__ __forceinline__ void st_half(gwords p, size_t i, __half v) { p[i] = __half_as_ushort(v); }
 template <typename T> __device__ __forceinline__ const Phys<T> &phys(const Inst &I);
 template <> __device__ __forceinline__ const Phys<float> &phys<float>(const Inst &I) { return I.pf; }
 template <> __device__ __forceinline__ const Phys<double> &phys<double>(const Inst &I) { return I.pd; }
@@ -141,13 +163,17 @@ constexpr float SC_L = 65536.f;  // |l_j| < 1
 
 template <typename S, typename T> struct PopIO {
   static constexpr bool split = false;
-  __device__ static __forceinline__ T ld(const S *p, size_t i, T) { return (T)p[i]; }
+  template <typename P> __device__ static __forceinline__ T ld(P p, size_t i, T) { return (T)p[i]; }
+  template <typename P> __device__ static __forceinline__ void put(P p, size_t i, S v) { p[i] = v; }
   __device__ static __forceinline__ S cv(T v, T) { return (S)v; }
   __device__ static __forceinline__ T back(S s, T) { return (T)s; }
 };
 template <> struct PopIO<__half, float> {
   static constexpr bool split = true;
-  __device__ static __forceinline__ float ld(const __half *p, size_t i, float sc) { return __half2float(p[i]) / sc; }
+  template <typename P> __device__ static __forceinline__ float ld(P p, size_t i, float sc) {
+    return __half2float(ld_half(p, i)) / sc;
+  }
+  template <typename P> __device__ static __forceinline__ void put(P p, size_t i, __half v) { st_half(p, i, v); }
   __device__ static __forceinline__ __half cv(float v, float sc) { return __float2half_rn(v * sc); }
   __device__ static __forceinline__ float back(__half s, float sc) { return __half2float(s) / sc; }
 };
@@ -293,8 +319,8 @@ __device__ __forceinline__ void reduce_partials(const double *__restrict__ part,
 // mode 1: anti-bounce-back toward Dirichlet values (vb bottom, vt top).
 // sc: storage scale (FP16S); skip0: do not store the rest population.
 // Returns the sum of the moving populations as stored (after rounding).
-template <class L, typename T, typename S>
-__device__ __forceinline__ T push(S *__restrict__ dst, const T (&v)[L::Q], const Inst &I, const Node &nd,
+template <class L, typename T, typename S, typename P>
+__device__ __forceinline__ T push(P dst, const T (&v)[L::Q], const Inst &I, const Node &nd,
                                   int mode, T psi, T ub, T ut, T vb, T vt, T sc, bool skip0) {
   using IO = PopIO<S, T>;
   const int nx = I.nx, ny = I.ny, N = I.N, n = nd.n;
@@ -321,7 +347,7 @@ __device__ __forceinline__ T push(S *__restrict__ dst, const T (&v)[L::Q], const
     }
     if (j == 0 && skip0) continue;
     const S st = IO::cv(out, sc);
-    dst[idx] = st;
+    IO::put(dst, idx, st);
     if (j) moved += IO::back(st, sc);
   }
   return moved;
@@ -347,12 +373,12 @@ __global__ __launch_bounds__(NT) void k_moments(const Inst *__restrict__ insts, 
   const int N = I.N, n = nd.n;
   using IO = PopIO<S, T>;
   const int fb = fbuf(I, pc);
-  const S *f = (const S *)I.f[fb];
-  const S *l = (const S *)I.l[pc];
-  T *phi = (T *)I.phi;
+  auto f = gbl((const S *)I.f[fb]);
+  auto l = gbl((const S *)I.l[pc]);
+  auto phi = gbl((T *)I.phi);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    T a = IO::split ? (T)I.f0[fb][(size_t)i * N + n] : T(0);
+    T a = IO::split ? (T)gbl(I.f0[fb])[(size_t)i * N + n] : T(0);
 #pragma unroll
     for (int j = IO::split ? 1 : 0; j < Q; ++j) a += IO::ld(f, (size_t)(i * Q + j) * N + n, T(SC_F));
     phi[(size_t)i * N + n] = a;
@@ -361,7 +387,7 @@ __global__ __launch_bounds__(NT) void k_moments(const Inst *__restrict__ insts, 
   T b = 0;
 #pragma unroll
   for (int j = 0; j < Q; ++j) b += IO::ld(l, (size_t)j * N + n, T(SC_L));
-  ((T *)I.lsum)[n] = b;
+  (gbl((T *)I.lsum))[n] = b;
 }
 
 // a2 + a3: permittivity/conductivity stencils (Eq. 33 on the eps and sigma
@@ -378,7 +404,7 @@ __global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, cons
   const Inst &I = *Ip;
   const Phys<T> &P = phys<T>(I);
   const int N = I.N, n = nd.n;
-  const T *phi = (const T *)I.phi;
+  auto phi = gbl((const T *)I.phi);
   T ev[Q], sv[Q];
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
@@ -390,7 +416,7 @@ __global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, cons
   T ge[D], gs[D], dummy;
   fdq<L>(ev, ge, dummy);
   fdq<L>(sv, gs, dummy);
-  const T *E = (const T *)I.E;
+  auto E = gbl((const T *)I.E);
   T e[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) e[d] = E[(size_t)d * N + n];
@@ -402,10 +428,10 @@ __global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, cons
     gse += gs[d] * e[d];
   }
   const T Rp = se * gee - gse;
-  const T q = (((const T *)I.lsum)[n] + T(0.5) * Rp) / (T(1) + T(0.5) * se);
-  ((T *)I.q)[n] = q;
-  ((T *)I.R)[n] = -se * q + Rp;
-  ((T *)I.eps)[n] = ev[0];
+  const T q = ((gbl((const T *)I.lsum))[n] + T(0.5) * Rp) / (T(1) + T(0.5) * se);
+  (gbl((T *)I.q))[n] = q;
+  (gbl((T *)I.R))[n] = -se * q + Rp;
+  (gbl((T *)I.eps))[n] = ev[0];
   if (rc.q) {
     rc.q[n] = q;
     rc.R[n] = -se * q + Rp;
@@ -473,20 +499,20 @@ __global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, 
   double red[2] = {0.0, 0.0};
   if (nd.valid) {
     const int N = I.N, n = nd.n;
-    const T *src = (const T *)I.h[hc];
-    T *dst = (T *)I.h[hc ^ 1];
+    auto src = gbl((const T *)I.h[hc]);
+    auto dst = gbl((T *)I.h[hc ^ 1]);
     T h[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) h[j] = src[(size_t)j * N + n];
     if (rec_in)
 #pragma unroll
       for (int j = 0; j < Q; ++j) rec_in[(size_t)j * N + n] = h[j];
-    const T epshat = ((const T *)I.eps)[n] - P.eps_ref;
-    const T q = ((const T *)I.q)[n];
+    const T epshat = (gbl((const T *)I.eps))[n] - P.eps_ref;
+    const T q = (gbl((const T *)I.q))[n];
     T v[Q];
     const T pot = poisson_collide<L>(h, epshat, q, P, v);
     if (write_psi) {
-      T *psi = (T *)I.psi;
+      auto psi = gbl((T *)I.psi);
       if (resid) {
         const double d = (double)pot - (double)psi[n];
         red[0] = d * d;
@@ -531,8 +557,8 @@ __global__ __launch_bounds__(P2NT) void k_poisson2(const Inst *__restrict__ inst
   const Phys<T> &P = phys<T>(I);
   const int nx = I.nx, ny = I.ny, N = I.N, walls = I.bc_y;
   const int hc = I.ctl->hcur ^ hpar;
-  const T *src = (const T *)I.h[hc];
-  T *dst = (T *)I.h[hc ^ 1];
+  auto src = gbl((const T *)I.h[hc]);
+  auto dst = gbl((T *)I.h[hc ^ 1]);
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int gx = wrapx(((t.y - 2 + tx) % nx + nx) % nx, nx);
   T h[P2RPT][Q], eh[P2RPT], qq[P2RPT];
@@ -551,8 +577,8 @@ __global__ __launch_bounds__(P2NT) void k_poisson2(const Inst *__restrict__ inst
       const int n = y * nx + gx;
 #pragma unroll
       for (int j = 0; j < Q; ++j) h[k][j] = src[(size_t)j * N + n];
-      eh[k] = ((const T *)I.eps)[n] - P.eps_ref;
-      qq[k] = ((const T *)I.q)[n];
+      eh[k] = (gbl((const T *)I.eps))[n] - P.eps_ref;
+      qq[k] = (gbl((const T *)I.q))[n];
     } else {
 #pragma unroll
       for (int j = 0; j < Q; ++j) h[k][j] = T(0);
@@ -585,7 +611,7 @@ __global__ __launch_bounds__(P2NT) void k_poisson2(const Inst *__restrict__ inst
       const T pot = poisson_collide<D2Q9>(h[k], eh[k], qq[k], P, v);
       if (it == 1 && write_psi && inside[k] && r >= 2 && r < 2 + P2H && tx >= 2 && tx < 2 + P2W) {
         const int ux = t.y + tx - 2, uy = t.z + r - 2;
-        if (ux < nx && uy < ny) ((T *)I.psi)[gy[k] * nx + gx] = pot;
+        if (ux < nx && uy < ny) (gbl((T *)I.psi))[gy[k] * nx + gx] = pot;
       }
 #pragma unroll
       for (int j = 0; j < Q; ++j) buf[j * (P2EW * P2ER) + e] = v[j];
@@ -669,7 +695,7 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
   double red[2] = {0.0, 0.0};
   if (nd.valid) {
     const int N = I.N, n = nd.n;
-    const T *h = (const T *)I.h[ctl->hcur ^ hofs];
+    auto h = gbl((const T *)I.h[ctl->hcur ^ hofs]);
     T s1 = 0, m[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) m[d] = 0;
@@ -680,18 +706,18 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
 #pragma unroll
       for (int d = 0; d < D; ++d) m[d] += lc<L, T>(j, d) * v;
     }
-    const T eps = ((const T *)I.eps)[n];
+    const T eps = (gbl((const T *)I.eps))[n];
     const T pot = s1 / (T(1) - lw<L, T>(0));
     const T den = (eps - P.eps_ref) + P.tau_h / T(3);
     T e[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) e[d] = m[d] / den + P.Eext[d];
-    T *psi = (T *)I.psi;
+    auto psi = gbl((T *)I.psi);
     const double dd = (double)pot - (double)psi[n];
     red[0] = dd * dd;
     red[1] = (double)pot * (double)pot;
     psi[n] = pot;
-    T *E = (T *)I.E;
+    auto E = gbl((T *)I.E);
     T e2 = e[0] * e[0];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -699,8 +725,8 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
       if (rc.En) rc.En[(size_t)d * N + n] = e[d];
       if (d) e2 += e[d] * e[d];
     }
-    const T *phi = (const T *)I.phi;
-    T *mu = (T *)I.mu;
+    auto phi = gbl((const T *)I.phi);
+    auto mu = gbl((T *)I.mu);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       T v[Q];
@@ -752,8 +778,8 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
   if (nd.valid) {
     const Phys<T> &P = phys<T>(I);
     const int N = I.N, n = nd.n;
-    const T *phi = (const T *)I.phi;
-    const T *mu = (const T *)I.mu;
+    auto phi = gbl((const T *)I.phi);
+    auto mu = gbl((const T *)I.mu);
     int m[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) m[j] = nbr<L>(I, nd, j);
@@ -782,8 +808,8 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
       muc[i] = v[0];
     }
     const T rho = rv[0];
-    const T q = ((const T *)I.q)[n];
-    const T *E = (const T *)I.E;
+    const T q = (gbl((const T *)I.q))[n];
+    auto E = gbl((const T *)I.E);
 
     // force and flow moments
     T F[D];
@@ -793,11 +819,41 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
 #pragma unroll
       for (int i = 0; i < 3; ++i) F[d] -= ph[i] * gm[i][d];
     }
+    // Every population and history value is loaded before the first store:
+    // the stores (to buffers the compiler cannot tell apart from the loaded
+    // ones) would otherwise hold back the loads issued after them.  With
+    // 8-byte values the CH populations are loaded per family instead (the
+    // early copy would halve the occupancy).
     using IO = PopIO<S, T>;
-    const S *gs = (const S *)I.g[pc];
-    T g[Q];
+    constexpr bool early = sizeof(T) <= 4;
+    const bool ch = I.phase_mode == 0;
+    const int fbs = fbuf(I, pc);
+    auto gs = gbl((const S *)I.g[pc]);
+    auto fs = gbl((const S *)I.f[fbs]);
+    auto ls = gbl((const S *)I.l[pc]);
+    auto hpu = gbl((T *)I.hpu);
+    auto hqu = gbl((T *)I.hqu);
+    T g[Q], fin[3][Q], lin[Q], hp0[3][D], hq0[D];
 #pragma unroll
     for (int j = 0; j < Q; ++j) g[j] = IO::ld(gs, (size_t)j * N + n, T(SC_G));
+    auto ldf = [&](int i, int j) -> T {
+      return (IO::split && j == 0) ? (T)gbl(I.f0[fbs])[(size_t)i * N + n]
+                                   : IO::ld(fs, (size_t)(i * Q + j) * N + n, T(SC_F));
+    };
+    if (early && ch)
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < Q; ++j) fin[i][j] = ldf(i, j);
+#pragma unroll
+    for (int j = 0; j < Q; ++j) lin[j] = IO::ld(ls, (size_t)j * N + n, T(SC_L));
+    const T R = (gbl((const T *)I.R))[n];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int d = 0; d < D; ++d) hp0[i][d] = hpu[(size_t)(i * D + d) * N + n];
+#pragma unroll
+    for (int d = 0; d < D; ++d) hq0[d] = hqu[(size_t)d * N + n];
     if (rc.g)
 #pragma unroll
       for (int j = 0; j < Q; ++j) rc.g[(size_t)j * N + n] = g[j];
@@ -823,37 +879,34 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
     const T pp = (s1 + T(0.5) * udr + rho * s0) / (T(3) * (T(1) - lw<L, T>(0)));
     if (write_macro) {
 #pragma unroll
-      for (int d = 0; d < D; ++d) ((T *)I.u)[(size_t)d * N + n] = u[d];
-      ((T *)I.p)[n] = pp;
-      ((T *)I.rho)[n] = rho;
+      for (int d = 0; d < D; ++d) (gbl((T *)I.u))[(size_t)d * N + n] = u[d];
+      (gbl((T *)I.p))[n] = pp;
+      (gbl((T *)I.rho))[n] = rho;
     }
 
     // history of phi_i u and q u (first-order time derivatives)
-    T *hpu = (T *)I.hpu;
-    T *hqu = (T *)I.hqu;
     T dp[3][D], dq[D];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         const T a = ph[i] * u[d];
-        dp[i][d] = a - hpu[(size_t)(i * D + d) * N + n];
+        dp[i][d] = a - hp0[i][d];
         hpu[(size_t)(i * D + d) * N + n] = a;
       }
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const T a = q * u[d];
-      dq[d] = a - hqu[(size_t)d * N + n];
+      dq[d] = a - hq0[d];
       hqu[(size_t)d * N + n] = a;
     }
 
     const int nc = pc ^ 1;
     // three CH families
-    if (I.phase_mode == 0) {
+    if (ch) {
       const T m0 = P.m0, itf = T(1) / P.tau_f, cf = T(1) - T(0.5) * itf;
-      const int fbs = fbuf(I, pc), fbd = fbuf(I, nc);
-      const S *fs = (const S *)I.f[fbs];
-      S *fd = (S *)I.f[fbd];
+      const int fbd = fbuf(I, nc);
+      auto fd = gbl((S *)I.f[fbd]);
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         // degenerate mobility row i: M_ik = -m0 phi_i phi_k, M_ii = -sum_k M_ik
@@ -878,8 +931,7 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
         T v[Q];
 #pragma unroll
         for (int j = 0; j < Q; ++j) {
-          const T fj = (IO::split && j == 0) ? (T)I.f0[fbs][(size_t)i * N + n]
-                                             : IO::ld(fs, (size_t)(i * Q + j) * N + n, T(SC_F));
+          const T fj = early ? fin[i][j] : ldf(i, j);
           const T cu = cdot<L>(j, pu);
           const T feq = j == 0 ? ph[i] - (T(1) - lw<L, T>(0)) * muc[i] : lw<L, T>(j) * muc[i] + lw<L, T>(j) * cu * T(3);
           const T Fj = lw<L, T>(j) * cdot<L>(j, dt);
@@ -891,7 +943,7 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
           T tot = 0;
 #pragma unroll
           for (int j = 0; j < Q; ++j) tot += v[j];
-          I.f0[fbd][(size_t)i * N + n] = (float)(tot - moved);
+          gbl(I.f0[fbd])[(size_t)i * N + n] = (float)(tot - moved);
         }
       }
     }
@@ -911,18 +963,16 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
         const T Gb = lw<L, T>(j) * (udr + cF * T(3) + (cu * cgr - udr / T(3)) * T(3));
         v[j] = g[j] - (g[j] - geq) * itg + cg * Gb;
       }
-      push<L, T, S>((S *)I.g[nc], v, I, nd, 0, rho, P.wall_u[0], P.wall_u[1], T(0), T(0), T(SC_G), false);
+      push<L, T, S>(gbl((S *)I.g[nc]), v, I, nd, 0, rho, P.wall_u[0], P.wall_u[1], T(0), T(0), T(SC_G), false);
     }
 
     // charge family
     {
-      const S *ls = (const S *)I.l[pc];
       const T itl = T(1) / P.tau_l, cl = T(1) - T(0.5) * itl;
-      const T R = ((const T *)I.R)[n];
       T v[Q];
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
-        const T lj = IO::ld(ls, (size_t)j * N + n, T(SC_L));
+        const T lj = lin[j];
         const T cu = cdot<L>(j, u);
         const T leq = lw<L, T>(j) * q * (T(1) + cu * T(3));
         const T Sj = cl * lw<L, T>(j) * R;
@@ -930,7 +980,7 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
         v[j] = lj - (lj - leq) * itl + Sj + Tj;
       }
       const int mode = I.wall_q_mode == 1 ? 1 : 0;
-      push<L, T, S>((S *)I.l[nc], v, I, nd, mode, q, P.wall_u[0], P.wall_u[1], P.wall_q[0], P.wall_q[1],
+      push<L, T, S>(gbl((S *)I.l[nc]), v, I, nd, mode, q, P.wall_u[0], P.wall_u[1], P.wall_q[0], P.wall_q[1],
                     T(SC_L), false);
     }
   }
@@ -950,10 +1000,10 @@ __global__ __launch_bounds__(NT) void k_init_potential(const Inst *__restrict__ 
   const Inst &I = *Ip;
   const Phys<T> &P = phys<T>(I);
   const int N = I.N, n = nd.n;
-  const T *phi = (const T *)I.phi;
-  ((T *)I.eps)[n] = P.eps[0] * herm(phi[n]) + P.eps[1] * herm(phi[(size_t)N + n]) + P.eps[2] * herm(phi[(size_t)2 * N + n]);
-  const T v = ((const T *)I.psi)[n];
-  T *h = (T *)I.h[I.ctl->hcur];
+  auto phi = gbl((const T *)I.phi);
+  (gbl((T *)I.eps))[n] = P.eps[0] * herm(phi[n]) + P.eps[1] * herm(phi[(size_t)N + n]) + P.eps[2] * herm(phi[(size_t)2 * N + n]);
+  const T v = (gbl((const T *)I.psi))[n];
+  auto h = gbl((T *)I.h[I.ctl->hcur]);
 #pragma unroll
   for (int j = 0; j < Q; ++j) h[(size_t)j * N + n] = j == 0 ? (lw<L, T>(0) - T(1)) * v : lw<L, T>(j) * v;
 }
@@ -972,19 +1022,19 @@ __global__ __launch_bounds__(NT) void k_init_pops(const Inst *__restrict__ insts
   if (!nd.valid) return;
   const Phys<T> &P = phys<T>(I);
   const int N = I.N, n = nd.n, pc = 0;
-  const T *phi = (const T *)I.phi;
-  const T *mu = (const T *)I.mu;
+  auto phi = gbl((const T *)I.phi);
+  auto mu = gbl((const T *)I.mu);
   T u[D], usq = 0;
 #pragma unroll
   for (int d = 0; d < D; ++d) {
-    u[d] = ((const T *)I.u)[(size_t)d * N + n];
+    u[d] = (gbl((const T *)I.u))[(size_t)d * N + n];
     usq += u[d] * u[d];
   }
-  const T q = ((const T *)I.q)[n];
+  const T q = (gbl((const T *)I.q))[n];
   T rho = 0;
   using IO = PopIO<S, T>;
-  S *f = (S *)I.f[pc];
-  T *hpu = (T *)I.hpu;
+  auto f = gbl((S *)I.f[pc]);
+  auto hpu = gbl((T *)I.hpu);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const T ph = phi[(size_t)i * N + n], m = mu[(size_t)i * N + n];
@@ -996,26 +1046,26 @@ __global__ __launch_bounds__(NT) void k_init_pops(const Inst *__restrict__ insts
       const T feq = j == 0 ? ph - (T(1) - lw<L, T>(0)) * m : lw<L, T>(j) * m + lw<L, T>(j) * cu * T(3);
       if (IO::split && j == 0) continue;
       const S st = IO::cv(feq, T(SC_F));
-      f[(size_t)(i * Q + j) * N + n] = st;
+      IO::put(f, (size_t)(i * Q + j) * N + n, st);
       moved += IO::back(st, T(SC_F));
     }
-    if (IO::split) I.f0[pc][(size_t)i * N + n] = (float)(ph - moved);
+    if (IO::split) gbl(I.f0[pc])[(size_t)i * N + n] = (float)(ph - moved);
 #pragma unroll
     for (int d = 0; d < D; ++d) hpu[(size_t)(i * D + d) * N + n] = ph * u[d];
   }
-  S *g = (S *)I.g[pc];
-  S *l = (S *)I.l[pc];
+  auto g = gbl((S *)I.g[pc]);
+  auto l = gbl((S *)I.l[pc]);
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
     const T cu = cdot<L>(j, u);
-    g[(size_t)j * N + n] = IO::cv(rho * lw<L, T>(j) * (cu * T(3) + cu * cu * T(4.5) - usq * T(1.5)), T(SC_G));
-    l[(size_t)j * N + n] = IO::cv(lw<L, T>(j) * q * (T(1) + cu * T(3)), T(SC_L));
+    IO::put(g, (size_t)j * N + n, IO::cv(rho * lw<L, T>(j) * (cu * T(3) + cu * cu * T(4.5) - usq * T(1.5)), T(SC_G)));
+    IO::put(l, (size_t)j * N + n, IO::cv(lw<L, T>(j) * q * (T(1) + cu * T(3)), T(SC_L)));
   }
 #pragma unroll
-  for (int d = 0; d < D; ++d) ((T *)I.hqu)[(size_t)d * N + n] = q * u[d];
-  ((T *)I.p)[n] = T(0);
-  ((T *)I.rho)[n] = rho;
-  ((T *)I.R)[n] = T(0);
+  for (int d = 0; d < D; ++d) (gbl((T *)I.hqu))[(size_t)d * N + n] = q * u[d];
+  (gbl((T *)I.p))[n] = T(0);
+  (gbl((T *)I.rho))[n] = rho;
+  (gbl((T *)I.R))[n] = T(0);
 }
 
 // ------------------------------------------------------------ output / diag
@@ -1040,13 +1090,13 @@ __global__ __launch_bounds__(NT) void k_export_pops(const Inst *__restrict__ ins
   const size_t N = I.N;
   if (fam == 0) {
     const int fb = fbuf(I, pc);
-    const S *f = (const S *)I.f[fb];
+    auto f = gbl((const S *)I.f[fb]);
     for (int j = 0; j < 3 * Q; ++j) {
-      const T v = (IO::split && j % Q == 0) ? (T)I.f0[fb][(j / Q) * N + n] : IO::ld(f, j * N + n, T(SC_F));
+      const T v = (IO::split && j % Q == 0) ? (T)gbl(I.f0[fb])[(j / Q) * N + n] : IO::ld(f, j * N + n, T(SC_F));
       dst[j * N + n] = (Tout)v;
     }
   } else if (fam == 3) {
-    const T *h = (const T *)I.h[I.ctl->hcur];
+    auto h = gbl((const T *)I.h[I.ctl->hcur]);
     for (int j = 0; j < Q; ++j) dst[j * N + n] = (Tout)h[j * N + n];
   } else {
     const S *p = (const S *)(fam == 1 ? I.g[pc] : I.l[pc]);
@@ -1115,25 +1165,25 @@ __global__ __launch_bounds__(NT) void k_diag(const Inst *__restrict__ insts, con
   double mx = 0.0;
   if (nd.valid) {
     const int N = I.N, n = nd.n;
-    const T *phi = (const T *)I.phi;
+    auto phi = gbl((const T *)I.phi);
     const double p1 = (double)phi[n], p2 = (double)phi[(size_t)N + n], p3 = (double)phi[(size_t)2 * N + n];
     v[0] = p1;
     v[1] = p2;
     v[2] = p3;
-    v[3] = (double)((const T *)I.q)[n];
+    v[3] = (double)(gbl((const T *)I.q))[n];
     mx = fabs(p1 + p2 + p3 - 1.0);
     using IO = PopIO<S, T>;
     int bad = 0;
     const int fb = fbuf(I, pc);
-    const S *f = (const S *)I.f[fb];
+    auto f = gbl((const S *)I.f[fb]);
     for (int j = 0; j < 3 * Q; ++j) {
-      const T v = (IO::split && j % Q == 0) ? (T)I.f0[fb][(size_t)(j / Q) * N + n]
+      const T v = (IO::split && j % Q == 0) ? (T)gbl(I.f0[fb])[(size_t)(j / Q) * N + n]
                                              : IO::ld(f, (size_t)j * N + n, T(SC_F));
       bad += !isfinite((double)v);
     }
-    const S *g = (const S *)I.g[pc];
-    const S *l = (const S *)I.l[pc];
-    const T *h = (const T *)I.h[I.ctl->hcur];
+    auto g = gbl((const S *)I.g[pc]);
+    auto l = gbl((const S *)I.l[pc]);
+    auto h = gbl((const T *)I.h[I.ctl->hcur]);
     for (int j = 0; j < Q; ++j) {
       bad += !isfinite((double)IO::ld(g, (size_t)j * N + n, T(SC_G)));
       bad += !isfinite((double)IO::ld(l, (size_t)j * N + n, T(SC_L)));
