@@ -179,6 +179,40 @@ def field_compound_drop(n=1024, r_shell=80.0, r_core=60.0, ca_e=0.2,
     return p, init
 
 
+# Phase ratios of the two-drop interaction runs (Sec. 4.5), in this code's
+# numbering (phase 1 host, 2 shell, 3 core; the paper numbers the bulk 3 and
+# the core 1): (eps2/eps1, eps3/eps1), (sigma2/sigma1, sigma3/sigma1).
+TWO_DROP_REGIMES = {
+    # S_shell/bulk = 8, R_shell/bulk = 6, S_core/shell = 1/8, R_core/shell = 1/6
+    "coalescence": ((8.0, 1.0), (6.0, 1.0)),
+    # S_shell/bulk = 0.2, R_shell/bulk = 1.04, S_core/shell = 5, R_core/shell = 1/1.04
+    "separation": ((0.2, 1.0), (1.04, 1.0)),
+}
+
+
+def two_compound_drops(nx=256, ny=384, r_shell=30.0, r_core=18.0, gap=8.0, regime="coalescence",
+                       ca_e=0.2, tau_l=0.8, sub=(4, 4, 0.0), init_iters=4000, init_tol=0.0):
+    """Two equal concentric compound drops on the vertical centre line,
+    aligned with the field between electrodes (walls in y), shells `gap`
+    nodes apart (Sec. 4.5); equal densities and viscosities; ca_e =
+    eps1 E0^2 R_shell / gamma."""
+    eps_ratio, sigma_ratio = TWO_DROP_REGIMES[regime]
+    eps1, sig1, gamma = 0.1, 1e-3, 1e-3
+    E0 = math.sqrt(ca_e * gamma / (eps1 * r_shell))
+    dV = E0 * ny
+    eps = (eps1, eps1 * eps_ratio[0], eps1 * eps_ratio[1])
+    sig = (sig1, sig1 * sigma_ratio[0], sig1 * sigma_ratio[1])
+    p = base_params(nx, ny, bc_y=1, wall_phi=(0.0, dV), eps=eps, sigma=sig, tau_l=tau_l,
+                    sub_min=int(sub[0]), sub_max=int(sub[1]), sub_tol=float(sub[2]),
+                    init_sub_max=int(init_iters), init_tol=float(init_tol))
+    cx, cy = 0.5 * (nx - 1), 0.5 * (ny - 1)
+    off = r_shell + 0.5 * gap
+    core = sum(tanh_drop(nx, ny, cx, cy + s * off, r_core, 4.0) for s in (-1, 1))
+    shell = (1.0 - core) * sum(tanh_drop(nx, ny, cx, cy + s * off, r_shell, 4.0) for s in (-1, 1))
+    _, y = _grid(nx, ny)
+    return p, {"phi0": np.stack([1.0 - core - shell, shell, core]), "psi0": dV * (y + 0.5) / ny}
+
+
 def batch_sweep(n_inst=64, seed=5787, lo=128, hi=512, sub=(4, 4, 0.0), init_iters=2000):
     """Parameter sweep of compound drops (workload 4): grid sizes uniform over
     multiples of 32 in [lo, hi], Ca_e ~ U[0.05, 0.4], eps and sigma ratios

@@ -80,3 +80,26 @@ def test_binding_refuses_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(binding, "_lib", None)
     with pytest.raises(binding.LbmEhdError):
         binding.load()
+
+
+def test_two_drop_workload_geometry():
+    """The two-drop inputs (Sec. 4.5): phases sum to one, two shells and two
+    cores mirror-symmetric about the box centre along the field, the shells
+    the stated gap apart, and the regime's ratios in this code's numbering."""
+    import numpy as np
+    from scipy import ndimage
+    from paper_2608_05787_amd import inputs
+    p, init = inputs.two_compound_drops(nx=96, ny=160, r_shell=20.0, r_core=12.0, gap=8.0, regime="coalescence")
+    phi = init["phi0"]
+    np.testing.assert_allclose(phi.sum(0), 1.0, atol=1e-14)
+    assert phi.min() >= 0.0
+    np.testing.assert_allclose(phi, phi[:, ::-1, :], atol=1e-12)
+    assert ndimage.label(phi[0] < 0.5)[1] == 2 and ndimage.label(phi[2] > 0.5)[1] == 2
+    col = phi[0][:, 47]
+    inside = np.nonzero(col < 0.5)[0]
+    gap = np.nonzero(np.diff(inside) > 1)[0]
+    assert len(gap) == 1 and inside[gap[0] + 1] - inside[gap[0]] - 1 == 8
+    assert p["eps"][1] / p["eps"][0] == 8.0 and p["sigma"][1] / p["sigma"][0] == 6.0
+    q, _ = inputs.two_compound_drops(regime="separation")
+    assert abs(q["eps"][1] / q["eps"][0] - 0.2) < 1e-12 and abs(q["sigma"][1] / q["sigma"][0] - 1.04) < 1e-12
+    assert p["bc_y"] == 1 and p["wall_phi"][1] > 0
