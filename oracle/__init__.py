@@ -21,7 +21,7 @@ _SRC = os.path.join(_HERE, "lbm_ehd_oracle.c")
 _LIB = os.path.join(_HERE, "_lbm_ehd_oracle.so")
 
 FIELDS = ["phi1", "phi2", "phi3", "rho", "ux", "uy", "p", "psi", "Ex", "Ey",
-          "q", "mu1", "mu2", "mu3", "eps", "R", "uz", "Ez"]
+          "q", "mu1", "mu2", "mu3", "eps", "R", "uz", "Ez", "n_plus", "n_minus"]
 FAMILIES = {"f": (0, 3), "g": (1, 1), "l": (2, 1), "h": (3, 1)}  # id, planes per lattice direction
 
 
@@ -51,6 +51,8 @@ class _Params(ctypes.Structure):
         ("eps", ctypes.c_double * 3), ("sigma", ctypes.c_double * 3),
         ("tau_f", ctypes.c_double), ("tau_l", ctypes.c_double),
         ("nz", ctypes.c_int32), ("lattice", ctypes.c_int32), ("E_ext_z", ctypes.c_double),
+        ("charge_model", ctypes.c_int32), ("pad1", ctypes.c_int32),
+        ("ion_tau", ctypes.c_double), ("ion_beta", ctypes.c_double), ("ion_charge", ctypes.c_double),
     ]
 
 
@@ -63,7 +65,7 @@ def _load():
         lib = ctypes.CDLL(build())
         dp = ctypes.POINTER(ctypes.c_double)
         lib.or_create.restype = ctypes.c_void_p
-        lib.or_create.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, dp]
+        lib.or_create.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, dp, dp]
         lib.or_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
         lib.or_free.argtypes = [ctypes.c_void_p]
         lib.or_field.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
@@ -107,6 +109,10 @@ def _params(cfg: dict) -> _Params:
     p.nz = int(cfg.get("nz", 1))
     p.lattice = int(cfg.get("lattice", 0))
     p.E_ext_z = float(cfg.get("E_ext_z", 0.0))
+    p.charge_model = int(cfg.get("charge_model", 0))
+    p.ion_tau = float(cfg.get("ion_tau", 0.8))
+    p.ion_beta = float(cfg.get("ion_beta", 0.0))
+    p.ion_charge = float(cfg.get("ion_charge", 0.0))
     return p
 
 
@@ -126,7 +132,8 @@ class Oracle:
     ``paper_2608_05787_amd.inputs``); ``init`` holds the initial fields as
     float64 arrays on the lattice's grid G ([ny, nx] for D2Q9, [nz, ny, nx]
     for D3Q15): ``phi0`` [3, *G], optional ``u0`` [D, *G], ``q0`` and
-    ``psi0`` G.
+    ``psi0`` G; under the Nernst-Planck charge model ``ions0`` [2, *G]
+    (n_+, n_-).
     """
 
     def __init__(self, cfg: dict, init: dict):
@@ -144,7 +151,8 @@ class Oracle:
             assert v.shape == ((lead,) + shp if lead else shp), (name, v.shape)
             return v
 
-        self._keep = [arr("phi0", 3), arr("u0", self.dim), arr("q0", 0), arr("psi0", 0)]
+        self.nl = 2 if int(cfg.get("charge_model", 0)) == 1 else 1
+        self._keep = [arr("phi0", 3), arr("u0", self.dim), arr("q0", 0), arr("psi0", 0), arr("ions0", 2)]
         h = lib.or_create(ctypes.byref(self._p), *[_ptr(a) for a in self._keep])
         if not h:
             raise ValueError("oracle rejected the parameters")
@@ -170,6 +178,8 @@ class Oracle:
 
     def pops(self, fam: str) -> np.ndarray:
         idx, mult = FAMILIES[fam]
+        if fam == "l":
+            mult = self.nl
         out = np.empty((mult * self.q,) + self.shape, np.float64)
         assert _load().or_pops(self._h, idx, _ptr(out)) == 0
         return out

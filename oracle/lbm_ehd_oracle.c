@@ -49,6 +49,13 @@
  *       the 14 moving directions (Eq. 43 gives 1/8 for D2Q9: the same rule,
  *       weights summing to one with zero first moment); every other formula
  *       is written for a general lattice and dimension.
+ *   R23 two-ion Nernst-Planck charge model (Eq. 52, symmetric binary
+ *       electrolyte, valences +1 and -1): each ion concentration n_s is the
+ *       zeroth moment of a BGK advection-diffusion family with equilibrium
+ *       w_j n_s (1 + c_j . (u + v_s)/cs2), drift v_s = z_s beta D E (beta =
+ *       e/(k_B T), E of the current step), D = cs2 (tau_n - 1/2); the charge
+ *       is q = e (n_+ - n_-) with no Ohmic source (conductivities zero);
+ *       walls are no-flux bounce-back.  The paper gives no LB for Eq. (52).
  */
 #include <math.h>
 #include <stdint.h>
@@ -103,6 +110,11 @@ typedef struct {
   int32_t nz;         /* layers in z (1 for D2Q9) */
   int32_t lattice;    /* 0 D2Q9, 1 D3Q15 */
   double E_ext_z;     /* z component of the applied field (D3Q15) */
+  int32_t charge_model; /* 0 leaky dielectric (Eqs. 46-50), 1 two-ion Nernst-Planck (R23) */
+  int32_t pad1;
+  double ion_tau;     /* relaxation time of the ion families: D = cs2 (ion_tau - 1/2) */
+  double ion_beta;    /* e / (k_B T) in potential units */
+  double ion_charge;  /* e: q = e (n_+ - n_-) */
 } or_params;
 
 typedef struct {
@@ -110,7 +122,8 @@ typedef struct {
   const lattice *L;
   int nx, ny, nz, N, Q, D;
   double lam[3], m0, alpha, eps_ref, tau_h, Eext[3];
-  double *f, *g, *l, *h;       /* populations, [family][q][N] */
+  double *f, *g, *l, *h;       /* populations, [family][q][N]; l holds the two ion
+                                  families [2][Q][N] under the Nernst-Planck model */
   double *fn, *gn, *ln, *hn;   /* streaming targets */
   double *phi, *lsum;          /* [3][N], [N] */
   double *rho, *sig, *eps, *visc;
@@ -120,6 +133,8 @@ typedef struct {
   double *mu, *gmu;            /* [3][N], [3][D][N] */
   double *u, *pr;              /* [D][N], [N] */
   double *hpu, *hqu;           /* history (phi_i u)^{n-1} [3][D][N], (q u)^{n-1} [D][N] */
+  double *ion;                 /* Nernst-Planck: ion concentrations n_+, n_- [2][N] */
+  int nl;                      /* families in l: 1, or 2 under the Nernst-Planck model */
   double *rowbuf;              /* per-row partial sums (deterministic reductions) */
   int64_t nstep;
   int k_used;
@@ -345,9 +360,19 @@ static void moments(or_state *s) {
       for (int j = 0; j < Q; ++j) a += s->f[(i * Q + j) * N + n];
       s->phi[i * N + n] = a;
     }
-    double b = 0;
-    for (int j = 0; j < Q; ++j) b += s->l[j * N + n];
-    s->lsum[n] = b;
+    if (s->p.charge_model == 1) {
+      /* ion concentrations and the charge they carry (R23) */
+      for (int k = 0; k < 2; ++k) {
+        double a = 0;
+        for (int j = 0; j < Q; ++j) a += s->l[(k * Q + j) * N + n];
+        s->ion[k * N + n] = a;
+      }
+      s->lsum[n] = s->p.ion_charge * (s->ion[n] - s->ion[N + n]);
+    } else {
+      double b = 0;
+      for (int j = 0; j < Q; ++j) b += s->l[j * N + n];
+      s->lsum[n] = b;
+    }
   }
 }
 
@@ -373,6 +398,14 @@ static void properties_and_stencils(or_state *s) {
  * step (R9). */
 static void charge(or_state *s) {
   const int N = s->N, D = s->D;
+  if (s->p.charge_model == 1) {
+    /* Nernst-Planck: the ions carry the charge, no Ohmic source (R23) */
+    for (int n = 0; n < N; ++n) {
+      s->q[n] = s->lsum[n];
+      s->R[n] = 0.0;
+    }
+    return;
+  }
 #pragma omp parallel for schedule(static)
   for (int n = 0; n < N; ++n) {
     const double se = s->sig[n] / s->eps[n];
@@ -513,6 +546,23 @@ static void collide(or_state *s) {
       s->gn[j * N + n] = gj - (gj - geq) / tg + (1.0 - 0.5 / tg) * Gb;
     }
 
+    if (P->charge_model == 1) {
+      /* two ion families (R23): BGK advection-diffusion with the drift
+         velocity z_s beta D E of the current field */
+      const double tn = P->ion_tau, Dn = CS2 * (tn - 0.5);
+      for (int k = 0; k < 2; ++k) {
+        const double z = k == 0 ? 1.0 : -1.0, ns = s->ion[k * N + n];
+        double v[3];
+        for (int d = 0; d < D; ++d) v[d] = u[d] + z * P->ion_beta * Dn * s->E[d * N + n];
+        for (int j = 0; j < Q; ++j) {
+          const double mj = s->l[(k * Q + j) * N + n];
+          const double meq = L->w[j] * ns * (1.0 + dotc(L, j, v) / CS2);
+          s->ln[(k * Q + j) * N + n] = mj - (mj - meq) / tn;
+        }
+      }
+      continue;
+    }
+
     /* charge family, Eqs. (48)-(50) */
     const double Rn = s->R[n];
     for (int j = 0; j < Q; ++j) {
@@ -533,6 +583,10 @@ static void stream_all(or_state *s) {
       stream_family(s, s->fn + i * Q * N, s->f + i * Q * N, 0, s->phi + i * N, 0, 0);
   }
   stream_family(s, s->gn, s->g, 0, s->rho, 0, 0);
+  if (s->p.charge_model == 1) {
+    for (int k = 0; k < 2; ++k) stream_family(s, s->ln + k * Q * N, s->l + k * Q * N, 0, s->ion + k * N, 0, 0);
+    return;
+  }
   if (s->p.wall_q_mode == 1)
     stream_family(s, s->ln, s->l, 1, NULL, s->p.wall_q[0], s->p.wall_q[1]);
   else
@@ -547,22 +601,25 @@ void or_free(or_state *s) {
                     &s->phi, &s->lsum, &s->rho, &s->sig, &s->eps, &s->visc,
                     &s->gphi, &s->lphi, &s->grho, &s->gsig, &s->geps, &s->q,
                     &s->R, &s->psi, &s->psi_prev, &s->E, &s->mu, &s->gmu,
-                    &s->u, &s->pr, &s->hpu, &s->hqu, &s->rowbuf};
+                    &s->u, &s->pr, &s->hpu, &s->hqu, &s->ion, &s->rowbuf};
   for (size_t i = 0; i < sizeof(all) / sizeof(all[0]); ++i) free(*all[i]);
   free(s);
 }
 
 /* Create: parameter mapping, initial fields, cold-start potential, equilibria.
- * phi0 [3][N] (required); u0 [D][N], q0 [N], psi0 [N] may be NULL (zero).
- * Returns NULL on invalid parameters. */
+ * phi0 [3][N] (required); u0 [D][N], q0 [N], psi0 [N] may be NULL (zero);
+ * ions0 [2][N] (n_+, n_-; Nernst-Planck model only, then required; q0 is
+ * ignored and q = e (n_+ - n_-)).  Returns NULL on invalid parameters. */
 or_state *or_create(const or_params *P, const double *phi0, const double *u0,
-                    const double *q0, const double *psi0) {
+                    const double *q0, const double *psi0, const double *ions0) {
   if (!P || !phi0 || P->nx < 1 || P->ny < 1) return NULL;
   if (P->tau_f <= 0.5 || P->tau_l <= 0.5) return NULL;
   if (P->eps_ref_phase < 0 || P->eps_ref_phase > 2) return NULL;
   if (P->lattice != 0 && P->lattice != 1) return NULL;
   if (P->lattice == 0 && P->nz != 1) return NULL;
   if (P->nz < 1) return NULL;
+  if (P->charge_model != 0 && P->charge_model != 1) return NULL;
+  if (P->charge_model == 1 && (!ions0 || P->ion_tau <= 0.5)) return NULL;
   or_state *s = (or_state *)calloc(1, sizeof(or_state));
   s->p = *P;
   s->L = P->lattice == 1 ? &D3Q15 : &D2Q9;
@@ -588,7 +645,9 @@ or_state *or_create(const or_params *P, const double *phi0, const double *u0,
 
   s->f = zalloc(3 * Q * (size_t)N); s->fn = zalloc(3 * Q * (size_t)N);
   s->g = zalloc(Q * (size_t)N);  s->gn = zalloc(Q * (size_t)N);
-  s->l = zalloc(Q * (size_t)N);  s->ln = zalloc(Q * (size_t)N);
+  s->nl = P->charge_model == 1 ? 2 : 1;
+  s->l = zalloc(s->nl * Q * (size_t)N);  s->ln = zalloc(s->nl * Q * (size_t)N);
+  s->ion = zalloc(2 * (size_t)N);
   s->h = zalloc(Q * (size_t)N);  s->hn = zalloc(Q * (size_t)N);
   s->phi = zalloc(3 * (size_t)N); s->lsum = zalloc(N);
   s->rho = zalloc(N); s->sig = zalloc(N); s->eps = zalloc(N); s->visc = zalloc(N);
@@ -604,7 +663,12 @@ or_state *or_create(const or_params *P, const double *phi0, const double *u0,
 
   memcpy(s->phi, phi0, 3 * (size_t)N * sizeof(double));
   if (u0) memcpy(s->u, u0, D * (size_t)N * sizeof(double));
-  if (q0) memcpy(s->q, q0, (size_t)N * sizeof(double));
+  if (P->charge_model == 1) {
+    memcpy(s->ion, ions0, 2 * (size_t)N * sizeof(double));
+    for (int n = 0; n < N; ++n) s->q[n] = P->ion_charge * (s->ion[n] - s->ion[N + n]);
+  } else if (q0) {
+    memcpy(s->q, q0, (size_t)N * sizeof(double));
+  }
   properties_and_stencils(s);
 
   /* potential: equilibrium of the initial guess, then cold-start iterations
@@ -636,7 +700,17 @@ or_state *or_create(const or_params *P, const double *phi0, const double *u0,
     for (int j = 0; j < Q; ++j) {
       const double cu = dotc(L, j, u);
       s->g[j * N + n] = rho * L->w[j] * (cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - usq / (2.0 * CS2));
-      s->l[j * N + n] = L->w[j] * s->q[n] * (1.0 + cu / CS2);
+      if (P->charge_model == 0) s->l[j * N + n] = L->w[j] * s->q[n] * (1.0 + cu / CS2);
+    }
+    if (P->charge_model == 1) {
+      /* ion equilibria with the drift of the cold-start field */
+      const double Dn = CS2 * (P->ion_tau - 0.5);
+      for (int k = 0; k < 2; ++k) {
+        const double z = k == 0 ? 1.0 : -1.0, ns = s->ion[k * N + n];
+        double v[3];
+        for (int d = 0; d < D; ++d) v[d] = u[d] + z * P->ion_beta * Dn * s->E[d * N + n];
+        for (int j = 0; j < Q; ++j) s->l[(k * Q + j) * N + n] = L->w[j] * ns * (1.0 + dotc(L, j, v) / CS2);
+      }
     }
     for (int d = 0; d < D; ++d) s->hqu[d * N + n] = s->q[n] * u[d];
     s->pr[n] = 0.0;
@@ -663,7 +737,7 @@ void or_step(or_state *s, int64_t nsteps) {
  * (after create: the initial fields).  UZ and EZ are zero on D2Q9. */
 enum {
   OR_PHI1 = 0, OR_PHI2, OR_PHI3, OR_RHO, OR_UX, OR_UY, OR_P, OR_PSI, OR_EX, OR_EY,
-  OR_Q, OR_MU1, OR_MU2, OR_MU3, OR_EPS, OR_R, OR_UZ, OR_EZ, OR_NFIELDS
+  OR_Q, OR_MU1, OR_MU2, OR_MU3, OR_EPS, OR_R, OR_UZ, OR_EZ, OR_NPLUS, OR_NMINUS, OR_NFIELDS
 };
 
 int or_field(const or_state *s, int id, double *out) {
@@ -684,6 +758,7 @@ int or_field(const or_state *s, int id, double *out) {
     case OR_MU1: case OR_MU2: case OR_MU3: src = s->mu + (id - OR_MU1) * N; break;
     case OR_EPS: src = s->eps; break;
     case OR_R: src = s->R; break;
+    case OR_NPLUS: case OR_NMINUS: src = s->p.charge_model == 1 ? s->ion + (id - OR_NPLUS) * N : NULL; break;
     default: return -1;
   }
   if (src)
@@ -694,13 +769,13 @@ int or_field(const or_state *s, int id, double *out) {
 }
 
 /* Raw pre-collision populations of the current level.
- * fam 0: f [3][Q][N], 1: g [Q][N], 2: l [Q][N], 3: h [Q][N]. */
+ * fam 0: f [3][Q][N], 1: g [Q][N], 2: l [Q][N] (ions: [2][Q][N]), 3: h [Q][N]. */
 int or_pops(const or_state *s, int fam, double *out) {
   const size_t N = (size_t)s->N, Q = (size_t)s->Q;
   switch (fam) {
     case 0: memcpy(out, s->f, 3 * Q * N * sizeof(double)); return 0;
     case 1: memcpy(out, s->g, Q * N * sizeof(double)); return 0;
-    case 2: memcpy(out, s->l, Q * N * sizeof(double)); return 0;
+    case 2: memcpy(out, s->l, s->nl * Q * N * sizeof(double)); return 0;
     case 3: memcpy(out, s->h, Q * N * sizeof(double)); return 0;
     default: return -1;
   }

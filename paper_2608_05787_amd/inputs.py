@@ -40,7 +40,8 @@ def base_params(nx: int, ny: int, **kw) -> dict:
              rho=(1.0, 1.0, 1.0), visc=(0.1, 0.1, 0.1), eps=(0.1, 0.1, 0.1),
              sigma=(1e-3, 1e-3, 1e-3), tau_f=0.8, tau_l=0.8, eps_ref_phase=0,
              phase_mode=0, sub_min=1, sub_max=1, sub_tol=0.0,
-             init_sub_max=0, init_tol=0.0, nz=1, lattice=0, E_ext_z=0.0)
+             init_sub_max=0, init_tol=0.0, nz=1, lattice=0, E_ext_z=0.0,
+             charge_model=0, ion_tau=0.8, ion_beta=0.0, ion_charge=0.0)
     p.update(kw)
     return p
 
@@ -140,6 +141,38 @@ def eof_channel(nx=64, ny=32, zeta=1.0, debye=4.0, E=1e-4, tau=0.8, closed_form_
         init["psi0"] = psi
         init["q0"] = -eps * kappa * kappa * psi
     meta = dict(kappa=kappa, h=0.5 * ny, zeta=zeta, E=E, eps=eps, mu=nu, alpha=alpha, sigma=sigma)
+    return p, init, meta
+
+
+def np_eof_channel(nx=4, ny=32, zeta=0.05, debye=4.0, E=1e-4, beta=1.0, n0=1.0, tau=0.8,
+                   ion_tau=0.8, closed_form_start=True):
+    """Electro-osmotic channel with a two-ion Nernst-Planck electrolyte
+    (Eq. 52, valences +1/-1; single phase, frozen order parameters).
+
+    Walls at y = -1/2 and ny - 1/2 hold potential zeta and no ion flux; the
+    Debye length follows kappa^2 = 2 e n0 beta / eps (Eq. 53) with the
+    elementary charge e chosen for it; beta = e/(k_B T); beta zeta << 1 is the
+    Debye-Hueckel regime.  The start is the closed-form potential with
+    Boltzmann ion profiles n_+- = n0 exp(-+ beta psi), fluid at rest.
+    Returns (params, init, meta)."""
+    cs2 = 1.0 / 3.0
+    nu = cs2 * (tau - 0.5)
+    eps = nu
+    kappa = 1.0 / debye
+    e = kappa * kappa * eps / (2.0 * n0 * beta)
+    p = base_params(nx, ny, bc_y=1, wall_phi=(zeta, zeta), E_ext=(E, 0.0), visc=(nu, nu, nu),
+                    eps=(eps, eps, eps), sigma=(0.0, 0.0, 0.0), tau_f=tau, tau_l=tau, phase_mode=1,
+                    sub_min=1, sub_max=1, init_sub_max=4000, init_tol=1e-13,
+                    charge_model=1, ion_tau=ion_tau, ion_beta=beta, ion_charge=e)
+    phi0 = np.zeros((3, ny, nx))
+    phi0[0] = 1.0
+    _, y = _grid(nx, ny)
+    yc = y - 0.5 * (ny - 1)
+    h = 0.5 * ny
+    psi = zeta * np.cosh(kappa * yc) / math.cosh(kappa * h) if closed_form_start else np.zeros((ny, nx))
+    init = {"phi0": phi0, "psi0": psi, "ions0": np.stack([n0 * np.exp(-beta * psi), n0 * np.exp(beta * psi)])}
+    meta = dict(kappa=kappa, h=h, zeta=zeta, E=E, eps=eps, mu=nu, e=e, beta=beta, n0=n0,
+                D=cs2 * (ion_tau - 0.5))
     return p, init, meta
 
 
