@@ -318,6 +318,8 @@ def main():
     ap.add_argument("--grad-steps", type=int, default=5000, help="0 skips the gradient leg")
     ap.add_argument("--grad-every", type=int, default=250, help="checkpoint interval of the reverse sweep")
     ap.add_argument("--n3", type=int, default=128, help="edge of the D3Q15 box (0 skips the 3-D leg)")
+    ap.add_argument("--d3q15-only", action="store_true",
+                    help="run only the D3Q15 leg (for profiling) and print its JSON object")
     ap.add_argument("--gradient-only", action="store_true",
                     help="run only the gradient leg (for profiling) and print its JSON object")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -332,6 +334,11 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     from paper_2608_05787_amd import binding
     binding.load()
+
+    if args.d3q15_only:
+        print(json.dumps({"d3q15": d3q15_bench(args.n3, max(args.steps // 4, 10), max(args.warmup // 4, 5), args.sub,
+                                               1000, args.profile_steps)}), flush=True)
+        return
 
     if args.gradient_only:
         print(json.dumps({"gradient": gradient_bench(512, args.grad_steps, args.sub, 2000, args.grad_every)}),

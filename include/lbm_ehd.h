@@ -46,6 +46,9 @@ enum {
 
 enum { LBM_BC_PERIODIC = 0, LBM_BC_WALL = 1 }; /* x (and z) are always periodic */
 enum { LBM_LATTICE_D2Q9 = 0, LBM_LATTICE_D3Q15 = 1 };
+/* Charge transport: the leaky-dielectric charge family (Eqs. 46-50) or a
+ * symmetric two-ion Nernst-Planck electrolyte (Eq. 52). */
+enum { LBM_CHARGE_LEAKY = 0, LBM_CHARGE_NERNST_PLANCK = 1 };
 enum { LBM_PREC_FP32 = 0, LBM_PREC_FP16S = 1, LBM_PREC_FP64 = 2, LBM_PREC_TANGENT = 3 };
 /* LBM_DTYPE_TANGENT_F64: the derivative part of a tangent-mode handle's
  * fields, as float64. */
@@ -59,7 +62,8 @@ enum {
   LBM_F_PSI = 1u << 7, LBM_F_EX = 1u << 8, LBM_F_EY = 1u << 9, LBM_F_Q = 1u << 10,
   LBM_F_MU1 = 1u << 11, LBM_F_MU2 = 1u << 12, LBM_F_MU3 = 1u << 13,
   LBM_F_EPS = 1u << 14, LBM_F_R = 1u << 15,
-  LBM_F_UZ = 1u << 16, LBM_F_EZ = 1u << 17 /* D3Q15 only */
+  LBM_F_UZ = 1u << 16, LBM_F_EZ = 1u << 17, /* D3Q15 only */
+  LBM_F_NPLUS = 1u << 18, LBM_F_NMINUS = 1u << 19 /* Nernst-Planck only */
 };
 /* Population families for lbm_ehd_populations. */
 enum { LBM_POP_F = 0, LBM_POP_G = 1, LBM_POP_L = 2, LBM_POP_H = 3 };
@@ -113,6 +117,20 @@ enum { LBM_POP_F = 0, LBM_POP_G = 1, LBM_POP_L = 2, LBM_POP_H = 3 };
  *                D2Q9).  Reverse-mode gradients are D2Q9 only.
  *  nz            layers in z (D3Q15); 0 is read as 1.
  *  E_ext_z       z component of the applied field (D3Q15).
+ *  charge_model  LBM_CHARGE_LEAKY: charge family with the Ohmic source of
+ *                Eq. (47).  LBM_CHARGE_NERNST_PLANCK: two ion
+ *                concentrations n_+ and n_- (valences +1, -1) transported by
+ *                Eq. (52); each is the zeroth moment of a BGK
+ *                advection-diffusion family (the l populations hold both,
+ *                [2][Q][N]) with equilibrium w_j n (1 + c_j . (u + v)/cs^2)
+ *                and drift v = z ion_beta D E, D = cs^2 (ion_tau - 1/2); the
+ *                charge is q = ion_charge (n_+ - n_-) and walls are no-flux.
+ *                Requires sigma = 0 (ions carry the current), wall_q_mode 0,
+ *                FP32, FP64 or tangent precision, and init ions0; forward
+ *                mode only (reverse-mode gradients are refused).
+ *  ion_tau, ion_beta, ion_charge  Nernst-Planck: relaxation time of the
+ *                ion families (> 1/2), e/(k_B T) in potential units, and the
+ *                charge e of a unit concentration.
  *  dtheta        tangent mode only: direction in the parameter space
  *                theta = (eps2/eps1, eps3/eps1, sigma2/sigma1, sigma3/sigma1,
  *                E0).  The first four scale eps2, eps3, sigma2, sigma3 with
@@ -133,14 +151,18 @@ typedef struct {
   double tau_f, tau_l;
   double dtheta[5];
   double E_ext_z;
+  int32_t charge_model, reserved0;
+  double ion_tau, ion_beta, ion_charge;
 } lbm_ehd_params;
 
-/* Initial fields of one instance, HOST pointers to float64 arrays:
- * phi0 [3][ny][nx] (required); u0 [2][ny][nx], q0 [ny][nx] and psi0 (initial
- * guess of the potential) [ny][nx] may be NULL (zero).  Read during create
- * only. */
+/* Initial fields of one instance, HOST pointers to float64 arrays on the
+ * instance's grid G ([ny][nx], or [nz][ny][nx] on D3Q15):
+ * phi0 [3][G] (required); u0 [D][G], q0 [G] and psi0 (initial guess of the
+ * potential) [G] may be NULL (zero); ions0 [2][G] (n_+, n_-) is required
+ * under the Nernst-Planck charge model, which then ignores q0 (q =
+ * ion_charge (n_+ - n_-)), and ignored otherwise.  Read during create only. */
 typedef struct {
-  const double *phi0, *u0, *q0, *psi0;
+  const double *phi0, *u0, *q0, *psi0, *ions0;
 } lbm_ehd_init;
 
 /* Bytes of device workspace that lbm_ehd_create needs for n_inst instances
@@ -177,8 +199,9 @@ int lbm_ehd_graph(lbm_ehd_t h, int32_t steps_per_graph);
 int lbm_ehd_fields(lbm_ehd_t h, int32_t inst, uint32_t mask, void *dev_dst, int32_t dtype);
 
 /* Pre-collision populations of the current level of instance `inst`,
- * converted to dtype: family LBM_POP_F gives [3][9][ny][nx], the others
- * [9][ny][nx].  FP16S values are unscaled (the stored half value divided by
+ * converted to dtype: family LBM_POP_F gives [3][Q][G], LBM_POP_L under the
+ * Nernst-Planck model [2][Q][G] (n_+ then n_-), the others [Q][G] (Q = 9 on
+ * D2Q9, 15 on D3Q15).  FP16S values are unscaled (the stored half value divided by
  * its family's power-of-two scale; f^i_0 from its FP32 plane).  Async. */
 int lbm_ehd_populations(lbm_ehd_t h, int32_t inst, int32_t family, void *dev_dst, int32_t dtype);
 

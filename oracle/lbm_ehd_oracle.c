@@ -20,7 +20,7 @@
  * stored as D planes (x, y[, z]).
  *
  * Where the paper is silent or garbled, the reading taken is stated at the
- * point of use (and listed, numbered R1..R22, in the design notes):
+ * point of use (and listed, numbered R1..R21, in the design notes):
  *   R1  mu_i follows Eq. (20) (derivative form); Eq. (27c) is a misprint.
  *   R2  the CH source Eq. (36) is w_j c_j . [d_t(phi_i u)/cs2 - X_i/m0].
  *   R3  phi_i is the zeroth moment of f^i (sum of f, not of f^eq).
@@ -45,11 +45,11 @@
  *   R15 a uniform applied field E_ext is added to -grad(potential).
  *   R16 initial populations are the equilibria of the initial fields; the
  *       potential is first iterated with q0 (cold start).
- *   R22 D3Q15: the potential source weights are varpi_0 = 0 and 1/14 for
+ *   R20 D3Q15: the potential source weights are varpi_0 = 0 and 1/14 for
  *       the 14 moving directions (Eq. 43 gives 1/8 for D2Q9: the same rule,
  *       weights summing to one with zero first moment); every other formula
  *       is written for a general lattice and dimension.
- *   R23 two-ion Nernst-Planck charge model (Eq. 52, symmetric binary
+ *   R21 two-ion Nernst-Planck charge model (Eq. 52, symmetric binary
  *       electrolyte, valences +1 and -1): each ion concentration n_s is the
  *       zeroth moment of a BGK advection-diffusion family with equilibrium
  *       w_j n_s (1 + c_j . (u + v_s)/cs2), drift v_s = z_s beta D E (beta =
@@ -71,7 +71,7 @@ typedef struct {
   int c[QMAX][3];
   double w[QMAX];
   int opp[QMAX];
-  double varpi[QMAX]; /* potential source weights, Eq. (43) (R22) */
+  double varpi[QMAX]; /* potential source weights, Eq. (43) (R20) */
 } lattice;
 
 static const lattice D2Q9 = {
@@ -110,7 +110,7 @@ typedef struct {
   int32_t nz;         /* layers in z (1 for D2Q9) */
   int32_t lattice;    /* 0 D2Q9, 1 D3Q15 */
   double E_ext_z;     /* z component of the applied field (D3Q15) */
-  int32_t charge_model; /* 0 leaky dielectric (Eqs. 46-50), 1 two-ion Nernst-Planck (R23) */
+  int32_t charge_model; /* 0 leaky dielectric (Eqs. 46-50), 1 two-ion Nernst-Planck (R21) */
   int32_t pad1;
   double ion_tau;     /* relaxation time of the ion families: D = cs2 (ion_tau - 1/2) */
   double ion_beta;    /* e / (k_B T) in potential units */
@@ -361,7 +361,7 @@ static void moments(or_state *s) {
       s->phi[i * N + n] = a;
     }
     if (s->p.charge_model == 1) {
-      /* ion concentrations and the charge they carry (R23) */
+      /* ion concentrations and the charge they carry (R21) */
       for (int k = 0; k < 2; ++k) {
         double a = 0;
         for (int j = 0; j < Q; ++j) a += s->l[(k * Q + j) * N + n];
@@ -399,7 +399,7 @@ static void properties_and_stencils(or_state *s) {
 static void charge(or_state *s) {
   const int N = s->N, D = s->D;
   if (s->p.charge_model == 1) {
-    /* Nernst-Planck: the ions carry the charge, no Ohmic source (R23) */
+    /* Nernst-Planck: the ions carry the charge, no Ohmic source (R21) */
     for (int n = 0; n < N; ++n) {
       s->q[n] = s->lsum[n];
       s->R[n] = 0.0;
@@ -547,7 +547,7 @@ static void collide(or_state *s) {
     }
 
     if (P->charge_model == 1) {
-      /* two ion families (R23): BGK advection-diffusion with the drift
+      /* two ion families (R21): BGK advection-diffusion with the drift
          velocity z_s beta D E of the current field */
       const double tn = P->ion_tau, Dn = CS2 * (tn - 0.5);
       for (int k = 0; k < 2; ++k) {

@@ -15,7 +15,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm_ehd.so")
 
 FIELDS = ["phi1", "phi2", "phi3", "rho", "ux", "uy", "p", "psi", "Ex", "Ey",
-          "q", "mu1", "mu2", "mu3", "eps", "R", "uz", "Ez"]  # uz, Ez: D3Q15 only
+          "q", "mu1", "mu2", "mu3", "eps", "R", "uz", "Ez",  # uz, Ez: D3Q15 only
+          "n_plus", "n_minus"]  # Nernst-Planck charge model only
 PRECISION = {"fp32": 0, "fp16s": 1, "fp64": 2, "tangent": 3}
 FAMILY = {"f": (0, 3), "g": (1, 1), "l": (2, 1), "h": (3, 1)}  # id, planes per lattice velocity
 DIAG_KEYS = ["mass1", "mass2", "mass3", "charge", "max_sum_dev", "residual", "k_sub",
@@ -43,6 +44,8 @@ class Params(ctypes.Structure):
         ("tau_f", ctypes.c_double), ("tau_l", ctypes.c_double),
         ("dtheta", ctypes.c_double * 5),
         ("E_ext_z", ctypes.c_double),
+        ("charge_model", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("ion_tau", ctypes.c_double), ("ion_beta", ctypes.c_double), ("ion_charge", ctypes.c_double),
     ]
 
 
@@ -50,7 +53,7 @@ _dp = ctypes.POINTER(ctypes.c_double)
 
 
 class Init(ctypes.Structure):
-    _fields_ = [("phi0", _dp), ("u0", _dp), ("q0", _dp), ("psi0", _dp)]
+    _fields_ = [("phi0", _dp), ("u0", _dp), ("q0", _dp), ("psi0", _dp), ("ions0", _dp)]
 
 
 EXPORTS = ["lbm_ehd_adjoint_workspace_bytes", "lbm_ehd_workspace_bytes", "lbm_ehd_create", "lbm_ehd_step", "lbm_ehd_fields",
@@ -129,6 +132,10 @@ def make_params(cfg: dict, precision: str = "fp32") -> Params:
     p.nz = int(cfg.get("nz", 1))
     p.lattice = int(cfg.get("lattice", 0))
     p.E_ext_z = float(cfg.get("E_ext_z", 0.0))
+    p.charge_model = int(cfg.get("charge_model", 0))
+    p.ion_tau = float(cfg.get("ion_tau", 0.8))
+    p.ion_beta = float(cfg.get("ion_beta", 0.0))
+    p.ion_charge = float(cfg.get("ion_charge", 0.0))
     return p
 
 
@@ -144,7 +151,8 @@ class Sim:
 
     cfgs: parameter dict or list of dicts; inits: dict or list of dicts of
     float64 host arrays on the lattice's grid G ([ny, nx] for D2Q9,
-    [nz, ny, nx] for D3Q15): phi0 [3, *G], optional u0 [D, *G], q0, psi0 G.
+    [nz, ny, nx] for D3Q15): phi0 [3, *G], optional u0 [D, *G], q0, psi0 G;
+    under the Nernst-Planck charge model ions0 [2, *G] (n_+, n_-).
     """
 
     def __init__(self, cfgs, inits, precision: str = "fp32", device="cuda", stream=None):
@@ -155,6 +163,7 @@ class Sim:
         self.n_inst = len(cfgs)
         self.shapes = [grid_shape(c) for c in cfgs]
         self.q = 15 if int(cfgs[0].get("lattice", 0)) == 1 else 9
+        self.ions = int(cfgs[0].get("charge_model", 0)) == 1
         self.precision = precision
         self.device = torch.device(device)
         n = self.n_inst
@@ -166,7 +175,7 @@ class Sim:
         self._keep = []
         init_arr = (Init * n)()
         for i, ini in enumerate(inits):
-            for k in ("phi0", "u0", "q0", "psi0"):
+            for k in ("phi0", "u0", "q0", "psi0", "ions0"):
                 v = ini.get(k)
                 if v is not None:
                     v = np.ascontiguousarray(v, dtype=np.float64)
@@ -232,6 +241,8 @@ class Sim:
     def populations(self, fam: str, inst: int = 0, dtype=None):
         import torch
         idx, mult = FAMILY[fam]
+        if fam == "l" and self.ions:
+            mult = 2
         dtype = dtype or torch.float64
         out = torch.empty((mult * self.q,) + self.shapes[inst], dtype=dtype, device=self.device)
         dt = 1 if dtype == torch.float64 else 0

@@ -32,12 +32,14 @@ struct Layout {
   int nblk;
 };
 // Macroscopic plane groups, each [k][nz][ny][nx] contiguous with plane
-// stride N: phi(3) lsum eps q R psi E(D) mu(3) u(D) p rho hpu(3D) hqu(D)
-constexpr int N_GROUPS = 13;
-int group_planes(int g, int D) {
-  const int k[N_GROUPS] = {3, 1, 1, 1, 1, 1, D, 3, D, 1, 1, 3 * D, D};
+// stride N: phi(3) lsum eps q R psi E(D) mu(3) u(D) p rho hpu(3D) hqu(D),
+// and the ion concentrations (2, Nernst-Planck model only)
+constexpr int N_GROUPS = 14;
+int group_planes(int g, int D, int nion) {
+  const int k[N_GROUPS] = {3, 1, 1, 1, 1, 1, D, 3, D, 1, 1, 3 * D, D, nion};
   return k[g];
 }
+int ion_planes(const lbm_ehd_params &p) { return p.charge_model == LBM_CHARGE_NERNST_PLANCK ? 2 : 0; }
 int lat_q(const lbm_ehd_params &p) { return p.lattice == LBM_LATTICE_D3Q15 ? 15 : 9; }
 int lat_d(const lbm_ehd_params &p) { return p.lattice == LBM_LATTICE_D3Q15 ? 3 : 2; }
 int lat_nz(const lbm_ehd_params &p) { return p.nz > 1 ? p.nz : 1; }
@@ -63,7 +65,8 @@ Layout layout_one(const lbm_ehd_params &p, size_t off) {
   L.part_d = off;
   off = align_up(off + (size_t)L.nblk * 16 * sizeof(double));
   L.planes = off;
-  for (int g = 0; g < N_GROUPS; ++g) off += align_up(group_planes(g, D) * N * te);
+  for (int g = 0; g < N_GROUPS; ++g) off += align_up(group_planes(g, D, ion_planes(p)) * N * te);
+  const size_t nl = p.charge_model == LBM_CHARGE_NERNST_PLANCK ? 2 : 1;  // families in l
   for (int b = 0; b < 2; ++b) {
     L.f[b] = off;
     off = align_up(off + 3 * Q * N * se);
@@ -72,7 +75,7 @@ Layout layout_one(const lbm_ehd_params &p, size_t off) {
     L.g[b] = off;
     off = align_up(off + Q * N * se);
     L.l[b] = off;
-    off = align_up(off + Q * N * se);
+    off = align_up(off + nl * Q * N * se);
     L.h[b] = off;
     off = align_up(off + Q * N * te);
   }
@@ -134,6 +137,9 @@ template <typename T> void fill_phys(Phys<T> &P, const lbm_ehd_params &p) {
     P.wall_q[s] = (T)p.wall_q[s];
   }
   P.Eext[2] = (T)(p.lattice == LBM_LATTICE_D3Q15 ? p.E_ext_z : 0.0);
+  P.ion_tau = (T)p.ion_tau;
+  P.ion_beta = (T)p.ion_beta;
+  P.ion_e = (T)p.ion_charge;
 }
 
 // Applied-field magnitude E0 and the mean electrode potential about which
@@ -158,6 +164,7 @@ void fill_tangent(Phys<DualD> &T, const lbm_ehd_params &p) {
   T.m0 = v.m0; T.tau_f = v.tau_f; T.tau_l = v.tau_l; T.tau_h = v.tau_h; T.eps_ref = v.eps_ref; T.D = v.D;
   cp(T.rho, v.rho, 3); cp(T.visc, v.visc, 3); cp(T.eps, v.eps, 3); cp(T.sig, v.sig, 3);
   cp(T.Eext, v.Eext, 3); cp(T.wall_u, v.wall_u, 2); cp(T.wall_phi, v.wall_phi, 2); cp(T.wall_q, v.wall_q, 2);
+  T.ion_tau = v.ion_tau; T.ion_beta = v.ion_beta; T.ion_e = v.ion_e;
   T.eps[1].d = p.eps[0] * p.dtheta[0];
   T.eps[2].d = p.eps[0] * p.dtheta[1];
   T.sig[1].d = p.sigma[0] * p.dtheta[2];
@@ -203,6 +210,15 @@ const char *validate(const lbm_ehd_params &p, const lbm_ehd_params &p0) {
   if (p.precision != LBM_PREC_FP32 && p.precision != LBM_PREC_FP64 && p.precision != LBM_PREC_FP16S &&
       p.precision != LBM_PREC_TANGENT)
     return "unknown precision";
+  if (p.charge_model != LBM_CHARGE_LEAKY && p.charge_model != LBM_CHARGE_NERNST_PLANCK) return "unknown charge_model";
+  if (p.charge_model != p0.charge_model) return "all instances of a handle must share the charge model";
+  if (p.charge_model == LBM_CHARGE_NERNST_PLANCK) {
+    if (p.sigma[0] != 0 || p.sigma[1] != 0 || p.sigma[2] != 0)
+      return "the Nernst-Planck charge model needs sigma = 0 (the ions carry the current)";
+    if (p.wall_q_mode != 0) return "the Nernst-Planck charge model needs wall_q_mode 0 (no-flux walls)";
+    if (!(p.ion_tau > 0.5)) return "ion_tau must exceed 1/2";
+    if (p.precision == LBM_PREC_FP16S) return "the Nernst-Planck charge model does not support FP16S storage";
+  }
   if (p.precision == LBM_PREC_TANGENT && p.eps_ref_phase != 0 && (p.dtheta[0] != 0 || p.dtheta[1] != 0))
     return "tangent mode along permittivity ratios needs eps_ref_phase 0 (tau_h must stay fixed)";
   if (p.precision != p0.precision || p.sub_min != p0.sub_min || p.sub_max != p0.sub_max ||
@@ -228,7 +244,7 @@ struct lbm_ehd_s {
   long long steps = 0;
   std::string err;
   // host copies of the initial fields (gradient runs restart from them)
-  std::vector<std::vector<double>> init_phi, init_u, init_q, init_psi;
+  std::vector<std::vector<double>> init_phi, init_u, init_q, init_psi, init_ions;
   // recording made by lbm_ehd_record (checkpoints in the caller's buffer)
   void *rec_work = nullptr;
   int64_t rec_n = -1;
@@ -343,7 +359,16 @@ int do_create(lbm_ehd_s *H, const lbm_ehd_init *init) {
     int rc;
     if ((rc = up(init[i].phi0, I.phi, 3 * N))) return rc;
     if ((rc = up(init[i].u0, I.u, (size_t)Lat::D * N))) return rc;
-    if ((rc = up(init[i].q0, I.q, N))) return rc;
+    if (H->params[i].charge_model == LBM_CHARGE_NERNST_PLANCK) {
+      // ion concentrations and the charge they carry, q = e (n_+ - n_-)
+      const double *c = init[i].ions0, e = H->params[i].ion_charge;
+      if ((rc = up(c, I.ion, 2 * N))) return rc;
+      std::vector<double> q0(N);
+      for (size_t k = 0; k < N; ++k) q0[k] = e * (c[k] - c[N + k]);
+      if ((rc = up(q0.data(), I.q, N))) return rc;
+    } else if ((rc = up(init[i].q0, I.q, N))) {
+      return rc;
+    }
     if constexpr (std::is_same<T, DualD>::value) {
       // the initial potential guess scales with the applied field about the
       // electrodes' mean potential, like the electrode data
@@ -533,6 +558,10 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
       g_create_error = "init.phi0 is required";
       return LBM_EHD_EINVAL;
     }
+    if (run_init && params[i].charge_model == LBM_CHARGE_NERNST_PLANCK && !init[i].ions0) {
+      g_create_error = "init.ions0 is required under the Nernst-Planck charge model";
+      return LBM_EHD_EINVAL;
+    }
   }
   if (!dev_workspace || ((uintptr_t)dev_workspace % ALIGN) != 0) {
     g_create_error = "workspace must be non-NULL and 256-byte aligned";
@@ -568,6 +597,7 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
     I.bc_y = p.bc_y;
     I.wall_q_mode = p.wall_q_mode;
     I.phase_mode = p.phase_mode;
+    I.charge_model = p.charge_model;
     I.nblk = L.nblk;
     for (int b = 0; b < 2; ++b) {
       I.f[b] = H->ws + L.f[b];
@@ -578,11 +608,12 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
     }
     char *base = H->ws + L.planes;
     void **group[N_GROUPS] = {&I.phi, &I.lsum, &I.eps, &I.q, &I.R, &I.psi, &I.E,
-                              &I.mu, &I.u, &I.p, &I.rho, &I.hpu, &I.hqu};
+                              &I.mu, &I.u, &I.p, &I.rho, &I.hpu, &I.hqu, &I.ion};
     for (int g = 0; g < N_GROUPS; ++g) {
       *group[g] = base;
-      base += align_up(group_planes(g, lat_d(p)) * (size_t)I.N * te);
+      base += align_up(group_planes(g, lat_d(p), ion_planes(p)) * (size_t)I.N * te);
     }
+    if (!ion_planes(p)) I.ion = nullptr;
     I.part_p = (double *)(H->ws + L.part_p);
     I.part_mu = (double *)(H->ws + L.part_mu);
     I.part_d = (double *)(H->ws + L.part_d);
@@ -641,6 +672,7 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
     keep(H->init_u, init[i].u0, (size_t)lat_d(params[i]) * N);
     keep(H->init_q, init[i].q0, N);
     keep(H->init_psi, init[i].psi0, N);
+    keep(H->init_ions, params[i].charge_model == LBM_CHARGE_NERNST_PLANCK ? init[i].ions0 : nullptr, 2 * N);
   }
   rc = dispatch<CreateF>(H, H, init);
   if (rc) return bad(rc);
@@ -709,6 +741,7 @@ const char *adjoint_unsupported(const lbm_ehd_s *H) {
   const lbm_ehd_params &p = H->params[0];
   if (p.init_tol > 0 && p.init_sub_max > 1) return "reverse mode needs a fixed-count cold start (init_tol <= 0)";
   if (p.eps_ref_phase != 0) return "gradients along permittivity ratios need eps_ref_phase 0";
+  if (p.charge_model != LBM_CHARGE_LEAKY) return "reverse mode is built for the leaky-dielectric charge model";
   return nullptr;
 }
 
@@ -1027,28 +1060,31 @@ static void *field_src(const Inst &I, int bit) {
     case 15: return I.R;
     case 16: return I.u;
     case 17: return I.E;
+    case 18: case 19: return I.ion;
     default: return nullptr;
   }
 }
 static int field_sub(int bit) {
   switch (bit) {
-    case 1: case 5: case 9: case 12: return 1;
+    case 1: case 5: case 9: case 12: case 19: return 1;
     case 2: case 13: case 16: case 17: return 2;
     default: return 0;
   }
 }
 
 int lbm_ehd_fields(lbm_ehd_t H, int32_t inst, uint32_t mask, void *dev_dst, int32_t dtype) {
-  if (!H || inst < 0 || inst >= H->n_inst || !dev_dst || (mask >> 18) != 0)
+  if (!H || inst < 0 || inst >= H->n_inst || !dev_dst || (mask >> 20) != 0)
     return H ? H->fail(LBM_EHD_EINVAL, "fields: bad argument") : LBM_EHD_EINVAL;
-  if ((mask >> 16) != 0 && H->lattice != LBM_LATTICE_D3Q15)
+  if ((mask & (3u << 16)) != 0 && H->lattice != LBM_LATTICE_D3Q15)
     return H->fail(LBM_EHD_EINVAL, "fields: z components exist on D3Q15 only");
+  if ((mask & (3u << 18)) != 0 && H->params[inst].charge_model != LBM_CHARGE_NERNST_PLANCK)
+    return H->fail(LBM_EHD_EINVAL, "fields: ion concentrations exist under the Nernst-Planck model only");
   if (dtype != LBM_DTYPE_F32 && dtype != LBM_DTYPE_F64 && dtype != LBM_DTYPE_TANGENT_F64)
     return H->fail(LBM_EHD_EINVAL, "fields: bad dtype");
   const Inst &I = H->hinst[inst];
   const size_t N = (size_t)I.N, te = elem_size(H->prec), de = dtype == LBM_DTYPE_F32 ? 4 : 8;
   char *dst = (char *)dev_dst;
-  for (int bit = 0; bit < 18; ++bit) {
+  for (int bit = 0; bit < 20; ++bit) {
     if (!(mask & (1u << bit))) continue;
     const char *src = (const char *)field_src(I, bit) + field_sub(bit) * N * te;
     int rc = convert_any(H, (int)te, src, dst, N, dtype);
@@ -1142,7 +1178,9 @@ int lbm_ehd_tangent_gradient(lbm_ehd_t H, int64_t n_steps, const void *dev_seed,
                              void *dev_work, size_t work_bytes, double grad_theta[5]) {
   if (!H || !grad_theta || !dev_seed || n_steps < 0) return LBM_EHD_EINVAL;
   if (H->n_inst != 1) return H->fail(LBM_EHD_EUNSUPPORTED, "gradients need a single-instance handle");
-  if (seed_mask == 0 || (seed_mask >> 18) != 0 || ((seed_mask >> 16) != 0 && H->lattice != LBM_LATTICE_D3Q15))
+  if (seed_mask == 0 || (seed_mask >> 20) != 0 ||
+      ((seed_mask & (3u << 16)) != 0 && H->lattice != LBM_LATTICE_D3Q15) ||
+      ((seed_mask & (3u << 18)) != 0 && H->params[0].charge_model != LBM_CHARGE_NERNST_PLANCK))
     return H->fail(LBM_EHD_EINVAL, "tangent gradient: bad seed mask");
   size_t need = 0;
   lbm_ehd_tangent_workspace_bytes(H, &need);
@@ -1153,6 +1191,7 @@ int lbm_ehd_tangent_gradient(lbm_ehd_t H, int64_t n_steps, const void *dev_seed,
   ini.u0 = H->init_u[0].empty() ? nullptr : H->init_u[0].data();
   ini.q0 = H->init_q[0].empty() ? nullptr : H->init_q[0].data();
   ini.psi0 = H->init_psi[0].empty() ? nullptr : H->init_psi[0].data();
+  ini.ions0 = H->init_ions[0].empty() ? nullptr : H->init_ions[0].data();
   for (int dir = 0; dir < 5; ++dir) {
     const lbm_ehd_params t = tangent_params(H->params[0], dir);
     lbm_ehd_t T = nullptr;
@@ -1168,7 +1207,7 @@ int lbm_ehd_tangent_gradient(lbm_ehd_t H, int64_t n_steps, const void *dev_seed,
     const Inst &I = T->hinst[0];
     SeedPlanes sp;
     sp.count = 0;
-    for (int bit = 0; bit < 18; ++bit)
+    for (int bit = 0; bit < 20; ++bit)
       if (seed_mask & (1u << bit))
         sp.plane[sp.count++] = (const DualD *)field_src(I, bit) + (size_t)field_sub(bit) * I.N;
     k_seed_dot<<<dim3(I.nblk), dim3(NT), 0, T->stream>>>(T->d_insts, sp, (const double *)dev_seed);
@@ -1228,6 +1267,7 @@ int lbm_ehd_adjoint(lbm_ehd_t H, int64_t n_steps, int32_t ckpt_every, const void
     ini.u0 = H->init_u[0].empty() ? nullptr : H->init_u[0].data();
     ini.q0 = H->init_q[0].empty() ? nullptr : H->init_q[0].data();
     ini.psi0 = H->init_psi[0].empty() ? nullptr : H->init_psi[0].data();
+  ini.ions0 = H->init_ions[0].empty() ? nullptr : H->init_ions[0].data();
     rc = create_impl(&H->params[0], 1, &ini, work + L.shell, (void *)H->stream, &W, true);
     if (!rc) {
       rc = record_run(W, work, L, n_steps, ckpt_every);

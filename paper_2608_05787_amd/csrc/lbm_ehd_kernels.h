@@ -104,16 +104,19 @@ template <typename T> struct Phys {
   T m0, tau_f, tau_l, tau_h, eps_ref, D;
   T rho[3], visc[3], eps[3], sig[3];
   T Eext[3], wall_u[2], wall_phi[2], wall_q[2];
+  T ion_tau, ion_beta, ion_e;  // Nernst-Planck charge model
 };
 
 // Instance descriptor (device memory, read with uniform loads).
 struct Inst {
   int nx, ny, N, bc_y;
   int wall_q_mode, phase_mode, nblk, nz;
+  int charge_model, pad_[3];  // 0 leaky dielectric, 1 two-ion Nernst-Planck (l holds [2][Q][N])
   void *f[2], *g[2], *l[2], *h[2];
   float *f0[2];  // FP16S only: FP32 rest populations f^i_0, [3][N]
   // planes: phi 3, lsum, eps, q, R, psi, E D, mu 3, u D, p, rho, hpu 3D, hqu D
   void *phi, *lsum, *eps, *q, *R, *psi, *E, *mu, *u, *p, *rho, *hpu, *hqu;
+  void *ion;  // Nernst-Planck: n_+, n_- [2][N] (null otherwise)
   double *part_p;   // potential residual partials, nblk x 2
   double *part_mu;  // last-iteration residual partials, nblk x 2
   double *part_d;   // diagnostics partials, nblk x 16
@@ -383,6 +386,19 @@ __global__ __launch_bounds__(NT) void k_moments(const Inst *__restrict__ insts, 
     for (int j = IO::split ? 1 : 0; j < Q; ++j) a += IO::ld(f, (size_t)(i * Q + j) * N + n, T(SC_F));
     phi[(size_t)i * N + n] = a;
     if (rc.phi) rc.phi[(size_t)i * N + n] = a;
+  }
+  if (I.charge_model == 1) {
+    // ion concentrations and the charge they carry (Eq. 52 model)
+    T c[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      c[k] = 0;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) c[k] += IO::ld(l, (size_t)(k * Q + j) * N + n, T(SC_L));
+      (gbl((T *)I.ion))[(size_t)k * N + n] = c[k];
+    }
+    (gbl((T *)I.lsum))[n] = phys<T>(I).ion_e * (c[0] - c[1]);
+    return;
   }
   T b = 0;
 #pragma unroll
@@ -845,8 +861,10 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < Q; ++j) fin[i][j] = ldf(i, j);
+    const bool ions = I.charge_model == 1;
+    if (!ions)
 #pragma unroll
-    for (int j = 0; j < Q; ++j) lin[j] = IO::ld(ls, (size_t)j * N + n, T(SC_L));
+      for (int j = 0; j < Q; ++j) lin[j] = IO::ld(ls, (size_t)j * N + n, T(SC_L));
     const T R = (gbl((const T *)I.R))[n];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -966,8 +984,36 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
       push<L, T, S>(gbl((S *)I.g[nc]), v, I, nd, 0, rho, P.wall_u[0], P.wall_u[1], T(0), T(0), T(SC_G), false);
     }
 
+    // two ion families (Nernst-Planck model): BGK advection-diffusion with
+    // the drift z beta D E of this step's field, no-flux walls
+    if (ions) {
+      const T itn = T(1) / P.ion_tau, Dn = (P.ion_tau - T(0.5)) / T(3);
+      auto E = gbl((const T *)I.E);
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const T z = k == 0 ? T(1) : T(-1);
+        T m[Q], ns = 0;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+          m[j] = IO::ld(ls, (size_t)(k * Q + j) * N + n, T(SC_L));
+          ns += m[j];
+        }
+        T w[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) w[d] = u[d] + z * P.ion_beta * Dn * E[(size_t)d * N + n];
+        T v[Q];
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+          const T meq = lw<L, T>(j) * ns * (T(1) + cdot<L>(j, w) * T(3));
+          v[j] = m[j] - (m[j] - meq) * itn;
+        }
+        push<L, T, S>(gbl((S *)I.l[nc]) + (size_t)k * Q * N, v, I, nd, 0, ns, P.wall_u[0], P.wall_u[1], T(0), T(0),
+                      T(SC_L), false);
+      }
+    }
+
     // charge family
-    {
+    if (!ions) {
       const T itl = T(1) / P.tau_l, cl = T(1) - T(0.5) * itl;
       T v[Q];
 #pragma unroll
@@ -1059,7 +1105,23 @@ __global__ __launch_bounds__(NT) void k_init_pops(const Inst *__restrict__ insts
   for (int j = 0; j < Q; ++j) {
     const T cu = cdot<L>(j, u);
     IO::put(g, (size_t)j * N + n, IO::cv(rho * lw<L, T>(j) * (cu * T(3) + cu * cu * T(4.5) - usq * T(1.5)), T(SC_G)));
-    IO::put(l, (size_t)j * N + n, IO::cv(lw<L, T>(j) * q * (T(1) + cu * T(3)), T(SC_L)));
+    if (I.charge_model == 0) IO::put(l, (size_t)j * N + n, IO::cv(lw<L, T>(j) * q * (T(1) + cu * T(3)), T(SC_L)));
+  }
+  if (I.charge_model == 1) {
+    // ion equilibria with the drift of the cold-start field
+    const T Dn = (P.ion_tau - T(0.5)) / T(3);
+    auto E = gbl((const T *)I.E);
+    auto ion = gbl((const T *)I.ion);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const T z = k == 0 ? T(1) : T(-1), ns = ion[(size_t)k * N + n];
+      T w[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) w[d] = u[d] + z * P.ion_beta * Dn * E[(size_t)d * N + n];
+#pragma unroll
+      for (int j = 0; j < Q; ++j)
+        IO::put(l, (size_t)(k * Q + j) * N + n, IO::cv(lw<L, T>(j) * ns * (T(1) + cdot<L>(j, w) * T(3)), T(SC_L)));
+    }
   }
 #pragma unroll
   for (int d = 0; d < D; ++d) (gbl((T *)I.hqu))[(size_t)d * N + n] = q * u[d];
@@ -1101,7 +1163,8 @@ __global__ __launch_bounds__(NT) void k_export_pops(const Inst *__restrict__ ins
   } else {
     const S *p = (const S *)(fam == 1 ? I.g[pc] : I.l[pc]);
     const T sc = fam == 1 ? T(SC_G) : T(SC_L);
-    for (int j = 0; j < Q; ++j) dst[j * N + n] = (Tout)IO::ld(p, j * N + n, sc);
+    const int nq = (fam == 2 && I.charge_model == 1) ? 2 * Q : Q;
+    for (int j = 0; j < nq; ++j) dst[j * N + n] = (Tout)IO::ld(p, j * N + n, sc);
   }
 }
 
@@ -1127,7 +1190,7 @@ __global__ __launch_bounds__(NT) void k_tangent(const DualD *__restrict__ src, T
 // Seeded directional derivative, first pass: per block, sum over the
 // selected planes of seed * tangent (planes: pointers to [N] dual planes).
 struct SeedPlanes {
-  const DualD *plane[18];
+  const DualD *plane[20];
   int count;
 };
 __global__ __launch_bounds__(NT) void k_seed_dot(const Inst *__restrict__ insts, SeedPlanes sp,
@@ -1189,6 +1252,8 @@ __global__ __launch_bounds__(NT) void k_diag(const Inst *__restrict__ insts, con
       bad += !isfinite((double)IO::ld(l, (size_t)j * N + n, T(SC_L)));
       bad += !isfinite((double)h[(size_t)j * N + n]);
     }
+    if (I.charge_model == 1)
+      for (int j = Q; j < 2 * Q; ++j) bad += !isfinite((double)IO::ld(l, (size_t)j * N + n, T(SC_L)));
     v[4] = bad;
     const double xx = nd.x, yy = nd.y;
     const double wo = drop_indicator(1.0 - p1), wi = drop_indicator(p3);

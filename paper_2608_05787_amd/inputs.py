@@ -14,7 +14,9 @@ A parameter dict carries:
   nx, ny, bc_y (0 periodic, 1 walls), wall_u, wall_phi, wall_q_mode, wall_q,
   E_ext, gamma12, gamma13, gamma23, width, rho[3], visc[3], eps[3], sigma[3],
   tau_f, tau_l, eps_ref_phase, phase_mode, sub_min, sub_max, sub_tol,
-  init_sub_max, init_tol, nz, lattice (0 D2Q9, 1 D3Q15), E_ext_z.
+  init_sub_max, init_tol, nz, lattice (0 D2Q9, 1 D3Q15), E_ext_z,
+  charge_model (0 leaky dielectric, 1 two-ion Nernst-Planck), ion_tau,
+  ion_beta, ion_charge.
 """
 from __future__ import annotations
 
@@ -27,6 +29,7 @@ __all__ = [
     "eof_channel", "static_doublet", "field_compound_drop", "batch_sweep",
     "adjoint_case", "parity_case", "applied_field", "theta_of", "with_theta", "liquid_lens",
     "base_params3d", "sphere_drop", "compound_drop3d", "parity_case3d", "field_compound_drop3d",
+    "two_compound_drops", "np_eof_channel", "np_parity_case",
 ]
 
 
@@ -323,6 +326,24 @@ def parity_case(nx, ny, seed=0, walls=True, field=True, shear=True, sub=(2, 2, 0
         p.update(E_ext=(2e-3, -1e-3))
     psi0 = 0.4 * (y + 0.5) / ny if (walls and field) else np.zeros((ny, nx))
     return p, {"phi0": phi0, "u0": u0, "q0": q0, "psi0": psi0}
+
+
+def np_parity_case(nx, ny, nz=0, seed=0, walls=True, sub=(2, 2, 0.0)):
+    """parity_case (D2Q9, nz = 0) or parity_case3d (D3Q15, nz > 0) under
+    the two-ion Nernst-Planck charge model: conductivities zero, seeded ion
+    concentrations around 1 (so a non-zero initial charge), drift strong
+    enough to move them within a few steps."""
+    if nz > 0:
+        p, init = parity_case3d(nx, ny, nz, seed=seed, walls=walls, sub=sub)
+    else:
+        p, init = parity_case(nx, ny, seed=seed, walls=walls, sub=sub)
+    rng = np.random.default_rng(1000 + seed)
+    shape = init["phi0"].shape[1:]
+    ions = np.stack([1.0 + 0.05 * rng.standard_normal(shape), 1.0 + 0.05 * rng.standard_normal(shape)])
+    p.update(sigma=(0.0, 0.0, 0.0), charge_model=1, ion_tau=0.75, ion_beta=5.0, ion_charge=2e-3)
+    init = dict(init, ions0=ions)
+    init.pop("q0", None)
+    return p, init
 
 
 def parity_case3d(nx, ny, nz, seed=0, walls=True, field=True, shear=True, sub=(2, 2, 0.0)):

@@ -103,3 +103,28 @@ def test_two_drop_workload_geometry():
     q, _ = inputs.two_compound_drops(regime="separation")
     assert abs(q["eps"][1] / q["eps"][0] - 0.2) < 1e-12 and abs(q["sigma"][1] / q["sigma"][0] - 1.04) < 1e-12
     assert p["bc_y"] == 1 and p["wall_phi"][1] > 0
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of lbm_ehd_params and lbm_ehd_init have the C
+    header's size and field offsets (compiled with the host compiler)."""
+    import ctypes
+    import subprocess
+    from paper_2608_05787_amd import binding
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    fields = [f[0] for f in binding.Params._fields_ if not f[0].startswith("reserved")]
+    src = tmp_path / "probe.c"
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "lbm_ehd.h"', "int main(void) {",
+             '  printf("params %zu\\n", sizeof(lbm_ehd_params));',
+             '  printf("init %zu\\n", sizeof(lbm_ehd_init));']
+    lines += ['  printf("%s %%zu\\n", offsetof(lbm_ehd_params, %s));' % (f, f) for f in fields]
+    lines += ['  printf("ions0 %zu\\n", offsetof(lbm_ehd_init, ions0));', "  return 0;", "}"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(root, "include"), "-o", str(exe), str(src)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)]).decode().splitlines())
+    assert int(got["params"]) == ctypes.sizeof(binding.Params)
+    assert int(got["init"]) == ctypes.sizeof(binding.Init)
+    for f in fields:
+        assert int(got[f]) == getattr(binding.Params, f).offset, f
+    assert int(got["ions0"]) == binding.Init.ions0.offset
