@@ -67,6 +67,17 @@ __device__ __forceinline__ bool push_slot(const Inst &I, int x, int y, int n, in
 template <typename F>
 __device__ __forceinline__ void for_sources(const Inst &I, int x, int y, F &&f) {
   const int nx = I.nx, ny = I.ny;
+  if (!I.bc_y || (y > 0 && y < ny - 1)) {
+    // away from walls every source is a plain (wrapped) neighbour: calls
+    // without conditions, whose gathers the compiler can issue together
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      int sy = y - cy(j);
+      sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
+      f(j, sy * nx + wrapx(x - cx(j), nx));
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
     const int sx = wrapx(x - cx(j), nx);
@@ -194,6 +205,26 @@ __global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ ins
     return wall(j) ? -T(6) * wgt<T>(j) * T(cx(j)) * (cy(j) > 0 ? P.wall_u[1] : P.wall_u[0]) : T(0);
   };
 
+  // ---- the pulled adjoints (and the moment adjoint they carry), loaded
+  // before the first store: stores to planes the compiler cannot tell apart
+  // from A would otherwise hold back every later load
+  T la[Q], ga[Q], fa[3][Q], hp[3][2];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) la[j] = at(A + (size_t)AO_L * N, j) + PBc[(size_t)3 * N + dnode(j)];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) ga[j] = at(A + (size_t)AO_G * N, j);
+  if (I.phase_mode == 0)
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < Q; ++j) fa[i][j] = at(A + (size_t)(i * Q) * N, j) + PBc[(size_t)i * N + dnode(j)];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    hp[i][0] = A[(size_t)(AO_HPU + 2 * i) * N + n];
+    hp[i][1] = A[(size_t)(AO_HPU + 2 * i + 1) * N + n];
+  }
+  const T hqx = A[(size_t)AO_HQU * N + n], hqy = A[(size_t)(AO_HQU + 1) * N + n];
+
   // ---- adjoint accumulators
   T ph_b[3] = {T(0), T(0), T(0)}, mu_b[3] = {T(0), T(0), T(0)};
   T gmx_b[3] = {T(0), T(0), T(0)}, gmy_b[3] = {T(0), T(0), T(0)};
@@ -207,7 +238,7 @@ __global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ ins
     T dqx_b = 0, dqy_b = 0;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-      const T a = at(A + (size_t)AO_L * N, j) + PBc[(size_t)3 * N + dnode(j)];
+      const T a = la[j];
       const T vb = (dir && wall(j)) ? -a : a;
       if (!dir) q_b += a * wu(j);
       An[(size_t)AO_L * N + (size_t)j * N + n] = vb * (T(1) - itl);
@@ -221,7 +252,7 @@ __global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ ins
       dqy_b += vb * cl * wgt<T>(j) * T(3) * T(cy(j));
     }
     // dq = q u - (q u)_prev; (q u) is also this step's history output
-    const T hx = A[(size_t)AO_HQU * N + n], hy = A[(size_t)(AO_HQU + 1) * N + n];
+    const T hx = hqx, hy = hqy;
     q_b += (dqx_b + hx) * ux + (dqy_b + hy) * uy;
     ux_b += q * (dqx_b + hx);
     uy_b += q * (dqy_b + hy);
@@ -233,7 +264,7 @@ __global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ ins
   T g_b[Q];
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
-    const T vb = at(A + (size_t)AO_G * N, j);
+    const T vb = ga[j];
     rho_b += vb * wu(j);
     const T cu = T(cx(j)) * ux + T(cy(j)) * uy;
     const T sj = wgt<T>(j) * (cu * T(3) + cu * cu * T(4.5) - usq * T(1.5));
@@ -267,14 +298,14 @@ __global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ ins
   // ---- order-parameter families (Eqs. 34-36) and their history
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const T hx = A[(size_t)(AO_HPU + 2 * i) * N + n], hy = A[(size_t)(AO_HPU + 2 * i + 1) * N + n];
+    const T hx = hp[i][0], hy = hp[i][1];
     T dpx_b = 0, dpy_b = 0;
     if (I.phase_mode == 0) {
       const T m0 = P.m0, itf = T(1) / P.tau_f, cf = T(1) - T(0.5) * itf, im0 = T(1) / P.m0;
       T dtx_b = 0, dty_b = 0;
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
-        const T vb = at(A + (size_t)(i * Q) * N, j) + PBc[(size_t)i * N + dnode(j)];
+        const T vb = fa[i][j];
         ph_b[i] += vb * wu(j);
         An[(size_t)(i * Q + j) * N + n] = vb * (T(1) - itf);
         if (j == 0) {
