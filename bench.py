@@ -86,7 +86,11 @@ def workload(n, sub, init_iters):
     return p, init
 
 
-def run_gpu(p, init, precision, steps, warmup, profile_steps):
+def run_gpu(p, init, precision, steps, warmup, profile_steps, tune_steps=0):
+    """Create, warm up, optionally autotune the launch configuration (bitwise
+    the same results), then time `steps` steps with HIP events on the
+    handle's stream.  Returns (sim, ms, per-kernel profile, diagnostics,
+    tuning result or None)."""
     import torch
     from paper_2608_05787_amd import binding
     t0 = time.time()
@@ -95,6 +99,11 @@ def run_gpu(p, init, precision, steps, warmup, profile_steps):
     log("%s create (cold start) %.2fs" % (precision, time.time() - t0))
     sim.step(warmup)
     torch.cuda.synchronize()
+    tune = None
+    if tune_steps > 0:
+        tune = sim.autotune(steps=tune_steps)
+        log("%s autotune: config %d, ms/step per config %s" % (precision, tune["config"],
+                                                               ["%.4f" % v for v in tune["ms_per_step"]]))
     stream = sim.stream
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -110,7 +119,7 @@ def run_gpu(p, init, precision, steps, warmup, profile_steps):
         sim.step(profile_steps)
         prof = sim.profile_end()
     d = sim.diagnostics()
-    return sim, ms, prof, d
+    return sim, ms, prof, d, tune
 
 
 def cpu_baseline(p, init, budget_s):
@@ -193,6 +202,9 @@ def batch_bench(n_inst, steps, sub, init_iters, graph_len=10):
     batch = binding.Sim(cfgs, inits, precision="fp32", stream=stream)
     torch.cuda.synchronize()
     log("batch create %.1fs, %d instances, %d nodes" % (time.time() - t0, n_inst, nodes))
+    tune = batch.autotune(steps=10)
+    log("batch autotune: config %d, ms/step per config %s" % (tune["config"],
+                                                              ["%.3f" % v for v in tune["ms_per_step"]]))
     ms_eager = timed(batch.step, steps)
     batch.graph(graph_len)
     ms_graph = timed(batch.step, steps)
@@ -208,7 +220,8 @@ def batch_bench(n_inst, steps, sub, init_iters, graph_len=10):
     mlups = lambda ms: round(nodes * steps / (ms * 1e-3) / 1e6, 1)
     return {"instances": n_inst, "nodes": nodes, "steps": steps, "potential_subiterations": sub,
             "graph_steps": graph_len, "mlups_graph": mlups(ms_graph), "mlups_batched_eager": mlups(ms_eager),
-            "mlups_sequential": mlups(ms_seq), "speedup_graph_vs_sequential": round(ms_seq / ms_graph, 2)}
+            "mlups_sequential": mlups(ms_seq), "speedup_graph_vs_sequential": round(ms_seq / ms_graph, 2),
+            "tuning": tune}
 
 
 def d3q15_bench(n, steps, warmup, sub, init_iters, profile_steps):
@@ -225,7 +238,7 @@ def d3q15_bench(n, steps, warmup, sub, init_iters, profile_steps):
            "nodes": nodes, "potential_subiterations": sub}
     for prec in ("fp32", "fp16s", "fp64"):
         k = steps if prec != "fp64" else max(steps // 2, 1)
-        sim, ms, prof, diag = run_gpu(p, init, prec, k, warmup, profile_steps if prec == "fp32" else 0)
+        sim, ms, prof, diag, _ = run_gpu(p, init, prec, k, warmup, profile_steps if prec == "fp32" else 0)
         step_bytes = sum(bytes_per_node(kk, prec, 15, 3) * (sub if kk == "poisson" else 1)
                          for kk in ("moments", "pre", "poisson", "mu", "collide"))
         out[prec] = {"mlups": round(nodes * k / (ms * 1e-3) / 1e6, 1), "ms_per_step": ms / k,
@@ -308,6 +321,8 @@ def main():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--sub", type=int, default=4, help="potential sub-iterations per step")
     ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument("--tune-steps", type=int, default=20,
+                    help="steps timed per launch configuration by the autotuner (0: default configuration)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -355,7 +370,8 @@ def main():
         del a, b
     p, init = workload(args.n, args.sub, args.init_iters)
     nodes = p["nx"] * p["ny"]
-    sim, ms, prof, diag = run_gpu(p, init, "fp32", args.steps, args.warmup, args.profile_steps)
+    sim, ms, prof, diag, tune = run_gpu(p, init, "fp32", args.steps, args.warmup, args.profile_steps,
+                                        args.tune_steps)
     mlups = nodes * args.steps / (ms * 1e-3) / 1e6
     k_mean = args.sub
 
@@ -380,7 +396,10 @@ def main():
         for k, v in kernels.items():
             if k in BYTES_PER_NODE_FP32:
                 v["gbs"] = round(BYTES_PER_NODE_FP32[k] * nodes / (v["avg_us"] * 1e-6) / 1e9, 1)
-    n2, n1 = args.sub // 2, args.sub % 2
+    # potential launches of a step: two-iteration pairs plus one single when
+    # K is odd, or K singles when the tuner chose single launches
+    single = bool(tune and (tune["config"] & 2))
+    n2, n1 = (0, args.sub) if single else (args.sub // 2, args.sub % 2)
     step_bytes = {prec: sum(bytes_per_node(k, prec) * {"poisson": n1, "poisson2": n2}.get(k, 1)
                             for k in BYTES_PER_NODE_FP32) for prec in ("fp32", "fp16s", "fp64")}
 
@@ -389,11 +408,11 @@ def main():
     errors = None
     if not args.no_variants:
         del sim
-        _, ms64, _, _ = run_gpu(p, init, "fp64", max(args.steps // 2, 1), args.warmup // 2, 0)
+        _, ms64, _, _, _ = run_gpu(p, init, "fp64", max(args.steps // 2, 1), args.warmup // 2, 0, args.tune_steps)
         variants["fp64"] = {"mlups": round(nodes * max(args.steps // 2, 1) / (ms64 * 1e-3) / 1e6, 1),
                             "ms_per_step": ms64 / max(args.steps // 2, 1),
                             "bytes_per_node_update": step_bytes["fp64"]}
-        _, ms16, _, _ = run_gpu(p, init, "fp16s", args.steps, args.warmup, 0)
+        _, ms16, _, _, _ = run_gpu(p, init, "fp16s", args.steps, args.warmup, 0, args.tune_steps)
         variants["fp16s"] = {"mlups": round(nodes * args.steps / (ms16 * 1e-3) / 1e6, 1),
                              "ms_per_step": ms16 / args.steps,
                              "bytes_per_node_update": step_bytes["fp16s"]}
@@ -430,6 +449,7 @@ def main():
                                "sigma ratios 3/0.3, radii 80/60)" % (args.n, args.n),
                    "nodes": nodes, "potential_subiterations": k_mean, "precision": "fp32",
                    "algorithmic_bytes_per_node_update": step_bytes["fp32"]},
+        "tuning": tune,
         "roofline": roofline,
         "kernels": kernels,
         "variants": variants,

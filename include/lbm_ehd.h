@@ -223,6 +223,37 @@ int lbm_ehd_diagnostics(lbm_ehd_t h, int32_t inst, double out[10]);
  * instances.  Synchronises. */
 int lbm_ehd_scalars(lbm_ehd_t h, double out[3]);
 
+/* Launch configuration (autotuning).  The block order and the collide load
+ * schedule do not change the results (bitwise); the two potential kernel
+ * forms agree to rounding (their multiply-adds are scheduled differently).
+ * Bits:
+ *  LBM_TUNE_LINEAR_ORDER: launched blocks take node blocks (and potential
+ *    tiles) in row order, instead of giving each XCD a contiguous range of
+ *    rows (neighbour rows then share that XCD's L2);
+ *  LBM_TUNE_SINGLE_POTENTIAL: fixed-count potential sub-iterations run one
+ *    launch each instead of the LDS-tiled two-iteration kernel (which exists
+ *    for fixed-count D2Q9 handles in FP32, FP16S or FP64; elsewhere single
+ *    launches are the only form and the bit changes nothing);
+ *  LBM_TUNE_COLLIDE_PER_FAMILY: the collide kernel loads each population
+ *    family next to its use (fewer registers, more waves per SIMD) instead
+ *    of issuing every load before its first store (more loads in flight);
+ *    FP32 and FP16S handles (FP64 and tangent always load per family).
+ * A captured graph (lbm_ehd_graph) is re-captured with the new
+ * configuration. */
+enum { LBM_TUNE_LINEAR_ORDER = 1, LBM_TUNE_SINGLE_POTENTIAL = 2, LBM_TUNE_COLLIDE_PER_FAMILY = 4 };
+int lbm_ehd_set_tuning(lbm_ehd_t h, int32_t config);
+int lbm_ehd_get_tuning(lbm_ehd_t h, int32_t *config);
+
+/* Autotuner: from the handle's current state, runs 2 warm-up steps and
+ * times `steps` steps (HIP events on the handle's stream) under each
+ * configuration 0..7, then restores the state and keeps the fastest.
+ * dev_scratch: caller device memory of lbm_ehd_checkpoint_bytes (holds the
+ * saved state).  ms_per_step[c]: time per step of configuration c, or -1 for
+ * a configuration that coincides with another on this handle (a bit that
+ * changes nothing; not run).  *best (may be NULL) receives the configuration kept.
+ * Synchronises the stream; not while profiling (ESTATE). */
+int lbm_ehd_tune(lbm_ehd_t h, int32_t steps, void *dev_scratch, double ms_per_step[8], int32_t *best);
+
 /* Save / restore the complete evolving state (populations of the current
  * level, history planes, last fields, control words) to / from caller
  * device memory of lbm_ehd_checkpoint_bytes.  Checkpoint is async; restore

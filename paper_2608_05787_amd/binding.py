@@ -61,7 +61,9 @@ EXPORTS = ["lbm_ehd_adjoint_workspace_bytes", "lbm_ehd_workspace_bytes", "lbm_eh
            "lbm_ehd_checkpoint_bytes", "lbm_ehd_checkpoint", "lbm_ehd_restore",
            "lbm_ehd_adjoint", "lbm_ehd_record", "lbm_ehd_tangent_workspace_bytes", "lbm_ehd_tangent_gradient",
            "lbm_ehd_profile_begin", "lbm_ehd_profile_end", "lbm_ehd_graph",
+           "lbm_ehd_set_tuning", "lbm_ehd_get_tuning", "lbm_ehd_tune",
            "lbm_ehd_destroy", "lbm_ehd_strerror", "lbm_ehd_last_error"]
+TUNE_LINEAR_ORDER, TUNE_SINGLE_POTENTIAL, TUNE_COLLIDE_PER_FAMILY = 1, 2, 4
 KERNELS = ["moments", "pre", "poisson", "mu", "collide", "diag", "poisson2"]
 
 _lib = None
@@ -95,6 +97,9 @@ def load():
     lib.lbm_ehd_profile_begin.argtypes = [vp]
     lib.lbm_ehd_profile_end.argtypes = [vp, _dp, ctypes.POINTER(ctypes.c_int64)]
     lib.lbm_ehd_graph.argtypes = [vp, ctypes.c_int32]
+    lib.lbm_ehd_set_tuning.argtypes = [vp, ctypes.c_int32]
+    lib.lbm_ehd_get_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.lbm_ehd_tune.argtypes = [vp, ctypes.c_int32, vp, _dp, ctypes.POINTER(ctypes.c_int32)]
     lib.lbm_ehd_destroy.argtypes = [vp]
     lib.lbm_ehd_destroy.restype = None
     lib.lbm_ehd_strerror.argtypes = [ctypes.c_int]
@@ -329,6 +334,58 @@ class Sim:
     def graph(self, steps_per_graph: int):
         """Capture a block of steps into a HIP graph replayed by step()."""
         self._check(load().lbm_ehd_graph(self._h, int(steps_per_graph)), self._h)
+
+    # -- launch configuration (results are bitwise the same in every one)
+    def set_tuning(self, config: int):
+        self._check(load().lbm_ehd_set_tuning(self._h, int(config)), self._h)
+
+    def get_tuning(self) -> int:
+        c = ctypes.c_int32()
+        self._check(load().lbm_ehd_get_tuning(self._h, ctypes.byref(c)), self._h)
+        return int(c.value)
+
+    def tuning_key(self) -> str:
+        """What the timing of a configuration depends on: lattice, precision,
+        sub-iteration settings, charge model and the instance sizes."""
+        import json
+        p = self._params
+        return json.dumps({"lattice": int(p[0].lattice), "precision": self.precision,
+                           "sub": [int(p[0].sub_min), int(p[0].sub_max), float(p[0].sub_tol)],
+                           "charge_model": int(p[0].charge_model),
+                           "sizes": [list(s) for s in self.shapes]}, sort_keys=True)
+
+    def autotune(self, steps: int = 20, cache: str = None) -> dict:
+        """Pick the fastest launch configuration for this handle.  With a
+        cache file (JSON), a configuration stored under this handle's
+        tuning_key() is applied without timing; otherwise lbm_ehd_tune times
+        the configurations on the handle's own state (which it restores) and
+        the choice is stored.  Returns {"config", "ms_per_step", "cached"}."""
+        import json
+        import torch
+        key = self.tuning_key()
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+            if key in table:
+                self.set_tuning(int(table[key]["config"]))
+                return dict(table[key], cached=True)
+        nb = ctypes.c_size_t()
+        self._check(load().lbm_ehd_checkpoint_bytes(self._h, ctypes.byref(nb)), self._h)
+        scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        ms = (ctypes.c_double * 8)()
+        best = ctypes.c_int32()
+        self._check(load().lbm_ehd_tune(self._h, int(steps), ctypes.c_void_p(scratch.data_ptr()), ms,
+                                        ctypes.byref(best)), self._h)
+        entry = {"config": int(best.value), "ms_per_step": [float(v) for v in ms]}
+        if cache:
+            table[key] = entry
+            tmp = cache + ".tmp%d" % os.getpid()
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return dict(entry, cached=False)
 
     def profile_begin(self):
         self._check(load().lbm_ehd_profile_begin(self._h), self._h)

@@ -95,14 +95,15 @@ Plan make_plan(const lbm_ehd_params *p, int n) {
   size_t off = align_up((size_t)n * sizeof(Inst));
   P.total_blocks = 0;
   for (int i = 0; i < n; ++i) P.total_blocks += (int)(((size_t)p[i].nx * p[i].ny * lat_nz(p[i]) + NT - 1) / NT);
+  // block and tile tables, each in two orders (XCD-grouped, linear)
   P.b2i_off = off;
-  off = align_up(off + (size_t)P.total_blocks * sizeof(int2));
+  off = align_up(off + 2 * (size_t)P.total_blocks * sizeof(int2));
   P.total_tiles2 = 0;
   // two-iteration potential tiles (D2Q9 planes only)
   for (int i = 0; i < n; ++i)
     if (p[i].lattice == LBM_LATTICE_D2Q9) P.total_tiles2 += ((p[i].nx + P2W - 1) / P2W) * ((p[i].ny + P2H - 1) / P2H);
   P.t2_off = off;
-  off = align_up(off + (size_t)P.total_tiles2 * sizeof(int4));
+  off = align_up(off + 2 * (size_t)P.total_tiles2 * sizeof(int4));
   P.state_off = off;
   for (int i = 0; i < n; ++i) {
     P.lay.push_back(layout_one(p[i], off));
@@ -237,8 +238,16 @@ struct lbm_ehd_s {
   std::vector<lbm_ehd_params> params;
   std::vector<Inst> hinst;
   Inst *d_insts = nullptr;
-  int2 *d_b2i = nullptr;
-  int4 *d_t2 = nullptr;
+  int2 *d_b2i = nullptr;  // block table in the order in use
+  int4 *d_t2 = nullptr;   // tile table of the two-iteration potential kernel, in use
+  // launch configuration (lbm_ehd_set_tuning): LBM_TUNE_* bits
+  int tuning = 0;
+  bool pairs() const { return !(tuning & LBM_TUNE_SINGLE_POTENTIAL); }
+  void apply_order() {
+    const int lin = (tuning & LBM_TUNE_LINEAR_ORDER) ? 1 : 0;
+    d_b2i = (int2 *)(ws + plan.b2i_off) + (size_t)lin * plan.total_blocks;
+    d_t2 = (int4 *)(ws + plan.t2_off) + (size_t)lin * plan.total_tiles2;
+  }
   int sub_min = 1, sub_max = 1, adaptive = 0;
   double sub_tol = 0;
   long long steps = 0;
@@ -319,24 +328,26 @@ int enqueue_fixed_potential(lbm_ehd_s *H, int K) {
   const dim3 grid(H->plan.total_blocks), grid2(H->plan.total_tiles2), block(NT), block2(P2NT);
   int L = 0, k = 1;
   if constexpr (sizeof(T) <= 8 && std::is_same<Lat, D2Q9>::value) {
-    if (K & 1) {
-      hipEvent_t e = H->prof_start(2);
-      k_poisson<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, 1, K, 0, 0);
-      H->prof_stop(e);
-      L = 1;
-      k = 2;
+    if (H->pairs()) {
+      if (K & 1) {
+        hipEvent_t e = H->prof_start(2);
+        k_poisson<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, 1, K, 0, 0);
+        H->prof_stop(e);
+        L = 1;
+        k = 2;
+      }
+      for (; k + 1 <= K; k += 2, ++L) {
+        hipEvent_t e = H->prof_start(6);
+        k_poisson2<T><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, k + 1 == K ? 1 : 0);
+        H->prof_stop(e);
+      }
+      return L;
     }
-    for (; k + 1 <= K; k += 2, ++L) {
-      hipEvent_t e = H->prof_start(6);
-      k_poisson2<T><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, k + 1 == K ? 1 : 0);
-      H->prof_stop(e);
-    }
-  } else {
-    for (; k <= K; ++k, ++L) {
-      hipEvent_t e = H->prof_start(2);
-      k_poisson<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, k, K, 0, L & 1);
-      H->prof_stop(e);
-    }
+  }
+  for (; k <= K; ++k, ++L) {
+    hipEvent_t e = H->prof_start(2);
+    k_poisson<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, k, K, 0, L & 1);
+    H->prof_stop(e);
   }
   return L;
 }
@@ -450,8 +461,12 @@ int do_step(lbm_ehd_s *H, int64_t n) {
     k_mu<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, hflip);
     H->prof_stop(e);
     e = H->prof_start(4);
-    k_collide<Lat, T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, pc, s == n - 1 ? 1 : 0,
-                                                        ad ? 0 : K, hflip);
+    if (sizeof(T) <= 4 && !(H->tuning & LBM_TUNE_COLLIDE_PER_FAMILY))
+      k_collide<Lat, T, S, true><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, pc, s == n - 1 ? 1 : 0,
+                                                                ad ? 0 : K, hflip);
+    else
+      k_collide<Lat, T, S, false><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, pc, s == n - 1 ? 1 : 0,
+                                                                 ad ? 0 : K, hflip);
     H->prof_stop(e);
     HIPC(H, hipGetLastError());
   }
@@ -580,8 +595,7 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
   H->sub_tol = params[0].sub_tol;
   H->adaptive = (H->sub_tol > 0 && H->sub_max > H->sub_min) ? 1 : 0;
   H->d_insts = (Inst *)(H->ws + H->plan.desc_off);
-  H->d_b2i = (int2 *)(H->ws + H->plan.b2i_off);
-  H->d_t2 = (int4 *)(H->ws + H->plan.t2_off);
+  H->apply_order();
 
   const size_t te = elem_size(H->prec);
   // logical block order: instances one after another, blocks in row order
@@ -631,16 +645,23 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
     return x * q8 + std::min(x, r8) + i;
   };
   const int B = (int)logical.size();
-  std::vector<int2> b2i(B);
-  for (int b = 0; b < B; ++b) b2i[b] = logical[xcd_order(B, b)];
+  std::vector<int2> b2i(2 * (size_t)B);  // XCD-grouped order, then linear order
+  for (int b = 0; b < B; ++b) {
+    b2i[b] = logical[xcd_order(B, b)];
+    b2i[B + b] = logical[b];
+  }
   // tiles of the two-iteration potential kernel, rows of tiles in order
   std::vector<int4> tl;
   for (int i = 0; i < n_inst; ++i)
     if (params[i].lattice == LBM_LATTICE_D2Q9)
       for (int y0 = 0; y0 < params[i].ny; y0 += P2H)
         for (int x0 = 0; x0 < params[i].nx; x0 += P2W) tl.push_back(make_int4(i, x0, y0, 0));
-  std::vector<int4> t2(tl.size());
-  for (int b = 0; b < (int)tl.size(); ++b) t2[b] = tl[xcd_order((int)tl.size(), b)];
+  const int T2 = (int)tl.size();
+  std::vector<int4> t2(2 * (size_t)T2);
+  for (int b = 0; b < T2; ++b) {
+    t2[b] = tl[xcd_order(T2, b)];
+    t2[T2 + b] = tl[b];
+  }
   int rc = LBM_EHD_OK;
   auto bad = [&](int code) {
     g_create_error = H->err;
@@ -1131,6 +1152,76 @@ int lbm_ehd_scalars(lbm_ehd_t H, double out[3]) {
   out[1] = ktot;
   out[2] = H->n_inst;
   return LBM_EHD_OK;
+}
+
+int lbm_ehd_get_tuning(lbm_ehd_t H, int32_t *config) {
+  if (!H || !config) return LBM_EHD_EINVAL;
+  *config = H->tuning;
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_set_tuning(lbm_ehd_t H, int32_t config) {
+  if (!H || (config & ~7) != 0) return H ? H->fail(LBM_EHD_EINVAL, "set_tuning: unknown bits") : LBM_EHD_EINVAL;
+  if (H->prof) return H->fail(LBM_EHD_ESTATE, "set_tuning: not while profiling");
+  const int glen = H->glen;
+  H->drop_graph();  // a captured graph holds the previous tables
+  H->tuning = config;
+  H->apply_order();
+  return glen ? lbm_ehd_graph(H, glen) : LBM_EHD_OK;
+}
+
+int lbm_ehd_tune(lbm_ehd_t H, int32_t steps, void *dev_scratch, double ms_per_step[8], int32_t *best) {
+  if (!H || steps < 1 || !dev_scratch || !ms_per_step) return LBM_EHD_EINVAL;
+  if (H->prof) return H->fail(LBM_EHD_ESTATE, "tune: not while profiling");
+  // the two-iteration kernel exists for fixed-count D2Q9 FP32/FP16S/FP64 handles
+  const bool pair_form = H->lattice == LBM_LATTICE_D2Q9 && !H->adaptive && H->prec != LBM_PREC_TANGENT;
+  // the two collide load schedules differ for 4-byte arithmetic (FP32, FP16S)
+  const bool sched_form = H->prec == LBM_PREC_FP32 || H->prec == LBM_PREC_FP16S;
+  const int glen = H->glen;
+  H->drop_graph();
+  int rc = lbm_ehd_checkpoint(H, dev_scratch);
+  if (rc) return rc;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPC(H, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return H->fail(LBM_EHD_EHIP, "tune: hipEventCreate failed");
+  }
+  int pick = -1;
+  for (int c = 0; c < 8 && rc == LBM_EHD_OK; ++c) {
+    ms_per_step[c] = -1.0;
+    // bits that change nothing on this handle: same launches as without them
+    if ((c & LBM_TUNE_SINGLE_POTENTIAL) && !pair_form) continue;
+    if ((c & LBM_TUNE_COLLIDE_PER_FAMILY) && !sched_form) continue;
+    H->tuning = c;
+    H->apply_order();
+    if ((rc = lbm_ehd_restore(H, dev_scratch)) || (rc = lbm_ehd_step(H, 2))) break;
+    float ms = 0.f;
+    hipError_t e = hipEventRecord(e0, H->stream);
+    if (e == hipSuccess && (rc = lbm_ehd_step(H, steps)) == LBM_EHD_OK) {
+      e = hipEventRecord(e1, H->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    }
+    if (rc) break;
+    if (e != hipSuccess) {
+      rc = H->fail(LBM_EHD_EHIP, "tune: %s", hipGetErrorString(e));
+      break;
+    }
+    ms_per_step[c] = (double)ms / steps;
+    if (pick < 0 || ms_per_step[c] < ms_per_step[pick]) pick = c;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // the state as it was, the fastest configuration (or the previous one on failure)
+  const int keep = rc == LBM_EHD_OK && pick >= 0 ? pick : 0;
+  const int rr = lbm_ehd_restore(H, dev_scratch);
+  if (rc) return rc;
+  if (rr) return rr;
+  if (best) *best = keep;
+  H->tuning = keep;
+  H->apply_order();
+  return glen ? lbm_ehd_graph(H, glen) : LBM_EHD_OK;
 }
 
 int lbm_ehd_checkpoint_bytes(lbm_ehd_t H, size_t *bytes) {

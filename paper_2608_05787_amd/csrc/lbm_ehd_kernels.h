@@ -773,8 +773,11 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
 //   fixedK: sub-iterations of a fixed-count step (0 in adaptive mode) and
 //   hflip the buffer parity of its launches, which block 0 folds into
 //   ctl->hcur (no other kernel of the step reads it any more).
-template <class L, typename T, typename S>
-__global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
+//   EARLY: load schedule (see below; a launch-configuration choice, both
+//   give bitwise the same results).  The per-family D2Q9 FP32/FP16S form is
+//   held to 128 VGPRs (4 waves per SIMD), which it fits without spilling.
+template <class L, typename T, typename S, bool EARLY = (sizeof(T) <= 4)>
+__global__ __launch_bounds__(NT, (EARLY || sizeof(T) > 4 || L::Q > 9) ? 1 : 4) void k_collide(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
                                                 int pc, int write_macro, int fixedK, int hflip,
                                                 Rec<T> rc = Rec<T>{}) {
   constexpr int Q = L::Q, D = L::D;
@@ -835,13 +838,15 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
 #pragma unroll
       for (int i = 0; i < 3; ++i) F[d] -= ph[i] * gm[i][d];
     }
-    // Every population and history value is loaded before the first store:
-    // the stores (to buffers the compiler cannot tell apart from the loaded
-    // ones) would otherwise hold back the loads issued after them.  With
-    // 8-byte values the CH populations are loaded per family instead (the
-    // early copy would halve the occupancy).
+    // Load schedule.  EARLY: every population and history value is loaded
+    // before the first store (the stores, to buffers the compiler cannot
+    // tell apart from the loaded ones, would otherwise hold back the loads
+    // issued after them): most loads in flight, ~160 VGPRs.  Otherwise each
+    // family is loaded next to its use: fewer registers, higher occupancy,
+    // which wins when the state sits in the Infinity Cache.  8-byte values
+    // always use the second form (the early copy would halve the occupancy).
     using IO = PopIO<S, T>;
-    constexpr bool early = sizeof(T) <= 4;
+    constexpr bool early = EARLY && sizeof(T) <= 4;
     const bool ch = I.phase_mode == 0;
     const int fbs = fbuf(I, pc);
     auto gs = gbl((const S *)I.g[pc]);
@@ -862,16 +867,18 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
 #pragma unroll
         for (int j = 0; j < Q; ++j) fin[i][j] = ldf(i, j);
     const bool ions = I.charge_model == 1;
-    if (!ions)
+    if (early && !ions)
 #pragma unroll
       for (int j = 0; j < Q; ++j) lin[j] = IO::ld(ls, (size_t)j * N + n, T(SC_L));
     const T R = (gbl((const T *)I.R))[n];
+    if (early) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+      for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int d = 0; d < D; ++d) hp0[i][d] = hpu[(size_t)(i * D + d) * N + n];
+        for (int d = 0; d < D; ++d) hp0[i][d] = hpu[(size_t)(i * D + d) * N + n];
 #pragma unroll
-    for (int d = 0; d < D; ++d) hq0[d] = hqu[(size_t)d * N + n];
+      for (int d = 0; d < D; ++d) hq0[d] = hqu[(size_t)d * N + n];
+    }
     if (rc.g)
 #pragma unroll
       for (int j = 0; j < Q; ++j) rc.g[(size_t)j * N + n] = g[j];
@@ -909,13 +916,13 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         const T a = ph[i] * u[d];
-        dp[i][d] = a - hp0[i][d];
+        dp[i][d] = a - (early ? hp0[i][d] : hpu[(size_t)(i * D + d) * N + n]);
         hpu[(size_t)(i * D + d) * N + n] = a;
       }
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const T a = q * u[d];
-      dq[d] = a - hq0[d];
+      dq[d] = a - (early ? hq0[d] : hqu[(size_t)d * N + n]);
       hqu[(size_t)d * N + n] = a;
     }
 
@@ -1018,7 +1025,7 @@ __global__ __launch_bounds__(NT) void k_collide(const Inst *__restrict__ insts, 
       T v[Q];
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
-        const T lj = lin[j];
+        const T lj = early ? lin[j] : IO::ld(ls, (size_t)j * N + n, T(SC_L));
         const T cu = cdot<L>(j, u);
         const T leq = lw<L, T>(j) * q * (T(1) + cu * T(3));
         const T Sj = cl * lw<L, T>(j) * R;
