@@ -43,6 +43,13 @@ int ion_planes(const lbm_ehd_params &p) { return p.charge_model == LBM_CHARGE_NE
 int lat_q(const lbm_ehd_params &p) { return p.lattice == LBM_LATTICE_D3Q15 ? 15 : 9; }
 int lat_d(const lbm_ehd_params &p) { return p.lattice == LBM_LATTICE_D3Q15 ? 3 : 2; }
 int lat_nz(const lbm_ehd_params &p) { return p.nz > 1 ? p.nz : 1; }
+size_t lat_nodes(const lbm_ehd_params &p) { return (size_t)p.nx * p.ny * lat_nz(p); }
+// Plane stride: the node count rounded up to 64 nodes (planes 256-byte
+// aligned) plus a skew of 37 x 64 nodes.  Without the skew some sizes put
+// the ~36 planes a kernel streams at relative offsets that collide in the
+// HBM address mapping (1020^2: collide 27% and moments 28% slower than at
+// 1024^2 per node; the skew removes it and costs no traffic).
+size_t plane_stride(const lbm_ehd_params &p) { return (lat_nodes(p) + 63) / 64 * 64 + 64 * 37; }
 
 size_t elem_size(int prec) { return prec == LBM_PREC_TANGENT ? 16 : (prec == LBM_PREC_FP64 ? 8 : 4); }
 size_t pop_size(int prec) {
@@ -51,11 +58,11 @@ size_t pop_size(int prec) {
 
 Layout layout_one(const lbm_ehd_params &p, size_t off) {
   Layout L;
-  const size_t N = (size_t)p.nx * p.ny * lat_nz(p);
+  const size_t nodes = lat_nodes(p), N = plane_stride(p);
   const size_t Q = lat_q(p);
   const int D = lat_d(p);
   const size_t te = elem_size(p.precision), se = pop_size(p.precision);
-  L.nblk = (int)((N + NT - 1) / NT);
+  L.nblk = (int)((nodes + NT - 1) / NT);
   L.ctl = off;
   off = align_up(off + sizeof(Ctl));
   L.part_p = off;
@@ -359,25 +366,29 @@ int do_create(lbm_ehd_s *H, const lbm_ehd_init *init) {
   // upload initial fields (converted to T on the host)
   for (int i = 0; i < H->n_inst; ++i) {
     const Inst &I = H->hinst[i];
-    const size_t N = (size_t)I.N;
-    std::vector<T> buf(3 * N);
-    auto up = [&](const double *src, void *dst, size_t count) -> int {
-      for (size_t k = 0; k < count; ++k) buf[k] = src ? (T)src[k] : T(0);
-      HIPC(H, hipMemcpyAsync(dst, buf.data(), count * te, hipMemcpyHostToDevice, H->stream));
-      HIPC(H, hipStreamSynchronize(H->stream));
+    const size_t N = (size_t)I.nn, stride = (size_t)I.N;  // nodes (dense host arrays), plane stride
+    std::vector<T> buf(N);
+    // planes of N dense host values into planes of the state's stride
+    auto up = [&](const double *src, void *dst, size_t planes) -> int {
+      for (size_t k = 0; k < planes; ++k) {
+        for (size_t m = 0; m < N; ++m) buf[m] = src ? (T)src[k * N + m] : T(0);
+        HIPC(H, hipMemcpyAsync((char *)dst + k * stride * te, buf.data(), N * te, hipMemcpyHostToDevice,
+                               H->stream));
+        HIPC(H, hipStreamSynchronize(H->stream));
+      }
       return LBM_EHD_OK;
     };
     int rc;
-    if ((rc = up(init[i].phi0, I.phi, 3 * N))) return rc;
-    if ((rc = up(init[i].u0, I.u, (size_t)Lat::D * N))) return rc;
+    if ((rc = up(init[i].phi0, I.phi, 3))) return rc;
+    if ((rc = up(init[i].u0, I.u, (size_t)Lat::D))) return rc;
     if (H->params[i].charge_model == LBM_CHARGE_NERNST_PLANCK) {
       // ion concentrations and the charge they carry, q = e (n_+ - n_-)
       const double *c = init[i].ions0, e = H->params[i].ion_charge;
-      if ((rc = up(c, I.ion, 2 * N))) return rc;
+      if ((rc = up(c, I.ion, 2))) return rc;
       std::vector<double> q0(N);
       for (size_t k = 0; k < N; ++k) q0[k] = e * (c[k] - c[N + k]);
-      if ((rc = up(q0.data(), I.q, N))) return rc;
-    } else if ((rc = up(init[i].q0, I.q, N))) {
+      if ((rc = up(q0.data(), I.q, 1))) return rc;
+    } else if ((rc = up(init[i].q0, I.q, 1))) {
       return rc;
     }
     if constexpr (std::is_same<T, DualD>::value) {
@@ -394,7 +405,7 @@ int do_create(lbm_ehd_s *H, const lbm_ehd_init *init) {
       HIPC(H, hipMemcpyAsync(I.psi, buf.data(), N * te, hipMemcpyHostToDevice, H->stream));
       HIPC(H, hipStreamSynchronize(H->stream));
     } else {
-      if ((rc = up(init[i].psi0, I.psi, N))) return rc;
+      if ((rc = up(init[i].psi0, I.psi, 1))) return rc;
     }
   }
   k_init_potential<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i);
@@ -607,7 +618,8 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
     I.nx = p.nx;
     I.ny = p.ny;
     I.nz = lat_nz(p);
-    I.N = p.nx * p.ny * I.nz;
+    I.nn = (int)lat_nodes(p);
+    I.N = (int)plane_stride(p);
     I.bc_y = p.bc_y;
     I.wall_q_mode = p.wall_q_mode;
     I.phase_mode = p.phase_mode;
@@ -724,7 +736,7 @@ struct AdjLayout {
 AdjLayout adj_layout(const lbm_ehd_s *H, int64_t n_steps, int every) {
   AdjLayout L{};
   const lbm_ehd_params &p = H->params[0];
-  const size_t N = (size_t)p.nx * p.ny, te = elem_size(H->prec);
+  const size_t N = plane_stride(p), te = elem_size(H->prec);
   L.rev = n_steps > 1 ? n_steps - 1 : 0;
   L.nseg = (int)((L.rev + every - 1) / every);
   L.nck = L.nseg > 0 ? L.nseg : 1;
@@ -931,8 +943,9 @@ int reverse_sweep(lbm_ehd_s *H, lbm_ehd_s *W, char *work, const AdjLayout &L, in
   {
     std::vector<T> buf(N);
     const std::vector<double> &ps = H->init_psi[0];
-    for (size_t k = 0; k < N; ++k) buf[k] = ps.empty() ? T(0) : (T)ps[k];
-    HIPC(H, hipMemcpyAsync(psi0, buf.data(), N * sizeof(T), hipMemcpyHostToDevice, W->stream));
+    const size_t nodes = (size_t)I.nn;  // dense host plane; the sweep's planes have stride N
+    for (size_t k = 0; k < nodes; ++k) buf[k] = ps.empty() ? T(0) : (T)ps[k];
+    HIPC(H, hipMemcpyAsync(psi0, buf.data(), nodes * sizeof(T), hipMemcpyHostToDevice, W->stream));
     HIPC(H, hipStreamSynchronize(W->stream));
   }
   const int K0 = p.init_sub_max;
@@ -1103,14 +1116,15 @@ int lbm_ehd_fields(lbm_ehd_t H, int32_t inst, uint32_t mask, void *dev_dst, int3
   if (dtype != LBM_DTYPE_F32 && dtype != LBM_DTYPE_F64 && dtype != LBM_DTYPE_TANGENT_F64)
     return H->fail(LBM_EHD_EINVAL, "fields: bad dtype");
   const Inst &I = H->hinst[inst];
-  const size_t N = (size_t)I.N, te = elem_size(H->prec), de = dtype == LBM_DTYPE_F32 ? 4 : 8;
+  // state planes have stride I.N; the output planes are dense (I.nn values)
+  const size_t N = (size_t)I.N, M = (size_t)I.nn, te = elem_size(H->prec), de = dtype == LBM_DTYPE_F32 ? 4 : 8;
   char *dst = (char *)dev_dst;
   for (int bit = 0; bit < 20; ++bit) {
     if (!(mask & (1u << bit))) continue;
     const char *src = (const char *)field_src(I, bit) + field_sub(bit) * N * te;
-    int rc = convert_any(H, (int)te, src, dst, N, dtype);
+    int rc = convert_any(H, (int)te, src, dst, M, dtype);
     if (rc) return rc;
-    dst += N * de;
+    dst += M * de;
   }
   return LBM_EHD_OK;
 }
@@ -1120,7 +1134,7 @@ int lbm_ehd_populations(lbm_ehd_t H, int32_t inst, int32_t family, void *dev_dst
     return H ? H->fail(LBM_EHD_EINVAL, "populations: bad argument") : LBM_EHD_EINVAL;
   if (dtype != LBM_DTYPE_F32 && dtype != LBM_DTYPE_F64) return H->fail(LBM_EHD_EINVAL, "populations: bad dtype");
   const Inst &I = H->hinst[inst];
-  const dim3 grid((unsigned)((I.N + NT - 1) / NT)), block(NT);
+  const dim3 grid((unsigned)((I.nn + NT - 1) / NT)), block(NT);
   const int pc = (int)(H->steps & 1);
   dispatch<ExportF>(H, H, grid, block, inst, family, pc, dev_dst, dtype);
   HIPC(H, hipGetLastError());

@@ -749,7 +749,8 @@ __global__ __launch_bounds__(NT) void k_adj_seed(const Inst *__restrict__ insts,
   if (!nd.valid) return;
   const int N = Ip->N, n = nd.n;
   const int s[3] = {sel.x, sel.y, sel.z};
-  for (int k = 0; k < count; ++k) pb[(size_t)s[k] * N + n] += (T)seed[(size_t)k * N + n];
+  // seed planes are dense ([count][nn]); pb has the state's plane stride
+  for (int k = 0; k < count; ++k) pb[(size_t)s[k] * N + n] += (T)seed[(size_t)k * Ip->nn + n];
 }
 
 // Create-time populations are the equilibria of the initial fields (Eq. 35):

@@ -108,10 +108,14 @@ template <typename T> struct Phys {
 };
 
 // Instance descriptor (device memory, read with uniform loads).
+// N is the plane stride: the node count nn rounded up to 64 nodes (every
+// plane 256-byte aligned) plus a fixed skew against HBM address-mapping
+// conflicts between planes.  Node n of a plane sits at offset n < nn; the
+// tail up to N is padding no kernel reads.
 struct Inst {
   int nx, ny, N, bc_y;
   int wall_q_mode, phase_mode, nblk, nz;
-  int charge_model, pad_[3];  // 0 leaky dielectric, 1 two-ion Nernst-Planck (l holds [2][Q][N])
+  int charge_model, nn, pad_[2];  // charge model: 0 leaky dielectric, 1 two-ion Nernst-Planck (l holds [2][Q][N])
   void *f[2], *g[2], *l[2], *h[2];
   float *f0[2];  // FP16S only: FP32 rest populations f^i_0, [3][N]
   // planes: phi 3, lsum, eps, q, R, psi, E D, mu 3, u D, p, rho, hpu 3D, hqu D
@@ -213,7 +217,7 @@ __device__ __forceinline__ Node locate(const Inst *__restrict__ insts, const int
   lblk = t.y;
   Ip = insts + nd.inst;
   const int local = t.y * NT + (int)threadIdx.x;
-  nd.valid = local < Ip->N;
+  nd.valid = local < Ip->nn;
   nd.n = nd.valid ? local : 0;
   int r = nd.n;
   nd.z = 0;
@@ -1155,23 +1159,23 @@ __global__ __launch_bounds__(NT) void k_export_pops(const Inst *__restrict__ ins
   using IO = PopIO<S, T>;
   const Inst &I = insts[inst];
   const int n = blockIdx.x * NT + threadIdx.x;
-  if (n >= I.N) return;
-  const size_t N = I.N;
+  if (n >= I.nn) return;
+  const size_t N = I.N, M = I.nn;  // plane stride of the state, of the dense output
   if (fam == 0) {
     const int fb = fbuf(I, pc);
     auto f = gbl((const S *)I.f[fb]);
     for (int j = 0; j < 3 * Q; ++j) {
       const T v = (IO::split && j % Q == 0) ? (T)gbl(I.f0[fb])[(j / Q) * N + n] : IO::ld(f, j * N + n, T(SC_F));
-      dst[j * N + n] = (Tout)v;
+      dst[j * M + n] = (Tout)v;
     }
   } else if (fam == 3) {
     auto h = gbl((const T *)I.h[I.ctl->hcur]);
-    for (int j = 0; j < Q; ++j) dst[j * N + n] = (Tout)h[j * N + n];
+    for (int j = 0; j < Q; ++j) dst[j * M + n] = (Tout)h[j * N + n];
   } else {
     const S *p = (const S *)(fam == 1 ? I.g[pc] : I.l[pc]);
     const T sc = fam == 1 ? T(SC_G) : T(SC_L);
     const int nq = (fam == 2 && I.charge_model == 1) ? 2 * Q : Q;
-    for (int j = 0; j < nq; ++j) dst[j * N + n] = (Tout)IO::ld(p, j * N + n, sc);
+    for (int j = 0; j < nq; ++j) dst[j * M + n] = (Tout)IO::ld(p, j * N + n, sc);
   }
 }
 
@@ -1205,8 +1209,8 @@ __global__ __launch_bounds__(NT) void k_seed_dot(const Inst *__restrict__ insts,
   const Inst &I = insts[0];
   const int n = blockIdx.x * NT + threadIdx.x;
   double v[1] = {0.0};
-  if (n < I.N)
-    for (int k = 0; k < sp.count; ++k) v[0] += seed[(size_t)k * I.N + n] * sp.plane[k][n].d;
+  if (n < I.nn)  // seed planes are dense ([count][nn])
+    for (int k = 0; k < sp.count; ++k) v[0] += seed[(size_t)k * I.nn + n] * sp.plane[k][n].d;
   block_sum<1>(v);
   if (threadIdx.x == 0) I.part_p[(size_t)blockIdx.x * 2] = v[0];
 }
