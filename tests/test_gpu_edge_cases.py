@@ -1,0 +1,73 @@
+"""Edge cases on the GPU, through the C ABI: the smallest grids the ABI
+accepts (neighbours wrap onto the node itself or mirror the only other row),
+a D3Q15 box one layer thick, an absent phase that must stay exactly zero in
+every storage precision (the reduction of the three-phase model to the
+two-phase one), and zero steps."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+from oracle import Oracle  # noqa: E402
+from paper_2608_05787_amd import binding, inputs  # noqa: E402
+
+from test_gpu_parity import FP64_TOL, compare  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("nx,ny,walls", [(2, 2, False), (2, 2, True), (3, 2, True), (5, 3, False), (2, 7, True)])
+def test_smallest_grids_match_oracle(nx, ny, walls):
+    print("case tiny", nx, ny, walls, flush=True)
+    p, init = inputs.parity_case(nx, ny, seed=nx * 10 + ny, walls=walls, sub=(3, 3, 0.0))
+    ref = Oracle(p, init)
+    sim = binding.Sim(p, init, precision="fp64")
+    compare(sim, ref, FP64_TOL)
+    ref.step(6)
+    sim.step(6)
+    compare(sim, ref, FP64_TOL)
+
+
+def test_d3q15_single_layer_matches_oracle():
+    print("case d3q15 nz=1", flush=True)
+    p, init = inputs.parity_case3d(9, 8, 1, seed=5)
+    ref = Oracle(p, init)
+    sim = binding.Sim(p, init, precision="fp64")
+    ref.step(5)
+    sim.step(5)
+    names = ["phi1", "phi2", "phi3", "ux", "uy", "uz", "psi", "q", "Ez"]
+    got = {k: v.cpu().numpy() for k, v in sim.fields(names).items()}
+    for k in names:
+        r = ref.field(k)
+        assert np.abs(got[k] - r).max() <= FP64_TOL * max(np.abs(r).max(), 1e-300), k
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
+def test_absent_phase_stays_exactly_zero(prec):
+    """A field-driven drop of phase 2 only (phase 3 absent everywhere): its
+    populations, order parameter and chemical potential stay exactly zero,
+    and in FP64 the run matches the oracle."""
+    print("case absent phase", prec, flush=True)
+    p, init = inputs.field_compound_drop(64, r_shell=16.0, r_core=9.0, init_iters=50, init_tol=0.0)
+    phi0 = init["phi0"].copy()
+    phi0[1] += phi0[2]
+    phi0[2] = 0.0
+    init = dict(init, phi0=phi0)
+    sim = binding.Sim(p, init, precision=prec)
+    sim.step(40)
+    f = sim.fields(["phi3", "mu3"])
+    assert torch.count_nonzero(f["phi3"]) == 0 and torch.count_nonzero(f["mu3"]) == 0
+    assert torch.count_nonzero(sim.populations("f")[18:]) == 0
+    if prec == "fp64":
+        ref = Oracle(p, init)
+        ref.step(40)
+        compare(sim, ref, FP64_TOL)
+
+
+def test_zero_steps_change_nothing():
+    print("case zero steps", flush=True)
+    p, init = inputs.parity_case(33, 17, seed=1)
+    sim = binding.Sim(p, init, precision="fp32")
+    sim.step(3)
+    before = [sim.populations(fam).clone() for fam in "fglh"]
+    sim.step(0)
+    assert all(torch.equal(a, sim.populations(fam)) for a, fam in zip(before, "fglh"))
