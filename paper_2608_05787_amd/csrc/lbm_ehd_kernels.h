@@ -383,22 +383,37 @@ __global__ __launch_bounds__(NT) void k_moments(const Inst *__restrict__ insts, 
   auto f = gbl((const S *)I.f[fb]);
   auto l = gbl((const S *)I.l[pc]);
   auto phi = gbl((T *)I.phi);
+  // Every load before the first store: a store to a plane the compiler
+  // cannot tell apart from the loaded ones would hold back the later loads.
+  const bool ions = I.charge_model == 1;
+  T fv[3][Q], lv[2][Q];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < Q; ++j)
+      fv[i][j] = (IO::split && j == 0) ? (T)gbl(I.f0[fb])[(size_t)i * N + n]
+                                       : IO::ld(f, (size_t)(i * Q + j) * N + n, T(SC_F));
+#pragma unroll
+  for (int j = 0; j < Q; ++j) lv[0][j] = IO::ld(l, (size_t)j * N + n, T(SC_L));
+  if (ions)
+#pragma unroll
+    for (int j = 0; j < Q; ++j) lv[1][j] = IO::ld(l, (size_t)(Q + j) * N + n, T(SC_L));
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    T a = IO::split ? (T)gbl(I.f0[fb])[(size_t)i * N + n] : T(0);
+    T a = IO::split ? fv[i][0] : T(0);
 #pragma unroll
-    for (int j = IO::split ? 1 : 0; j < Q; ++j) a += IO::ld(f, (size_t)(i * Q + j) * N + n, T(SC_F));
+    for (int j = IO::split ? 1 : 0; j < Q; ++j) a += fv[i][j];
     phi[(size_t)i * N + n] = a;
     if (rc.phi) rc.phi[(size_t)i * N + n] = a;
   }
-  if (I.charge_model == 1) {
+  if (ions) {
     // ion concentrations and the charge they carry (Eq. 52 model)
     T c[2];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       c[k] = 0;
 #pragma unroll
-      for (int j = 0; j < Q; ++j) c[k] += IO::ld(l, (size_t)(k * Q + j) * N + n, T(SC_L));
+      for (int j = 0; j < Q; ++j) c[k] += lv[k][j];
       (gbl((T *)I.ion))[(size_t)k * N + n] = c[k];
     }
     (gbl((T *)I.lsum))[n] = phys<T>(I).ion_e * (c[0] - c[1]);
@@ -406,7 +421,7 @@ __global__ __launch_bounds__(NT) void k_moments(const Inst *__restrict__ insts, 
   }
   T b = 0;
 #pragma unroll
-  for (int j = 0; j < Q; ++j) b += IO::ld(l, (size_t)j * N + n, T(SC_L));
+  for (int j = 0; j < Q; ++j) b += lv[0][j];
   (gbl((T *)I.lsum))[n] = b;
 }
 
@@ -733,6 +748,17 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
 #pragma unroll
     for (int d = 0; d < D; ++d) e[d] = m[d] / den + P.Eext[d];
     auto psi = gbl((T *)I.psi);
+    // the phi stencils and the previous potential, loaded before the first
+    // store (later loads would wait for it: the compiler cannot tell the
+    // planes apart)
+    auto phi = gbl((const T *)I.phi);
+    T pv[3][Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const int m = nbr<L>(I, nd, j);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) pv[i][j] = phi[(size_t)i * N + m];
+    }
     const double dd = (double)pot - (double)psi[n];
     red[0] = dd * dd;
     red[1] = (double)pot * (double)pot;
@@ -745,16 +771,12 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
       if (rc.En) rc.En[(size_t)d * N + n] = e[d];
       if (d) e2 += e[d] * e[d];
     }
-    auto phi = gbl((const T *)I.phi);
     auto mu = gbl((T *)I.mu);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      T v[Q];
-#pragma unroll
-      for (int j = 0; j < Q; ++j) v[j] = phi[(size_t)i * N + nbr<L>(I, nd, j)];
       T gg[D], lap;
-      fdq<L>(v, gg, lap);
-      const T ph = v[0];
+      fdq<L>(pv[i], gg, lap);
+      const T ph = pv[i][0];
       const T bulk = T(24) / P.D * P.lam[i] * ph * (ph - T(0.5)) * (ph - T(1));
       const T grad = T(0.75) * P.D * P.lam[i] * lap;
       const T elec = T(0.5) * (T(6) * P.eps[i] * ph * (T(1) - ph)) * e2;
