@@ -237,22 +237,31 @@ int lbm_ehd_scalars(lbm_ehd_t h, double out[3]);
  *  LBM_TUNE_COLLIDE_PER_FAMILY: the collide kernel loads each population
  *    family next to its use (fewer registers, more waves per SIMD) instead
  *    of issuing every load before its first store (more loads in flight);
- *    FP32 and FP16S handles (FP64 and tangent always load per family).
+ *    FP32 and FP16S handles (FP64 and tangent always load per family);
+ *  LBM_TUNE_TALL_TILES: the two-iteration potential kernel uses 64 x 32
+ *    tiles (two rows per thread, 60 x 28 written) instead of 64 x 16
+ *    (60 x 12): less ring recomputation, twice the LDS, half the blocks
+ *    (FP32 and FP16S handles where the two-iteration kernel runs).
  * A captured graph (lbm_ehd_graph) is re-captured with the new
  * configuration. */
-enum { LBM_TUNE_LINEAR_ORDER = 1, LBM_TUNE_SINGLE_POTENTIAL = 2, LBM_TUNE_COLLIDE_PER_FAMILY = 4 };
+enum {
+  LBM_TUNE_LINEAR_ORDER = 1,
+  LBM_TUNE_SINGLE_POTENTIAL = 2,
+  LBM_TUNE_COLLIDE_PER_FAMILY = 4,
+  LBM_TUNE_TALL_TILES = 8
+};
 int lbm_ehd_set_tuning(lbm_ehd_t h, int32_t config);
 int lbm_ehd_get_tuning(lbm_ehd_t h, int32_t *config);
 
 /* Autotuner: from the handle's current state, runs 2 warm-up steps and
  * times `steps` steps (HIP events on the handle's stream) under each
- * configuration 0..7, then restores the state and keeps the fastest.
+ * configuration 0..15, then restores the state and keeps the fastest.
  * dev_scratch: caller device memory of lbm_ehd_checkpoint_bytes (holds the
  * saved state).  ms_per_step[c]: time per step of configuration c, or -1 for
  * a configuration that coincides with another on this handle (a bit that
  * changes nothing; not run).  *best (may be NULL) receives the configuration kept.
  * Synchronises the stream; not while profiling (ESTATE). */
-int lbm_ehd_tune(lbm_ehd_t h, int32_t steps, void *dev_scratch, double ms_per_step[8], int32_t *best);
+int lbm_ehd_tune(lbm_ehd_t h, int32_t steps, void *dev_scratch, double ms_per_step[16], int32_t *best);
 
 /* Save / restore the complete evolving state (populations of the current
  * level, history planes, last fields, control words) to / from caller

@@ -63,7 +63,7 @@ EXPORTS = ["lbm_ehd_adjoint_workspace_bytes", "lbm_ehd_workspace_bytes", "lbm_eh
            "lbm_ehd_profile_begin", "lbm_ehd_profile_end", "lbm_ehd_graph",
            "lbm_ehd_set_tuning", "lbm_ehd_get_tuning", "lbm_ehd_tune",
            "lbm_ehd_destroy", "lbm_ehd_strerror", "lbm_ehd_last_error"]
-TUNE_LINEAR_ORDER, TUNE_SINGLE_POTENTIAL, TUNE_COLLIDE_PER_FAMILY = 1, 2, 4
+TUNE_LINEAR_ORDER, TUNE_SINGLE_POTENTIAL, TUNE_COLLIDE_PER_FAMILY, TUNE_TALL_TILES = 1, 2, 4, 8
 KERNELS = ["moments", "pre", "poisson", "mu", "collide", "diag", "poisson2"]
 
 _lib = None
@@ -374,7 +374,7 @@ class Sim:
         self._check(load().lbm_ehd_checkpoint_bytes(self._h, ctypes.byref(nb)), self._h)
         scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
-        ms = (ctypes.c_double * 8)()
+        ms = (ctypes.c_double * 16)()
         best = ctypes.c_int32()
         self._check(load().lbm_ehd_tune(self._h, int(steps), ctypes.c_void_p(scratch.data_ptr()), ms,
                                         ctypes.byref(best)), self._h)
@@ -391,7 +391,7 @@ class Sim:
         self._check(load().lbm_ehd_profile_begin(self._h), self._h)
 
     def profile_end(self) -> dict:
-        ms = (ctypes.c_double * 8)()
+        ms = (ctypes.c_double * 16)()
         cnt = (ctypes.c_int64 * 8)()
         self._check(load().lbm_ehd_profile_end(self._h, ms, cnt), self._h)
         return {k: (ms[i], int(cnt[i])) for i, k in enumerate(KERNELS)}

@@ -92,7 +92,8 @@ Layout layout_one(const lbm_ehd_params &p, size_t off) {
 
 struct Plan {
   size_t desc_off, b2i_off, t2_off, state_off, total;
-  int total_blocks, total_tiles2;
+  int total_blocks, total_tiles2;  // tiles of the default (64 x 16) two-iteration shape
+  int total_tiles2t;               // tiles of the tall (64 x 32) shape
   std::vector<Layout> lay;
 };
 
@@ -105,12 +106,17 @@ Plan make_plan(const lbm_ehd_params *p, int n) {
   // block and tile tables, each in two orders (XCD-grouped, linear)
   P.b2i_off = off;
   off = align_up(off + 2 * (size_t)P.total_blocks * sizeof(int2));
-  P.total_tiles2 = 0;
-  // two-iteration potential tiles (D2Q9 planes only)
+  P.total_tiles2 = P.total_tiles2t = 0;
+  // two-iteration potential tiles (D2Q9 planes only), both shapes
+  constexpr int H1 = P2Shape<1>::H, H2 = P2Shape<2>::H;
   for (int i = 0; i < n; ++i)
-    if (p[i].lattice == LBM_LATTICE_D2Q9) P.total_tiles2 += ((p[i].nx + P2W - 1) / P2W) * ((p[i].ny + P2H - 1) / P2H);
+    if (p[i].lattice == LBM_LATTICE_D2Q9) {
+      P.total_tiles2 += ((p[i].nx + P2W - 1) / P2W) * ((p[i].ny + H1 - 1) / H1);
+      P.total_tiles2t += ((p[i].nx + P2W - 1) / P2W) * ((p[i].ny + H2 - 1) / H2);
+    }
+  // tile tables: default shape (XCD-grouped, linear), then tall shape (same)
   P.t2_off = off;
-  off = align_up(off + 2 * (size_t)P.total_tiles2 * sizeof(int4));
+  off = align_up(off + 2 * (size_t)(P.total_tiles2 + P.total_tiles2t) * sizeof(int4));
   P.state_off = off;
   for (int i = 0; i < n; ++i) {
     P.lay.push_back(layout_one(p[i], off));
@@ -249,11 +255,23 @@ struct lbm_ehd_s {
   int4 *d_t2 = nullptr;   // tile table of the two-iteration potential kernel, in use
   // launch configuration (lbm_ehd_set_tuning): LBM_TUNE_* bits
   int tuning = 0;
+  int n_t2 = 0;           // tiles in d_t2
   bool pairs() const { return !(tuning & LBM_TUNE_SINGLE_POTENTIAL); }
+  // the tall tile shape is built for 4-byte arithmetic (FP32, FP16S) only
+  bool tall() const {
+    return (tuning & LBM_TUNE_TALL_TILES) != 0 && (prec == LBM_PREC_FP32 || prec == LBM_PREC_FP16S);
+  }
   void apply_order() {
     const int lin = (tuning & LBM_TUNE_LINEAR_ORDER) ? 1 : 0;
     d_b2i = (int2 *)(ws + plan.b2i_off) + (size_t)lin * plan.total_blocks;
-    d_t2 = (int4 *)(ws + plan.t2_off) + (size_t)lin * plan.total_tiles2;
+    int4 *t = (int4 *)(ws + plan.t2_off);
+    if (tall()) {
+      d_t2 = t + 2 * (size_t)plan.total_tiles2 + (size_t)lin * plan.total_tiles2t;
+      n_t2 = plan.total_tiles2t;
+    } else {
+      d_t2 = t + (size_t)lin * plan.total_tiles2;
+      n_t2 = plan.total_tiles2;
+    }
   }
   int sub_min = 1, sub_max = 1, adaptive = 0;
   double sub_tol = 0;
@@ -332,7 +350,7 @@ namespace {
 // (its parity is the buffer flip of the whole loop).
 template <class Lat, typename T>
 int enqueue_fixed_potential(lbm_ehd_s *H, int K) {
-  const dim3 grid(H->plan.total_blocks), grid2(H->plan.total_tiles2), block(NT), block2(P2NT);
+  const dim3 grid(H->plan.total_blocks), grid2(H->n_t2), block(NT), block2(P2NT);
   int L = 0, k = 1;
   if constexpr (sizeof(T) <= 8 && std::is_same<Lat, D2Q9>::value) {
     if (H->pairs()) {
@@ -345,7 +363,14 @@ int enqueue_fixed_potential(lbm_ehd_s *H, int K) {
       }
       for (; k + 1 <= K; k += 2, ++L) {
         hipEvent_t e = H->prof_start(6);
-        k_poisson2<T><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, k + 1 == K ? 1 : 0);
+        if constexpr (sizeof(T) == 4) {
+          if (H->tall())
+            k_poisson2<T, 2><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, k + 1 == K ? 1 : 0);
+          else
+            k_poisson2<T, 1><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, k + 1 == K ? 1 : 0);
+        } else {
+          k_poisson2<T, 1><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, k + 1 == K ? 1 : 0);
+        }
         H->prof_stop(e);
       }
       return L;
@@ -663,16 +688,16 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
     b2i[B + b] = logical[b];
   }
   // tiles of the two-iteration potential kernel, rows of tiles in order
-  std::vector<int4> tl;
-  for (int i = 0; i < n_inst; ++i)
-    if (params[i].lattice == LBM_LATTICE_D2Q9)
-      for (int y0 = 0; y0 < params[i].ny; y0 += P2H)
-        for (int x0 = 0; x0 < params[i].nx; x0 += P2W) tl.push_back(make_int4(i, x0, y0, 0));
-  const int T2 = (int)tl.size();
-  std::vector<int4> t2(2 * (size_t)T2);
-  for (int b = 0; b < T2; ++b) {
-    t2[b] = tl[xcd_order(T2, b)];
-    t2[T2 + b] = tl[b];
+  std::vector<int4> t2;  // per shape: XCD-grouped order, then linear order
+  for (int rows : {P2Shape<1>::H, P2Shape<2>::H}) {
+    std::vector<int4> tl;
+    for (int i = 0; i < n_inst; ++i)
+      if (params[i].lattice == LBM_LATTICE_D2Q9)
+        for (int y0 = 0; y0 < params[i].ny; y0 += rows)
+          for (int x0 = 0; x0 < params[i].nx; x0 += P2W) tl.push_back(make_int4(i, x0, y0, 0));
+    const int T2 = (int)tl.size();
+    for (int b = 0; b < T2; ++b) t2.push_back(tl[xcd_order(T2, b)]);
+    t2.insert(t2.end(), tl.begin(), tl.end());
   }
   int rc = LBM_EHD_OK;
   auto bad = [&](int code) {
@@ -1175,7 +1200,7 @@ int lbm_ehd_get_tuning(lbm_ehd_t H, int32_t *config) {
 }
 
 int lbm_ehd_set_tuning(lbm_ehd_t H, int32_t config) {
-  if (!H || (config & ~7) != 0) return H ? H->fail(LBM_EHD_EINVAL, "set_tuning: unknown bits") : LBM_EHD_EINVAL;
+  if (!H || (config & ~15) != 0) return H ? H->fail(LBM_EHD_EINVAL, "set_tuning: unknown bits") : LBM_EHD_EINVAL;
   if (H->prof) return H->fail(LBM_EHD_ESTATE, "set_tuning: not while profiling");
   const int glen = H->glen;
   H->drop_graph();  // a captured graph holds the previous tables
@@ -1184,13 +1209,15 @@ int lbm_ehd_set_tuning(lbm_ehd_t H, int32_t config) {
   return glen ? lbm_ehd_graph(H, glen) : LBM_EHD_OK;
 }
 
-int lbm_ehd_tune(lbm_ehd_t H, int32_t steps, void *dev_scratch, double ms_per_step[8], int32_t *best) {
+int lbm_ehd_tune(lbm_ehd_t H, int32_t steps, void *dev_scratch, double ms_per_step[16], int32_t *best) {
   if (!H || steps < 1 || !dev_scratch || !ms_per_step) return LBM_EHD_EINVAL;
   if (H->prof) return H->fail(LBM_EHD_ESTATE, "tune: not while profiling");
   // the two-iteration kernel exists for fixed-count D2Q9 FP32/FP16S/FP64 handles
   const bool pair_form = H->lattice == LBM_LATTICE_D2Q9 && !H->adaptive && H->prec != LBM_PREC_TANGENT;
   // the two collide load schedules differ for 4-byte arithmetic (FP32, FP16S)
   const bool sched_form = H->prec == LBM_PREC_FP32 || H->prec == LBM_PREC_FP16S;
+  // the tall tile shape exists for the two-iteration kernel in 4-byte arithmetic
+  const bool tall_form = pair_form && sched_form;
   const int glen = H->glen;
   H->drop_graph();
   int rc = lbm_ehd_checkpoint(H, dev_scratch);
@@ -1202,11 +1229,12 @@ int lbm_ehd_tune(lbm_ehd_t H, int32_t steps, void *dev_scratch, double ms_per_st
     return H->fail(LBM_EHD_EHIP, "tune: hipEventCreate failed");
   }
   int pick = -1;
-  for (int c = 0; c < 8 && rc == LBM_EHD_OK; ++c) {
+  for (int c = 0; c < 16 && rc == LBM_EHD_OK; ++c) {
     ms_per_step[c] = -1.0;
     // bits that change nothing on this handle: same launches as without them
     if ((c & LBM_TUNE_SINGLE_POTENTIAL) && !pair_form) continue;
     if ((c & LBM_TUNE_COLLIDE_PER_FAMILY) && !sched_form) continue;
+    if ((c & LBM_TUNE_TALL_TILES) && (!tall_form || (c & LBM_TUNE_SINGLE_POTENTIAL))) continue;
     H->tuning = c;
     H->apply_order();
     if ((rc = lbm_ehd_restore(H, dev_scratch)) || (rc = lbm_ehd_step(H, 2))) break;

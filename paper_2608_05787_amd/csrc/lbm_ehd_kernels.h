@@ -577,16 +577,24 @@ __global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, 
 //   tiles: (instance, x0, y0, -) per block; hpar: input parity relative to
 //   ctl->hcur; write_psi: store the potential of the second iteration's input
 //   (the last iteration of the step).
-constexpr int P2NT = 1024;  // threads per block of the two-iteration kernel (one node each)
+constexpr int P2NT = 1024;  // threads per block of the two-iteration kernel
 constexpr int P2EW = 64, P2ER = 16, P2W = P2EW - 4, P2H = P2ER - 4, P2RPT = P2ER / (P2NT / 64);
+// Tile shapes of the two-iteration kernel: RPT extended rows per thread, so
+// a 64 x 16 RPT extended tile with a (16 RPT - 4)-row interior (RPT = 1:
+// 60 x 12, 70% of the loaded nodes written; RPT = 2: 60 x 28, 82%, twice
+// the LDS and half the blocks).  The launch configuration picks one.
+template <int RPT> struct P2Shape {
+  static constexpr int ER = 16 * RPT, H = ER - 4;
+};
 
 //   rec_in, rec_mid: when set, receive the input level and the level after
 //   the first sub-iteration (recording runs).
-template <typename T>
+template <typename T, int RPT = 1>
 __global__ __launch_bounds__(P2NT) void k_poisson2(const Inst *__restrict__ insts, const int4 *__restrict__ tiles,
                                                  int hpar, int write_psi, T *rec_in = nullptr,
                                                  T *rec_mid = nullptr) {
-  __shared__ T buf[Q * P2EW * P2ER];
+  constexpr int ER = P2Shape<RPT>::ER, H2 = P2Shape<RPT>::H;
+  __shared__ T buf[Q * P2EW * ER];
   const int4 t = tiles[blockIdx.x];
   const Inst &I = insts[t.x];
   const Phys<T> &P = phys<T>(I);
@@ -596,11 +604,11 @@ __global__ __launch_bounds__(P2NT) void k_poisson2(const Inst *__restrict__ inst
   auto dst = gbl((T *)I.h[hc ^ 1]);
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int gx = wrapx(((t.y - 2 + tx) % nx + nx) % nx, nx);
-  T h[P2RPT][Q], eh[P2RPT], qq[P2RPT];
-  int gy[P2RPT];
-  bool inside[P2RPT];
+  T h[RPT][Q], eh[RPT], qq[RPT];
+  int gy[RPT];
+  bool inside[RPT];
 #pragma unroll
-  for (int k = 0; k < P2RPT; ++k) {
+  for (int k = 0; k < RPT; ++k) {
     const int r = ty + (P2NT / 64) * k;  // extended row of this thread's k-th node
     int y = t.z - 2 + r;
     bool in = true;
@@ -624,14 +632,14 @@ __global__ __launch_bounds__(P2NT) void k_poisson2(const Inst *__restrict__ inst
   // interior node of this tile (the nodes the launch writes)
   auto interior = [&](int k, int &n) {
     const int r = ty + (P2NT / 64) * k;
-    if (r < 2 || r >= 2 + P2H || tx < 2 || tx >= 2 + P2W || !inside[k]) return false;
+    if (r < 2 || r >= 2 + H2 || tx < 2 || tx >= 2 + P2W || !inside[k]) return false;
     if (t.y + tx - 2 >= nx || t.z + r - 2 >= ny) return false;
     n = gy[k] * nx + gx;
     return true;
   };
   if (rec_in)
 #pragma unroll
-    for (int k = 0; k < P2RPT; ++k) {
+    for (int k = 0; k < RPT; ++k) {
       int n;
       if (interior(k, n))
 #pragma unroll
@@ -640,37 +648,37 @@ __global__ __launch_bounds__(P2NT) void k_poisson2(const Inst *__restrict__ inst
   for (int it = 0; it < 2; ++it) {
     // collide every node this iteration can still use, post values to LDS
 #pragma unroll
-    for (int k = 0; k < P2RPT; ++k) {
+    for (int k = 0; k < RPT; ++k) {
       const int r = ty + (P2NT / 64) * k, e = r * P2EW + tx;
       T v[Q];
       const T pot = poisson_collide<D2Q9>(h[k], eh[k], qq[k], P, v);
-      if (it == 1 && write_psi && inside[k] && r >= 2 && r < 2 + P2H && tx >= 2 && tx < 2 + P2W) {
+      if (it == 1 && write_psi && inside[k] && r >= 2 && r < 2 + H2 && tx >= 2 && tx < 2 + P2W) {
         const int ux = t.y + tx - 2, uy = t.z + r - 2;
         if (ux < nx && uy < ny) (gbl((T *)I.psi))[gy[k] * nx + gx] = pot;
       }
 #pragma unroll
-      for (int j = 0; j < Q; ++j) buf[j * (P2EW * P2ER) + e] = v[j];
+      for (int j = 0; j < Q; ++j) buf[j * (P2EW * ER) + e] = v[j];
     }
     __syncthreads();
     // pull streaming inside the tile; sources beyond an electrode reflect
     const int lo = it + 1;  // ring still valid after this streaming
 #pragma unroll
-    for (int k = 0; k < P2RPT; ++k) {
+    for (int k = 0; k < RPT; ++k) {
       const int r = ty + (P2NT / 64) * k, e = r * P2EW + tx;
-      if (r < lo || r >= P2ER - lo || tx < lo || tx >= P2EW - lo || !inside[k]) continue;
+      if (r < lo || r >= ER - lo || tx < lo || tx >= P2EW - lo || !inside[k]) continue;
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
         const int sy = gy[k] - cy(j);
         if (walls && (sy < 0 || sy >= ny))
-          h[k][j] = -buf[opp(j) * (P2EW * P2ER) + e] + T(2) * wgt<T>(j) * (sy < 0 ? P.wall_phi[0] : P.wall_phi[1]);
+          h[k][j] = -buf[opp(j) * (P2EW * ER) + e] + T(2) * wgt<T>(j) * (sy < 0 ? P.wall_phi[0] : P.wall_phi[1]);
         else
-          h[k][j] = buf[j * (P2EW * P2ER) + e - cy(j) * P2EW - cx(j)];
+          h[k][j] = buf[j * (P2EW * ER) + e - cy(j) * P2EW - cx(j)];
       }
     }
     __syncthreads();
     if (it == 0 && rec_mid)
 #pragma unroll
-      for (int k = 0; k < P2RPT; ++k) {
+      for (int k = 0; k < RPT; ++k) {
         int n;
         if (interior(k, n))
 #pragma unroll
@@ -679,9 +687,9 @@ __global__ __launch_bounds__(P2NT) void k_poisson2(const Inst *__restrict__ inst
   }
   // interior pre-collision values of the next level
 #pragma unroll
-  for (int k = 0; k < P2RPT; ++k) {
+  for (int k = 0; k < RPT; ++k) {
     const int r = ty + (P2NT / 64) * k;
-    if (r < 2 || r >= 2 + P2H || tx < 2 || tx >= 2 + P2W || !inside[k]) continue;
+    if (r < 2 || r >= 2 + H2 || tx < 2 || tx >= 2 + P2W || !inside[k]) continue;
     const int ux = t.y + tx - 2, uy = t.z + r - 2;
     if (ux >= nx || uy >= ny) continue;
     const int n = gy[k] * nx + gx;

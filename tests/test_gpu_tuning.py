@@ -1,6 +1,6 @@
 """The launch-configuration autotuner.  Block order and collide load
-schedule give bitwise the same state; the two potential kernel forms (LDS
-two-iteration tiles, single launches) agree to rounding.  lbm_ehd_tune leaves
+schedule give bitwise the same state; the potential kernel forms (LDS
+two-iteration tiles of either shape, single launches) agree to rounding.  lbm_ehd_tune leaves
 the handle's state and step count as they were, keeps a graph working, and
 the Python cache applies a stored choice without timing."""
 import json
@@ -30,20 +30,28 @@ def test_every_configuration_gives_the_same_state(prec, sub):
     print("case tuning configs", prec, sub, flush=True)
     cfgs, inits = batch(sub)
     ref = {}
-    for config in range(8):
+    for config in range(16):
         sim = binding.Sim(cfgs, inits, precision=prec)
         sim.set_tuning(config)
         assert sim.get_tuning() == config
         sim.step(7)
         got = pops(sim, 3)
-        form = config & binding.TUNE_SINGLE_POTENTIAL
+        # the potential form: single launches, or pairs on one of the two tile
+        # shapes (the tall shape exists in 4-byte arithmetic)
+        if config & binding.TUNE_SINGLE_POTENTIAL:
+            form = "single"
+        elif config & binding.TUNE_TALL_TILES and prec != "fp64":
+            form = "tall"
+        else:
+            form = "pairs"
         if form not in ref:
             ref[form] = got
         else:
             assert all(torch.equal(a, b) for a, b in zip(got, ref[form])), config
-    for a, b in zip(ref[0], ref[binding.TUNE_SINGLE_POTENTIAL]):
-        err = float(torch.linalg.norm(a - b)) / max(float(torch.linalg.norm(b)), 1e-300)
-        assert err <= ROUNDING[prec], err
+    for form in ref:
+        for a, b in zip(ref[form], ref["pairs"]):
+            err = float(torch.linalg.norm(a - b)) / max(float(torch.linalg.norm(b)), 1e-300)
+            assert err <= ROUNDING[prec], (form, err)
 
 
 def test_d3q15_orders_give_the_same_state():
@@ -72,8 +80,10 @@ def test_tune_restores_state_and_keeps_graph():
     a.graph(4)
     before = pops(a, 3)
     res = a.autotune(steps=6)
-    assert not res["cached"] and res["config"] in range(8)
-    assert all(v > 0 for v in res["ms_per_step"]), res
+    assert not res["cached"] and res["config"] in range(16)
+    # every configuration is timed except tall tiles with single launches
+    timed = [c for c in range(16) if res["ms_per_step"][c] > 0]
+    assert timed == [c for c in range(16) if not (c & 8 and c & 2)], res
     assert a.get_tuning() == res["config"]
     assert all(torch.equal(x, y) for x, y in zip(pops(a, 3), before))
     b.set_tuning(res["config"])  # the potential forms agree to rounding only
@@ -94,10 +104,10 @@ def test_autotune_cache(tmp_path):
     s2 = binding.Sim(p, init, precision="fp32")
     r2 = s2.autotune(steps=4, cache=cache)
     assert r2["cached"] and r2["config"] == r1["config"] and s2.get_tuning() == r1["config"]
-    # adaptive sub-iterations: the single-launch bit is not timed; FP64: the
-    # load-schedule bit is not either
+    # adaptive sub-iterations: the single-launch and tile-shape bits are not
+    # timed; FP64: the load-schedule and tile-shape bits are not either
     q = dict(p, sub_min=1, sub_max=6, sub_tol=1e-6)
     r3 = binding.Sim(q, init, precision="fp32").autotune(steps=4)
-    assert [c for c in range(8) if r3["ms_per_step"][c] > 0] == [0, 1, 4, 5] and r3["config"] in (0, 1, 4, 5)
+    assert [c for c in range(16) if r3["ms_per_step"][c] > 0] == [0, 1, 4, 5] and r3["config"] in (0, 1, 4, 5)
     r4 = binding.Sim(p, init, precision="fp64").autotune(steps=4)
-    assert [c for c in range(8) if r4["ms_per_step"][c] > 0] == [0, 1, 2, 3]
+    assert [c for c in range(16) if r4["ms_per_step"][c] > 0] == [0, 1, 2, 3]
