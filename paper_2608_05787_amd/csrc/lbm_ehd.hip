@@ -363,13 +363,14 @@ int enqueue_fixed_potential(lbm_ehd_s *H, int K) {
       }
       for (; k + 1 <= K; k += 2, ++L) {
         hipEvent_t e = H->prof_start(6);
+        const int last = k + 1 == K ? 1 : 0;
         if constexpr (sizeof(T) == 4) {
           if (H->tall())
-            k_poisson2<T, 2><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, k + 1 == K ? 1 : 0);
+            k_poisson2<T, 2><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, last);
           else
-            k_poisson2<T, 1><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, k + 1 == K ? 1 : 0);
+            k_poisson2<T, 1><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, last);
         } else {
-          k_poisson2<T, 1><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, k + 1 == K ? 1 : 0);
+          k_poisson2<T, 1><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, last);
         }
         H->prof_stop(e);
       }
@@ -1400,7 +1401,7 @@ int lbm_ehd_adjoint(lbm_ehd_t H, int64_t n_steps, int32_t ckpt_every, const void
     ini.u0 = H->init_u[0].empty() ? nullptr : H->init_u[0].data();
     ini.q0 = H->init_q[0].empty() ? nullptr : H->init_q[0].data();
     ini.psi0 = H->init_psi[0].empty() ? nullptr : H->init_psi[0].data();
-  ini.ions0 = H->init_ions[0].empty() ? nullptr : H->init_ions[0].data();
+    ini.ions0 = H->init_ions[0].empty() ? nullptr : H->init_ions[0].data();
     rc = create_impl(&H->params[0], 1, &ini, work + L.shell, (void *)H->stream, &W, true);
     if (!rc) {
       rc = record_run(W, work, L, n_steps, ckpt_every);

@@ -150,6 +150,13 @@ __device__ __forceinline__ __half ld_half(gcwords p, size_t i) { return __ushort
 __device__ __forceinline__ __half ld_half(gwords p, size_t i) { return __ushort_as_half(p[i]); }
 __device__ __forceinline__ void st_half(__half *p, size_t i, __half v) { p[i] = v; }
 __device__ __forceinline__ void st_half(gwords p, size_t i, __half v) { p[i] = __half_as_ushort(v); }
+// Read-only view in the constant address space, for descriptors no thread
+// writes while the kernel runs (instance and tile tables, the control word
+// outside the kernels that update it): uniform reads through it are scalar
+// loads, off the vector-memory queue the population loads wait on.
+template <typename T> using cptr = const T __attribute__((address_space(4))) *;
+template <typename T> __device__ __forceinline__ cptr<T> cst(const T *p) { return (cptr<T>)p; }
+
 template <typename T> __device__ __forceinline__ const Phys<T> &phys(const Inst &I);
 template <> __device__ __forceinline__ const Phys<float> &phys<float>(const Inst &I) { return I.pf; }
 template <> __device__ __forceinline__ const Phys<double> &phys<double>(const Inst &I) { return I.pd; }
@@ -233,9 +240,11 @@ __device__ __forceinline__ Node locate(const Inst *__restrict__ insts, const int
 
 __device__ __forceinline__ int wrapx(int x, int nx) { return x < 0 ? x + nx : (x >= nx ? x - nx : x); }
 // finite-difference neighbour row: wrap (periodic) or mirror ghost (walls)
+// (both forms computed and selected: no branch between the stencil loads)
 __device__ __forceinline__ int fdrow(int y, int ny, int walls) {
-  if (walls) return y < 0 ? 0 : (y >= ny ? ny - 1 : y);
-  return y < 0 ? y + ny : (y >= ny ? y - ny : y);
+  const int mirror = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+  const int wrap = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+  return walls ? mirror : wrap;
 }
 
 // Node index of the Eq. (33) stencil point x + c_j (periodic wrap in x and
@@ -440,6 +449,13 @@ __global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, cons
   const Phys<T> &P = phys<T>(I);
   const int N = I.N, n = nd.n;
   auto phi = gbl((const T *)I.phi);
+  // the node's own loads first: issued with the stencil's, one memory
+  // round trip for the whole kernel
+  auto E = gbl((const T *)I.E);
+  T e[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) e[d] = E[(size_t)d * N + n];
+  const T lsum = (gbl((const T *)I.lsum))[n];
   T ev[Q], sv[Q];
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
@@ -451,10 +467,6 @@ __global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, cons
   T ge[D], gs[D], dummy;
   fdq<L>(ev, ge, dummy);
   fdq<L>(sv, gs, dummy);
-  auto E = gbl((const T *)I.E);
-  T e[D];
-#pragma unroll
-  for (int d = 0; d < D; ++d) e[d] = E[(size_t)d * N + n];
   const T se = sv[0] / ev[0];
   T gee = ge[0] * e[0], gse = gs[0] * e[0];
 #pragma unroll
@@ -463,7 +475,7 @@ __global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, cons
     gse += gs[d] * e[d];
   }
   const T Rp = se * gee - gse;
-  const T q = ((gbl((const T *)I.lsum))[n] + T(0.5) * Rp) / (T(1) + T(0.5) * se);
+  const T q = (lsum + T(0.5) * Rp) / (T(1) + T(0.5) * se);
   (gbl((T *)I.q))[n] = q;
   (gbl((T *)I.R))[n] = -se * q + Rp;
   (gbl((T *)I.eps))[n] = ev[0];
@@ -479,8 +491,8 @@ __global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, cons
 // Potential LB at one node (Eqs. 43-45): potential and gradient from the
 // pre-collision h, then the collision with the eps_hat first-moment source
 // and the charge source.  Returns the potential of the input h.
-template <class L, typename T>
-__device__ __forceinline__ T poisson_collide(const T (&h)[L::Q], T epshat, T q, const Phys<T> &P, T (&v)[L::Q]) {
+template <class L, typename T, class PP>
+__device__ __forceinline__ T poisson_collide(const T (&h)[L::Q], T epshat, T q, const PP &P, T (&v)[L::Q]) {
   constexpr int Q = L::Q, D = L::D;
   T s1 = 0, m[D];
 #pragma unroll
@@ -525,7 +537,7 @@ __global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, 
   int lblk;
   const Node nd = locate<L>(insts, b2i, Ip, lblk);
   const Inst &I = *Ip;
-  const Ctl *ctl = I.ctl;
+  const cptr<Ctl> ctl = cst(I.ctl);  // written only by the control pass between launches
   if (adaptive && ctl->done) return;  // uniform over the instance
   const Phys<T> &P = phys<T>(I);
   const int hc = adaptive ? ctl->hcur : (ctl->hcur ^ hpar);
@@ -536,20 +548,22 @@ __global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, 
     const int N = I.N, n = nd.n;
     auto src = gbl((const T *)I.h[hc]);
     auto dst = gbl((T *)I.h[hc ^ 1]);
+    // every load before the first store (a later load would wait for it)
     T h[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) h[j] = src[(size_t)j * N + n];
+    const T epshat = (gbl((const T *)I.eps))[n] - P.eps_ref;
+    const T q = (gbl((const T *)I.q))[n];
+    auto psi = gbl((T *)I.psi);
+    const T psi_prev = resid ? psi[n] : T(0);
     if (rec_in)
 #pragma unroll
       for (int j = 0; j < Q; ++j) rec_in[(size_t)j * N + n] = h[j];
-    const T epshat = (gbl((const T *)I.eps))[n] - P.eps_ref;
-    const T q = (gbl((const T *)I.q))[n];
     T v[Q];
     const T pot = poisson_collide<L>(h, epshat, q, P, v);
     if (write_psi) {
-      auto psi = gbl((T *)I.psi);
       if (resid) {
-        const double d = (double)pot - (double)psi[n];
+        const double d = (double)pot - (double)psi_prev;
         red[0] = d * d;
         red[1] = (double)pot * (double)pot;
       }
@@ -587,63 +601,111 @@ template <int RPT> struct P2Shape {
   static constexpr int ER = 16 * RPT, H = ER - 4;
 };
 
-//   rec_in, rec_mid: when set, receive the input level and the level after
-//   the first sub-iteration (recording runs).
-template <typename T, int RPT = 1>
-__global__ __launch_bounds__(P2NT) void k_poisson2(const Inst *__restrict__ insts, const int4 *__restrict__ tiles,
-                                                 int hpar, int write_psi, T *rec_in = nullptr,
-                                                 T *rec_mid = nullptr) {
-  constexpr int ER = P2Shape<RPT>::ER, H2 = P2Shape<RPT>::H;
-  __shared__ T buf[Q * P2EW * ER];
-  const int4 t = tiles[blockIdx.x];
-  const Inst &I = insts[t.x];
-  const Phys<T> &P = phys<T>(I);
-  const int nx = I.nx, ny = I.ny, N = I.N, walls = I.bc_y;
-  const int hc = I.ctl->hcur ^ hpar;
-  auto src = gbl((const T *)I.h[hc]);
-  auto dst = gbl((T *)I.h[hc ^ 1]);
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int gx = wrapx(((t.y - 2 + tx) % nx + nx) % nx, nx);
+// Per-tile values of the two-iteration kernel, read with scalar loads
+// before the tile's population loads are issued.
+template <typename T> struct P2Meta {
+  const T *src, *eps, *q;
+  T *dst, *psi;
+  int nx, ny, N, walls;
+  T tau_h, eps_ref, wall_phi[2];
+};
+
+template <typename T>
+__device__ __forceinline__ P2Meta<T> p2_meta(const Inst *insts, const int4 *tiles, int ti, int hpar, int4 &t) {
+  const cptr<int> tp = cst((const int *)tiles) + 4 * (size_t)ti;
+  t = make_int4(tp[0], tp[1], tp[2], 0);
+  const cptr<Inst> I = cst(insts) + t.x;
+  const int hc = cst(I->ctl)->hcur ^ hpar;
+  P2Meta<T> m;
+  m.src = (const T *)I->h[hc];
+  m.dst = (T *)I->h[hc ^ 1];
+  m.eps = (const T *)I->eps;
+  m.q = (const T *)I->q;
+  m.psi = (T *)I->psi;
+  m.nx = I->nx;
+  m.ny = I->ny;
+  m.N = I->N;
+  m.walls = I->bc_y;
+  if constexpr (sizeof(T) == 4) {
+    m.tau_h = I->pf.tau_h;
+    m.eps_ref = I->pf.eps_ref;
+    m.wall_phi[0] = I->pf.wall_phi[0];
+    m.wall_phi[1] = I->pf.wall_phi[1];
+  } else {
+    m.tau_h = I->pd.tau_h;
+    m.eps_ref = I->pd.eps_ref;
+    m.wall_phi[0] = I->pd.wall_phi[0];
+    m.wall_phi[1] = I->pd.wall_phi[1];
+  }
+  return m;
+}
+
+// Registers of one tile of the two-iteration kernel: this thread's RPT
+// extended-tile nodes (h, eps, q; zeros beyond an electrode wall).  eps_hat
+// = eps - eps_ref is formed after the loads, not between them.
+template <typename T, int RPT> struct P2Regs {
   T h[RPT][Q], eh[RPT], qq[RPT];
   int gy[RPT];
   bool inside[RPT];
+};
+
+template <typename T, int RPT>
+__device__ __forceinline__ void p2_load(const P2Meta<T> &m, const int4 t, P2Regs<T, RPT> &s) {
+  const int nx = m.nx, ny = m.ny, N = m.N;
+  auto src = gbl(m.src);
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int gx = wrapx(((t.y - 2 + tx) % nx + nx) % nx, nx);
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     const int r = ty + (P2NT / 64) * k;  // extended row of this thread's k-th node
     int y = t.z - 2 + r;
     bool in = true;
-    if (walls) in = (y >= 0 && y < ny);
+    if (m.walls) in = (y >= 0 && y < ny);
     else y = ((y % ny) + ny) % ny;
-    gy[k] = y;
-    inside[k] = in;
+    s.gy[k] = y;
+    s.inside[k] = in;
     if (in) {
       const int n = y * nx + gx;
 #pragma unroll
-      for (int j = 0; j < Q; ++j) h[k][j] = src[(size_t)j * N + n];
-      eh[k] = (gbl((const T *)I.eps))[n] - P.eps_ref;
-      qq[k] = (gbl((const T *)I.q))[n];
+      for (int j = 0; j < Q; ++j) s.h[k][j] = src[(size_t)j * N + n];
+      s.eh[k] = (gbl(m.eps))[n];
+      s.qq[k] = (gbl(m.q))[n];
     } else {
 #pragma unroll
-      for (int j = 0; j < Q; ++j) h[k][j] = T(0);
-      eh[k] = T(0);
-      qq[k] = T(0);
+      for (int j = 0; j < Q; ++j) s.h[k][j] = T(0);
+      s.eh[k] = T(0);
+      s.qq[k] = T(0);
     }
   }
+}
+
+// The two sub-iterations of one loaded tile and the store of its interior.
+template <typename T, int RPT>
+__device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int write_psi, T *rec_in, T *rec_mid,
+                                       P2Regs<T, RPT> &s, T *buf) {
+  constexpr int ER = P2Shape<RPT>::ER, H2 = P2Shape<RPT>::H;
+  const int nx = m.nx, ny = m.ny, N = m.N, walls = m.walls;
+  auto dst = gbl(m.dst);
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int gx = wrapx(((t.y - 2 + tx) % nx + nx) % nx, nx);
   // interior node of this tile (the nodes the launch writes)
   auto interior = [&](int k, int &n) {
     const int r = ty + (P2NT / 64) * k;
-    if (r < 2 || r >= 2 + H2 || tx < 2 || tx >= 2 + P2W || !inside[k]) return false;
+    if (r < 2 || r >= 2 + H2 || tx < 2 || tx >= 2 + P2W || !s.inside[k]) return false;
     if (t.y + tx - 2 >= nx || t.z + r - 2 >= ny) return false;
-    n = gy[k] * nx + gx;
+    n = s.gy[k] * nx + gx;
     return true;
   };
+#pragma unroll
+  for (int k = 0; k < RPT; ++k)
+    if (s.inside[k]) s.eh[k] -= m.eps_ref;
   if (rec_in)
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       int n;
       if (interior(k, n))
 #pragma unroll
-        for (int j = 0; j < Q; ++j) rec_in[(size_t)j * N + n] = h[k][j];
+        for (int j = 0; j < Q; ++j) rec_in[(size_t)j * N + n] = s.h[k][j];
     }
   for (int it = 0; it < 2; ++it) {
     // collide every node this iteration can still use, post values to LDS
@@ -651,11 +713,9 @@ __global__ __launch_bounds__(P2NT) void k_poisson2(const Inst *__restrict__ inst
     for (int k = 0; k < RPT; ++k) {
       const int r = ty + (P2NT / 64) * k, e = r * P2EW + tx;
       T v[Q];
-      const T pot = poisson_collide<D2Q9>(h[k], eh[k], qq[k], P, v);
-      if (it == 1 && write_psi && inside[k] && r >= 2 && r < 2 + H2 && tx >= 2 && tx < 2 + P2W) {
-        const int ux = t.y + tx - 2, uy = t.z + r - 2;
-        if (ux < nx && uy < ny) (gbl((T *)I.psi))[gy[k] * nx + gx] = pot;
-      }
+      const T pot = poisson_collide<D2Q9>(s.h[k], s.eh[k], s.qq[k], m, v);
+      int n;
+      if (it == 1 && write_psi && interior(k, n)) (gbl(m.psi))[n] = pot;
 #pragma unroll
       for (int j = 0; j < Q; ++j) buf[j * (P2EW * ER) + e] = v[j];
     }
@@ -665,14 +725,14 @@ __global__ __launch_bounds__(P2NT) void k_poisson2(const Inst *__restrict__ inst
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int r = ty + (P2NT / 64) * k, e = r * P2EW + tx;
-      if (r < lo || r >= ER - lo || tx < lo || tx >= P2EW - lo || !inside[k]) continue;
+      if (r < lo || r >= ER - lo || tx < lo || tx >= P2EW - lo || !s.inside[k]) continue;
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
-        const int sy = gy[k] - cy(j);
+        const int sy = s.gy[k] - cy(j);
         if (walls && (sy < 0 || sy >= ny))
-          h[k][j] = -buf[opp(j) * (P2EW * ER) + e] + T(2) * wgt<T>(j) * (sy < 0 ? P.wall_phi[0] : P.wall_phi[1]);
+          s.h[k][j] = -buf[opp(j) * (P2EW * ER) + e] + T(2) * wgt<T>(j) * (sy < 0 ? m.wall_phi[0] : m.wall_phi[1]);
         else
-          h[k][j] = buf[j * (P2EW * ER) + e - cy(j) * P2EW - cx(j)];
+          s.h[k][j] = buf[j * (P2EW * ER) + e - cy(j) * P2EW - cx(j)];
       }
     }
     __syncthreads();
@@ -682,20 +742,33 @@ __global__ __launch_bounds__(P2NT) void k_poisson2(const Inst *__restrict__ inst
         int n;
         if (interior(k, n))
 #pragma unroll
-          for (int j = 0; j < Q; ++j) rec_mid[(size_t)j * N + n] = h[k][j];
+          for (int j = 0; j < Q; ++j) rec_mid[(size_t)j * N + n] = s.h[k][j];
       }
   }
   // interior pre-collision values of the next level
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
-    const int r = ty + (P2NT / 64) * k;
-    if (r < 2 || r >= 2 + H2 || tx < 2 || tx >= 2 + P2W || !inside[k]) continue;
-    const int ux = t.y + tx - 2, uy = t.z + r - 2;
-    if (ux >= nx || uy >= ny) continue;
-    const int n = gy[k] * nx + gx;
+    int n;
+    if (interior(k, n))
 #pragma unroll
-    for (int j = 0; j < Q; ++j) dst[(size_t)j * N + n] = h[k][j];
+      for (int j = 0; j < Q; ++j) dst[(size_t)j * N + n] = s.h[k][j];
   }
+}
+
+//   tiles: (instance, x0, y0, -) per block.
+//   rec_in, rec_mid: when set, receive the input level and the level after
+//   the first sub-iteration (recording runs).
+template <typename T, int RPT = 1>
+__global__ __launch_bounds__(P2NT) void k_poisson2(const Inst *__restrict__ insts, const int4 *__restrict__ tiles,
+                                                 int hpar, int write_psi, T *rec_in = nullptr,
+                                                 T *rec_mid = nullptr) {
+  constexpr int ER = P2Shape<RPT>::ER;
+  __shared__ T buf[Q * P2EW * ER];
+  int4 t;
+  const P2Meta<T> m = p2_meta<T>(insts, tiles, blockIdx.x, hpar, t);
+  P2Regs<T, RPT> s;
+  p2_load<T, RPT>(m, t, s);
+  p2_run<T, RPT>(m, t, write_psi, rec_in, rec_mid, s, buf);
 }
 
 // Adaptive potential loop control, one block per instance, after iteration
@@ -733,7 +806,7 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
   int lblk;
   const Node nd = locate<L>(insts, b2i, Ip, lblk);
   const Inst &I = *Ip;
-  const Ctl *ctl = I.ctl;
+  const cptr<Ctl> ctl = cst(I.ctl);  // not written during this kernel
   const Phys<T> &P = phys<T>(I);
   double red[2] = {0.0, 0.0};
   if (nd.valid) {
