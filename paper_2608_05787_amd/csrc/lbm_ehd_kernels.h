@@ -806,7 +806,9 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
   int lblk;
   const Node nd = locate<L>(insts, b2i, Ip, lblk);
   const Inst &I = *Ip;
-  const cptr<Ctl> ctl = cst(I.ctl);  // not written during this kernel
+  // (the control word through a plain pointer: a scalar read here staggers
+  // less and measured slower)
+  const Ctl *ctl = I.ctl;
   const Phys<T> &P = phys<T>(I);
   double red[2] = {0.0, 0.0};
   if (nd.valid) {
