@@ -456,13 +456,18 @@ __global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, cons
 #pragma unroll
   for (int d = 0; d < D; ++d) e[d] = E[(size_t)d * N + n];
   const T lsum = (gbl((const T *)I.lsum))[n];
-  T ev[Q], sv[Q];
+  T pv[3][Q];
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
     const int m = nbr<L>(I, nd, j);
-    const T p1 = phi[m], p2 = phi[(size_t)N + m], p3 = phi[(size_t)2 * N + m];
-    ev[j] = P.eps[0] * herm(p1) + P.eps[1] * herm(p2) + P.eps[2] * herm(p3);
-    sv[j] = P.sig[0] * p1 + P.sig[1] * p2 + P.sig[2] * p3;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) pv[i][j] = phi[(size_t)i * N + m];
+  }
+  T ev[Q], sv[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    ev[j] = P.eps[0] * herm(pv[0][j]) + P.eps[1] * herm(pv[1][j]) + P.eps[2] * herm(pv[2][j]);
+    sv[j] = P.sig[0] * pv[0][j] + P.sig[1] * pv[1][j] + P.sig[2] * pv[2][j];
   }
   T ge[D], gs[D], dummy;
   fdq<L>(ev, ge, dummy);
