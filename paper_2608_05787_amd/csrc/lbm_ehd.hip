@@ -45,11 +45,13 @@ int lat_d(const lbm_ehd_params &p) { return p.lattice == LBM_LATTICE_D3Q15 ? 3 :
 int lat_nz(const lbm_ehd_params &p) { return p.nz > 1 ? p.nz : 1; }
 size_t lat_nodes(const lbm_ehd_params &p) { return (size_t)p.nx * p.ny * lat_nz(p); }
 // Plane stride: the node count rounded up to 64 nodes (planes 256-byte
-// aligned) plus a skew of 37 x 64 nodes.  Without the skew some sizes put
-// the ~36 planes a kernel streams at relative offsets that collide in the
-// HBM address mapping (1020^2: collide 27% and moments 28% slower than at
-// 1024^2 per node; the skew removes it and costs no traffic).
-size_t plane_stride(const lbm_ehd_params &p) { return (lat_nodes(p) + 63) / 64 * 64 + 64 * 37; }
+// aligned) plus a skew of 27 x 64 nodes.  Without a skew some sizes put the
+// ~36 planes a kernel streams at relative offsets that collide in the HBM
+// address mapping (1020^2: collide 27% and moments 28% slower than at
+// 1024^2 per node).  Swept over skews 0 - 151 and six sizes near 1M nodes,
+// 27 is within 1% of the best step time on five and 2.5% off on 1020^2; it
+// costs no traffic.
+size_t plane_stride(const lbm_ehd_params &p) { return (lat_nodes(p) + 63) / 64 * 64 + 64 * 27; }
 
 size_t elem_size(int prec) { return prec == LBM_PREC_TANGENT ? 16 : (prec == LBM_PREC_FP64 ? 8 : 4); }
 size_t pop_size(int prec) {
