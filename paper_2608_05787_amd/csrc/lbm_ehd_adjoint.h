@@ -412,6 +412,16 @@ __global__ __launch_bounds__(NT) void k_adj_mu(const Inst *__restrict__ insts, c
 #pragma unroll
     for (int i = 0; i < 3; ++i) mu_b[i] = ab.muL[(size_t)i * N + n];
     T ex_b = ab.a[cur][(size_t)AO_E * N + n], ey_b = ab.a[cur][(size_t)(AO_E + 1) * N + n];
+    // the accumulators this node adds to, read now (distinct buffers from
+    // every plane the kernel writes first; a read after a store would wait
+    // for it)
+    T *hb = ab.hb[hsel];
+    T *PBn = ab.pb[cur ^ 1];
+    T hb0[Q], pb0[3];
+#pragma unroll
+    for (int j = 1; j < Q; ++j) hb0[j] = hb[(size_t)j * N + n];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) pb0[i] = PBn[(size_t)i * N + n];
     if (with_step) {
       T gr_t = 0;
       for_sources(I, nd.x, nd.y, [&](int j, int s) {
@@ -446,12 +456,10 @@ __global__ __launch_bounds__(NT) void k_adj_mu(const Inst *__restrict__ insts, c
     const T mx = (Ex - P.Eext[0]) * den, my = (Ey - P.Eext[1]) * den;
     const T mx_b = ex_b / den, my_b = ey_b / den;
     ab.eb[n] = -(ex_b * mx + ey_b * my) / (den * den);
-    T *hb = ab.hb[hsel];
 #pragma unroll
-    for (int j = 1; j < Q; ++j) hb[(size_t)j * N + n] += T(cx(j)) * mx_b + T(cy(j)) * my_b;
-    T *PBn = ab.pb[cur ^ 1];
+    for (int j = 1; j < Q; ++j) hb[(size_t)j * N + n] = hb0[j] + (T(cx(j)) * mx_b + T(cy(j)) * my_b);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) PBn[(size_t)i * N + n] += ph_b[i];
+    for (int i = 0; i < 3; ++i) PBn[(size_t)i * N + n] = pb0[i] + ph_b[i];
   }
   add_theta(I, ab.tb, lblk, th);
 }
@@ -562,15 +570,28 @@ __global__ __launch_bounds__(P2NT) void k_adj_poisson2(const Inst *__restrict__ 
   const int n = gy * nx + gx;
   const int e = r * P2EW + tx;
   const T *Hs = ab.hb[src];
-#pragma unroll
-  for (int j = 0; j < Q; ++j) buf[j * (P2EW * P2ER) + e] = inside ? Hs[(size_t)j * N + n] : T(0);
-  __syncthreads();
   const bool ring1 = inside && r >= 1 && r < P2ER - 1 && tx >= 1 && tx < P2EW - 1;
   const bool interior = inside && r >= 2 && r < 2 + P2H && tx >= 2 && tx < 2 + P2W && t.y + tx - 2 < nx &&
                         t.z + r - 2 < ny;
+  // the adjoint level, and the first iteration's forward level and eps
+  // where they are used, in one burst of loads ahead of the first barrier
+  T hv[Q], h1v[Q], epsv = T(0);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) hv[j] = h1v[j] = T(0);
+  if (inside)
+#pragma unroll
+    for (int j = 0; j < Q; ++j) hv[j] = Hs[(size_t)j * N + n];
+  if (ring1) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) h1v[j] = h1[(size_t)j * N + n];
+    epsv = eps[n];
+  }
+#pragma unroll
+  for (int j = 0; j < Q; ++j) buf[j * (P2EW * P2ER) + e] = hv[j];
+  __syncthreads();
   double th = 0.0;
   T eh_b = 0, q_b = 0;
-  const T eh = ring1 ? eps[n] - P.eps_ref : T(0);
+  const T eh = ring1 ? epsv - P.eps_ref : T(0);
   // pull of the adjoint through the push of node (r, tx); wall slots at the node itself
   auto pull = [&](T (&vb)[Q]) {
 #pragma unroll
@@ -587,12 +608,10 @@ __global__ __launch_bounds__(P2NT) void k_adj_poisson2(const Inst *__restrict__ 
   };
   T hb[Q];
   if (ring1) {
-    T vb[Q], h[Q];
+    T vb[Q];
     pull(vb);
-#pragma unroll
-    for (int j = 0; j < Q; ++j) h[j] = h1[(size_t)j * N + n];
     T eb1 = 0, qb1 = 0;
-    adj_poisson_local(vb, h, eh, P, hb, eb1, qb1);
+    adj_poisson_local(vb, h1v, eh, P, hb, eb1, qb1);
     if (interior) {
       eh_b += eb1;
       q_b += qb1;
@@ -642,6 +661,11 @@ __global__ __launch_bounds__(NT) void k_adj_pre(const Inst *__restrict__ insts, 
   if (nd.valid) {
     const Phys<T> &P = phys<T>(I);
     const int N = I.N, nx = I.nx, n = nd.n;
+    // the accumulator this node adds to, read before any store
+    T *PBn = ab.pb[cur ^ 1];
+    T pb0[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) pb0[i] = PBn[(size_t)i * N + n];
     T ph_b[3] = {T(0), T(0), T(0)};
     // transpose of the Laplacian in mu: 6 sum_j w_j v(m + c_j) - 6 v(m)
     for_sources(I, nd.x, nd.y, [&](int j, int s) {
@@ -692,9 +716,8 @@ __global__ __launch_bounds__(NT) void k_adj_pre(const Inst *__restrict__ insts, 
       th[i] += (double)(ev_b * herm(ph[i]));
       th[3 + i] += (double)(sv_b * ph[i]);
     }
-    T *PBn = ab.pb[cur ^ 1];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) PBn[(size_t)i * N + n] += ph_b[i];
+    for (int i = 0; i < 3; ++i) PBn[(size_t)i * N + n] = pb0[i] + ph_b[i];
     PBn[(size_t)3 * N + n] = Ls_b;
     T *An = ab.a[cur ^ 1];
     An[(size_t)AO_E * N + n] = ex_b;
@@ -720,17 +743,23 @@ __global__ __launch_bounds__(NT) void k_adj_phi(const Inst *__restrict__ insts, 
   if (nd.valid) {
     const Phys<T> &P = phys<T>(I);
     const int N = I.N, n = nd.n;
+    T *PBn = ab.pb[cur ^ 1];
+    T pb0[3], phv[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      pb0[i] = PBn[(size_t)i * N + n];
+      phv[i] = rc.phi[(size_t)i * N + n];
+    }
     T te = 0, ts = 0;
     for_sources(I, nd.x, nd.y, [&](int j, int s) {
       const T w3 = T(3) * wgt<T>(j);
       te += w3 * (T(cx(j)) * ab.ge[s] + T(cy(j)) * ab.ge[(size_t)N + s]);
       ts += w3 * (T(cx(j)) * ab.gs[s] + T(cy(j)) * ab.gs[(size_t)N + s]);
     });
-    T *PBn = ab.pb[cur ^ 1];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const T ph = rc.phi[(size_t)i * N + n];
-      PBn[(size_t)i * N + n] += te * P.eps[i] * T(6) * ph * (T(1) - ph) + ts * P.sig[i];
+      const T ph = phv[i];
+      PBn[(size_t)i * N + n] = pb0[i] + (te * P.eps[i] * T(6) * ph * (T(1) - ph) + ts * P.sig[i]);
       th[i] += (double)(te * herm(ph));
       th[3 + i] += (double)(ts * ph);
     }
