@@ -41,7 +41,7 @@ def bytes_per_node(kernel, prec="fp32", Q=9, D=2):
         "moments": fpops + Q * s + 4 * t,                  # f, l in; phi, l-sum out
         "pre": (3 + 1 + D) * t + 3 * t,                    # phi, l-sum, E in; eps, q, R out
         "poisson": (Q + 1 + 1) * t + Q * t,                # h, eps, q in; h out (one sub-iteration)
-        "poisson2": (Q + 1 + 1) * t + Q * t,               # the same for two sub-iterations per launch
+        "poisson2": (Q + 1 + 1) * t + Q * t,               # the same for two or four sub-iterations per launch
         "mu": (Q + 1 + 1 + 3) * t + (1 + D + 3) * t,        # h, eps, psi, phi in; psi, E, mu out
         # pops in and out; phi, mu, q, R, E, history (phi_i u, q u) in; history out
         "collide": 2 * pops + (3 + 3 + 1 + 1 + D + 4 * D) * t + 4 * D * t,
@@ -86,7 +86,7 @@ def workload(n, sub, init_iters):
     return p, init
 
 
-def run_gpu(p, init, precision, steps, warmup, profile_steps, tune_steps=0):
+def run_gpu(p, init, precision, steps, warmup, profile_steps, tune_steps=0, config=-1):
     """Create, warm up, optionally autotune the launch configuration (bitwise
     the same results), then time `steps` steps with HIP events on the
     handle's stream.  Returns (sim, ms, per-kernel profile, diagnostics,
@@ -100,7 +100,10 @@ def run_gpu(p, init, precision, steps, warmup, profile_steps, tune_steps=0):
     sim.step(warmup)
     torch.cuda.synchronize()
     tune = None
-    if tune_steps > 0:
+    if config >= 0:  # a fixed launch configuration (profiling the tuned one without the tuner's launches)
+        sim.set_tuning(config)
+        tune = {"config": config, "cached": False, "fixed": True}
+    elif tune_steps > 0:
         tune = sim.autotune(steps=tune_steps)
         log("%s autotune: config %d, ms/step per config %s" % (precision, tune["config"],
                                                                ["%.4f" % v for v in tune["ms_per_step"]]))
@@ -323,6 +326,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--tune-steps", type=int, default=20,
                     help="steps timed per launch configuration by the autotuner (0: default configuration)")
+    ap.add_argument("--config", type=int, default=-1,
+                    help="launch configuration of the 1024^2 legs, in place of the autotuner (-1: tune)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -371,7 +376,7 @@ def main():
     p, init = workload(args.n, args.sub, args.init_iters)
     nodes = p["nx"] * p["ny"]
     sim, ms, prof, diag, tune = run_gpu(p, init, "fp32", args.steps, args.warmup, args.profile_steps,
-                                        args.tune_steps)
+                                        args.tune_steps, args.config)
     mlups = nodes * args.steps / (ms * 1e-3) / 1e6
     k_mean = args.sub
 
@@ -396,11 +401,19 @@ def main():
         for k, v in kernels.items():
             if k in BYTES_PER_NODE_FP32:
                 v["gbs"] = round(BYTES_PER_NODE_FP32[k] * nodes / (v["avg_us"] * 1e-6) / 1e9, 1)
-    # potential launches of a step: two-iteration pairs plus one single when
-    # K is odd, or K singles when the tuner chose single launches
-    single = bool(tune and (tune["config"] & 2))
-    n2, n1 = (0, args.sub) if single else (args.sub // 2, args.sub % 2)
-    step_bytes = {prec: sum(bytes_per_node(k, prec) * {"poisson": n1, "poisson2": n2}.get(k, 1)
+    # potential launches of a step: one single launch when K is odd, then
+    # LDS-tiled launches of four sub-iterations (tall tiles, 4-byte
+    # arithmetic) and of two; K singles when the tuner chose single launches
+    cfg = tune["config"] if tune else 0
+
+    def launches(prec):
+        if cfg & 2:
+            return 0, args.sub
+        n1, rest = args.sub % 2, args.sub - args.sub % 2
+        quads = rest // 4 if (cfg & 8) and prec != "fp64" else 0
+        return quads + (rest - 4 * quads) // 2, n1
+
+    step_bytes = {prec: sum(bytes_per_node(k, prec) * dict(zip(("poisson2", "poisson"), launches(prec))).get(k, 1)
                             for k in BYTES_PER_NODE_FP32) for prec in ("fp32", "fp16s", "fp64")}
 
     variants = {"fp32": {"mlups": round(mlups, 1), "ms_per_step": ms / args.steps,
@@ -408,11 +421,12 @@ def main():
     errors = None
     if not args.no_variants:
         del sim
-        _, ms64, _, _, _ = run_gpu(p, init, "fp64", max(args.steps // 2, 1), args.warmup // 2, 0, args.tune_steps)
+        _, ms64, _, _, _ = run_gpu(p, init, "fp64", max(args.steps // 2, 1), args.warmup // 2, 0, args.tune_steps,
+                                   args.config)
         variants["fp64"] = {"mlups": round(nodes * max(args.steps // 2, 1) / (ms64 * 1e-3) / 1e6, 1),
                             "ms_per_step": ms64 / max(args.steps // 2, 1),
                             "bytes_per_node_update": step_bytes["fp64"]}
-        _, ms16, _, _, _ = run_gpu(p, init, "fp16s", args.steps, args.warmup, 0, args.tune_steps)
+        _, ms16, _, _, _ = run_gpu(p, init, "fp16s", args.steps, args.warmup, 0, args.tune_steps, args.config)
         variants["fp16s"] = {"mlups": round(nodes * args.steps / (ms16 * 1e-3) / 1e6, 1),
                              "ms_per_step": ms16 / args.steps,
                              "bytes_per_node_update": step_bytes["fp16s"]}

@@ -238,10 +238,13 @@ int lbm_ehd_scalars(lbm_ehd_t h, double out[3]);
  *    family next to its use (fewer registers, more waves per SIMD) instead
  *    of issuing every load before its first store (more loads in flight);
  *    FP32 and FP16S handles (FP64 and tangent always load per family);
- *  LBM_TUNE_TALL_TILES: the two-iteration potential kernel uses 64 x 32
- *    tiles (two rows per thread, 60 x 28 written) instead of 64 x 16
- *    (60 x 12): less ring recomputation, twice the LDS, half the blocks
- *    (FP32 and FP16S handles where the two-iteration kernel runs).
+ *  LBM_TUNE_TALL_TILES: the LDS-tiled potential kernel uses 64 x 32 tiles
+ *    (two rows per thread) instead of 64 x 16 (60 x 12 written), and runs
+ *    four sub-iterations per launch (ring of 4, 56 x 24 written, one HBM
+ *    round trip of h per four sub-iterations) while four remain, then two
+ *    (60 x 28 written); FP32 and FP16S handles where the LDS-tiled kernel
+ *    runs.  Every form gives bitwise the same potential populations as the
+ *    64 x 16 two-iteration form.
  * A captured graph (lbm_ehd_graph) is re-captured with the new
  * configuration. */
 enum {

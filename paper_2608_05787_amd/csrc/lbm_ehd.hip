@@ -92,10 +92,17 @@ Layout layout_one(const lbm_ehd_params &p, size_t off) {
   return L;
 }
 
+// Interior size of the LDS-tiled potential kernel's tile shapes: 0 the
+// 64 x 16 tile with two sub-iterations, 1 the 64 x 32 tile with two, 2 the
+// 64 x 32 tile with four.
+constexpr int tile_cols(int s) { return s == 2 ? P2Shape<2, 4>::W : P2Shape<1>::W; }
+constexpr int tile_rows(int s) { return s == 0 ? P2Shape<1>::H : s == 1 ? P2Shape<2>::H : P2Shape<2, 4>::H; }
+
 struct Plan {
   size_t desc_off, b2i_off, t2_off, state_off, total;
   int total_blocks, total_tiles2;  // tiles of the default (64 x 16) two-iteration shape
   int total_tiles2t;               // tiles of the tall (64 x 32) shape
+  int total_tiles4;                // tiles of the tall shape with four sub-iterations per launch
   std::vector<Layout> lay;
 };
 
@@ -108,17 +115,19 @@ Plan make_plan(const lbm_ehd_params *p, int n) {
   // block and tile tables, each in two orders (XCD-grouped, linear)
   P.b2i_off = off;
   off = align_up(off + 2 * (size_t)P.total_blocks * sizeof(int2));
-  P.total_tiles2 = P.total_tiles2t = 0;
-  // two-iteration potential tiles (D2Q9 planes only), both shapes
-  constexpr int H1 = P2Shape<1>::H, H2 = P2Shape<2>::H;
+  P.total_tiles2 = P.total_tiles2t = P.total_tiles4 = 0;
+  // LDS-tiled potential tiles (D2Q9 planes only), all three shapes
   for (int i = 0; i < n; ++i)
-    if (p[i].lattice == LBM_LATTICE_D2Q9) {
-      P.total_tiles2 += ((p[i].nx + P2W - 1) / P2W) * ((p[i].ny + H1 - 1) / H1);
-      P.total_tiles2t += ((p[i].nx + P2W - 1) / P2W) * ((p[i].ny + H2 - 1) / H2);
-    }
-  // tile tables: default shape (XCD-grouped, linear), then tall shape (same)
+    if (p[i].lattice == LBM_LATTICE_D2Q9)
+      for (int s = 0; s < 3; ++s) {
+        const int w = tile_cols(s), h = tile_rows(s);
+        (s == 0 ? P.total_tiles2 : s == 1 ? P.total_tiles2t : P.total_tiles4) +=
+            ((p[i].nx + w - 1) / w) * ((p[i].ny + h - 1) / h);
+      }
+  // tile tables: per shape (default, tall, tall four-iteration) the
+  // XCD-grouped order, then the linear order
   P.t2_off = off;
-  off = align_up(off + 2 * (size_t)(P.total_tiles2 + P.total_tiles2t) * sizeof(int4));
+  off = align_up(off + 2 * (size_t)(P.total_tiles2 + P.total_tiles2t + P.total_tiles4) * sizeof(int4));
   P.state_off = off;
   for (int i = 0; i < n; ++i) {
     P.lay.push_back(layout_one(p[i], off));
@@ -255,6 +264,7 @@ struct lbm_ehd_s {
   Inst *d_insts = nullptr;
   int2 *d_b2i = nullptr;  // block table in the order in use
   int4 *d_t2 = nullptr;   // tile table of the two-iteration potential kernel, in use
+  int4 *d_t4 = nullptr;   // tile table of the four-iteration form (tall tiles), in use
   // launch configuration (lbm_ehd_set_tuning): LBM_TUNE_* bits
   int tuning = 0;
   int n_t2 = 0;           // tiles in d_t2
@@ -267,6 +277,7 @@ struct lbm_ehd_s {
     const int lin = (tuning & LBM_TUNE_LINEAR_ORDER) ? 1 : 0;
     d_b2i = (int2 *)(ws + plan.b2i_off) + (size_t)lin * plan.total_blocks;
     int4 *t = (int4 *)(ws + plan.t2_off);
+    d_t4 = t + 2 * ((size_t)plan.total_tiles2 + plan.total_tiles2t) + (size_t)lin * plan.total_tiles4;
     if (tall()) {
       d_t2 = t + 2 * (size_t)plan.total_tiles2 + (size_t)lin * plan.total_tiles2t;
       n_t2 = plan.total_tiles2t;
@@ -362,6 +373,16 @@ int enqueue_fixed_potential(lbm_ehd_s *H, int K) {
         H->prof_stop(e);
         L = 1;
         k = 2;
+      }
+      // tall tiles: four sub-iterations per launch while four remain
+      if constexpr (sizeof(T) == 4) {
+        if (H->tall())
+          for (; k + 3 <= K; k += 4, ++L) {
+            hipEvent_t e = H->prof_start(6);
+            k_poisson2<T, 2, 4><<<dim3(H->plan.total_tiles4), block2, 0, H->stream>>>(H->d_insts, H->d_t4, L & 1,
+                                                                                      k + 3 == K ? 1 : 0);
+            H->prof_stop(e);
+          }
       }
       for (; k + 1 <= K; k += 2, ++L) {
         hipEvent_t e = H->prof_start(6);
@@ -692,12 +713,13 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
   }
   // tiles of the two-iteration potential kernel, rows of tiles in order
   std::vector<int4> t2;  // per shape: XCD-grouped order, then linear order
-  for (int rows : {P2Shape<1>::H, P2Shape<2>::H}) {
+  for (int shape = 0; shape < 3; ++shape) {
+    const int rows = tile_rows(shape), cols = tile_cols(shape);
     std::vector<int4> tl;
     for (int i = 0; i < n_inst; ++i)
       if (params[i].lattice == LBM_LATTICE_D2Q9)
         for (int y0 = 0; y0 < params[i].ny; y0 += rows)
-          for (int x0 = 0; x0 < params[i].nx; x0 += P2W) tl.push_back(make_int4(i, x0, y0, 0));
+          for (int x0 = 0; x0 < params[i].nx; x0 += cols) tl.push_back(make_int4(i, x0, y0, 0));
     const int T2 = (int)tl.size();
     for (int b = 0; b < T2; ++b) t2.push_back(tl[xcd_order(T2, b)]);
     t2.insert(t2.end(), tl.begin(), tl.end());
@@ -714,7 +736,8 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
           hipSuccess ||
       (e = hipMemcpyAsync(H->d_b2i, b2i.data(), sizeof(int2) * b2i.size(), hipMemcpyHostToDevice, H->stream)) !=
           hipSuccess ||
-      (e = hipMemcpyAsync(H->d_t2, t2.data(), sizeof(int4) * t2.size(), hipMemcpyHostToDevice, H->stream)) !=
+      (e = hipMemcpyAsync(H->ws + H->plan.t2_off, t2.data(), sizeof(int4) * t2.size(), hipMemcpyHostToDevice,
+                          H->stream)) !=
           hipSuccess ||
       (e = hipStreamSynchronize(H->stream)) != hipSuccess) {
     H->err = std::string("workspace setup: ") + hipGetErrorString(e);

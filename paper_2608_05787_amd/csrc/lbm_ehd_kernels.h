@@ -602,8 +602,10 @@ constexpr int P2EW = 64, P2ER = 16, P2W = P2EW - 4, P2H = P2ER - 4, P2RPT = P2ER
 // a 64 x 16 RPT extended tile with a (16 RPT - 4)-row interior (RPT = 1:
 // 60 x 12, 70% of the loaded nodes written; RPT = 2: 60 x 28, 82%, twice
 // the LDS and half the blocks).  The launch configuration picks one.
-template <int RPT> struct P2Shape {
-  static constexpr int ER = 16 * RPT, H = ER - 4;
+//   IT: sub-iterations per launch (the width of the recomputed ring); the
+//   interior is (64 - 2 IT) x (16 RPT - 2 IT).
+template <int RPT, int IT = 2> struct P2Shape {
+  static constexpr int ER = 16 * RPT, H = ER - 2 * IT, W = P2EW - 2 * IT;
 };
 
 // Per-tile values of the two-iteration kernel, read with scalar loads
@@ -654,16 +656,16 @@ template <typename T, int RPT> struct P2Regs {
   bool inside[RPT];
 };
 
-template <typename T, int RPT>
+template <typename T, int RPT, int IT>
 __device__ __forceinline__ void p2_load(const P2Meta<T> &m, const int4 t, P2Regs<T, RPT> &s) {
   const int nx = m.nx, ny = m.ny, N = m.N;
   auto src = gbl(m.src);
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int gx = wrapx(((t.y - 2 + tx) % nx + nx) % nx, nx);
+  const int gx = wrapx(((t.y - IT + tx) % nx + nx) % nx, nx);
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     const int r = ty + (P2NT / 64) * k;  // extended row of this thread's k-th node
-    int y = t.z - 2 + r;
+    int y = t.z - IT + r;
     bool in = true;
     if (m.walls) in = (y >= 0 && y < ny);
     else y = ((y % ny) + ny) % ny;
@@ -684,20 +686,20 @@ __device__ __forceinline__ void p2_load(const P2Meta<T> &m, const int4 t, P2Regs
   }
 }
 
-// The two sub-iterations of one loaded tile and the store of its interior.
-template <typename T, int RPT>
+// The IT sub-iterations of one loaded tile and the store of its interior.
+template <typename T, int RPT, int IT>
 __device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int write_psi, T *rec_in, T *rec_mid,
                                        P2Regs<T, RPT> &s, T *buf) {
-  constexpr int ER = P2Shape<RPT>::ER, H2 = P2Shape<RPT>::H;
+  constexpr int ER = P2Shape<RPT, IT>::ER, H2 = P2Shape<RPT, IT>::H, W2 = P2Shape<RPT, IT>::W;
   const int nx = m.nx, ny = m.ny, N = m.N, walls = m.walls;
   auto dst = gbl(m.dst);
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int gx = wrapx(((t.y - 2 + tx) % nx + nx) % nx, nx);
+  const int gx = wrapx(((t.y - IT + tx) % nx + nx) % nx, nx);
   // interior node of this tile (the nodes the launch writes)
   auto interior = [&](int k, int &n) {
     const int r = ty + (P2NT / 64) * k;
-    if (r < 2 || r >= 2 + H2 || tx < 2 || tx >= 2 + P2W || !s.inside[k]) return false;
-    if (t.y + tx - 2 >= nx || t.z + r - 2 >= ny) return false;
+    if (r < IT || r >= IT + H2 || tx < IT || tx >= IT + W2 || !s.inside[k]) return false;
+    if (t.y + tx - IT >= nx || t.z + r - IT >= ny) return false;
     n = s.gy[k] * nx + gx;
     return true;
   };
@@ -712,7 +714,7 @@ __device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int wri
 #pragma unroll
         for (int j = 0; j < Q; ++j) rec_in[(size_t)j * N + n] = s.h[k][j];
     }
-  for (int it = 0; it < 2; ++it) {
+  for (int it = 0; it < IT; ++it) {
     // collide every node this iteration can still use, post values to LDS
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
@@ -720,7 +722,7 @@ __device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int wri
       T v[Q];
       const T pot = poisson_collide<D2Q9>(s.h[k], s.eh[k], s.qq[k], m, v);
       int n;
-      if (it == 1 && write_psi && interior(k, n)) (gbl(m.psi))[n] = pot;
+      if (it == IT - 1 && write_psi && interior(k, n)) (gbl(m.psi))[n] = pot;
 #pragma unroll
       for (int j = 0; j < Q; ++j) buf[j * (P2EW * ER) + e] = v[j];
     }
@@ -763,17 +765,17 @@ __device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int wri
 //   tiles: (instance, x0, y0, -) per block.
 //   rec_in, rec_mid: when set, receive the input level and the level after
 //   the first sub-iteration (recording runs).
-template <typename T, int RPT = 1>
-__global__ __launch_bounds__(P2NT) void k_poisson2(const Inst *__restrict__ insts, const int4 *__restrict__ tiles,
+template <typename T, int RPT = 1, int IT = 2>
+__global__ __launch_bounds__(P2NT, 8) void k_poisson2(const Inst *__restrict__ insts, const int4 *__restrict__ tiles,
                                                  int hpar, int write_psi, T *rec_in = nullptr,
                                                  T *rec_mid = nullptr) {
-  constexpr int ER = P2Shape<RPT>::ER;
+  constexpr int ER = P2Shape<RPT, IT>::ER;
   __shared__ T buf[Q * P2EW * ER];
   int4 t;
   const P2Meta<T> m = p2_meta<T>(insts, tiles, blockIdx.x, hpar, t);
   P2Regs<T, RPT> s;
-  p2_load<T, RPT>(m, t, s);
-  p2_run<T, RPT>(m, t, write_psi, rec_in, rec_mid, s, buf);
+  p2_load<T, RPT, IT>(m, t, s);
+  p2_run<T, RPT, IT>(m, t, write_psi, rec_in, rec_mid, s, buf);
 }
 
 // Adaptive potential loop control, one block per instance, after iteration

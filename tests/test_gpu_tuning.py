@@ -1,6 +1,7 @@
 """The launch-configuration autotuner.  Block order and collide load
 schedule give bitwise the same state; the potential kernel forms (LDS
-two-iteration tiles of either shape, single launches) agree to rounding.  lbm_ehd_tune leaves
+tiles of either shape with two or four sub-iterations per launch, single
+launches) agree to rounding.  lbm_ehd_tune leaves
 the handle's state and step count as they were, keeps a graph working, and
 the Python cache applies a stored choice without timing."""
 import json
@@ -25,7 +26,11 @@ def pops(sim, n_inst):
 ROUNDING = {"fp32": 1e-5, "fp16s": 1e-2, "fp64": 1e-12}
 
 
-@pytest.mark.parametrize("prec,sub", [("fp32", (3, 3, 0.0)), ("fp64", (4, 4, 0.0)), ("fp16s", (2, 2, 0.0))])
+# fp32 K = 3: one single launch and one pair; K = 5: single + a four-iteration
+# launch on tall tiles (pairs otherwise); K = 6: a four-iteration launch and a
+# tall pair; fp16s K = 4: one four-iteration launch
+@pytest.mark.parametrize("prec,sub", [("fp32", (3, 3, 0.0)), ("fp32", (5, 5, 0.0)), ("fp32", (6, 6, 0.0)),
+                                      ("fp64", (4, 4, 0.0)), ("fp16s", (2, 2, 0.0)), ("fp16s", (4, 4, 0.0))])
 def test_every_configuration_gives_the_same_state(prec, sub):
     print("case tuning configs", prec, sub, flush=True)
     cfgs, inits = batch(sub)
