@@ -243,8 +243,8 @@ int lbm_ehd_scalars(lbm_ehd_t h, double out[3]);
  *    four sub-iterations per launch (ring of 4, 56 x 24 written, one HBM
  *    round trip of h per four sub-iterations) while four remain, then two
  *    (60 x 28 written); FP32 and FP16S handles where the LDS-tiled kernel
- *    runs.  Every form gives bitwise the same potential populations as the
- *    64 x 16 two-iteration form.
+ *    runs.  The forms agree to rounding (the compiler fuses their
+ *    multiply-adds differently).
  * A captured graph (lbm_ehd_graph) is re-captured with the new
  * configuration. */
 enum {

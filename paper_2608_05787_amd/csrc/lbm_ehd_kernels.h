@@ -496,8 +496,11 @@ __global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, cons
 // Potential LB at one node (Eqs. 43-45): potential and gradient from the
 // pre-collision h, then the collision with the eps_hat first-moment source
 // and the charge source.  Returns the potential of the input h.
+//   iden: 1 / (eps_hat + tau_h / 3), the node's gradient denominator, which
+//   does not change between the sub-iterations of a step.
 template <class L, typename T, class PP>
-__device__ __forceinline__ T poisson_collide(const T (&h)[L::Q], T epshat, T q, const PP &P, T (&v)[L::Q]) {
+__device__ __forceinline__ T poisson_collide(const T (&h)[L::Q], T epshat, T iden, T q, const PP &P,
+                                             T (&v)[L::Q]) {
   constexpr int Q = L::Q, D = L::D;
   T s1 = 0, m[D];
 #pragma unroll
@@ -508,11 +511,10 @@ __device__ __forceinline__ T poisson_collide(const T (&h)[L::Q], T epshat, T q, 
   for (int j = 0; j < Q; ++j)
 #pragma unroll
     for (int d = 0; d < D; ++d) m[d] += lc<L, T>(j, d) * h[j];
-  const T pot = s1 / (T(1) - lw<L, T>(0));
-  const T den = epshat + P.tau_h / T(3);
+  const T pot = s1 * (T(1) / (T(1) - lw<L, T>(0)));
   T g[D];
 #pragma unroll
-  for (int d = 0; d < D; ++d) g[d] = -m[d] / den;  // grad(potential), Eq. (45)
+  for (int d = 0; d < D; ++d) g[d] = -m[d] * iden;  // grad(potential), Eq. (45)
   const T ith = T(1) / P.tau_h;
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
@@ -521,6 +523,13 @@ __device__ __forceinline__ T poisson_collide(const T (&h)[L::Q], T epshat, T q, 
     v[j] = h[j] - (h[j] - heq) * ith - epshat * T(3) * lw<L, T>(j) * cg * ith + L::template varpi<T>(j) * q;
   }
   return pot;
+}
+template <typename T, class PP> __device__ __forceinline__ T poisson_iden(T epshat, const PP &P) {
+  return T(1) / (epshat + P.tau_h / T(3));
+}
+template <class L, typename T, class PP>
+__device__ __forceinline__ T poisson_collide(const T (&h)[L::Q], T epshat, T q, const PP &P, T (&v)[L::Q]) {
+  return poisson_collide<L>(h, epshat, poisson_iden(epshat, P), q, P, v);
 }
 
 // a4: one potential sub-iteration (Eqs. 43-45): local potential and gradient
@@ -651,7 +660,7 @@ __device__ __forceinline__ P2Meta<T> p2_meta(const Inst *insts, const int4 *tile
 // extended-tile nodes (h, eps, q; zeros beyond an electrode wall).  eps_hat
 // = eps - eps_ref is formed after the loads, not between them.
 template <typename T, int RPT> struct P2Regs {
-  T h[RPT][Q], eh[RPT], qq[RPT];
+  T h[RPT][Q], eh[RPT], qq[RPT], id[RPT];
   int gy[RPT];
   bool inside[RPT];
 };
@@ -704,8 +713,10 @@ __device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int wri
     return true;
   };
 #pragma unroll
-  for (int k = 0; k < RPT; ++k)
+  for (int k = 0; k < RPT; ++k) {
     if (s.inside[k]) s.eh[k] -= m.eps_ref;
+    s.id[k] = poisson_iden(s.eh[k], m);
+  }
   if (rec_in)
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
@@ -720,7 +731,7 @@ __device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int wri
     for (int k = 0; k < RPT; ++k) {
       const int r = ty + (P2NT / 64) * k, e = r * P2EW + tx;
       T v[Q];
-      const T pot = poisson_collide<D2Q9>(s.h[k], s.eh[k], s.qq[k], m, v);
+      const T pot = poisson_collide<D2Q9>(s.h[k], s.eh[k], s.id[k], s.qq[k], m, v);
       int n;
       if (it == IT - 1 && write_psi && interior(k, n)) (gbl(m.psi))[n] = pot;
 #pragma unroll
