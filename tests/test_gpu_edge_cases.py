@@ -1,5 +1,6 @@
 """Edge cases on the GPU, through the C ABI: the smallest grids the ABI
-accepts (neighbours wrap onto the node itself or mirror the only other row),
+accepts (neighbours wrap onto the node itself or mirror the only other row;
+also with the four-iteration potential tiles, whose ring is wider than the grid),
 a D3Q15 box one layer thick, an absent phase that must stay exactly zero in
 every storage precision (the reduction of the three-phase model to the
 two-phase one), and zero steps."""
@@ -10,7 +11,7 @@ torch = pytest.importorskip("torch")
 from oracle import Oracle  # noqa: E402
 from paper_2608_05787_amd import binding, inputs  # noqa: E402
 
-from test_gpu_parity import FP64_TOL, compare  # noqa: E402
+from test_gpu_parity import FP32_TOL, FP64_TOL, compare  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -25,6 +26,22 @@ def test_smallest_grids_match_oracle(nx, ny, walls):
     ref.step(6)
     sim.step(6)
     compare(sim, ref, FP64_TOL)
+
+
+@pytest.mark.parametrize("nx,ny,walls", [(2, 2, False), (2, 2, True), (3, 2, True), (5, 3, False), (2, 7, True)])
+def test_smallest_grids_four_iteration_tiles(nx, ny, walls):
+    """The tall-tile potential form (four sub-iterations per launch, a ring of
+    4 around a 56 x 24 interior) on grids smaller than its ring, where
+    extended rows and columns wrap several times or fall beyond a wall:
+    against the oracle within the FP32 parity bounds."""
+    print("case tiny four-iteration", nx, ny, walls, flush=True)
+    p, init = inputs.parity_case(nx, ny, seed=nx * 10 + ny, walls=walls, sub=(4, 4, 0.0))
+    ref = Oracle(p, init)
+    sim = binding.Sim(p, init, precision="fp32")
+    sim.set_tuning(binding.TUNE_TALL_TILES)
+    ref.step(6)
+    sim.step(6)
+    compare(sim, ref, FP32_TOL)
 
 
 def test_d3q15_single_layer_matches_oracle():
