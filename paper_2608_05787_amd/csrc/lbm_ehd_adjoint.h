@@ -468,8 +468,9 @@ __global__ __launch_bounds__(NT) void k_adj_mu(const Inst *__restrict__ insts, c
 // is the adjoint of the node's post-collision populations (already pulled
 // through the push), h its forward input; returns the adjoint of h and adds
 // to eps_hat-bar and q-bar.
+//   iden: 1 / (eps_hat + tau_h / 3), as the forward collision forms it.
 template <typename T>
-__device__ __forceinline__ void adj_poisson_local(const T (&vb)[Q], const T (&h)[Q], T eh, const Phys<T> &P,
+__device__ __forceinline__ void adj_poisson_local(const T (&vb)[Q], const T (&h)[Q], T eh, T iden, const Phys<T> &P,
                                                   T (&hb)[Q], T &eh_b, T &q_b) {
   T mx = 0, my = 0;
 #pragma unroll
@@ -477,8 +478,7 @@ __device__ __forceinline__ void adj_poisson_local(const T (&vb)[Q], const T (&h)
     mx += T(cx(j)) * h[j];
     my += T(cy(j)) * h[j];
   }
-  const T den = eh + P.tau_h / T(3);
-  const T gx = -mx / den, gy = -my / den;
+  const T gx = -mx * iden, gy = -my * iden;
   const T ith = T(1) / P.tau_h;
   T pot_b = 0, gx_b = 0, gy_b = 0;
 #pragma unroll
@@ -490,11 +490,17 @@ __device__ __forceinline__ void adj_poisson_local(const T (&vb)[Q], const T (&h)
     eh_b -= c3 * (T(cx(j)) * gx + T(cy(j)) * gy);
     if (j) q_b += T(0.125) * vb[j];
   }
-  const T mx_b = -gx_b / den, my_b = -gy_b / den;
-  eh_b += (gx_b * mx + gy_b * my) / (den * den);
-  const T ps_b = pot_b / (T(1) - wgt<T>(0));
+  // g = -m iden with iden = 1 / (eps_hat + tau_h / 3): dg/d eps_hat = m iden^2
+  const T mx_b = -gx_b * iden, my_b = -gy_b * iden;
+  eh_b += (gx_b * mx + gy_b * my) * (iden * iden);
+  const T ps_b = pot_b * (T(1) / (T(1) - wgt<T>(0)));
 #pragma unroll
   for (int j = 0; j < Q; ++j) hb[j] = vb[j] * (T(1) - ith) + T(cx(j)) * mx_b + T(cy(j)) * my_b + (j ? ps_b : T(0));
+}
+template <typename T>
+__device__ __forceinline__ void adj_poisson_local(const T (&vb)[Q], const T (&h)[Q], T eh, const Phys<T> &P,
+                                                  T (&hb)[Q], T &eh_b, T &q_b) {
+  adj_poisson_local(vb, h, eh, poisson_iden(eh, P), P, hb, eh_b, q_b);
 }
 
 // Adjoint of one potential sub-iteration (Eqs. 43-45 with anti-bounce-back
@@ -592,6 +598,7 @@ __global__ __launch_bounds__(P2NT) void k_adj_poisson2(const Inst *__restrict__ 
   double th = 0.0;
   T eh_b = 0, q_b = 0;
   const T eh = ring1 ? epsv - P.eps_ref : T(0);
+  const T iden = poisson_iden(eh, P);
   // pull of the adjoint through the push of node (r, tx); wall slots at the node itself
   auto pull = [&](T (&vb)[Q]) {
 #pragma unroll
@@ -611,7 +618,7 @@ __global__ __launch_bounds__(P2NT) void k_adj_poisson2(const Inst *__restrict__ 
     T vb[Q];
     pull(vb);
     T eb1 = 0, qb1 = 0;
-    adj_poisson_local(vb, h1v, eh, P, hb, eb1, qb1);
+    adj_poisson_local(vb, h1v, eh, iden, P, hb, eb1, qb1);
     if (interior) {
       eh_b += eb1;
       q_b += qb1;
@@ -627,7 +634,7 @@ __global__ __launch_bounds__(P2NT) void k_adj_poisson2(const Inst *__restrict__ 
     pull(vb);
 #pragma unroll
     for (int j = 0; j < Q; ++j) h[j] = h0[(size_t)j * N + n];
-    adj_poisson_local(vb, h, eh, P, hb, eh_b, q_b);
+    adj_poisson_local(vb, h, eh, iden, P, hb, eh_b, q_b);
     T *Hd = ab.hb[src ^ 1];
 #pragma unroll
     for (int j = 0; j < Q; ++j) Hd[(size_t)j * N + n] = hb[j];
