@@ -863,9 +863,17 @@ void step_record(lbm_ehd_s *W, char *slot) {
     L = 1;
     k = 2;
   }
+  // 4-byte arithmetic: four sub-iterations per launch on the tall tiles
+  // while four remain, recording all four input levels
+  if constexpr (sizeof(T) == 4)
+    for (; k + 3 <= K; k += 4, ++L)
+      k_poisson2<T, 2, 4><<<dim3(W->plan.total_tiles4), block2, 0, W->stream>>>(
+          W->d_insts, W->d_t4, L & 1, k + 3 == K ? 1 : 0,
+          P2Rec<T, 4>{{rec_level<T>(slot, N, k - 1), rec_level<T>(slot, N, k), rec_level<T>(slot, N, k + 1),
+                       rec_level<T>(slot, N, k + 2)}});
   for (; k + 1 <= K; k += 2, ++L)
     k_poisson2<T><<<grid2, block2, 0, W->stream>>>(W->d_insts, W->d_t2, L & 1, k + 1 == K ? 1 : 0,
-                                                   rec_level<T>(slot, N, k - 1), rec_level<T>(slot, N, k));
+                                                   P2Rec<T, 2>{{rec_level<T>(slot, N, k - 1), rec_level<T>(slot, N, k)}});
   const int hflip = L & 1;
   k_mu<D2Q9, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, hflip, rc);
   k_collide<D2Q9, T, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, pc, 0, K, hflip, rc);

@@ -696,8 +696,15 @@ __device__ __forceinline__ void p2_load(const P2Meta<T> &m, const int4 t, P2Regs
 }
 
 // The IT sub-iterations of one loaded tile and the store of its interior.
+// Record outputs of the LDS-tiled kernel (recording runs): lev[i], when
+// set, receives the input level of the launch's i-th sub-iteration on the
+// tile's interior.
+template <typename T, int IT> struct P2Rec {
+  T *lev[IT];
+};
+
 template <typename T, int RPT, int IT>
-__device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int write_psi, T *rec_in, T *rec_mid,
+__device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int write_psi, const P2Rec<T, IT> &rec,
                                        P2Regs<T, RPT> &s, T *buf) {
   constexpr int ER = P2Shape<RPT, IT>::ER, H2 = P2Shape<RPT, IT>::H, W2 = P2Shape<RPT, IT>::W;
   const int nx = m.nx, ny = m.ny, N = m.N, walls = m.walls;
@@ -717,15 +724,15 @@ __device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int wri
     if (s.inside[k]) s.eh[k] -= m.eps_ref;
     s.id[k] = poisson_iden(s.eh[k], m);
   }
-  if (rec_in)
-#pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-      int n;
-      if (interior(k, n))
-#pragma unroll
-        for (int j = 0; j < Q; ++j) rec_in[(size_t)j * N + n] = s.h[k][j];
-    }
   for (int it = 0; it < IT; ++it) {
+    if (T *lev = rec.lev[it])
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        int n;
+        if (interior(k, n))
+#pragma unroll
+          for (int j = 0; j < Q; ++j) lev[(size_t)j * N + n] = s.h[k][j];
+      }
     // collide every node this iteration can still use, post values to LDS
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
@@ -754,14 +761,6 @@ __device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int wri
       }
     }
     __syncthreads();
-    if (it == 0 && rec_mid)
-#pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        int n;
-        if (interior(k, n))
-#pragma unroll
-          for (int j = 0; j < Q; ++j) rec_mid[(size_t)j * N + n] = s.h[k][j];
-      }
   }
   // interior pre-collision values of the next level
 #pragma unroll
@@ -774,19 +773,17 @@ __device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int wri
 }
 
 //   tiles: (instance, x0, y0, -) per block.
-//   rec_in, rec_mid: when set, receive the input level and the level after
-//   the first sub-iteration (recording runs).
+//   rec: the input levels of the sub-iterations, for recording runs.
 template <typename T, int RPT = 1, int IT = 2>
 __global__ __launch_bounds__(P2NT, 8) void k_poisson2(const Inst *__restrict__ insts, const int4 *__restrict__ tiles,
-                                                 int hpar, int write_psi, T *rec_in = nullptr,
-                                                 T *rec_mid = nullptr) {
+                                                 int hpar, int write_psi, P2Rec<T, IT> rec = P2Rec<T, IT>{}) {
   constexpr int ER = P2Shape<RPT, IT>::ER;
   __shared__ T buf[Q * P2EW * ER];
   int4 t;
   const P2Meta<T> m = p2_meta<T>(insts, tiles, blockIdx.x, hpar, t);
   P2Regs<T, RPT> s;
   p2_load<T, RPT, IT>(m, t, s);
-  p2_run<T, RPT, IT>(m, t, write_psi, rec_in, rec_mid, s, buf);
+  p2_run<T, RPT, IT>(m, t, write_psi, rec, s, buf);
 }
 
 // Adaptive potential loop control, one block per instance, after iteration
