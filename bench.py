@@ -268,18 +268,21 @@ def gradient_bench(n, steps, sub, init_iters, every):
     reverse sweep: lbm_ehd_record (the FP32 forward with a checkpoint every
     `every` steps) then lbm_ehd_adjoint (segments recomputed from their
     checkpoints, step adjoints backwards, then create's).  Times are against
-    the plain FP32 forward run of the same length from create; the FP32
-    gradient is compared with the FP64 sweep's."""
+    the plain FP32 forward run of the same length from create, in the launch
+    configuration the autotuner picks for it (the recording forward uses the
+    same); the FP32 gradient is compared with the FP64 sweep's."""
     import torch
     from paper_2608_05787_amd import autograd, binding, inputs
     p, init = inputs.field_compound_drop(n, r_shell=40.0, r_core=30.0, sub=(sub, sub, 0.0),
                                          init_iters=init_iters, init_tol=0.0)
     warm = binding.Sim(p, init, precision="fp32")  # first-use costs stay out of the timings
     warm.step(10)
+    cfg = warm.autotune(steps=10)["config"]  # the forward runs in its fastest launch configuration
     torch.cuda.synchronize()
     del warm
     t0 = time.time()
     fwd = binding.Sim(p, init, precision="fp32")
+    fwd.set_tuning(cfg)
     fwd.step(steps)
     phi = fwd.fields(["phi1"])["phi1"]
     torch.cuda.synchronize()
@@ -292,6 +295,7 @@ def gradient_bench(n, steps, sub, init_iters, every):
     torch.cuda.synchronize()
     t0 = time.time()
     rec = binding.Sim(p, init, precision="fp32")
+    rec.set_tuning(cfg)
     rec.record(steps, every)
     torch.cuda.synchronize()
     t_rec = time.time() - t0
@@ -309,6 +313,7 @@ def gradient_bench(n, steps, sub, init_iters, every):
     return {"workload": "field compound drop %dx%d, radii 40/30, %d steps, %d potential sub-iterations, "
                         "cold start %d iterations" % (n, n, steps, sub, init_iters),
             "method": "reverse sweep, FP32, checkpoint every %d steps" % every,
+            "forward_launch_config": cfg,
             "D_outer": float(D.detach()), "dD_dtheta": g, "dD_dtheta_fp64_sweep": g64,
             "rel_diff_fp32_vs_fp64": rel,
             "forward_s": round(t_fwd, 4), "record_s": round(t_rec, 4), "adjoint_s": round(t_adj, 4),

@@ -273,18 +273,22 @@ struct lbm_ehd_s {
   bool tall() const {
     return (tuning & LBM_TUNE_TALL_TILES) != 0 && (prec == LBM_PREC_FP32 || prec == LBM_PREC_FP16S);
   }
+  // tile table of shape s (0: 64 x 16, two sub-iterations; 1: 64 x 32, two;
+  // 2: 64 x 32, four) in the block order in use
+  int4 *table(int s) const {
+    const size_t lin = (tuning & LBM_TUNE_LINEAR_ORDER) ? 1 : 0;
+    int4 *t = (int4 *)(ws + plan.t2_off);
+    if (s == 0) return t + lin * plan.total_tiles2;
+    t += 2 * (size_t)plan.total_tiles2;
+    if (s == 1) return t + lin * plan.total_tiles2t;
+    return t + 2 * (size_t)plan.total_tiles2t + lin * plan.total_tiles4;
+  }
   void apply_order() {
     const int lin = (tuning & LBM_TUNE_LINEAR_ORDER) ? 1 : 0;
     d_b2i = (int2 *)(ws + plan.b2i_off) + (size_t)lin * plan.total_blocks;
-    int4 *t = (int4 *)(ws + plan.t2_off);
-    d_t4 = t + 2 * ((size_t)plan.total_tiles2 + plan.total_tiles2t) + (size_t)lin * plan.total_tiles4;
-    if (tall()) {
-      d_t2 = t + 2 * (size_t)plan.total_tiles2 + (size_t)lin * plan.total_tiles2t;
-      n_t2 = plan.total_tiles2t;
-    } else {
-      d_t2 = t + (size_t)lin * plan.total_tiles2;
-      n_t2 = plan.total_tiles2;
-    }
+    d_t4 = table(2);
+    d_t2 = table(tall() ? 1 : 0);
+    n_t2 = tall() ? plan.total_tiles2t : plan.total_tiles2;
   }
   int sub_min = 1, sub_max = 1, adaptive = 0;
   double sub_tol = 0;
@@ -847,11 +851,11 @@ template <typename T> Rec<T> rec_slot(char *slot, size_t N) {
 template <typename T> T *rec_level(char *slot, size_t N, int k) { return (T *)slot + (REC_FIXED + 9 * (size_t)k) * N; }
 
 // One forward step that also writes its record: the launches of an
-// ordinary fixed-count step, the potential kernels storing the input level
-// of every sub-iteration.
+// ordinary fixed-count step in the handle's launch configuration, the
+// potential kernels storing the input level of every sub-iteration.
 template <typename T>
 void step_record(lbm_ehd_s *W, char *slot) {
-  const dim3 grid(W->plan.total_blocks), block(NT), grid2(W->plan.total_tiles2), block2(P2NT);
+  const dim3 grid(W->plan.total_blocks), block(NT), block2(P2NT);
   const size_t N = (size_t)W->hinst[0].N;
   const int K = W->sub_max, pc = (int)(W->steps & 1);
   const Rec<T> rc = rec_slot<T>(slot, N);
@@ -863,20 +867,27 @@ void step_record(lbm_ehd_s *W, char *slot) {
     L = 1;
     k = 2;
   }
-  // 4-byte arithmetic: four sub-iterations per launch on the tall tiles
-  // while four remain, recording all four input levels
-  if constexpr (sizeof(T) == 4)
-    for (; k + 3 <= K; k += 4, ++L)
-      k_poisson2<T, 2, 4><<<dim3(W->plan.total_tiles4), block2, 0, W->stream>>>(
-          W->d_insts, W->d_t4, L & 1, k + 3 == K ? 1 : 0,
-          P2Rec<T, 4>{{rec_level<T>(slot, N, k - 1), rec_level<T>(slot, N, k), rec_level<T>(slot, N, k + 1),
-                       rec_level<T>(slot, N, k + 2)}});
+  auto lev = [&](int i) { return rec_level<T>(slot, N, i); };
+  if constexpr (sizeof(T) == 4) {
+    if (W->tall()) {
+      // four sub-iterations per launch while four remain, then tall pairs
+      for (; k + 3 <= K; k += 4, ++L)
+        k_poisson2<T, 2, 4><<<dim3(W->plan.total_tiles4), block2, 0, W->stream>>>(
+            W->d_insts, W->table(2), L & 1, k + 3 == K ? 1 : 0, P2Rec<T, 4>{{lev(k - 1), lev(k), lev(k + 1), lev(k + 2)}});
+      for (; k + 1 <= K; k += 2, ++L)
+        k_poisson2<T, 2><<<dim3(W->plan.total_tiles2t), block2, 0, W->stream>>>(
+            W->d_insts, W->table(1), L & 1, k + 1 == K ? 1 : 0, P2Rec<T, 2>{{lev(k - 1), lev(k)}});
+    }
+  }
   for (; k + 1 <= K; k += 2, ++L)
-    k_poisson2<T><<<grid2, block2, 0, W->stream>>>(W->d_insts, W->d_t2, L & 1, k + 1 == K ? 1 : 0,
-                                                   P2Rec<T, 2>{{rec_level<T>(slot, N, k - 1), rec_level<T>(slot, N, k)}});
+    k_poisson2<T><<<dim3(W->plan.total_tiles2), block2, 0, W->stream>>>(
+        W->d_insts, W->table(0), L & 1, k + 1 == K ? 1 : 0, P2Rec<T, 2>{{lev(k - 1), lev(k)}});
   const int hflip = L & 1;
   k_mu<D2Q9, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, hflip, rc);
-  k_collide<D2Q9, T, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, pc, 0, K, hflip, rc);
+  if (sizeof(T) <= 4 && (W->tuning & LBM_TUNE_COLLIDE_PER_FAMILY))
+    k_collide<D2Q9, T, T, false><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, pc, 0, K, hflip, rc);
+  else
+    k_collide<D2Q9, T, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, pc, 0, K, hflip, rc);
   W->steps += 1;
 }
 
@@ -894,7 +905,7 @@ void step_adjoint(lbm_ehd_s *W, char *slot, const AdjBufs<T> &ab, int &cur, int 
   int k = K;
   for (; k >= 2; k -= 2) {
     k_adj_poisson2<T><<<dim3(W->plan.total_tiles2), dim3(P2NT), 0, W->stream>>>(
-        W->d_insts, W->d_t2, rec_level<T>(slot, N, k - 1), rec_level<T>(slot, N, k - 2), rc.eps, ab, hs, ab.qb);
+        W->d_insts, W->table(0), rec_level<T>(slot, N, k - 1), rec_level<T>(slot, N, k - 2), rc.eps, ab, hs, ab.qb);
     hs ^= 1;
   }
   if (k == 1) {
@@ -1039,7 +1050,7 @@ int reverse_sweep(lbm_ehd_s *H, lbm_ehd_s *W, char *work, const AdjLayout &L, in
       for (int k = kb - 1; k >= ka;) {
         if (k - 1 >= ka) {
           k_adj_poisson2<T><<<dim3(W->plan.total_tiles2), dim3(P2NT), 0, W->stream>>>(
-              W->d_insts, W->d_t2, lev + (size_t)(k - ka) * lv, lev + (size_t)(k - 1 - ka) * lv, (const T *)I.eps,
+              W->d_insts, W->table(0), lev + (size_t)(k - ka) * lv, lev + (size_t)(k - 1 - ka) * lv, (const T *)I.eps,
               ab, hs, ab.rb);
           k -= 2;
         } else {
@@ -1426,8 +1437,15 @@ int lbm_ehd_adjoint(lbm_ehd_t H, int64_t n_steps, int32_t ckpt_every, const void
   const bool recorded = H->rec_work == dev_work && H->rec_n == n_steps && H->rec_every == ckpt_every;
   lbm_ehd_t W = nullptr;
   int rc;
+  // the sweep's handle runs in the caller's launch configuration: its
+  // recomputed segments then repeat the recorded forward's kernels
+  auto configure = [&]() {
+    W->tuning = H->tuning;
+    W->apply_order();
+  };
   if (recorded) {
     rc = create_impl(&H->params[0], 1, nullptr, work + L.shell, (void *)H->stream, &W, false);
+    if (!rc) configure();
   } else {
     lbm_ehd_init ini;
     ini.phi0 = H->init_phi[0].data();
@@ -1437,6 +1455,7 @@ int lbm_ehd_adjoint(lbm_ehd_t H, int64_t n_steps, int32_t ckpt_every, const void
     ini.ions0 = H->init_ions[0].empty() ? nullptr : H->init_ions[0].data();
     rc = create_impl(&H->params[0], 1, &ini, work + L.shell, (void *)H->stream, &W, true);
     if (!rc) {
+      configure();
       rc = record_run(W, work, L, n_steps, ckpt_every);
       if (rc) H->err = W->err;
     }

@@ -129,6 +129,31 @@ def test_reverse_fp32_against_fp64():
     assert np.all(np.abs(g32 - g64) <= 1e-3 * np.abs(g64) + 1e-5 * np.abs(g64).max()), (g32, g64)
 
 
+@pytest.mark.parametrize("config", [8, 12, 13])
+def test_reverse_fp32_in_tuned_configurations(config):
+    """K = 4 in a tuned launch configuration (tall tiles: four potential
+    sub-iterations per launch; 12: also per-family collide loads; 13: also
+    the linear block order).  The sweep recomputes its segments in the
+    caller's configuration: FP32 gradients against the FP64 sweep, and the
+    adjoint over a recording equals, bitwise, the one that records its own
+    run."""
+    print("case reverse tuned", config, flush=True)
+    cfg, init = inputs.field_compound_drop(48, r_shell=12.0, r_core=7.0, ca_e=0.4, init_iters=100,
+                                           init_tol=0.0, sub=(4, 4, 0.0))
+    seed = seeds((cfg["ny"], cfg["nx"]), ["phi1", "phi3"], seed=7)
+    g64 = np.array(reverse_grad(cfg, init, seed))
+    st = {k: torch.from_numpy(v) for k, v in seed.items()}
+    a = binding.Sim(cfg, init, precision="fp32")
+    a.set_tuning(config)
+    a.record(STEPS, 16)
+    g32 = a.adjoint(STEPS, st, 16)
+    assert np.all(np.abs(np.array(g32) - g64) <= 1e-3 * np.abs(g64) + 1e-5 * np.abs(g64).max()), (g32, g64)
+    b = binding.Sim(cfg, init, precision="fp32")
+    b.set_tuning(config)
+    b.step(STEPS)
+    assert b.adjoint(STEPS, st, 16) == g32
+
+
 def test_record_matches_step_and_is_reused():
     """record() advances the handle exactly like step(); the adjoint over
     that recording equals the adjoint that records its own run."""
