@@ -901,8 +901,18 @@ void step_adjoint(lbm_ehd_s *W, char *slot, const AdjBufs<T> &ab, int &cur, int 
   const Rec<T> rc = rec_slot<T>(slot, N);
   k_adj_collide<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, rc, ab, cur);
   k_adj_mu<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, rc, ab, cur, hs, 1);
-  // sub-iterations K, K-1, ... in pairs on LDS tiles, a single one last when K is odd
+  // sub-iterations K, K-1, ... on LDS tiles: in fours on the tall tiles
+  // (4-byte arithmetic in that launch configuration), then in pairs, a
+  // single one last when K is odd
   int k = K;
+  if constexpr (sizeof(T) == 4)
+    if (W->tall())
+      for (; k >= 4; k -= 4) {
+        k_adj_poisson4<T><<<dim3(W->plan.total_tiles4), dim3(P2NT), 0, W->stream>>>(
+            W->d_insts, W->table(2), rec_level<T>(slot, N, k - 4), rec_level<T>(slot, N, k - 3),
+            rec_level<T>(slot, N, k - 2), rec_level<T>(slot, N, k - 1), rc.eps, ab, hs, ab.qb);
+        hs ^= 1;
+      }
   for (; k >= 2; k -= 2) {
     k_adj_poisson2<T><<<dim3(W->plan.total_tiles2), dim3(P2NT), 0, W->stream>>>(
         W->d_insts, W->table(0), rec_level<T>(slot, N, k - 1), rec_level<T>(slot, N, k - 2), rc.eps, ab, hs, ab.qb);

@@ -653,6 +653,132 @@ __global__ __launch_bounds__(P2NT) void k_adj_poisson2(const Inst *__restrict__ 
   }
 }
 
+// Adjoints of four potential sub-iterations in one launch, the transpose of
+// the four-iteration k_poisson2 on 64 x 32 tiles (two extended rows per
+// thread): the adjoint of the output level is loaded for the extended tile
+// into LDS; sub-iterations 4, 3, 2, 1 are reversed in turn on the nodes at
+// least 1, 2, 3, 4 nodes inside the tile (their push targets hold the
+// adjoint of the next level there), each with its forward input level
+// lv[3], lv[2], lv[1], lv[0], writing the level's adjoint back to LDS.  The
+// interior's adjoint of the input level goes to hb[src ^ 1] and its eps-bar
+// and q-bar of all four sub-iterations are added; wall tiles add their
+// d/d E0 terms to slot blockIdx.x of tb.
+template <typename T>
+__global__ __launch_bounds__(P2NT) void k_adj_poisson4(const Inst *__restrict__ insts, const int4 *__restrict__ tiles,
+                                                      const T *__restrict__ lv0, const T *__restrict__ lv1,
+                                                      const T *__restrict__ lv2, const T *__restrict__ lv3,
+                                                      const T *__restrict__ eps, AdjBufs<T> ab, int src, T *qb) {
+  constexpr int RPT = 2, IT = 4, ER = P2Shape<RPT, IT>::ER, H4 = P2Shape<RPT, IT>::H, W4 = P2Shape<RPT, IT>::W;
+  constexpr int PL = P2EW * ER;  // LDS plane
+  __shared__ T buf[Q * PL];
+  __shared__ double red[P2NT / 64];
+  const int4 t = tiles[blockIdx.x];
+  const Inst &I = insts[t.x];
+  const Phys<T> &P = phys<T>(I);
+  const int nx = I.nx, ny = I.ny, N = I.N, walls = I.bc_y;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int gx = wrapx(((t.y - IT + tx) % nx + nx) % nx, nx);
+  int gy[RPT], n[RPT], e[RPT], dist[RPT];
+  bool inside[RPT], interior[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int r = ty + (P2NT / 64) * k;
+    int y = t.z - IT + r;
+    bool in = true;
+    if (walls) in = y >= 0 && y < ny;
+    else y = ((y % ny) + ny) % ny;
+    gy[k] = y;
+    inside[k] = in;
+    n[k] = y * nx + gx;
+    e[k] = r * P2EW + tx;
+    const int dr = r < ER - 1 - r ? r : ER - 1 - r, dc = tx < P2EW - 1 - tx ? tx : P2EW - 1 - tx;
+    dist[k] = dr < dc ? dr : dc;  // 0 on the tile's outermost ring
+    interior[k] = in && dist[k] >= IT && r - IT < H4 && tx - IT < W4 && t.y + tx - IT < nx && t.z + r - IT < ny;
+  }
+  // the adjoint of the output level and eps, in one burst of loads
+  const T *Hs = ab.hb[src];
+  T hv[RPT][Q], epsv[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) hv[k][j] = inside[k] ? Hs[(size_t)j * N + n[k]] : T(0);
+    epsv[k] = inside[k] && dist[k] >= 1 ? eps[n[k]] : T(0);
+  }
+#pragma unroll
+  for (int k = 0; k < RPT; ++k)
+#pragma unroll
+    for (int j = 0; j < Q; ++j) buf[j * PL + e[k]] = hv[k][j];
+  __syncthreads();
+  double th = 0.0;
+  T eh[RPT], iden[RPT], eh_b[RPT], q_b[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    eh[k] = inside[k] && dist[k] >= 1 ? epsv[k] - P.eps_ref : T(0);
+    iden[k] = poisson_iden(eh[k], P);
+    eh_b[k] = q_b[k] = T(0);
+  }
+  const T *lvs[IT] = {lv0, lv1, lv2, lv3};
+  T hb[RPT][Q];
+#pragma unroll 1
+  for (int i = IT; i >= 1; --i) {
+    const int need = IT - i + 1;  // nodes this reversal reaches: at least `need` inside the tile
+    const T *lv = lvs[i - 1];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      if (!inside[k] || dist[k] < need) continue;
+      T vb[Q], h[Q];
+      // pull of the adjoint through the push of this node; wall slots at the node itself
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        const int yd = gy[k] + cy(j);
+        if (walls && (yd < 0 || yd >= ny)) {
+          const T a = buf[opp(j) * PL + e[k]];
+          vb[j] = -a;
+          if (interior[k]) th += 2.0 * (double)(wgt<T>(j) * a) * ab.dwall[yd >= ny ? 1 : 0];
+        } else {
+          vb[j] = buf[j * PL + e[k] + cy(j) * P2EW + cx(j)];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < Q; ++j) h[j] = lv[(size_t)j * N + n[k]];
+      T eb1 = 0, qb1 = 0;
+      adj_poisson_local(vb, h, eh[k], iden[k], P, hb[k], eb1, qb1);
+      if (interior[k]) {
+        eh_b[k] += eb1;
+        q_b[k] += qb1;
+      }
+    }
+    if (i > 1) {
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < RPT; ++k)
+        if (inside[k] && dist[k] >= need)
+#pragma unroll
+          for (int j = 0; j < Q; ++j) buf[j * PL + e[k]] = hb[k][j];
+      __syncthreads();
+    }
+  }
+  T *Hd = ab.hb[src ^ 1];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k)
+    if (interior[k]) {
+#pragma unroll
+      for (int j = 0; j < Q; ++j) Hd[(size_t)j * N + n[k]] = hb[k][j];
+      ab.eb[n[k]] += eh_b[k];
+      qb[n[k]] += q_b[k];
+    }
+  if (walls && (t.z == 0 || t.z + H4 >= ny)) {
+    for (int o = 32; o > 0; o >>= 1) th += __shfl_down(th, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = th;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0;
+      for (int w = 0; w < P2NT / 64; ++w) s += red[w];
+      ab.tb[(size_t)blockIdx.x * TB_SLOTS + 6] += s;
+    }
+  }
+}
+
 // Adjoint of charge recovery (Eq. 47 with the previous step's field) and of
 // the permittivity field; gathers the Laplacian-bar of the mu adjoint.
 // Writes the lsum-bar, the previous field's adjoint (state), and the
