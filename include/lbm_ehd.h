@@ -231,7 +231,7 @@ int lbm_ehd_scalars(lbm_ehd_t h, double out[3]);
  *    tiles) in row order, instead of giving each XCD a contiguous range of
  *    rows (neighbour rows then share that XCD's L2);
  *  LBM_TUNE_SINGLE_POTENTIAL: fixed-count potential sub-iterations run one
- *    launch each instead of the LDS-tiled two-iteration kernel (which exists
+ *    launch each instead of the LDS-tiled kernel (which exists
  *    for fixed-count D2Q9 handles in FP32, FP16S or FP64; elsewhere single
  *    launches are the only form and the bit changes nothing);
  *  LBM_TUNE_COLLIDE_PER_FAMILY: the collide kernel loads each population

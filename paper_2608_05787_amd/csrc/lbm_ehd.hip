@@ -100,7 +100,7 @@ constexpr int tile_rows(int s) { return s == 0 ? P2Shape<1>::H : s == 1 ? P2Shap
 
 struct Plan {
   size_t desc_off, b2i_off, t2_off, state_off, total;
-  int total_blocks, total_tiles2;  // tiles of the default (64 x 16) two-iteration shape
+  int total_blocks, total_tiles2;  // tiles of the default shape (64 x 16, two sub-iterations)
   int total_tiles2t;               // tiles of the tall (64 x 32) shape
   int total_tiles4;                // tiles of the tall shape with four sub-iterations per launch
   std::vector<Layout> lay;
@@ -263,7 +263,7 @@ struct lbm_ehd_s {
   std::vector<Inst> hinst;
   Inst *d_insts = nullptr;
   int2 *d_b2i = nullptr;  // block table in the order in use
-  int4 *d_t2 = nullptr;   // tile table of the two-iteration potential kernel, in use
+  int4 *d_t2 = nullptr;   // tile table of the two-sub-iteration launches, in use
   int4 *d_t4 = nullptr;   // tile table of the four-iteration form (tall tiles), in use
   // launch configuration (lbm_ehd_set_tuning): LBM_TUNE_* bits
   int tuning = 0;
@@ -361,9 +361,10 @@ struct lbm_ehd_s {
 namespace {
 
 // Fixed-count potential iterations 1..K: on D2Q9 planes one
-// single-iteration launch first when K is odd, then two-iteration LDS-tiled
-// launches; elsewhere (D3Q15 boxes, 16-byte tangent values that leave no
-// room for the tile) one launch per iteration.  Returns the launch count
+// single-iteration launch first when K is odd, then LDS-tiled launches of
+// four sub-iterations (tall tiles, 4-byte arithmetic) and of two; elsewhere
+// (D3Q15 boxes, 16-byte tangent values that leave no room for the tile) one
+// launch per iteration.  Returns the launch count
 // (its parity is the buffer flip of the whole loop).
 template <class Lat, typename T>
 int enqueue_fixed_potential(lbm_ehd_s *H, int K) {
@@ -715,7 +716,7 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
     b2i[b] = logical[xcd_order(B, b)];
     b2i[B + b] = logical[b];
   }
-  // tiles of the two-iteration potential kernel, rows of tiles in order
+  // tiles of the LDS-tiled potential kernel, rows of tiles in order
   std::vector<int4> t2;  // per shape: XCD-grouped order, then linear order
   for (int shape = 0; shape < 3; ++shape) {
     const int rows = tile_rows(shape), cols = tile_cols(shape);
@@ -1267,11 +1268,11 @@ int lbm_ehd_set_tuning(lbm_ehd_t H, int32_t config) {
 int lbm_ehd_tune(lbm_ehd_t H, int32_t steps, void *dev_scratch, double ms_per_step[16], int32_t *best) {
   if (!H || steps < 1 || !dev_scratch || !ms_per_step) return LBM_EHD_EINVAL;
   if (H->prof) return H->fail(LBM_EHD_ESTATE, "tune: not while profiling");
-  // the two-iteration kernel exists for fixed-count D2Q9 FP32/FP16S/FP64 handles
+  // the LDS-tiled potential kernel exists for fixed-count D2Q9 FP32/FP16S/FP64 handles
   const bool pair_form = H->lattice == LBM_LATTICE_D2Q9 && !H->adaptive && H->prec != LBM_PREC_TANGENT;
   // the two collide load schedules differ for 4-byte arithmetic (FP32, FP16S)
   const bool sched_form = H->prec == LBM_PREC_FP32 || H->prec == LBM_PREC_FP16S;
-  // the tall tile shape exists for the two-iteration kernel in 4-byte arithmetic
+  // the tall tile shapes exist for 4-byte arithmetic
   const bool tall_form = pair_form && sched_form;
   const int glen = H->glen;
   H->drop_graph();

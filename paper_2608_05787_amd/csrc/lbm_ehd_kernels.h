@@ -594,30 +594,31 @@ __global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, 
   }
 }
 
-// Two potential sub-iterations in one launch (fixed count, D2Q9).  A block owns a
-// P2W x P2H tile and recomputes a ring of width 2 around it: it loads h,
-// eps_hat and q of the (P2W + 4) x (P2H + 4) extended tile (neighbour rows
-// come from L2), collides every extended node, streams inside LDS (pull, with
-// anti-bounce-back where the source lies beyond an electrode), collides
-// again where both neighbours were valid, streams again, and writes the
+// Several potential sub-iterations in one launch (fixed count, D2Q9).  A
+// block owns a tile and recomputes a ring of width IT (the sub-iterations
+// per launch, 2 or 4) around it: it loads h, eps_hat and q of the extended
+// tile (neighbour rows come from L2), collides every extended node, streams
+// inside LDS (pull, with anti-bounce-back where the source lies beyond an
+// electrode), and repeats on the region still valid, then writes the
 // interior's pre-collision values to the other buffer: 80 B/node of HBM
-// traffic for two iterations instead of 160.
+// traffic per launch instead of 80 per sub-iteration.
 //   tiles: (instance, x0, y0, -) per block; hpar: input parity relative to
-//   ctl->hcur; write_psi: store the potential of the second iteration's input
-//   (the last iteration of the step).
-constexpr int P2NT = 1024;  // threads per block of the two-iteration kernel
+//   ctl->hcur; write_psi: store the potential of the last sub-iteration's
+//   input (the last launch of the step).
+constexpr int P2NT = 1024;  // threads per block of the LDS-tiled potential kernel
 constexpr int P2EW = 64, P2ER = 16, P2W = P2EW - 4, P2H = P2ER - 4, P2RPT = P2ER / (P2NT / 64);
-// Tile shapes of the two-iteration kernel: RPT extended rows per thread, so
-// a 64 x 16 RPT extended tile with a (16 RPT - 4)-row interior (RPT = 1:
-// 60 x 12, 70% of the loaded nodes written; RPT = 2: 60 x 28, 82%, twice
-// the LDS and half the blocks).  The launch configuration picks one.
+// Tile shapes: RPT extended rows per thread, so a 64 x 16 RPT extended tile
+// with a (16 RPT - 2 IT)-row, (64 - 2 IT)-column interior (RPT = 1, IT = 2:
+// 60 x 12, 70% of the loaded nodes written; RPT = 2, IT = 2: 60 x 28, 82%,
+// twice the LDS and half the blocks; RPT = 2, IT = 4: 56 x 24, 66%, one HBM
+// round trip for four sub-iterations).  The launch configuration picks one.
 //   IT: sub-iterations per launch (the width of the recomputed ring); the
 //   interior is (64 - 2 IT) x (16 RPT - 2 IT).
 template <int RPT, int IT = 2> struct P2Shape {
   static constexpr int ER = 16 * RPT, H = ER - 2 * IT, W = P2EW - 2 * IT;
 };
 
-// Per-tile values of the two-iteration kernel, read with scalar loads
+// Per-tile values of the LDS-tiled potential kernel, read with scalar loads
 // before the tile's population loads are issued.
 template <typename T> struct P2Meta {
   const T *src, *eps, *q;
@@ -656,7 +657,7 @@ __device__ __forceinline__ P2Meta<T> p2_meta(const Inst *insts, const int4 *tile
   return m;
 }
 
-// Registers of one tile of the two-iteration kernel: this thread's RPT
+// Registers of one tile of the LDS-tiled potential kernel: this thread's RPT
 // extended-tile nodes (h, eps, q; zeros beyond an electrode wall).  eps_hat
 // = eps - eps_ref is formed after the loads, not between them.
 template <typename T, int RPT> struct P2Regs {
