@@ -129,17 +129,17 @@ def test_reverse_fp32_against_fp64():
     assert np.all(np.abs(g32 - g64) <= 1e-3 * np.abs(g64) + 1e-5 * np.abs(g64).max()), (g32, g64)
 
 
-@pytest.mark.parametrize("config", [8, 12, 13])
-def test_reverse_fp32_in_tuned_configurations(config):
-    """K = 4 in a tuned launch configuration (tall tiles: four potential
-    sub-iterations per launch; 12: also per-family collide loads; 13: also
-    the linear block order).  The sweep recomputes its segments in the
-    caller's configuration: FP32 gradients against the FP64 sweep, and the
-    adjoint over a recording equals, bitwise, the one that records its own
-    run."""
-    print("case reverse tuned", config, flush=True)
+@pytest.mark.parametrize("config,K", [(8, 4), (12, 4), (13, 4), (12, 5), (12, 6)])
+def test_reverse_fp32_in_tuned_configurations(config, K):
+    """A tuned launch configuration (tall tiles: four potential sub-iterations
+    per launch while four remain; 12: also per-family collide loads; 13: also
+    the linear block order); K = 5 adds a single sub-iteration, K = 6 a tall
+    pair.  The sweep recomputes its segments in the caller's configuration:
+    FP32 gradients against the FP64 sweep, and the adjoint over a recording
+    equals, bitwise, the one that records its own run."""
+    print("case reverse tuned", config, K, flush=True)
     cfg, init = inputs.field_compound_drop(48, r_shell=12.0, r_core=7.0, ca_e=0.4, init_iters=100,
-                                           init_tol=0.0, sub=(4, 4, 0.0))
+                                           init_tol=0.0, sub=(K, K, 0.0))
     seed = seeds((cfg["ny"], cfg["nx"]), ["phi1", "phi3"], seed=7)
     g64 = np.array(reverse_grad(cfg, init, seed))
     st = {k: torch.from_numpy(v) for k, v in seed.items()}
