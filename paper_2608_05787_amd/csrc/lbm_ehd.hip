@@ -890,7 +890,10 @@ void step_record(lbm_ehd_s *W, char *slot) {
   const size_t N = (size_t)W->hinst[0].N;
   const int K = W->sub_max, pc = (int)(W->steps & 1);
   const Rec<T> rc = rec_slot<T>(slot, N);
-  k_moments<D2Q9, T, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, pc, rc);
+  if (W->vec_moments)
+    k_moments4<T, T><<<dim3(W->plan.total_blocks4), block, 0, W->stream>>>(W->d_insts, W->d_b2i4, pc, rc);
+  else
+    k_moments<D2Q9, T, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, pc, rc);
   k_pre<D2Q9, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, rc);
   int L = 0, k = 1;
   if (K & 1) {

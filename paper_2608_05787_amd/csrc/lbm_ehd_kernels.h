@@ -445,9 +445,10 @@ constexpr int M4 = 4 * NT;  // nodes per block of k_moments4
 template <typename T> struct Vec4 {
   typedef T v __attribute__((ext_vector_type(4)));
 };
+//   rc: when rc.phi is set, the order parameters also go there (recording runs).
 template <typename T, typename S>
 __global__ __launch_bounds__(NT) void k_moments4(const Inst *__restrict__ insts, const int2 *__restrict__ b2i4,
-                                                 int pc) {
+                                                 int pc, Rec<T> rc = Rec<T>{}) {
   constexpr int Q = D2Q9::Q;
   using V = typename Vec4<T>::v;
   using GV = const V __attribute__((address_space(1))) *;
@@ -509,6 +510,7 @@ __global__ __launch_bounds__(NT) void k_moments4(const Inst *__restrict__ insts,
 #pragma unroll
     for (int j = split ? 1 : 0; j < Q; ++j) a += fv[i][j];
     phi[(size_t)i * N4 + b4] = a;
+    if (rc.phi) ((V *)rc.phi)[(size_t)i * N4 + b4] = a;
   }
   V b = V(T(0));
 #pragma unroll
