@@ -519,9 +519,12 @@ int do_step(lbm_ehd_s *H, int64_t n) {
     const int pc = (int)((H->steps + s) & 1);
     hipEvent_t e = H->prof_start(0);
     bool vec = false;
-    if constexpr (std::is_same<Lat, D2Q9>::value && sizeof(T) <= 8) {
+    if constexpr ((std::is_same<Lat, D2Q9>::value && sizeof(T) <= 8) || sizeof(T) == 4) {
       if (H->vec_moments) {
-        k_moments4<T, S><<<dim3(H->plan.total_blocks4), block, 0, H->stream>>>(H->d_insts, H->d_b2i4, pc);
+        // D3Q15 in FP32: two nodes per thread (four would need 240 VGPRs of data)
+        constexpr int W = std::is_same<Lat, D3Q15>::value && std::is_same<S, float>::value ? 2 : 4;
+        k_moments4<Lat, T, S, W>
+            <<<dim3(H->plan.total_blocks4 * (4 / W)), block, 0, H->stream>>>(H->d_insts, H->d_b2i4, pc);
         vec = true;
       }
     }
@@ -670,9 +673,10 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
   H->n_inst = n_inst;
   H->prec = params[0].precision;
   H->lattice = params[0].lattice;
-  // the vector moments kernel serves D2Q9 leaky-dielectric handles in FP32,
-  // FP16S and FP64
-  H->vec_moments = H->lattice == LBM_LATTICE_D2Q9 && H->prec != LBM_PREC_TANGENT;
+  // the vector moments kernel serves leaky-dielectric handles: D2Q9 in FP32,
+  // FP16S and FP64, D3Q15 in FP32 and FP16S (60 vectors of doubles would spill)
+  H->vec_moments = H->prec != LBM_PREC_TANGENT &&
+                   (H->lattice == LBM_LATTICE_D2Q9 || H->prec != LBM_PREC_FP64);
   for (int i = 0; i < n_inst; ++i)
     if (params[i].charge_model != LBM_CHARGE_LEAKY) H->vec_moments = false;
   H->stream = (hipStream_t)hip_stream;
@@ -891,7 +895,7 @@ void step_record(lbm_ehd_s *W, char *slot) {
   const int K = W->sub_max, pc = (int)(W->steps & 1);
   const Rec<T> rc = rec_slot<T>(slot, N);
   if (W->vec_moments)
-    k_moments4<T, T><<<dim3(W->plan.total_blocks4), block, 0, W->stream>>>(W->d_insts, W->d_b2i4, pc, rc);
+    k_moments4<D2Q9, T, T><<<dim3(W->plan.total_blocks4), block, 0, W->stream>>>(W->d_insts, W->d_b2i4, pc, rc);
   else
     k_moments<D2Q9, T, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, pc, rc);
   k_pre<D2Q9, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, rc);

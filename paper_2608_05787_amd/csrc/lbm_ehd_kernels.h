@@ -434,59 +434,62 @@ __global__ __launch_bounds__(NT) void k_moments(const Inst *__restrict__ insts, 
   (gbl((T *)I.lsum))[n] = b;
 }
 
-// a1 four nodes per thread (D2Q9, leaky-dielectric charge model): the same
-// sums as k_moments, read and written as 4-wide vectors (16-byte loads and
-// stores in FP32, 8-byte half loads in FP16S): a quarter of the memory
-// instructions of the node-per-thread form for a kernel that only streams.
-// Plane strides and block bases are multiples of 4 nodes; the last vector
-// of an instance may run into the plane's padding, which no kernel reads.
-//   b2i4: (instance, block of 4 NT nodes within it) per launched block.
-constexpr int M4 = 4 * NT;  // nodes per block of k_moments4
-template <typename T> struct Vec4 {
-  typedef T v __attribute__((ext_vector_type(4)));
+// a1 four nodes per thread (leaky-dielectric charge model): the same
+// sums as k_moments, read and written as vectors of W nodes (16-byte loads
+// and stores for four FP32 nodes, 8-byte half loads in FP16S): a quarter (or
+// half) of the memory instructions of the node-per-thread form for a kernel
+// that only streams.  Plane strides and block bases are multiples of 4
+// nodes; the last vector of an instance may run into the plane's padding,
+// which no kernel reads.
+//   b2i4: (instance, block of 4 NT nodes within it) per table entry; with
+//         W = 2 two consecutive launched blocks share an entry, one half each
+//         (D3Q15 in FP32: 60 vectors of four floats would fill every VGPR).
+constexpr int M4 = 4 * NT;  // nodes per block-table entry of k_moments4
+template <typename T, int W> struct VecN {
+  typedef T v __attribute__((ext_vector_type(W)));
 };
 //   rc: when rc.phi is set, the order parameters also go there (recording runs).
-template <typename T, typename S>
+template <class L, typename T, typename S, int W = 4>
 __global__ __launch_bounds__(NT) void k_moments4(const Inst *__restrict__ insts, const int2 *__restrict__ b2i4,
                                                  int pc, Rec<T> rc = Rec<T>{}) {
-  constexpr int Q = D2Q9::Q;
-  using V = typename Vec4<T>::v;
+  static_assert(W == 4 || W == 2, "four or two nodes per thread");
+  constexpr int Q = L::Q, PER = 4 / W;  // launched blocks per table entry
+  using V = typename VecN<T, W>::v;
   using GV = const V __attribute__((address_space(1))) *;
   using GVW = V __attribute__((address_space(1))) *;
-  const int2 t = b2i4[blockIdx.x];
+  const int2 t = b2i4[blockIdx.x / PER];
+  const int sub = (int)(blockIdx.x % PER);
   const Inst &I = insts[t.x];
-  if (t.y == 0 && threadIdx.x == 0) {
+  if (t.y == 0 && sub == 0 && threadIdx.x == 0) {
     I.ctl->done = 0;
     I.ctl->k_used = 0;
   }
-  const int base = t.y * M4 + 4 * (int)threadIdx.x;
+  const int base = t.y * M4 + sub * (W * NT) + W * (int)threadIdx.x;
   if (base >= I.nn) return;
-  const size_t b4 = (size_t)base / 4, N4 = (size_t)I.N / 4;
+  const size_t bv = (size_t)base / W, NV = (size_t)I.N / W;
   const int fb = fbuf(I, pc);
   V fv[3][Q], lv[Q];
   if constexpr (std::is_same<S, __half>::value) {
-    // 4 half words per vector: f^i_0 in its FP32 plane, the rest as stored deviations
-    typedef unsigned short hv __attribute__((ext_vector_type(4)));
+    // W half words per vector: f^i_0 in its FP32 plane, the rest as stored deviations
+    typedef unsigned short hv __attribute__((ext_vector_type(W)));
     using GH = const hv __attribute__((address_space(1))) *;
     const GH f = (GH)I.f[fb], l = (GH)I.l[pc];
     const GV f0 = (GV)I.f0[fb];
     auto cvt = [](hv w, float sc) {
       V r;
-      r.x = __half2float(__ushort_as_half(w.x)) / sc;
-      r.y = __half2float(__ushort_as_half(w.y)) / sc;
-      r.z = __half2float(__ushort_as_half(w.z)) / sc;
-      r.w = __half2float(__ushort_as_half(w.w)) / sc;
+#pragma unroll
+      for (int c = 0; c < W; ++c) r[c] = __half2float(__ushort_as_half(w[c])) / sc;
       return r;
     };
     hv fw[3][Q], lw[Q];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 1; j < Q; ++j) fw[i][j] = f[(size_t)(i * Q + j) * N4 + b4];
+      for (int j = 1; j < Q; ++j) fw[i][j] = f[(size_t)(i * Q + j) * NV + bv];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) fv[i][0] = f0[(size_t)i * N4 + b4];
+    for (int i = 0; i < 3; ++i) fv[i][0] = f0[(size_t)i * NV + bv];
 #pragma unroll
-    for (int j = 0; j < Q; ++j) lw[j] = l[(size_t)j * N4 + b4];
+    for (int j = 0; j < Q; ++j) lw[j] = l[(size_t)j * NV + bv];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -498,9 +501,9 @@ __global__ __launch_bounds__(NT) void k_moments4(const Inst *__restrict__ insts,
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 0; j < Q; ++j) fv[i][j] = f[(size_t)(i * Q + j) * N4 + b4];
+      for (int j = 0; j < Q; ++j) fv[i][j] = f[(size_t)(i * Q + j) * NV + bv];
 #pragma unroll
-    for (int j = 0; j < Q; ++j) lv[j] = l[(size_t)j * N4 + b4];
+    for (int j = 0; j < Q; ++j) lv[j] = l[(size_t)j * NV + bv];
   }
   constexpr bool split = PopIO<S, T>::split;
   const GVW phi = (GVW)I.phi;
@@ -509,13 +512,13 @@ __global__ __launch_bounds__(NT) void k_moments4(const Inst *__restrict__ insts,
     V a = split ? fv[i][0] : V(T(0));
 #pragma unroll
     for (int j = split ? 1 : 0; j < Q; ++j) a += fv[i][j];
-    phi[(size_t)i * N4 + b4] = a;
-    if (rc.phi) ((V *)rc.phi)[(size_t)i * N4 + b4] = a;
+    phi[(size_t)i * NV + bv] = a;
+    if (rc.phi) ((V *)rc.phi)[(size_t)i * NV + bv] = a;
   }
   V b = V(T(0));
 #pragma unroll
   for (int j = 0; j < Q; ++j) b += lv[j];
-  ((GVW)I.lsum)[b4] = b;
+  ((GVW)I.lsum)[bv] = b;
 }
 
 // a2 + a3: permittivity/conductivity stencils (Eq. 33 on the eps and sigma
