@@ -521,8 +521,9 @@ int do_step(lbm_ehd_s *H, int64_t n) {
     bool vec = false;
     if constexpr ((std::is_same<Lat, D2Q9>::value && sizeof(T) <= 8) || sizeof(T) == 4) {
       if (H->vec_moments) {
-        // D3Q15 in FP32: two nodes per thread (four would need 240 VGPRs of data)
-        constexpr int W = std::is_same<Lat, D3Q15>::value && std::is_same<S, float>::value ? 2 : 4;
+        // D3Q15 in FP32 and D2Q9 in FP64: two nodes per thread (four would need
+        // 240 or 288 VGPRs of data)
+        constexpr int W = (std::is_same<Lat, D3Q15>::value && std::is_same<S, float>::value) || sizeof(T) == 8 ? 2 : 4;
         k_moments4<Lat, T, S, W>
             <<<dim3(H->plan.total_blocks4 * (4 / W)), block, 0, H->stream>>>(H->d_insts, H->d_b2i4, pc);
         vec = true;
@@ -894,8 +895,10 @@ void step_record(lbm_ehd_s *W, char *slot) {
   const size_t N = (size_t)W->hinst[0].N;
   const int K = W->sub_max, pc = (int)(W->steps & 1);
   const Rec<T> rc = rec_slot<T>(slot, N);
+  constexpr int MW = sizeof(T) == 8 ? 2 : 4;  // nodes per thread, as in the plain step
   if (W->vec_moments)
-    k_moments4<D2Q9, T, T><<<dim3(W->plan.total_blocks4), block, 0, W->stream>>>(W->d_insts, W->d_b2i4, pc, rc);
+    k_moments4<D2Q9, T, T, MW>
+        <<<dim3(W->plan.total_blocks4 * (4 / MW)), block, 0, W->stream>>>(W->d_insts, W->d_b2i4, pc, rc);
   else
     k_moments<D2Q9, T, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, pc, rc);
   k_pre<D2Q9, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, rc);
