@@ -56,13 +56,29 @@ class _Params(ctypes.Structure):
     ]
 
 
-_lib = None
+_libs = {}
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        lib = ctypes.CDLL(build())
+def compile_variant(src_text: str, out_path: str) -> str:
+    """Compile a variant of the oracle source (used only by the tests that
+    check a pin rejects a planted mistake) into out_path."""
+    src = out_path + ".c"
+    with open(src, "w") as f:
+        f.write(src_text)
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-std=c99", "-w", "-shared", "-fPIC",
+                           "-o", out_path, src, "-lm"])
+    return out_path
+
+
+def source_text() -> str:
+    with open(_SRC) as f:
+        return f.read()
+
+
+def _load(path=None):
+    key = path or _LIB
+    if key not in _libs:
+        lib = ctypes.CDLL(path or build())
         dp = ctypes.POINTER(ctypes.c_double)
         lib.or_create.restype = ctypes.c_void_p
         lib.or_create.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, dp, dp]
@@ -74,8 +90,8 @@ def _load():
         lib.or_stencil.argtypes = [ctypes.POINTER(_Params), dp, dp, dp]
         lib.or_sizeof_params.restype = ctypes.c_int
         assert lib.or_sizeof_params() == ctypes.sizeof(_Params)
-        _lib = lib
-    return _lib
+        _libs[key] = lib
+    return _libs[key]
 
 
 def _ptr(a):
@@ -136,8 +152,8 @@ class Oracle:
     (n_+, n_-).
     """
 
-    def __init__(self, cfg: dict, init: dict):
-        lib = _load()
+    def __init__(self, cfg: dict, init: dict, lib_path=None):
+        lib = self._lib = _load(lib_path)
         self.nx, self.ny = int(cfg["nx"]), int(cfg["ny"])
         self._p = _params(cfg)
         shp, self.dim, self.q = _geometry(cfg)
@@ -160,16 +176,16 @@ class Oracle:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and _lib is not None:
-            _lib.or_free(h)
+        if h is not None and getattr(self, "_lib", None) is not None:
+            self._lib.or_free(h)
             self._h = None
 
     def step(self, n: int = 1):
-        _load().or_step(self._h, int(n))
+        self._lib.or_step(self._h, int(n))
 
     def field(self, name: str) -> np.ndarray:
         out = np.empty(self.shape, np.float64)
-        rc = _load().or_field(self._h, FIELDS.index(name), _ptr(out))
+        rc = self._lib.or_field(self._h, FIELDS.index(name), _ptr(out))
         assert rc == 0
         return out
 
@@ -181,12 +197,12 @@ class Oracle:
         if fam == "l":
             mult = self.nl
         out = np.empty((mult * self.q,) + self.shape, np.float64)
-        assert _load().or_pops(self._h, idx, _ptr(out)) == 0
+        assert self._lib.or_pops(self._h, idx, _ptr(out)) == 0
         return out
 
     def scalars(self) -> dict:
         out = np.zeros(9, np.float64)
-        _load().or_scalars(self._h, _ptr(out))
+        self._lib.or_scalars(self._h, _ptr(out))
         return {"steps": int(out[0]), "k_used": int(out[1]), "residual": out[2],
                 "lambda": tuple(out[3:6]), "m0": out[6], "alpha": out[7], "tau_h": out[8]}
 

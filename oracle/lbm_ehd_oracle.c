@@ -42,7 +42,12 @@
  *       tol; sub_min == sub_max or tol <= 0 runs a fixed count.
  *   R14 the reference permittivity of the h equation is that of one chosen
  *       (bulk) phase: eps_ref = eps[eps_ref_phase], tau_h = 1/2 + eps_ref/cs2.
- *   R15 a uniform applied field E_ext is added to -grad(potential).
+ *   R15 a uniform applied field E_ext is an imposed mean gradient: the
+ *       potential is psi = psi' - E_ext . x with psi' periodic (the h
+ *       populations carry psi'); Eq. (42) holds for the full psi, so the
+ *       eps_hat source of Eq. (43) and the gradient of Eq. (45) are those of
+ *       psi, and E = -grad(psi).  With uniform eps this is the plain sum
+ *       E = -grad(psi') + E_ext.
  *   R16 initial populations are the equilibria of the initial fields; the
  *       potential is first iterated with q0 (cold start).
  *   R20 D3Q15: the potential source weights are varpi_0 = 0 and 1/14 for
@@ -254,7 +259,12 @@ static void swap_ptr(double **a, double **b) {
 
 /* ------------------------------------------------------ potential (h) LB */
 
-/* Potential and its gradient from the local h moments, Eq. (45). */
+/* Potential and the gradient of the full potential from the local h
+ * moments, Eq. (45).  The populations carry the periodic part psi' of the
+ * potential psi = psi' - E_ext . x (R15); the eps_hat source of Eq. (43)
+ * carries eps_hat grad(psi), so the first moment is
+ * -(cs2 tau_h) grad(psi') - eps_hat grad(psi), which gives
+ * grad(psi) = -(m + cs2 tau_h E_ext) / (eps_hat + cs2 tau_h). */
 static void h_moments(const or_state *s, int n, double epshat, double *pot, double *g) {
   const lattice *L = s->L;
   const int N = s->N;
@@ -264,7 +274,7 @@ static void h_moments(const or_state *s, int n, double epshat, double *pot, doub
     for (int d = 0; d < L->D; ++d) m[d] += L->c[j][d] * s->h[j * N + n];
   *pot = s0 / (1.0 - L->w[0]);
   const double den = epshat + CS2 * s->tau_h;
-  for (int d = 0; d < L->D; ++d) g[d] = -m[d] / den;
+  for (int d = 0; d < L->D; ++d) g[d] = -(m[d] + CS2 * s->tau_h * s->Eext[d]) / den;
 }
 
 static void eval_potential(or_state *s, double *dst) {
@@ -321,7 +331,7 @@ static double rel_change(or_state *s, const double *a, const double *b) {
 
 /* Sub-iteration loop with the stopping rule R13.  On return psi holds the
  * potential of the final h, res_last the relative change of the potential over
- * the last iteration, and E = -grad(potential) + E_ext (Eq. 45, R15). */
+ * the last iteration, and E = -grad(psi) of the full potential (Eq. 45, R15). */
 static void solve_potential(or_state *s, int kmin, int kmax, double tol) {
   const int adaptive = (tol > 0.0) && (kmax > kmin);
   int kdone = kmax > 0 ? kmax : 0;
@@ -344,7 +354,7 @@ static void solve_potential(or_state *s, int kmin, int kmax, double tol) {
   for (int n = 0; n < N; ++n) {
     double pot, g[3];
     h_moments(s, n, s->eps[n] - s->eps_ref, &pot, g);
-    for (int d = 0; d < D; ++d) s->E[d * N + n] = -g[d] + s->Eext[d];
+    for (int d = 0; d < D; ++d) s->E[d * N + n] = -g[d];
   }
 }
 
