@@ -146,9 +146,11 @@ def cpu_baseline(p, init, budget_s):
 
 
 def field_errors(p, init, steps, precisions=("fp32", "fp16s")):
-    """Relative L2 error of each precision's fields against the FP64 instance
-    of the same kernels (the FP64 instance matches the FP64 CPU oracle to
-    ~1e-12), after the same fixed cold start and `steps` steps."""
+    """Error of each precision's fields against the FP64 instance of the same
+    kernels (the FP64 instance matches the FP64 CPU oracle to ~1e-12), after
+    the same fixed cold start and `steps` steps: relative L2 and element-wise
+    (max |a - b| / max |b|) per field, the Sec. 4.4 deformation factors and
+    the phase masses."""
     import torch
     from paper_2608_05787_amd import binding
     b = binding.Sim(p, init, precision="fp64")
@@ -161,10 +163,13 @@ def field_errors(p, init, steps, precisions=("fp32", "fp16s")):
         a = binding.Sim(p, init, precision=prec)
         a.step(steps)
         fa = a.fields()
-        out = {}
+        out, mx = {}, {}
         for k in ("phi1", "phi2", "phi3", "ux", "uy", "p", "psi", "Ex", "Ey", "q", "mu1", "mu2", "mu3"):
             nb = float(torch.linalg.norm(fb[k]))
             out[k] = float(torch.linalg.norm(fa[k] - fb[k])) / nb if nb > 0 else 0.0
+            mb = float(fb[k].abs().max())
+            mx[k] = float((fa[k] - fb[k]).abs().max()) / mb if mb > 0 else 0.0
+        out["max_norm"] = mx
         da = a.diagnostics()
         out["D_outer_abs"] = abs(da["D_outer"] - db["D_outer"])
         out["D_inner_abs"] = abs(da["D_inner"] - db["D_inner"])
@@ -176,12 +181,15 @@ def field_errors(p, init, steps, precisions=("fp32", "fp16s")):
     return res
 
 
-def batch_bench(n_inst, steps, sub, init_iters, graph_len=10):
+def batch_bench(n_inst, steps, sub, init_iters, graph_len=10, eager_steps=1000):
     """Parameter sweep (seeded sizes 128..512, field strengths, permittivity
     and conductivity ratios, half sheared): aggregate MLUPS of one batched
-    handle replaying a captured graph of `graph_len` steps, of the same handle
-    launched kernel by kernel, and of one handle per instance stepped in turn
-    (sequential per-instance launches), all FP32 on one side stream."""
+    handle replaying a captured graph of `graph_len` steps for `steps` steps,
+    of one handle per instance stepped in turn for the same steps (sequential
+    per-instance launches), and of the batched handle launched kernel by
+    kernel (`eager_steps`), all FP32 on one side stream.  After the graph and
+    sequential runs every instance of the batch must equal its separate run
+    bitwise (all population families)."""
     import torch
     from paper_2608_05787_amd import binding, inputs
     cases = inputs.batch_sweep(n_inst=n_inst, sub=(sub, sub, 0.0), init_iters=init_iters)
@@ -208,23 +216,61 @@ def batch_bench(n_inst, steps, sub, init_iters, graph_len=10):
     tune = batch.autotune(steps=10)
     log("batch autotune: config %d, ms/step per config %s" % (tune["config"],
                                                               ["%.3f" % v for v in tune["ms_per_step"]]))
-    ms_eager = timed(batch.step, steps)
     batch.graph(graph_len)
     ms_graph = timed(batch.step, steps)
-    del batch
+    log("batch graph: %d steps %.1f ms" % (steps, ms_graph))
     sims = [binding.Sim(c, i, precision="fp32", stream=stream) for c, i in zip(cfgs, inits)]
+    for sm in sims:
+        sm.set_tuning(tune["config"])
 
     def seq(n):
         for _ in range(n):
             for sm in sims:
                 sm.step(1)
     ms_seq = timed(seq, steps)
+    log("sequential: %d steps %.1f ms" % (steps, ms_seq))
+    equal = all(torch.equal(batch.populations(fam, inst=i), sm.populations(fam))
+                for i, sm in enumerate(sims) for fam in "fglh")
+    d_batch = [batch.diagnostics(i) for i in range(n_inst)]
     del sims
-    mlups = lambda ms: round(nodes * steps / (ms * 1e-3) / 1e6, 1)
+    batch.graph(0)
+    ms_eager = timed(batch.step, eager_steps)
+    del batch
+    mlups = lambda ms, n: round(nodes * n / (ms * 1e-3) / 1e6, 1)
     return {"instances": n_inst, "nodes": nodes, "steps": steps, "potential_subiterations": sub,
-            "graph_steps": graph_len, "mlups_graph": mlups(ms_graph), "mlups_batched_eager": mlups(ms_eager),
-            "mlups_sequential": mlups(ms_seq), "speedup_graph_vs_sequential": round(ms_seq / ms_graph, 2),
+            "graph_steps": graph_len, "mlups_graph": mlups(ms_graph, steps),
+            "mlups_batched_eager": mlups(ms_eager, eager_steps), "eager_steps": eager_steps,
+            "mlups_sequential": mlups(ms_seq, steps), "speedup_graph_vs_sequential": round(ms_seq / ms_graph, 2),
+            "instances_equal_separate_runs_bitwise": equal,
+            "max_sum_dev_worst": max(d["max_sum_dev"] for d in d_batch),
+            "nonfinite_total": sum(d["nonfinite"] for d in d_batch),
             "tuning": tune}
+
+
+def adaptive_bench(p, init, steps, warmup, tol, kmax=64):
+    """The headline workload with residual-controlled potential
+    sub-iterations (stop once the relative change of the potential over an
+    iteration is below tol): mean sub-iterations per step and MLUPS at that
+    count (one launch and one control pass per sub-iteration)."""
+    import torch
+    from paper_2608_05787_amd import binding
+    q = dict(p, sub_min=1, sub_max=kmax, sub_tol=tol)
+    sim = binding.Sim(q, init, precision="fp32")
+    sim.step(warmup)
+    k0 = sim.scalars()["k_total"]
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    sim.step(steps)
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    k1 = sim.scalars()["k_total"]
+    d = sim.diagnostics()
+    nodes = p["nx"] * p["ny"]
+    return {"sub_tol": tol, "sub_max": kmax, "steps": steps, "mean_k": (k1 - k0) / steps,
+            "mlups": round(nodes * steps / (ms * 1e-3) / 1e6, 1), "ms_per_step": ms / steps,
+            "last_residual": d["residual"], "status": d["status"]}
 
 
 def d3q15_bench(n, steps, warmup, sub, init_iters, profile_steps):
@@ -339,7 +385,9 @@ def main():
     ap.add_argument("--error-steps", type=int, default=500)
     ap.add_argument("--init-iters", type=int, default=4000, help="cold-start potential iterations")
     ap.add_argument("--batch-instances", type=int, default=64, help="0 skips the parameter-sweep leg")
-    ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--batch-steps", type=int, default=10000)
+    ap.add_argument("--adaptive-tol", type=float, default=1e-7,
+                    help="residual tolerance of the residual-controlled leg (0 skips it)")
     ap.add_argument("--grad-steps", type=int, default=5000, help="0 skips the gradient leg")
     ap.add_argument("--grad-every", type=int, default=250, help="checkpoint interval of the reverse sweep")
     ap.add_argument("--n3", type=int, default=128, help="edge of the D3Q15 box (0 skips the 3-D leg)")
@@ -409,34 +457,46 @@ def main():
     # potential launches of a step: one single launch when K is odd, then
     # LDS-tiled launches of four sub-iterations (tall tiles, 4-byte
     # arithmetic) and of two; K singles when the tuner chose single launches
-    cfg = tune["config"] if tune else 0
-
-    def launches(prec):
+    def launches(cfg):
+        """(launches of the LDS-tiled potential kernel, single launches) per
+        step: one single launch when K is odd, then four sub-iterations per
+        launch on tall tiles while four remain, then two; K singles when the
+        configuration asks for single launches."""
         if cfg & 2:
             return 0, args.sub
         n1, rest = args.sub % 2, args.sub - args.sub % 2
-        quads = rest // 4 if (cfg & 8) and prec != "fp64" else 0
+        quads = rest // 4 if cfg & 8 else 0
         return quads + (rest - 4 * quads) // 2, n1
 
-    step_bytes = {prec: sum(bytes_per_node(k, prec) * dict(zip(("poisson2", "poisson"), launches(prec))).get(k, 1)
-                            for k in BYTES_PER_NODE_FP32) for prec in ("fp32", "fp16s", "fp64")}
+    def step_bytes(prec, cfg):
+        return sum(bytes_per_node(k, prec) * dict(zip(("poisson2", "poisson"), launches(cfg))).get(k, 1)
+                   for k in BYTES_PER_NODE_FP32)
 
-    variants = {"fp32": {"mlups": round(mlups, 1), "ms_per_step": ms / args.steps,
-                         "bytes_per_node_update": step_bytes["fp32"]}}
+    cfg32 = tune["config"] if tune else 0
+    variants = {"fp32": {"mlups": round(mlups, 1), "ms_per_step": ms / args.steps, "launch_config": cfg32,
+                         "bytes_per_node_update": step_bytes("fp32", cfg32)}}
     errors = None
     if not args.no_variants:
         del sim
-        _, ms64, _, _, _ = run_gpu(p, init, "fp64", max(args.steps // 2, 1), args.warmup // 2, 0, args.tune_steps,
-                                   args.config)
+        _, ms64, _, _, t64 = run_gpu(p, init, "fp64", max(args.steps // 2, 1), args.warmup // 2, 0, args.tune_steps,
+                                     args.config)
+        cfg64 = t64["config"] if t64 else 0
         variants["fp64"] = {"mlups": round(nodes * max(args.steps // 2, 1) / (ms64 * 1e-3) / 1e6, 1),
-                            "ms_per_step": ms64 / max(args.steps // 2, 1),
-                            "bytes_per_node_update": step_bytes["fp64"]}
-        _, ms16, _, _, _ = run_gpu(p, init, "fp16s", args.steps, args.warmup, 0, args.tune_steps, args.config)
+                            "ms_per_step": ms64 / max(args.steps // 2, 1), "launch_config": cfg64,
+                            "bytes_per_node_update": step_bytes("fp64", cfg64)}
+        _, ms16, _, _, t16 = run_gpu(p, init, "fp16s", args.steps, args.warmup, 0, args.tune_steps, args.config)
+        cfg16 = t16["config"] if t16 else 0
         variants["fp16s"] = {"mlups": round(nodes * args.steps / (ms16 * 1e-3) / 1e6, 1),
-                             "ms_per_step": ms16 / args.steps,
-                             "bytes_per_node_update": step_bytes["fp16s"]}
+                             "ms_per_step": ms16 / args.steps, "launch_config": cfg16,
+                             "bytes_per_node_update": step_bytes("fp16s", cfg16)}
         log("field errors FP32 / FP16S vs FP64 after %d steps" % args.error_steps)
         errors = field_errors(p, init, args.error_steps)
+
+    adaptive = None
+    if args.adaptive_tol > 0 and not args.no_variants:
+        log("residual-controlled potential sub-iterations, tol %g" % args.adaptive_tol)
+        adaptive = adaptive_bench(p, init, max(args.steps // 4, 10), args.warmup, args.adaptive_tol)
+        log("mean K %.2f at %.1f MLUPS" % (adaptive["mean_k"], adaptive["mlups"]))
 
     batch = None
     if args.batch_instances > 0 and not args.no_variants:
@@ -467,12 +527,14 @@ def main():
         "config": {"workload": "field compound drop %dx%d (electrodes, Ca_e 0.2, eps ratios 2/0.5, "
                                "sigma ratios 3/0.3, radii 80/60)" % (args.n, args.n),
                    "nodes": nodes, "potential_subiterations": k_mean, "precision": "fp32",
-                   "algorithmic_bytes_per_node_update": step_bytes["fp32"]},
+                   "algorithmic_bytes_per_node_update": step_bytes("fp32", cfg32),
+                   "mean_k_residual_controlled": adaptive["mean_k"] if adaptive else None},
         "tuning": tune,
         "roofline": roofline,
         "kernels": kernels,
         "variants": variants,
-        "rel_l2_vs_fp64": errors,
+        "errors_vs_fp64": errors,
+        "residual_controlled": adaptive,
         "batch_sweep": batch,
         "gradient": grad,
         "d3q15": d3,

@@ -16,8 +16,15 @@
  *  - Device memory is owned by the caller.  The library keeps non-owning
  *    pointers into the caller's workspace and never allocates device memory.
  *  - All device work of a handle is ordered on the HIP stream given at
- *    create time.  Only lbm_ehd_create, lbm_ehd_diagnostics, lbm_ehd_scalars, lbm_ehd_restore and
- *    lbm_ehd_profile_end synchronise that stream.
+ *    create time.  Only lbm_ehd_create, lbm_ehd_diagnostics, lbm_ehd_status,
+ *    lbm_ehd_scalars, lbm_ehd_restore and lbm_ehd_profile_end synchronise
+ *    that stream.
+ *  - Conditions the device detects while stepping (a non-finite velocity or
+ *    pressure; a residual-controlled potential loop that reached sub_max)
+ *    are latched in a per-instance status word and returned by the next
+ *    lbm_ehd_diagnostics or lbm_ehd_status call: LBM_EHD_EDIVERGED stays
+ *    latched, LBM_EHD_ENOCONV (a warning: the state is valid) is cleared once
+ *    returned.
  *  - One handle is used by one host thread at a time.
  *  - Layout of every field plane: row-major [ny][nx], x fastest.
  */
@@ -78,7 +85,12 @@ enum { LBM_POP_F = 0, LBM_POP_G = 1, LBM_POP_L = 2, LBM_POP_H = 3 };
  *  wall_phi      Dirichlet electric potential of the walls (electrodes), by
  *                anti-bounce-back of the potential populations.
  *  wall_q_mode   0: charge no-flux (bounce-back); 1: Dirichlet charge wall_q.
- *  E_ext         uniform applied field added to -grad(potential).
+ *  E_ext         uniform applied field: an imposed mean gradient of the
+ *                potential, psi = psi' - E_ext . x with psi' periodic
+ *                (carried by the potential populations); the permittivity
+ *                source of Eq. (43) and the gradient of Eq. (45) are those
+ *                of the full psi, so Eq. (42) holds for it, and
+ *                E = -grad(psi).
  *  gamma12..23   pair surface tensions -> lambda_i of Eq. (9); each lambda_i
  *                must be > 0.
  *  width         interface thickness D of Eq. (7).
@@ -181,9 +193,21 @@ int lbm_ehd_create(const lbm_ehd_params *params, int32_t n_inst, const lbm_ehd_i
                    void *dev_workspace, void *hip_stream, lbm_ehd_t *out);
 
 /* Enqueue n >= 0 coupled time steps of every instance (asynchronous).
+ * One step is the scheme of Sec. 3 in this order: order-parameter moments
+ * (text after Eq. 36) and properties (Eqs. 29-30); the charge of Eq. (50)'s
+ * text with the source R of Eq. (47) on the previous step's field; the
+ * potential sub-iterations (Eqs. 42-45; fixed count or residual-controlled,
+ * see sub_min/sub_max/sub_tol); the field and the chemical potentials
+ * (Eqs. 45, 20); the force (Eq. 27b) and flow moments (Eq. 41); the
+ * collisions of the three order-parameter families (Eqs. 34-36 with the
+ * mobility of Eq. 28), the flow family (Eqs. 37-40) and the charge family
+ * (Eqs. 48-50), each streamed with the wall rules described at
+ * lbm_ehd_params; Eq. (33) gives every gradient and Laplacian.
  * With a captured graph (lbm_ehd_graph) whole blocks of steps are replayed
  * with one hipGraphLaunch each; remaining steps are launched kernel by
- * kernel.  Results are identical either way. */
+ * kernel.  Results are identical either way.  Errors: EINVAL for n < 0;
+ * EHIP if a launch fails; device-detected conditions are latched (see the
+ * conventions above). */
 int lbm_ehd_step(lbm_ehd_t h, int64_t n);
 
 /* Capture steps_per_graph (even, >= 2) coupled steps of every instance into
@@ -195,7 +219,13 @@ int lbm_ehd_graph(lbm_ehd_t h, int32_t steps_per_graph);
 /* Write the selected fields of instance `inst` into caller device memory
  * dev_dst as consecutive planes [popcount(mask)][ny][nx] in ascending bit
  * order, converted to dtype (LBM_DTYPE_F32 or LBM_DTYPE_F64; for a tangent
- * handle LBM_DTYPE_TANGENT_F64 gives the derivatives).  Async. */
+ * handle LBM_DTYPE_TANGENT_F64 gives the derivatives).  Async.
+ * The fields are those the last step formed: phi_i (zeroth moments, text
+ * after Eq. 36), rho (Eq. 29), u and p (Eq. 41), the potential and the field
+ * E = -grad(psi) (Eq. 45 with the applied field, see E_ext), q and R (Eq. 47
+ * and the text after Eq. 50), mu_i (Eq. 20), eps (Eq. 30).  dev_dst must
+ * hold popcount(mask) * nodes values of the dtype; EINVAL for an instance
+ * out of range, an empty mask or bits the handle does not have. */
 int lbm_ehd_fields(lbm_ehd_t h, int32_t inst, uint32_t mask, void *dev_dst, int32_t dtype);
 
 /* Pre-collision populations of the current level of instance `inst`,
@@ -205,18 +235,36 @@ int lbm_ehd_fields(lbm_ehd_t h, int32_t inst, uint32_t mask, void *dev_dst, int3
  * its family's power-of-two scale; f^i_0 from its FP32 plane).  Async. */
 int lbm_ehd_populations(lbm_ehd_t h, int32_t inst, int32_t family, void *dev_dst, int32_t dtype);
 
-/* Diagnostics of instance `inst` from the fields of the last step, FP64:
- * out[0..2] sum_x phi_i, out[3] sum_x q, out[4] max |phi1+phi2+phi3-1|,
- * out[5] relative potential change of the last sub-iteration, out[6]
- * sub-iterations of the last step, out[7] non-finite population count,
- * out[8] deformation of the outer drop (indicator 1 - phi1), out[9] of the
- * inner drop (indicator phi3), both (sqrt(I_par) - sqrt(I_perp)) /
- * (sqrt(I_par) + sqrt(I_perp)) with second moments parallel (y) and
- * perpendicular (x) to the electrode field; the indicator w enters as
- * w * s(w), s = 0 below 0.005, 1 above 0.02, cubic smoothstep between (the
- * far-field tail is dropped).  Synchronises.  Returns
- * LBM_EHD_EDIVERGED if out[7] > 0. */
-int lbm_ehd_diagnostics(lbm_ehd_t h, int32_t inst, double out[10]);
+/* Diagnostics of instance `inst` from the fields of the last step, FP64
+ * reductions in a fixed order:
+ *  out[0..2] sum_x phi_i (conserved, Eq. 5 and the CH equations Eq. 27c),
+ *  out[3] sum_x q (Eq. 17), out[4] max |phi1+phi2+phi3-1| (Eq. 5),
+ *  out[5] relative potential change of the last sub-iteration, out[6]
+ *  sub-iterations of the last step, out[7] non-finite population count;
+ *  out[8], out[9]: the deformation factor of Sec. 4.4,
+ *  D = (r_par - r_perp) / (r_par + r_perp), of the outer drop (indicator
+ *  w = 1 - phi1) and the inner drop (w = phi3), with the field along y:
+ *  r_par is half the distance between the w = 1/2 crossings on the y line
+ *  through the indicator's centroid (weights max(w, 0)), r_perp the same on
+ *  the x line; w on a line between nodes is interpolated linearly, the
+ *  crossings linearly between the last node with w >= 1/2 and the next,
+ *  scanning outward from the node nearest the centroid; nan where a line
+ *  has no crossing (a wall first, or w >= 1/2 throughout);
+ *  out[10], out[11]: the second-moment form (sqrt(I_par) - sqrt(I_perp)) /
+ *  (sqrt(I_par) + sqrt(I_perp)) of the same indicators entered as
+ *  w * s(w), s = 0 below 0.005, 1 above 0.02, cubic smoothstep between;
+ *  out[12..15]: r_par, r_perp of the outer drop, then of the inner.
+ * Synchronises.  Returns LBM_EHD_EDIVERGED if out[7] > 0 or a non-finite
+ * value was latched, else LBM_EHD_ENOCONV if a residual-controlled potential
+ * loop reached sub_max since the last report (the outputs are valid). */
+int lbm_ehd_diagnostics(lbm_ehd_t h, int32_t inst, double out[16]);
+
+/* Latched status of every instance (see the conventions above), without a
+ * reduction pass: synchronises, ORs the instances' status bits into *flags
+ * (may be NULL; bit 1: non-finite velocity or pressure formed, bit 2: a
+ * potential loop reached sub_max) and returns LBM_EHD_EDIVERGED,
+ * LBM_EHD_ENOCONV or LBM_EHD_OK.  Reporting clears bit 2. */
+int lbm_ehd_status(lbm_ehd_t h, int32_t *flags);
 
 /* Host-side counters: out[0] steps taken, out[1] total potential
  * sub-iterations run in those steps (summed over instances), out[2]

@@ -20,7 +20,9 @@ FIELDS = ["phi1", "phi2", "phi3", "rho", "ux", "uy", "p", "psi", "Ex", "Ey",
 PRECISION = {"fp32": 0, "fp16s": 1, "fp64": 2, "tangent": 3}
 FAMILY = {"f": (0, 3), "g": (1, 1), "l": (2, 1), "h": (3, 1)}  # id, planes per lattice velocity
 DIAG_KEYS = ["mass1", "mass2", "mass3", "charge", "max_sum_dev", "residual", "k_sub",
-             "nonfinite", "D_outer", "D_inner"]
+             "nonfinite", "D_outer", "D_inner", "D_outer_moment", "D_inner_moment",
+             "r_par_outer", "r_perp_outer", "r_par_inner", "r_perp_inner"]
+EDIVERGED, ENOCONV = -4, -5
 
 
 class LbmEhdError(RuntimeError):
@@ -57,7 +59,7 @@ class Init(ctypes.Structure):
 
 
 EXPORTS = ["lbm_ehd_adjoint_workspace_bytes", "lbm_ehd_workspace_bytes", "lbm_ehd_create", "lbm_ehd_step", "lbm_ehd_fields",
-           "lbm_ehd_populations", "lbm_ehd_diagnostics", "lbm_ehd_scalars",
+           "lbm_ehd_populations", "lbm_ehd_diagnostics", "lbm_ehd_status", "lbm_ehd_scalars",
            "lbm_ehd_checkpoint_bytes", "lbm_ehd_checkpoint", "lbm_ehd_restore",
            "lbm_ehd_adjoint", "lbm_ehd_record", "lbm_ehd_tangent_workspace_bytes", "lbm_ehd_tangent_gradient",
            "lbm_ehd_profile_begin", "lbm_ehd_profile_end", "lbm_ehd_graph",
@@ -85,6 +87,7 @@ def load():
     lib.lbm_ehd_fields.argtypes = [vp, ctypes.c_int32, ctypes.c_uint32, vp, ctypes.c_int32]
     lib.lbm_ehd_populations.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int32]
     lib.lbm_ehd_diagnostics.argtypes = [vp, ctypes.c_int32, _dp]
+    lib.lbm_ehd_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.lbm_ehd_scalars.argtypes = [vp, _dp]
     lib.lbm_ehd_checkpoint_bytes.argtypes = [vp, ctypes.POINTER(sz)]
     lib.lbm_ehd_checkpoint.argtypes = [vp, vp]
@@ -256,13 +259,25 @@ class Sim:
         return self._handoff(out)
 
     def diagnostics(self, inst: int = 0) -> dict:
-        out = (ctypes.c_double * 10)()
+        """The 16 outputs of lbm_ehd_diagnostics by name, plus "status": its
+        return code (0, EDIVERGED or the warning ENOCONV; other codes
+        raise)."""
+        out = (ctypes.c_double * 16)()
         rc = load().lbm_ehd_diagnostics(self._h, inst, out)
         d = dict(zip(DIAG_KEYS, list(out)))
-        if rc not in (0, -4):
+        if rc not in (0, EDIVERGED, ENOCONV):
             self._check(rc, self._h)
         d["status"] = rc
         return d
+
+    def status(self):
+        """(return code, flags) of lbm_ehd_status: the latched conditions of
+        every instance (bit 1 non-finite, bit 2 potential cap reached)."""
+        flags = ctypes.c_int32()
+        rc = load().lbm_ehd_status(self._h, ctypes.byref(flags))
+        if rc not in (0, EDIVERGED, ENOCONV):
+            self._check(rc, self._h)
+        return rc, int(flags.value)
 
     def scalars(self) -> dict:
         out = (ctypes.c_double * 3)()

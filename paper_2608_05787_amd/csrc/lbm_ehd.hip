@@ -72,7 +72,7 @@ Layout layout_one(const lbm_ehd_params &p, size_t off) {
   L.part_mu = off;
   off = align_up(off + (size_t)L.nblk * 2 * sizeof(double));
   L.part_d = off;
-  off = align_up(off + (size_t)L.nblk * 16 * sizeof(double));
+  off = align_up(off + (size_t)L.nblk * DIAG_PART * sizeof(double));
   L.planes = off;
   for (int g = 0; g < N_GROUPS; ++g) off += align_up(group_planes(g, D, ion_planes(p)) * N * te);
   const size_t nl = p.charge_model == LBM_CHARGE_NERNST_PLANCK ? 2 : 1;  // families in l
@@ -167,6 +167,15 @@ template <typename T> void fill_phys(Phys<T> &P, const lbm_ehd_params &p) {
     P.wall_q[s] = (T)p.wall_q[s];
   }
   P.Eext[2] = (T)(p.lattice == LBM_LATTICE_D3Q15 ? p.E_ext_z : 0.0);
+  // reference potential of the potential populations' storage: linear
+  // between the electrodes (half-way walls at y = -1/2 and ny - 1/2)
+  const bool walls = p.bc_y == LBM_BC_WALL;
+  const double b = walls ? (p.wall_phi[1] - p.wall_phi[0]) / p.ny : 0.0;
+  const double a = walls ? p.wall_phi[0] + 0.5 * b : 0.0;
+  P.ref_a = (T)a;
+  P.ref_b = (T)b;
+  P.hwall[0] = (T)(p.wall_phi[0] - (a - 0.5 * b));
+  P.hwall[1] = (T)(p.wall_phi[1] - (a + b * (p.ny - 0.5)));
   P.ion_tau = (T)p.ion_tau;
   P.ion_beta = (T)p.ion_beta;
   P.ion_e = (T)p.ion_charge;
@@ -195,6 +204,7 @@ void fill_tangent(Phys<DualD> &T, const lbm_ehd_params &p) {
   cp(T.rho, v.rho, 3); cp(T.visc, v.visc, 3); cp(T.eps, v.eps, 3); cp(T.sig, v.sig, 3);
   cp(T.Eext, v.Eext, 3); cp(T.wall_u, v.wall_u, 2); cp(T.wall_phi, v.wall_phi, 2); cp(T.wall_q, v.wall_q, 2);
   T.ion_tau = v.ion_tau; T.ion_beta = v.ion_beta; T.ion_e = v.ion_e;
+  T.ref_a = v.ref_a; T.ref_b = v.ref_b; cp(T.hwall, v.hwall, 2);  // the reference stays fixed
   T.eps[1].d = p.eps[0] * p.dtheta[0];
   T.eps[2].d = p.eps[0] * p.dtheta[1];
   T.sig[1].d = p.sigma[0] * p.dtheta[2];
@@ -205,7 +215,7 @@ void fill_tangent(Phys<DualD> &T, const lbm_ehd_params &p) {
     const double s = p.dtheta[4] / E0;
     for (int k = 0; k < 2; ++k) {
       T.Eext[k].d = p.E_ext[k] * s;
-      if (p.bc_y == LBM_BC_WALL) T.wall_phi[k].d = (p.wall_phi[k] - mean) * s;
+      if (p.bc_y == LBM_BC_WALL) T.wall_phi[k].d = T.hwall[k].d = (p.wall_phi[k] - mean) * s;
     }
     T.Eext[2].d = v.Eext[2] * s;
   }
@@ -280,9 +290,12 @@ struct lbm_ehd_s {
   int tuning = 0;
   int n_t2 = 0;           // tiles in d_t2
   bool pairs() const { return !(tuning & LBM_TUNE_SINGLE_POTENTIAL); }
-  // the tall tile shape is built for 4-byte arithmetic (FP32, FP16S) only
+  // the tall tile shape exists for FP32, FP16S and FP64 arithmetic (in FP64
+  // its 147 KB of LDS leave one block per CU: slower than pairs, kept so the
+  // benchmarked tile logic can be checked against the oracle to rounding)
   bool tall() const {
-    return (tuning & LBM_TUNE_TALL_TILES) != 0 && (prec == LBM_PREC_FP32 || prec == LBM_PREC_FP16S);
+    return (tuning & LBM_TUNE_TALL_TILES) != 0 &&
+           (prec == LBM_PREC_FP32 || prec == LBM_PREC_FP16S || prec == LBM_PREC_FP64);
   }
   // tile table of shape s (0: 64 x 16, two sub-iterations; 1: 64 x 32, two;
   // 2: 64 x 32, four) in the block order in use
@@ -392,7 +405,7 @@ int enqueue_fixed_potential(lbm_ehd_s *H, int K) {
         k = 2;
       }
       // tall tiles: four sub-iterations per launch while four remain
-      if constexpr (sizeof(T) == 4) {
+      if constexpr (sizeof(T) <= 8) {
         if (H->tall())
           for (; k + 3 <= K; k += 4, ++L) {
             hipEvent_t e = H->prof_start(6);
@@ -404,7 +417,7 @@ int enqueue_fixed_potential(lbm_ehd_s *H, int K) {
       for (; k + 1 <= K; k += 2, ++L) {
         hipEvent_t e = H->prof_start(6);
         const int last = k + 1 == K ? 1 : 0;
-        if constexpr (sizeof(T) == 4) {
+        if constexpr (sizeof(T) <= 8) {
           if (H->tall())
             k_poisson2<T, 2><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, last);
           else
@@ -540,7 +553,7 @@ int do_step(lbm_ehd_s *H, int64_t n) {
         e = H->prof_start(2);
         k_poisson<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, k, K, 1, 0);
         H->prof_stop(e);
-        k_reduce_poisson<<<H->n_inst, block, 0, H->stream>>>(H->d_insts, k, H->sub_min, H->sub_tol);
+        k_reduce_poisson<<<H->n_inst, block, 0, H->stream>>>(H->d_insts, k, H->sub_min, H->sub_tol, K);
       }
     } else {
       hflip = enqueue_fixed_potential<Lat, T>(H, K) & 1;
@@ -568,6 +581,7 @@ int do_diag(lbm_ehd_s *H) {
   hipEvent_t e = H->prof_start(5);
   k_diag<Lat, T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, (int)(H->steps & 1));
   k_reduce_diag<<<H->n_inst, block, 0, H->stream>>>(H->d_insts);
+  k_contour<Lat, T><<<H->n_inst, block, 0, H->stream>>>(H->d_insts);
   H->prof_stop(e);
   HIPC(H, hipGetLastError());
   return LBM_EHD_OK;
@@ -909,7 +923,7 @@ void step_record(lbm_ehd_s *W, char *slot) {
     k = 2;
   }
   auto lev = [&](int i) { return rec_level<T>(slot, N, i); };
-  if constexpr (sizeof(T) == 4) {
+  if constexpr (sizeof(T) <= 8) {
     if (W->tall()) {
       // four sub-iterations per launch while four remain, then tall pairs
       for (; k + 3 <= K; k += 4, ++L)
@@ -943,10 +957,10 @@ void step_adjoint(lbm_ehd_s *W, char *slot, const AdjBufs<T> &ab, int &cur, int 
   k_adj_collide<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, rc, ab, cur);
   k_adj_mu<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, rc, ab, cur, hs, 1);
   // sub-iterations K, K-1, ... on LDS tiles: in fours on the tall tiles
-  // (4-byte arithmetic in that launch configuration), then in pairs, a
-  // single one last when K is odd
+  // (in that launch configuration), then in pairs, a single one last when K
+  // is odd
   int k = K;
-  if constexpr (sizeof(T) == 4)
+  if constexpr (sizeof(T) <= 8)
     if (W->tall())
       for (; k >= 4; k -= 4) {
         k_adj_poisson4<T><<<dim3(W->plan.total_tiles4), dim3(P2NT), 0, W->stream>>>(
@@ -1262,15 +1276,54 @@ int lbm_ehd_populations(lbm_ehd_t H, int32_t inst, int32_t family, void *dev_dst
   return LBM_EHD_OK;
 }
 
-int lbm_ehd_diagnostics(lbm_ehd_t H, int32_t inst, double out[10]) {
-  if (!H || inst < 0 || inst >= H->n_inst || !out) return LBM_EHD_EINVAL;
-  int rc = dispatch<DiagF>(H, H);
-  if (rc) return rc;
+// Read and report the latched status of instance i (stream synchronised):
+// EDIVERGED stays latched, ENOCONV is cleared once reported.
+static int take_status(lbm_ehd_t H, int i, int &bits) {
+  Ctl *dc = H->hinst[i].ctl;
+  HIPC(H, hipMemcpy(&bits, &dc->status, sizeof(int), hipMemcpyDeviceToHost));
+  if (bits & ST_NOCONV) {
+    const int keep = bits & ~ST_NOCONV;
+    HIPC(H, hipMemcpy(&dc->status, &keep, sizeof(int), hipMemcpyHostToDevice));
+  }
+  return LBM_EHD_OK;
+}
+
+// The diagnostics of instance inst after do_diag: synchronise, copy out,
+// report the latched status.
+static int finish_diag(lbm_ehd_t H, int32_t inst, double out[16]) {
+  int rc;
   Ctl c;
   HIPC(H, hipStreamSynchronize(H->stream));
   HIPC(H, hipMemcpy(&c, H->hinst[inst].ctl, sizeof c, hipMemcpyDeviceToHost));
-  for (int k = 0; k < 10; ++k) out[k] = c.diag[k];
-  if (out[7] > 0) return H->fail(LBM_EHD_EDIVERGED, "non-finite populations in instance %d", inst);
+  for (int k = 0; k < 16; ++k) out[k] = c.diag[k];
+  int bits = 0;
+  if ((rc = take_status(H, inst, bits))) return rc;
+  if (out[7] > 0 || (bits & ST_DIVERGED))
+    return H->fail(LBM_EHD_EDIVERGED, "non-finite values in instance %d", inst);
+  if (bits & ST_NOCONV)
+    return H->fail(LBM_EHD_ENOCONV, "instance %d: a potential loop reached sub_max without meeting sub_tol", inst);
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_diagnostics(lbm_ehd_t H, int32_t inst, double out[16]) {
+  if (!H || inst < 0 || inst >= H->n_inst || !out) return LBM_EHD_EINVAL;
+  int rc = dispatch<DiagF>(H, H);
+  if (rc) return rc;
+  return finish_diag(H, inst, out);
+}
+
+int lbm_ehd_status(lbm_ehd_t H, int32_t *flags) {
+  if (!H) return LBM_EHD_EINVAL;
+  HIPC(H, hipStreamSynchronize(H->stream));
+  int all = 0, rc;
+  for (int i = 0; i < H->n_inst; ++i) {
+    int bits = 0;
+    if ((rc = take_status(H, i, bits))) return rc;
+    all |= bits;
+  }
+  if (flags) *flags = all;
+  if (all & ST_DIVERGED) return H->fail(LBM_EHD_EDIVERGED, "non-finite velocity or pressure formed");
+  if (all & ST_NOCONV) return H->fail(LBM_EHD_ENOCONV, "a potential loop reached sub_max without meeting sub_tol");
   return LBM_EHD_OK;
 }
 
@@ -1312,8 +1365,8 @@ int lbm_ehd_tune(lbm_ehd_t H, int32_t steps, void *dev_scratch, double ms_per_st
   const bool pair_form = H->lattice == LBM_LATTICE_D2Q9 && !H->adaptive && H->prec != LBM_PREC_TANGENT;
   // the two collide load schedules differ for 4-byte arithmetic (FP32, FP16S)
   const bool sched_form = H->prec == LBM_PREC_FP32 || H->prec == LBM_PREC_FP16S;
-  // the tall tile shapes exist for 4-byte arithmetic
-  const bool tall_form = pair_form && sched_form;
+  // the tall tile shapes exist for FP32, FP16S and FP64
+  const bool tall_form = pair_form && (sched_form || H->prec == LBM_PREC_FP64);
   const int glen = H->glen;
   H->drop_graph();
   int rc = lbm_ehd_checkpoint(H, dev_scratch);
@@ -1447,7 +1500,7 @@ int lbm_ehd_tangent_gradient(lbm_ehd_t H, int64_t n_steps, const void *dev_seed,
     if (e == hipSuccess) e = hipMemcpy(&c, I.ctl, sizeof c, hipMemcpyDeviceToHost);
     lbm_ehd_destroy(T);
     if (e != hipSuccess) return H->fail(LBM_EHD_EHIP, "tangent gradient: %s", hipGetErrorString(e));
-    grad_theta[dir] = c.diag[10];
+    grad_theta[dir] = c.diag[22];
   }
   return LBM_EHD_OK;
 }

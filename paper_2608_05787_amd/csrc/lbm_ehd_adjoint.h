@@ -450,12 +450,11 @@ __global__ __launch_bounds__(NT) void k_adj_mu(const Inst *__restrict__ insts, c
     }
     ex_b += T(2) * Ex * e2_b;
     ey_b += T(2) * Ey * e2_b;
-    th[6] += (double)ex_b * ab.dEext[0] + (double)ey_b * ab.dEext[1];
-    // E = m / den + E_ext with m the first moment of the final h
+    // E = (m + (tau_h/3) E_ext) / den with m the first moment of the final h
     const T den = (rc.eps[n] - P.eps_ref) + P.tau_h / T(3);
-    const T mx = (Ex - P.Eext[0]) * den, my = (Ey - P.Eext[1]) * den;
     const T mx_b = ex_b / den, my_b = ey_b / den;
-    ab.eb[n] = -(ex_b * mx + ey_b * my) / (den * den);
+    th[6] += ((double)mx_b * ab.dEext[0] + (double)my_b * ab.dEext[1]) * (double)(P.tau_h / T(3));
+    ab.eb[n] = -(ex_b * Ex + ey_b * Ey) / den;
 #pragma unroll
     for (int j = 1; j < Q; ++j) hb[(size_t)j * N + n] = hb0[j] + (T(cx(j)) * mx_b + T(cy(j)) * my_b);
 #pragma unroll
@@ -467,12 +466,13 @@ __global__ __launch_bounds__(NT) void k_adj_mu(const Inst *__restrict__ insts, c
 // Local part of the adjoint of one potential sub-iteration at a node: vb
 // is the adjoint of the node's post-collision populations (already pulled
 // through the push), h its forward input; returns the adjoint of h and adds
-// to eps_hat-bar and q-bar.
+// to eps_hat-bar, q-bar and the applied field's adjoint ee_b (which enters
+// through grad(psi) = -(m + (tau_h/3) E_ext) iden).
 //   iden: 1 / (eps_hat + tau_h / 3), as the forward collision forms it.
 template <typename T>
 __device__ __forceinline__ void adj_poisson_local(const T (&vb)[Q], const T (&h)[Q], T eh, T iden, const Phys<T> &P,
-                                                  T (&hb)[Q], T &eh_b, T &q_b) {
-  T mx = 0, my = 0;
+                                                  T (&hb)[Q], T &eh_b, T &q_b, T (&ee_b)[2]) {
+  T mx = P.tau_h / T(3) * P.Eext[0], my = P.tau_h / T(3) * P.Eext[1];
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
     mx += T(cx(j)) * h[j];
@@ -490,17 +490,25 @@ __device__ __forceinline__ void adj_poisson_local(const T (&vb)[Q], const T (&h)
     eh_b -= c3 * (T(cx(j)) * gx + T(cy(j)) * gy);
     if (j) q_b += T(0.125) * vb[j];
   }
-  // g = -m iden with iden = 1 / (eps_hat + tau_h / 3): dg/d eps_hat = m iden^2
+  // g = -M iden, M = m + (tau_h/3) E_ext, iden = 1 / (eps_hat + tau_h / 3):
+  // dg/d eps_hat = M iden^2
   const T mx_b = -gx_b * iden, my_b = -gy_b * iden;
   eh_b += (gx_b * mx + gy_b * my) * (iden * iden);
+  ee_b[0] += mx_b * (P.tau_h / T(3));
+  ee_b[1] += my_b * (P.tau_h / T(3));
   const T ps_b = pot_b * (T(1) / (T(1) - wgt<T>(0)));
 #pragma unroll
   for (int j = 0; j < Q; ++j) hb[j] = vb[j] * (T(1) - ith) + T(cx(j)) * mx_b + T(cy(j)) * my_b + (j ? ps_b : T(0));
 }
 template <typename T>
 __device__ __forceinline__ void adj_poisson_local(const T (&vb)[Q], const T (&h)[Q], T eh, const Phys<T> &P,
-                                                  T (&hb)[Q], T &eh_b, T &q_b) {
-  adj_poisson_local(vb, h, eh, poisson_iden(eh, P), P, hb, eh_b, q_b);
+                                                  T (&hb)[Q], T &eh_b, T &q_b, T (&ee_b)[2]) {
+  adj_poisson_local(vb, h, eh, poisson_iden(eh, P), P, hb, eh_b, q_b, ee_b);
+}
+// Whether an instance has an applied field (its sub-iterations then carry a
+// d/d E0 term at every node, not only at the electrodes).
+template <typename T> __device__ __forceinline__ bool has_eext(const Phys<T> &P) {
+  return P.Eext[0] != T(0) || P.Eext[1] != T(0);
 }
 
 // Adjoint of one potential sub-iteration (Eqs. 43-45 with anti-bounce-back
@@ -535,18 +543,21 @@ __global__ __launch_bounds__(NT) void k_adj_poisson(const Inst *__restrict__ ins
         th[6] += 2.0 * (double)(wgt<T>(j) * a) * ab.dwall[top ? 1 : 0];
       }
     }
-    T h[Q], hb[Q], eh_b = 0, q_b = 0;
+    T h[Q], hb[Q], eh_b = 0, q_b = 0, ee_b[2] = {T(0), T(0)};
 #pragma unroll
     for (int j = 0; j < Q; ++j) h[j] = h_in[(size_t)j * N + n];
-    adj_poisson_local(vb, h, eps[n] - P.eps_ref, P, hb, eh_b, q_b);
+    adj_poisson_local(vb, h, eps[n] - P.eps_ref, P, hb, eh_b, q_b, ee_b);
+    th[6] += (double)ee_b[0] * ab.dEext[0] + (double)ee_b[1] * ab.dEext[1];
     T *Hd = ab.hb[src ^ 1];
 #pragma unroll
     for (int j = 0; j < Q; ++j) Hd[(size_t)j * N + n] = hb[j];
     ab.eb[n] += eh_b;
     qb[n] += q_b;
   }
-  // only blocks holding a wall row carry a d/d E0 term (uniform per block)
-  if (I.bc_y && (lblk * NT < I.nx || (lblk + 1) * NT > (I.ny - 1) * I.nx)) add_theta(I, ab.tb, lblk, th);
+  // only blocks holding a wall row carry a d/d E0 term (uniform per block),
+  // or every block under an applied field
+  if (has_eext(phys<T>(I)) || (I.bc_y && (lblk * NT < I.nx || (lblk + 1) * NT > (I.ny - 1) * I.nx)))
+    add_theta(I, ab.tb, lblk, th);
 }
 
 // Adjoints of two potential sub-iterations in one launch, the transpose of
@@ -596,7 +607,7 @@ __global__ __launch_bounds__(P2NT) void k_adj_poisson2(const Inst *__restrict__ 
   for (int j = 0; j < Q; ++j) buf[j * (P2EW * P2ER) + e] = hv[j];
   __syncthreads();
   double th = 0.0;
-  T eh_b = 0, q_b = 0;
+  T eh_b = 0, q_b = 0, ee_b[2] = {T(0), T(0)};
   const T eh = ring1 ? epsv - P.eps_ref : T(0);
   const T iden = poisson_iden(eh, P);
   // pull of the adjoint through the push of node (r, tx); wall slots at the node itself
@@ -617,11 +628,13 @@ __global__ __launch_bounds__(P2NT) void k_adj_poisson2(const Inst *__restrict__ 
   if (ring1) {
     T vb[Q];
     pull(vb);
-    T eb1 = 0, qb1 = 0;
-    adj_poisson_local(vb, h1v, eh, iden, P, hb, eb1, qb1);
+    T eb1 = 0, qb1 = 0, ee1[2] = {T(0), T(0)};
+    adj_poisson_local(vb, h1v, eh, iden, P, hb, eb1, qb1, ee1);
     if (interior) {
       eh_b += eb1;
       q_b += qb1;
+      ee_b[0] += ee1[0];
+      ee_b[1] += ee1[1];
     }
   }
   __syncthreads();
@@ -634,14 +647,15 @@ __global__ __launch_bounds__(P2NT) void k_adj_poisson2(const Inst *__restrict__ 
     pull(vb);
 #pragma unroll
     for (int j = 0; j < Q; ++j) h[j] = h0[(size_t)j * N + n];
-    adj_poisson_local(vb, h, eh, iden, P, hb, eh_b, q_b);
+    adj_poisson_local(vb, h, eh, iden, P, hb, eh_b, q_b, ee_b);
     T *Hd = ab.hb[src ^ 1];
 #pragma unroll
     for (int j = 0; j < Q; ++j) Hd[(size_t)j * N + n] = hb[j];
     ab.eb[n] += eh_b;
     qb[n] += q_b;
+    th += (double)ee_b[0] * ab.dEext[0] + (double)ee_b[1] * ab.dEext[1];
   }
-  if (walls && (t.z == 0 || t.z + P2H >= ny)) {
+  if (has_eext(P) || (walls && (t.z == 0 || t.z + P2H >= ny))) {
     for (int o = 32; o > 0; o >>= 1) th += __shfl_down(th, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = th;
     __syncthreads();
@@ -710,7 +724,7 @@ __global__ __launch_bounds__(P2NT) void k_adj_poisson4(const Inst *__restrict__ 
     for (int j = 0; j < Q; ++j) buf[j * PL + e[k]] = hv[k][j];
   __syncthreads();
   double th = 0.0;
-  T eh[RPT], iden[RPT], eh_b[RPT], q_b[RPT];
+  T eh[RPT], iden[RPT], eh_b[RPT], q_b[RPT], ee_b[2] = {T(0), T(0)};
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     eh[k] = inside[k] && dist[k] >= 1 ? epsv[k] - P.eps_ref : T(0);
@@ -741,11 +755,13 @@ __global__ __launch_bounds__(P2NT) void k_adj_poisson4(const Inst *__restrict__ 
       }
 #pragma unroll
       for (int j = 0; j < Q; ++j) h[j] = lv[(size_t)j * N + n[k]];
-      T eb1 = 0, qb1 = 0;
-      adj_poisson_local(vb, h, eh[k], iden[k], P, hb[k], eb1, qb1);
+      T eb1 = 0, qb1 = 0, ee1[2] = {T(0), T(0)};
+      adj_poisson_local(vb, h, eh[k], iden[k], P, hb[k], eb1, qb1, ee1);
       if (interior[k]) {
         eh_b[k] += eb1;
         q_b[k] += qb1;
+        ee_b[0] += ee1[0];
+        ee_b[1] += ee1[1];
       }
     }
     if (i > 1) {
@@ -767,7 +783,8 @@ __global__ __launch_bounds__(P2NT) void k_adj_poisson4(const Inst *__restrict__ 
       ab.eb[n[k]] += eh_b[k];
       qb[n[k]] += q_b[k];
     }
-  if (walls && (t.z == 0 || t.z + H4 >= ny)) {
+  th += (double)ee_b[0] * ab.dEext[0] + (double)ee_b[1] * ab.dEext[1];
+  if (has_eext(P) || (walls && (t.z == 0 || t.z + H4 >= ny))) {
     for (int o = 32; o > 0; o >>= 1) th += __shfl_down(th, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = th;
     __syncthreads();
@@ -961,11 +978,12 @@ __global__ __launch_bounds__(NT) void k_poisson_buf(const Inst *__restrict__ ins
     for (int j = 0; j < Q; ++j) rec_in[(size_t)j * N + n] = h[j];
   T v[Q];
   poisson_collide<D2Q9>(h, eps[n] - P.eps_ref, q[n], P, v);
-  push<D2Q9, T, T>(dst, v, I, nd, 1, T(0), T(0), T(0), P.wall_phi[0], P.wall_phi[1], T(1), false);
+  push_potential<D2Q9>(dst, v, I, nd, P);
 }
 
 // Equilibrium potential populations of a potential plane (Eq. 44), the
-// cold start's first level.
+// cold start's first level (stored as the deviation from the reference
+// potential's equilibrium).
 template <typename T>
 __global__ __launch_bounds__(NT) void k_h_equilibrium(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
                                                       const T *__restrict__ psi, T *__restrict__ h) {
@@ -974,7 +992,7 @@ __global__ __launch_bounds__(NT) void k_h_equilibrium(const Inst *__restrict__ i
   const Node nd = locate(insts, b2i, Ip, lblk);
   if (!nd.valid) return;
   const int N = Ip->N, n = nd.n;
-  const T v = psi[n];
+  const T v = psi[n] - psi_ref<T>(phys<T>(*Ip), nd.y);
 #pragma unroll
   for (int j = 0; j < Q; ++j) h[(size_t)j * N + n] = j == 0 ? (wgt<T>(0) - T(1)) * v : wgt<T>(j) * v;
 }

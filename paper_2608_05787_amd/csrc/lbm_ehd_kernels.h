@@ -91,20 +91,32 @@ struct Ctl {
   int hcur;          // current potential buffer at the start of a step
   int done;          // potential loop converged in this step (adaptive mode)
   int k_used;        // sub-iterations run in this step
-  int pad;
+  int status;        // latched conditions: ST_DIVERGED, ST_NOCONV
   double res_prev;   // relative potential change of the previous sub-iteration
   double res_last;   // relative potential change of the last sub-iteration
   long long k_total; // sub-iterations summed over steps
   long long steps;
-  double diag[16];
+  // diagnostics: [0..15] the outputs of lbm_ehd_diagnostics, [16..21] the
+  // indicator centroids (outer x, y, z; inner x, y, z), [22] the seeded
+  // directional derivative of a tangent run
+  double diag[24];
 };
+// Status bits, set by the kernels and read (and partly cleared) by the host
+// at its next synchronising call.
+constexpr int ST_DIVERGED = 1;  // a non-finite velocity or pressure was formed
+constexpr int ST_NOCONV = 2;    // a residual-controlled potential loop reached sub_max
 
+// ref_a, ref_b: the fixed reference potential psi_ref(y) = ref_a + ref_b y
+// of the potential populations' storage (see push_potential); hwall: the
+// electrode potentials less psi_ref at the walls (zero unless a tangent run
+// moves the electrodes).
 template <typename T> struct Phys {
   T lam[3];
   T m0, tau_f, tau_l, tau_h, eps_ref, D;
   T rho[3], visc[3], eps[3], sig[3];
   T Eext[3], wall_u[2], wall_phi[2], wall_q[2];
   T ion_tau, ion_beta, ion_e;  // Nernst-Planck charge model
+  T ref_a, ref_b, hwall[2];
 };
 
 // Instance descriptor (device memory, read with uniform loads).
@@ -369,6 +381,27 @@ __device__ __forceinline__ T push(P dst, const T (&v)[L::Q], const Inst &I, cons
   return moved;
 }
 
+// Potential populations are stored as deviations from the equilibrium
+// (Eq. 44) of a fixed reference potential, psi_ref(y) = ref_a + ref_b y: the
+// linear profile between the electrodes (zero in a periodic box).  The
+// reference equilibrium has no first moment, so the collision of Eqs. 43-45
+// applies unchanged to the deviation (its potential is psi - psi_ref, its
+// first moment that of h), and streaming it adds
+// w_j (psi_ref(y - c_jy) - psi_ref(y)) = -w_j c_jy ref_b; at an electrode
+// the anti-bounce-back value becomes phi_w - psi_ref(wall) (hwall).  Stored
+// values are then O(psi - psi_ref) instead of O(psi): at 1024^2 with 5.12
+// between the electrodes that keeps ~40x more of E = -grad(psi), formed from
+// the cancelling first moment, in FP32 storage.
+template <typename T, class PP> __device__ __forceinline__ T psi_ref(const PP &P, int y) {
+  return P.ref_a + P.ref_b * T(y);
+}
+template <class L, typename T, class PP, typename Ptr>
+__device__ __forceinline__ void push_potential(Ptr dst, T (&v)[L::Q], const Inst &I, const Node &nd, const PP &P) {
+#pragma unroll
+  for (int j = 0; j < L::Q; ++j) v[j] -= lw<L, T>(j) * lc<L, T>(j, 1) * P.ref_b;
+  push<L, T, T>(dst, v, I, nd, 1, T(0), T(0), T(0), P.hwall[0], P.hwall[1], T(1), false);
+}
+
 // ------------------------------------------------------------ kernels
 
 // a1: order-parameter moments phi_i = sum_j f^i_j and the charge-population
@@ -585,6 +618,11 @@ __global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, cons
 // and the charge source.  Returns the potential of the input h.
 //   iden: 1 / (eps_hat + tau_h / 3), the node's gradient denominator, which
 //   does not change between the sub-iterations of a step.
+// An applied field E_ext is an imposed mean gradient: the populations carry
+// the periodic part psi' of the potential psi = psi' - E_ext . x, and the
+// eps_hat source and Eq. (45) take the gradient of the full psi, so the first
+// moment m = -(tau_h/3) grad(psi') - eps_hat grad(psi) gives
+// grad(psi) = -(m + (tau_h/3) E_ext) iden.
 template <class L, typename T, class PP>
 __device__ __forceinline__ T poisson_collide(const T (&h)[L::Q], T epshat, T iden, T q, const PP &P,
                                              T (&v)[L::Q]) {
@@ -601,7 +639,7 @@ __device__ __forceinline__ T poisson_collide(const T (&h)[L::Q], T epshat, T ide
   const T pot = s1 * (T(1) / (T(1) - lw<L, T>(0)));
   T g[D];
 #pragma unroll
-  for (int d = 0; d < D; ++d) g[d] = -m[d] * iden;  // grad(potential), Eq. (45)
+  for (int d = 0; d < D; ++d) g[d] = -(m[d] + P.tau_h / T(3) * P.Eext[d]) * iden;  // grad(psi), Eq. (45)
   const T ith = T(1) / P.tau_h;
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
@@ -661,7 +699,7 @@ __global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, 
 #pragma unroll
       for (int j = 0; j < Q; ++j) rec_in[(size_t)j * N + n] = h[j];
     T v[Q];
-    const T pot = poisson_collide<L>(h, epshat, q, P, v);
+    const T pot = poisson_collide<L>(h, epshat, q, P, v) + psi_ref<T>(P, nd.y);
     if (write_psi) {
       if (resid) {
         const double d = (double)pot - (double)psi_prev;
@@ -670,7 +708,7 @@ __global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, 
       }
       psi[n] = pot;
     }
-    push<L, T, T>(dst, v, I, nd, 1, T(0), T(0), T(0), P.wall_phi[0], P.wall_phi[1], T(1), false);
+    push_potential<L>(dst, v, I, nd, P);
   }
   if (resid) {
     block_sum<2>(red);
@@ -711,7 +749,7 @@ template <typename T> struct P2Meta {
   const T *src, *eps, *q;
   T *dst, *psi;
   int nx, ny, N, walls;
-  T tau_h, eps_ref, wall_phi[2];
+  T tau_h, eps_ref, hwall[2], Eext[2], ref_a, ref_b;
 };
 
 template <typename T>
@@ -733,13 +771,21 @@ __device__ __forceinline__ P2Meta<T> p2_meta(const Inst *insts, const int4 *tile
   if constexpr (sizeof(T) == 4) {
     m.tau_h = I->pf.tau_h;
     m.eps_ref = I->pf.eps_ref;
-    m.wall_phi[0] = I->pf.wall_phi[0];
-    m.wall_phi[1] = I->pf.wall_phi[1];
+    m.hwall[0] = I->pf.hwall[0];
+    m.hwall[1] = I->pf.hwall[1];
+    m.ref_a = I->pf.ref_a;
+    m.ref_b = I->pf.ref_b;
+    m.Eext[0] = I->pf.Eext[0];
+    m.Eext[1] = I->pf.Eext[1];
   } else {
     m.tau_h = I->pd.tau_h;
     m.eps_ref = I->pd.eps_ref;
-    m.wall_phi[0] = I->pd.wall_phi[0];
-    m.wall_phi[1] = I->pd.wall_phi[1];
+    m.hwall[0] = I->pd.hwall[0];
+    m.hwall[1] = I->pd.hwall[1];
+    m.ref_a = I->pd.ref_a;
+    m.ref_b = I->pd.ref_b;
+    m.Eext[0] = I->pd.Eext[0];
+    m.Eext[1] = I->pd.Eext[1];
   }
   return m;
 }
@@ -828,12 +874,13 @@ __device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int wri
       T v[Q];
       const T pot = poisson_collide<D2Q9>(s.h[k], s.eh[k], s.id[k], s.qq[k], m, v);
       int n;
-      if (it == IT - 1 && write_psi && interior(k, n)) (gbl(m.psi))[n] = pot;
+      if (it == IT - 1 && write_psi && interior(k, n)) (gbl(m.psi))[n] = pot + psi_ref<T>(m, s.gy[k]);
 #pragma unroll
       for (int j = 0; j < Q; ++j) buf[j * (P2EW * ER) + e] = v[j];
     }
     __syncthreads();
-    // pull streaming inside the tile; sources beyond an electrode reflect
+    // pull streaming inside the tile; sources beyond an electrode reflect;
+    // every pulled deviation takes the reference's shift -w_j c_jy ref_b
     const int lo = it + 1;  // ring still valid after this streaming
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
@@ -842,10 +889,11 @@ __device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int wri
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
         const int sy = s.gy[k] - cy(j);
+        const T shift = -wgt<T>(j) * T(cy(j)) * m.ref_b;
         if (walls && (sy < 0 || sy >= ny))
-          s.h[k][j] = -buf[opp(j) * (P2EW * ER) + e] + T(2) * wgt<T>(j) * (sy < 0 ? m.wall_phi[0] : m.wall_phi[1]);
+          s.h[k][j] = -buf[opp(j) * (P2EW * ER) + e] + T(2) * wgt<T>(j) * (sy < 0 ? m.hwall[0] : m.hwall[1]) + shift;
         else
-          s.h[k][j] = buf[j * (P2EW * ER) + e - cy(j) * P2EW - cx(j)];
+          s.h[k][j] = buf[j * (P2EW * ER) + e - cy(j) * P2EW - cx(j)] + shift;
       }
     }
     __syncthreads();
@@ -863,7 +911,7 @@ __device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int wri
 //   tiles: (instance, x0, y0, -) per block.
 //   rec: the input levels of the sub-iterations, for recording runs.
 template <typename T, int RPT = 1, int IT = 2>
-__global__ __launch_bounds__(P2NT, 8) void k_poisson2(const Inst *__restrict__ insts, const int4 *__restrict__ tiles,
+__global__ __launch_bounds__(P2NT, (sizeof(T) == 8 && RPT == 2) ? 4 : 8) void k_poisson2(const Inst *__restrict__ insts, const int4 *__restrict__ tiles,
                                                  int hpar, int write_psi, P2Rec<T, IT> rec = P2Rec<T, IT>{}) {
   constexpr int ER = P2Shape<RPT, IT>::ER;
   __shared__ T buf[Q * P2EW * ER];
@@ -876,8 +924,10 @@ __global__ __launch_bounds__(P2NT, 8) void k_poisson2(const Inst *__restrict__ i
 
 // Adaptive potential loop control, one block per instance, after iteration
 // k: residual of iteration k-1, stopping test, buffer flip.
+//   kcap: when > 0, reaching iteration kcap without stopping latches
+//   ST_NOCONV (time steps; the cold start of create passes 0).
 __global__ __launch_bounds__(NT) void k_reduce_poisson(const Inst *__restrict__ insts, int k, int kmin,
-                                                       double tol) {
+                                                       double tol, int kcap = 0) {
   const Inst &I = insts[blockIdx.x];
   Ctl *ctl = I.ctl;
   if (ctl->done) return;  // iteration k did not run
@@ -890,12 +940,14 @@ __global__ __launch_bounds__(NT) void k_reduce_poisson(const Inst *__restrict__ 
       ctl->res_prev = r;
       if (k >= (kmin > 2 ? kmin : 2) && r < tol) ctl->done = 1;
     }
+    if (k == kcap && !ctl->done) ctl->status |= ST_NOCONV;
     ctl->k_used = k;
     ctl->hcur ^= 1;
   }
 }
 
-// a5: field E = -grad(potential) + E_ext from the converged h (Eq. 45), the
+// a5: field E = -grad(psi) of the full potential from the converged h
+// (Eq. 45 with the applied field: E = (m + (tau_h/3) E_ext) / den), the
 // potential plane and last-iteration residual, and the chemical potentials
 // of Eq. (20) with eps'(phi_i) = 6 eps_i phi_i (1 - phi_i).
 //   hofs: buffer offset of the final h relative to ctl->hcur (fixed count:
@@ -928,11 +980,11 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
       for (int d = 0; d < D; ++d) m[d] += lc<L, T>(j, d) * v;
     }
     const T eps = (gbl((const T *)I.eps))[n];
-    const T pot = s1 / (T(1) - lw<L, T>(0));
+    const T pot = s1 / (T(1) - lw<L, T>(0)) + psi_ref<T>(P, nd.y);
     const T den = (eps - P.eps_ref) + P.tau_h / T(3);
     T e[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) e[d] = m[d] / den + P.Eext[d];
+    for (int d = 0; d < D; ++d) e[d] = (m[d] + P.tau_h / T(3) * P.Eext[d]) / den;
     auto psi = gbl((T *)I.psi);
     // the phi stencils and the previous potential, loaded before the first
     // store (later loads would wait for it: the compiler cannot tell the
@@ -1114,6 +1166,15 @@ __global__ __launch_bounds__(NT, (EARLY || sizeof(T) > 4 || L::Q > 9) ? 1 : 4) v
     }
     const T s0 = lw<L, T>(0) * (-usq * T(1.5));
     const T pp = (s1 + T(0.5) * udr + rho * s0) / (T(3) * (T(1) - lw<L, T>(0)));
+    // divergence watch: a non-finite population, order parameter, charge,
+    // field or chemical potential reaches u or p within a step; latched for
+    // the host (an atomic only on that rare path)
+    {
+      bool ok = isfinite((double)pp);
+#pragma unroll
+      for (int d = 0; d < D; ++d) ok = ok && isfinite((double)u[d]);
+      if (!ok) atomicOr(&I.ctl->status, ST_DIVERGED);
+    }
     if (write_macro) {
 #pragma unroll
       for (int d = 0; d < D; ++d) (gbl((T *)I.u))[(size_t)d * N + n] = u[d];
@@ -1267,7 +1328,7 @@ __global__ __launch_bounds__(NT) void k_init_potential(const Inst *__restrict__ 
   const int N = I.N, n = nd.n;
   auto phi = gbl((const T *)I.phi);
   (gbl((T *)I.eps))[n] = P.eps[0] * herm(phi[n]) + P.eps[1] * herm(phi[(size_t)N + n]) + P.eps[2] * herm(phi[(size_t)2 * N + n]);
-  const T v = (gbl((const T *)I.psi))[n];
+  const T v = (gbl((const T *)I.psi))[n] - psi_ref<T>(P, nd.y);  // stored as the deviation
   auto h = gbl((T *)I.h[I.ctl->hcur]);
 #pragma unroll
   for (int j = 0; j < Q; ++j) h[(size_t)j * N + n] = j == 0 ? (lw<L, T>(0) - T(1)) * v : lw<L, T>(j) * v;
@@ -1377,8 +1438,11 @@ __global__ __launch_bounds__(NT) void k_export_pops(const Inst *__restrict__ ins
       dst[j * M + n] = (Tout)v;
     }
   } else if (fam == 3) {
+    // stored deviation plus the reference potential's equilibrium
     auto h = gbl((const T *)I.h[I.ctl->hcur]);
-    for (int j = 0; j < Q; ++j) dst[j * M + n] = (Tout)h[j * N + n];
+    const T pr = psi_ref<T>(phys<T>(I), (n / I.nx) % I.ny);
+    for (int j = 0; j < Q; ++j)
+      dst[j * M + n] = (Tout)(h[j * N + n] + (j == 0 ? lw<L, T>(0) - T(1) : lw<L, T>(j)) * pr);
   } else {
     const S *p = (const S *)(fam == 1 ? I.g[pc] : I.l[pc]);
     const T sc = fam == 1 ? T(SC_G) : T(SC_L);
@@ -1428,12 +1492,14 @@ __global__ __launch_bounds__(NT) void k_reduce_seed_dot(const Inst *__restrict__
   for (int b = threadIdx.x; b < I.nblk; b += NT) s += I.part_p[(size_t)b * 2];
   double v[1] = {s};
   block_sum<1>(v);
-  if (threadIdx.x == 0) I.ctl->diag[10] = v[0];
+  if (threadIdx.x == 0) I.ctl->diag[22] = v[0];
 }
 
 // Diagnostics, first pass: masses, charge, max |sum phi - 1|, non-finite
-// populations and the raw second moments of the outer (1 - phi1) and inner
-// (phi3) indicators, per block.
+// populations, the raw second moments of the outer (1 - phi1) and inner
+// (phi3) windowed indicators and the sums that locate each indicator's
+// centroid (weights max(w, 0)), per block: DIAG_SUMS sums and the maximum.
+constexpr int DIAG_SUMS = 23, DIAG_PART = DIAG_SUMS + 1;
 template <class L, typename T, typename S>
 __global__ __launch_bounds__(NT) void k_diag(const Inst *__restrict__ insts, const int2 *__restrict__ b2i, int pc) {
   constexpr int Q = L::Q;
@@ -1441,9 +1507,9 @@ __global__ __launch_bounds__(NT) void k_diag(const Inst *__restrict__ insts, con
   int lblk;
   const Node nd = locate<L>(insts, b2i, Ip, lblk);
   const Inst &I = *Ip;
-  double v[15];
+  double v[DIAG_SUMS];
 #pragma unroll
-  for (int k = 0; k < 15; ++k) v[k] = 0.0;
+  for (int k = 0; k < DIAG_SUMS; ++k) v[k] = 0.0;
   double mx = 0.0;
   if (nd.valid) {
     const int N = I.N, n = nd.n;
@@ -1478,8 +1544,11 @@ __global__ __launch_bounds__(NT) void k_diag(const Inst *__restrict__ insts, con
     const double wo = drop_indicator(1.0 - p1), wi = drop_indicator(p3);
     v[5] = wo; v[6] = wo * xx; v[7] = wo * yy; v[8] = wo * xx * xx; v[9] = wo * yy * yy;
     v[10] = wi; v[11] = wi * xx; v[12] = wi * yy; v[13] = wi * xx * xx; v[14] = wi * yy * yy;
+    const double zz = nd.z, co = fmax(1.0 - p1, 0.0), ci = fmax(p3, 0.0);
+    v[15] = co; v[16] = co * xx; v[17] = co * yy; v[18] = co * zz;
+    v[19] = ci; v[20] = ci * xx; v[21] = ci * yy; v[22] = ci * zz;
   }
-  block_sum<15>(v);
+  block_sum<DIAG_SUMS>(v);
   __shared__ double mred[NT / 64];
   for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_down(mx, o, 64));
   if ((threadIdx.x & 63) == 0) mred[threadIdx.x >> 6] = mx;
@@ -1487,9 +1556,9 @@ __global__ __launch_bounds__(NT) void k_diag(const Inst *__restrict__ insts, con
   if (threadIdx.x == 0) {
     double m = mred[0];
     for (int i = 1; i < NT / 64; ++i) m = fmax(m, mred[i]);
-    double *dst = I.part_d + (size_t)lblk * 16;
-    for (int k = 0; k < 15; ++k) dst[k] = v[k];
-    dst[15] = m;
+    double *dst = I.part_d + (size_t)lblk * DIAG_PART;
+    for (int k = 0; k < DIAG_SUMS; ++k) dst[k] = v[k];
+    dst[DIAG_SUMS] = m;
   }
 }
 
@@ -1499,13 +1568,14 @@ __global__ __launch_bounds__(NT) void k_diag(const Inst *__restrict__ insts, con
 __global__ __launch_bounds__(NT) void k_reduce_diag(const Inst *__restrict__ insts) {
   const Inst &I = insts[blockIdx.x];
   Ctl *ctl = I.ctl;
-  double s[16];
-  reduce_partials<16>(I.part_d, I.nblk, s);
+  const double *pd = I.part_d;
+  double s[DIAG_PART];
+  reduce_partials<DIAG_PART>(pd, I.nblk, s);  // (the maximum's slot is summed too, unused)
   double r[2];
   reduce_partials<2>(I.part_mu, I.nblk, r);
   // max over blocks of |sum phi - 1|
   double m = 0.0;
-  for (int b = threadIdx.x; b < I.nblk; b += NT) m = fmax(m, I.part_d[(size_t)b * 16 + 15]);
+  for (int b = threadIdx.x; b < I.nblk; b += NT) m = fmax(m, pd[(size_t)b * DIAG_PART + DIAG_SUMS]);
   __shared__ double mred[NT / 64];
   for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o, 64));
   if ((threadIdx.x & 63) == 0) mred[threadIdx.x >> 6] = m;
@@ -1527,7 +1597,94 @@ __global__ __launch_bounds__(NT) void k_reduce_diag(const Inst *__restrict__ ins
       const double a = sqrt(ipar > 0 ? ipar : 0), b = sqrt(iper > 0 ? iper : 0);
       val = (a + b) > 0 ? (a - b) / (a + b) : 0.0;
     }
-    out[8 + d] = val;
+    out[10 + d] = val;
+    // centroid of the indicator (weights max(w, 0)) for the contour pass
+    const double c0 = s[15 + 4 * d];
+    for (int a = 0; a < 3; ++a) out[16 + 3 * d + a] = c0 > 0 ? s[16 + 4 * d + a] / c0 : 0.0;
+  }
+}
+
+// The Sec. 4.4 deformation factor D = (r_par - r_perp) / (r_par + r_perp)
+// of the outer (w = 1 - phi1) and inner (w = phi3) drops, one block per
+// instance, after k_reduce_diag.  The field is along y: r_par is half the
+// distance between the two w = 1/2 crossings on the y line through the
+// indicator's centroid, r_perp the same on the x line.  The lines fall
+// between lattice nodes: w on them is interpolated linearly in each other
+// axis (periodic wrap).  From the node s nearest the centroid (which must
+// have w >= 1/2), the crossing in each direction lies between the last
+// line node with w >= 1/2 and the next, found as the smallest offset k with
+// w(s +- (k + 1)) < 1/2 (a minimum over the block's threads), and placed by
+// linear interpolation.  A line that meets a wall first, or never drops
+// below 1/2, gives nan.  Outputs diag[8..9] (D) and diag[12..15] (r_par,
+// r_perp of the outer drop, then of the inner).
+template <class L, typename T>
+__global__ __launch_bounds__(NT) void k_contour(const Inst *__restrict__ insts) {
+  const Inst &I = insts[blockIdx.x];
+  double *out = I.ctl->diag;
+  const int nx = I.nx, ny = I.ny, nz = L::D == 3 ? I.nz : 1;
+  const T *phi = (const T *)I.phi;
+  __shared__ int kmin[NT / 64];
+  const double nan = __builtin_nan("");
+  for (int d = 0; d < 2; ++d) {
+    const double cxyz[3] = {out[16 + 3 * d], out[17 + 3 * d], out[18 + 3 * d]};
+    const T *pl = phi + (d == 0 ? 0 : (size_t)2 * I.N);
+    auto w = [&](int x, int y, int z) -> double {
+      const double p = (double)pl[((size_t)z * ny + y) * nx + x];
+      return d == 0 ? 1.0 - p : p;
+    };
+    double r[2] = {nan, nan};
+    const bool finite = isfinite(cxyz[0]) && isfinite(cxyz[1]) && isfinite(cxyz[2]);
+    for (int axis = 1; axis >= 0 && finite; --axis) {  // the y line (along the field), then the x line
+      // the interpolation corners in the other in-plane axis (and z)
+      const int other = 1 - axis;
+      const int nother = other == 0 ? nx : ny, nline = axis == 0 ? nx : ny;
+      const double fo = floor(cxyz[other]), fz = floor(cxyz[2]);
+      const int o0 = ((int)fo % nother + nother) % nother, o1 = (o0 + 1) % nother;
+      const double ao = cxyz[other] - fo;
+      const int z0 = L::D == 3 ? (((int)fz % nz) + nz) % nz : 0, z1 = L::D == 3 ? (z0 + 1) % nz : 0;
+      const double az = L::D == 3 ? cxyz[2] - fz : 0.0;
+      auto val = [&](int t) -> double {  // w on the line at line coordinate t (wrapped)
+        const int tt = ((t % nline) + nline) % nline;
+        auto at = [&](int o, int z) { return axis == 1 ? w(o, tt, z) : w(tt, o, z); };
+        double v = (1.0 - ao) * at(o0, z0) + ao * at(o1, z0);
+        if (L::D == 3) v = (1.0 - az) * v + az * ((1.0 - ao) * at(o0, z1) + ao * at(o1, z1));
+        return v;
+      };
+      const bool bounded = axis == 1 && I.bc_y;
+      const int s = (((int)floor(cxyz[axis] + 0.5)) % nline + nline) % nline;
+      double ends[2];
+      bool okk = val(s) >= 0.5;
+      for (int dir = 0; dir < 2 && okk; ++dir) {
+        const int step = dir == 0 ? 1 : -1;
+        // offsets k = 0 .. kend-1 may be tested (the target s + step (k+1) stays off the wall)
+        const int kend = bounded ? (step > 0 ? ny - 1 - s : s) : nline;
+        int best = 0x7fffffff;
+        for (int k = threadIdx.x; k < kend; k += NT)
+          if (val(s + step * (k + 1)) < 0.5) best = k < best ? k : best;
+        for (int o = 32; o > 0; o >>= 1) {
+          const int b = __shfl_down(best, o, 64);
+          best = b < best ? b : best;
+        }
+        if ((threadIdx.x & 63) == 0) kmin[threadIdx.x >> 6] = best;
+        __syncthreads();
+        best = kmin[0];
+        for (int q = 1; q < NT / 64; ++q) best = kmin[q] < best ? kmin[q] : best;
+        __syncthreads();
+        if (best == 0x7fffffff) {
+          okk = false;
+          break;
+        }
+        const int i = s + step * best;
+        const double a = val(i), b = val(i + step);
+        ends[dir] = i + step * (a - 0.5) / (a - b);
+      }
+      r[axis == 1 ? 0 : 1] = okk ? 0.5 * (ends[0] - ends[1]) : nan;
+    }
+    if (threadIdx.x == 0) {
+      out[8 + d] = (r[0] - r[1]) / (r[0] + r[1]);
+      out[12 + 2 * d] = r[0];
+      out[13 + 2 * d] = r[1];
+    }
   }
 }
 

@@ -37,7 +37,8 @@ def test_field_drop_deformation_full_length():
         with open(os.path.join(out_dir, "deformation_field_drop_1024.json"), "w") as f:
             json.dump({"steps": STEPS, "every": EVERY, "curves": curves}, f)
     ref = curves["fp64"]
-    assert abs(ref[-1][1]) > 1e-4  # the outer drop has deformed
+    # the drops have deformed well beyond the tolerance (Sec. 4.4 contour D)
+    assert abs(ref[-1][1]) > 5e-3 and abs(ref[-1][2]) > 2e-3, ref[-1]
     for prec in ("fp32", "fp16s"):
         for (t, do, di, _), (_, ro, ri, _) in zip(curves[prec], ref):
             assert abs(do - ro) < 1e-3 and abs(di - ri) < 1e-3, (prec, t, do, ro, di, ri)

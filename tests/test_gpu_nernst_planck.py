@@ -13,7 +13,11 @@ torch = pytest.importorskip("torch")
 from oracle import Oracle  # noqa: E402
 from paper_2608_05787_amd import binding, inputs  # noqa: E402
 
-from test_gpu_parity import FP32_TOL, FP64_TOL, rel_err, rel_l2  # noqa: E402
+from test_gpu_parity import FP32_TOL, FP64_TOL, rel_err  # noqa: E402
+
+# the ion charge e (n_+ - n_-) is a difference of two O(1) concentrations:
+# measured 5.3e-6 element-wise after 12 FP32 steps
+FP32_TOL = dict(FP32_TOL, q=1.5e-5)
 
 pytestmark = pytest.mark.gpu
 
@@ -22,7 +26,7 @@ FIELDS_NP = ["phi1", "phi2", "phi3", "rho", "ux", "uy", "p", "psi", "Ex", "Ey", 
 
 
 def compare_np(sim, ref, tol, names):
-    metric = rel_err if not isinstance(tol, dict) else rel_l2
+    metric = rel_err  # element-wise, relative to the largest magnitude
     if isinstance(tol, dict):
         tol = dict(tol, n_plus=tol["phi1"], n_minus=tol["phi1"], uz=tol["ux"], Ez=tol["Ex"])
     got = {k: v.cpu().numpy() for k, v in sim.fields(names).items()}
@@ -30,6 +34,7 @@ def compare_np(sim, ref, tol, names):
     for fam in "fglh":
         errs["pop_" + fam] = metric(sim.populations(fam).cpu().numpy(), ref.pops(fam))
     lim = (lambda k: tol[k]) if isinstance(tol, dict) else (lambda k: tol)
+    print("max-norm errors", " ".join("%s=%.1e" % kv for kv in errs.items()), flush=True)
     bad = {k: v for k, v in errs.items() if not v <= lim(k)}
     assert not bad, (bad, errs)
 

@@ -16,16 +16,19 @@ pytestmark = pytest.mark.gpu
 
 FIELDS = ["phi1", "phi2", "phi3", "rho", "ux", "uy", "p", "psi", "Ex", "Ey", "q", "mu1", "mu2", "mu3", "eps", "R"]
 FP64_TOL = 1e-9
-# FP32 bounds on the relative L2 error per field.  FP32 keeps ~6e-8 of each
-# stored value: fields carried directly by populations (phi_i, rho, eps) keep
-# that level; the potential and charge are integrated by the sub-iterations,
-# which accumulate rounding over ~1/(slowest decay rate) iterations; mu, p and
-# E are differences of O(1) stored values (Laplacian of phi, first moment of
-# h, sum of g) and lose the ratio |stored| / |derived| in relative accuracy.
-FP32_TOL = {"phi1": 5e-5, "phi2": 5e-5, "phi3": 5e-5, "rho": 5e-5, "eps": 5e-5,
-            "psi": 5e-4, "q": 5e-4, "R": 5e-4, "ux": 5e-4, "uy": 5e-4,
-            "p": 1e-2, "Ex": 1e-2, "Ey": 1e-2, "mu1": 1e-2, "mu2": 1e-2, "mu3": 1e-2,
-            "pop_f": 5e-5, "pop_l": 5e-4, "pop_h": 5e-4, "pop_g": 1e-2}
+# FP32 bounds on the element-wise error, relative to each field's largest
+# magnitude (max-norm), ~3x the errors measured after 12 steps on the cases
+# below.  FP32 keeps ~6e-8 of each stored value.  Fields carried by
+# populations (phi_i, rho, eps) and, with the potential populations stored as
+# deviations from the electrode profile's equilibrium, the potential, field
+# and charge stay near 1e-6 (measured <= 9e-7, 4e-7, 8e-7, 6e-7); mu and p
+# are small differences of O(1) values (bulk against Laplacian terms of
+# phi ~ 1, the zeroth moment of g) and lose that ratio (mu <= 9.4e-5, p
+# 7.7e-5, the g populations 8.1e-5); u follows from the mu gradients (1.7e-5).
+FP32_TOL = {"phi1": 3e-6, "phi2": 3e-6, "phi3": 3e-6, "rho": 3e-6, "eps": 3e-6,
+            "psi": 5e-6, "q": 5e-6, "R": 6e-6, "Ex": 5e-6, "Ey": 5e-6,
+            "ux": 5e-5, "uy": 5e-5, "p": 3e-4, "mu1": 3e-4, "mu2": 3e-4, "mu3": 3e-4,
+            "pop_f": 3e-6, "pop_l": 5e-6, "pop_h": 5e-6, "pop_g": 3e-4}
 
 
 def rel_err(a, b):
@@ -39,28 +42,37 @@ def rel_l2(a, b):
 
 
 def compare(sim, ref, tol, fields=FIELDS, pops=True):
-    """FP64 (tol is a float): max-norm relative error of every element.
-    FP32 (tol is a dict): relative L2 error per field."""
-    metric = rel_err if not isinstance(tol, dict) else rel_l2
+    """Element-wise error of every field (and population family) relative to
+    its largest magnitude, against one bound (FP64) or a bound per field
+    (FP32, FP16S).  Prints the measured errors."""
+    metric = rel_err
     got = {k: v.cpu().numpy() for k, v in sim.fields(fields).items()}
     errs = {k: metric(got[k], ref.field(k)) for k in fields}
     if pops:
         for fam in "fglh":
             errs["pop_" + fam] = metric(sim.populations(fam).cpu().numpy(), ref.pops(fam))
     lim = (lambda k: tol[k]) if isinstance(tol, dict) else (lambda k: tol)
+    print("max-norm errors", " ".join("%s=%.1e" % kv for kv in errs.items()), flush=True)
     bad = {k: v for k, v in errs.items() if not v <= lim(k)}
     assert not bad, (bad, errs)
     return errs
 
 
 # FP16S (half-precision populations scaled per family, FP32 rest populations
-# f^i_0, FP32 arithmetic and FP32 potential populations): phi carried by the
-# FP32 f^i_0 plus 8 half values of size ~w_j mu keeps ~1e-6; charge, flow and
-# potential inherit the 2^-11 relative step of the half values of l and g.
-FP16_TOL = {"phi1": 5e-5, "phi2": 5e-5, "phi3": 5e-5, "rho": 5e-5, "eps": 5e-5,
-            "psi": 1e-2, "q": 1e-2, "R": 1e-2, "ux": 1e-2, "uy": 1e-2,
-            "p": 2e-2, "Ex": 2e-2, "Ey": 2e-2, "mu1": 2e-2, "mu2": 2e-2, "mu3": 2e-2,
-            "pop_f": 5e-5, "pop_l": 1e-2, "pop_h": 1e-2, "pop_g": 2e-2}
+# f^i_0, FP32 arithmetic and FP32 potential populations), element-wise, ~3x
+# the errors measured after 12 steps: phi carried by the FP32 f^i_0 plus 8
+# half values of size ~w_j mu keeps ~4e-6; charge, flow and potential
+# inherit the 2^-11 relative step of the half values of l and g (q 4.1e-4,
+# psi 3.0e-4, u 9.3e-4, g populations 1.2e-3).
+FP16_TOL = {"phi1": 1.5e-5, "phi2": 1.5e-5, "phi3": 1.5e-5, "rho": 1.5e-5, "eps": 1.5e-5,
+            "psi": 1.5e-3, "q": 1.5e-3, "R": 1.5e-3, "Ex": 1.5e-3, "Ey": 1.5e-3,
+            "ux": 3e-3, "uy": 3e-3, "p": 3e-3, "mu1": 3e-3, "mu2": 3e-3, "mu3": 3e-3,
+            "pop_f": 1.5e-5, "pop_l": 1.5e-3, "pop_h": 1.5e-3, "pop_g": 4e-3}
+# The static doublet after 300 steps (no field): the order parameters'
+# rounding accumulates (phi <= 2.1e-5 FP32, 2.3e-5 FP16S) and mu amplifies it
+# (<= 2.0e-3, 2.5e-3).
+DOUBLET_TOL = {"phi1": 6e-5, "phi2": 6e-5, "phi3": 6e-5, "mu1": 6e-3, "mu2": 6e-3, "mu3": 6e-3,
+               "ux": 1e-4, "uy": 1e-4, "p": 1e-3}
 
 CASES = [(8, 8, True), (9, 7, False), (33, 17, True), (130, 70, True), (64, 48, False)]
 
@@ -187,20 +199,81 @@ def test_static_doublet_fp32_full_size():
     sim = binding.Sim(p, init, precision="fp32")
     ref.step(300)
     sim.step(300)
-    compare(sim, ref, FP32_TOL, fields=["phi1", "phi2", "phi3", "mu1", "mu2", "mu3", "ux", "uy", "p"], pops=False)
+    compare(sim, ref, DOUBLET_TOL, fields=list(DOUBLET_TOL), pops=False)
+
+
+@pytest.mark.parametrize("tuning", [binding.TUNE_TALL_TILES,
+                                    binding.TUNE_TALL_TILES | binding.TUNE_COLLIDE_PER_FAMILY,
+                                    binding.TUNE_TALL_TILES | binding.TUNE_LINEAR_ORDER])
+@pytest.mark.parametrize("K,nx,ny,walls", [(4, 130, 70, True), (6, 70, 45, False), (5, 131, 58, True)])
+def test_fp64_tall_tiles_match_oracle(tuning, K, nx, ny, walls):
+    """The potential kernel of the benchmarked launch configurations (64 x 32
+    tiles, four sub-iterations per launch while four remain, then tall
+    pairs) instantiated in FP64 matches the oracle to rounding on grids
+    spanning several tiles in both directions, walled and periodic, with
+    ragged edges and an odd count."""
+    print("case fp64 tall", tuning, K, nx, ny, walls, flush=True)
+    p, init = inputs.parity_case(nx, ny, seed=K + nx, walls=walls, sub=(K, K, 0.0))
+    p["init_sub_max"] = 2 * K
+    ref = Oracle(p, init)
+    sim = binding.Sim(p, init, precision="fp64")
+    sim.set_tuning(tuning)
+    ref.step(5)
+    sim.step(5)
+    compare(sim, ref, FP64_TOL)
+
+
+# After only 2 steps from rest the flow is still tiny, so its element-wise
+# error relative to the largest |u| is larger than in the 12-step cases
+# (measured u 8.0e-5, p 1.8e-4, mu 1.5e-4; the rest as those cases).
+FP32_TOL_1024 = dict(FP32_TOL, ux=2.5e-4, uy=2.5e-4, p=5e-4, mu1=5e-4, mu2=5e-4, mu3=5e-4)
+_BENCH_TUNINGS = (0, binding.TUNE_TALL_TILES, binding.TUNE_TALL_TILES | binding.TUNE_COLLIDE_PER_FAMILY)
 
 
 def test_field_drop_1024_fp32():
-    """1024x1024 compound drop between electrodes (third workload) in the
-    launch configuration the benchmark times: every field after a shortened
-    cold start and 2 steps, element by element."""
+    """1024x1024 compound drop between electrodes (third workload) against the
+    oracle in the default launch configuration and the two the autotuner
+    picks for the benchmark (tall potential tiles with four sub-iterations
+    per launch; with and without the per-family collide schedule): every
+    field, element by element, after a shortened cold start and 2 steps."""
     print("case 1024", flush=True)
     p, init = inputs.field_compound_drop(1024, init_iters=60, init_tol=0.0, sub=(4, 4, 0.0))
     ref = Oracle(p, init)
-    sim = binding.Sim(p, init, precision="fp32")
     ref.step(2)
-    sim.step(2)
-    compare(sim, ref, FP32_TOL, pops=False)
+    for tuning in _BENCH_TUNINGS:
+        print("case 1024 tuning", tuning, flush=True)
+        sim = binding.Sim(p, init, precision="fp32")
+        sim.set_tuning(tuning)
+        sim.step(2)
+        compare(sim, ref, FP32_TOL_1024, pops=False)
+        del sim
+
+
+def test_contour_deformation_matches_helper():
+    """The library's Sec. 4.4 deformation factors (contour form) equal the
+    oracle-side helper applied to the same order-parameter fields (FP64
+    handle: to rounding; FP32: the helper on the FP32 fields), for a
+    compound drop deformed by the field, and the FP64 fields equal the
+    oracle's, so the library's D is the oracle's D."""
+    from oracle.deformation import contour_deformation
+    print("case contour", flush=True)
+    p, init = inputs.field_compound_drop(96, r_shell=22, r_core=14, ca_e=0.4, init_iters=300, init_tol=0.0)
+    ref = Oracle(p, init)
+    ref.step(400)
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-6)):
+        sim = binding.Sim(p, init, precision=prec)
+        sim.step(400)
+        d = sim.diagnostics()
+        assert d["status"] == 0
+        f = {k: v.cpu().numpy().astype(np.float64) for k, v in sim.fields(["phi1", "phi3"]).items()}
+        for key, w, rk in (("D_outer", 1 - f["phi1"], "outer"), ("D_inner", f["phi3"], "inner")):
+            D, rpar, rperp = contour_deformation(w, walls=True)
+            assert abs(d[key] - D) < tol, (prec, key, d[key], D)
+            assert abs(d["r_par_" + rk] - rpar) < 1e3 * tol and abs(d["r_perp_" + rk] - rperp) < 1e3 * tol
+            assert abs(d["D_outer"]) > 1e-4
+        if prec == "fp64":
+            Dref = contour_deformation(1 - ref.field("phi1"), walls=True)[0]
+            assert abs(d["D_outer"] - Dref) < 1e-10
 
 
 def test_batch_equals_separate_runs_bitwise():
@@ -276,7 +349,7 @@ def test_diagnostics_and_mass_conservation():
     def indicator(w):
         sm = np.clip((w - 0.005) / 0.015, 0.0, 1.0)
         return np.where(w <= 0.005, 0.0, w * sm * sm * (3 - 2 * sm))
-    for key, w in (("D_outer", indicator(1 - f["phi1"])), ("D_inner", indicator(f["phi3"]))):
+    for key, w in (("D_outer_moment", indicator(1 - f["phi1"])), ("D_inner_moment", indicator(f["phi3"]))):
         W = w.sum()
         xb, yb = (w * x).sum() / W, (w * y).sum() / W
         a = np.sqrt((w * (y - yb) ** 2).sum() / W)
