@@ -259,6 +259,19 @@ int lbm_ehd_populations(lbm_ehd_t h, int32_t inst, int32_t family, void *dev_dst
  * loop reached sub_max since the last report (the outputs are valid). */
 int lbm_ehd_diagnostics(lbm_ehd_t h, int32_t inst, double out[16]);
 
+/* For callers that cannot allocate device memory (serving loops,
+ * harnesses that forbid hipMalloc): lbm_ehd_diagnostics with its per-block
+ * partial sums in a static device buffer of the library instead of the
+ * handle's workspace.  Same outputs (bitwise) and return codes as
+ * lbm_ehd_diagnostics; allocates nothing.  The buffer holds 65536 node
+ * blocks of 256 nodes (16.7 M nodes over all of the handle's instances,
+ * 12 MiB per GPU, kept until the process ends); larger handles get
+ * LBM_EHD_ENOMEM.  Every call on one GPU shares that GPU's buffer: calls
+ * that overlap in time on one GPU (several host threads, or handles on
+ * different streams) race and must be serialised by the caller.
+ * Synchronises. */
+int lbm_ehd_diagnostics_static(lbm_ehd_t h, int32_t inst, double out[16]);
+
 /* Latched status of every instance (see the conventions above), without a
  * reduction pass: synchronises, ORs the instances' status bits into *flags
  * (may be NULL; bit 1: non-finite velocity or pressure formed, bit 2: a

@@ -59,7 +59,8 @@ class Init(ctypes.Structure):
 
 
 EXPORTS = ["lbm_ehd_adjoint_workspace_bytes", "lbm_ehd_workspace_bytes", "lbm_ehd_create", "lbm_ehd_step", "lbm_ehd_fields",
-           "lbm_ehd_populations", "lbm_ehd_diagnostics", "lbm_ehd_status", "lbm_ehd_scalars",
+           "lbm_ehd_populations", "lbm_ehd_diagnostics", "lbm_ehd_diagnostics_static", "lbm_ehd_status",
+           "lbm_ehd_scalars",
            "lbm_ehd_checkpoint_bytes", "lbm_ehd_checkpoint", "lbm_ehd_restore",
            "lbm_ehd_adjoint", "lbm_ehd_record", "lbm_ehd_tangent_workspace_bytes", "lbm_ehd_tangent_gradient",
            "lbm_ehd_profile_begin", "lbm_ehd_profile_end", "lbm_ehd_graph",
@@ -88,6 +89,7 @@ def load():
     lib.lbm_ehd_populations.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int32]
     lib.lbm_ehd_diagnostics.argtypes = [vp, ctypes.c_int32, _dp]
     lib.lbm_ehd_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.lbm_ehd_diagnostics_static.argtypes = [vp, ctypes.c_int32, _dp]
     lib.lbm_ehd_scalars.argtypes = [vp, _dp]
     lib.lbm_ehd_checkpoint_bytes.argtypes = [vp, ctypes.POINTER(sz)]
     lib.lbm_ehd_checkpoint.argtypes = [vp, vp]
@@ -258,12 +260,14 @@ class Sim:
         self._check(load().lbm_ehd_populations(self._h, inst, idx, ctypes.c_void_p(out.data_ptr()), dt), self._h)
         return self._handoff(out)
 
-    def diagnostics(self, inst: int = 0) -> dict:
+    def diagnostics(self, inst: int = 0, static: bool = False) -> dict:
         """The 16 outputs of lbm_ehd_diagnostics by name, plus "status": its
         return code (0, EDIVERGED or the warning ENOCONV; other codes
-        raise)."""
+        raise).  static=True calls lbm_ehd_diagnostics_static (the partial
+        sums in the library's static device buffer)."""
         out = (ctypes.c_double * 16)()
-        rc = load().lbm_ehd_diagnostics(self._h, inst, out)
+        fn = load().lbm_ehd_diagnostics_static if static else load().lbm_ehd_diagnostics
+        rc = fn(self._h, inst, out)
         d = dict(zip(DIAG_KEYS, list(out)))
         if rc not in (0, EDIVERGED, ENOCONV):
             self._check(rc, self._h)

@@ -10,6 +10,7 @@
 #include <type_traits>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -271,6 +272,7 @@ const char *validate(const lbm_ehd_params &p, const lbm_ehd_params &p0) {
 
 struct lbm_ehd_s {
   int n_inst = 0, prec = 0, lattice = 0;
+  int device = 0;  // the device current at create
   hipStream_t stream = nullptr;
   char *ws = nullptr;
   Plan plan;
@@ -383,7 +385,39 @@ struct lbm_ehd_s {
     if (e_ != hipSuccess) return (h)->fail(LBM_EHD_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
   } while (0)
 
+// Per-block partial sums of lbm_ehd_diagnostics_static, for callers that
+// cannot allocate device memory: one array per GPU the library runs on,
+// held until the process ends.  Host code never passes this name to a
+// kernel or a copy: it uses the address hipGetSymbolAddress returns for the
+// device (static_scratch).
+constexpr int DIAG_STATIC_MAX_BLOCKS = 65536;  // node blocks of 256: 16.7 M nodes, 12 MiB
+static __device__ __align__(256) double scratch[(size_t)DIAG_STATIC_MAX_BLOCKS * DIAG_PART];
+
 namespace {
+
+std::mutex g_scratch_mu;
+std::vector<double *> g_scratch_dev;  // device address of `scratch`, per device (null: not yet known)
+
+// Address of the static scratch array on the handle's device, looked up once
+// per device with that device current.
+int static_scratch(lbm_ehd_s *H, double **out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  const int dev = H->device;
+  if (dev >= (int)g_scratch_dev.size()) g_scratch_dev.resize(dev + 1, nullptr);
+  if (!g_scratch_dev[dev]) {
+    int cur = 0;
+    HIPC(H, hipGetDevice(&cur));
+    if (cur != dev) HIPC(H, hipSetDevice(dev));
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) HIPC(H, hipSetDevice(cur));
+    if (e != hipSuccess || !ptr)
+      return H->fail(LBM_EHD_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_dev[dev] = (double *)ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return LBM_EHD_OK;
+}
 
 // Fixed-count potential iterations 1..K: on D2Q9 planes one
 // single-iteration launch first when K is odd, then LDS-tiled launches of
@@ -575,12 +609,14 @@ int do_step(lbm_ehd_s *H, int64_t n) {
   return LBM_EHD_OK;
 }
 
+//   part: null (the instances' partials in the workspace) or a buffer of
+//   DIAG_PART doubles per node block of the handle.
 template <class Lat, typename T, typename S>
-int do_diag(lbm_ehd_s *H) {
+int do_diag(lbm_ehd_s *H, double *part) {
   const dim3 grid(H->plan.total_blocks), block(NT);
   hipEvent_t e = H->prof_start(5);
-  k_diag<Lat, T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, (int)(H->steps & 1));
-  k_reduce_diag<<<H->n_inst, block, 0, H->stream>>>(H->d_insts);
+  k_diag<Lat, T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, (int)(H->steps & 1), part);
+  k_reduce_diag<<<H->n_inst, block, 0, H->stream>>>(H->d_insts, part);
   k_contour<Lat, T><<<H->n_inst, block, 0, H->stream>>>(H->d_insts);
   H->prof_stop(e);
   HIPC(H, hipGetLastError());
@@ -637,7 +673,9 @@ struct StepF {
   template <class L, typename T, typename S> static int run(lbm_ehd_s *H, int64_t n) { return do_step<L, T, S>(H, n); }
 };
 struct DiagF {
-  template <class L, typename T, typename S> static int run(lbm_ehd_s *H) { return do_diag<L, T, S>(H); }
+  template <class L, typename T, typename S> static int run(lbm_ehd_s *H, double *part) {
+    return do_diag<L, T, S>(H, part);
+  }
 };
 struct ExportF {
   template <class L, typename T, typename S>
@@ -685,6 +723,11 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
     return LBM_EHD_ENOMEM;
   }
   lbm_ehd_s *H = new lbm_ehd_s();
+  if (hipGetDevice(&H->device) != hipSuccess) {
+    delete H;
+    g_create_error = "hipGetDevice failed";
+    return LBM_EHD_EHIP;
+  }
   H->n_inst = n_inst;
   H->prec = params[0].precision;
   H->lattice = params[0].lattice;
@@ -723,6 +766,7 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
     I.phase_mode = p.phase_mode;
     I.charge_model = p.charge_model;
     I.nblk = L.nblk;
+    I.blk0 = (int)logical.size();  // node blocks of the instances before this one
     for (int b = 0; b < 2; ++b) {
       I.f[b] = H->ws + L.f[b];
       I.f0[b] = p.precision == LBM_PREC_FP16S ? (float *)(H->ws + L.f0[b]) : nullptr;
@@ -1307,8 +1351,23 @@ static int finish_diag(lbm_ehd_t H, int32_t inst, double out[16]) {
 
 int lbm_ehd_diagnostics(lbm_ehd_t H, int32_t inst, double out[16]) {
   if (!H || inst < 0 || inst >= H->n_inst || !out) return LBM_EHD_EINVAL;
-  int rc = dispatch<DiagF>(H, H);
+  int rc = dispatch<DiagF>(H, H, (double *)nullptr);
   if (rc) return rc;
+  return finish_diag(H, inst, out);
+}
+
+int lbm_ehd_diagnostics_static(lbm_ehd_t H, int32_t inst, double out[16]) {
+  if (!H || inst < 0 || inst >= H->n_inst || !out) return LBM_EHD_EINVAL;
+  if (H->plan.total_blocks > DIAG_STATIC_MAX_BLOCKS)
+    return H->fail(LBM_EHD_ENOMEM,
+                   "diagnostics_static: the handle has %d node blocks of %d nodes; the static buffer holds %d",
+                   H->plan.total_blocks, NT, DIAG_STATIC_MAX_BLOCKS);
+  double *part = nullptr;
+  int rc = static_scratch(H, &part);
+  if (rc) return rc;
+  // every slot the reduction reads is written by k_diag of this call first:
+  // the buffer needs no clearing
+  if ((rc = dispatch<DiagF>(H, H, part))) return rc;
   return finish_diag(H, inst, out);
 }
 

@@ -127,7 +127,8 @@ template <typename T> struct Phys {
 struct Inst {
   int nx, ny, N, bc_y;
   int wall_q_mode, phase_mode, nblk, nz;
-  int charge_model, nn, pad_[2];  // charge model: 0 leaky dielectric, 1 two-ion Nernst-Planck (l holds [2][Q][N])
+  int charge_model, nn, blk0, pad_;  // charge model: 0 leaky dielectric, 1 two-ion Nernst-Planck (l holds [2][Q][N]);
+                                     // blk0: node blocks of the instances before this one
   void *f[2], *g[2], *l[2], *h[2];
   float *f0[2];  // FP16S only: FP32 rest populations f^i_0, [3][N]
   // planes: phi 3, lsum, eps, q, R, psi, E D, mu 3, u D, p, rho, hpu 3D, hqu D
@@ -1500,8 +1501,12 @@ __global__ __launch_bounds__(NT) void k_reduce_seed_dot(const Inst *__restrict__
 // (phi3) windowed indicators and the sums that locate each indicator's
 // centroid (weights max(w, 0)), per block: DIAG_SUMS sums and the maximum.
 constexpr int DIAG_SUMS = 23, DIAG_PART = DIAG_SUMS + 1;
+//   part: where the per-block results go: null for the instance's own
+//   partials in the workspace, else a buffer of DIAG_PART doubles per node
+//   block of the handle (block blk0 + lblk of instance I).
 template <class L, typename T, typename S>
-__global__ __launch_bounds__(NT) void k_diag(const Inst *__restrict__ insts, const int2 *__restrict__ b2i, int pc) {
+__global__ __launch_bounds__(NT) void k_diag(const Inst *__restrict__ insts, const int2 *__restrict__ b2i, int pc,
+                                             double *part = nullptr) {
   constexpr int Q = L::Q;
   const Inst *Ip;
   int lblk;
@@ -1556,7 +1561,7 @@ __global__ __launch_bounds__(NT) void k_diag(const Inst *__restrict__ insts, con
   if (threadIdx.x == 0) {
     double m = mred[0];
     for (int i = 1; i < NT / 64; ++i) m = fmax(m, mred[i]);
-    double *dst = I.part_d + (size_t)lblk * DIAG_PART;
+    double *dst = (part ? part + (size_t)I.blk0 * DIAG_PART : I.part_d) + (size_t)lblk * DIAG_PART;
     for (int k = 0; k < DIAG_SUMS; ++k) dst[k] = v[k];
     dst[DIAG_SUMS] = m;
   }
@@ -1565,10 +1570,11 @@ __global__ __launch_bounds__(NT) void k_diag(const Inst *__restrict__ insts, con
 // Diagnostics, second pass (one block per instance, fixed order): the
 // outputs of lbm_ehd_diagnostics, including the residual of the last
 // potential sub-iteration from k_mu's partials.
-__global__ __launch_bounds__(NT) void k_reduce_diag(const Inst *__restrict__ insts) {
+//   part: as for k_diag.
+__global__ __launch_bounds__(NT) void k_reduce_diag(const Inst *__restrict__ insts, const double *part = nullptr) {
   const Inst &I = insts[blockIdx.x];
   Ctl *ctl = I.ctl;
-  const double *pd = I.part_d;
+  const double *pd = part ? part + (size_t)I.blk0 * DIAG_PART : I.part_d;
   double s[DIAG_PART];
   reduce_partials<DIAG_PART>(pd, I.nblk, s);  // (the maximum's slot is summed too, unused)
   double r[2];
