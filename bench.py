@@ -43,8 +43,9 @@ def bytes_per_node(kernel, prec="fp32", Q=9, D=2):
         "poisson": (Q + 1 + 1) * t + Q * t,                # h, eps, q in; h out (one sub-iteration)
         "poisson2": (Q + 1 + 1) * t + Q * t,               # the same for two or four sub-iterations per launch
         "mu": (Q + 1 + 1 + 3) * t + (1 + D + 3) * t,        # h, eps, psi, phi in; psi, E, mu out
-        # pops in and out; phi, mu, q, R, E, history (phi_i u, q u) in; history out
-        "collide": 2 * pops + (3 + 3 + 1 + 1 + D + 4 * D) * t + 4 * D * t,
+        # pops in and out; phi and q of this and the previous step, mu, R, E,
+        # the previous velocity in; the velocity out (p, rho on output steps only)
+        "collide": 2 * pops + (3 + 3 + 3 + 1 + 1 + 1 + D + D) * t + D * t,
     }[kernel]
 
 
@@ -267,10 +268,20 @@ def adaptive_bench(p, init, steps, warmup, tol, kmax=64):
     ms = e0.elapsed_time(e1)
     k1 = sim.scalars()["k_total"]
     d = sim.diagnostics()
+    # the fixed-count run over the same steps: deformation and fields
+    fix = binding.Sim(p, init, precision="fp32")
+    fix.step(warmup + steps)
+    df = fix.diagnostics()
+    fa, fb = sim.fields(), fix.fields()
+    diff = {k: float((fa[k] - fb[k]).abs().max() / fb[k].abs().max()) for k in ("phi1", "ux", "psi", "Ey", "q", "mu1")}
     nodes = p["nx"] * p["ny"]
     return {"sub_tol": tol, "sub_max": kmax, "steps": steps, "mean_k": (k1 - k0) / steps,
             "mlups": round(nodes * steps / (ms * 1e-3) / 1e6, 1), "ms_per_step": ms / steps,
-            "last_residual": d["residual"], "status": d["status"]}
+            "last_residual": d["residual"], "status": d["status"],
+            "fixed_k": p["sub_max"], "fixed_k_last_residual": df["residual"],
+            "D_outer_diff_vs_fixed_k": abs(d["D_outer"] - df["D_outer"]),
+            "D_inner_diff_vs_fixed_k": abs(d["D_inner"] - df["D_inner"]),
+            "field_max_norm_diff_vs_fixed_k": diff}
 
 
 def d3q15_bench(n, steps, warmup, sub, init_iters, profile_steps):

@@ -33,11 +33,11 @@ struct Layout {
   int nblk;
 };
 // Macroscopic plane groups, each [k][nz][ny][nx] contiguous with plane
-// stride N: phi(3) lsum eps q R psi E(D) mu(3) u(D) p rho hpu(3D) hqu(D),
-// and the ion concentrations (2, Nernst-Planck model only)
-constexpr int N_GROUPS = 14;
+// stride N: phi(2 x 3) lsum eps q(2) R psi E(D) mu(3) u(D) p rho, and the ion
+// concentrations (2, Nernst-Planck model only)
+constexpr int N_GROUPS = 12;
 int group_planes(int g, int D, int nion) {
-  const int k[N_GROUPS] = {3, 1, 1, 1, 1, 1, D, 3, D, 1, 1, 3 * D, D, nion};
+  const int k[N_GROUPS] = {6, 1, 1, 2, 1, 1, D, 3, D, 1, 1, nion};
   return k[g];
 }
 int ion_planes(const lbm_ehd_params &p) { return p.charge_model == LBM_CHARGE_NERNST_PLANCK ? 2 : 0; }
@@ -425,15 +425,16 @@ int static_scratch(lbm_ehd_s *H, double **out) {
 // (D3Q15 boxes, 16-byte tangent values that leave no room for the tile) one
 // launch per iteration.  Returns the launch count
 // (its parity is the buffer flip of the whole loop).
+//   fb: the field buffer holding the charge (the step's; 1 at create).
 template <class Lat, typename T>
-int enqueue_fixed_potential(lbm_ehd_s *H, int K) {
+int enqueue_fixed_potential(lbm_ehd_s *H, int K, int fb) {
   const dim3 grid(H->plan.total_blocks), grid2(H->n_t2), block(NT), block2(P2NT);
   int L = 0, k = 1;
   if constexpr (sizeof(T) <= 8 && std::is_same<Lat, D2Q9>::value) {
     if (H->pairs()) {
       if (K & 1) {
         hipEvent_t e = H->prof_start(2);
-        k_poisson<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, 1, K, 0, 0);
+        k_poisson<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, 1, K, 0, 0, fb);
         H->prof_stop(e);
         L = 1;
         k = 2;
@@ -444,7 +445,7 @@ int enqueue_fixed_potential(lbm_ehd_s *H, int K) {
           for (; k + 3 <= K; k += 4, ++L) {
             hipEvent_t e = H->prof_start(6);
             k_poisson2<T, 2, 4><<<dim3(H->plan.total_tiles4), block2, 0, H->stream>>>(H->d_insts, H->d_t4, L & 1,
-                                                                                      k + 3 == K ? 1 : 0);
+                                                                                      k + 3 == K ? 1 : 0, fb);
             H->prof_stop(e);
           }
       }
@@ -453,11 +454,11 @@ int enqueue_fixed_potential(lbm_ehd_s *H, int K) {
         const int last = k + 1 == K ? 1 : 0;
         if constexpr (sizeof(T) <= 8) {
           if (H->tall())
-            k_poisson2<T, 2><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, last);
+            k_poisson2<T, 2><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, last, fb);
           else
-            k_poisson2<T, 1><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, last);
+            k_poisson2<T, 1><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, last, fb);
         } else {
-          k_poisson2<T, 1><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, last);
+          k_poisson2<T, 1><<<grid2, block2, 0, H->stream>>>(H->d_insts, H->d_t2, L & 1, last, fb);
         }
         H->prof_stop(e);
       }
@@ -466,7 +467,7 @@ int enqueue_fixed_potential(lbm_ehd_s *H, int K) {
   }
   for (; k <= K; ++k, ++L) {
     hipEvent_t e = H->prof_start(2);
-    k_poisson<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, k, K, 0, L & 1);
+    k_poisson<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, k, K, 0, L & 1, fb);
     H->prof_stop(e);
   }
   return L;
@@ -492,7 +493,8 @@ int do_create(lbm_ehd_s *H, const lbm_ehd_init *init) {
       return LBM_EHD_OK;
     };
     int rc;
-    if ((rc = up(init[i].phi0, I.phi, 3))) return rc;
+    // create's fields live in field buffer 1 (the first step's previous level)
+    if ((rc = up(init[i].phi0, I.phi[1], 3))) return rc;
     if ((rc = up(init[i].u0, I.u, (size_t)Lat::D))) return rc;
     if (H->params[i].charge_model == LBM_CHARGE_NERNST_PLANCK) {
       // ion concentrations and the charge they carry, q = e (n_+ - n_-)
@@ -500,8 +502,8 @@ int do_create(lbm_ehd_s *H, const lbm_ehd_init *init) {
       if ((rc = up(c, I.ion, 2))) return rc;
       std::vector<double> q0(N);
       for (size_t k = 0; k < N; ++k) q0[k] = e * (c[k] - c[N + k]);
-      if ((rc = up(q0.data(), I.q, 1))) return rc;
-    } else if ((rc = up(init[i].q0, I.q, 1))) {
+      if ((rc = up(q0.data(), I.q[1], 1))) return rc;
+    } else if ((rc = up(init[i].q0, I.q[1], 1))) {
       return rc;
     }
     if constexpr (std::is_same<T, DualD>::value) {
@@ -530,13 +532,13 @@ int do_create(lbm_ehd_s *H, const lbm_ehd_init *init) {
   const int chunk = 256;
   int nlaunch = 0;
   if (!adaptive) {
-    nlaunch = enqueue_fixed_potential<Lat, T>(H, kmax);
+    nlaunch = enqueue_fixed_potential<Lat, T>(H, kmax, 1);
     HIPC(H, hipGetLastError());
   }
   for (int k0 = 1; adaptive && k0 <= kmax; k0 += chunk) {
     const int k1 = std::min(kmax, k0 + chunk - 1);
     for (int k = k0; k <= k1; ++k) {
-      k_poisson<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, k, kmax, 1, 0);
+      k_poisson<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, k, kmax, 1, 0, 1);
       k_reduce_poisson<<<H->n_inst, block, 0, H->stream>>>(H->d_insts, k, 1, p0.init_tol);
     }
     HIPC(H, hipGetLastError());
@@ -551,7 +553,7 @@ int do_create(lbm_ehd_s *H, const lbm_ehd_init *init) {
     if (all) break;
   }
   const int hofs = adaptive ? 0 : (nlaunch & 1);
-  k_mu<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, hofs);
+  k_mu<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, hofs, 1);
   k_init_pops<Lat, T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, hofs);
   HIPC(H, hipGetLastError());
   HIPC(H, hipStreamSynchronize(H->stream));
@@ -579,21 +581,21 @@ int do_step(lbm_ehd_s *H, int64_t n) {
     if (!vec) k_moments<Lat, T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, pc);
     H->prof_stop(e);
     e = H->prof_start(1);
-    k_pre<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i);
+    k_pre<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, pc);
     H->prof_stop(e);
     int hflip = 0;
     if (ad) {
       for (int k = 1; k <= K; ++k) {
         e = H->prof_start(2);
-        k_poisson<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, k, K, 1, 0);
+        k_poisson<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, k, K, 1, 0, pc);
         H->prof_stop(e);
         k_reduce_poisson<<<H->n_inst, block, 0, H->stream>>>(H->d_insts, k, H->sub_min, H->sub_tol, K);
       }
     } else {
-      hflip = enqueue_fixed_potential<Lat, T>(H, K) & 1;
+      hflip = enqueue_fixed_potential<Lat, T>(H, K, pc) & 1;
     }
     e = H->prof_start(3);
-    k_mu<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, hflip);
+    k_mu<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, hflip, pc);
     H->prof_stop(e);
     e = H->prof_start(4);
     if (sizeof(T) <= 4 && !(H->tuning & LBM_TUNE_COLLIDE_PER_FAMILY))
@@ -617,7 +619,7 @@ int do_diag(lbm_ehd_s *H, double *part) {
   hipEvent_t e = H->prof_start(5);
   k_diag<Lat, T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, (int)(H->steps & 1), part);
   k_reduce_diag<<<H->n_inst, block, 0, H->stream>>>(H->d_insts, part);
-  k_contour<Lat, T><<<H->n_inst, block, 0, H->stream>>>(H->d_insts);
+  k_contour<Lat, T><<<H->n_inst, block, 0, H->stream>>>(H->d_insts, (int)((H->steps + 1) & 1));
   H->prof_stop(e);
   HIPC(H, hipGetLastError());
   return LBM_EHD_OK;
@@ -775,12 +777,14 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
       I.h[b] = H->ws + L.h[b];
     }
     char *base = H->ws + L.planes;
-    void **group[N_GROUPS] = {&I.phi, &I.lsum, &I.eps, &I.q, &I.R, &I.psi, &I.E,
-                              &I.mu, &I.u, &I.p, &I.rho, &I.hpu, &I.hqu, &I.ion};
+    void **group[N_GROUPS] = {&I.phi[0], &I.lsum, &I.eps, &I.q[0], &I.R, &I.psi, &I.E,
+                              &I.mu, &I.u, &I.p, &I.rho, &I.ion};
     for (int g = 0; g < N_GROUPS; ++g) {
       *group[g] = base;
       base += align_up(group_planes(g, lat_d(p), ion_planes(p)) * (size_t)I.N * te);
     }
+    I.phi[1] = (char *)I.phi[0] + 3 * (size_t)I.N * te;
+    I.q[1] = (char *)I.q[0] + (size_t)I.N * te;
     if (!ion_planes(p)) I.ion = nullptr;
     I.part_p = (double *)(H->ws + L.part_p);
     I.part_mu = (double *)(H->ws + L.part_mu);
@@ -959,10 +963,10 @@ void step_record(lbm_ehd_s *W, char *slot) {
         <<<dim3(W->plan.total_blocks4 * (4 / MW)), block, 0, W->stream>>>(W->d_insts, W->d_b2i4, pc, rc);
   else
     k_moments<D2Q9, T, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, pc, rc);
-  k_pre<D2Q9, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, rc);
+  k_pre<D2Q9, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, pc, rc);
   int L = 0, k = 1;
   if (K & 1) {
-    k_poisson<D2Q9, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, 1, K, 0, 0, rec_level<T>(slot, N, 0));
+    k_poisson<D2Q9, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, 1, K, 0, 0, pc, rec_level<T>(slot, N, 0));
     L = 1;
     k = 2;
   }
@@ -972,17 +976,18 @@ void step_record(lbm_ehd_s *W, char *slot) {
       // four sub-iterations per launch while four remain, then tall pairs
       for (; k + 3 <= K; k += 4, ++L)
         k_poisson2<T, 2, 4><<<dim3(W->plan.total_tiles4), block2, 0, W->stream>>>(
-            W->d_insts, W->table(2), L & 1, k + 3 == K ? 1 : 0, P2Rec<T, 4>{{lev(k - 1), lev(k), lev(k + 1), lev(k + 2)}});
+            W->d_insts, W->table(2), L & 1, k + 3 == K ? 1 : 0, pc,
+            P2Rec<T, 4>{{lev(k - 1), lev(k), lev(k + 1), lev(k + 2)}});
       for (; k + 1 <= K; k += 2, ++L)
         k_poisson2<T, 2><<<dim3(W->plan.total_tiles2t), block2, 0, W->stream>>>(
-            W->d_insts, W->table(1), L & 1, k + 1 == K ? 1 : 0, P2Rec<T, 2>{{lev(k - 1), lev(k)}});
+            W->d_insts, W->table(1), L & 1, k + 1 == K ? 1 : 0, pc, P2Rec<T, 2>{{lev(k - 1), lev(k)}});
     }
   }
   for (; k + 1 <= K; k += 2, ++L)
     k_poisson2<T><<<dim3(W->plan.total_tiles2), block2, 0, W->stream>>>(
-        W->d_insts, W->table(0), L & 1, k + 1 == K ? 1 : 0, P2Rec<T, 2>{{lev(k - 1), lev(k)}});
+        W->d_insts, W->table(0), L & 1, k + 1 == K ? 1 : 0, pc, P2Rec<T, 2>{{lev(k - 1), lev(k)}});
   const int hflip = L & 1;
-  k_mu<D2Q9, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, hflip, rc);
+  k_mu<D2Q9, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, hflip, pc, rc);
   if (sizeof(T) <= 4 && (W->tuning & LBM_TUNE_COLLIDE_PER_FAMILY))
     k_collide<D2Q9, T, T, false><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, pc, 0, K, hflip, rc);
   else
@@ -1112,7 +1117,7 @@ int reverse_sweep(lbm_ehd_s *H, lbm_ehd_s *W, char *work, const AdjLayout &L, in
     if (rc) return H->fail(rc, "adjoint: restore: %s", W->err.c_str());
     k_adj_init_pops<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, ab, cur);
     Rec<T> rc0{};
-    rc0.phi = (T *)I.phi;
+    rc0.phi = (T *)I.phi[1];  // create's fields: buffer 1
     rc0.eps = (T *)I.eps;
     rc0.En = (T *)I.E;
     k_adj_mu<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, rc0, ab, cur, hs, 0);
@@ -1144,7 +1149,7 @@ int reverse_sweep(lbm_ehd_s *H, lbm_ehd_s *W, char *work, const AdjLayout &L, in
                                W->stream));
       if (k + 1 < kck)
         k_poisson_buf<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, cold[cp], cold[cp ^ 1],
-                                                        (const T *)I.eps, (const T *)I.q, nullptr);
+                                                        (const T *)I.eps, (const T *)I.q[1], nullptr);
       cp ^= 1;
     }
     for (int c = L.cold_chunks - 1; c >= 0; --c) {
@@ -1153,7 +1158,7 @@ int reverse_sweep(lbm_ehd_s *H, lbm_ehd_s *W, char *work, const AdjLayout &L, in
       cp = 0;
       for (int k = ka; k < kb; ++k) {
         k_poisson_buf<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, cold[cp], cold[cp ^ 1],
-                                                        (const T *)I.eps, (const T *)I.q, lev + (size_t)(k - ka) * lv);
+                                                        (const T *)I.eps, (const T *)I.q[1], lev + (size_t)(k - ka) * lv);
         cp ^= 1;
       }
       for (int k = kb - 1; k >= ka;) {
@@ -1173,7 +1178,7 @@ int reverse_sweep(lbm_ehd_s *H, lbm_ehd_s *W, char *work, const AdjLayout &L, in
     }
   }
   if (n_steps >= 1)
-    k_adj_create_tail<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, ab, hs, (const T *)I.phi, psi0, mean,
+    k_adj_create_tail<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, ab, hs, (const T *)I.phi[1], psi0, mean,
                                                         inv_e0);
   double *out = (double *)(work + L.out);
   k_adj_reduce<<<1, block, 0, W->stream>>>(ab.tb, L.tb_slots, out);
@@ -1259,15 +1264,17 @@ int lbm_ehd_graph(lbm_ehd_t H, int32_t steps_per_graph) {
   return LBM_EHD_OK;
 }
 
-static void *field_src(const Inst &I, int bit) {
+// Plane group of output field `bit`; fb: the field buffer of the last step
+// (or of create), (steps + 1) & 1.
+static void *field_src(const Inst &I, int bit, int fb) {
   switch (bit) {
-    case 0: case 1: case 2: return I.phi;  // offset applied by caller
+    case 0: case 1: case 2: return I.phi[fb];  // offset applied by caller
     case 3: return I.rho;
     case 4: case 5: return I.u;
     case 6: return I.p;
     case 7: return I.psi;
     case 8: case 9: return I.E;
-    case 10: return I.q;
+    case 10: return I.q[fb];
     case 11: case 12: case 13: return I.mu;
     case 14: return I.eps;
     case 15: return I.R;
@@ -1300,7 +1307,7 @@ int lbm_ehd_fields(lbm_ehd_t H, int32_t inst, uint32_t mask, void *dev_dst, int3
   char *dst = (char *)dev_dst;
   for (int bit = 0; bit < 20; ++bit) {
     if (!(mask & (1u << bit))) continue;
-    const char *src = (const char *)field_src(I, bit) + field_sub(bit) * N * te;
+    const char *src = (const char *)field_src(I, bit, (int)((H->steps + 1) & 1)) + field_sub(bit) * N * te;
     int rc = convert_any(H, (int)te, src, dst, M, dtype);
     if (rc) return rc;
     dst += M * de;
@@ -1550,7 +1557,7 @@ int lbm_ehd_tangent_gradient(lbm_ehd_t H, int64_t n_steps, const void *dev_seed,
     sp.count = 0;
     for (int bit = 0; bit < 20; ++bit)
       if (seed_mask & (1u << bit))
-        sp.plane[sp.count++] = (const DualD *)field_src(I, bit) + (size_t)field_sub(bit) * I.N;
+        sp.plane[sp.count++] = (const DualD *)field_src(I, bit, (int)((T->steps + 1) & 1)) + (size_t)field_sub(bit) * I.N;
     k_seed_dot<<<dim3(I.nblk), dim3(NT), 0, T->stream>>>(T->d_insts, sp, (const double *)dev_seed);
     k_reduce_seed_dot<<<1, NT, 0, T->stream>>>(T->d_insts);
     Ctl c;

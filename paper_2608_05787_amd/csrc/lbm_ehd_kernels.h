@@ -131,8 +131,12 @@ struct Inst {
                                      // blk0: node blocks of the instances before this one
   void *f[2], *g[2], *l[2], *h[2];
   float *f0[2];  // FP16S only: FP32 rest populations f^i_0, [3][N]
-  // planes: phi 3, lsum, eps, q, R, psi, E D, mu 3, u D, p, rho, hpu 3D, hqu D
-  void *phi, *lsum, *eps, *q, *R, *psi, *E, *mu, *u, *p, *rho, *hpu, *hqu;
+  // planes: phi 3 (two buffers), lsum, eps, q (two buffers), R, psi, E D,
+  // mu 3, u D, p, rho.  The order parameters and the charge formed in step n
+  // are in buffer n & 1 (create's initial fields in buffer 1), so the
+  // collide kernel finds the previous step's at its node for the time
+  // derivatives of phi_i u and q u.
+  void *phi[2], *lsum, *eps, *q[2], *R, *psi, *E, *mu, *u, *p, *rho;
   void *ion;  // Nernst-Planck: n_+, n_- [2][N] (null otherwise)
   double *part_p;   // potential residual partials, nblk x 2
   double *part_mu;  // last-iteration residual partials, nblk x 2
@@ -425,7 +429,7 @@ __global__ __launch_bounds__(NT) void k_moments(const Inst *__restrict__ insts, 
   const int fb = fbuf(I, pc);
   auto f = gbl((const S *)I.f[fb]);
   auto l = gbl((const S *)I.l[pc]);
-  auto phi = gbl((T *)I.phi);
+  auto phi = gbl((T *)I.phi[pc]);
   // Every load before the first store: a store to a plane the compiler
   // cannot tell apart from the loaded ones would hold back the later loads.
   const bool ions = I.charge_model == 1;
@@ -540,7 +544,7 @@ __global__ __launch_bounds__(NT) void k_moments4(const Inst *__restrict__ insts,
     for (int j = 0; j < Q; ++j) lv[j] = l[(size_t)j * NV + bv];
   }
   constexpr bool split = PopIO<S, T>::split;
-  const GVW phi = (GVW)I.phi;
+  const GVW phi = (GVW)I.phi[pc];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     V a = split ? fv[i][0] : V(T(0));
@@ -558,8 +562,9 @@ __global__ __launch_bounds__(NT) void k_moments4(const Inst *__restrict__ insts,
 // a2 + a3: permittivity/conductivity stencils (Eq. 33 on the eps and sigma
 // fields of Eqs. 29-30), charge recovery q = (sum l + R'/2)/(1 + sigma/(2 eps))
 // and the Ohmic source R of Eq. (47) with the previous step's field.
+//   pc: the step's field buffer.
 template <class L, typename T>
-__global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
+__global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, const int2 *__restrict__ b2i, int pc,
                                             Rec<T> rc = Rec<T>{}) {
   constexpr int Q = L::Q, D = L::D;
   const Inst *Ip;
@@ -569,7 +574,7 @@ __global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, cons
   const Inst &I = *Ip;
   const Phys<T> &P = phys<T>(I);
   const int N = I.N, n = nd.n;
-  auto phi = gbl((const T *)I.phi);
+  auto phi = gbl((const T *)I.phi[pc]);
   // the node's own loads first: issued with the stencil's, one memory
   // round trip for the whole kernel
   auto E = gbl((const T *)I.E);
@@ -602,7 +607,7 @@ __global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, cons
   }
   const T Rp = se * gee - gse;
   const T q = (lsum + T(0.5) * Rp) / (T(1) + T(0.5) * se);
-  (gbl((T *)I.q))[n] = q;
+  (gbl((T *)I.q[pc]))[n] = q;
   (gbl((T *)I.R))[n] = -se * q + Rp;
   (gbl((T *)I.eps))[n] = ev[0];
   if (rc.q) {
@@ -668,10 +673,11 @@ __device__ __forceinline__ T poisson_collide(const T (&h)[L::Q], T epshat, T q, 
 //   Adaptive: skipped once the loop has converged; stores the potential of
 //   its input and, from k = 2 on, the residual partials of the previous
 //   iteration for k_reduce_poisson.
+//   fb: the field buffer holding the charge (the step's; 1 at create).
 //   rec_in: when set, receives the input level (recording runs).
 template <class L, typename T>
 __global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
-                                                int k, int K, int adaptive, int hpar, T *rec_in = nullptr) {
+                                                int k, int K, int adaptive, int hpar, int fb, T *rec_in = nullptr) {
   constexpr int Q = L::Q;
   const Inst *Ip;
   int lblk;
@@ -693,7 +699,7 @@ __global__ __launch_bounds__(NT) void k_poisson(const Inst *__restrict__ insts, 
 #pragma unroll
     for (int j = 0; j < Q; ++j) h[j] = src[(size_t)j * N + n];
     const T epshat = (gbl((const T *)I.eps))[n] - P.eps_ref;
-    const T q = (gbl((const T *)I.q))[n];
+    const T q = (gbl((const T *)I.q[fb]))[n];
     auto psi = gbl((T *)I.psi);
     const T psi_prev = resid ? psi[n] : T(0);
     if (rec_in)
@@ -754,7 +760,7 @@ template <typename T> struct P2Meta {
 };
 
 template <typename T>
-__device__ __forceinline__ P2Meta<T> p2_meta(const Inst *insts, const int4 *tiles, int ti, int hpar, int4 &t) {
+__device__ __forceinline__ P2Meta<T> p2_meta(const Inst *insts, const int4 *tiles, int ti, int hpar, int fb, int4 &t) {
   const cptr<int> tp = cst((const int *)tiles) + 4 * (size_t)ti;
   t = make_int4(tp[0], tp[1], tp[2], 0);
   const cptr<Inst> I = cst(insts) + t.x;
@@ -763,7 +769,7 @@ __device__ __forceinline__ P2Meta<T> p2_meta(const Inst *insts, const int4 *tile
   m.src = (const T *)I->h[hc];
   m.dst = (T *)I->h[hc ^ 1];
   m.eps = (const T *)I->eps;
-  m.q = (const T *)I->q;
+  m.q = (const T *)I->q[fb];
   m.psi = (T *)I->psi;
   m.nx = I->nx;
   m.ny = I->ny;
@@ -910,14 +916,15 @@ __device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int wri
 }
 
 //   tiles: (instance, x0, y0, -) per block.
+//   fb: the field buffer holding the charge (the step's; 1 at create).
 //   rec: the input levels of the sub-iterations, for recording runs.
 template <typename T, int RPT = 1, int IT = 2>
 __global__ __launch_bounds__(P2NT, (sizeof(T) == 8 && RPT == 2) ? 4 : 8) void k_poisson2(const Inst *__restrict__ insts, const int4 *__restrict__ tiles,
-                                                 int hpar, int write_psi, P2Rec<T, IT> rec = P2Rec<T, IT>{}) {
+                                                 int hpar, int write_psi, int fb, P2Rec<T, IT> rec = P2Rec<T, IT>{}) {
   constexpr int ER = P2Shape<RPT, IT>::ER;
   __shared__ T buf[Q * P2EW * ER];
   int4 t;
-  const P2Meta<T> m = p2_meta<T>(insts, tiles, blockIdx.x, hpar, t);
+  const P2Meta<T> m = p2_meta<T>(insts, tiles, blockIdx.x, hpar, fb, t);
   P2Regs<T, RPT> s;
   p2_load<T, RPT, IT>(m, t, s);
   p2_run<T, RPT, IT>(m, t, write_psi, rec, s, buf);
@@ -954,9 +961,10 @@ __global__ __launch_bounds__(NT) void k_reduce_poisson(const Inst *__restrict__ 
 //   hofs: buffer offset of the final h relative to ctl->hcur (fixed count:
 //   parity of the potential launches; adaptive: 0, the control pass already
 //   flipped it).
+//   pc: the step's field buffer (1 at create).
 template <class L, typename T>
 __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
-                                           int hofs, Rec<T> rc = Rec<T>{}) {
+                                           int hofs, int pc, Rec<T> rc = Rec<T>{}) {
   constexpr int Q = L::Q, D = L::D;
   const Inst *Ip;
   int lblk;
@@ -990,7 +998,7 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
     // the phi stencils and the previous potential, loaded before the first
     // store (later loads would wait for it: the compiler cannot tell the
     // planes apart)
-    auto phi = gbl((const T *)I.phi);
+    auto phi = gbl((const T *)I.phi[pc]);
     T pv[3][Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
@@ -1062,7 +1070,7 @@ __global__ __launch_bounds__(NT, (EARLY || sizeof(T) > 4 || L::Q > 9) ? 1 : 4) v
   if (nd.valid) {
     const Phys<T> &P = phys<T>(I);
     const int N = I.N, n = nd.n;
-    auto phi = gbl((const T *)I.phi);
+    auto phi = gbl((const T *)I.phi[pc]);
     auto mu = gbl((const T *)I.mu);
     int m[Q];
 #pragma unroll
@@ -1092,7 +1100,7 @@ __global__ __launch_bounds__(NT, (EARLY || sizeof(T) > 4 || L::Q > 9) ? 1 : 4) v
       muc[i] = v[0];
     }
     const T rho = rv[0];
-    const T q = (gbl((const T *)I.q))[n];
+    const T q = (gbl((const T *)I.q[pc]))[n];
     auto E = gbl((const T *)I.E);
 
     // force and flow moments
@@ -1103,7 +1111,7 @@ __global__ __launch_bounds__(NT, (EARLY || sizeof(T) > 4 || L::Q > 9) ? 1 : 4) v
 #pragma unroll
       for (int i = 0; i < 3; ++i) F[d] -= ph[i] * gm[i][d];
     }
-    // Load schedule.  EARLY: every population and history value is loaded
+    // Load schedule.  EARLY: every population and previous-step value is loaded
     // before the first store (the stores, to buffers the compiler cannot
     // tell apart from the loaded ones, would otherwise hold back the loads
     // issued after them): most loads in flight, ~160 VGPRs.  Otherwise each
@@ -1117,9 +1125,11 @@ __global__ __launch_bounds__(NT, (EARLY || sizeof(T) > 4 || L::Q > 9) ? 1 : 4) v
     auto gs = gbl((const S *)I.g[pc]);
     auto fs = gbl((const S *)I.f[fbs]);
     auto ls = gbl((const S *)I.l[pc]);
-    auto hpu = gbl((T *)I.hpu);
-    auto hqu = gbl((T *)I.hqu);
-    T g[Q], fin[3][Q], lin[Q], hp0[3][D], hq0[D];
+    // the previous step's phi_i, q (the other field buffer) and u at this node
+    auto php = gbl((const T *)I.phi[pc ^ 1]);
+    auto qp = gbl((const T *)I.q[pc ^ 1]);
+    auto uu = gbl((T *)I.u);
+    T g[Q], fin[3][Q], lin[Q], ph0[3], u0[D], q0 = 0;
 #pragma unroll
     for (int j = 0; j < Q; ++j) g[j] = IO::ld(gs, (size_t)j * N + n, T(SC_G));
     auto ldf = [&](int i, int j) -> T {
@@ -1136,14 +1146,14 @@ __global__ __launch_bounds__(NT, (EARLY || sizeof(T) > 4 || L::Q > 9) ? 1 : 4) v
 #pragma unroll
       for (int j = 0; j < Q; ++j) lin[j] = IO::ld(ls, (size_t)j * N + n, T(SC_L));
     const T R = (gbl((const T *)I.R))[n];
-    if (early) {
+    auto ld_prev = [&]() {
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
+      for (int i = 0; i < 3; ++i) ph0[i] = php[(size_t)i * N + n];
 #pragma unroll
-        for (int d = 0; d < D; ++d) hp0[i][d] = hpu[(size_t)(i * D + d) * N + n];
-#pragma unroll
-      for (int d = 0; d < D; ++d) hq0[d] = hqu[(size_t)d * N + n];
-    }
+      for (int d = 0; d < D; ++d) u0[d] = uu[(size_t)d * N + n];
+      q0 = qp[n];
+    };
+    if (early) ld_prev();
     if (rc.g)
 #pragma unroll
       for (int j = 0; j < Q; ++j) rc.g[(size_t)j * N + n] = g[j];
@@ -1176,28 +1186,28 @@ __global__ __launch_bounds__(NT, (EARLY || sizeof(T) > 4 || L::Q > 9) ? 1 : 4) v
       for (int d = 0; d < D; ++d) ok = ok && isfinite((double)u[d]);
       if (!ok) atomicOr(&I.ctl->status, ST_DIVERGED);
     }
-    if (write_macro) {
-#pragma unroll
-      for (int d = 0; d < D; ++d) (gbl((T *)I.u))[(size_t)d * N + n] = u[d];
-      (gbl((T *)I.p))[n] = pp;
-      (gbl((T *)I.rho))[n] = rho;
-    }
-
-    // history of phi_i u and q u (first-order time derivatives)
+    if (!early) ld_prev();
+    // first-order time derivatives of phi_i u and q u against the previous
+    // step's values (the products formed as the previous step formed them)
     T dp[3][D], dq[D];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        const T a = ph[i] * u[d];
-        dp[i][d] = a - (early ? hp0[i][d] : hpu[(size_t)(i * D + d) * N + n]);
-        hpu[(size_t)(i * D + d) * N + n] = a;
+        const T b = ph0[i] * u0[d];
+        dp[i][d] = ph[i] * u[d] - b;
       }
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      const T a = q * u[d];
-      dq[d] = a - (early ? hq0[d] : hqu[(size_t)d * N + n]);
-      hqu[(size_t)d * N + n] = a;
+      const T b = q0 * u0[d];
+      dq[d] = q * u[d] - b;
+    }
+    // u every step (the next step's previous velocity); p and rho for output
+#pragma unroll
+    for (int d = 0; d < D; ++d) uu[(size_t)d * N + n] = u[d];
+    if (write_macro) {
+      (gbl((T *)I.p))[n] = pp;
+      (gbl((T *)I.rho))[n] = rho;
     }
 
     const int nc = pc ^ 1;
@@ -1327,7 +1337,7 @@ __global__ __launch_bounds__(NT) void k_init_potential(const Inst *__restrict__ 
   const Inst &I = *Ip;
   const Phys<T> &P = phys<T>(I);
   const int N = I.N, n = nd.n;
-  auto phi = gbl((const T *)I.phi);
+  auto phi = gbl((const T *)I.phi[1]);  // create's fields: buffer 1
   (gbl((T *)I.eps))[n] = P.eps[0] * herm(phi[n]) + P.eps[1] * herm(phi[(size_t)N + n]) + P.eps[2] * herm(phi[(size_t)2 * N + n]);
   const T v = (gbl((const T *)I.psi))[n] - psi_ref<T>(P, nd.y);  // stored as the deviation
   auto h = gbl((T *)I.h[I.ctl->hcur]);
@@ -1335,8 +1345,9 @@ __global__ __launch_bounds__(NT) void k_init_potential(const Inst *__restrict__ 
   for (int j = 0; j < Q; ++j) h[(size_t)j * N + n] = j == 0 ? (lw<L, T>(0) - T(1)) * v : lw<L, T>(j) * v;
 }
 
-// Equilibria of the initial fields (p = 0) into buffer 0 and the history
-// planes; block 0 folds the cold start's buffer parity hofs into ctl->hcur.
+// Equilibria of the initial fields (p = 0) into population buffer 0 (the
+// initial fields in field buffer 1 and u serve as the first step's previous
+// values); block 0 folds the cold start's buffer parity hofs into ctl->hcur.
 template <class L, typename T, typename S>
 __global__ __launch_bounds__(NT) void k_init_pops(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
                                                   int hofs) {
@@ -1349,7 +1360,7 @@ __global__ __launch_bounds__(NT) void k_init_pops(const Inst *__restrict__ insts
   if (!nd.valid) return;
   const Phys<T> &P = phys<T>(I);
   const int N = I.N, n = nd.n, pc = 0;
-  auto phi = gbl((const T *)I.phi);
+  auto phi = gbl((const T *)I.phi[1]);
   auto mu = gbl((const T *)I.mu);
   T u[D], usq = 0;
 #pragma unroll
@@ -1357,11 +1368,10 @@ __global__ __launch_bounds__(NT) void k_init_pops(const Inst *__restrict__ insts
     u[d] = (gbl((const T *)I.u))[(size_t)d * N + n];
     usq += u[d] * u[d];
   }
-  const T q = (gbl((const T *)I.q))[n];
+  const T q = (gbl((const T *)I.q[1]))[n];
   T rho = 0;
   using IO = PopIO<S, T>;
   auto f = gbl((S *)I.f[pc]);
-  auto hpu = gbl((T *)I.hpu);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const T ph = phi[(size_t)i * N + n], m = mu[(size_t)i * N + n];
@@ -1377,8 +1387,6 @@ __global__ __launch_bounds__(NT) void k_init_pops(const Inst *__restrict__ insts
       moved += IO::back(st, T(SC_F));
     }
     if (IO::split) gbl(I.f0[pc])[(size_t)i * N + n] = (float)(ph - moved);
-#pragma unroll
-    for (int d = 0; d < D; ++d) hpu[(size_t)(i * D + d) * N + n] = ph * u[d];
   }
   auto g = gbl((S *)I.g[pc]);
   auto l = gbl((S *)I.l[pc]);
@@ -1404,8 +1412,6 @@ __global__ __launch_bounds__(NT) void k_init_pops(const Inst *__restrict__ insts
         IO::put(l, (size_t)(k * Q + j) * N + n, IO::cv(lw<L, T>(j) * ns * (T(1) + cdot<L>(j, w) * T(3)), T(SC_L)));
     }
   }
-#pragma unroll
-  for (int d = 0; d < D; ++d) (gbl((T *)I.hqu))[(size_t)d * N + n] = q * u[d];
   (gbl((T *)I.p))[n] = T(0);
   (gbl((T *)I.rho))[n] = rho;
   (gbl((T *)I.R))[n] = T(0);
@@ -1518,12 +1524,13 @@ __global__ __launch_bounds__(NT) void k_diag(const Inst *__restrict__ insts, con
   double mx = 0.0;
   if (nd.valid) {
     const int N = I.N, n = nd.n;
-    auto phi = gbl((const T *)I.phi);
+    // pc: the next step's population buffer; the last step's fields are in pc ^ 1
+    auto phi = gbl((const T *)I.phi[pc ^ 1]);
     const double p1 = (double)phi[n], p2 = (double)phi[(size_t)N + n], p3 = (double)phi[(size_t)2 * N + n];
     v[0] = p1;
     v[1] = p2;
+    v[3] = (double)(gbl((const T *)I.q[pc ^ 1]))[n];
     v[2] = p3;
-    v[3] = (double)(gbl((const T *)I.q))[n];
     mx = fabs(p1 + p2 + p3 - 1.0);
     using IO = PopIO<S, T>;
     int bad = 0;
@@ -1623,12 +1630,13 @@ __global__ __launch_bounds__(NT) void k_reduce_diag(const Inst *__restrict__ ins
 // linear interpolation.  A line that meets a wall first, or never drops
 // below 1/2, gives nan.  Outputs diag[8..9] (D) and diag[12..15] (r_par,
 // r_perp of the outer drop, then of the inner).
+//   fb: the field buffer of the last step.
 template <class L, typename T>
-__global__ __launch_bounds__(NT) void k_contour(const Inst *__restrict__ insts) {
+__global__ __launch_bounds__(NT) void k_contour(const Inst *__restrict__ insts, int fb) {
   const Inst &I = insts[blockIdx.x];
   double *out = I.ctl->diag;
   const int nx = I.nx, ny = I.ny, nz = L::D == 3 ? I.nz : 1;
-  const T *phi = (const T *)I.phi;
+  const T *phi = (const T *)I.phi[fb];
   __shared__ int kmin[NT / 64];
   const double nan = __builtin_nan("");
   for (int d = 0; d < 2; ++d) {
