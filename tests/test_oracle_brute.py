@@ -7,7 +7,8 @@ transcription slip in either (an index, a sign, a dropped term) shows up as
 a difference far above round-off.  Every field and population family is
 compared after create and after several steps, with walls, electrodes,
 shear, an applied field, charge, unequal properties, a residual-controlled
-potential loop, a Dirichlet charge wall and frozen phases.
+potential loop, the order-parameter sum relaxation from fields whose sum is
+off one, a Dirichlet charge wall and frozen phases.
 """
 import numpy as np
 import pytest
@@ -28,6 +29,11 @@ def _cases():
     yield "ragged_7x5_K3", p, init, 3
     p, init = I.parity_case(8, 8, seed=14, sub=(1, 6, 1e-3))
     yield "adaptive_potential", p, init, 3
+    p, init = I.parity_case(8, 7, seed=15)
+    p["sum_relax"] = 1
+    rng = np.random.default_rng(15)
+    init = dict(init, phi0=init["phi0"] * (1.0 + 0.03 * rng.standard_normal(init["phi0"].shape)))
+    yield "sum_relax_off_one", p, init, 4
     p, init, _ = I.eof_channel(nx=3, ny=8, debye=2.0)
     p["init_sub_max"] = 50
     yield "frozen_dirichlet_charge", p, init, 5
