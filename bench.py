@@ -79,6 +79,25 @@ def measured_traffic(kernel, launch_nodes):
     return float(k["bytes_per_launch"]) if k.get("nodes") == launch_nodes else None
 
 
+def copy_rate(mib=1024, reps=20):
+    """Bytes moved per second (read + write) by a plain device-to-device copy
+    of `mib` MiB, the streaming rate a memory-bound kernel can hope for."""
+    import torch
+    a = torch.ones(mib * 262144, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    s = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    return round(2 * mib * 2 ** 20 / s / 1e9, 1)
+
+
 def workload(n, sub, init_iters):
     """Fixed cold-start count, so that every precision starts from the same
     potential iterate."""
@@ -437,6 +456,7 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy of %d MiB done" % args.calib_copy_mib)
         del a, b
+    copy_gbs = copy_rate() if args.profile_steps > 0 else None
     p, init = workload(args.n, args.sub, args.init_iters)
     nodes = p["nx"] * p["ny"]
     sim, ms, prof, diag, tune = run_gpu(p, init, "fp32", args.steps, args.warmup, args.profile_steps,
@@ -461,7 +481,10 @@ def main():
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "bytes_per_launch": bpl, "bytes_per_node": BYTES_PER_NODE_FP32[dom],
-                    "traffic": measured_traffic(dom, nodes)}
+                    "traffic": measured_traffic(dom, nodes),
+                    # context: a plain device copy (read + write) on the same GPU
+                    "copy_gbs": copy_gbs,
+                    "frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs else None}
         for k, v in kernels.items():
             if k in BYTES_PER_NODE_FP32:
                 v["gbs"] = round(BYTES_PER_NODE_FP32[k] * nodes / (v["avg_us"] * 1e-6) / 1e9, 1)

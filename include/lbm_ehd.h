@@ -140,6 +140,18 @@ enum { LBM_POP_F = 0, LBM_POP_G = 1, LBM_POP_L = 2, LBM_POP_H = 3 };
  *                Requires sigma = 0 (ions carry the current), wall_q_mode 0,
  *                FP32, FP64 or tangent precision, and init ions0; forward
  *                mode only (reverse-mode gradients are refused).
+ *  sum_relax     0: the CH equilibria of Eq. (35) as printed.  1: the rest
+ *                component of each CH equilibrium carries phi_i / S, S =
+ *                phi_1 + phi_2 + phi_3, instead of phi_i, so that every
+ *                collision returns the fraction 1/tau_f of S - 1 to the
+ *                model's constraint S = 1 (Sec. 2, Eq. 56), shared among the
+ *                phases in proportion to phi_i: absent phases stay absent.
+ *                Identical to the printed scheme where S = 1; it removes
+ *                the truncation error that the three separately evolved
+ *                order parameters accumulate in S where the flow's
+ *                continuity error is largest (triple junctions at density
+ *                jumps, Sec. 4.3).  Phase masses are then conserved up to
+ *                that correction.  Forward mode only.
  *  ion_tau, ion_beta, ion_charge  Nernst-Planck: relaxation time of the
  *                ion families (> 1/2), e/(k_B T) in potential units, and the
  *                charge e of a unit concentration.
@@ -163,7 +175,7 @@ typedef struct {
   double tau_f, tau_l;
   double dtheta[5];
   double E_ext_z;
-  int32_t charge_model, reserved0;
+  int32_t charge_model, sum_relax;
   double ion_tau, ion_beta, ion_charge;
 } lbm_ehd_params;
 

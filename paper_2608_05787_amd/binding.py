@@ -46,7 +46,7 @@ class Params(ctypes.Structure):
         ("tau_f", ctypes.c_double), ("tau_l", ctypes.c_double),
         ("dtheta", ctypes.c_double * 5),
         ("E_ext_z", ctypes.c_double),
-        ("charge_model", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("charge_model", ctypes.c_int32), ("sum_relax", ctypes.c_int32),
         ("ion_tau", ctypes.c_double), ("ion_beta", ctypes.c_double), ("ion_charge", ctypes.c_double),
     ]
 
@@ -143,6 +143,7 @@ def make_params(cfg: dict, precision: str = "fp32") -> Params:
     p.lattice = int(cfg.get("lattice", 0))
     p.E_ext_z = float(cfg.get("E_ext_z", 0.0))
     p.charge_model = int(cfg.get("charge_model", 0))
+    p.sum_relax = int(cfg.get("sum_relax", 0))
     p.ion_tau = float(cfg.get("ion_tau", 0.8))
     p.ion_beta = float(cfg.get("ion_beta", 0.0))
     p.ion_charge = float(cfg.get("ion_charge", 0.0))

@@ -252,6 +252,7 @@ const char *validate(const lbm_ehd_params &p, const lbm_ehd_params &p0) {
       p.precision != LBM_PREC_TANGENT)
     return "unknown precision";
   if (p.charge_model != LBM_CHARGE_LEAKY && p.charge_model != LBM_CHARGE_NERNST_PLANCK) return "unknown charge_model";
+  if (p.sum_relax != 0 && p.sum_relax != 1) return "sum_relax must be 0 or 1";
   if (p.charge_model != p0.charge_model) return "all instances of a handle must share the charge model";
   if (p.charge_model == LBM_CHARGE_NERNST_PLANCK) {
     if (p.sigma[0] != 0 || p.sigma[1] != 0 || p.sigma[2] != 0)
@@ -767,6 +768,7 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
     I.wall_q_mode = p.wall_q_mode;
     I.phase_mode = p.phase_mode;
     I.charge_model = p.charge_model;
+    I.sum_relax = p.sum_relax;
     I.nblk = L.nblk;
     I.blk0 = (int)logical.size();  // node blocks of the instances before this one
     for (int b = 0; b < 2; ++b) {
@@ -928,6 +930,7 @@ const char *adjoint_unsupported(const lbm_ehd_s *H) {
   if (p.init_tol > 0 && p.init_sub_max > 1) return "reverse mode needs a fixed-count cold start (init_tol <= 0)";
   if (p.eps_ref_phase != 0) return "gradients along permittivity ratios need eps_ref_phase 0";
   if (p.charge_model != LBM_CHARGE_LEAKY) return "reverse mode is built for the leaky-dielectric charge model";
+  if (p.sum_relax) return "reverse mode is built for the CH equilibria as printed (sum_relax 0)";
   return nullptr;
 }
 

@@ -127,8 +127,9 @@ template <typename T> struct Phys {
 struct Inst {
   int nx, ny, N, bc_y;
   int wall_q_mode, phase_mode, nblk, nz;
-  int charge_model, nn, blk0, pad_;  // charge model: 0 leaky dielectric, 1 two-ion Nernst-Planck (l holds [2][Q][N]);
-                                     // blk0: node blocks of the instances before this one
+  int charge_model, nn, blk0, sum_relax;  // charge model: 0 leaky dielectric, 1 two-ion Nernst-Planck (l holds
+                                          // [2][Q][N]); blk0: node blocks of the instances before this one;
+                                          // sum_relax: the collisions restore phi_1 + phi_2 + phi_3 = 1
   void *f[2], *g[2], *l[2], *h[2];
   float *f0[2];  // FP16S only: FP32 rest populations f^i_0, [3][N]
   // planes: phi 3 (two buffers), lsum, eps, q (two buffers), R, psi, E D,
@@ -1214,6 +1215,9 @@ __global__ __launch_bounds__(NT, (EARLY || sizeof(T) > 4 || L::Q > 9) ? 1 : 4) v
     // three CH families
     if (ch) {
       const T m0 = P.m0, itf = T(1) / P.tau_f, cf = T(1) - T(0.5) * itf;
+      // optional restoration of the constraint S = phi_1 + phi_2 + phi_3 = 1:
+      // the rest component of the equilibrium carries phi_i / S
+      const T rsum = I.sum_relax ? T(1) / (ph[0] + ph[1] + ph[2]) : T(1);
       const int fbd = fbuf(I, nc);
       auto fd = gbl((S *)I.f[fbd]);
 #pragma unroll
@@ -1242,7 +1246,8 @@ __global__ __launch_bounds__(NT, (EARLY || sizeof(T) > 4 || L::Q > 9) ? 1 : 4) v
         for (int j = 0; j < Q; ++j) {
           const T fj = early ? fin[i][j] : ldf(i, j);
           const T cu = cdot<L>(j, pu);
-          const T feq = j == 0 ? ph[i] - (T(1) - lw<L, T>(0)) * muc[i] : lw<L, T>(j) * muc[i] + lw<L, T>(j) * cu * T(3);
+          const T feq = j == 0 ? ph[i] * rsum - (T(1) - lw<L, T>(0)) * muc[i]
+                               : lw<L, T>(j) * muc[i] + lw<L, T>(j) * cu * T(3);
           const T Fj = lw<L, T>(j) * cdot<L>(j, dt);
           v[j] = fj - (fj - feq) * itf + cf * Fj;
         }

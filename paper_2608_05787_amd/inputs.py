@@ -44,7 +44,7 @@ def base_params(nx: int, ny: int, **kw) -> dict:
              sigma=(1e-3, 1e-3, 1e-3), tau_f=0.8, tau_l=0.8, eps_ref_phase=0,
              phase_mode=0, sub_min=1, sub_max=1, sub_tol=0.0,
              init_sub_max=0, init_tol=0.0, nz=1, lattice=0, E_ext_z=0.0,
-             charge_model=0, ion_tau=0.8, ion_beta=0.0, ion_charge=0.0)
+             charge_model=0, ion_tau=0.8, ion_beta=0.0, ion_charge=0.0, sum_relax=0)
     p.update(kw)
     return p
 
@@ -272,7 +272,7 @@ def batch_sweep(n_inst=64, seed=5787, lo=128, hi=512, sub=(4, 4, 0.0), init_iter
 
 
 def liquid_lens(n=200, radius=30.0, ratio=(1.0, 1.0, 1.0), gamma=2e-3, rho=(10.0, 1.0, 5.0), width=4.0,
-                tau=0.8):
+                tau=0.8, sum_relax=0):
     """Liquid lens (Eq. 56): a drop of phase 1 centred on the flat interface
     between phase 2 (above) and phase 3 (below); walls at top and bottom,
     periodic in x.  Surface tensions gamma * ratio (gamma12 : gamma13 :
@@ -287,7 +287,7 @@ def liquid_lens(n=200, radius=30.0, ratio=(1.0, 1.0, 1.0), gamma=2e-3, rho=(10.0
     cs2 = 1.0 / 3.0
     visc = tuple(cs2 * (tau - 0.5) * r for r in rho)
     p = base_params(n, n, bc_y=1, gamma12=g12, gamma13=g13, gamma23=g23, width=width,
-                    rho=tuple(rho), visc=visc, sigma=(0.0, 0.0, 0.0), tau_f=tau)
+                    rho=tuple(rho), visc=visc, sigma=(0.0, 0.0, 0.0), tau_f=tau, sum_relax=sum_relax)
     return p, {"phi0": phi0}
 
 

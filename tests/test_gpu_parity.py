@@ -89,6 +89,31 @@ def test_fp64_matches_oracle(nx, ny, walls):
     compare(sim, ref, FP64_TOL)
 
 
+def _sum_relax_case(nx, ny, walls):
+    """Parity case with the order-parameter sum relaxation on, from order
+    parameters whose sum is off one by a few per cent."""
+    p, init = inputs.parity_case(nx, ny, seed=nx + ny + 1, walls=walls)
+    p["sum_relax"] = 1
+    rng = np.random.default_rng(nx * ny)
+    phi0 = init["phi0"] * (1.0 + 0.03 * rng.standard_normal(init["phi0"].shape))
+    return p, dict(init, phi0=phi0)
+
+
+@pytest.mark.parametrize("nx,ny,walls", [(33, 17, True), (64, 48, False)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_sum_relax_matches_oracle(prec, nx, ny, walls):
+    print("case sum_relax", prec, nx, ny, walls, flush=True)
+    p, init = _sum_relax_case(nx, ny, walls)
+    ref = Oracle(p, init)
+    sim = binding.Sim(p, init, precision=prec)
+    tol = FP64_TOL if prec == "fp64" else FP32_TOL
+    if prec == "fp64":
+        compare(sim, ref, tol)
+    ref.step(12)
+    sim.step(12)
+    compare(sim, ref, tol)
+
+
 @pytest.mark.parametrize("K,walls", [(1, True), (3, True), (4, False), (5, True)])
 def test_fp64_potential_iteration_counts(K, walls):
     """Fixed counts run as one single-iteration launch (odd K) plus
