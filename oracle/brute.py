@@ -99,14 +99,6 @@ class Brute:
                     self.hqu[d][y][x] = self.q[y][x] * u[d]
 
     # ------------------------------------------------------------ helpers
-    def _phi_eq(self, i, x, y):
-        """Order parameter in the rest component of the CH equilibrium:
-        phi_i, or phi_i over the sum of the three when the collisions restore
-        the sum (R23)."""
-        ph = self.phi[i][y][x]
-        if self.sum_relax:
-            ph /= self.phi[0][y][x] + self.phi[1][y][x] + self.phi[2][y][x]
-        return ph
 
     @staticmethod
     def _cdot(j, v):
@@ -138,9 +130,9 @@ class Brute:
             s += 2.0 * W[j] * (fld[yy][xx] - fld[y][x])
         return s / CS2
 
-    def _feq(self, j, ph, mu, u, ph_rest=None):  # Eq. (35); ph_rest: rest-component value (R23)
+    def _feq(self, j, ph, mu, u):  # Eq. (35)
         if j == 0:
-            return (ph if ph_rest is None else ph_rest) - (1.0 - W[0]) * mu
+            return ph - (1.0 - W[0]) * mu
         return W[j] * mu + W[j] * ph * self._cdot(j, u) / CS2
 
     @staticmethod
@@ -326,10 +318,15 @@ class Brute:
                 mii = -sum(off)
                 X = [(mii - self.m0) * gmu[i][d] + sum(off[k] * gmu[k][d] for k in range(3) if k != i)
                      for d in range(2)]
+                if self.sum_relax:
+                    # restoring flux m0 (phi_i / S) grad S of the order-parameter sum (R23)
+                    S = ph[0] + ph[1] + ph[2]
+                    gS = [sum(self._grad(self.phi[k], x, y)[d] for k in range(3)) for d in range(2)]
+                    X = [X[d] + self.m0 * ph[i] / S * gS[d] for d in range(2)]
                 for j in range(Q):
                     fj = self.f[i][j][y][x]
                     Fj = W[j] * (self._cdot(j, dpu[i]) / CS2 - self._cdot(j, X) / self.m0)
-                    fpost[i][j][y][x] = (fj - (fj - self._feq(j, ph[i], self.mu[i][y][x], u, self._phi_eq(i, x, y))) / self.tau_f
+                    fpost[i][j][y][x] = (fj - (fj - self._feq(j, ph[i], self.mu[i][y][x], u)) / self.tau_f
                                          + (1.0 - 0.5 / self.tau_f) * Fj)
         # flow family, Eqs. (37)-(40), local tau_g (R6)
         tg = 0.5 + self.visc[y][x] / (rho * CS2)

@@ -61,10 +61,10 @@
  *       e/(k_B T), E of the current step), D = cs2 (tau_n - 1/2); the charge
  *       is q = e (n_+ - n_-) with no Ohmic source (conductivities zero);
  *       walls are no-flux bounce-back.  The paper gives no LB for Eq. (52).
- *   R23 (optional, sum_relax) the rest component of the CH equilibrium
- *       carries phi_i / S, S = phi_1 + phi_2 + phi_3, instead of phi_i: each
- *       collision returns the fraction 1/tau_f of S - 1 to the constraint
- *       S = 1, shared in proportion to phi_i.
+ *   R23 (optional, sum_relax) the variable part of the diffusion flux of
+ *       phase i in Eq. (36) gains m0 (phi_i / S) grad S, S = phi_1 + phi_2 +
+ *       phi_3: the sum diffuses back to the constraint S = 1 and each phase
+ *       keeps its mass.
  */
 #include <math.h>
 #include <stdint.h>
@@ -120,7 +120,7 @@ typedef struct {
   int32_t lattice;    /* 0 D2Q9, 1 D3Q15 */
   double E_ext_z;     /* z component of the applied field (D3Q15) */
   int32_t charge_model; /* 0 leaky dielectric (Eqs. 46-50), 1 two-ion Nernst-Planck (R21) */
-  int32_t sum_relax;    /* 1: collisions restore the order-parameter sum (R23) */
+  int32_t sum_relax;    /* 1: restoring flux of the order-parameter sum (R23) */
   double ion_tau;     /* relaxation time of the ion families: D = cs2 (ion_tau - 1/2) */
   double ion_beta;    /* e / (k_B T) in potential units */
   double ion_charge;  /* e: q = e (n_+ - n_-) */
@@ -478,12 +478,16 @@ static void force_and_flow(or_state *s, int n, double *F, double *u, double *pp)
   *pp = CS2 / (1.0 - L->w[0]) * (s1 + 0.5 * udr + rho * s0);
 }
 
-/* R23: the order parameter in the rest component of the CH equilibrium of
- * Eq. (35): phi_i as printed, or phi_i / S with S the sum of the three (the
- * model's constraint S = 1 restored by the collision; sum_relax on). */
-static double eq_phi(const or_params *P, const double *ph, int i) {
-  if (!P->sum_relax) return ph[i];
-  return ph[i] / (ph[0] + ph[1] + ph[2]);
+/* R23 (sum_relax on): component d of the flux m0 (phi_i / S) grad S added to
+ * the variable part of the diffusion flux of phase i, S = phi_1 + phi_2 +
+ * phi_3; grad S is the sum of the Eq. (33) gradients of the three.  Summed
+ * over i it is m0 grad S: the sum diffuses back to one while every phase's
+ * mass stays conserved. */
+static double restoring_flux(const or_state *s, const double *ph, int i, int d, int n) {
+  const int N = s->N, D = s->D;
+  double gS = 0;
+  for (int k = 0; k < 3; ++k) gS += s->gphi[(k * D + d) * N + n];
+  return s->m0 * ph[i] / (ph[0] + ph[1] + ph[2]) * gS;
 }
 
 /* Collisions of Eqs. (34)-(36), (37)-(40) and (48)-(50). */
@@ -537,12 +541,13 @@ static void collide(or_state *s) {
           X[d] = (Mm[i][i] - m0) * s->gmu[(i * D + d) * N + n];
           for (int k = 0; k < 3; ++k)
             if (k != i) X[d] += Mm[i][k] * s->gmu[(k * D + d) * N + n];
+          if (P->sum_relax) X[d] += restoring_flux(s, ph, i, d, n);
         }
-        const double mu = s->mu[i * N + n], pe = eq_phi(P, ph, i);
+        const double mu = s->mu[i * N + n];
         for (int j = 0; j < Q; ++j) {
           const double fj = s->f[(i * Q + j) * N + n];
           const double cu = ph[i] * dotc(L, j, u);
-          const double feq = (j == 0) ? pe - (1.0 - L->w[0]) * mu : L->w[j] * mu + L->w[j] * cu / CS2;
+          const double feq = (j == 0) ? ph[i] - (1.0 - L->w[0]) * mu : L->w[j] * mu + L->w[j] * cu / CS2;
           /* source of Eq. (36), reading R2 */
           const double Fj = L->w[j] * (dotc(L, j, dpu[i]) / CS2 - dotc(L, j, X) / m0);
           s->fn[(i * Q + j) * N + n] = fj - (fj - feq) / tf + (1.0 - 0.5 / tf) * Fj;

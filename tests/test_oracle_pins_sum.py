@@ -1,24 +1,23 @@
-"""Pins of the optional restoration of the order-parameter sum (reading
+"""Pins of the optional restoring flux of the order-parameter sum (reading
 R23), CPU.
 
-With sum_relax on, the rest component of each CH equilibrium (Eq. 35)
-carries phi_i / S instead of phi_i, S = phi_1 + phi_2 + phi_3.  What that
+With sum_relax on, the variable part of the diffusion flux of phase i in
+Eq. (36) gains m0 (phi_i / S) grad S, S = phi_1 + phi_2 + phi_3.  What that
 must do, independent of how the oracle writes it:
 
-* A uniform mixture at rest has no gradients, so the source of Eq. (36) and
-  the streaming do nothing and each collision maps phi_i to
-  phi_i - (phi_i - phi_i / S) / tau_f exactly: S - 1 is multiplied by
-  1 - 1/tau_f per step (-1/4 at tau_f = 0.8), the fractions phi_i / S stay
-  fixed and an absent phase stays exactly zero.  With sum_relax off, S
-  stays put.
-* Where S = 1 the scheme is the printed one: a two-phase state whose order
-  parameters sum to exactly one evolves identically with and without it
-  for one step.
-* A sine mode of S decays at that same local rate, whatever its
-  wavelength.
+* Summed over the phases the weights phi_i / S add up to one, so S obeys
+  the linear diffusion equation with the mobility m0: a sine mode of S
+  decays at m0 k^2 (second order in k), a large one generates no second
+  harmonic, and with the flux off the mode stays put.
+* Each phase receives its share phi_i / S: the fractions of a mixture whose
+  phases are proportional to S stay fixed, an absent phase stays exactly
+  zero, and every phase's mass is conserved (the flux enters through a
+  source with zero zeroth moment).
+* Where S = 1 the flux vanishes: a two-phase state built as phi and 1 - phi
+  takes its first step as with the flux off.
 
-Surface tensions are 1e-7 in the uniform cases (mu plays no part in the
-zeroth moments, but it drives the flow through the force).
+Surface tensions are 1e-7 in the mode cases so that mu, and through it the
+flow, stays at the 1e-8 level.
 """
 import os
 
@@ -29,44 +28,72 @@ import oracle
 from oracle import Oracle
 from paper_2608_05787_amd import inputs
 
-TAU = 0.8
+M0 = (0.8 - 0.5) / 3.0
 
 
-def _uniform(weights, S0, steps, relax=1, lib=None, n=6):
-    p = inputs.base_params(n, n, gamma12=1e-7, gamma13=1e-7, gamma23=1e-7, sigma=(0.0, 0.0, 0.0),
-                           sum_relax=relax, tau_f=TAU)
-    phi0 = np.stack([np.full((n, n), w * S0) for w in weights])
-    o = Oracle(p, {"phi0": phi0}, lib_path=lib)
-    out = []
-    for _ in range(steps):
-        o.step(1)
-        out.append(np.stack([o.field("phi%d" % i) for i in (1, 2, 3)]))
-    return out
+def _mode(v, L, m):
+    x = np.arange(L)
+    return 2.0 * np.mean(v * np.sin(2 * np.pi * m * x / L)), 2.0 * np.mean(v * np.cos(2 * np.pi * m * x / L))
 
 
-def test_uniform_sum_relaxes_geometrically():
-    """The fields reported after step n are that step's moments, i.e. after
-    n - 1 collisions."""
-    w, S0 = (0.25, 0.75, 0.0), 1.02
-    hist = _uniform(w, S0, 12)
-    for n, ph in enumerate(hist, start=0):
-        S = ph.sum(0)
-        want = 1.0 + (S0 - 1.0) * (1.0 - 1.0 / TAU) ** n
-        assert np.abs(S - want).max() < 1e-14, (n, S.max(), want)
-        assert np.abs(ph[0] / S - w[0]).max() < 1e-14
-        assert np.all(ph[2] == 0.0)
+def decay(L, amp=0.01, weights=(1.0, 0.0, 0.0), relax=1, lib=None, ny=2):
+    """Run half an e-folding time of a sine mode of S; return the measured
+    rate over m0 k^2 and the fields before and after."""
+    p = inputs.base_params(L, ny, gamma12=1e-7, gamma13=1e-7, gamma23=1e-7, sigma=(0.0, 0.0, 0.0),
+                           sum_relax=relax)
+    x = np.arange(L)
+    e = amp * np.sin(2 * np.pi * x / L)[None, :].repeat(ny, 0)
+    o = Oracle(p, {"phi0": np.stack([w * (1.0 + e) for w in weights])}, lib_path=lib)
+    before = np.stack([o.field("phi%d" % i) for i in (1, 2, 3)])
+    k = 2 * np.pi / L
+    T = int(0.5 / (M0 * k * k))
+    o.step(T)
+    after = np.stack([o.field("phi%d" % i) for i in (1, 2, 3)])
+    a0 = _mode(before.sum(0)[0] - 1.0, L, 1)[0]
+    a1 = _mode(after.sum(0)[0] - 1.0, L, 1)[0]
+    return -np.log(a1 / a0) / T / (M0 * k * k), before, after
 
 
-def test_uniform_sum_stays_without_restoration():
-    hist = _uniform((0.25, 0.75, 0.0), 1.02, 6, relax=0)
-    for ph in hist:
-        assert np.abs(ph.sum(0) - 1.02).max() < 1e-14
+def test_sum_mode_decays_at_mobility():
+    r = {L: decay(L)[0] for L in (16, 32, 64)}
+    print("rate / m0 k^2:", r)
+    for L in (16, 32, 64):
+        assert abs(r[L] - 1.0) < 16.0 / L ** 2, (L, r[L])
+    assert 3.2 < abs(r[16] - 1) / abs(r[32] - 1) < 5.0   # second order in k
+    assert 3.2 < abs(r[32] - 1) / abs(r[64] - 1) < 5.0
+
+
+def test_sum_mode_stays_without_flux():
+    r, _, _ = decay(32, relax=0)
+    assert abs(r) < 1e-4, r
+
+
+def test_large_mode_generates_no_harmonic():
+    L = 32
+    r, _, after = decay(L, amp=0.3)
+    s = after.sum(0)[0] - 1.0
+    a1, a2 = np.hypot(*_mode(s, L, 1)), np.hypot(*_mode(s, L, 2))
+    print("rate ratio %.6f, harmonic 2 / fundamental %.2e" % (r, a2 / a1))
+    assert abs(r - 1.0) < 16.0 / L ** 2
+    assert a2 / a1 < 1e-5
+
+
+def test_shares_absent_phase_and_masses():
+    """Phases 1 and 2 in proportion 0.3 : 0.7 times a sine mode of S, phase
+    3 absent."""
+    L = 32
+    r, before, after = decay(L, amp=0.05, weights=(0.3, 0.7, 0.0))
+    assert abs(r - 1.0) < 16.0 / L ** 2
+    assert np.abs(after[0] / after.sum(0) - 0.3).max() < 1e-6
+    assert np.all(after[2] == 0.0)  # exactly
+    for i in range(2):
+        assert abs(after[i].sum() - before[i].sum()) <= 1e-12 * before[i].sum()
 
 
 def test_printed_scheme_where_sum_is_one():
-    """A drop of phase 2 in phase 1 (phase 3 absent), the two order
-    parameters built as phi and 1 - phi: one step with and without the
-    restoration gives the same populations to rounding."""
+    """A drop of phase 2 in phase 1 (phase 3 absent), built as phi and
+    1 - phi: the first step, whose collision sees S = 1 to rounding, gives
+    the same populations with and without the flux."""
     n = 24
     phi2 = inputs.tanh_drop(n, n, 11.3, 12.1, 6.0, 4.0)
     phi0 = np.stack([1.0 - phi2, phi2, np.zeros_like(phi2)])
@@ -80,28 +107,13 @@ def test_printed_scheme_where_sum_is_one():
     assert np.abs(outs[0] - outs[1]).max() < 1e-15
 
 
-def test_mode_of_sum_decays_locally():
-    """A sine mode of S (amplitude 0.01) over a periodic box, phases 1 and 2
-    in proportion 0.3 : 0.7: the mode's amplitude after n steps is
-    (1 - 1/tau_f)^n of the initial one for wavelengths 8 and 32."""
-    for L in (8, 32):
-        p = inputs.base_params(L, 2, gamma12=1e-7, gamma13=1e-7, gamma23=1e-7, sigma=(0.0, 0.0, 0.0),
-                               sum_relax=1, tau_f=TAU)
-        x = np.arange(L)
-        e = 0.01 * np.sin(2 * np.pi * x / L)[None, :].repeat(2, 0)
-        o = Oracle(p, {"phi0": np.stack([0.3 * (1 + e), 0.7 * (1 + e), 0 * e])})
-        o.step(6)  # moments of the sixth step: five collisions
-        S = sum(o.field("phi%d" % i) for i in (1, 2, 3))[0] - 1.0
-        amp = 2.0 * np.mean(S * np.sin(2 * np.pi * x / L))
-        assert abs(amp / 0.01 - (1.0 - 1.0 / TAU) ** 5) < 1e-6, (L, amp)
-
-
-# planted mistakes in the oracle's restoration, each failing a pin above
+# planted mistakes in the oracle's restoring flux, each failing a pin above
+_OLD = "  return s->m0 * ph[i] / (ph[0] + ph[1] + ph[2]) * gS;"
 MUTANTS = {
-    "multiplied": ("return ph[i] / (ph[0] + ph[1] + ph[2]);", "return ph[i] * (ph[0] + ph[1] + ph[2]);"),
-    "equal_shares": ("return ph[i] / (ph[0] + ph[1] + ph[2]);",
-                     "return ph[i] - (ph[0] + ph[1] + ph[2] - 1.0) / 3.0;"),
-    "ignored": ("  if (!P->sum_relax) return ph[i];", "  return ph[i];"),
+    "sign": (_OLD, "  return -s->m0 * ph[i] / (ph[0] + ph[1] + ph[2]) * gS;"),
+    "no_division": (_OLD, "  return s->m0 * ph[i] * gS;"),
+    "equal_shares": (_OLD, "  return s->m0 / 3.0 * gS;"),
+    "double": (_OLD, "  return 2.0 * s->m0 * ph[i] / (ph[0] + ph[1] + ph[2]) * gS;"),
 }
 
 
@@ -116,10 +128,14 @@ def test_pins_reject_planted_mistake(name, mutant_dir):
     src = oracle.source_text()
     assert src.count(old) == 1
     lib = oracle.compile_variant(src.replace(old, new), os.path.join(mutant_dir, name + ".so"))
-    w, S0 = (0.25, 0.75, 0.0), 1.02
-    ph = _uniform(w, S0, 4, lib=lib)[-1]
-    S = ph.sum(0)
-    want = 1.0 + (S0 - 1.0) * (1.0 - 1.0 / TAU) ** 3
-    bad_sum = np.abs(S - want).max() > 1e-6
-    bad_share = np.abs(ph[0] / S - w[0]).max() > 1e-6 or np.any(ph[2] != 0.0)
-    assert bad_sum or bad_share, name
+    if name in ("sign", "double"):
+        r, _, _ = decay(16, lib=lib)
+        assert not abs(r - 1.0) < 16.0 / 16 ** 2, r
+    elif name == "no_division":
+        L = 32
+        _, _, after = decay(L, amp=0.3, lib=lib)
+        s = after.sum(0)[0] - 1.0
+        assert np.hypot(*_mode(s, L, 2)) / np.hypot(*_mode(s, L, 1)) > 1e-3
+    else:
+        _, _, after = decay(32, amp=0.05, weights=(0.3, 0.7, 0.0), lib=lib)
+        assert np.abs(after[2]).max() > 1e-6
