@@ -140,18 +140,17 @@ enum { LBM_POP_F = 0, LBM_POP_G = 1, LBM_POP_L = 2, LBM_POP_H = 3 };
  *                Requires sigma = 0 (ions carry the current), wall_q_mode 0,
  *                FP32, FP64 or tangent precision, and init ions0; forward
  *                mode only (reverse-mode gradients are refused).
- *  sum_relax     0: the CH equilibria of Eq. (35) as printed.  1: the rest
- *                component of each CH equilibrium carries phi_i / S, S =
- *                phi_1 + phi_2 + phi_3, instead of phi_i, so that every
- *                collision returns the fraction 1/tau_f of S - 1 to the
- *                model's constraint S = 1 (Sec. 2, Eq. 56), shared among the
- *                phases in proportion to phi_i: absent phases stay absent.
- *                Identical to the printed scheme where S = 1; it removes
- *                the truncation error that the three separately evolved
- *                order parameters accumulate in S where the flow's
- *                continuity error is largest (triple junctions at density
- *                jumps, Sec. 4.3).  Phase masses are then conserved up to
- *                that correction.  Forward mode only.
+ *  sum_relax     0: the CH scheme of Eqs. (34)-(36) as printed.  1: the
+ *                variable part of the diffusion flux of phase i in Eq. (36)
+ *                gains m0 (phi_i / S) grad S, S = phi_1 + phi_2 + phi_3
+ *                (grad S by Eq. 33), so that the three families carry S back
+ *                to the model's constraint S = 1 (Sec. 2, Eq. 56) by
+ *                diffusion with the mobility m0.  Every phase keeps its mass,
+ *                an absent phase stays absent, and where S = 1 the scheme
+ *                is the printed one.  It removes the truncation error that
+ *                the three separately evolved order parameters accumulate
+ *                in S where the flow's continuity error is largest (triple
+ *                junctions at density jumps, Sec. 4.3).  Forward mode only.
  *  ion_tau, ion_beta, ion_charge  Nernst-Planck: relaxation time of the
  *                ion families (> 1/2), e/(k_B T) in potential units, and the
  *                charge e of a unit concentration.

@@ -129,7 +129,7 @@ struct Inst {
   int wall_q_mode, phase_mode, nblk, nz;
   int charge_model, nn, blk0, sum_relax;  // charge model: 0 leaky dielectric, 1 two-ion Nernst-Planck (l holds
                                           // [2][Q][N]); blk0: node blocks of the instances before this one;
-                                          // sum_relax: the collisions restore phi_1 + phi_2 + phi_3 = 1
+                                          // sum_relax: restoring flux of phi_1 + phi_2 + phi_3
   void *f[2], *g[2], *l[2], *h[2];
   float *f0[2];  // FP16S only: FP32 rest populations f^i_0, [3][N]
   // planes: phi 3 (two buffers), lsum, eps, q (two buffers), R, psi, E D,
@@ -1091,6 +1091,15 @@ __global__ __launch_bounds__(NT, (EARLY || sizeof(T) > 4 || L::Q > 9) ? 1 : 4) v
     }
     T gr[D], dummy;
     fdq<L>(rv, gr, dummy);
+    T gS[D];  // gradient of S = phi_1 + phi_2 + phi_3 (restoring flux of the sum)
+#pragma unroll
+    for (int d = 0; d < D; ++d) gS[d] = T(0);
+    if (I.sum_relax) {
+      T sv[Q];
+#pragma unroll
+      for (int j = 0; j < Q; ++j) sv[j] = phi[m[j]] + phi[(size_t)N + m[j]] + phi[(size_t)2 * N + m[j]];
+      fdq<L>(sv, gS, dummy);
+    }
     T gm[3][D], muc[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -1215,9 +1224,8 @@ __global__ __launch_bounds__(NT, (EARLY || sizeof(T) > 4 || L::Q > 9) ? 1 : 4) v
     // three CH families
     if (ch) {
       const T m0 = P.m0, itf = T(1) / P.tau_f, cf = T(1) - T(0.5) * itf;
-      // optional restoration of the constraint S = phi_1 + phi_2 + phi_3 = 1:
-      // the rest component of the equilibrium carries phi_i / S
-      const T rsum = I.sum_relax ? T(1) / (ph[0] + ph[1] + ph[2]) : T(1);
+      // optional restoring flux m0 (phi_i / S) grad S of the constraint S = 1
+      const T wsum = I.sum_relax ? m0 / (ph[0] + ph[1] + ph[2]) : T(0);
       const int fbd = fbuf(I, nc);
       auto fd = gbl((S *)I.f[fbd]);
 #pragma unroll
@@ -1237,7 +1245,7 @@ __global__ __launch_bounds__(NT, (EARLY || sizeof(T) > 4 || L::Q > 9) ? 1 : 4) v
         T dt[D], pu[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-          X[d] += (mii - m0) * gm[i][d];
+          X[d] += (mii - m0) * gm[i][d] + wsum * ph[i] * gS[d];
           dt[d] = dp[i][d] * T(3) - X[d] / m0;
           pu[d] = ph[i] * u[d];
         }
@@ -1246,8 +1254,7 @@ __global__ __launch_bounds__(NT, (EARLY || sizeof(T) > 4 || L::Q > 9) ? 1 : 4) v
         for (int j = 0; j < Q; ++j) {
           const T fj = early ? fin[i][j] : ldf(i, j);
           const T cu = cdot<L>(j, pu);
-          const T feq = j == 0 ? ph[i] * rsum - (T(1) - lw<L, T>(0)) * muc[i]
-                               : lw<L, T>(j) * muc[i] + lw<L, T>(j) * cu * T(3);
+          const T feq = j == 0 ? ph[i] - (T(1) - lw<L, T>(0)) * muc[i] : lw<L, T>(j) * muc[i] + lw<L, T>(j) * cu * T(3);
           const T Fj = lw<L, T>(j) * cdot<L>(j, dt);
           v[j] = fj - (fj - feq) * itf + cf * Fj;
         }
