@@ -272,12 +272,14 @@ def batch_sweep(n_inst=64, seed=5787, lo=128, hi=512, sub=(4, 4, 0.0), init_iter
 
 
 def liquid_lens(n=200, radius=30.0, ratio=(1.0, 1.0, 1.0), gamma=2e-3, rho=(10.0, 1.0, 5.0), width=4.0,
-                tau=0.8, sum_relax=0):
+                tau=0.8, sum_relax=1):
     """Liquid lens (Eq. 56): a drop of phase 1 centred on the flat interface
     between phase 2 (above) and phase 3 (below); walls at top and bottom,
     periodic in x.  Surface tensions gamma * ratio (gamma12 : gamma13 :
     gamma23); densities rho; dynamic viscosities 0.1 rho_i so that the flow
-    relaxation time is tau = 0.8 in every phase.  No field."""
+    relaxation time is tau = 0.8 in every phase.  No field.  The restoring
+    flux of the order-parameter sum is on unless sum_relax=0 (the triple
+    junctions at the density jumps would otherwise carry the sum off one)."""
     xc = yc = 0.5 * (n - 1)
     phi1 = tanh_drop(n, n, xc, yc, radius, width)
     _, y = _grid(n, n)
