@@ -382,16 +382,31 @@ def gradient_bench(n, steps, sub, init_iters, every):
     del rec
     torch.cuda.empty_cache()
     ref = binding.Sim(p, init, precision="fp64")
+    torch.cuda.synchronize()
+    t0 = time.time()
     g64 = ref.adjoint(steps, seed, every)
+    torch.cuda.synchronize()
+    t_adj64 = time.time() - t0
     del ref
     torch.cuda.empty_cache()
+    # the FP64 forward's own deformation: how far the FP32 forward already is
+    f64 = binding.Sim(p, init, precision="fp64")
+    f64.step(steps)
+    w64 = 1.0 - f64.fields(["phi1"], dtype=torch.float64)["phi1"]
+    D64 = float(autograd.deformation(autograd.drop_indicator(w64)))
+    del f64
+    torch.cuda.empty_cache()
     rel = [abs(a - b) / abs(b) if b != 0 else abs(a) for a, b in zip(g, g64)]
+    gmax = max(abs(b) for b in g64)
     return {"workload": "field compound drop %dx%d, radii 40/30, %d steps, %d potential sub-iterations, "
                         "cold start %d iterations" % (n, n, steps, sub, init_iters),
             "method": "reverse sweep, FP32, checkpoint every %d steps" % every,
             "forward_launch_config": cfg,
             "D_outer": float(D.detach()), "dD_dtheta": g, "dD_dtheta_fp64_sweep": g64,
             "rel_diff_fp32_vs_fp64": rel,
+            "diff_fp32_vs_fp64_over_max_component": [abs(a - b) / gmax for a, b in zip(g, g64)],
+            "D_outer_fp64_forward": D64, "rel_diff_D_fp32_vs_fp64_forward": abs(float(D.detach()) - D64) / abs(D64) if D64 else None,
+            "adjoint_fp64_s": round(t_adj64, 4),
             "forward_s": round(t_fwd, 4), "record_s": round(t_rec, 4), "adjoint_s": round(t_adj, 4),
             "adjoint_over_forward": round(t_adj / t_fwd, 2),
             "record_plus_adjoint_over_forward": round((t_rec + t_adj) / t_fwd, 2)}
