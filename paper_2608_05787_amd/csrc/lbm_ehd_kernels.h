@@ -277,15 +277,18 @@ __device__ __forceinline__ int nbr(const Inst &I, const Node &nd, int j) {
 
 // Eq. (33) gradient g[D] and Laplacian from the Q stencil values v[j]
 // (v[j] = chi(x + c_j)).
+// Terms whose lattice coefficient is zero are left out (they add exact
+// zeros, which IEEE arithmetic would otherwise have to compute).
 template <class L, typename T>
 __device__ __forceinline__ void fdq(const T *v, T (&g)[L::D], T &lap) {
   T sg[L::D], sl = 0;
 #pragma unroll
   for (int d = 0; d < L::D; ++d) sg[d] = 0;
 #pragma unroll
-  for (int j = 0; j < L::Q; ++j) {
+  for (int j = 1; j < L::Q; ++j) {
 #pragma unroll
-    for (int d = 0; d < L::D; ++d) sg[d] += lw<L, T>(j) * lc<L, T>(j, d) * v[j];
+    for (int d = 0; d < L::D; ++d)
+      if (L::c(j, d) != 0) sg[d] += lw<L, T>(j) * lc<L, T>(j, d) * v[j];
     sl += T(2) * lw<L, T>(j) * (v[j] - v[0]);
   }
 #pragma unroll
@@ -302,12 +305,20 @@ __device__ __forceinline__ void fd9(const T *v, T &gx, T &gy, T &lap) {
   gy = g[1];
 }
 
-// c_j . a for a D-vector a.
+// c_j . a for a D-vector a, over the nonzero components of c_j (the
+// components are -1, 0 or 1: the products are exact).
 template <class L, typename T>
 __device__ __forceinline__ T cdot(int j, const T (&a)[L::D]) {
-  T r = lc<L, T>(j, 0) * a[0];
+  T r = T(0);
+  bool any = false;
 #pragma unroll
-  for (int d = 1; d < L::D; ++d) r += lc<L, T>(j, d) * a[d];
+  for (int d = 0; d < L::D; ++d) {
+    const int c = L::c(j, d);
+    if (c == 0) continue;
+    const T t = c > 0 ? a[d] : -a[d];
+    r = any ? r + t : t;
+    any = true;
+  }
   return r;
 }
 
@@ -404,7 +415,8 @@ template <typename T, class PP> __device__ __forceinline__ T psi_ref(const PP &P
 template <class L, typename T, class PP, typename Ptr>
 __device__ __forceinline__ void push_potential(Ptr dst, T (&v)[L::Q], const Inst &I, const Node &nd, const PP &P) {
 #pragma unroll
-  for (int j = 0; j < L::Q; ++j) v[j] -= lw<L, T>(j) * lc<L, T>(j, 1) * P.ref_b;
+  for (int j = 0; j < L::Q; ++j)
+    if (L::c(j, 1) != 0) v[j] -= lw<L, T>(j) * lc<L, T>(j, 1) * P.ref_b;
   push<L, T, T>(dst, v, I, nd, 1, T(0), T(0), T(0), P.hwall[0], P.hwall[1], T(1), false);
 }
 
@@ -630,30 +642,50 @@ __global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, cons
 // eps_hat source and Eq. (45) take the gradient of the full psi, so the first
 // moment m = -(tau_h/3) grad(psi') - eps_hat grad(psi) gives
 // grad(psi) = -(m + (tau_h/3) E_ext) iden.
-template <class L, typename T, class PP>
-__device__ __forceinline__ T poisson_collide(const T (&h)[L::Q], T epshat, T iden, T q, const PP &P,
+// Per-instance constants of the potential collision: 1/tau_h, 1 - 1/tau_h
+// and the applied-field term (tau_h/3) E_ext of Eq. (45).
+template <typename T, int D> struct PotK {
+  T ith, omi, ge[D];
+};
+template <int D, typename T, class PP> __device__ __forceinline__ PotK<T, D> pot_k(const PP &P) {
+  PotK<T, D> k;
+  k.ith = T(1) / P.tau_h;
+  k.omi = T(1) - k.ith;
+#pragma unroll
+  for (int d = 0; d < D; ++d) k.ge[d] = P.tau_h / T(3) * P.Eext[d];
+  return k;
+}
+
+// Collision of one node's potential populations (Eqs. 43-45); returns the
+// local potential.  BGK relaxation towards Eq. (44) with the eps_hat
+// first-moment source of Eq. (43):
+//   v_j = h_j (1 - 1/tau_h) + heq_j / tau_h - 3 w_j eps_hat c_j . grad(psi) / tau_h + varpi_j q,
+// grad(psi) = -(m + (tau_h/3) E_ext) iden, iden = 1 / (eps_hat + tau_h/3)
+// (Eq. 45); the factor 3 eps_hat / tau_h is folded into the gradient once.
+template <class L, typename T>
+__device__ __forceinline__ T poisson_collide(const T (&h)[L::Q], T epshat, T iden, T q, const PotK<T, L::D> &K,
                                              T (&v)[L::Q]) {
   constexpr int Q = L::Q, D = L::D;
-  T s1 = 0, m[D];
+  T s1 = h[1], m[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) m[d] = 0;
 #pragma unroll
-  for (int j = 1; j < Q; ++j) s1 += h[j];
+  for (int j = 2; j < Q; ++j) s1 += h[j];
 #pragma unroll
-  for (int j = 0; j < Q; ++j)
+  for (int j = 1; j < Q; ++j)
 #pragma unroll
-    for (int d = 0; d < D; ++d) m[d] += lc<L, T>(j, d) * h[j];
+    for (int d = 0; d < D; ++d)
+      if (L::c(j, d) != 0) m[d] += lc<L, T>(j, d) * h[j];
   const T pot = s1 * (T(1) / (T(1) - lw<L, T>(0)));
-  T g[D];
+  const T sc = -T(3) * epshat * K.ith * iden;
+  T gs[D];
 #pragma unroll
-  for (int d = 0; d < D; ++d) g[d] = -(m[d] + P.tau_h / T(3) * P.Eext[d]) * iden;  // grad(psi), Eq. (45)
-  const T ith = T(1) / P.tau_h;
+  for (int d = 0; d < D; ++d) gs[d] = (m[d] + K.ge[d]) * sc;
+  const T pb = pot * K.ith;
+  v[0] = h[0] * K.omi + (lw<L, T>(0) - T(1)) * pb;
 #pragma unroll
-  for (int j = 0; j < Q; ++j) {
-    const T heq = j == 0 ? (lw<L, T>(0) - T(1)) * pot : lw<L, T>(j) * pot;
-    const T cg = cdot<L>(j, g);
-    v[j] = h[j] - (h[j] - heq) * ith - epshat * T(3) * lw<L, T>(j) * cg * ith + L::template varpi<T>(j) * q;
-  }
+  for (int j = 1; j < Q; ++j)
+    v[j] = h[j] * K.omi + (lw<L, T>(j) * pb - lw<L, T>(j) * cdot<L>(j, gs) + L::template varpi<T>(j) * q);
   return pot;
 }
 template <typename T, class PP> __device__ __forceinline__ T poisson_iden(T epshat, const PP &P) {
@@ -661,7 +693,7 @@ template <typename T, class PP> __device__ __forceinline__ T poisson_iden(T epsh
 }
 template <class L, typename T, class PP>
 __device__ __forceinline__ T poisson_collide(const T (&h)[L::Q], T epshat, T q, const PP &P, T (&v)[L::Q]) {
-  return poisson_collide<L>(h, epshat, poisson_iden(epshat, P), q, P, v);
+  return poisson_collide<L>(h, epshat, poisson_iden(epshat, P), q, pot_k<L::D, T>(P), v);
 }
 
 // a4: one potential sub-iteration (Eqs. 43-45): local potential and gradient
@@ -811,7 +843,8 @@ template <typename T, int RPT, int IT>
 __device__ __forceinline__ void p2_load(const P2Meta<T> &m, const int4 t, P2Regs<T, RPT> &s) {
   const int nx = m.nx, ny = m.ny, N = m.N;
   auto src = gbl(m.src);
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  // a 64-lane wave covers one row of the tile: the row index is uniform
+  const int tx = threadIdx.x & 63, ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int gx = wrapx(((t.y - IT + tx) % nx + nx) % nx, nx);
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
@@ -851,7 +884,8 @@ __device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int wri
   constexpr int ER = P2Shape<RPT, IT>::ER, H2 = P2Shape<RPT, IT>::H, W2 = P2Shape<RPT, IT>::W;
   const int nx = m.nx, ny = m.ny, N = m.N, walls = m.walls;
   auto dst = gbl(m.dst);
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  // a 64-lane wave covers one row of the tile: row tests are uniform branches
+  const int tx = threadIdx.x & 63, ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int gx = wrapx(((t.y - IT + tx) % nx + nx) % nx, nx);
   // interior node of this tile (the nodes the launch writes)
   auto interior = [&](int k, int &n) {
@@ -861,11 +895,16 @@ __device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int wri
     n = s.gy[k] * nx + gx;
     return true;
   };
+  // rows next to an electrode pull some values through the wall
+  bool wall_row[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) wall_row[k] = walls && (s.gy[k] == 0 || s.gy[k] == ny - 1);
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     if (s.inside[k]) s.eh[k] -= m.eps_ref;
     s.id[k] = poisson_iden(s.eh[k], m);
   }
+  const PotK<T, 2> pk = pot_k<2, T>(m);
   for (int it = 0; it < IT; ++it) {
     if (T *lev = rec.lev[it])
 #pragma unroll
@@ -875,16 +914,22 @@ __device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int wri
 #pragma unroll
           for (int j = 0; j < Q; ++j) lev[(size_t)j * N + n] = s.h[k][j];
       }
-    // collide every node this iteration can still use, post values to LDS
+    // collide the rows this iteration can still use (rows outside the valid
+    // ring hold no streamed values; the skip is uniform over a wave), post
+    // the moving values to LDS; the rest value stays in a register
+    T rest[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int r = ty + (P2NT / 64) * k, e = r * P2EW + tx;
+      rest[k] = T(0);
+      if (r < it || r >= ER - it) continue;
       T v[Q];
-      const T pot = poisson_collide<D2Q9>(s.h[k], s.eh[k], s.id[k], s.qq[k], m, v);
+      const T pot = poisson_collide<D2Q9>(s.h[k], s.eh[k], s.id[k], s.qq[k], pk, v);
       int n;
       if (it == IT - 1 && write_psi && interior(k, n)) (gbl(m.psi))[n] = pot + psi_ref<T>(m, s.gy[k]);
+      rest[k] = v[0];
 #pragma unroll
-      for (int j = 0; j < Q; ++j) buf[j * (P2EW * ER) + e] = v[j];
+      for (int j = 1; j < Q; ++j) buf[(j - 1) * (P2EW * ER) + e] = v[j];
     }
     __syncthreads();
     // pull streaming inside the tile; sources beyond an electrode reflect;
@@ -894,14 +939,21 @@ __device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int wri
     for (int k = 0; k < RPT; ++k) {
       const int r = ty + (P2NT / 64) * k, e = r * P2EW + tx;
       if (r < lo || r >= ER - lo || tx < lo || tx >= P2EW - lo || !s.inside[k]) continue;
+      s.h[k][0] = rest[k];
+      if (wall_row[k]) {
 #pragma unroll
-      for (int j = 0; j < Q; ++j) {
-        const int sy = s.gy[k] - cy(j);
-        const T shift = -wgt<T>(j) * T(cy(j)) * m.ref_b;
-        if (walls && (sy < 0 || sy >= ny))
-          s.h[k][j] = -buf[opp(j) * (P2EW * ER) + e] + T(2) * wgt<T>(j) * (sy < 0 ? m.hwall[0] : m.hwall[1]) + shift;
-        else
-          s.h[k][j] = buf[j * (P2EW * ER) + e - cy(j) * P2EW - cx(j)] + shift;
+        for (int j = 1; j < Q; ++j) {
+          const int sy = s.gy[k] - cy(j);
+          const T shift = -wgt<T>(j) * T(cy(j)) * m.ref_b;
+          if (sy < 0 || sy >= ny)
+            s.h[k][j] = -buf[(opp(j) - 1) * (P2EW * ER) + e] + T(2) * wgt<T>(j) * (sy < 0 ? m.hwall[0] : m.hwall[1]) + shift;
+          else
+            s.h[k][j] = buf[(j - 1) * (P2EW * ER) + e - cy(j) * P2EW - cx(j)] + shift;
+        }
+      } else {
+#pragma unroll
+        for (int j = 1; j < Q; ++j)
+          s.h[k][j] = buf[(j - 1) * (P2EW * ER) + e - cy(j) * P2EW - cx(j)] - wgt<T>(j) * T(cy(j)) * m.ref_b;
       }
     }
     __syncthreads();
@@ -923,7 +975,7 @@ template <typename T, int RPT = 1, int IT = 2>
 __global__ __launch_bounds__(P2NT, (sizeof(T) == 8 && RPT == 2) ? 4 : 8) void k_poisson2(const Inst *__restrict__ insts, const int4 *__restrict__ tiles,
                                                  int hpar, int write_psi, int fb, P2Rec<T, IT> rec = P2Rec<T, IT>{}) {
   constexpr int ER = P2Shape<RPT, IT>::ER;
-  __shared__ T buf[Q * P2EW * ER];
+  __shared__ T buf[(Q - 1) * P2EW * ER];  // the moving values; the rest value never leaves its node
   int4 t;
   const P2Meta<T> m = p2_meta<T>(insts, tiles, blockIdx.x, hpar, fb, t);
   P2Regs<T, RPT> s;
@@ -987,7 +1039,8 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
       const T v = h[(size_t)j * N + n];
       if (j) s1 += v;
 #pragma unroll
-      for (int d = 0; d < D; ++d) m[d] += lc<L, T>(j, d) * v;
+      for (int d = 0; d < D; ++d)
+        if (L::c(j, d) != 0) m[d] += lc<L, T>(j, d) * v;
     }
     const T eps = (gbl((const T *)I.eps))[n];
     const T pot = s1 / (T(1) - lw<L, T>(0)) + psi_ref<T>(P, nd.y);
@@ -1173,7 +1226,8 @@ __global__ __launch_bounds__(NT, (EARLY || sizeof(T) > 4 || L::Q > 9) ? 1 : 4) v
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
 #pragma unroll
-      for (int d = 0; d < D; ++d) mg[d] += lc<L, T>(j, d) * g[j];
+      for (int d = 0; d < D; ++d)
+        if (L::c(j, d) != 0) mg[d] += lc<L, T>(j, d) * g[j];
       if (j) s1 += g[j];
     }
     T u[D];
