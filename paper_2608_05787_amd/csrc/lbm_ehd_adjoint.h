@@ -41,6 +41,12 @@ template <typename T> struct AdjBufs {
   double dwall[2]; // d wall_phi / d E0
 };
 
+// v c_x(j) and v c_y(j) for the D2Q9 components -1, 0, 1: exact; a zero
+// component gives -0, which an addition drops at compile time, so the
+// unrolled loops carry no multiplications by zero.
+template <typename T> __device__ __forceinline__ T mcx(int j, T v) { return cx(j) > 0 ? v : (cx(j) < 0 ? -v : T(-0.0)); }
+template <typename T> __device__ __forceinline__ T mcy(int j, T v) { return cy(j) > 0 ? v : (cy(j) < 0 ? -v : T(-0.0)); }
+
 // Destination slot of the population (x, y, j) pushed by the forward step:
 // returns false at a wall, where the slot is (opp(j), this node).
 __device__ __forceinline__ bool push_slot(const Inst &I, int x, int y, int n, int j, size_t &slot, int &dn,
@@ -160,8 +166,8 @@ __global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ ins
   T mxg = 0, myg = 0, s1 = 0;
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
-    mxg += T(cx(j)) * g[j];
-    myg += T(cy(j)) * g[j];
+    mxg += mcx(j, g[j]);
+    myg += mcy(j, g[j]);
     if (j) s1 += g[j];
   }
   // the sweep multiplies by reciprocals (its values need not match the
@@ -242,14 +248,14 @@ __global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ ins
       const T vb = (dir && wall(j)) ? -a : a;
       if (!dir) q_b += a * wu(j);
       An[(size_t)AO_L * N + (size_t)j * N + n] = vb * (T(1) - itl);
-      const T cu = T(cx(j)) * ux + T(cy(j)) * uy;
+      const T cu = mcx(j, ux) + mcy(j, uy);
       const T wv = vb * itl * wgt<T>(j);
       q_b += wv * (T(1) + T(3) * cu);
-      ux_b += wv * q * T(3) * T(cx(j));
-      uy_b += wv * q * T(3) * T(cy(j));
+      ux_b += mcx(j, wv * q * T(3));
+      uy_b += mcy(j, wv * q * T(3));
       R_b += vb * cl * wgt<T>(j);
-      dqx_b += vb * cl * wgt<T>(j) * T(3) * T(cx(j));
-      dqy_b += vb * cl * wgt<T>(j) * T(3) * T(cy(j));
+      dqx_b += mcx(j, vb * cl * wgt<T>(j) * T(3));
+      dqy_b += mcy(j, vb * cl * wgt<T>(j) * T(3));
     }
     // dq = q u - (q u)_prev; (q u) is also this step's history output
     const T hx = hqx, hy = hqy;
@@ -266,26 +272,26 @@ __global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ ins
   for (int j = 0; j < Q; ++j) {
     const T vb = ga[j];
     rho_b += vb * wu(j);
-    const T cu = T(cx(j)) * ux + T(cy(j)) * uy;
+    const T cu = mcx(j, ux) + mcy(j, uy);
     const T sj = wgt<T>(j) * (cu * T(3) + cu * cu * T(4.5) - usq * T(1.5));
     const T geq = (j == 0 ? (wgt<T>(0) - T(1)) * pp * T(3) : wgt<T>(j) * pp * T(3)) + rho * sj;
-    const T cF = T(cx(j)) * Fx + T(cy(j)) * Fy;
-    const T cgr = T(cx(j)) * grx + T(cy(j)) * gry;
+    const T cF = mcx(j, Fx) + mcy(j, Fy);
+    const T cgr = mcx(j, grx) + mcy(j, gry);
     const T Gb = wgt<T>(j) * (udr + cF * T(3) + (cu * cgr - udr / T(3)) * T(3));
     g_b[j] = vb * (T(1) - itg);
     itg_b += vb * (-(g[j] - geq) - T(0.5) * Gb);
     pp_b += vb * itg * (j == 0 ? T(3) * (wgt<T>(0) - T(1)) : T(3) * wgt<T>(j));
     rho_b += vb * itg * sj;
     const T ws = vb * itg * rho * wgt<T>(j);
-    ux_b += ws * (T(3) * T(cx(j)) + T(9) * cu * T(cx(j)) - T(3) * ux);
-    uy_b += ws * (T(3) * T(cy(j)) + T(9) * cu * T(cy(j)) - T(3) * uy);
+    ux_b += ws * (mcx(j, T(3) + T(9) * cu) - T(3) * ux);
+    uy_b += ws * (mcy(j, T(3) + T(9) * cu) - T(3) * uy);
     const T Gb_b = vb * cg * T(3) * wgt<T>(j);
-    Fx_b += Gb_b * T(cx(j));
-    Fy_b += Gb_b * T(cy(j));
-    ux_b += Gb_b * cgr * T(cx(j));
-    uy_b += Gb_b * cgr * T(cy(j));
-    grx_b += Gb_b * cu * T(cx(j));
-    gry_b += Gb_b * cu * T(cy(j));
+    Fx_b += mcx(j, Gb_b);
+    Fy_b += mcy(j, Gb_b);
+    ux_b += mcx(j, Gb_b * cgr);
+    uy_b += mcy(j, Gb_b * cgr);
+    grx_b += mcx(j, Gb_b * cu);
+    gry_b += mcy(j, Gb_b * cu);
   }
   {
     const T tg_b = -itg_b * itg * itg;
@@ -313,13 +319,13 @@ __global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ ins
           mu_b[i] -= vb * itf * (T(1) - wgt<T>(0));
         } else {
           const T wv = vb * itf * wgt<T>(j);
-          ph_b[i] += wv * T(3) * (T(cx(j)) * ux + T(cy(j)) * uy);
-          ux_b += wv * T(3) * ph[i] * T(cx(j));
-          uy_b += wv * T(3) * ph[i] * T(cy(j));
+          ph_b[i] += wv * T(3) * (mcx(j, ux) + mcy(j, uy));
+          ux_b += mcx(j, wv * T(3) * ph[i]);
+          uy_b += mcy(j, wv * T(3) * ph[i]);
           mu_b[i] += wv;
         }
-        dtx_b += cf * vb * wgt<T>(j) * T(cx(j));
-        dty_b += cf * vb * wgt<T>(j) * T(cy(j));
+        dtx_b += mcx(j, cf * vb * wgt<T>(j));
+        dty_b += mcy(j, cf * vb * wgt<T>(j));
       }
       dpx_b = T(3) * dtx_b;
       dpy_b = T(3) * dty_b;
@@ -369,7 +375,7 @@ __global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ ins
     rho_b -= (ux_b * ux + uy_b * uy) * irho;
 #pragma unroll
     for (int j = 0; j < Q; ++j)
-      An[(size_t)(AO_G + j) * N + n] = g_b[j] + T(cx(j)) * mx_b + T(cy(j)) * my_b + (j ? s1_b : T(0));
+      An[(size_t)(AO_G + j) * N + n] = g_b[j] + mcx(j, mx_b) + mcy(j, my_b) + (j ? s1_b : T(-0.0));
   }
 
   // ---- force -sum phi_i grad mu_i + q E (Eq. 27b) and rho of Eq. (29)
@@ -428,8 +434,8 @@ __global__ __launch_bounds__(NT) void k_adj_mu(const Inst *__restrict__ insts, c
         const T w3 = T(3) * wgt<T>(j);
 #pragma unroll
         for (int i = 0; i < 3; ++i)
-          mu_b[i] += w3 * (T(cx(j)) * ab.gm[(size_t)(2 * i) * N + s] + T(cy(j)) * ab.gm[(size_t)(2 * i + 1) * N + s]);
-        gr_t += w3 * (T(cx(j)) * ab.gr[s] + T(cy(j)) * ab.gr[(size_t)N + s]);
+          mu_b[i] += w3 * (mcx(j, ab.gm[(size_t)(2 * i) * N + s]) + mcy(j, ab.gm[(size_t)(2 * i + 1) * N + s]));
+        gr_t += w3 * (mcx(j, ab.gr[s]) + mcy(j, ab.gr[(size_t)N + s]));
       });
 #pragma unroll
       for (int i = 0; i < 3; ++i) ph_b[i] += P.rho[i] * gr_t;
@@ -451,12 +457,12 @@ __global__ __launch_bounds__(NT) void k_adj_mu(const Inst *__restrict__ insts, c
     ex_b += T(2) * Ex * e2_b;
     ey_b += T(2) * Ey * e2_b;
     // E = (m + (tau_h/3) E_ext) / den with m the first moment of the final h
-    const T den = (rc.eps[n] - P.eps_ref) + P.tau_h / T(3);
-    const T mx_b = ex_b / den, my_b = ey_b / den;
-    th[6] += ((double)mx_b * ab.dEext[0] + (double)my_b * ab.dEext[1]) * (double)(P.tau_h / T(3));
-    ab.eb[n] = -(ex_b * Ex + ey_b * Ey) / den;
+    const T th3 = P.tau_h / T(3), iden = T(1) / ((rc.eps[n] - P.eps_ref) + th3);
+    const T mx_b = ex_b * iden, my_b = ey_b * iden;
+    th[6] += ((double)mx_b * ab.dEext[0] + (double)my_b * ab.dEext[1]) * (double)th3;
+    ab.eb[n] = -(ex_b * Ex + ey_b * Ey) * iden;
 #pragma unroll
-    for (int j = 1; j < Q; ++j) hb[(size_t)j * N + n] = hb0[j] + (T(cx(j)) * mx_b + T(cy(j)) * my_b);
+    for (int j = 1; j < Q; ++j) hb[(size_t)j * N + n] = hb0[j] + (mcx(j, mx_b) + mcy(j, my_b));
 #pragma unroll
     for (int i = 0; i < 3; ++i) PBn[(size_t)i * N + n] = pb0[i] + ph_b[i];
   }
@@ -469,36 +475,60 @@ __global__ __launch_bounds__(NT) void k_adj_mu(const Inst *__restrict__ insts, c
 // to eps_hat-bar, q-bar and the applied field's adjoint ee_b (which enters
 // through grad(psi) = -(m + (tau_h/3) E_ext) iden).
 //   iden: 1 / (eps_hat + tau_h / 3), as the forward collision forms it.
+// Constants of the potential collision's adjoint: 1/tau_h and tau_h/3.
+template <typename T> struct AdjPotK {
+  T ith, tau3;
+};
+template <typename T> __device__ __forceinline__ AdjPotK<T> adj_pot_k(const Phys<T> &P) {
+  AdjPotK<T> k;
+  k.ith = T(1) / P.tau_h;
+  k.tau3 = P.tau_h / T(3);
+  return k;
+}
+// Terms with a zero lattice coefficient are left out (they are exact zeros).
 template <typename T>
 __device__ __forceinline__ void adj_poisson_local(const T (&vb)[Q], const T (&h)[Q], T eh, T iden, const Phys<T> &P,
-                                                  T (&hb)[Q], T &eh_b, T &q_b, T (&ee_b)[2]) {
-  T mx = P.tau_h / T(3) * P.Eext[0], my = P.tau_h / T(3) * P.Eext[1];
+                                                  const AdjPotK<T> &K, T (&hb)[Q], T &eh_b, T &q_b, T (&ee_b)[2]) {
+  T mx = K.tau3 * P.Eext[0], my = K.tau3 * P.Eext[1];
 #pragma unroll
-  for (int j = 0; j < Q; ++j) {
-    mx += T(cx(j)) * h[j];
-    my += T(cy(j)) * h[j];
+  for (int j = 1; j < Q; ++j) {
+    if (cx(j)) mx += T(cx(j)) * h[j];
+    if (cy(j)) my += T(cy(j)) * h[j];
   }
   const T gx = -mx * iden, gy = -my * iden;
-  const T ith = T(1) / P.tau_h;
+  const T ith = K.ith;
   T pot_b = 0, gx_b = 0, gy_b = 0;
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
     pot_b += vb[j] * ith * (j == 0 ? wgt<T>(0) - T(1) : wgt<T>(j));
+    if (j == 0) continue;
     const T c3 = vb[j] * T(3) * wgt<T>(j) * ith;
-    gx_b -= c3 * eh * T(cx(j));
-    gy_b -= c3 * eh * T(cy(j));
-    eh_b -= c3 * (T(cx(j)) * gx + T(cy(j)) * gy);
-    if (j) q_b += T(0.125) * vb[j];
+    if (cx(j)) gx_b -= c3 * eh * T(cx(j));
+    if (cy(j)) gy_b -= c3 * eh * T(cy(j));
+    const T cg = cx(j) && cy(j) ? T(cx(j)) * gx + T(cy(j)) * gy : (cx(j) ? T(cx(j)) * gx : T(cy(j)) * gy);
+    eh_b -= c3 * cg;
+    q_b += T(0.125) * vb[j];
   }
   // g = -M iden, M = m + (tau_h/3) E_ext, iden = 1 / (eps_hat + tau_h / 3):
   // dg/d eps_hat = M iden^2
   const T mx_b = -gx_b * iden, my_b = -gy_b * iden;
   eh_b += (gx_b * mx + gy_b * my) * (iden * iden);
-  ee_b[0] += mx_b * (P.tau_h / T(3));
-  ee_b[1] += my_b * (P.tau_h / T(3));
+  ee_b[0] += mx_b * K.tau3;
+  ee_b[1] += my_b * K.tau3;
   const T ps_b = pot_b * (T(1) / (T(1) - wgt<T>(0)));
+  hb[0] = vb[0] * (T(1) - ith);
 #pragma unroll
-  for (int j = 0; j < Q; ++j) hb[j] = vb[j] * (T(1) - ith) + T(cx(j)) * mx_b + T(cy(j)) * my_b + (j ? ps_b : T(0));
+  for (int j = 1; j < Q; ++j) {
+    T a = vb[j] * (T(1) - ith);
+    if (cx(j)) a += T(cx(j)) * mx_b;
+    if (cy(j)) a += T(cy(j)) * my_b;
+    hb[j] = a + ps_b;
+  }
+}
+template <typename T>
+__device__ __forceinline__ void adj_poisson_local(const T (&vb)[Q], const T (&h)[Q], T eh, T iden, const Phys<T> &P,
+                                                  T (&hb)[Q], T &eh_b, T &q_b, T (&ee_b)[2]) {
+  adj_poisson_local(vb, h, eh, iden, P, adj_pot_k(P), hb, eh_b, q_b, ee_b);
 }
 template <typename T>
 __device__ __forceinline__ void adj_poisson_local(const T (&vb)[Q], const T (&h)[Q], T eh, const Phys<T> &P,
@@ -578,7 +608,8 @@ __global__ __launch_bounds__(P2NT) void k_adj_poisson2(const Inst *__restrict__ 
   const Inst &I = insts[t.x];
   const Phys<T> &P = phys<T>(I);
   const int nx = I.nx, ny = I.ny, N = I.N, walls = I.bc_y;
-  const int tx = threadIdx.x & 63, r = threadIdx.x >> 6;  // one extended node per thread (P2RPT == 1)
+  // one extended node per thread (P2RPT == 1); a wave covers one row
+  const int tx = threadIdx.x & 63, r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int gx = wrapx(((t.y - 2 + tx) % nx + nx) % nx, nx);
   int gy = t.z - 2 + r;
   bool inside = true;
@@ -610,18 +641,26 @@ __global__ __launch_bounds__(P2NT) void k_adj_poisson2(const Inst *__restrict__ 
   T eh_b = 0, q_b = 0, ee_b[2] = {T(0), T(0)};
   const T eh = ring1 ? epsv - P.eps_ref : T(0);
   const T iden = poisson_iden(eh, P);
-  // pull of the adjoint through the push of node (r, tx); wall slots at the node itself
+  const AdjPotK<T> pk = adj_pot_k(P);
+  const bool wall_row = walls && (gy == 0 || gy == ny - 1);
+  // pull of the adjoint through the push of node (r, tx); wall slots at the
+  // node itself (rows next to an electrode only)
   auto pull = [&](T (&vb)[Q]) {
+    if (wall_row) {
 #pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      const int yd = gy + cy(j);
-      if (walls && (yd < 0 || yd >= ny)) {
-        const T a = buf[opp(j) * (P2EW * P2ER) + e];
-        vb[j] = -a;
-        if (interior) th += 2.0 * (double)(wgt<T>(j) * a) * ab.dwall[yd >= ny ? 1 : 0];
-      } else {
-        vb[j] = buf[j * (P2EW * P2ER) + e + cy(j) * P2EW + cx(j)];
+      for (int j = 0; j < Q; ++j) {
+        const int yd = gy + cy(j);
+        if (yd < 0 || yd >= ny) {
+          const T a = buf[opp(j) * (P2EW * P2ER) + e];
+          vb[j] = -a;
+          if (interior) th += 2.0 * (double)(wgt<T>(j) * a) * ab.dwall[yd >= ny ? 1 : 0];
+        } else {
+          vb[j] = buf[j * (P2EW * P2ER) + e + cy(j) * P2EW + cx(j)];
+        }
       }
+    } else {
+#pragma unroll
+      for (int j = 0; j < Q; ++j) vb[j] = buf[j * (P2EW * P2ER) + e + cy(j) * P2EW + cx(j)];
     }
   };
   T hb[Q];
@@ -629,7 +668,7 @@ __global__ __launch_bounds__(P2NT) void k_adj_poisson2(const Inst *__restrict__ 
     T vb[Q];
     pull(vb);
     T eb1 = 0, qb1 = 0, ee1[2] = {T(0), T(0)};
-    adj_poisson_local(vb, h1v, eh, iden, P, hb, eb1, qb1, ee1);
+    adj_poisson_local(vb, h1v, eh, iden, P, pk, hb, eb1, qb1, ee1);
     if (interior) {
       eh_b += eb1;
       q_b += qb1;
@@ -647,7 +686,7 @@ __global__ __launch_bounds__(P2NT) void k_adj_poisson2(const Inst *__restrict__ 
     pull(vb);
 #pragma unroll
     for (int j = 0; j < Q; ++j) h[j] = h0[(size_t)j * N + n];
-    adj_poisson_local(vb, h, eh, iden, P, hb, eh_b, q_b, ee_b);
+    adj_poisson_local(vb, h, eh, iden, P, pk, hb, eh_b, q_b, ee_b);
     T *Hd = ab.hb[src ^ 1];
 #pragma unroll
     for (int j = 0; j < Q; ++j) Hd[(size_t)j * N + n] = hb[j];
@@ -690,10 +729,11 @@ __global__ __launch_bounds__(P2NT) void k_adj_poisson4(const Inst *__restrict__ 
   const Inst &I = insts[t.x];
   const Phys<T> &P = phys<T>(I);
   const int nx = I.nx, ny = I.ny, N = I.N, walls = I.bc_y;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  // a 64-lane wave covers one row of the tile: row tests are uniform branches
+  const int tx = threadIdx.x & 63, ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int gx = wrapx(((t.y - IT + tx) % nx + nx) % nx, nx);
   int gy[RPT], n[RPT], e[RPT], dist[RPT];
-  bool inside[RPT], interior[RPT];
+  bool inside[RPT], interior[RPT], wall_row[RPT];
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     const int r = ty + (P2NT / 64) * k;
@@ -708,6 +748,7 @@ __global__ __launch_bounds__(P2NT) void k_adj_poisson4(const Inst *__restrict__ 
     const int dr = r < ER - 1 - r ? r : ER - 1 - r, dc = tx < P2EW - 1 - tx ? tx : P2EW - 1 - tx;
     dist[k] = dr < dc ? dr : dc;  // 0 on the tile's outermost ring
     interior[k] = in && dist[k] >= IT && r - IT < H4 && tx - IT < W4 && t.y + tx - IT < nx && t.z + r - IT < ny;
+    wall_row[k] = walls && (y == 0 || y == ny - 1);
   }
   // the adjoint of the output level and eps, in one burst of loads
   const T *Hs = ab.hb[src];
@@ -732,6 +773,7 @@ __global__ __launch_bounds__(P2NT) void k_adj_poisson4(const Inst *__restrict__ 
     eh_b[k] = q_b[k] = T(0);
   }
   const T *lvs[IT] = {lv0, lv1, lv2, lv3};
+  const AdjPotK<T> pk = adj_pot_k(P);
   T hb[RPT][Q];
 #pragma unroll 1
   for (int i = IT; i >= 1; --i) {
@@ -741,22 +783,28 @@ __global__ __launch_bounds__(P2NT) void k_adj_poisson4(const Inst *__restrict__ 
     for (int k = 0; k < RPT; ++k) {
       if (!inside[k] || dist[k] < need) continue;
       T vb[Q], h[Q];
-      // pull of the adjoint through the push of this node; wall slots at the node itself
+      // pull of the adjoint through the push of this node; wall slots at the
+      // node itself (rows next to an electrode only)
+      if (wall_row[k]) {
 #pragma unroll
-      for (int j = 0; j < Q; ++j) {
-        const int yd = gy[k] + cy(j);
-        if (walls && (yd < 0 || yd >= ny)) {
-          const T a = buf[opp(j) * PL + e[k]];
-          vb[j] = -a;
-          if (interior[k]) th += 2.0 * (double)(wgt<T>(j) * a) * ab.dwall[yd >= ny ? 1 : 0];
-        } else {
-          vb[j] = buf[j * PL + e[k] + cy(j) * P2EW + cx(j)];
+        for (int j = 0; j < Q; ++j) {
+          const int yd = gy[k] + cy(j);
+          if (yd < 0 || yd >= ny) {
+            const T a = buf[opp(j) * PL + e[k]];
+            vb[j] = -a;
+            if (interior[k]) th += 2.0 * (double)(wgt<T>(j) * a) * ab.dwall[yd >= ny ? 1 : 0];
+          } else {
+            vb[j] = buf[j * PL + e[k] + cy(j) * P2EW + cx(j)];
+          }
         }
+      } else {
+#pragma unroll
+        for (int j = 0; j < Q; ++j) vb[j] = buf[j * PL + e[k] + cy(j) * P2EW + cx(j)];
       }
 #pragma unroll
       for (int j = 0; j < Q; ++j) h[j] = lv[(size_t)j * N + n[k]];
       T eb1 = 0, qb1 = 0, ee1[2] = {T(0), T(0)};
-      adj_poisson_local(vb, h, eh[k], iden[k], P, hb[k], eb1, qb1, ee1);
+      adj_poisson_local(vb, h, eh[k], iden[k], P, pk, hb[k], eb1, qb1, ee1);
       if (interior[k]) {
         eh_b[k] += eb1;
         q_b[k] += qb1;
@@ -903,8 +951,8 @@ __global__ __launch_bounds__(NT) void k_adj_phi(const Inst *__restrict__ insts, 
     T te = 0, ts = 0;
     for_sources(I, nd.x, nd.y, [&](int j, int s) {
       const T w3 = T(3) * wgt<T>(j);
-      te += w3 * (T(cx(j)) * ab.ge[s] + T(cy(j)) * ab.ge[(size_t)N + s]);
-      ts += w3 * (T(cx(j)) * ab.gs[s] + T(cy(j)) * ab.gs[(size_t)N + s]);
+      te += w3 * (mcx(j, ab.ge[s]) + mcy(j, ab.ge[(size_t)N + s]));
+      ts += w3 * (mcx(j, ab.gs[s]) + mcy(j, ab.gs[(size_t)N + s]));
     });
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
