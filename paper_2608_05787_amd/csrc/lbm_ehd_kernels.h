@@ -159,6 +159,30 @@ template <typename T>
 using gptr = typename std::conditional<std::is_arithmetic<typename std::remove_cv<T>::type>::value,
                                        __attribute__((address_space(1))) T *, T *>::type;
 template <typename T> __device__ __forceinline__ gptr<T> gbl(T *p) { return (gptr<T>)p; }
+// Element i of a plane with a uniform base, addressed with a 32-bit byte
+// offset (scalar base + vector offset addressing instead of a 64-bit vector
+// address per load); a plane's byte offsets stay below 2^32 (fewer than 2^30
+// nodes of 4 bytes, 2^29 of 8).
+template <typename T>
+__device__ __forceinline__ T ld_plane(const __attribute__((address_space(1))) T *base, unsigned i) {
+  using cb = const __attribute__((address_space(1))) char *;
+  return *(const __attribute__((address_space(1))) T *)((cb)base + i * (unsigned)sizeof(T));
+}
+template <typename T> __device__ __forceinline__ T ld_plane(const T *base, unsigned i) { return base[i]; }
+// A pointer the caller knows to be uniform, materialised in scalar registers
+// (keeps the compiler from folding a plane offset into every lane's address).
+template <typename P> __device__ __forceinline__ P uniform_ptr(P p) {
+  const unsigned long long v = (unsigned long long)p;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (P)(((unsigned long long)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ void st_plane(__attribute__((address_space(1))) T *base, unsigned i, T v) {
+  using bp = __attribute__((address_space(1))) char *;
+  *(__attribute__((address_space(1))) T *)((bp)base + i * (unsigned)sizeof(T)) = v;
+}
+template <typename T> __device__ __forceinline__ void st_plane(T *base, unsigned i, T v) { base[i] = v; }
 using gwords = __attribute__((address_space(1))) unsigned short *;
 using gcwords = const __attribute__((address_space(1))) unsigned short *;
 __device__ __forceinline__ gwords gbl(__half *p) { return (gwords)p; }
@@ -595,12 +619,15 @@ __global__ __launch_bounds__(NT) void k_pre(const Inst *__restrict__ insts, cons
 #pragma unroll
   for (int d = 0; d < D; ++d) e[d] = E[(size_t)d * N + n];
   const T lsum = (gbl((const T *)I.lsum))[n];
+  // uniform plane bases and 32-bit node offsets (scalar base + vector offset
+  // addressing instead of a 64-bit vector address per load)
+  decltype(phi) pl[3] = {uniform_ptr(phi), uniform_ptr(phi + N), uniform_ptr(phi + 2 * (size_t)N)};
   T pv[3][Q];
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
     const int m = nbr<L>(I, nd, j);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) pv[i][j] = phi[(size_t)i * N + m];
+    for (int i = 0; i < 3; ++i) pv[i][j] = ld_plane(pl[i], (unsigned)m);
   }
   T ev[Q], sv[Q];
 #pragma unroll
@@ -1036,18 +1063,18 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
     for (int d = 0; d < D; ++d) m[d] = 0;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-      const T v = h[(size_t)j * N + n];
+      const T v = ld_plane(uniform_ptr(h + (size_t)j * N), (unsigned)n);
       if (j) s1 += v;
 #pragma unroll
       for (int d = 0; d < D; ++d)
         if (L::c(j, d) != 0) m[d] += lc<L, T>(j, d) * v;
     }
     const T eps = (gbl((const T *)I.eps))[n];
-    const T pot = s1 / (T(1) - lw<L, T>(0)) + psi_ref<T>(P, nd.y);
-    const T den = (eps - P.eps_ref) + P.tau_h / T(3);
+    const T pot = s1 * (T(1) / (T(1) - lw<L, T>(0))) + psi_ref<T>(P, nd.y);
+    const T th3 = P.tau_h / T(3), iden = T(1) / ((eps - P.eps_ref) + th3);
     T e[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) e[d] = (m[d] + P.tau_h / T(3) * P.Eext[d]) / den;
+    for (int d = 0; d < D; ++d) e[d] = (m[d] + th3 * P.Eext[d]) * iden;
     auto psi = gbl((T *)I.psi);
     // the phi stencils and the previous potential, loaded before the first
     // store (later loads would wait for it: the compiler cannot tell the
@@ -1058,7 +1085,7 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
     for (int j = 0; j < Q; ++j) {
       const int m = nbr<L>(I, nd, j);
 #pragma unroll
-      for (int i = 0; i < 3; ++i) pv[i][j] = phi[(size_t)i * N + m];
+      for (int i = 0; i < 3; ++i) pv[i][j] = ld_plane(uniform_ptr(phi + (size_t)i * N), (unsigned)m);
     }
     const double dd = (double)pot - (double)psi[n];
     red[0] = dd * dd;
@@ -1068,7 +1095,7 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
     T e2 = e[0] * e[0];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      E[(size_t)d * N + n] = e[d];
+      st_plane(uniform_ptr(E + (size_t)d * N), (unsigned)n, e[d]);
       if (rc.En) rc.En[(size_t)d * N + n] = e[d];
       if (d) e2 += e[d] * e[d];
     }
@@ -1081,7 +1108,7 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
       const T bulk = T(24) / P.D * P.lam[i] * ph * (ph - T(0.5)) * (ph - T(1));
       const T grad = T(0.75) * P.D * P.lam[i] * lap;
       const T elec = T(0.5) * (T(6) * P.eps[i] * ph * (T(1) - ph)) * e2;
-      mu[(size_t)i * N + n] = bulk - grad - elec;
+      st_plane(uniform_ptr(mu + (size_t)i * N), (unsigned)n, bulk - grad - elec);
       if (rc.mu) rc.mu[(size_t)i * N + n] = bulk - grad - elec;
     }
   }
