@@ -42,6 +42,10 @@ def bytes_per_node(kernel, prec="fp32", Q=9, D=2):
         "pre": (3 + 1 + D) * t + 3 * t,                    # phi, l-sum, E in; eps, q, R out
         "poisson": (Q + 1 + 1) * t + Q * t,                # h, eps, q in; h out (one sub-iteration)
         "poisson2": (Q + 1 + 1) * t + Q * t,               # the same for two or four sub-iterations per launch
+        # a step's first four-sub-iteration launch with the charge step folded
+        # in: h, phi, l-sum, E in; h, eps, q, R out (pre's traffic less the
+        # eps and q it no longer re-reads)
+        "poisson2_pre": (Q + 3 + 1 + D) * t + (Q + 3) * t,
         "mu": (Q + 1 + 1 + 3) * t + (1 + D + 3) * t,        # h, eps, psi, phi in; psi, E, mu out
         # pops in and out; phi and q of this and the previous step, mu, R, E,
         # the previous velocity in; the velocity out (p, rho on output steps only)
@@ -49,7 +53,8 @@ def bytes_per_node(kernel, prec="fp32", Q=9, D=2):
     }[kernel]
 
 
-BYTES_PER_NODE_FP32 = {k: bytes_per_node(k) for k in ("moments", "pre", "poisson", "poisson2", "mu", "collide")}
+BYTES_PER_NODE_FP32 = {k: bytes_per_node(k) for k in ("moments", "pre", "poisson", "poisson2", "poisson2_pre", "mu",
+                                                        "collide")}
 
 
 def log(*a):
@@ -518,8 +523,14 @@ def main():
         return quads + (rest - 4 * quads) // 2, n1
 
     def step_bytes(prec, cfg):
-        return sum(bytes_per_node(k, prec) * dict(zip(("poisson2", "poisson"), launches(cfg))).get(k, 1)
-                   for k in BYTES_PER_NODE_FP32)
+        """Algorithmic bytes per node of one step in configuration cfg: with
+        tall tiles and an even K >= 4 the charge step rides on the first
+        four-sub-iteration launch."""
+        n2, n1 = launches(cfg)
+        fold = bool(cfg & 8) and not cfg & 2 and args.sub >= 4 and args.sub % 2 == 0
+        count = {"moments": 1, "pre": 0 if fold else 1, "poisson": n1, "poisson2": n2 - fold,
+                 "poisson2_pre": int(fold), "mu": 1, "collide": 1}
+        return sum(bytes_per_node(k, prec) * c for k, c in count.items())
 
     cfg32 = tune["config"] if tune else 0
     variants = {"fp32": {"mlups": round(mlups, 1), "ms_per_step": ms / args.steps, "launch_config": cfg32,

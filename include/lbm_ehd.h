@@ -315,8 +315,10 @@ int lbm_ehd_scalars(lbm_ehd_t h, double out[3]);
  *    four sub-iterations per launch (ring of 4, 56 x 24 written, one HBM
  *    round trip of h per four sub-iterations) while four remain, then two
  *    (60 x 28 written); FP32 and FP16S handles where the LDS-tiled kernel
- *    runs.  The forms agree to rounding (the compiler fuses their
- *    multiply-adds differently).
+ *    runs.  With a fixed even K >= 4 the step's first four-sub-iteration
+ *    launch also forms the charge, Ohmic source and permittivity on its
+ *    tiles (no separate launch for them).  The forms agree to rounding (the
+ *    compiler fuses their multiply-adds differently).
  * A captured graph (lbm_ehd_graph) is re-captured with the new
  * configuration. */
 enum {
@@ -397,8 +399,10 @@ int lbm_ehd_tangent_gradient(lbm_ehd_t h, int64_t n_steps, const void *dev_seed,
  * lbm_ehd_profile_end synchronises and returns, per kernel kind, the summed
  * event time in ms and the launch count: index 0 moments, 1 charge/stencil
  * (pre), 2 single potential sub-iteration, 3 field + chemical potential,
- * 4 fused collide-and-stream, 5 diagnostics, 6 two potential sub-iterations
- * in one launch; 7 unused. */
+ * 4 fused collide-and-stream, 5 diagnostics, 6 two or four potential
+ * sub-iterations in one launch, 7 a step's first launch of four potential
+ * sub-iterations that also forms the charge (kind 1's work, which then has
+ * no launch of its own: a fixed even K >= 4 on tall tiles). */
 int lbm_ehd_profile_begin(lbm_ehd_t h);
 int lbm_ehd_profile_end(lbm_ehd_t h, double ms[8], int64_t launches[8]);
 

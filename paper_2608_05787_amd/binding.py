@@ -67,7 +67,7 @@ EXPORTS = ["lbm_ehd_adjoint_workspace_bytes", "lbm_ehd_workspace_bytes", "lbm_eh
            "lbm_ehd_set_tuning", "lbm_ehd_get_tuning", "lbm_ehd_tune",
            "lbm_ehd_destroy", "lbm_ehd_strerror", "lbm_ehd_last_error"]
 TUNE_LINEAR_ORDER, TUNE_SINGLE_POTENTIAL, TUNE_COLLIDE_PER_FAMILY, TUNE_TALL_TILES = 1, 2, 4, 8
-KERNELS = ["moments", "pre", "poisson", "mu", "collide", "diag", "poisson2"]
+KERNELS = ["moments", "pre", "poisson", "mu", "collide", "diag", "poisson2", "poisson2_pre"]
 
 _lib = None
 

@@ -427,8 +427,10 @@ int static_scratch(lbm_ehd_s *H, double **out) {
 // launch per iteration.  Returns the launch count
 // (its parity is the buffer flip of the whole loop).
 //   fb: the field buffer holding the charge (the step's; 1 at create).
+//   pre: the first launch also forms the step's charge, source and
+//   permittivity (fold_pre; k_pre is then not launched).
 template <class Lat, typename T>
-int enqueue_fixed_potential(lbm_ehd_s *H, int K, int fb) {
+int enqueue_fixed_potential(lbm_ehd_s *H, int K, int fb, bool pre = false) {
   const dim3 grid(H->plan.total_blocks), grid2(H->n_t2), block(NT), block2(P2NT);
   int L = 0, k = 1;
   if constexpr (sizeof(T) <= 8 && std::is_same<Lat, D2Q9>::value) {
@@ -444,9 +446,14 @@ int enqueue_fixed_potential(lbm_ehd_s *H, int K, int fb) {
       if constexpr (sizeof(T) <= 8) {
         if (H->tall())
           for (; k + 3 <= K; k += 4, ++L) {
-            hipEvent_t e = H->prof_start(6);
-            k_poisson2<T, 2, 4><<<dim3(H->plan.total_tiles4), block2, 0, H->stream>>>(H->d_insts, H->d_t4, L & 1,
-                                                                                      k + 3 == K ? 1 : 0, fb);
+            const bool fold = pre && k == 1;
+            hipEvent_t e = H->prof_start(fold ? 7 : 6);
+            if (fold)
+              k_poisson2<T, 2, 4, true><<<dim3(H->plan.total_tiles4), block2, 0, H->stream>>>(
+                  H->d_insts, H->d_t4, L & 1, k + 3 == K ? 1 : 0, fb);
+            else
+              k_poisson2<T, 2, 4><<<dim3(H->plan.total_tiles4), block2, 0, H->stream>>>(H->d_insts, H->d_t4, L & 1,
+                                                                                        k + 3 == K ? 1 : 0, fb);
             H->prof_stop(e);
           }
       }
@@ -472,6 +479,16 @@ int enqueue_fixed_potential(lbm_ehd_s *H, int K, int fb) {
     H->prof_stop(e);
   }
   return L;
+}
+
+// Whether a step folds k_pre into its first potential launch: a fixed, even
+// sub-iteration count K >= 4 on tall tiles, whose first launch is then a
+// four-sub-iteration one (D2Q9, FP32/FP16S/FP64 arithmetic).
+template <class Lat, typename T>
+bool fold_pre(const lbm_ehd_s *H, int K, int adaptive) {
+  if constexpr (std::is_same<Lat, D2Q9>::value && sizeof(T) <= 8)
+    return !adaptive && H->pairs() && H->tall() && K >= 4 && !(K & 1);
+  return false;
 }
 
 template <class Lat, typename T, typename S>
@@ -581,9 +598,12 @@ int do_step(lbm_ehd_s *H, int64_t n) {
     }
     if (!vec) k_moments<Lat, T, S><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, pc);
     H->prof_stop(e);
-    e = H->prof_start(1);
-    k_pre<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, pc);
-    H->prof_stop(e);
+    const bool fold = fold_pre<Lat, T>(H, K, ad);
+    if (!fold) {
+      e = H->prof_start(1);
+      k_pre<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, pc);
+      H->prof_stop(e);
+    }
     int hflip = 0;
     if (ad) {
       for (int k = 1; k <= K; ++k) {
@@ -593,7 +613,7 @@ int do_step(lbm_ehd_s *H, int64_t n) {
         k_reduce_poisson<<<H->n_inst, block, 0, H->stream>>>(H->d_insts, k, H->sub_min, H->sub_tol, K);
       }
     } else {
-      hflip = enqueue_fixed_potential<Lat, T>(H, K, pc) & 1;
+      hflip = enqueue_fixed_potential<Lat, T>(H, K, pc, fold) & 1;
     }
     e = H->prof_start(3);
     k_mu<Lat, T><<<grid, block, 0, H->stream>>>(H->d_insts, H->d_b2i, hflip, pc);

@@ -281,6 +281,9 @@ __device__ __forceinline__ Node locate(const Inst *__restrict__ insts, const int
 }
 
 __device__ __forceinline__ int wrapx(int x, int nx) { return x < 0 ? x + nx : (x >= nx ? x - nx : x); }
+// x mod n; one: x is known to lie in [-n, 2n) (a uniform test), which
+// takes one conditional add instead of the integer remainder
+__device__ __forceinline__ int wrapn(int x, int n, bool one) { return one ? wrapx(x, n) : ((x % n) + n) % n; }
 // finite-difference neighbour row: wrap (periodic) or mirror ghost (walls)
 // (both forms computed and selected: no branch between the stencil loads)
 __device__ __forceinline__ int fdrow(int y, int ny, int walls) {
@@ -817,9 +820,13 @@ template <typename T> struct P2Meta {
   T *dst, *psi;
   int nx, ny, N, walls;
   T tau_h, eps_ref, hwall[2], Eext[2], ref_a, ref_b;
+  // the charge step folded into the launch (PRE): its inputs and outputs
+  const T *phi, *Eo, *lsum;
+  T *q_out, *R_out, *eps_out;
+  T pe[3], ps[3];  // phase permittivities and conductivities (Eqs. 29-30)
 };
 
-template <typename T>
+template <typename T, bool PRE = false>
 __device__ __forceinline__ P2Meta<T> p2_meta(const Inst *insts, const int4 *tiles, int ti, int hpar, int fb, int4 &t) {
   const cptr<int> tp = cst((const int *)tiles) + 4 * (size_t)ti;
   t = make_int4(tp[0], tp[1], tp[2], 0);
@@ -854,6 +861,24 @@ __device__ __forceinline__ P2Meta<T> p2_meta(const Inst *insts, const int4 *tile
     m.Eext[0] = I->pd.Eext[0];
     m.Eext[1] = I->pd.Eext[1];
   }
+  if constexpr (PRE) {
+    m.phi = (const T *)I->phi[fb];
+    m.Eo = (const T *)I->E;
+    m.lsum = (const T *)I->lsum;
+    m.q_out = (T *)I->q[fb];
+    m.R_out = (T *)I->R;
+    m.eps_out = (T *)I->eps;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      if constexpr (sizeof(T) == 4) {
+        m.pe[i] = I->pf.eps[i];
+        m.ps[i] = I->pf.sig[i];
+      } else {
+        m.pe[i] = I->pd.eps[i];
+        m.ps[i] = I->pd.sig[i];
+      }
+    }
+  }
   return m;
 }
 
@@ -872,14 +897,14 @@ __device__ __forceinline__ void p2_load(const P2Meta<T> &m, const int4 t, P2Regs
   auto src = gbl(m.src);
   // a 64-lane wave covers one row of the tile: the row index is uniform
   const int tx = threadIdx.x & 63, ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int gx = wrapx(((t.y - IT + tx) % nx + nx) % nx, nx);
+  const int gx = wrapn(t.y - IT + tx, nx, nx >= P2EW);
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     const int r = ty + (P2NT / 64) * k;  // extended row of this thread's k-th node
     int y = t.z - IT + r;
     bool in = true;
     if (m.walls) in = (y >= 0 && y < ny);
-    else y = ((y % ny) + ny) % ny;
+    else y = wrapn(y, ny, ny >= 16 * RPT);
     s.gy[k] = y;
     s.inside[k] = in;
     if (in) {
@@ -897,6 +922,121 @@ __device__ __forceinline__ void p2_load(const P2Meta<T> &m, const int4 t, P2Regs
   }
 }
 
+// Interior node of a tile (the nodes a launch writes) for this thread's k-th
+// extended row: its node index in n.
+template <typename T, int RPT, int IT>
+__device__ __forceinline__ bool p2_interior(const P2Meta<T> &m, const int4 t, const P2Regs<T, RPT> &s, int k,
+                                            int tx, int ty, int gx, int &n) {
+  constexpr int H2 = P2Shape<RPT, IT>::H, W2 = P2Shape<RPT, IT>::W;
+  const int r = ty + (P2NT / 64) * k;
+  if (r < IT || r >= IT + H2 || tx < IT || tx >= IT + W2 || !s.inside[k]) return false;
+  if (t.y + tx - IT >= m.nx || t.z + r - IT >= m.ny) return false;
+  n = s.gy[k] * m.nx + gx;
+  return true;
+}
+
+// a2 + a3 folded into the first potential launch of a step: the charge q,
+// the Ohmic source R and the permittivity eps of k_pre, formed on the tile
+// instead of in a launch of their own.  The permittivity and conductivity
+// (Eqs. 29-30) of the extended tile and of a one-node ring around it (the
+// reach of the Eq. 33 stencil) are formed once per node into LDS (the
+// buffer the streaming uses afterwards); every extended node then takes its
+// Eq. 33 gradients from there and forms q and R with the previous step's
+// field, in k_pre's arithmetic; the interior stores q, R and eps for the
+// later kernels of the step.
+template <typename T, int RPT, int IT>
+__device__ __forceinline__ void p2_load_pre(const P2Meta<T> &m, const int4 t, P2Regs<T, RPT> &s, T *buf) {
+  constexpr int ER = P2Shape<RPT, IT>::ER, SW = P2EW + 2, SN = SW * (ER + 2), SP = (SN + P2NT - 1) / P2NT;
+  static_assert(2 * SN <= (Q - 1) * P2EW * ER, "the ring fits the streaming buffer");
+  const int nx = m.nx, ny = m.ny, N = m.N;
+  auto src = gbl(m.src);
+  auto phi = gbl(m.phi);
+  const int tx = threadIdx.x & 63, ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int gx = wrapn(t.y - IT + tx, nx, nx >= P2EW);
+  // the ring's order parameters first (needed first), then this thread's
+  // nodes: every load of the launch in flight at once
+  T pv[SP][3];
+#pragma unroll
+  for (int u = 0; u < SP; ++u) {
+    const int i = (int)threadIdx.x + u * P2NT;
+    if (i < SN) {
+      const int rr = i / SW, cc = i - rr * SW;
+      int y = t.z - IT - 1 + rr;  // mirror ghost rows at walls
+      y = m.walls ? (y < 0 ? 0 : (y >= ny ? ny - 1 : y)) : wrapn(y, ny, ny >= ER + 2);
+      const int n = y * nx + wrapn(t.y - IT - 1 + cc, nx, nx >= SW);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) pv[u][c] = phi[(size_t)c * N + n];
+    }
+  }
+  T e[RPT][2], ls[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int r = ty + (P2NT / 64) * k;
+    int y = t.z - IT + r;
+    bool in = true;
+    if (m.walls) in = (y >= 0 && y < ny);
+    else y = wrapn(y, ny, ny >= 16 * RPT);
+    s.gy[k] = y;
+    s.inside[k] = in;
+    if (in) {
+      const int n = y * nx + gx;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) s.h[k][j] = src[(size_t)j * N + n];
+      e[k][0] = (gbl(m.Eo))[n];
+      e[k][1] = (gbl(m.Eo))[(size_t)N + n];
+      ls[k] = (gbl(m.lsum))[n];
+    } else {
+#pragma unroll
+      for (int j = 0; j < Q; ++j) s.h[k][j] = T(0);
+      e[k][0] = e[k][1] = ls[k] = T(0);
+    }
+  }
+  // eps and sigma of the ring's nodes
+  T *sev = buf, *ssv = buf + SN;
+#pragma unroll
+  for (int u = 0; u < SP; ++u) {
+    const int i = (int)threadIdx.x + u * P2NT;
+    if (i < SN) {
+      sev[i] = m.pe[0] * herm(pv[u][0]) + m.pe[1] * herm(pv[u][1]) + m.pe[2] * herm(pv[u][2]);
+      ssv[i] = m.ps[0] * pv[u][0] + m.ps[1] * pv[u][1] + m.ps[2] * pv[u][2];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    if (!s.inside[k]) {
+      s.eh[k] = T(0);
+      s.qq[k] = T(0);
+      continue;
+    }
+    const int c = (ty + (P2NT / 64) * k + 1) * SW + tx + 1;
+    T ev[Q], sv[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      ev[j] = sev[c + cy(j) * SW + cx(j)];
+      sv[j] = ssv[c + cy(j) * SW + cx(j)];
+    }
+    T ge[2], gs[2], dummy;
+    fdq<D2Q9>(ev, ge, dummy);
+    fdq<D2Q9>(sv, gs, dummy);
+    const T se = sv[0] / ev[0];
+    T gee = ge[0] * e[k][0], gse = gs[0] * e[k][0];
+    gee += ge[1] * e[k][1];
+    gse += gs[1] * e[k][1];
+    const T Rp = se * gee - gse;
+    const T q = (ls[k] + T(0.5) * Rp) / (T(1) + T(0.5) * se);
+    s.eh[k] = ev[0];
+    s.qq[k] = q;
+    int n;
+    if (p2_interior<T, RPT, IT>(m, t, s, k, tx, ty, gx, n)) {
+      (gbl(m.q_out))[n] = q;
+      (gbl(m.R_out))[n] = -se * q + Rp;
+      (gbl(m.eps_out))[n] = ev[0];
+    }
+  }
+  __syncthreads();  // the ring's LDS is the streaming buffer from here on
+}
+
 // The IT sub-iterations of one loaded tile and the store of its interior.
 // Record outputs of the LDS-tiled kernel (recording runs): lev[i], when
 // set, receives the input level of the launch's i-th sub-iteration on the
@@ -908,20 +1048,14 @@ template <typename T, int IT> struct P2Rec {
 template <typename T, int RPT, int IT>
 __device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int write_psi, const P2Rec<T, IT> &rec,
                                        P2Regs<T, RPT> &s, T *buf) {
-  constexpr int ER = P2Shape<RPT, IT>::ER, H2 = P2Shape<RPT, IT>::H, W2 = P2Shape<RPT, IT>::W;
+  constexpr int ER = P2Shape<RPT, IT>::ER;
   const int nx = m.nx, ny = m.ny, N = m.N, walls = m.walls;
   auto dst = gbl(m.dst);
   // a 64-lane wave covers one row of the tile: row tests are uniform branches
   const int tx = threadIdx.x & 63, ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int gx = wrapx(((t.y - IT + tx) % nx + nx) % nx, nx);
+  const int gx = wrapn(t.y - IT + tx, nx, nx >= P2EW);
   // interior node of this tile (the nodes the launch writes)
-  auto interior = [&](int k, int &n) {
-    const int r = ty + (P2NT / 64) * k;
-    if (r < IT || r >= IT + H2 || tx < IT || tx >= IT + W2 || !s.inside[k]) return false;
-    if (t.y + tx - IT >= nx || t.z + r - IT >= ny) return false;
-    n = s.gy[k] * nx + gx;
-    return true;
-  };
+  auto interior = [&](int k, int &n) { return p2_interior<T, RPT, IT>(m, t, s, k, tx, ty, gx, n); };
   // rows next to an electrode pull some values through the wall
   bool wall_row[RPT];
 #pragma unroll
@@ -998,15 +1132,20 @@ __device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int wri
 //   tiles: (instance, x0, y0, -) per block.
 //   fb: the field buffer holding the charge (the step's; 1 at create).
 //   rec: the input levels of the sub-iterations, for recording runs.
-template <typename T, int RPT = 1, int IT = 2>
+//   PRE: the launch also forms the step's charge, source and permittivity
+//   (p2_load_pre; the first launch of a step, k_pre not launched).
+template <typename T, int RPT = 1, int IT = 2, bool PRE = false>
 __global__ __launch_bounds__(P2NT, (sizeof(T) == 8 && RPT == 2) ? 4 : 8) void k_poisson2(const Inst *__restrict__ insts, const int4 *__restrict__ tiles,
                                                  int hpar, int write_psi, int fb, P2Rec<T, IT> rec = P2Rec<T, IT>{}) {
   constexpr int ER = P2Shape<RPT, IT>::ER;
   __shared__ T buf[(Q - 1) * P2EW * ER];  // the moving values; the rest value never leaves its node
   int4 t;
-  const P2Meta<T> m = p2_meta<T>(insts, tiles, blockIdx.x, hpar, fb, t);
+  const P2Meta<T> m = p2_meta<T, PRE>(insts, tiles, blockIdx.x, hpar, fb, t);
   P2Regs<T, RPT> s;
-  p2_load<T, RPT, IT>(m, t, s);
+  if constexpr (PRE)
+    p2_load_pre<T, RPT, IT>(m, t, s, buf);
+  else
+    p2_load<T, RPT, IT>(m, t, s);
   p2_run<T, RPT, IT>(m, t, write_psi, rec, s, buf);
 }
 

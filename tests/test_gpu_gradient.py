@@ -154,16 +154,29 @@ def test_reverse_fp32_in_tuned_configurations(config, K):
     assert b.adjoint(STEPS, st, 16) == g32
 
 
-def test_record_matches_step_and_is_reused():
+@pytest.mark.parametrize("config,K", [(0, 2), (8, 4), (12, 6)])
+def test_record_matches_step_and_is_reused(config, K):
     """record() advances the handle exactly like step(); the adjoint over
-    that recording equals the adjoint that records its own run."""
-    print("case record", flush=True)
-    cfg, init = small_case()
+    that recording equals the adjoint that records its own run.  With tall
+    tiles and K = 4 or 6 the step forms the charge inside its first potential
+    launch, the recording in a launch of its own: the same bits."""
+    print("case record", config, K, flush=True)
+    cfg, init = inputs.field_compound_drop(48, r_shell=12.0, r_core=7.0, ca_e=0.4, init_iters=100,
+                                           init_tol=0.0, sub=(K, K, 0.0))
     seed = {k: torch.from_numpy(v) for k, v in seeds((cfg["ny"], cfg["nx"]), ["phi2"], seed=6).items()}
     a = binding.Sim(cfg, init, precision="fp32")
+    a.set_tuning(config)
     a.record(STEPS, 16)
     b = binding.Sim(cfg, init, precision="fp32")
-    b.step(STEPS)
+    b.set_tuning(config)
+    if config & binding.TUNE_TALL_TILES:
+        b.profile_begin()
+        b.step(2)
+        prof = b.profile_end()
+        assert prof["pre"][1] == 0 and prof["poisson2_pre"][1] == 2, prof
+        b.step(STEPS - 2)
+    else:
+        b.step(STEPS)
     for fam in "fglh":
         assert torch.equal(a.populations(fam), b.populations(fam)), fam
     assert a.adjoint(STEPS, seed, 16) == b.adjoint(STEPS, seed, 16)
