@@ -122,13 +122,13 @@ def run_gpu(p, init, precision, steps, warmup, profile_steps, tune_steps=0, conf
     sim = binding.Sim(p, init, precision=precision)
     torch.cuda.synchronize()
     log("%s create (cold start) %.2fs" % (precision, time.time() - t0))
-    sim.step(warmup)
-    torch.cuda.synchronize()
     tune = None
     if config >= 0:  # a fixed launch configuration (profiling the tuned one without the tuner's launches)
         sim.set_tuning(config)
         tune = {"config": config, "cached": False, "fixed": True}
-    elif tune_steps > 0:
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    if config < 0 and tune_steps > 0:
         tune = sim.autotune(steps=tune_steps)
         log("%s autotune: config %d, ms/step per config %s" % (precision, tune["config"],
                                                                ["%.4f" % v for v in tune["ms_per_step"]]))
