@@ -986,7 +986,10 @@ void step_record(lbm_ehd_s *W, char *slot) {
         <<<dim3(W->plan.total_blocks4 * (4 / MW)), block, 0, W->stream>>>(W->d_insts, W->d_b2i4, pc, rc);
   else
     k_moments<D2Q9, T, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, pc, rc);
-  k_pre<D2Q9, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, pc, rc);
+  // the charge step rides on the first four-sub-iteration launch where the
+  // plain step folds it (same arithmetic, same record)
+  const bool fold = sizeof(T) <= 8 && W->tall() && K >= 4 && !(K & 1);
+  if (!fold) k_pre<D2Q9, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, pc, rc);
   int L = 0, k = 1;
   if (K & 1) {
     k_poisson<D2Q9, T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, 1, K, 0, 0, pc, rec_level<T>(slot, N, 0));
@@ -997,10 +1000,20 @@ void step_record(lbm_ehd_s *W, char *slot) {
   if constexpr (sizeof(T) <= 8) {
     if (W->tall()) {
       // four sub-iterations per launch while four remain, then tall pairs
-      for (; k + 3 <= K; k += 4, ++L)
-        k_poisson2<T, 2, 4><<<dim3(W->plan.total_tiles4), block2, 0, W->stream>>>(
-            W->d_insts, W->table(2), L & 1, k + 3 == K ? 1 : 0, pc,
-            P2Rec<T, 4>{{lev(k - 1), lev(k), lev(k + 1), lev(k + 2)}});
+      for (; k + 3 <= K; k += 4, ++L) {
+        P2Rec<T, 4> pr{{lev(k - 1), lev(k), lev(k + 1), lev(k + 2)}};
+        if (fold && k == 1) {
+          pr.q = rc.q;
+          pr.R = rc.R;
+          pr.eps = rc.eps;
+          pr.Eo = rc.Eo;
+          k_poisson2<T, 2, 4, true><<<dim3(W->plan.total_tiles4), block2, 0, W->stream>>>(
+              W->d_insts, W->table(2), L & 1, k + 3 == K ? 1 : 0, pc, pr);
+        } else {
+          k_poisson2<T, 2, 4><<<dim3(W->plan.total_tiles4), block2, 0, W->stream>>>(
+              W->d_insts, W->table(2), L & 1, k + 3 == K ? 1 : 0, pc, pr);
+        }
+      }
       for (; k + 1 <= K; k += 2, ++L)
         k_poisson2<T, 2><<<dim3(W->plan.total_tiles2t), block2, 0, W->stream>>>(
             W->d_insts, W->table(1), L & 1, k + 1 == K ? 1 : 0, pc, P2Rec<T, 2>{{lev(k - 1), lev(k)}});

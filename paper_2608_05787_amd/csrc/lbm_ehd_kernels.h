@@ -922,6 +922,16 @@ __device__ __forceinline__ void p2_load(const P2Meta<T> &m, const int4 t, P2Regs
   }
 }
 
+// Record outputs of the LDS-tiled kernel (recording runs): lev[i], when
+// set, receives the input level of the launch's i-th sub-iteration on the
+// tile's interior.
+//   q, R, eps, Eo: when set, the charge step of a PRE launch records what
+//   k_pre records (its charge, source, permittivity and the field it read).
+template <typename T, int IT> struct P2Rec {
+  T *lev[IT];
+  T *q = nullptr, *R = nullptr, *eps = nullptr, *Eo = nullptr;
+};
+
 // Interior node of a tile (the nodes a launch writes) for this thread's k-th
 // extended row: its node index in n.
 template <typename T, int RPT, int IT>
@@ -945,7 +955,8 @@ __device__ __forceinline__ bool p2_interior(const P2Meta<T> &m, const int4 t, co
 // field, in k_pre's arithmetic; the interior stores q, R and eps for the
 // later kernels of the step.
 template <typename T, int RPT, int IT>
-__device__ __forceinline__ void p2_load_pre(const P2Meta<T> &m, const int4 t, P2Regs<T, RPT> &s, T *buf) {
+__device__ __forceinline__ void p2_load_pre(const P2Meta<T> &m, const int4 t, const P2Rec<T, IT> &rec,
+                                            P2Regs<T, RPT> &s, T *buf) {
   constexpr int ER = P2Shape<RPT, IT>::ER, SW = P2EW + 2, SN = SW * (ER + 2), SP = (SN + P2NT - 1) / P2NT;
   static_assert(2 * SN <= (Q - 1) * P2EW * ER, "the ring fits the streaming buffer");
   const int nx = m.nx, ny = m.ny, N = m.N;
@@ -1032,18 +1043,19 @@ __device__ __forceinline__ void p2_load_pre(const P2Meta<T> &m, const int4 t, P2
       (gbl(m.q_out))[n] = q;
       (gbl(m.R_out))[n] = -se * q + Rp;
       (gbl(m.eps_out))[n] = ev[0];
+      if (rec.q) {
+        rec.q[n] = q;
+        rec.R[n] = -se * q + Rp;
+        rec.eps[n] = ev[0];
+        rec.Eo[n] = e[k][0];
+        rec.Eo[(size_t)N + n] = e[k][1];
+      }
     }
   }
   __syncthreads();  // the ring's LDS is the streaming buffer from here on
 }
 
 // The IT sub-iterations of one loaded tile and the store of its interior.
-// Record outputs of the LDS-tiled kernel (recording runs): lev[i], when
-// set, receives the input level of the launch's i-th sub-iteration on the
-// tile's interior.
-template <typename T, int IT> struct P2Rec {
-  T *lev[IT];
-};
 
 template <typename T, int RPT, int IT>
 __device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int write_psi, const P2Rec<T, IT> &rec,
@@ -1143,7 +1155,7 @@ __global__ __launch_bounds__(P2NT, (sizeof(T) == 8 && RPT == 2) ? 4 : 8) void k_
   const P2Meta<T> m = p2_meta<T, PRE>(insts, tiles, blockIdx.x, hpar, fb, t);
   P2Regs<T, RPT> s;
   if constexpr (PRE)
-    p2_load_pre<T, RPT, IT>(m, t, s, buf);
+    p2_load_pre<T, RPT, IT>(m, t, rec, s, buf);
   else
     p2_load<T, RPT, IT>(m, t, s);
   p2_run<T, RPT, IT>(m, t, write_psi, rec, s, buf);

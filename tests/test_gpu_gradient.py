@@ -158,8 +158,8 @@ def test_reverse_fp32_in_tuned_configurations(config, K):
 def test_record_matches_step_and_is_reused(config, K):
     """record() advances the handle exactly like step(); the adjoint over
     that recording equals the adjoint that records its own run.  With tall
-    tiles and K = 4 or 6 the step forms the charge inside its first potential
-    launch, the recording in a launch of its own: the same bits."""
+    tiles and K = 4 or 6 the step and the recording form the charge inside
+    their first potential launch; with K = 2 in a launch of its own."""
     print("case record", config, K, flush=True)
     cfg, init = inputs.field_compound_drop(48, r_shell=12.0, r_core=7.0, ca_e=0.4, init_iters=100,
                                            init_tol=0.0, sub=(K, K, 0.0))
