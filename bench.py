@@ -211,10 +211,12 @@ def batch_bench(n_inst, steps, sub, init_iters, graph_len=10, eager_steps=1000):
     and conductivity ratios, half sheared): aggregate MLUPS of one batched
     handle replaying a captured graph of `graph_len` steps for `steps` steps,
     of one handle per instance stepped in turn for the same steps (sequential
-    per-instance launches), and of the batched handle launched kernel by
-    kernel (`eager_steps`), all FP32 on one side stream.  After the graph and
-    sequential runs every instance of the batch must equal its separate run
-    bitwise (all population families)."""
+    per-instance launches), of the grid-resident step (lbm_ehd_step_persistent)
+    over the same batch and steps, and of the batched handle launched kernel
+    by kernel (`eager_steps`), all FP32 on one side stream.  After the graph
+    and sequential runs every instance of the batch must equal its separate
+    run bitwise (all population families), and the persistent run the graph
+    run."""
     import torch
     from paper_2608_05787_amd import binding, inputs
     cases = inputs.batch_sweep(n_inst=n_inst, sub=(sub, sub, 0.0), init_iters=init_iters)
@@ -258,6 +260,17 @@ def batch_bench(n_inst, steps, sub, init_iters, graph_len=10, eager_steps=1000):
                 for i, sm in enumerate(sims) for fam in "fglh")
     d_batch = [batch.diagnostics(i) for i in range(n_inst)]
     del sims
+    torch.cuda.empty_cache()
+    # the grid-resident step (cooperative launches of up to 256 steps each)
+    # over the same batch and steps, against the graph-replayed handle
+    pers = binding.Sim(cfgs, inits, precision="fp32", stream=stream)
+    pers.set_tuning(tune["config"])
+    ms_pers = timed(pers.step_persistent, steps)
+    log("persistent: %d steps %.1f ms" % (steps, ms_pers))
+    pers_equal = all(torch.equal(batch.populations(fam, inst=i), pers.populations(fam, inst=i))
+                     for i in range(n_inst) for fam in "fglh")
+    del pers
+    torch.cuda.empty_cache()
     batch.graph(0)
     ms_eager = timed(batch.step, eager_steps)
     del batch
@@ -266,6 +279,7 @@ def batch_bench(n_inst, steps, sub, init_iters, graph_len=10, eager_steps=1000):
             "graph_steps": graph_len, "mlups_graph": mlups(ms_graph, steps),
             "mlups_batched_eager": mlups(ms_eager, eager_steps), "eager_steps": eager_steps,
             "mlups_sequential": mlups(ms_seq, steps), "speedup_graph_vs_sequential": round(ms_seq / ms_graph, 2),
+            "mlups_persistent": mlups(ms_pers, steps), "persistent_equals_graph_bitwise": pers_equal,
             "instances_equal_separate_runs_bitwise": equal,
             "max_sum_dev_worst": max(d["max_sum_dev"] for d in d_batch),
             "nonfinite_total": sum(d["nonfinite"] for d in d_batch),
@@ -445,6 +459,8 @@ def main():
                     help="run only the D3Q15 leg (for profiling) and print its JSON object")
     ap.add_argument("--gradient-only", action="store_true",
                     help="run only the gradient leg (for profiling) and print its JSON object")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the parameter-sweep leg and print its JSON object")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -465,6 +481,11 @@ def main():
 
     if args.gradient_only:
         print(json.dumps({"gradient": gradient_bench(512, args.grad_steps, args.sub, 2000, args.grad_every)}),
+              flush=True)
+        return
+
+    if args.batch_only:
+        print(json.dumps({"batch_sweep": batch_bench(args.batch_instances, args.batch_steps, args.sub, 1000)}),
               flush=True)
         return
 

@@ -227,6 +227,23 @@ int lbm_ehd_step(lbm_ehd_t h, int64_t n);
  * stream; enqueues nothing. */
 int lbm_ehd_graph(lbm_ehd_t h, int32_t steps_per_graph);
 
+/* n >= 0 coupled time steps of every instance (the scheme of Sec. 3, as
+ * lbm_ehd_step) run by one grid-resident kernel per block of up to 256
+ * steps: a cooperative launch of one 1024-thread block per CU takes every
+ * stage of a step (moments and properties, the charge step with the
+ * potential sub-iterations of Eqs. 42-45 four at a time on LDS tiles, field
+ * and chemical potentials, collide-and-stream) over the node and tile lists
+ * of all instances, with a grid-wide barrier between stages.  The state
+ * after n steps is bitwise that of lbm_ehd_step in a tall-tile launch
+ * configuration (LBM_TUNE_TALL_TILES set, LBM_TUNE_SINGLE_POTENTIAL
+ * clear); in the others it agrees to rounding.  Needs D2Q9, FP32 or FP16S
+ * storage, the leaky-dielectric charge model and a fixed sub-iteration
+ * count that is a multiple of 4 (LBM_EHD_EUNSUPPORTED otherwise); not while
+ * profiling (LBM_EHD_ESTATE).  Synchronises after every launch.  Every
+ * barrier wait is bounded: should one run out (about 2 s), the call returns
+ * LBM_EHD_EHIP and the state is undefined. */
+int lbm_ehd_step_persistent(lbm_ehd_t h, int64_t n);
+
 /* Write the selected fields of instance `inst` into caller device memory
  * dev_dst as consecutive planes [popcount(mask)][ny][nx] in ascending bit
  * order, converted to dtype (LBM_DTYPE_F32 or LBM_DTYPE_F64; for a tangent

@@ -17,6 +17,7 @@
 #include "lbm_ehd.h"
 #include "lbm_ehd_kernels.h"
 #include "lbm_ehd_adjoint.h"
+#include "lbm_ehd_persistent.h"
 
 using namespace lbm;
 
@@ -100,7 +101,7 @@ constexpr int tile_cols(int s) { return s == 2 ? P2Shape<2, 4>::W : P2Shape<1>::
 constexpr int tile_rows(int s) { return s == 0 ? P2Shape<1>::H : s == 1 ? P2Shape<2>::H : P2Shape<2, 4>::H; }
 
 struct Plan {
-  size_t desc_off, b2i_off, b2i4_off, t2_off, state_off, total;
+  size_t desc_off, b2i_off, b2i4_off, t2_off, bar_off, state_off, total;
   int total_blocks4;               // blocks of the four-nodes-per-thread moments kernel
   int total_blocks, total_tiles2;  // tiles of the default shape (64 x 16, two sub-iterations)
   int total_tiles2t;               // tiles of the tall (64 x 32) shape
@@ -134,6 +135,10 @@ Plan make_plan(const lbm_ehd_params *p, int n) {
   // XCD-grouped order, then the linear order
   P.t2_off = off;
   off = align_up(off + 2 * (size_t)(P.total_tiles2 + P.total_tiles2t + P.total_tiles4) * sizeof(int4));
+  // persistent step: barrier words (arrivals, failure), then its launch
+  // arguments
+  P.bar_off = off;
+  off = align_up(off + 2 * sizeof(unsigned) + ALIGN + sizeof(PersistArgs));
   P.state_off = off;
   for (int i = 0; i < n; ++i) {
     P.lay.push_back(layout_one(p[i], off));
@@ -1233,6 +1238,53 @@ int reverse_sweep(lbm_ehd_s *H, lbm_ehd_s *W, char *work, const AdjLayout &L, in
 
 }  // namespace
 
+namespace {
+constexpr int PERSIST_CHUNK = 256;  // steps per cooperative launch
+
+// n steps as cooperative launches of PERSIST_CHUNK steps or fewer, each
+// checked for a barrier wait that ran out.
+template <typename S>
+int do_step_persistent(lbm_ehd_s *H, int64_t n) {
+  int per_cu = 0, ncu = 0;
+  HIPC(H, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persistent<S>, P2NT, 0));
+  HIPC(H, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, H->device));
+  if (per_cu < 1 || ncu < 1) return H->fail(LBM_EHD_EUNSUPPORTED, "persistent step: the kernel does not fit a CU");
+  const int grid = per_cu * ncu;
+  unsigned *bar = (unsigned *)(H->ws + H->plan.bar_off);
+  int *fail = (int *)(bar + 1);
+  PersistArgs *d_args = (PersistArgs *)(H->ws + H->plan.bar_off + ALIGN);
+  PersistArgs a;
+  a.b2i4 = H->d_b2i4;
+  a.tiles = H->table(2);
+  a.b2i = H->d_b2i;
+  a.bar = bar;
+  a.fail = fail;
+  a.n_ent4 = H->plan.total_blocks4;
+  a.n_tiles = H->plan.total_tiles4;
+  a.n_blk = H->plan.total_blocks;
+  a.K = H->sub_max;
+  a.spin_max = 1 << 21;  // ~1 us per poll: a stage may take about 2 s before the launch gives up
+  const Inst *insts = H->d_insts;
+  while (n > 0) {
+    const int chunk = (int)(n < PERSIST_CHUNK ? n : PERSIST_CHUNK);
+    a.step0 = H->steps;
+    a.n_steps = chunk;
+    k_persist_begin<<<1, 64, 0, H->stream>>>(a, d_args);
+    HIPC(H, hipGetLastError());
+    const PersistArgs *pa = d_args;
+    void *args[] = {(void *)&insts, (void *)&pa};
+    HIPC(H, hipLaunchCooperativeKernel((const void *)k_persistent<S>, dim3(grid), dim3(P2NT), args, 0, H->stream));
+    int f = 0;
+    HIPC(H, hipMemcpyAsync(&f, fail, sizeof(int), hipMemcpyDeviceToHost, H->stream));
+    HIPC(H, hipStreamSynchronize(H->stream));
+    if (f) return H->fail(LBM_EHD_EHIP, "persistent step: a grid barrier wait ran out (state undefined)");
+    H->steps += chunk;
+    n -= chunk;
+  }
+  return LBM_EHD_OK;
+}
+}  // namespace
+
 extern "C" {
 
 int lbm_ehd_create(const lbm_ehd_params *params, int32_t n_inst, const lbm_ehd_init *init,
@@ -1269,6 +1321,19 @@ int lbm_ehd_step(lbm_ehd_t H, int64_t n) {
     n -= k;
   }
   return LBM_EHD_OK;
+}
+
+int lbm_ehd_step_persistent(lbm_ehd_t H, int64_t n) {
+  if (!H || n < 0) return LBM_EHD_EINVAL;
+  if (H->lattice != LBM_LATTICE_D2Q9 || (H->prec != LBM_PREC_FP32 && H->prec != LBM_PREC_FP16S))
+    return H->fail(LBM_EHD_EUNSUPPORTED, "persistent step: D2Q9 with FP32 or FP16S storage only");
+  if (H->adaptive || H->sub_max < 4 || H->sub_max % 4)
+    return H->fail(LBM_EHD_EUNSUPPORTED, "persistent step: needs a fixed sub-iteration count, a multiple of 4");
+  if (!H->vec_moments)
+    return H->fail(LBM_EHD_EUNSUPPORTED, "persistent step: leaky-dielectric charge model only");
+  if (H->prof) return H->fail(LBM_EHD_ESTATE, "persistent step: not while profiling");
+  if (n == 0) return LBM_EHD_OK;
+  return H->prec == LBM_PREC_FP16S ? do_step_persistent<__half>(H, n) : do_step_persistent<float>(H, n);
 }
 
 int lbm_ehd_graph(lbm_ehd_t H, int32_t steps_per_graph) {

@@ -257,15 +257,18 @@ template <typename T> struct Rec {
 // instance).  The host orders it so that the blocks one XCD receives
 // (consecutive block ids go round-robin over the 8 XCDs) cover a contiguous
 // range of rows: stencil neighbours then hit that XCD's own L2.
+//   bid, tid: the table entry and the thread within its NT nodes (a
+//   launched block and its thread, or a persistent block's share of them).
 template <class L = D2Q9>
-__device__ __forceinline__ Node locate(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
-                                       const Inst *&Ip, int &lblk) {
+__device__ __forceinline__ Node locate_at(const Inst *__restrict__ insts, const int2 *__restrict__ b2i, int bid,
+                                          int tid, const Inst *&Ip, int &lblk) {
+  __builtin_assume(tid >= 0 && tid < NT);
   Node nd;
-  const int2 t = b2i[blockIdx.x];
+  const int2 t = b2i[bid];
   nd.inst = t.x;
   lblk = t.y;
   Ip = insts + nd.inst;
-  const int local = t.y * NT + (int)threadIdx.x;
+  const int local = t.y * NT + tid;
   nd.valid = local < Ip->nn;
   nd.n = nd.valid ? local : 0;
   int r = nd.n;
@@ -278,6 +281,11 @@ __device__ __forceinline__ Node locate(const Inst *__restrict__ insts, const int
   nd.y = r / Ip->nx;
   nd.x = r - nd.y * Ip->nx;
   return nd;
+}
+template <class L = D2Q9>
+__device__ __forceinline__ Node locate(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
+                                       const Inst *&Ip, int &lblk) {
+  return locate_at<L>(insts, b2i, (int)blockIdx.x, (int)threadIdx.x, Ip, lblk);
 }
 
 __device__ __forceinline__ int wrapx(int x, int nx) { return x < 0 ? x + nx : (x >= nx ? x - nx : x); }
@@ -527,22 +535,24 @@ template <typename T, int W> struct VecN {
   typedef T v __attribute__((ext_vector_type(W)));
 };
 //   rc: when rc.phi is set, the order parameters also go there (recording runs).
+//   bid, tid: launched block (PER per table entry) and thread (k_moments4
+//   passes its own; the persistent step its blocks' shares).
 template <class L, typename T, typename S, int W = 4>
-__global__ __launch_bounds__(NT) void k_moments4(const Inst *__restrict__ insts, const int2 *__restrict__ b2i4,
-                                                 int pc, Rec<T> rc = Rec<T>{}) {
+__device__ __forceinline__ void moments4_body(const Inst *__restrict__ insts, const int2 *__restrict__ b2i4, int pc,
+                                              const Rec<T> &rc, int bid, int tid) {
   static_assert(W == 4 || W == 2, "four or two nodes per thread");
   constexpr int Q = L::Q, PER = 4 / W;  // launched blocks per table entry
   using V = typename VecN<T, W>::v;
   using GV = const V __attribute__((address_space(1))) *;
   using GVW = V __attribute__((address_space(1))) *;
-  const int2 t = b2i4[blockIdx.x / PER];
-  const int sub = (int)(blockIdx.x % PER);
+  const int2 t = b2i4[bid / PER];
+  const int sub = bid % PER;
   const Inst &I = insts[t.x];
-  if (t.y == 0 && sub == 0 && threadIdx.x == 0) {
+  if (t.y == 0 && sub == 0 && tid == 0) {
     I.ctl->done = 0;
     I.ctl->k_used = 0;
   }
-  const int base = t.y * M4 + sub * (W * NT) + W * (int)threadIdx.x;
+  const int base = t.y * M4 + sub * (W * NT) + W * tid;
   if (base >= I.nn) return;
   const size_t bv = (size_t)base / W, NV = (size_t)I.N / W;
   const int fb = fbuf(I, pc);
@@ -597,6 +607,11 @@ __global__ __launch_bounds__(NT) void k_moments4(const Inst *__restrict__ insts,
 #pragma unroll
   for (int j = 0; j < Q; ++j) b += lv[j];
   ((GVW)I.lsum)[bv] = b;
+}
+template <class L, typename T, typename S, int W = 4>
+__global__ __launch_bounds__(NT) void k_moments4(const Inst *__restrict__ insts, const int2 *__restrict__ b2i4,
+                                                 int pc, Rec<T> rc = Rec<T>{}) {
+  moments4_body<L, T, S, W>(insts, b2i4, pc, rc, (int)blockIdx.x, (int)threadIdx.x);
 }
 
 // a2 + a3: permittivity/conductivity stencils (Eq. 33 on the eps and sigma
@@ -826,12 +841,20 @@ template <typename T> struct P2Meta {
   T pe[3], ps[3];  // phase permittivities and conductivities (Eqs. 29-30)
 };
 
-template <typename T, bool PRE = false>
+//   COH: read the control word with a coherent load (the persistent step,
+//   where an earlier stage of the same launch rewrote it) instead of
+//   through the scalar cache.
+template <typename T, bool PRE = false, bool COH = false>
 __device__ __forceinline__ P2Meta<T> p2_meta(const Inst *insts, const int4 *tiles, int ti, int hpar, int fb, int4 &t) {
   const cptr<int> tp = cst((const int *)tiles) + 4 * (size_t)ti;
   t = make_int4(tp[0], tp[1], tp[2], 0);
   const cptr<Inst> I = cst(insts) + t.x;
-  const int hc = cst(I->ctl)->hcur ^ hpar;
+  int hcur;
+  if constexpr (COH)
+    hcur = __hip_atomic_load(&I->ctl->hcur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    hcur = cst(I->ctl)->hcur;
+  const int hc = hcur ^ hpar;
   P2Meta<T> m;
   m.src = (const T *)I->h[hc];
   m.dst = (T *)I->h[hc ^ 1];
@@ -1146,19 +1169,26 @@ __device__ __forceinline__ void p2_run(const P2Meta<T> &m, const int4 t, int wri
 //   rec: the input levels of the sub-iterations, for recording runs.
 //   PRE: the launch also forms the step's charge, source and permittivity
 //   (p2_load_pre; the first launch of a step, k_pre not launched).
-template <typename T, int RPT = 1, int IT = 2, bool PRE = false>
-__global__ __launch_bounds__(P2NT, (sizeof(T) == 8 && RPT == 2) ? 4 : 8) void k_poisson2(const Inst *__restrict__ insts, const int4 *__restrict__ tiles,
-                                                 int hpar, int write_psi, int fb, P2Rec<T, IT> rec = P2Rec<T, IT>{}) {
-  constexpr int ER = P2Shape<RPT, IT>::ER;
-  __shared__ T buf[(Q - 1) * P2EW * ER];  // the moving values; the rest value never leaves its node
+//   ti: the tile (the launched block, or a persistent block's current one);
+//   buf: the block's LDS of (Q - 1) P2EW ER values.
+template <typename T, int RPT, int IT, bool PRE, bool COH = false>
+__device__ __forceinline__ void p2_body(const Inst *__restrict__ insts, const int4 *__restrict__ tiles, int ti,
+                                        int hpar, int write_psi, int fb, const P2Rec<T, IT> &rec, T *buf) {
   int4 t;
-  const P2Meta<T> m = p2_meta<T, PRE>(insts, tiles, blockIdx.x, hpar, fb, t);
+  const P2Meta<T> m = p2_meta<T, PRE, COH>(insts, tiles, ti, hpar, fb, t);
   P2Regs<T, RPT> s;
   if constexpr (PRE)
     p2_load_pre<T, RPT, IT>(m, t, rec, s, buf);
   else
     p2_load<T, RPT, IT>(m, t, s);
   p2_run<T, RPT, IT>(m, t, write_psi, rec, s, buf);
+}
+template <typename T, int RPT = 1, int IT = 2, bool PRE = false>
+__global__ __launch_bounds__(P2NT, (sizeof(T) == 8 && RPT == 2) ? 4 : 8) void k_poisson2(const Inst *__restrict__ insts, const int4 *__restrict__ tiles,
+                                                 int hpar, int write_psi, int fb, P2Rec<T, IT> rec = P2Rec<T, IT>{}) {
+  constexpr int ER = P2Shape<RPT, IT>::ER;
+  __shared__ T buf[(Q - 1) * P2EW * ER];  // the moving values; the rest value never leaves its node
+  p2_body<T, RPT, IT, PRE>(insts, tiles, (int)blockIdx.x, hpar, write_psi, fb, rec, buf);
 }
 
 // Adaptive potential loop control, one block per instance, after iteration
@@ -1193,22 +1223,29 @@ __global__ __launch_bounds__(NT) void k_reduce_poisson(const Inst *__restrict__ 
 //   parity of the potential launches; adaptive: 0, the control pass already
 //   flipped it).
 //   pc: the step's field buffer (1 at create).
-template <class L, typename T>
-__global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
-                                           int hofs, int pc, Rec<T> rc = Rec<T>{}) {
+//   bid, tid: node block and thread (see locate_at); red receives this
+//   thread's residual terms, Ip and lblk the block's instance.  COH: the
+//   control word through a coherent load (see p2_meta).
+template <class L, typename T, bool COH = false>
+__device__ __forceinline__ void mu_body(const Inst *__restrict__ insts, const int2 *__restrict__ b2i, int hofs, int pc,
+                                        const Rec<T> &rc, int bid, int tid, double (&red)[2], const Inst *&Ip,
+                                        int &lblk) {
   constexpr int Q = L::Q, D = L::D;
-  const Inst *Ip;
-  int lblk;
-  const Node nd = locate<L>(insts, b2i, Ip, lblk);
+  const Node nd = locate_at<L>(insts, b2i, bid, tid, Ip, lblk);
   const Inst &I = *Ip;
   // (the control word through a plain pointer: a scalar read here staggers
   // less and measured slower)
   const Ctl *ctl = I.ctl;
   const Phys<T> &P = phys<T>(I);
-  double red[2] = {0.0, 0.0};
+  red[0] = red[1] = 0.0;
   if (nd.valid) {
     const int N = I.N, n = nd.n;
-    auto h = gbl((const T *)I.h[ctl->hcur ^ hofs]);
+    int hcur;
+    if constexpr (COH)
+      hcur = __hip_atomic_load(&ctl->hcur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+      hcur = ctl->hcur;
+    auto h = gbl((const T *)I.h[hcur ^ hofs]);
     T s1 = 0, m[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) m[d] = 0;
@@ -1263,10 +1300,18 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
       if (rc.mu) rc.mu[(size_t)i * N + n] = bulk - grad - elec;
     }
   }
+}
+template <class L, typename T>
+__global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
+                                           int hofs, int pc, Rec<T> rc = Rec<T>{}) {
+  double red[2];
+  const Inst *Ip;
+  int lblk;
+  mu_body<L, T>(insts, b2i, hofs, pc, rc, (int)blockIdx.x, (int)threadIdx.x, red, Ip, lblk);
   block_sum<2>(red);
   if (threadIdx.x == 0) {
-    I.part_mu[(size_t)lblk * 2] = red[0];
-    I.part_mu[(size_t)lblk * 2 + 1] = red[1];
+    Ip->part_mu[(size_t)lblk * 2] = red[0];
+    Ip->part_mu[(size_t)lblk * 2 + 1] = red[1];
   }
 }
 
@@ -1281,23 +1326,30 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
 //   EARLY: load schedule (see below; a launch-configuration choice, both
 //   give bitwise the same results).  The per-family D2Q9 FP32/FP16S form is
 //   held to 128 VGPRs (4 waves per SIMD), which it fits without spilling.
-template <class L, typename T, typename S, bool EARLY = (sizeof(T) <= 4)>
-__global__ __launch_bounds__(NT, (EARLY || sizeof(T) > 4 || L::Q > 9) ? 1 : 4) void k_collide(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
-                                                int pc, int write_macro, int fixedK, int hflip,
-                                                Rec<T> rc = Rec<T>{}) {
+//   bid, tid: node block and thread (see locate_at).
+template <class L, typename T, typename S, bool EARLY>
+__device__ __forceinline__ void collide_body(const Inst *__restrict__ insts, const int2 *__restrict__ b2i, int pc,
+                                             int write_macro, int fixedK, int hflip, const Rec<T> &rc, int bid,
+                                             int tid) {
   constexpr int Q = L::Q, D = L::D;
   const Inst *Ip;
   int lblk;
-  const Node nd = locate<L>(insts, b2i, Ip, lblk);
+  const Node nd = locate_at<L>(insts, b2i, bid, tid, Ip, lblk);
   const Inst &I = *Ip;
-  if (lblk == 0 && threadIdx.x == 0) {
+  if (lblk == 0 && tid == 0) {
+    // device-scope atomics: in the persistent step an earlier stage of the
+    // same launch, on another CU, wrote these words
     Ctl *ctl = I.ctl;
+    int ku;
     if (fixedK > 0) {
-      ctl->hcur ^= hflip;
-      ctl->k_used = fixedK;
+      __hip_atomic_fetch_xor(&ctl->hcur, hflip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->k_used, fixedK, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ku = fixedK;
+    } else {
+      ku = __hip_atomic_load(&ctl->k_used, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    ctl->k_total += ctl->k_used;
-    ctl->steps += 1;
+    __hip_atomic_fetch_add(&ctl->k_total, (long long)ku, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&ctl->steps, 1LL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (nd.valid) {
     const Phys<T> &P = phys<T>(I);
@@ -1565,6 +1617,12 @@ __global__ __launch_bounds__(NT, (EARLY || sizeof(T) > 4 || L::Q > 9) ? 1 : 4) v
                     T(SC_L), false);
     }
   }
+}
+template <class L, typename T, typename S, bool EARLY = (sizeof(T) <= 4)>
+__global__ __launch_bounds__(NT, (EARLY || sizeof(T) > 4 || L::Q > 9) ? 1 : 4) void k_collide(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
+                                                int pc, int write_macro, int fixedK, int hflip,
+                                                Rec<T> rc = Rec<T>{}) {
+  collide_body<L, T, S, EARLY>(insts, b2i, pc, write_macro, fixedK, hflip, rc, (int)blockIdx.x, (int)threadIdx.x);
 }
 
 // ------------------------------------------------------------ create-time
