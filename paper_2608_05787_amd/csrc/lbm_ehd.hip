@@ -135,10 +135,9 @@ Plan make_plan(const lbm_ehd_params *p, int n) {
   // XCD-grouped order, then the linear order
   P.t2_off = off;
   off = align_up(off + 2 * (size_t)(P.total_tiles2 + P.total_tiles2t + P.total_tiles4) * sizeof(int4));
-  // persistent step: barrier words (arrivals, failure), then its launch
-  // arguments
+  // persistent step: barrier words, then its launch arguments
   P.bar_off = off;
-  off = align_up(off + 2 * sizeof(unsigned) + ALIGN + sizeof(PersistArgs));
+  off = align_up(off + align_up(PS_WORDS * sizeof(unsigned)) + sizeof(PersistArgs));
   P.state_off = off;
   for (int i = 0; i < n; ++i) {
     P.lay.push_back(layout_one(p[i], off));
@@ -1251,14 +1250,13 @@ int do_step_persistent(lbm_ehd_s *H, int64_t n) {
   if (per_cu < 1 || ncu < 1) return H->fail(LBM_EHD_EUNSUPPORTED, "persistent step: the kernel does not fit a CU");
   const int grid = per_cu * ncu;
   unsigned *bar = (unsigned *)(H->ws + H->plan.bar_off);
-  int *fail = (int *)(bar + 1);
-  PersistArgs *d_args = (PersistArgs *)(H->ws + H->plan.bar_off + ALIGN);
+  int *fail = (int *)(bar + PS_FAIL);
+  PersistArgs *d_args = (PersistArgs *)(H->ws + H->plan.bar_off + align_up(PS_WORDS * sizeof(unsigned)));
   PersistArgs a;
   a.b2i4 = H->d_b2i4;
   a.tiles = H->table(2);
   a.b2i = H->d_b2i;
   a.bar = bar;
-  a.fail = fail;
   a.n_ent4 = H->plan.total_blocks4;
   a.n_tiles = H->plan.total_tiles4;
   a.n_blk = H->plan.total_blocks;

@@ -23,8 +23,7 @@ struct PersistArgs {
   const int2 *b2i4;   // moments table (four nodes per thread), n_ent4 entries
   const int4 *tiles;  // tall four-sub-iteration tiles, n_tiles entries
   const int2 *b2i;    // node blocks, n_blk entries
-  unsigned *bar;      // barrier arrivals since the launch (zero at launch)
-  int *fail;          // raised when a barrier wait ran out (zero at launch)
+  unsigned *bar;      // PS_WORDS barrier words (zero at launch; see grid_barrier)
   long long step0;    // steps taken before the launch (field buffer parity)
   int n_ent4, n_tiles, n_blk;
   int n_steps;        // steps of this launch
@@ -34,26 +33,40 @@ struct PersistArgs {
 
 constexpr int PS_SUB = P2NT / NT;  // node blocks one persistent block runs at once
 
-// Grid-wide barrier: every block arrives once per barrier, so the
-// arrivals counter reaches (passed + 1) x gridDim.x when the last block of
-// this one arrives.  Thread 0 publishes the block's writes (device-scope
-// release after the block barrier), arrives, polls, and takes the
-// device-scope acquire that drops this CU's and XCD's stale cache lines
-// before the block goes on.  Returns false (uniformly over the block) once
-// the wait ran out or another block gave up.
+// Barrier words: eight group counters (blocks take group blockIdx.x % 8,
+// the order in which the dispatcher deals consecutive blocks to the XCDs),
+// each on a 256-byte line of its own, then the counter of completed groups,
+// then the failure word.
+constexpr int PS_GROUPS = 8, PS_LINE = 64;  // groups; words per counter line
+constexpr int PS_TOP = PS_GROUPS * PS_LINE, PS_FAIL = PS_TOP + PS_LINE, PS_WORDS = PS_FAIL + PS_LINE;
+
+// Grid-wide barrier.  Every block arrives once per barrier, so a group's
+// counter reaches (passed + 1) x (its blocks) when the group's last block
+// arrives; that block then counts the group done, and all blocks wait for
+// (passed + 1) x (groups) on the top counter.  Thread 0 publishes the
+// block's writes (a device-scope release fence after the block barrier:
+// this XCD's L2 written back), arrives and polls with relaxed atomics, and
+// takes one device-scope acquire fence (this CU's and XCD's stale lines
+// dropped) before the block goes on.  Returns false (uniformly over the block)
+// once the wait ran out or another block gave up.
 __device__ __forceinline__ bool grid_barrier(const cptr<PersistArgs> a, unsigned &passed) {
   __shared__ int ok;
   __syncthreads();
   if (threadIdx.x == 0) {
     int good = 1;
     unsigned *bar = a->bar;
-    int *fail = a->fail;
+    int *fail = (int *)(bar + PS_FAIL);
     const int spin_max = a->spin_max;
-    __threadfence();
-    const unsigned target = (passed + 1) * gridDim.x;
-    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned nb = gridDim.x, g = blockIdx.x % PS_GROUPS;
+    const unsigned ng = nb < PS_GROUPS ? nb : PS_GROUPS;  // groups with blocks
+    const unsigned in_g = (nb - g + PS_GROUPS - 1) / PS_GROUPS;  // blocks of group g
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned prev = __hip_atomic_fetch_add(bar + g * PS_LINE, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev + 1 == (passed + 1) * in_g)
+      __hip_atomic_fetch_add(bar + PS_TOP, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned target = (passed + 1) * ng;
     int polls = 0;
-    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(bar + PS_TOP, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       if (__hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++polls > spin_max) {
         __hip_atomic_store(fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         good = 0;
@@ -61,7 +74,7 @@ __device__ __forceinline__ bool grid_barrier(const cptr<PersistArgs> a, unsigned
       }
       __builtin_amdgcn_s_sleep(2);
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     ok = good;
   }
   __syncthreads();
@@ -70,10 +83,10 @@ __device__ __forceinline__ bool grid_barrier(const cptr<PersistArgs> a, unsigned
   return r;
 }
 
-// The stages, each a function of its own, called once per stage: the
-// register allocator then sees one stage at a time, as in the separate
-// launches (inlined into one loop, the stages' values crowd the scalar
-// registers and the collide stage spills).  A call's arguments are taken
+// The stages but the last, each a function of its own, called once per
+// stage: the register allocator then sees one stage at a time, as in the
+// separate launches (all inlined into one loop, the stages' values crowd
+// the scalar registers and every stage spills).  A call's arguments are taken
 // as wave-uniform (readfirstlane) and the launch arguments read with scalar
 // loads from their device copy, so the instance descriptors are read with
 // scalar loads as in the separate launches.  A persistent block of 1024
@@ -82,16 +95,27 @@ __device__ __forceinline__ bool grid_barrier(const cptr<PersistArgs> a, unsigned
 __device__ __forceinline__ int ps_share() { return __builtin_amdgcn_readfirstlane((int)threadIdx.x / NT); }
 __device__ __forceinline__ int ps_u(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// a1: moments (the block's four shares take four consecutive entries).
+// Entry of the node list a share runs in a round: share s of persistent
+// block b takes entry (4 round + s) nb + b, so that, as with a launch of one
+// block per entry, the entries an XCD runs are those equal to its index
+// modulo 8 (the block order groups each XCD's rows; nb is a multiple of 8).
+__device__ __forceinline__ int ps_entry(int round, int sub, int nb) {
+  return (round * PS_SUB + sub) * nb + (int)blockIdx.x;
+}
+
+// a1: moments, two nodes per thread (the four-node form's 144 values of a
+// thread do not fit beside the other stages' 128 VGPRs; same sums).
 template <typename S>
 __device__ __noinline__ void ps_moments(const Inst *insts0, const PersistArgs *pa, int pc0) {
   const Inst *insts = uniform_ptr(insts0);
   const cptr<PersistArgs> a = cst(uniform_ptr(pa));
-  const int pc = ps_u(pc0), sub = ps_share(), tid = (int)threadIdx.x % NT, nb = (int)gridDim.x, n = a->n_ent4;
+  const int pc = ps_u(pc0), sub = ps_share(), tid = (int)threadIdx.x % NT, nb = (int)gridDim.x, n = 2 * a->n_ent4;
   const int2 *b2i4 = a->b2i4;
 #pragma unroll 1
-  for (int base = (int)blockIdx.x * PS_SUB; base < n; base += nb * PS_SUB)
-    if (base + sub < n) moments4_body<D2Q9, float, S, 4>(insts, b2i4, pc, Rec<float>{}, base + sub, tid);
+  for (int r = 0; r * PS_SUB * nb < n; ++r) {
+    const int e = ps_entry(r, sub, nb);
+    if (e < n) moments4_body<D2Q9, float, S, 2>(insts, b2i4, pc, Rec<float>{}, e, tid);
+  }
 }
 
 // a2-a4: one pass of four potential sub-iterations over the tall tiles, the
@@ -111,22 +135,25 @@ __device__ __noinline__ void ps_potential(const Inst *insts0, const PersistArgs 
   }
 }
 
-// a5: field and chemical potentials; each node block's residual terms
-// summed over its four waves in k_mu's order.
-__device__ __noinline__ void ps_mu(const Inst *insts0, const PersistArgs *pa, int pc0, int hflip0) {
+// a5: field and chemical potentials; with part set, each node block's
+// residual terms summed over its four waves in k_mu's order (the partials
+// the diagnostics read: the last step of a launch is the one they see, and
+// the other steps skip the block-wide sums).
+__device__ __noinline__ void ps_mu(const Inst *insts0, const PersistArgs *pa, int pc0, int hflip0, int part0) {
   __shared__ double red[P2NT / 64][2];
   const Inst *insts = uniform_ptr(insts0);
   const cptr<PersistArgs> a = cst(uniform_ptr(pa));
-  const int pc = ps_u(pc0), hflip = ps_u(hflip0), sub = ps_share(), tid = (int)threadIdx.x % NT,
+  const int pc = ps_u(pc0), hflip = ps_u(hflip0), part = ps_u(part0), sub = ps_share(), tid = (int)threadIdx.x % NT,
             nb = (int)gridDim.x, n = a->n_blk;
   const int2 *b2i = a->b2i;
 #pragma unroll 1
-  for (int base = (int)blockIdx.x * PS_SUB; base < n; base += nb * PS_SUB) {
-    const int b = base + sub;
+  for (int rd = 0; rd * PS_SUB * nb < n; ++rd) {
+    const int b = ps_entry(rd, sub, nb);
     double r[2] = {0.0, 0.0};
     const Inst *Ip = nullptr;
     int lblk = 0;
     if (b < n) mu_body<D2Q9, float, true>(insts, b2i, hflip, pc, Rec<float>{}, b, tid, r, Ip, lblk);
+    if (!part) continue;  // uniform over the launch
 #pragma unroll
     for (int k = 0; k < 2; ++k)
       for (int o = 32; o > 0; o >>= 1) r[k] += __shfl_down(r[k], o, 64);
@@ -148,16 +175,20 @@ __device__ __noinline__ void ps_mu(const Inst *insts0, const PersistArgs *pa, in
 }
 
 // a6-a11: collide-and-stream (u, p and rho written when write_macro).
+// Inlined into the step loop: as a call its spills cost more (156 against
+// 141 us per 1024^2 step).
 template <typename S>
-__device__ __noinline__ void ps_collide(const Inst *insts0, const PersistArgs *pa, int pc0, int hflip0, int wm0) {
+__device__ __forceinline__ void ps_collide(const Inst *insts0, const PersistArgs *pa, int pc0, int hflip0, int wm0) {
   const Inst *insts = uniform_ptr(insts0);
   const cptr<PersistArgs> a = cst(uniform_ptr(pa));
   const int pc = ps_u(pc0), hflip = ps_u(hflip0), wm = ps_u(wm0), sub = ps_share(), tid = (int)threadIdx.x % NT,
             nb = (int)gridDim.x, n = a->n_blk, K = a->K;
   const int2 *b2i = a->b2i;
 #pragma unroll 1
-  for (int base = (int)blockIdx.x * PS_SUB; base < n; base += nb * PS_SUB)
-    if (base + sub < n) collide_body<D2Q9, float, S, false>(insts, b2i, pc, wm, K, hflip, Rec<float>{}, base + sub, tid);
+  for (int rd = 0; rd * PS_SUB * nb < n; ++rd) {
+    const int b = ps_entry(rd, sub, nb);
+    if (b < n) collide_body<D2Q9, float, S, false>(insts, b2i, pc, wm, K, hflip, Rec<float>{}, b, tid);
+  }
 }
 
 // One block of 1024 threads per CU (the potential stage's tile needs all
@@ -178,7 +209,7 @@ __global__ __launch_bounds__(P2NT, 4) void k_persistent(const Inst *__restrict__
       ps_potential(insts, pa, pc, l);
       if (!grid_barrier(a, passed)) return;
     }
-    ps_mu(insts, pa, pc, hflip);
+    ps_mu(insts, pa, pc, hflip, s == n_steps - 1 ? 1 : 0);
     if (!grid_barrier(a, passed)) return;
     ps_collide<S>(insts, pa, pc, hflip, s == n_steps - 1 ? 1 : 0);
     if (!grid_barrier(a, passed)) return;
@@ -188,11 +219,8 @@ __global__ __launch_bounds__(P2NT, 4) void k_persistent(const Inst *__restrict__
 // Before a launch: the launch arguments into device memory and the
 // barrier words cleared (a kernel, not a copy and a memset).
 __global__ void k_persist_begin(PersistArgs a, PersistArgs *dst) {
-  if (threadIdx.x == 0) {
-    *dst = a;
-    *a.bar = 0u;
-    *a.fail = 0;
-  }
+  for (int i = (int)threadIdx.x; i < PS_WORDS; i += (int)blockDim.x) a.bar[i] = 0u;
+  if (threadIdx.x == 0) *dst = a;
 }
 
 }  // namespace lbm
