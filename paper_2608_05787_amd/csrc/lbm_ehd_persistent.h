@@ -20,7 +20,7 @@
 namespace lbm {
 
 struct PersistArgs {
-  const int2 *b2i4;   // moments table (four nodes per thread), n_ent4 entries
+  const int2 *b2i4;   // moments table (entries of 4 x 256 nodes), n_ent4 entries
   const int4 *tiles;  // tall four-sub-iteration tiles, n_tiles entries
   const int2 *b2i;    // node blocks, n_blk entries
   unsigned *bar;      // PS_WORDS barrier words (zero at launch; see grid_barrier)
