@@ -244,6 +244,12 @@ int lbm_ehd_graph(lbm_ehd_t h, int32_t steps_per_graph);
  * LBM_EHD_EHIP and the state is undefined. */
 int lbm_ehd_step_persistent(lbm_ehd_t h, int64_t n);
 
+/* Bound of one barrier wait of lbm_ehd_step_persistent, in polls of about
+ * 1 us (polls >= 1; default 2^21).  A wait that runs out makes every block
+ * of the launch leave and the call return LBM_EHD_EHIP with the state
+ * undefined: a small bound forces that path from the host (its test). */
+int lbm_ehd_set_persistent_polls(lbm_ehd_t h, int32_t polls);
+
 /* Write the selected fields of instance `inst` into caller device memory
  * dev_dst as consecutive planes [popcount(mask)][ny][nx] in ascending bit
  * order, converted to dtype (LBM_DTYPE_F32 or LBM_DTYPE_F64; for a tangent

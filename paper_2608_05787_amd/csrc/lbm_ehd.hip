@@ -295,6 +295,7 @@ struct lbm_ehd_s {
   int4 *d_t4 = nullptr;   // tile table of the four-iteration form (tall tiles), in use
   // launch configuration (lbm_ehd_set_tuning): LBM_TUNE_* bits
   int tuning = 0;
+  int persist_polls = 1 << 21;  // bound of a persistent-step barrier wait (polls of ~1 us)
   int n_t2 = 0;           // tiles in d_t2
   bool pairs() const { return !(tuning & LBM_TUNE_SINGLE_POTENTIAL); }
   // the tall tile shape exists for FP32, FP16S and FP64 arithmetic (in FP64
@@ -1261,7 +1262,7 @@ int do_step_persistent(lbm_ehd_s *H, int64_t n) {
   a.n_tiles = H->plan.total_tiles4;
   a.n_blk = H->plan.total_blocks;
   a.K = H->sub_max;
-  a.spin_max = 1 << 21;  // ~1 us per poll: a stage may take about 2 s before the launch gives up
+  a.spin_max = H->persist_polls;  // default 2^21 polls of ~1 us: a stage may take ~2 s
   const Inst *insts = H->d_insts;
   while (n > 0) {
     const int chunk = (int)(n < PERSIST_CHUNK ? n : PERSIST_CHUNK);
@@ -1510,6 +1511,13 @@ int lbm_ehd_scalars(lbm_ehd_t H, double out[3]) {
 int lbm_ehd_get_tuning(lbm_ehd_t H, int32_t *config) {
   if (!H || !config) return LBM_EHD_EINVAL;
   *config = H->tuning;
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_set_persistent_polls(lbm_ehd_t H, int32_t polls) {
+  if (!H) return LBM_EHD_EINVAL;
+  if (polls < 1) return H->fail(LBM_EHD_EINVAL, "set_persistent_polls: polls must be >= 1");
+  H->persist_polls = polls;
   return LBM_EHD_OK;
 }
 

@@ -5,7 +5,8 @@ steps its state equals, bitwise, that of lbm_ehd_step in a tall-tile launch
 configuration; the checks cover uneven instances (walls and periodic), FP32
 and FP16S storage, one and two four-sub-iteration passes per step, an odd
 step count, more steps than one launch takes (256), mixing with ordinary
-steps, and the cases it refuses."""
+steps, the cases it refuses, and a barrier wait that runs out (forced from
+the host with a bound of one poll)."""
 import numpy as np
 import pytest
 
@@ -91,3 +92,26 @@ def test_persistent_limits():
     ok.step_persistent(0)
     assert ok.scalars()["steps"] == 0
     assert np.isfinite(ok.diagnostics()["max_sum_dev"])
+
+
+def test_barrier_wait_that_runs_out_ends_the_launch():
+    """The failure path, forced from the host: with one poll per barrier wait
+    the first block to wait gives up before the others arrive, every block
+    leaves the launch, and the call reports it (the state is undefined).
+    The device is usable afterwards: fresh handles step as before."""
+    print("case persistent barrier bound", flush=True)
+    cfgs, inits = batch(4, sizes=((128, 96, True), (70, 40, False)))
+    a = binding.Sim(cfgs, inits, precision="fp32")
+    a.set_tuning(12)
+    a.set_persistent_polls(1)
+    with pytest.raises(binding.LbmEhdError):
+        a.step_persistent(4)
+    del a
+    torch.cuda.synchronize()
+    b = binding.Sim(cfgs, inits, precision="fp32")
+    b.set_tuning(12)
+    b.step_persistent(4)
+    c = binding.Sim(cfgs, inits, precision="fp32")
+    c.set_tuning(12)
+    c.step(4)
+    assert_same(b, c, 2)
