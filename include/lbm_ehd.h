@@ -48,7 +48,7 @@ enum {
   LBM_EHD_EDIVERGED = -4,    /* non-finite populations detected */
   LBM_EHD_ENOCONV = -5,      /* potential iteration hit its cap (state valid) */
   LBM_EHD_ESTATE = -6,       /* call not valid in the handle's state */
-  LBM_EHD_EUNSUPPORTED = -7  /* feature not available in this build */
+  LBM_EHD_EUNSUPPORTED = -7  /* feature not available in this library */
 };
 
 enum { LBM_BC_PERIODIC = 0, LBM_BC_WALL = 1 }; /* x (and z) are always periodic */
