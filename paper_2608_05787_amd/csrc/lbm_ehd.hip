@@ -1789,7 +1789,7 @@ const char *lbm_ehd_strerror(int code) {
     case LBM_EHD_EDIVERGED: return "simulation diverged (non-finite populations)";
     case LBM_EHD_ENOCONV: return "potential iteration reached its cap";
     case LBM_EHD_ESTATE: return "call not valid in this state";
-    case LBM_EHD_EUNSUPPORTED: return "not supported by this build";
+    case LBM_EHD_EUNSUPPORTED: return "not supported by this library";
     default: return "unknown error";
   }
 }

@@ -62,7 +62,7 @@ def test_negative_density_rejected_and_messages():
     rc, _, err = _bytes(p)
     assert rc == -1 and "densit" in err
     lib = binding.load()
-    assert lib.lbm_ehd_strerror(-7) == b"not supported by this build"
+    assert lib.lbm_ehd_strerror(-7) == b"not supported by this library"
     assert lib.lbm_ehd_strerror(0) == b"ok"
 
 
