@@ -269,6 +269,11 @@ def batch_bench(n_inst, steps, sub, init_iters, graph_len=10, eager_steps=1000):
     log("persistent: %d steps %.1f ms" % (steps, ms_pers))
     pers_equal = all(torch.equal(batch.populations(fam, inst=i), pers.populations(fam, inst=i))
                      for i in range(n_inst) for fam in "fglh")
+    # where its step goes: 100 more steps with the stage clocks on
+    pers.set_persistent_timing(True)
+    pers.step_persistent(100)
+    pers_stage_us = {k: round(v, 1) for k, v in pers.persistent_stage_times().items()}
+    log("persistent stage us per step %s" % pers_stage_us)
     del pers
     torch.cuda.empty_cache()
     batch.graph(0)
@@ -280,6 +285,7 @@ def batch_bench(n_inst, steps, sub, init_iters, graph_len=10, eager_steps=1000):
             "mlups_batched_eager": mlups(ms_eager, eager_steps), "eager_steps": eager_steps,
             "mlups_sequential": mlups(ms_seq, steps), "speedup_graph_vs_sequential": round(ms_seq / ms_graph, 2),
             "mlups_persistent": mlups(ms_pers, steps), "persistent_equals_graph_bitwise": pers_equal,
+            "persistent_stage_us": pers_stage_us,
             "instances_equal_separate_runs_bitwise": equal,
             "max_sum_dev_worst": max(d["max_sum_dev"] for d in d_batch),
             "nonfinite_total": sum(d["nonfinite"] for d in d_batch),

@@ -250,6 +250,19 @@ int lbm_ehd_step_persistent(lbm_ehd_t h, int64_t n);
  * undefined: a small bound forces that path from the host (its test). */
 int lbm_ehd_set_persistent_polls(lbm_ehd_t h, int32_t polls);
 
+/* Stage timing of lbm_ehd_step_persistent (on: 1; default 0): the launches
+ * then run a variant of the kernel in which one block reads the device's
+ * constant-rate wall clock after every grid barrier (same results; the
+ * readings cost the stages registers, ~2 % of the step). */
+int lbm_ehd_set_persistent_timing(lbm_ehd_t h, int32_t on);
+
+/* Where the last lbm_ehd_step_persistent call with stage timing on spent its
+ * time: us[0..3], the average microseconds per step of the moments stage,
+ * the charge step with the potential passes, the field and chemical
+ * potential stage and the collide-and-stream stage, each with the grid
+ * barrier that ends it.  LBM_EHD_ESTATE before such a call. */
+int lbm_ehd_persistent_stage_times(lbm_ehd_t h, double us[4]);
+
 /* Write the selected fields of instance `inst` into caller device memory
  * dev_dst as consecutive planes [popcount(mask)][ny][nx] in ascending bit
  * order, converted to dtype (LBM_DTYPE_F32 or LBM_DTYPE_F64; for a tangent

@@ -64,7 +64,7 @@ EXPORTS = ["lbm_ehd_adjoint_workspace_bytes", "lbm_ehd_workspace_bytes", "lbm_eh
            "lbm_ehd_checkpoint_bytes", "lbm_ehd_checkpoint", "lbm_ehd_restore",
            "lbm_ehd_adjoint", "lbm_ehd_record", "lbm_ehd_tangent_workspace_bytes", "lbm_ehd_tangent_gradient",
            "lbm_ehd_profile_begin", "lbm_ehd_profile_end", "lbm_ehd_graph", "lbm_ehd_step_persistent",
-           "lbm_ehd_set_persistent_polls",
+           "lbm_ehd_set_persistent_polls", "lbm_ehd_set_persistent_timing", "lbm_ehd_persistent_stage_times",
            "lbm_ehd_set_tuning", "lbm_ehd_get_tuning", "lbm_ehd_tune",
            "lbm_ehd_destroy", "lbm_ehd_strerror", "lbm_ehd_last_error"]
 TUNE_LINEAR_ORDER, TUNE_SINGLE_POTENTIAL, TUNE_COLLIDE_PER_FAMILY, TUNE_TALL_TILES = 1, 2, 4, 8
@@ -105,6 +105,8 @@ def load():
     lib.lbm_ehd_graph.argtypes = [vp, ctypes.c_int32]
     lib.lbm_ehd_step_persistent.argtypes = [vp, ctypes.c_int64]
     lib.lbm_ehd_set_persistent_polls.argtypes = [vp, ctypes.c_int32]
+    lib.lbm_ehd_persistent_stage_times.argtypes = [vp, _dp]
+    lib.lbm_ehd_set_persistent_timing.argtypes = [vp, ctypes.c_int32]
     lib.lbm_ehd_set_tuning.argtypes = [vp, ctypes.c_int32]
     lib.lbm_ehd_get_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.lbm_ehd_tune.argtypes = [vp, ctypes.c_int32, vp, _dp, ctypes.POINTER(ctypes.c_int32)]
@@ -242,6 +244,16 @@ class Sim:
 
     def set_persistent_polls(self, polls: int):
         self._check(load().lbm_ehd_set_persistent_polls(self._h, int(polls)), self._h)
+
+    def set_persistent_timing(self, on: bool):
+        self._check(load().lbm_ehd_set_persistent_timing(self._h, 1 if on else 0), self._h)
+
+    def persistent_stage_times(self) -> dict:
+        """Microseconds per step of each stage of the last timed
+        step_persistent call (barrier included)."""
+        us = (ctypes.c_double * 4)()
+        self._check(load().lbm_ehd_persistent_stage_times(self._h, us), self._h)
+        return dict(zip(("moments", "potential", "mu", "collide"), list(us)))
 
     def fields(self, names=None, inst: int = 0, dtype=None, tangent: bool = False):
         """Fields of the last step as [ny, nx] tensors; tangent=True gives the

@@ -296,6 +296,9 @@ struct lbm_ehd_s {
   // launch configuration (lbm_ehd_set_tuning): LBM_TUNE_* bits
   int tuning = 0;
   int persist_polls = 1 << 21;  // bound of a persistent-step barrier wait (polls of ~1 us)
+  int persist_timed = 0;              // run the timed persistent kernel
+  double persist_us[4] = {0, 0, 0, 0};  // last persistent call: us per step of each stage
+  long long persist_steps = 0;
   int n_t2 = 0;           // tiles in d_t2
   bool pairs() const { return !(tuning & LBM_TUNE_SINGLE_POTENTIAL); }
   // the tall tile shape exists for FP32, FP16S and FP64 arithmetic (in FP64
@@ -1246,7 +1249,8 @@ constexpr int PERSIST_CHUNK = 256;  // steps per cooperative launch
 template <typename S>
 int do_step_persistent(lbm_ehd_s *H, int64_t n) {
   int per_cu = 0, ncu = 0;
-  HIPC(H, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persistent<S>, P2NT, 0));
+  const void *kern = H->persist_timed ? (const void *)k_persistent<S, true> : (const void *)k_persistent<S, false>;
+  HIPC(H, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, P2NT, 0));
   HIPC(H, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, H->device));
   if (per_cu < 1 || ncu < 1) return H->fail(LBM_EHD_EUNSUPPORTED, "persistent step: the kernel does not fit a CU");
   const int grid = per_cu * ncu;
@@ -1264,6 +1268,12 @@ int do_step_persistent(lbm_ehd_s *H, int64_t n) {
   a.K = H->sub_max;
   a.spin_max = H->persist_polls;  // default 2^21 polls of ~1 us: a stage may take ~2 s
   const Inst *insts = H->d_insts;
+  int khz = 0;
+  HIPC(H, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, H->device));
+  long long ticks[PS_STAGES] = {0, 0, 0, 0};
+  for (double &v : H->persist_us) v = 0.0;
+  H->persist_steps = 0;
+  const int64_t n_all = n;
   while (n > 0) {
     const int chunk = (int)(n < PERSIST_CHUNK ? n : PERSIST_CHUNK);
     a.step0 = H->steps;
@@ -1272,13 +1282,20 @@ int do_step_persistent(lbm_ehd_s *H, int64_t n) {
     HIPC(H, hipGetLastError());
     const PersistArgs *pa = d_args;
     void *args[] = {(void *)&insts, (void *)&pa};
-    HIPC(H, hipLaunchCooperativeKernel((const void *)k_persistent<S>, dim3(grid), dim3(P2NT), args, 0, H->stream));
+    HIPC(H, hipLaunchCooperativeKernel(kern, dim3(grid), dim3(P2NT), args, 0, H->stream));
     int f = 0;
+    long long t[PS_STAGES];
     HIPC(H, hipMemcpyAsync(&f, fail, sizeof(int), hipMemcpyDeviceToHost, H->stream));
+    HIPC(H, hipMemcpyAsync(t, bar + PS_CLOCK, sizeof t, hipMemcpyDeviceToHost, H->stream));
     HIPC(H, hipStreamSynchronize(H->stream));
     if (f) return H->fail(LBM_EHD_EHIP, "persistent step: a grid barrier wait ran out (state undefined)");
+    for (int k = 0; k < PS_STAGES; ++k) ticks[k] += t[k];
     H->steps += chunk;
     n -= chunk;
+  }
+  if (khz > 0 && H->persist_timed) {
+    for (int k = 0; k < PS_STAGES; ++k) H->persist_us[k] = (double)ticks[k] / (khz * 1e-3) / (double)n_all;
+    H->persist_steps = n_all;
   }
   return LBM_EHD_OK;
 }
@@ -1511,6 +1528,20 @@ int lbm_ehd_scalars(lbm_ehd_t H, double out[3]) {
 int lbm_ehd_get_tuning(lbm_ehd_t H, int32_t *config) {
   if (!H || !config) return LBM_EHD_EINVAL;
   *config = H->tuning;
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_set_persistent_timing(lbm_ehd_t H, int32_t on) {
+  if (!H || (on != 0 && on != 1)) return H ? H->fail(LBM_EHD_EINVAL, "set_persistent_timing: 0 or 1") : LBM_EHD_EINVAL;
+  H->persist_timed = on;
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_persistent_stage_times(lbm_ehd_t H, double us[4]) {
+  if (!H || !us) return LBM_EHD_EINVAL;
+  if (H->persist_steps <= 0)
+    return H->fail(LBM_EHD_ESTATE, "persistent_stage_times: no timed persistent steps taken");
+  for (int k = 0; k < 4; ++k) us[k] = H->persist_us[k];
   return LBM_EHD_OK;
 }
 

@@ -36,9 +36,13 @@ constexpr int PS_SUB = P2NT / NT;  // node blocks one persistent block runs at o
 // Barrier words: eight group counters (blocks take group blockIdx.x % 8,
 // the order in which the dispatcher deals consecutive blocks to the XCDs),
 // each on a 256-byte line of its own, then the counter of completed groups,
-// then the failure word.
+// then the failure word, then the stage clock sums (PS_STAGES 64-bit words:
+// wall-clock ticks block 0 spent in each kind of stage, barrier included,
+// summed over the launch's steps).
 constexpr int PS_GROUPS = 8, PS_LINE = 64;  // groups; words per counter line
-constexpr int PS_TOP = PS_GROUPS * PS_LINE, PS_FAIL = PS_TOP + PS_LINE, PS_WORDS = PS_FAIL + PS_LINE;
+constexpr int PS_STAGES = 4;                // moments, charge + potential, field + mu, collide
+constexpr int PS_TOP = PS_GROUPS * PS_LINE, PS_FAIL = PS_TOP + PS_LINE, PS_CLOCK = PS_FAIL + PS_LINE,
+              PS_WORDS = PS_CLOCK + PS_LINE;
 
 // Grid-wide barrier.  Every block arrives once per barrier, so a group's
 // counter reaches (passed + 1) x (its blocks) when the group's last block
@@ -195,24 +199,52 @@ __device__ __forceinline__ void ps_collide(const Inst *insts0, const PersistArgs
 // of them and 64 KB of LDS); the bound keeps every stage at 128 VGPRs, four
 // waves per SIMD.
 //   pa: the launch arguments in device memory (k_persist_begin copies them).
-template <typename S>
+//   TIMED: block 0's thread 0 reads the wall clock after every barrier and
+//   adds each stage's ticks to its sum (lbm_ehd_persistent_stage_times); a
+//   separate instantiation, since the readings cost the stages registers.
+template <typename S, bool TIMED = false>
 __global__ __launch_bounds__(P2NT, 4) void k_persistent(const Inst *__restrict__ insts, const PersistArgs *pa) {
   const cptr<PersistArgs> a = cst(pa);
   const int L = a->K / 4, hflip = L & 1, n_steps = a->n_steps;
   const long long step0 = a->step0;
+  // the sums and the last reading live in LDS, not in registers the
+  // stages need
+  __shared__ long long sum[PS_STAGES + 1];
+  const bool timer = TIMED && blockIdx.x == 0 && threadIdx.x == 0;
+  if (timer) {
+#pragma unroll
+    for (int k = 0; k < PS_STAGES; ++k) sum[k] = 0;
+    sum[PS_STAGES] = wall_clock64();
+  }
+  auto lap = [&](int stage) {
+    if (timer) {
+      const long long t = wall_clock64();
+      sum[stage] += t - sum[PS_STAGES];
+      sum[PS_STAGES] = t;
+    }
+  };
   unsigned passed = 0;
   for (int s = 0; s < n_steps; ++s) {
     const int pc = (int)((step0 + s) & 1);
     ps_moments<S>(insts, pa, pc);
     if (!grid_barrier(a, passed)) return;
+    lap(0);
     for (int l = 0; l < L; ++l) {
       ps_potential(insts, pa, pc, l);
       if (!grid_barrier(a, passed)) return;
     }
+    lap(1);
     ps_mu(insts, pa, pc, hflip, s == n_steps - 1 ? 1 : 0);
     if (!grid_barrier(a, passed)) return;
+    lap(2);
     ps_collide<S>(insts, pa, pc, hflip, s == n_steps - 1 ? 1 : 0);
     if (!grid_barrier(a, passed)) return;
+    lap(3);
+  }
+  if (timer) {
+    long long *out = (long long *)(a->bar + PS_CLOCK);
+#pragma unroll
+    for (int k = 0; k < PS_STAGES; ++k) out[k] = sum[k];
   }
 }
 

@@ -115,3 +115,27 @@ def test_barrier_wait_that_runs_out_ends_the_launch():
     c.set_tuning(12)
     c.step(4)
     assert_same(b, c, 2)
+
+
+def test_stage_times_account_for_the_step():
+    """The per-stage clock sums of a timed persistent call: positive, and
+    together the call's time per step (host wall clock, which also holds
+    the launches' set-up)."""
+    import time
+    print("case persistent stage times", flush=True)
+    cfgs, inits = batch(4)
+    sim = binding.Sim(cfgs, inits, precision="fp32")
+    sim.set_tuning(12)
+    sim.step_persistent(20)
+    with pytest.raises(binding.LbmEhdError):
+        sim.persistent_stage_times()  # no timed persistent steps yet
+    sim.set_persistent_timing(True)
+    sim.step_persistent(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step_persistent(200)
+    wall_us = (time.perf_counter() - t0) * 1e6 / 200
+    st = sim.persistent_stage_times()
+    print("stage us per step", st, "wall us per step", wall_us, flush=True)
+    assert all(v > 0 for v in st.values())
+    assert 0.5 * wall_us < sum(st.values()) <= 1.1 * wall_us
