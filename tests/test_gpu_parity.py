@@ -230,13 +230,15 @@ def test_static_doublet_fp32_full_size():
 @pytest.mark.parametrize("tuning", [binding.TUNE_TALL_TILES,
                                     binding.TUNE_TALL_TILES | binding.TUNE_COLLIDE_PER_FAMILY,
                                     binding.TUNE_TALL_TILES | binding.TUNE_LINEAR_ORDER])
-@pytest.mark.parametrize("K,nx,ny,walls", [(4, 130, 70, True), (6, 70, 45, False), (5, 131, 58, True)])
+@pytest.mark.parametrize("K,nx,ny,walls", [(4, 130, 70, True), (6, 70, 45, False), (5, 131, 58, True),
+                                           (8, 70, 45, False)])
 def test_fp64_tall_tiles_match_oracle(tuning, K, nx, ny, walls):
     """The potential kernel of the benchmarked launch configurations (64 x 32
     tiles, four sub-iterations per launch while four remain, then tall
     pairs) instantiated in FP64 matches the oracle to rounding on grids
     spanning several tiles in both directions, walled and periodic, with
-    ragged edges and an odd count."""
+    ragged edges and an odd count; with an even K the first launch forms the
+    charge step (K = 8: two four-sub-iteration launches)."""
     print("case fp64 tall", tuning, K, nx, ny, walls, flush=True)
     p, init = inputs.parity_case(nx, ny, seed=K + nx, walls=walls, sub=(K, K, 0.0))
     p["init_sub_max"] = 2 * K
