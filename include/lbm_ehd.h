@@ -150,7 +150,8 @@ enum { LBM_POP_F = 0, LBM_POP_G = 1, LBM_POP_L = 2, LBM_POP_H = 3 };
  *                is the printed one.  It removes the truncation error that
  *                the three separately evolved order parameters accumulate
  *                in S where the flow's continuity error is largest (triple
- *                junctions at density jumps, Sec. 4.3).  Forward mode only.
+ *                junctions at density jumps, Sec. 4.3).  Both gradient
+ *                modes cover it.
  *  ion_tau, ion_beta, ion_charge  Nernst-Planck: relaxation time of the
  *                ion families (> 1/2), e/(k_B T) in potential units, and the
  *                charge e of a unit concentration.
@@ -415,7 +416,7 @@ int lbm_ehd_restore(lbm_ehd_t h, const void *dev_buf);
  * Returns LBM_EHD_EUNSUPPORTED otherwise.  dev_work: caller device memory
  * of lbm_ehd_adjoint_workspace_bytes(n_steps, ckpt_every), 256-byte
  * aligned: a workspace, one checkpoint per segment, ckpt_every step
- * records of (22 + 9 K) planes and 178 adjoint planes.
+ * records of (22 + 9 K) planes and 180 adjoint planes.
  *
  * Forward mode: lbm_ehd_tangent_gradient runs one tangent run of the same
  * kernels in FP64 (LBM_PREC_TANGENT) per component of theta inside dev_work

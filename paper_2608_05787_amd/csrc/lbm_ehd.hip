@@ -902,7 +902,7 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
 namespace {
 
 constexpr int REC_FIXED = 22;    // planes of a step record before the potential levels
-constexpr int ADJ_AREA = 178;    // planes of the adjoint buffers (see rev_bufs)
+constexpr int ADJ_AREA = 180;    // planes of the adjoint buffers (see rev_bufs)
 
 // Layout of the buffer shared by lbm_ehd_record and lbm_ehd_adjoint (byte
 // offsets from its start, 256-byte aligned): a private handle's workspace,
@@ -958,7 +958,6 @@ const char *adjoint_unsupported(const lbm_ehd_s *H) {
   if (p.init_tol > 0 && p.init_sub_max > 1) return "reverse mode needs a fixed-count cold start (init_tol <= 0)";
   if (p.eps_ref_phase != 0) return "gradients along permittivity ratios need eps_ref_phase 0";
   if (p.charge_model != LBM_CHARGE_LEAKY) return "reverse mode is built for the leaky-dielectric charge model";
-  if (p.sum_relax) return "reverse mode is built for the CH equilibria as printed (sum_relax 0)";
   return nullptr;
 }
 
@@ -1128,6 +1127,7 @@ int reverse_sweep(lbm_ehd_s *H, lbm_ehd_s *W, char *work, const AdjLayout &L, in
   ab.gs = base + 157 * N;
   T *psi0 = base + 159 * N;
   T *cold[2] = {base + 160 * N, base + 169 * N};
+  ab.gS = base + 178 * N;
   ab.tb = (double *)(work + L.tb);
   double E0, mean;
   applied_field(p, E0, mean);

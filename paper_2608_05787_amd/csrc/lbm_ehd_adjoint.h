@@ -34,8 +34,9 @@ template <typename T> struct AdjBufs {
   T *a[2], *hb[2], *pb[2];
   // per-step intermediates: mu-bar (local part) 3, grad(mu)-bar 6,
   // grad(rho)-bar 2, q-bar, R-bar, E-bar of the step's field 2, eps-bar,
-  // Laplacian-bar 3, grad(eps)-bar 2, grad(sigma)-bar 2
-  T *muL, *gm, *gr, *qb, *rb, *en, *eb, *lb, *ge, *gs;
+  // Laplacian-bar 3, grad(eps)-bar 2, grad(sigma)-bar 2, and with the
+  // restoring flux of the order-parameter sum S, grad(S)-bar 2
+  T *muL, *gm, *gr, *qb, *rb, *en, *eb, *lb, *ge, *gs, *gS;
   double *tb;      // nblk x TB_SLOTS
   double dEext[2]; // d E_ext / d E0
   double dwall[2]; // d wall_phi / d E0
@@ -130,11 +131,12 @@ __global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ ins
   int m[Q];
 #pragma unroll
   for (int j = 0; j < Q; ++j) m[j] = fdrow(y + cy(j), I.ny, I.bc_y) * nx + wrapx(x + cx(j), nx);
-  T ph[3], rv[Q];
+  T ph[3], rv[Q], sv[Q];
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
     const T p1 = rc.phi[m[j]], p2 = rc.phi[(size_t)N + m[j]], p3 = rc.phi[(size_t)2 * N + m[j]];
     rv[j] = P.rho[0] * p1 + P.rho[1] * p2 + P.rho[2] * p3;
+    sv[j] = p1 + p2 + p3;
     if (j == 0) {
       ph[0] = p1;
       ph[1] = p2;
@@ -143,6 +145,11 @@ __global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ ins
   }
   T grx, gry, dummy;
   fd9(rv, grx, gry, dummy);
+  // restoring flux of the sum S = phi_1 + phi_2 + phi_3 (off: gS = 0, and
+  // none of its adjoint terms below is formed)
+  const bool relax = I.sum_relax != 0 && I.phase_mode == 0;
+  T gSx = 0, gSy = 0;
+  if (relax) fd9(sv, gSx, gSy, dummy);
   T gmx[3], gmy[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -236,6 +243,8 @@ __global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ ins
   T gmx_b[3] = {T(0), T(0), T(0)}, gmy_b[3] = {T(0), T(0), T(0)};
   T ux_b = 0, uy_b = 0, rho_b = 0, pp_b = 0, Fx_b = 0, Fy_b = 0, grx_b = 0, gry_b = 0;
   T q_b = 0, R_b = 0, itg_b = 0;
+  // restoring flux: grad(S)-bar, and sum_i phi_i (X_i-bar . grad S)
+  T gSx_b = 0, gSy_b = 0, relax_t = 0;
 
   // ---- charge family (Eqs. 48-50)
   {
@@ -347,6 +356,16 @@ __global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ ins
           ph_b[i] += m0 * ph[k] * (si - sk);
           ph_b[k] += m0 * ph[i] * (si - sk);
         }
+      if (relax) {
+        // + (m0 / S) phi_i grad S: phi_i directly, S through m0 / S, and
+        // grad S, whose stencil the chemical-potential adjoint transposes
+        const T wsum = m0 / sv[0];
+        const T ti = Xx_b * gSx + Xy_b * gSy;
+        ph_b[i] += wsum * ti;
+        relax_t += ph[i] * ti;
+        gSx_b += wsum * ph[i] * Xx_b;
+        gSy_b += wsum * ph[i] * Xy_b;
+      }
     } else {
 #pragma unroll
       for (int j = 0; j < Q; ++j) An[(size_t)(i * Q + j) * N + n] = T(0);
@@ -380,8 +399,15 @@ __global__ __launch_bounds__(NT) void k_adj_collide(const Inst *__restrict__ ins
 
   // ---- force -sum phi_i grad mu_i + q E (Eq. 27b) and rho of Eq. (29)
   q_b += Fx_b * ex + Fy_b * ey;
+  // d(m0 / S) / dS = -(m0 / S) / S reaches every phase alike
+  const T S_b = relax ? -(P.m0 / sv[0]) / sv[0] * relax_t : T(0);
+  if (relax) {
+    ab.gS[n] = gSx_b;
+    ab.gS[(size_t)N + n] = gSy_b;
+  }
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
+    ph_b[i] += S_b;
     ph_b[i] -= Fx_b * gmx[i] + Fy_b * gmy[i] - P.rho[i] * rho_b;
     gmx_b[i] -= ph[i] * Fx_b;
     gmy_b[i] -= ph[i] * Fy_b;
@@ -429,7 +455,7 @@ __global__ __launch_bounds__(NT) void k_adj_mu(const Inst *__restrict__ insts, c
 #pragma unroll
     for (int i = 0; i < 3; ++i) pb0[i] = PBn[(size_t)i * N + n];
     if (with_step) {
-      T gr_t = 0;
+      T gr_t = 0, gS_t = 0;
       for_sources(I, nd.x, nd.y, [&](int j, int s) {
         const T w3 = T(3) * wgt<T>(j);
 #pragma unroll
@@ -437,8 +463,13 @@ __global__ __launch_bounds__(NT) void k_adj_mu(const Inst *__restrict__ insts, c
           mu_b[i] += w3 * (mcx(j, ab.gm[(size_t)(2 * i) * N + s]) + mcy(j, ab.gm[(size_t)(2 * i + 1) * N + s]));
         gr_t += w3 * (mcx(j, ab.gr[s]) + mcy(j, ab.gr[(size_t)N + s]));
       });
+      // grad S of the restoring flux: S reaches every phase with weight one
+      if (I.sum_relax != 0 && I.phase_mode == 0)
+        for_sources(I, nd.x, nd.y, [&](int j, int s) {
+          gS_t += T(3) * wgt<T>(j) * (mcx(j, ab.gS[s]) + mcy(j, ab.gS[(size_t)N + s]));
+        });
 #pragma unroll
-      for (int i = 0; i < 3; ++i) ph_b[i] += P.rho[i] * gr_t;
+      for (int i = 0; i < 3; ++i) ph_b[i] += P.rho[i] * gr_t + gS_t;
       ex_b += ab.en[n];
       ey_b += ab.en[(size_t)N + n];
     }

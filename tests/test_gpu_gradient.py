@@ -96,14 +96,27 @@ def reverse_cases():
     shear = inputs.field_compound_drop(40, r_shell=12.0, r_core=7.0, ca_e=0.4, init_iters=5,
                                        init_tol=0.0, sub=(3, 3, 0.0), wall_u=0.01)
     periodic = inputs.parity_case(37, 29, seed=4, walls=False, sub=(1, 1, 0.0))
-    return {"drop": (drop, 23, 5), "shear": (shear, 9, 4), "periodic": (periodic, 7, 3)}
+    return {"drop": (drop, 23, 5), "shear": (shear, 9, 4), "periodic": (periodic, 7, 3),
+            "relax": (relaxed(inputs.parity_case(33, 17, seed=6, walls=True, sub=(2, 2, 0.0))), 9, 4),
+            "relax_periodic": (relaxed(inputs.parity_case(30, 26, seed=7, walls=False, sub=(1, 1, 0.0))), 7, 3)}
 
 
-@pytest.mark.parametrize("name", ["drop", "shear", "periodic"])
+def relaxed(case):
+    """A case with the restoring flux of the order-parameter sum on, from
+    order parameters whose sum is off one by a few per cent (so grad S and
+    S - 1 are far from zero)."""
+    p, init = case
+    rng = np.random.default_rng(p["nx"] * p["ny"])
+    phi0 = init["phi0"] * (1.0 + 0.03 * rng.standard_normal(init["phi0"].shape))
+    return dict(p, sum_relax=1), dict(init, phi0=phi0)
+
+
+@pytest.mark.parametrize("name", ["drop", "shear", "periodic", "relax", "relax_periodic"])
 def test_reverse_matches_tangent_fp64(name):
     """The discrete adjoint equals forward mode to rounding: walls with
     electrodes and a shear start, a periodic box with an applied field,
-    1-3 sub-iterations, a cold start, several checkpoint segments."""
+    1-3 sub-iterations, a cold start, several checkpoint segments; and the
+    restoring flux of the order-parameter sum, with walls and periodic."""
     print("case reverse vs tangent", name, flush=True)
     (cfg, init), steps, every = reverse_cases()[name]
     seed = seeds((cfg["ny"], cfg["nx"]), ["phi1", "phi2", "phi3"], seed=3)
