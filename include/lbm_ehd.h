@@ -416,7 +416,7 @@ int lbm_ehd_restore(lbm_ehd_t h, const void *dev_buf);
  * Returns LBM_EHD_EUNSUPPORTED otherwise.  dev_work: caller device memory
  * of lbm_ehd_adjoint_workspace_bytes(n_steps, ckpt_every), 256-byte
  * aligned: a workspace, one checkpoint per segment, ckpt_every step
- * records of (22 + 9 K) planes and 180 adjoint planes.
+ * records of (22 + 9 K) planes and 176 adjoint planes.
  *
  * Forward mode: lbm_ehd_tangent_gradient runs one tangent run of the same
  * kernels in FP64 (LBM_PREC_TANGENT) per component of theta inside dev_work

@@ -902,7 +902,7 @@ static int create_impl(const lbm_ehd_params *params, int32_t n_inst, const lbm_e
 namespace {
 
 constexpr int REC_FIXED = 22;    // planes of a step record before the potential levels
-constexpr int ADJ_AREA = 180;    // planes of the adjoint buffers (see rev_bufs)
+constexpr int ADJ_AREA = 176;    // planes of the adjoint buffers (see rev_bufs)
 
 // Layout of the buffer shared by lbm_ehd_record and lbm_ehd_adjoint (byte
 // offsets from its start, 256-byte aligned): a private handle's workspace,
@@ -1071,7 +1071,6 @@ void step_adjoint(lbm_ehd_s *W, char *slot, const AdjBufs<T> &ab, int &cur, int 
     hs ^= 1;
   }
   k_adj_pre<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, rc, ab, cur);
-  k_adj_phi<T><<<grid, block, 0, W->stream>>>(W->d_insts, W->d_b2i, rc, ab, cur);
   cur ^= 1;
 }
 
@@ -1123,11 +1122,9 @@ int reverse_sweep(lbm_ehd_s *H, lbm_ehd_s *W, char *work, const AdjLayout &L, in
   ab.en = base + 149 * N;
   ab.eb = base + 151 * N;
   ab.lb = base + 152 * N;
-  ab.ge = base + 155 * N;
-  ab.gs = base + 157 * N;
-  T *psi0 = base + 159 * N;
-  T *cold[2] = {base + 160 * N, base + 169 * N};
-  ab.gS = base + 178 * N;
+  ab.gS = base + 155 * N;
+  T *psi0 = base + 157 * N;
+  T *cold[2] = {base + 158 * N, base + 167 * N};
   ab.tb = (double *)(work + L.tb);
   double E0, mean;
   applied_field(p, E0, mean);

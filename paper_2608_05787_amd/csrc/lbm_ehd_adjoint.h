@@ -34,9 +34,9 @@ template <typename T> struct AdjBufs {
   T *a[2], *hb[2], *pb[2];
   // per-step intermediates: mu-bar (local part) 3, grad(mu)-bar 6,
   // grad(rho)-bar 2, q-bar, R-bar, E-bar of the step's field 2, eps-bar,
-  // Laplacian-bar 3, grad(eps)-bar 2, grad(sigma)-bar 2, and with the
-  // restoring flux of the order-parameter sum S, grad(S)-bar 2
-  T *muL, *gm, *gr, *qb, *rb, *en, *eb, *lb, *ge, *gs, *gS;
+  // Laplacian-bar 3, and with the restoring flux of the order-parameter
+  // sum S, grad(S)-bar 2
+  T *muL, *gm, *gr, *qb, *rb, *en, *eb, *lb, *gS;
   double *tb;      // nblk x TB_SLOTS
   double dEext[2]; // d E_ext / d E0
   double dwall[2]; // d wall_phi / d E0
@@ -875,10 +875,23 @@ __global__ __launch_bounds__(P2NT) void k_adj_poisson4(const Inst *__restrict__ 
   }
 }
 
-// Adjoint of charge recovery (Eq. 47 with the previous step's field) and of
-// the permittivity field; gathers the Laplacian-bar of the mu adjoint.
-// Writes the lsum-bar, the previous field's adjoint (state), and the
-// gradient-bars of eps and sigma for the last kernel.
+// Adjoint-bar of the Ohmic source of Eq. (47) at node s (R' = (sigma/eps)
+// grad(eps).E - grad(sigma).E with the previous step's field): a function of
+// values at s alone (phi, the previous field, R-bar and q-bar there), so the
+// last kernel of a step's adjoint forms it at every source of its
+// transposed gradient stencils instead of reading it from a plane.
+template <typename T>
+__device__ __forceinline__ T pre_rp_bar(const Phys<T> &P, T p1, T p2, T p3, T R_b, T qb, T &se) {
+  se = (P.sig[0] * p1 + P.sig[1] * p2 + P.sig[2] * p3) / (P.eps[0] * herm(p1) + P.eps[1] * herm(p2) + P.eps[2] * herm(p3));
+  return R_b + T(0.5) * ((qb - se * R_b) / (T(1) + T(0.5) * se));
+}
+
+// Last kernel of a step's adjoint: charge recovery (Eq. 47 with the
+// previous step's field) and the permittivity and conductivity fields.
+// Gathers the Laplacian-bar of the mu adjoint, and transposes the eps and
+// sigma gradient stencils of Eq. (47) onto phi-bar (their gradient-bars
+// recomputed at each source node).  Writes phi-bar, the lsum-bar and the
+// previous field's adjoint (state).
 template <typename T>
 __global__ __launch_bounds__(NT) void k_adj_pre(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
                                                 Rec<T> rc, AdjBufs<T> ab, int cur) {
@@ -921,29 +934,37 @@ __global__ __launch_bounds__(NT) void k_adj_pre(const Inst *__restrict__ insts, 
     fd9(ev, gex, gey, dummy);
     fd9(sv, gsx, gsy, dummy);
     const T ex = rc.Eo[n], ey = rc.Eo[(size_t)N + n];
-    const T se = sv[0] / ev[0];
-    const T B = T(1) + T(0.5) * se;
     const T q = rc.q[n];
     // adjoints
-    const T R_b = ab.rb[n];
-    T q_b = ab.qb[n] - se * R_b;
-    T se_b = -q * R_b;
-    T Rp_b = R_b;
+    const T R_b = ab.rb[n], qb = ab.qb[n];
+    T se;
+    const T Rp_b = pre_rp_bar(P, ph[0], ph[1], ph[2], R_b, qb, se);
+    const T B = T(1) + T(0.5) * se;
+    const T q_b = qb - se * R_b;
     const T A_b = q_b / B, B_b = -q_b * q / B;
     const T Ls_b = A_b;
-    Rp_b += T(0.5) * A_b;
-    se_b += T(0.5) * B_b;
+    T se_b = -q * R_b + T(0.5) * B_b;
     se_b += Rp_b * (gex * ex + gey * ey);
-    const T gex_b = Rp_b * se * ex, gey_b = Rp_b * se * ey;
-    const T gsx_b = -Rp_b * ex, gsy_b = -Rp_b * ey;
     const T ex_b = Rp_b * (se * gex - gsx), ey_b = Rp_b * (se * gey - gsy);
     const T sv_b = se_b / ev[0];
     const T ev_b = -se_b * se / ev[0] + ab.eb[n];
+    // transposed gradients of eps and sigma: the sources' grad-bars,
+    // (Rp-bar se E) for eps and (-Rp-bar E) for sigma
+    T te = 0, ts = 0;
+    for_sources(I, nd.x, nd.y, [&](int j, int s) {
+      T ses;
+      const T rp = pre_rp_bar(P, rc.phi[s], rc.phi[(size_t)N + s], rc.phi[(size_t)2 * N + s], ab.rb[s], ab.qb[s], ses);
+      const T w3 = T(3) * wgt<T>(j);
+      const T exs = rp * rc.Eo[s], eys = rp * rc.Eo[(size_t)N + s];
+      te += w3 * (mcx(j, ses * exs) + mcy(j, ses * eys));
+      ts -= w3 * (mcx(j, exs) + mcy(j, eys));
+    });
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      ph_b[i] += ev_b * P.eps[i] * T(6) * ph[i] * (T(1) - ph[i]) + sv_b * P.sig[i];
-      th[i] += (double)(ev_b * herm(ph[i]));
-      th[3 + i] += (double)(sv_b * ph[i]);
+      const T e_b = ev_b + te, s_b = sv_b + ts;
+      ph_b[i] += e_b * P.eps[i] * T(6) * ph[i] * (T(1) - ph[i]) + s_b * P.sig[i];
+      th[i] += (double)(e_b * herm(ph[i]));
+      th[3 + i] += (double)(s_b * ph[i]);
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) PBn[(size_t)i * N + n] = pb0[i] + ph_b[i];
@@ -951,47 +972,6 @@ __global__ __launch_bounds__(NT) void k_adj_pre(const Inst *__restrict__ insts, 
     T *An = ab.a[cur ^ 1];
     An[(size_t)AO_E * N + n] = ex_b;
     An[(size_t)(AO_E + 1) * N + n] = ey_b;
-    ab.ge[n] = gex_b;
-    ab.ge[(size_t)N + n] = gey_b;
-    ab.gs[n] = gsx_b;
-    ab.gs[(size_t)N + n] = gsy_b;
-  }
-  add_theta(I, ab.tb, lblk, th);
-}
-
-// Last kernel of a step's adjoint: transposes the eps and sigma gradient
-// stencils of the charge-recovery kernel onto phi-bar.
-template <typename T>
-__global__ __launch_bounds__(NT) void k_adj_phi(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
-                                                Rec<T> rc, AdjBufs<T> ab, int cur) {
-  const Inst *Ip;
-  int lblk;
-  const Node nd = locate(insts, b2i, Ip, lblk);
-  const Inst &I = *Ip;
-  double th[TB_SLOTS] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (nd.valid) {
-    const Phys<T> &P = phys<T>(I);
-    const int N = I.N, n = nd.n;
-    T *PBn = ab.pb[cur ^ 1];
-    T pb0[3], phv[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      pb0[i] = PBn[(size_t)i * N + n];
-      phv[i] = rc.phi[(size_t)i * N + n];
-    }
-    T te = 0, ts = 0;
-    for_sources(I, nd.x, nd.y, [&](int j, int s) {
-      const T w3 = T(3) * wgt<T>(j);
-      te += w3 * (mcx(j, ab.ge[s]) + mcy(j, ab.ge[(size_t)N + s]));
-      ts += w3 * (mcx(j, ab.gs[s]) + mcy(j, ab.gs[(size_t)N + s]));
-    });
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const T ph = phv[i];
-      PBn[(size_t)i * N + n] = pb0[i] + (te * P.eps[i] * T(6) * ph * (T(1) - ph) + ts * P.sig[i]);
-      th[i] += (double)(te * herm(ph));
-      th[3 + i] += (double)(ts * ph);
-    }
   }
   add_theta(I, ab.tb, lblk, th);
 }
