@@ -5,8 +5,9 @@ steps its state equals, bitwise, that of lbm_ehd_step in a tall-tile launch
 configuration; the checks cover uneven instances (walls and periodic), FP32
 and FP16S storage, one and two four-sub-iteration passes per step, an odd
 step count, more steps than one launch takes (256), mixing with ordinary
-steps, the cases it refuses, and a barrier wait that runs out (forced from
-the host with a bound of one poll)."""
+steps, instances smaller than one potential tile, the cases it refuses,
+and a barrier wait that runs out (forced from the host with a bound of one
+poll)."""
 import numpy as np
 import pytest
 
@@ -47,6 +48,23 @@ def test_persistent_equals_step_bitwise(prec, K, config, steps):
     b.set_tuning(config)
     b.step_persistent(steps)
     assert_same(a, b, 3)
+
+
+def test_persistent_with_instances_smaller_than_a_tile():
+    """Instances of 2 x 2 to 5 x 3 nodes (walls and periodic) beside a larger
+    one: every stage's tables hold blocks and tiles that are mostly outside
+    the grid, and the tall tile's ring wraps several times.  Two instances
+    run the restoring flux of the order-parameter sum."""
+    print("case persistent tiny", flush=True)
+    cfgs, inits = batch(4, sizes=((2, 2, False), (3, 2, True), (5, 3, False), (2, 7, True), (70, 40, True)))
+    cfgs[2]["sum_relax"] = cfgs[4]["sum_relax"] = 1
+    a = binding.Sim(cfgs, inits, precision="fp32")
+    a.set_tuning(12)
+    a.step(6)
+    b = binding.Sim(cfgs, inits, precision="fp32")
+    b.set_tuning(12)
+    b.step_persistent(6)
+    assert_same(a, b, 5)
 
 
 def test_persistent_over_several_launches_and_mixed_with_steps():
