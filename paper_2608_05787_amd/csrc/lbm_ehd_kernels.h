@@ -263,23 +263,27 @@ template <class L = D2Q9>
 __device__ __forceinline__ Node locate_at(const Inst *__restrict__ insts, const int2 *__restrict__ b2i, int bid,
                                           int tid, const Inst *&Ip, int &lblk) {
   __builtin_assume(tid >= 0 && tid < NT);
+  // the tables are written by the host only: read through the constant
+  // address space (scalar loads where bid is uniform, in every kernel)
   Node nd;
-  const int2 t = b2i[bid];
-  nd.inst = t.x;
-  lblk = t.y;
+  const cptr<int> t = cst((const int *)b2i) + 2 * (size_t)bid;
+  nd.inst = t[0];
+  lblk = t[1];
   Ip = insts + nd.inst;
-  const int local = t.y * NT + tid;
-  nd.valid = local < Ip->nn;
+  const cptr<Inst> Ic = cst(Ip);
+  const int nx = Ic->nx;
+  const int local = lblk * NT + tid;
+  nd.valid = local < Ic->nn;
   nd.n = nd.valid ? local : 0;
   int r = nd.n;
   nd.z = 0;
   if (L::D == 3) {
-    const int plane = Ip->nx * Ip->ny;
+    const int plane = nx * Ic->ny;
     nd.z = r / plane;
     r -= nd.z * plane;
   }
-  nd.y = r / Ip->nx;
-  nd.x = r - nd.y * Ip->nx;
+  nd.y = r / nx;
+  nd.x = r - nd.y * nx;
   return nd;
 }
 template <class L = D2Q9>
@@ -303,11 +307,14 @@ __device__ __forceinline__ int fdrow(int y, int ny, int walls) {
 // Node index of the Eq. (33) stencil point x + c_j (periodic wrap in x and
 // z; mirror ghost rows at walls in y).
 template <class L>
-__device__ __forceinline__ int nbr(const Inst &I, const Node &nd, int j) {
-  const int row = fdrow(nd.y + L::c(j, 1), I.ny, I.bc_y);
-  const int col = wrapx(nd.x + L::c(j, 0), I.nx);
-  if (L::D == 2) return row * I.nx + col;
-  return (wrapx(nd.z + L::c(j, 2), I.nz) * I.ny + row) * I.nx + col;
+__device__ __forceinline__ int nbr(int nx, int ny, int nz, int bc_y, const Node &nd, int j) {
+  const int row = fdrow(nd.y + L::c(j, 1), ny, bc_y);
+  const int col = wrapx(nd.x + L::c(j, 0), nx);
+  if (L::D == 2) return row * nx + col;
+  return (wrapx(nd.z + L::c(j, 2), nz) * ny + row) * nx + col;
+}
+template <class L> __device__ __forceinline__ int nbr(const Inst &I, const Node &nd, int j) {
+  return nbr<L>(I.nx, I.ny, I.nz, I.bc_y, nd, j);
 }
 
 // Eq. (33) gradient g[D] and Laplacian from the Q stencil values v[j]
@@ -1219,99 +1226,149 @@ __global__ __launch_bounds__(NT) void k_reduce_poisson(const Inst *__restrict__ 
 // (Eq. 45 with the applied field: E = (m + (tau_h/3) E_ext) / den), the
 // potential plane and last-iteration residual, and the chemical potentials
 // of Eq. (20) with eps'(phi_i) = 6 eps_i phi_i (1 - phi_i).
-//   hofs: buffer offset of the final h relative to ctl->hcur (fixed count:
-//   parity of the potential launches; adaptive: 0, the control pass already
-//   flipped it).
-//   pc: the step's field buffer (1 at create).
-//   bid, tid: node block and thread (see locate_at); red receives this
-//   thread's residual terms, Ip and lblk the block's instance.  COH: the
-//   control word through a coherent load (see p2_meta).
+// In three phases, so that a caller can issue the loads of several node
+// blocks before it waits for any: mu_locate (the node, the control word
+// that names the final h buffer, and every plane address the node reads:
+// all the reads a plane load depends on), mu_fetch (the plane loads alone:
+// h, eps, the previous potential and the phi stencils) and mu_finish (the
+// arithmetic and the stores).
+template <class L, typename T> struct MuIn {
+  Node nd;
+  const Inst *Ip;
+  int lblk, N, nx, ny, nz, bc_y;
+  const T *h, *eps, *psi, *phi;
+  T hv[L::Q], epsv, psi0, pv[3][L::Q];
+};
+
+//   bid, tid: node block and thread (see locate_at).  hofs: buffer offset
+//   of the final h relative to ctl->hcur (fixed count: parity of the
+//   potential launches; adaptive: 0, the control pass already flipped it).
+//   pc: the step's field buffer (1 at create).  COH: the control word
+//   through a coherent load (see p2_meta).
 template <class L, typename T, bool COH = false>
-__device__ __forceinline__ void mu_body(const Inst *__restrict__ insts, const int2 *__restrict__ b2i, int hofs, int pc,
-                                        const Rec<T> &rc, int bid, int tid, double (&red)[2], const Inst *&Ip,
-                                        int &lblk) {
-  constexpr int Q = L::Q, D = L::D;
-  const Node nd = locate_at<L>(insts, b2i, bid, tid, Ip, lblk);
-  const Inst &I = *Ip;
+__device__ __forceinline__ void mu_locate(const Inst *__restrict__ insts, const int2 *__restrict__ b2i, int bid,
+                                          int tid, int hofs, int pc, MuIn<L, T> &in) {
+  in.nd = locate_at<L>(insts, b2i, bid, tid, in.Ip, in.lblk);
+  // a lane outside the grid fetches node 0 (in bounds; its values are not
+  // used), so that the fetch is free of branches
+  if (!in.nd.valid) in.nd.n = in.nd.x = in.nd.y = in.nd.z = 0;
+  // the block's instance values (one node block is one instance: wave-
+  // uniform values, kept in scalar registers; the descriptor is written by
+  // the host only and read through the constant address space)
+  const cptr<Inst> I = cst(in.Ip);
   // (the control word through a plain pointer: a scalar read here staggers
   // less and measured slower)
-  const Ctl *ctl = I.ctl;
-  const Phys<T> &P = phys<T>(I);
+  const Ctl *ctl = I->ctl;
+  int hcur;
+  if constexpr (COH)
+    hcur = __hip_atomic_load(&ctl->hcur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    hcur = ctl->hcur;
+  in.N = __builtin_amdgcn_readfirstlane(I->N);
+  in.nx = __builtin_amdgcn_readfirstlane(I->nx);
+  in.ny = __builtin_amdgcn_readfirstlane(I->ny);
+  in.nz = __builtin_amdgcn_readfirstlane(I->nz);
+  in.bc_y = __builtin_amdgcn_readfirstlane(I->bc_y);
+  in.h = uniform_ptr((const T *)I->h[hcur ^ hofs]);
+  in.eps = uniform_ptr((const T *)I->eps);
+  in.psi = uniform_ptr((const T *)I->psi);
+  in.phi = uniform_ptr((const T *)I->phi[pc]);
+}
+
+template <class L, typename T>
+__device__ __forceinline__ void mu_fetch(MuIn<L, T> &in) {
+  constexpr int Q = L::Q;
+  const int N = in.N, n = in.nd.n;
+  auto h = gbl(in.h);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) in.hv[j] = ld_plane(uniform_ptr(h + (size_t)j * N), (unsigned)n);
+  in.epsv = (gbl(in.eps))[n];
+  auto phi = gbl(in.phi);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const int m = nbr<L>(in.nx, in.ny, in.nz, in.bc_y, in.nd, j);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) in.pv[i][j] = ld_plane(uniform_ptr(phi + (size_t)i * N), (unsigned)m);
+  }
+  in.psi0 = (gbl(in.psi))[n];
+}
+
+//   red receives this thread's residual terms.
+template <class L, typename T>
+__device__ __forceinline__ void mu_finish(const MuIn<L, T> &in, const Rec<T> &rc, double (&red)[2]) {
+  constexpr int Q = L::Q, D = L::D;
   red[0] = red[1] = 0.0;
-  if (nd.valid) {
-    const int N = I.N, n = nd.n;
-    int hcur;
-    if constexpr (COH)
-      hcur = __hip_atomic_load(&ctl->hcur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else
-      hcur = ctl->hcur;
-    auto h = gbl((const T *)I.h[hcur ^ hofs]);
-    T s1 = 0, m[D];
+  if (!in.nd.valid) return;
+  const Inst &I = *in.Ip;
+  const Phys<T> &P = phys<T>(I);
+  // every descriptor value the node uses, read before its first store (as
+  // far as the compiler can tell a plane store may alias the descriptor, so
+  // a read after one would be issued, and waited for, after it)
+  const int N = in.N, n = in.nd.n;
+  T *const psi = (T *)in.psi, *const E = (T *)I.E, *const mu = (T *)I.mu;
+  const T pref = psi_ref<T>(P, in.nd.y), tau_h = P.tau_h, eps_ref = P.eps_ref, width = P.D;
+  T Eext[D], lam[3], epsi[3];
 #pragma unroll
-    for (int d = 0; d < D; ++d) m[d] = 0;
+  for (int d = 0; d < D; ++d) Eext[d] = P.Eext[d];
 #pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      const T v = ld_plane(uniform_ptr(h + (size_t)j * N), (unsigned)n);
-      if (j) s1 += v;
+  for (int i = 0; i < 3; ++i) {
+    lam[i] = P.lam[i];
+    epsi[i] = P.eps[i];
+  }
+  T s1 = 0, m[D];
 #pragma unroll
-      for (int d = 0; d < D; ++d)
-        if (L::c(j, d) != 0) m[d] += lc<L, T>(j, d) * v;
-    }
-    const T eps = (gbl((const T *)I.eps))[n];
-    const T pot = s1 * (T(1) / (T(1) - lw<L, T>(0))) + psi_ref<T>(P, nd.y);
-    const T th3 = P.tau_h / T(3), iden = T(1) / ((eps - P.eps_ref) + th3);
-    T e[D];
+  for (int d = 0; d < D; ++d) m[d] = 0;
 #pragma unroll
-    for (int d = 0; d < D; ++d) e[d] = (m[d] + th3 * P.Eext[d]) * iden;
-    auto psi = gbl((T *)I.psi);
-    // the phi stencils and the previous potential, loaded before the first
-    // store (later loads would wait for it: the compiler cannot tell the
-    // planes apart)
-    auto phi = gbl((const T *)I.phi[pc]);
-    T pv[3][Q];
+  for (int j = 0; j < Q; ++j) {
+    const T v = in.hv[j];
+    if (j) s1 += v;
 #pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      const int m = nbr<L>(I, nd, j);
+    for (int d = 0; d < D; ++d)
+      if (L::c(j, d) != 0) m[d] += lc<L, T>(j, d) * v;
+  }
+  const T pot = s1 * (T(1) / (T(1) - lw<L, T>(0))) + pref;
+  const T th3 = tau_h / T(3), iden = T(1) / ((in.epsv - eps_ref) + th3);
+  T e[D];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) pv[i][j] = ld_plane(uniform_ptr(phi + (size_t)i * N), (unsigned)m);
-    }
-    const double dd = (double)pot - (double)psi[n];
-    red[0] = dd * dd;
-    red[1] = (double)pot * (double)pot;
-    psi[n] = pot;
-    auto E = gbl((T *)I.E);
-    T e2 = e[0] * e[0];
+  for (int d = 0; d < D; ++d) e[d] = (m[d] + th3 * Eext[d]) * iden;
+  const double dd = (double)pot - (double)in.psi0;
+  red[0] = dd * dd;
+  red[1] = (double)pot * (double)pot;
+  (gbl(psi))[n] = pot;
+  auto Eg = gbl(E);
+  T e2 = e[0] * e[0];
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      st_plane(uniform_ptr(E + (size_t)d * N), (unsigned)n, e[d]);
-      if (rc.En) rc.En[(size_t)d * N + n] = e[d];
-      if (d) e2 += e[d] * e[d];
-    }
-    auto mu = gbl((T *)I.mu);
+  for (int d = 0; d < D; ++d) {
+    st_plane(uniform_ptr(Eg + (size_t)d * N), (unsigned)n, e[d]);
+    if (rc.En) rc.En[(size_t)d * N + n] = e[d];
+    if (d) e2 += e[d] * e[d];
+  }
+  auto mug = gbl(mu);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      T gg[D], lap;
-      fdq<L>(pv[i], gg, lap);
-      const T ph = pv[i][0];
-      const T bulk = T(24) / P.D * P.lam[i] * ph * (ph - T(0.5)) * (ph - T(1));
-      const T grad = T(0.75) * P.D * P.lam[i] * lap;
-      const T elec = T(0.5) * (T(6) * P.eps[i] * ph * (T(1) - ph)) * e2;
-      st_plane(uniform_ptr(mu + (size_t)i * N), (unsigned)n, bulk - grad - elec);
-      if (rc.mu) rc.mu[(size_t)i * N + n] = bulk - grad - elec;
-    }
+  for (int i = 0; i < 3; ++i) {
+    T gg[D], lap;
+    fdq<L>(in.pv[i], gg, lap);
+    const T ph = in.pv[i][0];
+    const T bulk = T(24) / width * lam[i] * ph * (ph - T(0.5)) * (ph - T(1));
+    const T grad = T(0.75) * width * lam[i] * lap;
+    const T elec = T(0.5) * (T(6) * epsi[i] * ph * (T(1) - ph)) * e2;
+    st_plane(uniform_ptr(mug + (size_t)i * N), (unsigned)n, bulk - grad - elec);
+    if (rc.mu) rc.mu[(size_t)i * N + n] = bulk - grad - elec;
   }
 }
+
 template <class L, typename T>
 __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
                                            int hofs, int pc, Rec<T> rc = Rec<T>{}) {
   double red[2];
-  const Inst *Ip;
-  int lblk;
-  mu_body<L, T>(insts, b2i, hofs, pc, rc, (int)blockIdx.x, (int)threadIdx.x, red, Ip, lblk);
+  MuIn<L, T> in;
+  mu_locate<L, T>(insts, b2i, (int)blockIdx.x, (int)threadIdx.x, hofs, pc, in);
+  mu_fetch<L, T>(in);
+  mu_finish<L, T>(in, rc, red);
   block_sum<2>(red);
   if (threadIdx.x == 0) {
-    Ip->part_mu[(size_t)lblk * 2] = red[0];
-    Ip->part_mu[(size_t)lblk * 2 + 1] = red[1];
+    in.Ip->part_mu[(size_t)in.lblk * 2] = red[0];
+    in.Ip->part_mu[(size_t)in.lblk * 2 + 1] = red[1];
   }
 }
 

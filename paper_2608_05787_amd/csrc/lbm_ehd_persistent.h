@@ -150,14 +150,8 @@ __device__ __noinline__ void ps_mu(const Inst *insts0, const PersistArgs *pa, in
   const int pc = ps_u(pc0), hflip = ps_u(hflip0), part = ps_u(part0), sub = ps_share(), tid = (int)threadIdx.x % NT,
             nb = (int)gridDim.x, n = a->n_blk;
   const int2 *b2i = a->b2i;
-#pragma unroll 1
-  for (int rd = 0; rd * PS_SUB * nb < n; ++rd) {
-    const int b = ps_entry(rd, sub, nb);
-    double r[2] = {0.0, 0.0};
-    const Inst *Ip = nullptr;
-    int lblk = 0;
-    if (b < n) mu_body<D2Q9, float, true>(insts, b2i, hflip, pc, Rec<float>{}, b, tid, r, Ip, lblk);
-    if (!part) continue;  // uniform over the launch
+  // residual partials of one node block into its slot (when part)
+  auto partials = [&](const MuIn<D2Q9, float> &in, int b, double (&r)[2]) {
 #pragma unroll
     for (int k = 0; k < 2; ++k)
       for (int o = 32; o > 0; o >>= 1) r[k] += __shfl_down(r[k], o, 64);
@@ -171,10 +165,39 @@ __device__ __noinline__ void ps_mu(const Inst *insts0, const PersistArgs *pa, in
       for (int k = 0; k < 2; ++k) {
         double t = 0;
         for (int i = 0; i < NT / 64; ++i) t += red[sub * (NT / 64) + i][k];
-        Ip->part_mu[(size_t)lblk * 2 + k] = t;
+        in.Ip->part_mu[(size_t)in.lblk * 2 + k] = t;
       }
     }
     __syncthreads();
+  };
+  // two node blocks per share and round: both blocks' loads are issued
+  // before either waits (a wave waits for its oldest loads first, so the
+  // control words of both are read before any plane)
+#pragma unroll 1
+  for (int rd = 0; rd * PS_SUB * nb < n; rd += 2) {
+    const int b0 = ps_entry(rd, sub, nb), b1 = ps_entry(rd + 1, sub, nb);
+    // (a block past the table's end fetches the last block's nodes and
+    // finishes none)
+    MuIn<D2Q9, float> in0, in1;
+    mu_locate<D2Q9, float, true>(insts, b2i, b0 < n ? b0 : n - 1, tid, hflip, pc, in0);
+    mu_locate<D2Q9, float, true>(insts, b2i, b1 < n ? b1 : n - 1, tid, hflip, pc, in1);
+    if (b0 >= n) in0.nd.valid = false;
+    if (b1 >= n) in1.nd.valid = false;
+    // both blocks' plane addresses in registers before the first plane
+    // load: no memory access moves across this point (left to itself, the
+    // compiler puts the first block's plane loads before the second block's
+    // lookups, whose wait then drains them)
+    asm volatile("" ::"v"(in0.h), "v"(in0.phi), "v"(in1.h), "v"(in1.phi) : "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    mu_fetch<D2Q9, float>(in0);
+    mu_fetch<D2Q9, float>(in1);
+    __builtin_amdgcn_sched_barrier(0);  // every load issued before any arithmetic on them
+    double r0[2], r1[2];
+    mu_finish<D2Q9, float>(in0, Rec<float>{}, r0);
+    mu_finish<D2Q9, float>(in1, Rec<float>{}, r1);
+    if (!part) continue;  // uniform over the launch
+    partials(in0, b0, r0);
+    partials(in1, b1, r1);
   }
 }
 
