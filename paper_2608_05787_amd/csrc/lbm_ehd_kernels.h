@@ -1226,8 +1226,8 @@ __global__ __launch_bounds__(NT) void k_reduce_poisson(const Inst *__restrict__ 
 // (Eq. 45 with the applied field: E = (m + (tau_h/3) E_ext) / den), the
 // potential plane and last-iteration residual, and the chemical potentials
 // of Eq. (20) with eps'(phi_i) = 6 eps_i phi_i (1 - phi_i).
-// In three phases, so that a caller can issue the loads of several node
-// blocks before it waits for any: mu_locate (the node, the control word
+// In three phases, so that a caller (the persistent step's field stage) can
+// issue the loads of several node blocks before it waits for any: mu_locate (the node, the control word
 // that names the final h buffer, and every plane address the node reads:
 // all the reads a plane load depends on), mu_fetch (the plane loads alone:
 // h, eps, the previous potential and the phi stencils) and mu_finish (the
@@ -1357,18 +1357,103 @@ __device__ __forceinline__ void mu_finish(const MuIn<L, T> &in, const Rec<T> &rc
   }
 }
 
+// The same arithmetic in one pass, for the separate launch (loads and
+// arithmetic interleaved as the compiler schedules them: 0.4 us faster at
+// 1024^2 than the three phases above; the two agree bitwise, which the
+// persistent-step tests check against ordinary steps).
+//   hofs: buffer offset of the final h relative to ctl->hcur (fixed count:
+//   parity of the potential launches; adaptive: 0, the control pass already
+//   flipped it).
+//   pc: the step's field buffer (1 at create).
+//   bid, tid: node block and thread (see locate_at); red receives this
+//   thread's residual terms, Ip and lblk the block's instance.  COH: the
+//   control word through a coherent load (see p2_meta).
+template <class L, typename T, bool COH = false>
+__device__ __forceinline__ void mu_body(const Inst *__restrict__ insts, const int2 *__restrict__ b2i, int hofs, int pc,
+                                        const Rec<T> &rc, int bid, int tid, double (&red)[2], const Inst *&Ip,
+                                        int &lblk) {
+  constexpr int Q = L::Q, D = L::D;
+  const Node nd = locate_at<L>(insts, b2i, bid, tid, Ip, lblk);
+  const Inst &I = *Ip;
+  // (the control word through a plain pointer: a scalar read here staggers
+  // less and measured slower)
+  const Ctl *ctl = I.ctl;
+  const Phys<T> &P = phys<T>(I);
+  red[0] = red[1] = 0.0;
+  if (nd.valid) {
+    const int N = I.N, n = nd.n;
+    int hcur;
+    if constexpr (COH)
+      hcur = __hip_atomic_load(&ctl->hcur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+      hcur = ctl->hcur;
+    auto h = gbl((const T *)I.h[hcur ^ hofs]);
+    T s1 = 0, m[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) m[d] = 0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const T v = ld_plane(uniform_ptr(h + (size_t)j * N), (unsigned)n);
+      if (j) s1 += v;
+#pragma unroll
+      for (int d = 0; d < D; ++d)
+        if (L::c(j, d) != 0) m[d] += lc<L, T>(j, d) * v;
+    }
+    const T eps = (gbl((const T *)I.eps))[n];
+    const T pot = s1 * (T(1) / (T(1) - lw<L, T>(0))) + psi_ref<T>(P, nd.y);
+    const T th3 = P.tau_h / T(3), iden = T(1) / ((eps - P.eps_ref) + th3);
+    T e[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) e[d] = (m[d] + th3 * P.Eext[d]) * iden;
+    auto psi = gbl((T *)I.psi);
+    // the phi stencils and the previous potential, loaded before the first
+    // store (later loads would wait for it: the compiler cannot tell the
+    // planes apart)
+    auto phi = gbl((const T *)I.phi[pc]);
+    T pv[3][Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const int m = nbr<L>(I, nd, j);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) pv[i][j] = ld_plane(uniform_ptr(phi + (size_t)i * N), (unsigned)m);
+    }
+    const double dd = (double)pot - (double)psi[n];
+    red[0] = dd * dd;
+    red[1] = (double)pot * (double)pot;
+    psi[n] = pot;
+    auto E = gbl((T *)I.E);
+    T e2 = e[0] * e[0];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      st_plane(uniform_ptr(E + (size_t)d * N), (unsigned)n, e[d]);
+      if (rc.En) rc.En[(size_t)d * N + n] = e[d];
+      if (d) e2 += e[d] * e[d];
+    }
+    auto mu = gbl((T *)I.mu);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      T gg[D], lap;
+      fdq<L>(pv[i], gg, lap);
+      const T ph = pv[i][0];
+      const T bulk = T(24) / P.D * P.lam[i] * ph * (ph - T(0.5)) * (ph - T(1));
+      const T grad = T(0.75) * P.D * P.lam[i] * lap;
+      const T elec = T(0.5) * (T(6) * P.eps[i] * ph * (T(1) - ph)) * e2;
+      st_plane(uniform_ptr(mu + (size_t)i * N), (unsigned)n, bulk - grad - elec);
+      if (rc.mu) rc.mu[(size_t)i * N + n] = bulk - grad - elec;
+    }
+  }
+}
 template <class L, typename T>
 __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const int2 *__restrict__ b2i,
                                            int hofs, int pc, Rec<T> rc = Rec<T>{}) {
   double red[2];
-  MuIn<L, T> in;
-  mu_locate<L, T>(insts, b2i, (int)blockIdx.x, (int)threadIdx.x, hofs, pc, in);
-  mu_fetch<L, T>(in);
-  mu_finish<L, T>(in, rc, red);
+  const Inst *Ip;
+  int lblk;
+  mu_body<L, T>(insts, b2i, hofs, pc, rc, (int)blockIdx.x, (int)threadIdx.x, red, Ip, lblk);
   block_sum<2>(red);
   if (threadIdx.x == 0) {
-    in.Ip->part_mu[(size_t)in.lblk * 2] = red[0];
-    in.Ip->part_mu[(size_t)in.lblk * 2 + 1] = red[1];
+    Ip->part_mu[(size_t)lblk * 2] = red[0];
+    Ip->part_mu[(size_t)lblk * 2 + 1] = red[1];
   }
 }
 
