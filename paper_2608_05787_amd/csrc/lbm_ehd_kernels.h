@@ -544,7 +544,7 @@ template <typename T, int W> struct VecN {
 //   rc: when rc.phi is set, the order parameters also go there (recording runs).
 //   bid, tid: launched block (PER per table entry) and thread (k_moments4
 //   passes its own; the persistent step its blocks' shares).
-template <class L, typename T, typename S, int W = 4>
+template <class L, typename T, typename S, int W = 4, bool CST = false>
 __device__ __forceinline__ void moments4_body(const Inst *__restrict__ insts, const int2 *__restrict__ b2i4, int pc,
                                               const Rec<T> &rc, int bid, int tid) {
   static_assert(W == 4 || W == 2, "four or two nodes per thread");
@@ -552,9 +552,19 @@ __device__ __forceinline__ void moments4_body(const Inst *__restrict__ insts, co
   using V = typename VecN<T, W>::v;
   using GV = const V __attribute__((address_space(1))) *;
   using GVW = V __attribute__((address_space(1))) *;
-  const int2 t = b2i4[bid / PER];
+  // CST: the table and the descriptor (written by the host only) read
+  // through the constant address space, scalar loads where the caller's
+  // pointers come from memory (the persistent step; a launch's restrict
+  // arguments give scalar loads already, and its code stays as it is)
+  int2 t;
+  if constexpr (CST) {
+    const cptr<int> te = cst((const int *)b2i4) + 2 * (size_t)(bid / PER);
+    t = make_int2(te[0], te[1]);
+  } else {
+    t = b2i4[bid / PER];
+  }
   const int sub = bid % PER;
-  const Inst &I = insts[t.x];
+  const Inst &I = CST ? *(const Inst *)(cst(insts) + t.x) : insts[t.x];
   if (t.y == 0 && sub == 0 && tid == 0) {
     I.ctl->done = 0;
     I.ctl->k_used = 0;
@@ -1299,7 +1309,7 @@ __device__ __forceinline__ void mu_finish(const MuIn<L, T> &in, const Rec<T> &rc
   constexpr int Q = L::Q, D = L::D;
   red[0] = red[1] = 0.0;
   if (!in.nd.valid) return;
-  const Inst &I = *in.Ip;
+  const Inst &I = *(const Inst *)cst(in.Ip);  // host-written: constant-space reads
   const Phys<T> &P = phys<T>(I);
   // every descriptor value the node uses, read before its first store (as
   // far as the compiler can tell a plane store may alias the descriptor, so
@@ -1469,7 +1479,7 @@ __global__ __launch_bounds__(NT) void k_mu(const Inst *__restrict__ insts, const
 //   give bitwise the same results).  The per-family D2Q9 FP32/FP16S form is
 //   held to 128 VGPRs (4 waves per SIMD), which it fits without spilling.
 //   bid, tid: node block and thread (see locate_at).
-template <class L, typename T, typename S, bool EARLY>
+template <class L, typename T, typename S, bool EARLY, bool CST = false>
 __device__ __forceinline__ void collide_body(const Inst *__restrict__ insts, const int2 *__restrict__ b2i, int pc,
                                              int write_macro, int fixedK, int hflip, const Rec<T> &rc, int bid,
                                              int tid) {
@@ -1477,7 +1487,10 @@ __device__ __forceinline__ void collide_body(const Inst *__restrict__ insts, con
   const Inst *Ip;
   int lblk;
   const Node nd = locate_at<L>(insts, b2i, bid, tid, Ip, lblk);
-  const Inst &I = *Ip;
+  // CST: the descriptor (written by the host only) read through the
+  // constant address space, for callers whose pointers come from memory
+  // (the persistent step); a launch keeps its code as it is
+  const Inst &I = CST ? *(const Inst *)cst(Ip) : *Ip;
   if (lblk == 0 && tid == 0) {
     // device-scope atomics: in the persistent step an earlier stage of the
     // same launch, on another CU, wrote these words

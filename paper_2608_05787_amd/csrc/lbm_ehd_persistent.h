@@ -118,7 +118,7 @@ __device__ __noinline__ void ps_moments(const Inst *insts0, const PersistArgs *p
 #pragma unroll 1
   for (int r = 0; r * PS_SUB * nb < n; ++r) {
     const int e = ps_entry(r, sub, nb);
-    if (e < n) moments4_body<D2Q9, float, S, 2>(insts, b2i4, pc, Rec<float>{}, e, tid);
+    if (e < n) moments4_body<D2Q9, float, S, 2, true>(insts, b2i4, pc, Rec<float>{}, e, tid);
   }
 }
 
@@ -214,7 +214,7 @@ __device__ __forceinline__ void ps_collide(const Inst *insts0, const PersistArgs
 #pragma unroll 1
   for (int rd = 0; rd * PS_SUB * nb < n; ++rd) {
     const int b = ps_entry(rd, sub, nb);
-    if (b < n) collide_body<D2Q9, float, S, false>(insts, b2i, pc, wm, K, hflip, Rec<float>{}, b, tid);
+    if (b < n) collide_body<D2Q9, float, S, false, true>(insts, b2i, pc, wm, K, hflip, Rec<float>{}, b, tid);
   }
 }
 
