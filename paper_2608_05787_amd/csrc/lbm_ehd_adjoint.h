@@ -880,10 +880,14 @@ __global__ __launch_bounds__(P2NT) void k_adj_poisson4(const Inst *__restrict__ 
 // values at s alone (phi, the previous field, R-bar and q-bar there), so the
 // last kernel of a step's adjoint forms it at every source of its
 // transposed gradient stencils instead of reading it from a plane.
+//   se: sigma / eps at s (Eq. 30 and the conductivity of Eq. 29).
+template <typename T> __device__ __forceinline__ T pre_rp_from(T se, T R_b, T qb) {
+  return R_b + T(0.5) * ((qb - se * R_b) / (T(1) + T(0.5) * se));
+}
 template <typename T>
 __device__ __forceinline__ T pre_rp_bar(const Phys<T> &P, T p1, T p2, T p3, T R_b, T qb, T &se) {
   se = (P.sig[0] * p1 + P.sig[1] * p2 + P.sig[2] * p3) / (P.eps[0] * herm(p1) + P.eps[1] * herm(p2) + P.eps[2] * herm(p3));
-  return R_b + T(0.5) * ((qb - se * R_b) / (T(1) + T(0.5) * se));
+  return pre_rp_from(se, R_b, qb);
 }
 
 // Last kernel of a step's adjoint: charge recovery (Eq. 47 with the
@@ -918,9 +922,11 @@ __global__ __launch_bounds__(NT) void k_adj_pre(const Inst *__restrict__ insts, 
     for (int i = 0; i < 3; ++i) ph_b[i] -= T(6) * ab.lb[(size_t)i * N + n];
     // forward values
     T ev[Q], sv[Q], ph[3];
+    int mm[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
       const int m = fdrow(nd.y + cy(j), I.ny, I.bc_y) * nx + wrapx(nd.x + cx(j), nx);
+      mm[j] = m;
       const T p1 = rc.phi[m], p2 = rc.phi[(size_t)N + m], p3 = rc.phi[(size_t)2 * N + m];
       ev[j] = P.eps[0] * herm(p1) + P.eps[1] * herm(p2) + P.eps[2] * herm(p3);
       sv[j] = P.sig[0] * p1 + P.sig[1] * p2 + P.sig[2] * p3;
@@ -951,14 +957,26 @@ __global__ __launch_bounds__(NT) void k_adj_pre(const Inst *__restrict__ insts, 
     // transposed gradients of eps and sigma: the sources' grad-bars,
     // (Rp-bar se E) for eps and (-Rp-bar E) for sigma
     T te = 0, ts = 0;
-    for_sources(I, nd.x, nd.y, [&](int j, int s) {
-      T ses;
-      const T rp = pre_rp_bar(P, rc.phi[s], rc.phi[(size_t)N + s], rc.phi[(size_t)2 * N + s], ab.rb[s], ab.qb[s], ses);
+    auto source = [&](int j, int s, T ses) {
+      const T rp = pre_rp_from(ses, ab.rb[s], ab.qb[s]);
       const T w3 = T(3) * wgt<T>(j);
       const T exs = rp * rc.Eo[s], eys = rp * rc.Eo[(size_t)N + s];
       te += w3 * (mcx(j, ses * exs) + mcy(j, ses * eys));
       ts -= w3 * (mcx(j, exs) + mcy(j, eys));
-    });
+    };
+    if (!I.bc_y || (nd.y > 0 && nd.y < I.ny - 1)) {
+      // away from the wall rows the source x - c_j is the stencil point
+      // x + c_opp(j) above, whose eps and sigma are at hand (the order and
+      // the arithmetic of the general form below)
+#pragma unroll
+      for (int j = 0; j < Q; ++j) source(j, mm[opp(j)], sv[opp(j)] / ev[opp(j)]);
+    } else {
+      for_sources(I, nd.x, nd.y, [&](int j, int s) {
+        T ses;
+        pre_rp_bar(P, rc.phi[s], rc.phi[(size_t)N + s], rc.phi[(size_t)2 * N + s], T(0), T(0), ses);
+        source(j, s, ses);
+      });
+    }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const T e_b = ev_b + te, s_b = sv_b + ts;
